@@ -1,0 +1,457 @@
+"""Oracle for the Gear-RT photon transport step -- TEST INFRASTRUCTURE ONLY.
+
+A plain FP64 CPU implementation of what the HIP library computes, written from
+the thesis (arXiv:2302.12727, Part II "Finite volume particle methods" and
+Part III "Numerical solution strategy").  Only `tests/`, the smoke check of
+`__graft_entry__` and the CPU-baseline leg of `bench.py` may import it; the
+product path never does.
+
+Layers:
+  * neighbour candidates from a periodic k-d tree (scipy.spatial.cKDTree, a
+    library primitive; the HIP path uses its own Morton-ordered tree);
+  * per-particle arithmetic in `rt_oracle.c` (plain loops, FP64);
+  * the 3x3 inversion B_i = E_i^{-1} by numpy.linalg.inv (LAPACK).
+
+Parity status: every function is pinned by the CPU tests (closed forms of the
+kernel and the M1 closure, partition of unity, linear exactness of the
+gradient, lattice surfaces, the two-particle step of Appendix E, photon
+conservation, brute-force sums).  The readings listed in the C file (limiter
+form, face normal, guards, injection units) have no worked example in the
+thesis; they are pinned only through those consequences.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "rt_oracle.c")
+LIB = os.path.join(HERE, "liborc.so")
+
+# H/h of the cubic spline in 3D (compact support radius over smoothing length),
+# fixed by the neighbour number of eq:number-of-neighbors: (4pi/3)(kappa*eta)^3 = 48
+# at eta = 1.2348.
+KAPPA = 1.825742
+ETA = 1.2348
+
+RT_OK, RT_ENOCONV, RT_ESINGULAR = 0, -4, -5
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(msg)
+        self.code = code
+
+
+def build(quiet: bool = True) -> str:
+    """Compile rt_oracle.c into liborc.so (gcc, -O2, OpenMP, no fast-math)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+           "-ffp-contract=off", "-o", LIB + ".tmp", SRC, "-lm"]
+    subprocess.run(cmd, check=True, capture_output=quiet)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_lib = None
+
+_d = ctypes.POINTER(ctypes.c_double)
+_i64 = ctypes.POINTER(ctypes.c_int64)
+_i32 = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        L.orc_w.restype = ctypes.c_double
+        L.orc_w.argtypes = [ctypes.c_double]
+        L.orc_dw.restype = ctypes.c_double
+        L.orc_dw.argtypes = [ctypes.c_double]
+        L.orc_W.restype = ctypes.c_double
+        L.orc_W.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_minmod.restype = ctypes.c_double
+        L.orc_minmod.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_solve_h.restype = ctypes.c_int32
+        L.orc_solve_h.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, ctypes.c_double,
+                                  ctypes.c_double, _d, _i32, _i32]
+        L.orc_transpose.restype = None
+        L.orc_transpose.argtypes = [ctypes.c_int64, _i64, _i64, _i64, _i64, _i64]
+        L.orc_sym_count.restype = ctypes.c_int64
+        L.orc_sym_count.argtypes = [ctypes.c_int64, _i64, _i64, _i64, _i64, _i64]
+        L.orc_sym_fill.restype = None
+        L.orc_sym_fill.argtypes = [ctypes.c_int64, _i64, _i64, _i64, _i64, _i64, _i64]
+        L.orc_geometry.restype = None
+        L.orc_geometry.argtypes = [ctypes.c_int64, _d, _d, _d, _i64, _i64, _d, _d, _d]
+        L.orc_gradient.restype = None
+        L.orc_gradient.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d, _d, _d,
+                                   _i64, _i64, _d, _d]
+        L.orc_m1_flux.restype = None
+        L.orc_m1_flux.argtypes = [_d, _d, ctypes.c_double, _d]
+        L.orc_glf.restype = None
+        L.orc_glf.argtypes = [_d, _d, _d, ctypes.c_double, _d]
+        L.orc_surface.restype = None
+        L.orc_surface.argtypes = [_d, _d, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, _d, _d, _d, _d]
+        L.orc_transport.restype = None
+        L.orc_transport.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d, _d, _d, _d,
+                                    _i64, _i64, ctypes.c_double, ctypes.c_double, _d, _d,
+                                    _d, _i64, _d]
+        L.orc_inject.restype = None
+        L.orc_inject.argtypes = [ctypes.c_int64, ctypes.c_int32, _i64, _i64, _d, _d, _d,
+                                 ctypes.c_double, _d]
+        L.orc_source_weights.restype = ctypes.c_int32
+        L.orc_source_weights.argtypes = [ctypes.c_int32, _d, _d, ctypes.c_double, _d, _d]
+        L.orc_photon_total.restype = None
+        L.orc_photon_total.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d]
+        L.orc_dt.restype = ctypes.c_double
+        L.orc_dt.argtypes = [ctypes.c_int64, _d, ctypes.c_double, ctypes.c_double]
+        L.orc_num_threads.restype = ctypes.c_int32
+        L.orc_num_threads.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray, t=_d):
+    return a.ctypes.data_as(t)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i64a(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+# ---------------------------------------------------------------------------
+# scalar helpers (used by the pins)
+
+def w(q: float) -> float:
+    return lib().orc_w(q)
+
+
+def dw(q: float) -> float:
+    return lib().orc_dw(q)
+
+
+def W(r: float, H: float) -> float:
+    return lib().orc_W(r, H)
+
+
+def minmod(a: float, b: float) -> float:
+    return lib().orc_minmod(a, b)
+
+
+def m1_flux(q, nh, c: float) -> np.ndarray:
+    q, nh = _f64(q), _f64(nh)
+    out = np.zeros(4)
+    lib().orc_m1_flux(_p(q), _p(nh), c, _p(out))
+    return out
+
+
+def glf(qL, qR, nh, c: float) -> np.ndarray:
+    qL, qR, nh = _f64(qL), _f64(qR), _f64(nh)
+    out = np.zeros(4)
+    lib().orc_glf(_p(qL), _p(qR), _p(nh), c, _p(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# neighbour candidates
+
+def _knn_covering(tree: cKDTree, pts: np.ndarray, radius_fn, k0: int = 96,
+                  kmax: int = 1 << 14):
+    """k-nearest candidate rows for every query point such that the last
+    candidate distance reaches radius_fn(rows, d, idx) (rows that fail are
+    queried again with twice the k).  Returns a list of (rows, d, idx)."""
+    n_pts = tree.n
+    out = []
+    rows = np.arange(pts.shape[0])
+    k = min(k0, n_pts)
+    while rows.size:
+        d, idx = tree.query(pts[rows], k=k)
+        d = d.reshape(rows.size, k)
+        idx = idx.reshape(rows.size, k).astype(np.int64)
+        ok = radius_fn(rows, d, idx)
+        if k >= n_pts:
+            ok[:] = True
+        out.append((rows[ok], d[ok], idx[ok]))
+        rows = rows[~ok]
+        if rows.size and k >= kmax:
+            raise OracleError(RT_ENOCONV, "neighbour candidate set exceeds kmax")
+        k = min(2 * k, n_pts)
+    return out
+
+
+def solve_h(tree: cKDTree, pts: np.ndarray, eta: float = ETA, kappa: float = KAPPA):
+    """Smoothing lengths of the query points over the particles in `tree`
+    (eq:number-of-neighbors; root of h^3 sum_j W(r_j, kappa h) = eta^3)."""
+    L = lib()
+    n = pts.shape[0]
+    h = np.zeros(n)
+    iters = np.zeros(n, dtype=np.int32)
+
+    def fn(rows, d, idx):
+        d = _f64(d)
+        hh = np.zeros(rows.size)
+        st = np.zeros(rows.size, dtype=np.int32)
+        it = np.zeros(rows.size, dtype=np.int32)
+        L.orc_solve_h(rows.size, d.shape[1], _p(d), eta, kappa, _p(hh), _p(st, _i32),
+                      _p(it, _i32))
+        if np.any(st == 2):
+            raise OracleError(RT_ENOCONV, "smoothing length did not converge")
+        ok = st == 0
+        h[rows[ok]] = hh[ok]
+        iters[rows[ok]] = it[ok]
+        return ok
+
+    _knn_covering(tree, pts, fn)
+    return h, iters
+
+
+def gather_lists(tree: cKDTree, x: np.ndarray, H: np.ndarray):
+    """CSR of G(i) = {j != i : r_ij < H_i}, rows sorted by partner index."""
+    n = x.shape[0]
+    rows_all, cols_all = [], []
+
+    def fn(rows, d, idx):
+        return d[:, -1] >= H[rows]
+
+    for rows, d, idx in _knn_covering(tree, x, fn):
+        m = (d < H[rows][:, None]) & (idx != rows[:, None])
+        r_, c_ = np.nonzero(m)
+        rows_all.append(rows[r_])
+        cols_all.append(idx[r_, c_])
+    r = np.concatenate(rows_all) if rows_all else np.zeros(0, np.int64)
+    cidx = np.concatenate(cols_all) if cols_all else np.zeros(0, np.int64)
+    order = np.lexsort((cidx, r))
+    r, cidx = r[order], cidx[order]
+    ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(ptr, r + 1, 1)
+    ptr = np.cumsum(ptr)
+    return _i64a(ptr), _i64a(cidx)
+
+
+def symmetric_lists(n: int, gptr: np.ndarray, gidx: np.ndarray):
+    """CSR of N(i) = G(i) union G^T(i), rows sorted, no duplicates."""
+    L = lib()
+    tptr = np.zeros(n + 1, dtype=np.int64)
+    tidx = np.zeros(gidx.size, dtype=np.int64)
+    fill = np.zeros(n, dtype=np.int64)
+    L.orc_transpose(n, _p(gptr, _i64), _p(gidx, _i64), _p(tptr, _i64), _p(tidx, _i64),
+                    _p(fill, _i64))
+    sptr = np.zeros(n + 1, dtype=np.int64)
+    tot = L.orc_sym_count(n, _p(gptr, _i64), _p(gidx, _i64), _p(tptr, _i64),
+                          _p(tidx, _i64), _p(sptr, _i64))
+    sidx = np.zeros(max(tot, 1), dtype=np.int64)
+    L.orc_sym_fill(n, _p(gptr, _i64), _p(gidx, _i64), _p(tptr, _i64), _p(tidx, _i64),
+                   _p(sptr, _i64), _p(sidx, _i64))
+    return sptr, sidx[:tot]
+
+
+# ---------------------------------------------------------------------------
+# static geometry
+
+@dataclasses.dataclass
+class Geometry:
+    x: np.ndarray
+    h: np.ndarray
+    H: np.ndarray
+    omega: np.ndarray
+    V: np.ndarray
+    E: np.ndarray        # (n, 3, 3)
+    B: np.ndarray        # (n, 3, 3)
+    gptr: np.ndarray
+    gidx: np.ndarray
+    sptr: np.ndarray
+    sidx: np.ndarray
+    dt: float
+    box: np.ndarray
+    c: float
+    cfl: float
+    eta: float
+    kappa: float
+    h_iters: Optional[np.ndarray] = None
+    tree: Optional[cKDTree] = None
+
+    @property
+    def n(self):
+        return self.x.shape[0]
+
+    @property
+    def n_pairs(self) -> int:
+        """Unordered interacting pairs (r_kl < max(H_k, H_l))."""
+        return int(self.sidx.size // 2)
+
+
+def build_geometry(x, eta: float = ETA, kappa: float = KAPPA, c: float = 1.0,
+                   cfl: float = 0.9, h: Optional[np.ndarray] = None,
+                   box: float = 1.0) -> Geometry:
+    L = lib()
+    x = _f64(x)
+    n = x.shape[0]
+    boxv = np.full(3, float(box))
+    tree = cKDTree(x, boxsize=box)
+    iters = None
+    if h is None:
+        h, iters = solve_h(tree, x, eta, kappa)
+    h = _f64(h)
+    H = kappa * h
+    if np.any(H >= 0.5 * box):
+        raise OracleError(-1, "compact support exceeds half the box")
+    gptr, gidx = gather_lists(tree, x, H)
+    sptr, sidx = symmetric_lists(n, gptr, gidx)
+    omega = np.zeros(n)
+    V = np.zeros(n)
+    E = np.zeros((n, 9))
+    L.orc_geometry(n, _p(x), _p(H), _p(boxv), _p(gptr, _i64), _p(gidx, _i64),
+                   _p(omega), _p(V), _p(E))
+    E = E.reshape(n, 3, 3)
+    ev = np.linalg.eigvalsh(E)
+    if np.any(ev[:, 0] <= 1e-12 * np.maximum(ev[:, 2], 1e-300)):
+        raise OracleError(RT_ESINGULAR, "singular E matrix (coplanar neighbourhood)")
+    B = np.linalg.inv(E)
+    dt = L.orc_dt(n, _p(V), cfl, c)
+    return Geometry(x, h, H, omega, V, E, _f64(B), gptr, gidx, sptr, sidx, dt, boxv,
+                    c, cfl, eta, kappa, iters, tree)
+
+
+@dataclasses.dataclass
+class Sources:
+    xs: np.ndarray
+    h: np.ndarray
+    src: np.ndarray     # entry -> source
+    gas: np.ndarray     # entry -> gas particle
+    xi: np.ndarray      # entry weight xi_sg
+    qnz: np.ndarray
+
+
+def build_sources(geom: Geometry, xs, eta_star: float = ETA) -> Sources:
+    L = lib()
+    xs = _f64(xs).reshape(-1, 3)
+    S = xs.shape[0]
+    if S == 0:
+        z = np.zeros(0, np.int64)
+        return Sources(xs, np.zeros(0), z, z, np.zeros(0), np.zeros(0, np.int32))
+    hs, _ = solve_h(geom.tree, xs, eta_star, geom.kappa)
+    Hs = geom.kappa * hs
+    src, gas, xi, qnz = [], [], [], []
+
+    def fn(rows, d, idx):
+        return d[:, -1] >= Hs[rows]
+
+    cand = {}
+    for rows, d, idx in _knn_covering(geom.tree, xs, fn):
+        for r_, dd, ii in zip(rows, d, idx):
+            cand[int(r_)] = ii[dd < Hs[r_]]
+    for s in range(S):
+        g = np.sort(cand[s])
+        xg = _f64(geom.x[g])
+        wts = np.zeros(g.size)
+        q = L.orc_source_weights(g.size, _p(_f64(xs[s])), _p(xg), Hs[s], _p(geom.box),
+                                 _p(wts))
+        if q < 0:
+            raise OracleError(-1, "source without gas neighbours")
+        src.append(np.full(g.size, s, np.int64))
+        gas.append(g)
+        xi.append(wts)
+        qnz.append(q)
+    src, gas, xi = np.concatenate(src), np.concatenate(gas), np.concatenate(xi)
+    order = np.lexsort((src, gas))
+    return Sources(xs, hs, _i64a(src[order]), _i64a(gas[order]), _f64(xi[order]),
+                   np.asarray(qnz, np.int32))
+
+
+# ---------------------------------------------------------------------------
+# per-step operators
+
+def inject(geom: Geometry, srcs: Sources, U: np.ndarray, L: np.ndarray,
+           dt: Optional[float] = None) -> None:
+    """In place: E_g += dt * sum_s xi_sg L_s / V_g."""
+    if srcs is None or srcs.src.size == 0:
+        return
+    dt = geom.dt if dt is None else dt
+    assert U.flags.c_contiguous and U.dtype == np.float64
+    Lm = _f64(L)
+    lib().orc_inject(srcs.src.size, U.shape[1], _p(srcs.src, _i64), _p(srcs.gas, _i64),
+                     _p(srcs.xi), _p(geom.V), _p(Lm), dt, _p(U))
+
+
+def gradient(geom: Geometry, U: np.ndarray) -> np.ndarray:
+    U = _f64(U)
+    n, G = U.shape[0], U.shape[1]
+    dU = np.zeros((n, G, 4, 3))
+    lib().orc_gradient(n, G, _p(geom.x), _p(geom.H), _p(geom.V), _p(_f64(geom.B)),
+                       _p(geom.box), _p(geom.gptr, _i64), _p(geom.gidx, _i64), _p(U),
+                       _p(dU))
+    return dU
+
+
+def transport(geom: Geometry, U: np.ndarray, dU: np.ndarray, dt: Optional[float] = None):
+    """Returns (U_new, counts[4], ledger[G])."""
+    U, dU = _f64(U), _f64(dU)
+    n, G = U.shape[0], U.shape[1]
+    dt = geom.dt if dt is None else dt
+    out = np.zeros_like(U)
+    counts = np.zeros(4, dtype=np.int64)
+    ledger = np.zeros(G)
+    lib().orc_transport(n, G, _p(geom.x), _p(geom.h), _p(geom.H), _p(geom.V),
+                        _p(_f64(geom.B)), _p(geom.box), _p(geom.sptr, _i64),
+                        _p(geom.sidx, _i64), geom.c, dt, _p(U), _p(dU), _p(out),
+                        _p(counts, _i64), _p(ledger))
+    return out, counts, ledger
+
+
+def photon_total(geom: Geometry, U: np.ndarray) -> np.ndarray:
+    U = _f64(U)
+    Q = np.zeros(U.shape[1])
+    lib().orc_photon_total(U.shape[0], U.shape[1], _p(geom.V), _p(U), _p(Q))
+    return Q
+
+
+def surface(geom: Geometry, k: int, l: int) -> np.ndarray:
+    A = np.zeros(3)
+    B = _f64(geom.B)
+    lib().orc_surface(_p(_f64(geom.x[k])), _p(_f64(geom.x[l])), geom.H[k], geom.H[l],
+                      geom.V[k], geom.V[l], _p(_f64(B[k])), _p(_f64(B[l])), _p(geom.box),
+                      _p(A))
+    return A
+
+
+def step(geom: Geometry, srcs: Optional[Sources], U: np.ndarray, L=None,
+         dt: Optional[float] = None):
+    """One RT step in the operator-splitting order inject -> gradient ->
+    transport.  Returns (U_new, info)."""
+    U = _f64(U).copy()
+    if srcs is not None and srcs.src.size:
+        inject(geom, srcs, U, L, dt)
+    dU = gradient(geom, U)
+    out, counts, ledger = transport(geom, U, dU, dt)
+    return out, {"counts": counts, "ledger": ledger, "U_injected": U, "dU": dU}
+
+
+def run(geom: Geometry, srcs: Optional[Sources], U0: np.ndarray, L, steps: int,
+        keep: bool = False):
+    U = _f64(U0).copy()
+    counts = np.zeros(4, dtype=np.int64)
+    ledger = np.zeros(U.shape[1])
+    states = [U.copy()] if keep else None
+    for _ in range(steps):
+        U, info = step(geom, srcs, U, L)
+        counts += info["counts"]
+        ledger += info["ledger"]
+        if keep:
+            states.append(U.copy())
+    return U, {"counts": counts, "ledger": ledger, "states": states}
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
