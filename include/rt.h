@@ -1,0 +1,201 @@
+/*
+ * rt.h -- C ABI of the MI355X (gfx950) photon-transport library.
+ *
+ * The library implements the transport step of Gear-RT, the particle-based
+ * moment (M1) radiative transfer scheme of arXiv:2302.12727, Part III
+ * ("Numerical solution strategy", sections "First step: injection" and
+ * "Second step: transport"), on the finite volume particle method of Part II
+ * (Hopkins formulation).  Particles are static interpolation points
+ * (Part III, "Using a particle based method: selecting reference frames"), so
+ * neighbour search and geometry are built once and reused by every step.
+ *
+ * Conventions shared by every entry point
+ *  - All array pointers are DEVICE pointers (HIP, gfx950) allocated and freed
+ *    by the caller, unless marked [host].  The library keeps no pointer to
+ *    caller memory across calls.
+ *  - Work is enqueued asynchronously on the context's HIP stream; nothing
+ *    synchronises the host except rt_create, rt_build_cells, rt_set_sources,
+ *    the rt_get_* queries and rt_sync.
+ *  - Particle arrays (state, gradients, smoothing lengths, volumes) are in the
+ *    library's Morton order once rt_build_cells has run: position i of those
+ *    arrays is input particle perm[i].
+ *  - The state U of one particle is G photon groups x (E, Fx, Fy, Fz), i.e.
+ *    U[n][G][4]; its gradient is dU[n][G][4][3] (d/dx, d/dy, d/dz).  The
+ *    element type is double for RT_FP64 and float for RT_FP32C.
+ *  - Errors: argument checks fail synchronously with RT_EINVAL and a message
+ *    (rt_last_error).  Conditions found on the device (smoothing length not
+ *    converged, singular E matrix, non-finite state) raise bits of a device
+ *    status word that the next rt_sync turns into its return code.
+ *  - One context per stream; calls on a context are not re-entrant.
+ */
+#ifndef GEARRT_RT_H
+#define GEARRT_RT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rt_ctx rt_ctx;
+
+typedef enum {
+    RT_OK = 0,
+    RT_EINVAL = -1,     /* bad argument (message in rt_last_error)           */
+    RT_ENOMEM = -2,     /* device allocation failed                          */
+    RT_EHIP = -3,       /* HIP runtime error                                 */
+    RT_ENOCONV = -4,    /* smoothing length iteration did not converge       */
+    RT_ESINGULAR = -5,  /* E_i not positive definite (coplanar neighbours)   */
+    RT_ESTATE = -6      /* call out of order (e.g. step before build)        */
+} rt_status;
+
+typedef enum { RT_FP64 = 0, RT_FP32C = 1 } rt_precision;
+
+/* Guard counters, accumulated by rt_transport (see there). */
+enum { RT_CNT_FACE_E = 0, RT_CNT_FACE_F = 1, RT_CNT_CELL_E = 2, RT_CNT_CELL_F = 3,
+       RT_NCOUNTS = 4 };
+
+typedef struct {
+    int64_t n;          /* particles, 1 .. 2^28                                  */
+    int32_t groups;     /* photon groups G, 1 .. 8                               */
+    int32_t precision;  /* rt_precision                                          */
+    double box;         /* side of the periodic cube [0, box)^3                  */
+    double eta;         /* resolution parameter eta_res (default 1.2348)         */
+    double kappa;       /* compact support over smoothing length H/h (1.825742)  */
+    double c_red;       /* (reduced) speed of light                              */
+    double cfl;         /* Courant number of the global time step                */
+    void *hip_stream;   /* hipStream_t the context enqueues on (NULL: default)   */
+} rt_params;
+
+/* Create a context for n particles.  [host] p, out.  Validates p (RT_EINVAL
+ * with a message through *out when p is invalid, *out may then be NULL).
+ * No device memory is touched before the arguments are validated. */
+rt_status rt_create(const rt_params *p, rt_ctx **out);
+void rt_destroy(rt_ctx *ctx);
+/* Last error message of ctx (or of the last failed rt_create when ctx is NULL). */
+const char *rt_last_error(const rt_ctx *ctx);
+/* Rebind the stream the context enqueues on. */
+rt_status rt_set_stream(rt_ctx *ctx, void *hip_stream);
+
+/* Static geometry (Part II "Partition of unity", "Neighbor search",
+ * "Finite volume particle methods following Hopkins"; Part III eq:rt-cfl).
+ *   x    [n][3] positions in [0, box), input order.
+ *   h_in [n] smoothing lengths in input order, or NULL to solve
+ *        h^3 sum_j W(r_ij, kappa h) = eta^3 for every particle
+ *        (eq:number-of-neighbors, Newton-Raphson with bisection).
+ *   perm [n] out: perm[i] = input index of Morton-ordered particle i.
+ *   h    [n] out (Morton order); V [n] out: V_i = 1/omega(x_i)
+ *        (eq:particle-volume);  dt [1] out: C_cfl min_i dx_i / c with
+ *        dx_i = (3 V_i / 4 pi)^{1/3}.
+ * Builds Morton order, the search tree, the neighbour lists
+ * {j : r_ij < max(H_i, H_j)} and per particle V_i and B_i = E_i^{-1}
+ * (eq:matrix_E, eq:matrix_B, inverted in FP64).  Synchronises the stream.
+ * Errors: RT_ENOCONV, RT_ESINGULAR, RT_EINVAL (compact support >= box/2). */
+rt_status rt_build_cells(rt_ctx *ctx, const double *x, const double *h_in,
+                         int64_t *perm, double *h, double *V, double *dt);
+
+/* Point sources (Part III "First step: injection", "Weights for distribution
+ * of energy density of a star onto particles").  xs [S][3] device positions.
+ * Solves each source's smoothing length over the gas with eta_star, then the
+ * weights xi_sg = mu_a psi(x_s - x_g, h_s) with the octant correction
+ * eq:isotropy-correction-with-zero.  S = 0 removes all sources.  Synchronises. */
+rt_status rt_set_sources(rt_ctx *ctx, int32_t n_src, const double *xs, double eta_star);
+
+/* Injection, in place on U (first operator of the RT step):
+ *   E_g += dt * sum_s xi_sg L_s / V_g   for every group, no flux injected.
+ * L [S][G] luminosities (double in both precisions), dt [1] device. */
+rt_status rt_inject(rt_ctx *ctx, void *U, const double *L, const double *dt);
+
+/* Least-squares gradients (eq:gradient) of every component of U:
+ *   dU_i = sum_{j: r_ij < H_i} (U_j - U_i) psi_tilde_j(x_i).
+ * U [n][G][4] in, dU [n][G][4][3] out.  U and dU must not overlap. */
+rt_status rt_gradient(rt_ctx *ctx, const void *U, void *dU);
+
+/* One transport step (eq:transport-update-explicit with one global dt):
+ *   U_out_k = U_k - dt/V_k sum_l Flux_kl . A_kl
+ * over all neighbours l, with A_kl of eq:HopkinsAij, the GLF solver of
+ * eq:riemann-GLF on minmod-limited states extrapolated to
+ * x_kl = x_k + h_k/(h_k + h_l)(x_l - x_k) (eq:rt-riemann-problem), and the M1
+ * closure (eq:eddington-group).  Face states and the updated state are
+ * guarded: E < 0 is set to 0 (with F = 0) and |F| > c E is scaled to c E.
+ *   U, dU     in (dU = rt_gradient(U));  U_out out, must not overlap U.
+ *   dt        [1] device.
+ *   photon_total [G] out or NULL: Q_g = sum_k V_k E_kg of U_out (FP64,
+ *             compensated, deterministic).
+ *   counts    [RT_NCOUNTS] int64, accumulated, or NULL: face states with E
+ *             clipped / F rescaled (each directed neighbour entry counts both
+ *             faces), updated states with E clipped / F rescaled.
+ *   ledger    [G] accumulated or NULL: sum_k V_k (energy density added by
+ *             clipping E < 0 of the updated state).
+ *   guard_mask [n][G] uint8 out or NULL: per updated state, bit0 = E clipped,
+ *             bit1 = F rescaled (consumed by rt_adjoint). */
+rt_status rt_transport(rt_ctx *ctx, const void *U, const void *dU, const double *dt,
+                       void *U_out, double *photon_total, int64_t *counts, double *ledger,
+                       uint8_t *guard_mask);
+
+/* Q_g = sum_k V_k E_kg of U, [G] out (FP64, compensated, deterministic). */
+rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q);
+
+/* Adjoint (vector-Jacobian product) of one full step
+ *   U_next = transport(inject(U_pre, L), gradient(inject(U_pre, L)))
+ * with respect to U_pre and L.  (The thesis has no adjoint; this is the exact
+ * derivative of the step above, taking the subgradient of the active branch at
+ * the minmod switches and guards.)
+ *   U_pre    [n][G][4] state before injection of this step.
+ *   L        [S][G] luminosities used by the step (NULL if no sources).
+ *   dt       [1] device.
+ *   dU       gradient of the post-injection state, or NULL (recomputed).
+ *   guard_mask from the forward rt_transport of this step, or NULL
+ *            (recomputed).
+ *   lam_next [n][G][4] dLoss/dU_next.  lam [n][G][4] out: dLoss/dU_pre; may
+ *            alias lam_next.
+ *   dL_dL    [S][G] double, accumulated (+=) dLoss/dL, or NULL. */
+rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
+                     const void *dU, const uint8_t *guard_mask, const void *lam_next,
+                     void *lam, double *dL_dL);
+
+/* Wait for the stream; return the first device-side error raised since the
+ * last rt_sync (RT_ENOCONV, RT_ESINGULAR) or RT_OK, and clear it. */
+rt_status rt_sync(rt_ctx *ctx);
+
+/* ---- queries (synchronising; for tests and diagnostics) ---------------- */
+typedef struct {
+    int64_t n;
+    int64_t n_entries;      /* directed neighbour entries sum_i |N(i)|          */
+    int64_t n_pairs;        /* unordered interacting pairs = n_entries / 2      */
+    int64_t n_gather;       /* directed entries with r_ij < H_i                 */
+    int64_t sell_slots;     /* padded slots of the wave-sliced neighbour table  */
+    int32_t max_neighbours;
+    int32_t h_iter_max;     /* most Newton/bisection iterations of one particle */
+    int64_t n_inject;       /* source-gas injection entries                     */
+    int64_t device_bytes;   /* device memory owned by the context               */
+} rt_stats;
+rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out /* [host] */);
+
+/* Per particle (Morton order): B [n][6] = (B00, B01, B02, B11, B12, B22) of
+ * B_i = E_i^{-1}; n_nbr [n] = |N(i)|, n_gath [n] = |{j : r_ij < H_i}|.
+ * Any pointer may be NULL. */
+rt_status rt_get_geometry(rt_ctx *ctx, double *B, int32_t *n_nbr, int32_t *n_gath);
+
+/* Neighbour lists (Morton indices) as CSR: ptr [n+1] int64, idx [n_entries]
+ * int32; row i lists first the gather neighbours (r_ij < H_i), then the
+ * others, each part in increasing index order. */
+rt_status rt_get_neighbours(rt_ctx *ctx, int64_t *ptr, int32_t *idx);
+
+/* Injection entries (sorted by gas, then source): gas, src [n_inject] int32,
+ * xi [n_inject] double; h_src [S] source smoothing lengths.  NULL allowed. */
+rt_status rt_get_sources(rt_ctx *ctx, int32_t *gas, int32_t *src, double *xi, double *h_src);
+
+/* Kernel timing with HIP events recorded on the context stream around each
+ * launch of the named kernel ("transport", "gradient", "inject", "adjoint").
+ * rt_timing(ctx, 1) starts recording and clears totals; rt_timing(ctx, 0)
+ * stops.  rt_get_timing returns the summed milliseconds and launch count
+ * (synchronising). */
+rt_status rt_timing(rt_ctx *ctx, int32_t on);
+rt_status rt_get_timing(rt_ctx *ctx, const char *kernel, double *ms_total, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEARRT_RT_H */

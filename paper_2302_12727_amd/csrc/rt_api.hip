@@ -1,0 +1,315 @@
+// C ABI of the photon-transport library: argument validation, context
+// lifetime, stream binding, queries and event timing.  The arithmetic lives in
+// rt_build.hip, rt_step.hip and rt_adjoint.hip.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "rt_internal.h"
+
+using namespace gearrt;
+
+static std::string g_create_err;
+
+rt_status rt_fail(rt_ctx *ctx, rt_status st, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    else g_create_err = msg;
+    return st;
+}
+
+rt_status rt_alloc(rt_ctx *ctx, void **ptr, size_t bytes) {
+    *ptr = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return rt_fail(ctx, RT_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                           hipGetErrorString(e));
+    }
+    ctx->device_bytes += (int64_t)bytes;
+    return RT_OK;
+}
+
+void rt_free(void *ptr) {
+    if (ptr) (void)hipFree(ptr);
+}
+
+void rt_timer_begin(rt_ctx *ctx, const char *) {
+    if (!ctx->timing) return;
+    if (ctx->ev_used + 2 > ctx->ev_pool.size()) {
+        for (int k = 0; k < 64; ++k) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            ctx->ev_pool.push_back(e);
+        }
+    }
+    ctx->ev_open = ctx->ev_pool[ctx->ev_used];
+    (void)hipEventRecord(ctx->ev_open, ctx->stream);
+}
+
+void rt_timer_end(rt_ctx *ctx, const char *name) {
+    if (!ctx->timing || !ctx->ev_open) return;
+    hipEvent_t b = ctx->ev_pool[ctx->ev_used + 1];
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->trecs.push_back({name, ctx->ev_open, b});
+    ctx->ev_used += 2;
+    ctx->ev_open = nullptr;
+}
+
+static bool finite_pos(double v) { return v > 0.0 && v < 1e300; }
+
+extern "C" {
+
+rt_status rt_create(const rt_params *p, rt_ctx **out) {
+    if (!out) return rt_fail(nullptr, RT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p) return rt_fail(nullptr, RT_EINVAL, "params is NULL");
+    if (p->n < 1 || p->n > (int64_t(1) << 28))
+        return rt_fail(nullptr, RT_EINVAL, "n must be in [1, 2^28]");
+    if (p->groups < 1 || p->groups > 8) return rt_fail(nullptr, RT_EINVAL, "groups must be in [1, 8]");
+    if (p->precision != RT_FP64 && p->precision != RT_FP32C)
+        return rt_fail(nullptr, RT_EINVAL, "precision must be RT_FP64 or RT_FP32C");
+    if (!finite_pos(p->box)) return rt_fail(nullptr, RT_EINVAL, "box must be positive");
+    if (!finite_pos(p->eta)) return rt_fail(nullptr, RT_EINVAL, "eta must be positive");
+    if (!finite_pos(p->kappa)) return rt_fail(nullptr, RT_EINVAL, "kappa must be positive");
+    if (!finite_pos(p->c_red)) return rt_fail(nullptr, RT_EINVAL, "c_red must be positive");
+    if (!finite_pos(p->cfl)) return rt_fail(nullptr, RT_EINVAL, "cfl must be positive");
+    rt_ctx *ctx = new (std::nothrow) rt_ctx();
+    if (!ctx) return rt_fail(nullptr, RT_ENOMEM, "host allocation failed");
+    ctx->p = *p;
+    ctx->stream = (hipStream_t)p->hip_stream;
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return rt_fail(nullptr, RT_EHIP, "no HIP device");
+    }
+    rt_status rs;
+    if ((rs = rt_alloc(ctx, (void **)&ctx->status, sizeof(int32_t))) != RT_OK ||
+        (rs = rt_alloc(ctx, (void **)&ctx->dt_dev, sizeof(double))) != RT_OK) {
+        g_create_err = ctx->err;
+        rt_destroy(ctx);
+        return rs;
+    }
+    if (hipMemset(ctx->status, 0, sizeof(int32_t)) != hipSuccess) {
+        rt_destroy(ctx);
+        return rt_fail(nullptr, RT_EHIP, "hipMemset failed");
+    }
+    *out = ctx;
+    return RT_OK;
+}
+
+void rt_destroy(rt_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    void *bufs[] = {ctx->xs, ctx->geo, ctx->geo32, ctx->perm32, ctx->keys, ctx->dt_dev,
+                    ctx->h_iters, ctx->node_lo, ctx->node_hi, ctx->node_hmax, ctx->n_nbr,
+                    ctx->n_gath, ctx->wave_base, ctx->nbr, ctx->src_h, ctx->inj_gptr,
+                    ctx->inj_gas, ctx->inj_src, ctx->inj_coef, ctx->inj_xi, ctx->src_ptr,
+                    ctx->src_gas, ctx->src_coef, ctx->status, ctx->partials, ctx->scan_tmp,
+                    ctx->adj_buf};
+    for (void *b : bufs) rt_free(b);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+const char *rt_last_error(const rt_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+rt_status rt_set_stream(rt_ctx *ctx, void *s) {
+    if (!ctx) return RT_EINVAL;
+    ctx->stream = (hipStream_t)s;
+    ctx->p.hip_stream = s;
+    return RT_OK;
+}
+
+rt_status rt_build_cells(rt_ctx *ctx, const double *x, const double *h_in, int64_t *perm,
+                         double *h, double *V, double *dt) {
+    if (!ctx) return RT_EINVAL;
+    if (!x || !h || !V) return rt_fail(ctx, RT_EINVAL, "x, h and V are required");
+    return rt_build_impl(ctx, x, h_in, perm, h, V, dt);
+}
+
+rt_status rt_set_sources(rt_ctx *ctx, int32_t n_src, const double *xs, double eta_star) {
+    if (!ctx) return RT_EINVAL;
+    if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
+    if (n_src < 0 || n_src > (1 << 20)) return rt_fail(ctx, RT_EINVAL, "n_src out of range");
+    if (n_src > 0 && !xs) return rt_fail(ctx, RT_EINVAL, "xs is NULL");
+    if (n_src > 0 && !finite_pos(eta_star)) return rt_fail(ctx, RT_EINVAL, "eta_star must be positive");
+    return rt_sources_impl(ctx, n_src, xs, eta_star);
+}
+
+rt_status rt_inject(rt_ctx *ctx, void *U, const double *L, const double *dt) {
+    if (!ctx) return RT_EINVAL;
+    if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
+    if (ctx->S == 0) return RT_OK;
+    if (!U || !L || !dt) return rt_fail(ctx, RT_EINVAL, "U, L and dt are required");
+    return rt_inject_impl(ctx, U, L, dt);
+}
+
+static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + nb && y < x + na;
+}
+
+rt_status rt_gradient(rt_ctx *ctx, const void *U, void *dU) {
+    if (!ctx) return RT_EINVAL;
+    if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
+    if (!U || !dU) return rt_fail(ctx, RT_EINVAL, "U and dU are required");
+    size_t es = ctx->p.precision == RT_FP64 ? 8 : 4;
+    size_t nu = es * 4 * ctx->p.groups * ctx->p.n;
+    if (overlap(U, nu, dU, 3 * nu)) return rt_fail(ctx, RT_EINVAL, "U and dU overlap");
+    return rt_gradient_impl(ctx, U, dU);
+}
+
+rt_status rt_transport(rt_ctx *ctx, const void *U, const void *dU, const double *dt,
+                       void *U_out, double *photon_total, int64_t *counts, double *ledger,
+                       uint8_t *guard_mask) {
+    if (!ctx) return RT_EINVAL;
+    if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
+    if (!U || !dU || !dt || !U_out) return rt_fail(ctx, RT_EINVAL, "U, dU, dt and U_out are required");
+    size_t es = ctx->p.precision == RT_FP64 ? 8 : 4;
+    size_t nu = es * 4 * ctx->p.groups * ctx->p.n;
+    if (overlap(U, nu, U_out, nu)) return rt_fail(ctx, RT_EINVAL, "U and U_out overlap");
+    if (overlap(dU, 3 * nu, U_out, nu)) return rt_fail(ctx, RT_EINVAL, "dU and U_out overlap");
+    return rt_transport_impl(ctx, U, dU, dt, U_out, photon_total, counts, ledger, guard_mask);
+}
+
+rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q) {
+    if (!ctx) return RT_EINVAL;
+    if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
+    if (!U || !Q) return rt_fail(ctx, RT_EINVAL, "U and Q are required");
+    return rt_total_impl(ctx, U, Q);
+}
+
+rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
+                     const void *dU, const uint8_t *guard_mask, const void *lam_next,
+                     void *lam, double *dL_dL) {
+    if (!ctx) return RT_EINVAL;
+    if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
+    if (!U_pre || !dt || !lam_next || !lam)
+        return rt_fail(ctx, RT_EINVAL, "U_pre, dt, lam_next and lam are required");
+    if (ctx->S > 0 && !L) return rt_fail(ctx, RT_EINVAL, "L is required when sources are set");
+    return rt_adjoint_impl(ctx, U_pre, L, dt, dU, guard_mask, lam_next, lam, dL_dL);
+}
+
+rt_status rt_sync(rt_ctx *ctx) {
+    if (!ctx) return RT_EINVAL;
+    RT_HIP(hipStreamSynchronize(ctx->stream));
+    RT_HIP(hipGetLastError());
+    int32_t st = 0;
+    RT_HIP(hipMemcpy(&st, ctx->status, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (st) RT_HIP(hipMemset(ctx->status, 0, sizeof(int32_t)));
+    if (st & ST_NOCONV) return rt_fail(ctx, RT_ENOCONV, "smoothing length did not converge");
+    if (st & ST_SINGULAR) return rt_fail(ctx, RT_ESINGULAR, "E_i not positive definite");
+    if (st & ST_BIGH) return rt_fail(ctx, RT_EINVAL, "compact support reaches half the box");
+    return RT_OK;
+}
+
+rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out) {
+    if (!ctx || !out) return RT_EINVAL;
+    memset(out, 0, sizeof *out);
+    out->n = ctx->p.n;
+    out->n_entries = ctx->n_entries;
+    out->n_pairs = ctx->n_entries / 2;
+    out->n_gather = ctx->n_gather_entries;
+    out->sell_slots = ctx->slots;
+    out->max_neighbours = ctx->max_nbr;
+    out->h_iter_max = ctx->h_iter_max;
+    out->n_inject = ctx->n_inj;
+    out->device_bytes = ctx->device_bytes;
+    return RT_OK;
+}
+
+rt_status rt_get_geometry(rt_ctx *ctx, double *B, int32_t *n_nbr, int32_t *n_gath) {
+    if (!ctx) return RT_EINVAL;
+    if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
+    const int64_t n = ctx->p.n;
+    RT_HIP(hipStreamSynchronize(ctx->stream));
+    if (B) {
+        // B_i = E_i^{-1} = Bv_i / (V_i^2 sigma / H_i^3)
+        std::vector<double> rec((size_t)n * kRec), out((size_t)n * 6);
+        RT_HIP(hipMemcpy(rec.data(), ctx->geo, sizeof(double) * kRec * n, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) {
+            const double *r = &rec[(size_t)i * kRec];
+            double iH = r[R_IH], V = r[R_V];
+            double f = 1.0 / (V * V * kSigma3 * iH * iH * iH);
+            for (int a = 0; a < 6; ++a) out[(size_t)i * 6 + a] = r[R_B + a] * f;
+        }
+        RT_HIP(hipMemcpy(B, out.data(), sizeof(double) * 6 * n, hipMemcpyHostToDevice));
+    }
+    if (n_nbr) RT_HIP(hipMemcpy(n_nbr, ctx->n_nbr, sizeof(int32_t) * n, hipMemcpyDeviceToDevice));
+    if (n_gath) RT_HIP(hipMemcpy(n_gath, ctx->n_gath, sizeof(int32_t) * n, hipMemcpyDeviceToDevice));
+    return RT_OK;
+}
+
+rt_status rt_get_neighbours(rt_ctx *ctx, int64_t *ptr, int32_t *idx) {
+    if (!ctx) return RT_EINVAL;
+    if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
+    const int64_t n = ctx->p.n;
+    RT_HIP(hipStreamSynchronize(ctx->stream));
+    std::vector<int32_t> nn(n), table((size_t)std::max<int64_t>(ctx->slots, 1));
+    std::vector<int64_t> wb(ctx->nwaves + 1), hp(n + 1);
+    RT_HIP(hipMemcpy(nn.data(), ctx->n_nbr, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    RT_HIP(hipMemcpy(wb.data(), ctx->wave_base, sizeof(int64_t) * (ctx->nwaves + 1), hipMemcpyDeviceToHost));
+    RT_HIP(hipMemcpy(table.data(), ctx->nbr, sizeof(int32_t) * std::max<int64_t>(ctx->slots, 1),
+                     hipMemcpyDeviceToHost));
+    hp[0] = 0;
+    for (int64_t i = 0; i < n; ++i) hp[i + 1] = hp[i] + nn[i];
+    std::vector<int32_t> hi((size_t)std::max<int64_t>(hp[n], 1));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t base = wb[i >> 6] + (i & 63);
+        for (int32_t k = 0; k < nn[i]; ++k) hi[hp[i] + k] = table[base + 64 * (int64_t)k];
+    }
+    if (ptr) RT_HIP(hipMemcpy(ptr, hp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    if (idx && hp[n] > 0) RT_HIP(hipMemcpy(idx, hi.data(), sizeof(int32_t) * hp[n], hipMemcpyHostToDevice));
+    return RT_OK;
+}
+
+rt_status rt_get_sources(rt_ctx *ctx, int32_t *gas, int32_t *src, double *xi, double *h_src) {
+    if (!ctx) return RT_EINVAL;
+    RT_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->S == 0) return RT_OK;
+    std::vector<int32_t> gp(ctx->n_inj_gas + 1), g(ctx->n_inj_gas), full(ctx->n_inj);
+    RT_HIP(hipMemcpy(gp.data(), ctx->inj_gptr, sizeof(int32_t) * (ctx->n_inj_gas + 1), hipMemcpyDeviceToHost));
+    RT_HIP(hipMemcpy(g.data(), ctx->inj_gas, sizeof(int32_t) * ctx->n_inj_gas, hipMemcpyDeviceToHost));
+    for (int32_t t = 0; t < ctx->n_inj_gas; ++t)
+        for (int32_t e = gp[t]; e < gp[t + 1]; ++e) full[e] = g[t];
+    if (gas) RT_HIP(hipMemcpy(gas, full.data(), sizeof(int32_t) * ctx->n_inj, hipMemcpyHostToDevice));
+    if (src) RT_HIP(hipMemcpy(src, ctx->inj_src, sizeof(int32_t) * ctx->n_inj, hipMemcpyDeviceToDevice));
+    if (xi) RT_HIP(hipMemcpy(xi, ctx->inj_xi, sizeof(double) * ctx->n_inj, hipMemcpyDeviceToDevice));
+    if (h_src) RT_HIP(hipMemcpy(h_src, ctx->src_h, sizeof(double) * ctx->S, hipMemcpyDeviceToDevice));
+    return RT_OK;
+}
+
+rt_status rt_timing(rt_ctx *ctx, int32_t on) {
+    if (!ctx) return RT_EINVAL;
+    if (on) {
+        RT_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->trecs.clear();
+        ctx->ev_used = 0;
+    }
+    ctx->timing = on ? 1 : 0;
+    return RT_OK;
+}
+
+rt_status rt_get_timing(rt_ctx *ctx, const char *kernel, double *ms_total, int64_t *launches) {
+    if (!ctx || !kernel) return RT_EINVAL;
+    RT_HIP(hipStreamSynchronize(ctx->stream));
+    double ms = 0.0;
+    int64_t cnt = 0;
+    for (auto &r : ctx->trecs) {
+        if (r.name != kernel) continue;
+        float t = 0.0f;
+        RT_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        ms += t;
+        ++cnt;
+    }
+    if (ms_total) *ms_total = ms;
+    if (launches) *launches = cnt;
+    return RT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,767 @@
+// Static geometry of the particle set: Morton order, search tree, smoothing
+// lengths, wave-sliced neighbour table, particle volumes and the inverse
+// least-squares matrices, global time step; point-source injection weights.
+//
+// Particles are static interpolation points for the radiation (Part III,
+// "Using a particle based method: selecting reference frames"), so everything
+// here is computed once and reused by every transport step.
+#include <cstring>
+
+#include <rocprim/rocprim.hpp>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "rt_internal.h"
+
+using namespace gearrt;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Morton keys: 21 bits per axis, interleaved into 63 bits.
+__device__ __forceinline__ uint64_t spread21(uint64_t v) {
+    v &= 0x1fffffULL;
+    v = (v | (v << 32)) & 0x1f00000000ffffULL;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffULL;
+    v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
+    v = (v | (v << 2)) & 0x1249249249249249ULL;
+    return v;
+}
+
+__global__ void k_morton(int64_t n, const double *__restrict__ x, double ibox,
+                         uint64_t *__restrict__ keys, int32_t *__restrict__ idx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double f = x[3 * i + a] * ibox;
+        f = fmin(fmax(f, 0.0), 1.0);
+        uint64_t q = (uint64_t)(f * 2097152.0);
+        c[a] = q > 2097151ULL ? 2097151ULL : q;
+    }
+    keys[i] = (spread21(c[0]) << 2) | (spread21(c[1]) << 1) | spread21(c[2]);
+    idx[i] = (int32_t)i;
+}
+
+__global__ void k_gather_sorted(int64_t n, const double *__restrict__ x,
+                                const int32_t *__restrict__ perm, const double *__restrict__ h_in,
+                                double *__restrict__ xs, double *__restrict__ h,
+                                int64_t *__restrict__ perm_out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t j = perm[i];
+    xs[3 * i + 0] = x[3 * j + 0];
+    xs[3 * i + 1] = x[3 * j + 1];
+    xs[3 * i + 2] = x[3 * j + 2];
+    if (h_in) h[i] = h_in[j];
+    if (perm_out) perm_out[i] = j;
+}
+
+// ---------------------------------------------------------------------------
+// Search tree: leaves of kLeaf consecutive Morton-ordered particles, complete
+// binary tree in heap layout above them.  Every node holds the bounding box
+// of its particles and the largest compact support radius H below it.
+__global__ void k_leaf_boxes(int64_t n, int64_t nleaf, int64_t P, const double *__restrict__ xs,
+                             const double *__restrict__ H, double *__restrict__ lo,
+                             double *__restrict__ hi, double *__restrict__ hmax) {
+    int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= P) return;
+    int64_t v = P + l;
+    double bl[3] = {INFINITY, INFINITY, INFINITY}, bh[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double hm = 0.0;
+    if (l < nleaf) {
+        int64_t j0 = l * kLeaf, j1 = min(n, j0 + kLeaf);
+        for (int64_t j = j0; j < j1; ++j) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                bl[a] = fmin(bl[a], xs[3 * j + a]);
+                bh[a] = fmax(bh[a], xs[3 * j + a]);
+            }
+            if (H) hm = fmax(hm, H[j]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[3 * v + a] = bl[a];
+        hi[3 * v + a] = bh[a];
+    }
+    hmax[v] = hm;
+}
+
+__global__ void k_merge_level(int64_t first, int64_t count, double *__restrict__ lo,
+                              double *__restrict__ hi, double *__restrict__ hmax) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    int64_t v = first + t, a = 2 * v, b = 2 * v + 1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[3 * v + d] = fmin(lo[3 * a + d], lo[3 * b + d]);
+        hi[3 * v + d] = fmax(hi[3 * a + d], hi[3 * b + d]);
+    }
+    hmax[v] = fmax(hmax[a], hmax[b]);
+}
+
+struct Tree {
+    const double *lo, *hi, *hmax;
+    int64_t P;
+};
+
+// ---------------------------------------------------------------------------
+// Smoothing length: root of g(h) = h^3 sum_j W(r_j, kappa h) - eta^3
+// (eq:number-of-neighbors), i.e. (sigma/kappa^3) sum_j w(r_j / (kappa h)) = eta^3,
+// by Newton-Raphson safeguarded with bisection.  Each evaluation of g and
+// dg/dh walks the tree with radius kappa h.
+__device__ void h_eval(const Tree &T, const double *__restrict__ xs, int64_t n, double px,
+                       double py, double pz, double h, double kappa, double box, double ibox,
+                       double &sw, double &sdw) {
+    const double H = kappa * h, H2 = H * H, iH = 1.0 / H;
+    const double acc2 = H2 * (1.0 + 1e-12);
+    double a = 0.0, b = 0.0;
+    traverse(
+        T.P,
+        [&](int64_t v) { return box_dist2(T.lo + 3 * v, T.hi + 3 * v, px, py, pz, box) < acc2; },
+        [&](int64_t l) {
+            int64_t j0 = l * kLeaf, j1 = min(n, j0 + kLeaf);
+            for (int64_t j = j0; j < j1; ++j) {
+                double sx = min_image(xs[3 * j] - px, box, ibox);
+                double sy = min_image(xs[3 * j + 1] - py, box, ibox);
+                double sz = min_image(xs[3 * j + 2] - pz, box, ibox);
+                double r2 = sx * sx + sy * sy + sz * sz;
+                if (r2 < H2) {
+                    double q = sqrt(r2) * iH;
+                    a += kern_w(q);
+                    b += kern_dw(q) * q;
+                }
+            }
+        });
+    sw = a;
+    sdw = b;
+}
+
+__device__ double h_solve_point(const Tree &T, const double *__restrict__ xs, int64_t n,
+                                double px, double py, double pz, double h0, double eta,
+                                double kappa, double box, double hcap, int32_t &iters,
+                                int32_t &flags) {
+    const double pref = kSigma3 / (kappa * kappa * kappa);
+    const double eta3 = eta * eta * eta;
+    const double eps4 = 4.0 * 2.220446049250313e-16;
+    const double ibox = 1.0 / box;
+    double lo = 0.0, hi = INFINITY, h = h0;
+    int32_t it = 0;
+    bool ok = false;
+    for (it = 0; it < 200; ++it) {
+        if (h > hcap) {      // compact support would exceed half the box
+            flags |= ST_BIGH;
+            break;
+        }
+        double sw, sdw;
+        h_eval(T, xs, n, px, py, pz, h, kappa, box, ibox, sw, sdw);
+        double g = pref * sw - eta3;
+        double dg = -pref * sdw / h;
+        if (g == 0.0) {
+            ok = true;
+            break;
+        }
+        if (g < 0.0) lo = h; else hi = h;
+        double hn;
+        if (hi == INFINITY) {
+            hn = 2.0 * h;                        // expand until bracketed
+            if (dg > 0.0) {
+                double nt = h - g / dg;
+                if (nt > h && nt < 4.0 * h) hn = nt;
+            }
+        } else {
+            hn = (dg > 0.0) ? h - g / dg : -1.0;
+            if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
+            if (fabs(hn - h) <= eps4 * h || hi - lo <= eps4 * hi) {
+                h = hn;
+                ok = true;
+                break;
+            }
+        }
+        h = hn;
+    }
+    iters = it;
+    if (!ok) flags |= ST_NOCONV;
+    return h;
+}
+
+__global__ void k_h_guess(int64_t n, int64_t P, const double *__restrict__ lo,
+                          const double *__restrict__ hi, double eta, double box,
+                          double *__restrict__ h) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t l = i / kLeaf, v = P + l;
+    int64_t cnt = min((int64_t)kLeaf, n - l * kLeaf);
+    double ext = 1.0;
+    double floor_ext = box / 2097152.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ext *= fmax(hi[3 * v + a] - lo[3 * v + a], floor_ext);
+    double g = eta * cbrt(ext / (double)cnt);
+    h[i] = fmin(g, 0.25 * box);
+}
+
+__global__ void k_h_solve(int64_t n, Tree T, const double *__restrict__ xs, double eta,
+                          double kappa, double box, double *__restrict__ h,
+                          int32_t *__restrict__ iters, int32_t *__restrict__ status) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t it = 0, fl = 0;
+    double hcap = 0.5 * box / kappa;
+    double hv = h_solve_point(T, xs, n, xs[3 * i], xs[3 * i + 1], xs[3 * i + 2],
+                              fmin(h[i], 0.5 * hcap), eta, kappa, box, hcap, it, fl);
+    h[i] = hv;
+    iters[i] = it;
+    if (fl) atomicOr(status, fl);
+}
+
+__global__ void k_scale(int64_t n, const double *__restrict__ a, double s, double *__restrict__ b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = s * a[i];
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour lists N(i) = { j != i : r_ij < max(H_i, H_j) }: a pair exchanges
+// flux whenever one of the two kernels reaches the other particle (then
+// A_ij != 0).  The tree is opened when the node is within max(H_i, Hmax_node).
+template <bool FILL>
+__global__ void k_neighbours(int64_t n, Tree T, const double *__restrict__ xs,
+                             const double *__restrict__ H, double box,
+                             int32_t *__restrict__ n_nbr, int32_t *__restrict__ n_gath,
+                             const int64_t *__restrict__ wave_base, int32_t *__restrict__ nbr) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double ibox = 1.0 / box;
+    const double px = xs[3 * i], py = xs[3 * i + 1], pz = xs[3 * i + 2];
+    const double Hi = H[i], Hi2 = Hi * Hi;
+    int32_t cg = 0, cs = 0;
+    int64_t base = 0;
+    int32_t gcount = 0, scount = 0;
+    if (FILL) {
+        base = wave_base[i >> 6] + (i & 63);
+        gcount = n_gath[i];
+        scount = n_nbr[i] - gcount;
+    }
+    traverse(
+        T.P,
+        [&](int64_t v) {
+            double R = fmax(Hi, T.hmax[v]);
+            return box_dist2(T.lo + 3 * v, T.hi + 3 * v, px, py, pz, box) < R * R * (1.0 + 1e-12);
+        },
+        [&](int64_t l) {
+            int64_t j0 = l * kLeaf, j1 = min(n, j0 + kLeaf);
+            for (int64_t j = j0; j < j1; ++j) {
+                if (j == i) continue;
+                double sx = min_image(xs[3 * j] - px, box, ibox);
+                double sy = min_image(xs[3 * j + 1] - py, box, ibox);
+                double sz = min_image(xs[3 * j + 2] - pz, box, ibox);
+                double r2 = sx * sx + sy * sy + sz * sz;
+                double Hj = H[j];
+                // the fill pass repeats the count pass exactly; the bounds only
+                // keep a lane inside its own column of the wave's slice
+                if (r2 < Hi2) {
+                    if (FILL && cg < gcount) nbr[base + 64 * (int64_t)cg] = (int32_t)j;
+                    ++cg;
+                } else if (r2 < Hj * Hj) {
+                    if (FILL && cs < scount) nbr[base + 64 * (int64_t)(gcount + cs)] = (int32_t)j;
+                    ++cs;
+                }
+            }
+        });
+    if (!FILL) {
+        n_nbr[i] = cg + cs;
+        n_gath[i] = cg;
+    }
+}
+
+__global__ void k_wave_width(int64_t n, int64_t nwaves, const int32_t *__restrict__ n_nbr,
+                             int64_t *__restrict__ width) {
+    int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w > nwaves) return;
+    if (w == nwaves) {
+        width[w] = 0;
+        return;
+    }
+    int32_t m = 0;
+    int64_t i0 = w * 64, i1 = min(n, i0 + 64);
+    for (int64_t i = i0; i < i1; ++i) m = max(m, n_nbr[i]);
+    width[w] = 64 * (int64_t)m;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry (Part II "Partition of unity" and "Finite volume particle methods
+// following Hopkins"): with w_ij = w(r_ij / H_i),
+//   omega_i = (sigma/H_i^3) (w(0) + sum_j w_ij),  V_i = 1/omega_i,
+//   E_i = sum_j s s^T psi_j(x_i) = (sigma/H_i^3) V_i S_i,  S_i = sum_j w_ij s s^T,
+//   B_i = E_i^{-1} = S_i^{-1} / ((sigma/H_i^3) V_i).
+// The record keeps Bv_i = V_i^2 (sigma/H_i^3) B_i = V_i S_i^{-1}, so that
+//   A_kl = V_k psi~_l(x_k) - V_l psi~_k(x_l) = (w_kl Bv_k + w_lk Bv_l) s_kl.
+// S_i is inverted in FP64 by cofactors.
+__global__ void k_geometry(int64_t n, const double *__restrict__ xs, const double *__restrict__ h,
+                           double kappa, double box, const int32_t *__restrict__ n_gath,
+                           const int64_t *__restrict__ wave_base, const int32_t *__restrict__ nbr,
+                           double *__restrict__ geo, float *__restrict__ geo32,
+                           double *__restrict__ V_out, double *__restrict__ dxmin_part,
+                           int32_t *__restrict__ status) {
+    __shared__ double sm[kBlock / kWave];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double dx = INFINITY;
+    if (i < n) {
+        const double ibox = 1.0 / box;
+        const double px = xs[3 * i], py = xs[3 * i + 1], pz = xs[3 * i + 2];
+        const double hi_ = h[i], H = kappa * hi_, iH = 1.0 / H;
+        const int64_t base = wave_base[i >> 6] + (i & 63);
+        const int32_t ng = n_gath[i];
+        double sw = 0.0, s00 = 0, s01 = 0, s02 = 0, s11 = 0, s12 = 0, s22 = 0;
+        for (int32_t k = 0; k < ng; ++k) {
+            int64_t j = nbr[base + 64 * (int64_t)k];
+            double sx = min_image(xs[3 * j] - px, box, ibox);
+            double sy = min_image(xs[3 * j + 1] - py, box, ibox);
+            double sz = min_image(xs[3 * j + 2] - pz, box, ibox);
+            double r = sqrt(sx * sx + sy * sy + sz * sz);
+            double w = kern_w(r * iH);
+            sw += w;
+            s00 += w * sx * sx; s01 += w * sx * sy; s02 += w * sx * sz;
+            s11 += w * sy * sy; s12 += w * sy * sz; s22 += w * sz * sz;
+        }
+        double wnorm = kSigma3 * iH * iH * iH;
+        double omega = wnorm * (0.5 + sw);
+        double V = 1.0 / omega;
+        // cofactor inverse of the symmetric S
+        double c00 = s11 * s22 - s12 * s12;
+        double c01 = s02 * s12 - s01 * s22;
+        double c02 = s01 * s12 - s02 * s11;
+        double c11 = s00 * s22 - s02 * s02;
+        double c12 = s01 * s02 - s00 * s12;
+        double c22 = s00 * s11 - s01 * s01;
+        double det = s00 * c00 + s01 * c01 + s02 * c02;
+        double tr = s00 + s11 + s22;
+        if (!(det > 1e-12 * tr * tr * tr / 27.0)) {
+            atomicOr(status, ST_SINGULAR);
+            det = INFINITY;   // zero matrix: no gradient, no surface from this side
+        }
+        double f = V / det;
+        double *rec = geo + (int64_t)kRec * i;
+        rec[R_X + 0] = px;
+        rec[R_X + 1] = py;
+        rec[R_X + 2] = pz;
+        rec[R_IH] = iH;
+        rec[R_H] = hi_;
+        rec[R_V] = V;
+        rec[R_B + 0] = f * c00;
+        rec[R_B + 1] = f * c01;
+        rec[R_B + 2] = f * c02;
+        rec[R_B + 3] = f * c11;
+        rec[R_B + 4] = f * c12;
+        rec[R_B + 5] = f * c22;
+        if (geo32) {
+            float *r32 = geo32 + (int64_t)F_REC * i;
+            r32[F_IH] = (float)iH;
+            r32[F_H] = (float)hi_;
+            r32[F_V] = (float)V;
+            r32[F_B + 0] = (float)(f * c00);
+            r32[F_B + 1] = (float)(f * c01);
+            r32[F_B + 2] = (float)(f * c02);
+            r32[F_B + 3] = (float)(f * c11);
+            r32[F_B + 4] = (float)(f * c12);
+            r32[F_B + 5] = (float)(f * c22);
+            r32[F_B + 6] = 0.0f;
+        }
+        V_out[i] = V;
+        dx = cbrt(V * (3.0 / (4.0 * kPi)));
+    }
+    // block minimum of dx
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dx = fmin(dx, __shfl_down(dx, o, 64));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = dx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = sm[0];
+        for (int w = 1; w < kBlock / kWave; ++w) m = fmin(m, sm[w]);
+        dxmin_part[blockIdx.x] = m;
+    }
+}
+
+__global__ void k_dt(int64_t nb, const double *__restrict__ part, double cfl, double c,
+                     double *__restrict__ dt) {
+    __shared__ double sm[kBlock];
+    double m = INFINITY;
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) m = fmin(m, part[b]);
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dt[0] = cfl * sm[0] / c;
+}
+
+__global__ void k_copy_dt(const double *__restrict__ a, double *__restrict__ b) { b[0] = a[0]; }
+
+// ---------------------------------------------------------------------------
+// Sources (Part III "Weights for distribution of energy density of a star onto
+// particles"): smoothing length of the source over the gas, then
+//   psi_sg = W(r_sg, H_s) / sum_g' W(r_sg', H_s),
+//   octant a(g) from the signs of x_g - x_s (components >= 0 count as +),
+//   w_a = sum_{g in a} psi_sg,  mu_a = sum_b w_b / (q_nz w_a),
+//   xi_sg = mu_a psi_sg   (eq:isotropy-correction-with-zero).
+__global__ void k_src_h(int32_t S, Tree T, const double *__restrict__ xs, int64_t n,
+                        const double *__restrict__ src_x, double eta, double kappa, double box,
+                        double h0, double *__restrict__ src_h, int32_t *__restrict__ status) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    int32_t it = 0, fl = 0;
+    double hcap = 0.5 * box / kappa;
+    src_h[s] = h_solve_point(T, xs, n, src_x[3 * s], src_x[3 * s + 1], src_x[3 * s + 2], h0,
+                             eta, kappa, box, hcap, it, fl);
+    if (fl) atomicOr(status, fl);
+}
+
+template <bool FILL>
+__global__ void k_src_gas(int32_t S, Tree T, const double *__restrict__ xs, int64_t n,
+                          const double *__restrict__ src_x, const double *__restrict__ src_h,
+                          double kappa, double box, const double *__restrict__ geo,
+                          int32_t *__restrict__ cnt, const int32_t *__restrict__ ptr,
+                          int32_t *__restrict__ gas, double *__restrict__ xi,
+                          double *__restrict__ coef) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const double ibox = 1.0 / box;
+    const double px = src_x[3 * s], py = src_x[3 * s + 1], pz = src_x[3 * s + 2];
+    const double H = kappa * src_h[s], H2 = H * H, iH = 1.0 / H;
+    int32_t c = 0;
+    int32_t o = FILL ? ptr[s] : 0;
+    int32_t cap = FILL ? ptr[s + 1] - ptr[s] : 0;
+    double wa[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    traverse(
+        T.P,
+        [&](int64_t v) {
+            return box_dist2(T.lo + 3 * v, T.hi + 3 * v, px, py, pz, box) < H2 * (1.0 + 1e-12);
+        },
+        [&](int64_t l) {
+            int64_t j0 = l * kLeaf, j1 = min(n, j0 + kLeaf);
+            for (int64_t j = j0; j < j1; ++j) {
+                double sx = min_image(xs[3 * j] - px, box, ibox);
+                double sy = min_image(xs[3 * j + 1] - py, box, ibox);
+                double sz = min_image(xs[3 * j + 2] - pz, box, ibox);
+                double r2 = sx * sx + sy * sy + sz * sz;
+                if (r2 < H2) {
+                    if (FILL && c < cap) {
+                        double w = kern_w(sqrt(r2) * iH);
+                        int oc = (sx >= 0.0) | ((sy >= 0.0) << 1) | ((sz >= 0.0) << 2);
+                        gas[o + c] = (int32_t)j;
+                        xi[o + c] = w;
+                        coef[o + c] = (double)oc;   // octant, replaced below
+                        wa[oc] += w;
+                    }
+                    ++c;
+                }
+            }
+        });
+    if (!FILL) {
+        cnt[s] = c;
+        return;
+    }
+    int qnz = 0;
+    for (int a = 0; a < 8; ++a) qnz += wa[a] > 0.0;
+    // xi_sg = mu_a psi_sg with psi_sg = w_sg / wsum and w_a in units of wsum:
+    // mu_a psi_sg = (wsum / (q_nz wa_a)) (w_sg / wsum) = w_sg / (q_nz wa_a)
+    if (c > cap) c = cap;
+    for (int32_t e = 0; e < c; ++e) {
+        int oc = (int)coef[o + e];
+        double x_ = xi[o + e] > 0.0 ? xi[o + e] / ((double)qnz * wa[oc]) : 0.0;
+        xi[o + e] = x_;
+        coef[o + e] = x_ / geo[(int64_t)kRec * gas[o + e] + R_V];
+    }
+}
+
+inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+
+static void build_tree(rt_ctx *ctx, const double *H) {
+    int64_t P = ctx->P;
+    k_leaf_boxes<<<nblk(P), kBlock, 0, ctx->stream>>>(ctx->p.n, ctx->nleaf, P, ctx->xs, H,
+                                                      ctx->node_lo, ctx->node_hi, ctx->node_hmax);
+    for (int64_t first = P / 2; first >= 1; first /= 2)
+        k_merge_level<<<nblk(first), kBlock, 0, ctx->stream>>>(first, first, ctx->node_lo,
+                                                               ctx->node_hi, ctx->node_hmax);
+}
+
+rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_t *perm,
+                        double *h, double *V, double *dt) {
+    const int64_t n = ctx->p.n;
+    hipStream_t st = ctx->stream;
+    rt_status rs;
+    // (re)allocate everything owned by a previous build
+    rt_free(ctx->xs); rt_free(ctx->geo); rt_free(ctx->geo32); rt_free(ctx->perm32);
+    rt_free(ctx->keys); rt_free(ctx->h_iters); rt_free(ctx->node_lo); rt_free(ctx->node_hi);
+    rt_free(ctx->node_hmax); rt_free(ctx->n_nbr); rt_free(ctx->n_gath); rt_free(ctx->wave_base);
+    rt_free(ctx->nbr);
+    ctx->xs = nullptr; ctx->geo = nullptr; ctx->geo32 = nullptr; ctx->perm32 = nullptr;
+    ctx->keys = nullptr; ctx->h_iters = nullptr; ctx->node_lo = nullptr; ctx->node_hi = nullptr;
+    ctx->node_hmax = nullptr; ctx->n_nbr = nullptr; ctx->n_gath = nullptr;
+    ctx->wave_base = nullptr; ctx->nbr = nullptr;
+    ctx->device_bytes = 0;
+    ctx->built = 0;
+
+    ctx->nleaf = (n + kLeaf - 1) / kLeaf;
+    ctx->P = 1;
+    while (ctx->P < ctx->nleaf) ctx->P *= 2;
+    ctx->nwaves = (n + 63) / 64;
+
+    uint64_t *keys_in = nullptr;
+    int32_t *idx_in = nullptr;
+    double *Htmp = nullptr, *dxpart = nullptr;
+    int64_t *width = nullptr;
+    void *sort_tmp = nullptr;
+    size_t sort_bytes = 0;
+
+#define ALLOC(p, bytes)                                              \
+    do {                                                             \
+        if ((rs = rt_alloc(ctx, (void **)&(p), (bytes))) != RT_OK) goto fail; \
+    } while (0)
+
+    ALLOC(ctx->xs, sizeof(double) * 3 * n);
+    ALLOC(ctx->geo, sizeof(double) * kRec * n);
+    if (ctx->p.precision == RT_FP32C) ALLOC(ctx->geo32, sizeof(float) * F_REC * n);
+    ALLOC(ctx->perm32, sizeof(int32_t) * n);
+    ALLOC(ctx->keys, sizeof(uint64_t) * n);
+    ALLOC(ctx->h_iters, sizeof(int32_t) * n);
+    ALLOC(ctx->node_lo, sizeof(double) * 3 * 2 * ctx->P);
+    ALLOC(ctx->node_hi, sizeof(double) * 3 * 2 * ctx->P);
+    ALLOC(ctx->node_hmax, sizeof(double) * 2 * ctx->P);
+    ALLOC(ctx->n_nbr, sizeof(int32_t) * n);
+    ALLOC(ctx->n_gath, sizeof(int32_t) * n);
+    ALLOC(ctx->wave_base, sizeof(int64_t) * (ctx->nwaves + 1));
+    ALLOC(keys_in, sizeof(uint64_t) * n);
+    ALLOC(idx_in, sizeof(int32_t) * n);
+    ALLOC(Htmp, sizeof(double) * n);
+    ALLOC(width, sizeof(int64_t) * (ctx->nwaves + 1));
+    ALLOC(dxpart, sizeof(double) * nblk(n));
+
+    {
+        // Morton order
+        k_morton<<<nblk(n), kBlock, 0, st>>>(n, x, 1.0 / ctx->p.box, keys_in, idx_in);
+        if (rocprim::radix_sort_pairs(nullptr, sort_bytes, keys_in, ctx->keys, idx_in,
+                                      ctx->perm32, (size_t)n, 0, 63, st) != hipSuccess) {
+            rs = rt_fail(ctx, RT_EHIP, "radix sort size query failed");
+            goto fail;
+        }
+        ALLOC(sort_tmp, sort_bytes);
+        if (rocprim::radix_sort_pairs(sort_tmp, sort_bytes, keys_in, ctx->keys, idx_in,
+                                      ctx->perm32, (size_t)n, 0, 63, st) != hipSuccess) {
+            rs = rt_fail(ctx, RT_EHIP, "radix sort failed");
+            goto fail;
+        }
+        k_gather_sorted<<<nblk(n), kBlock, 0, st>>>(n, x, ctx->perm32, h_in, ctx->xs, h, perm);
+
+        // tree on positions; smoothing lengths
+        build_tree(ctx, nullptr);
+        Tree T{ctx->node_lo, ctx->node_hi, ctx->node_hmax, ctx->P};
+        RT_HIP(hipMemsetAsync(ctx->status, 0, sizeof(int32_t), st));
+        RT_HIP(hipMemsetAsync(ctx->h_iters, 0, sizeof(int32_t) * n, st));
+        if (!h_in) {
+            k_h_guess<<<nblk(n), kBlock, 0, st>>>(n, ctx->P, ctx->node_lo, ctx->node_hi,
+                                                  ctx->p.eta, ctx->p.box, h);
+            k_h_solve<<<nblk(n), kBlock, 0, st>>>(n, T, ctx->xs, ctx->p.eta, ctx->p.kappa,
+                                                  ctx->p.box, h, ctx->h_iters, ctx->status);
+        }
+        k_scale<<<nblk(n), kBlock, 0, st>>>(n, h, ctx->p.kappa, Htmp);
+        int32_t stw = 0;
+        RT_HIP(hipMemcpyAsync(&stw, ctx->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        RT_HIP(hipStreamSynchronize(st));
+        if (stw & ST_NOCONV) { rs = rt_fail(ctx, RT_ENOCONV, "smoothing length did not converge"); goto fail; }
+        if (stw & ST_BIGH) { rs = rt_fail(ctx, RT_EINVAL, "compact support radius reaches half the box"); goto fail; }
+        {
+            // largest H must stay below half the box (nearest image is unique)
+            std::vector<double> hmaxv(1);
+            build_tree(ctx, Htmp);
+            RT_HIP(hipMemcpyAsync(hmaxv.data(), ctx->node_hmax + 1, sizeof(double),
+                                  hipMemcpyDeviceToHost, st));
+            RT_HIP(hipStreamSynchronize(st));
+            if (!(hmaxv[0] < 0.5 * ctx->p.box)) {
+                rs = rt_fail(ctx, RT_EINVAL, "compact support radius reaches half the box");
+                goto fail;
+            }
+        }
+        // neighbour table: counts, wave widths, offsets, fill
+        k_neighbours<false><<<nblk(n), kBlock, 0, st>>>(n, T, ctx->xs, Htmp, ctx->p.box,
+                                                        ctx->n_nbr, ctx->n_gath, nullptr, nullptr);
+        k_wave_width<<<nblk(ctx->nwaves + 1), kBlock, 0, st>>>(n, ctx->nwaves, ctx->n_nbr, width);
+        size_t scan_bytes = 0;
+        if (rocprim::exclusive_scan(nullptr, scan_bytes, width, ctx->wave_base,
+                                    (int64_t)0, (size_t)(ctx->nwaves + 1),
+                                    rocprim::plus<int64_t>(), st) != hipSuccess) {
+            rs = rt_fail(ctx, RT_EHIP, "scan size query failed");
+            goto fail;
+        }
+        if (scan_bytes > sort_bytes) {
+            rt_free(sort_tmp);
+            sort_tmp = nullptr;
+            ALLOC(sort_tmp, scan_bytes);
+            sort_bytes = scan_bytes;
+        }
+        if (rocprim::exclusive_scan(sort_tmp, scan_bytes, width, ctx->wave_base, (int64_t)0,
+                                    (size_t)(ctx->nwaves + 1), rocprim::plus<int64_t>(),
+                                    st) != hipSuccess) {
+            rs = rt_fail(ctx, RT_EHIP, "scan failed");
+            goto fail;
+        }
+        RT_HIP(hipMemcpyAsync(&ctx->slots, ctx->wave_base + ctx->nwaves, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+        RT_HIP(hipStreamSynchronize(st));
+        ALLOC(ctx->nbr, sizeof(int32_t) * std::max<int64_t>(ctx->slots, 1));
+        RT_HIP(hipMemsetAsync(ctx->nbr, 0xff, sizeof(int32_t) * std::max<int64_t>(ctx->slots, 1), st));
+        k_neighbours<true><<<nblk(n), kBlock, 0, st>>>(n, T, ctx->xs, Htmp, ctx->p.box,
+                                                       ctx->n_nbr, ctx->n_gath, ctx->wave_base,
+                                                       ctx->nbr);
+        // geometry records, volumes, time step
+        RT_HIP(hipMemsetAsync(ctx->status, 0, sizeof(int32_t), st));
+        k_geometry<<<nblk(n), kBlock, 0, st>>>(n, ctx->xs, h, ctx->p.kappa, ctx->p.box,
+                                               ctx->n_gath, ctx->wave_base, ctx->nbr, ctx->geo,
+                                               ctx->geo32, V, dxpart, ctx->status);
+        k_dt<<<1, kBlock, 0, st>>>(nblk(n), dxpart, ctx->p.cfl, ctx->p.c_red, ctx->dt_dev);
+        if (dt) k_copy_dt<<<1, 1, 0, st>>>(ctx->dt_dev, dt);
+        RT_HIP(hipGetLastError());
+        // statistics
+        std::vector<int32_t> nn(n), ng(n), it(n);
+        RT_HIP(hipMemcpyAsync(nn.data(), ctx->n_nbr, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+        RT_HIP(hipMemcpyAsync(ng.data(), ctx->n_gath, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+        RT_HIP(hipMemcpyAsync(it.data(), ctx->h_iters, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+        RT_HIP(hipMemcpyAsync(&stw, ctx->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        RT_HIP(hipStreamSynchronize(st));
+        if (stw & ST_SINGULAR) {
+            rs = rt_fail(ctx, RT_ESINGULAR, "E_i not positive definite (coplanar or too few neighbours)");
+            goto fail;
+        }
+        ctx->n_entries = 0;
+        ctx->n_gather_entries = 0;
+        ctx->max_nbr = 0;
+        ctx->h_iter_max = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            ctx->n_entries += nn[i];
+            ctx->n_gather_entries += ng[i];
+            ctx->max_nbr = std::max(ctx->max_nbr, nn[i]);
+            ctx->h_iter_max = std::max(ctx->h_iter_max, it[i]);
+        }
+    }
+    rt_free(keys_in); rt_free(idx_in); rt_free(Htmp); rt_free(width); rt_free(dxpart);
+    rt_free(sort_tmp);
+    if ((rs = rt_ensure_partials(ctx)) != RT_OK) return rs;
+    ctx->built = 1;
+    return RT_OK;
+fail:
+    (void)hipStreamSynchronize(st);
+    rt_free(keys_in); rt_free(idx_in); rt_free(Htmp); rt_free(width); rt_free(dxpart);
+    rt_free(sort_tmp);
+    return rs;
+#undef ALLOC
+}
+
+rt_status rt_sources_impl(rt_ctx *ctx, int32_t S, const double *xs, double eta_star) {
+    hipStream_t st = ctx->stream;
+    rt_free(ctx->src_h); rt_free(ctx->inj_gptr); rt_free(ctx->inj_gas); rt_free(ctx->inj_src);
+    rt_free(ctx->inj_coef); rt_free(ctx->inj_xi); rt_free(ctx->src_ptr); rt_free(ctx->src_gas);
+    rt_free(ctx->src_coef);
+    ctx->src_h = nullptr; ctx->inj_gptr = nullptr; ctx->inj_gas = nullptr; ctx->inj_src = nullptr;
+    ctx->inj_coef = nullptr; ctx->inj_xi = nullptr; ctx->src_ptr = nullptr; ctx->src_gas = nullptr;
+    ctx->src_coef = nullptr;
+    ctx->S = 0;
+    ctx->n_inj = 0;
+    ctx->n_inj_gas = 0;
+    if (S == 0) return RT_OK;
+    const int64_t n = ctx->p.n;
+    rt_status rs;
+    double *sx = nullptr, *sxi = nullptr;
+    int32_t *cnt = nullptr;
+    std::vector<int32_t> hc(S), hptr(S + 1);
+    Tree T{ctx->node_lo, ctx->node_hi, ctx->node_hmax, ctx->P};
+    if ((rs = rt_alloc(ctx, (void **)&sx, sizeof(double) * 3 * S)) != RT_OK) return rs;
+    if ((rs = rt_alloc(ctx, (void **)&ctx->src_h, sizeof(double) * S)) != RT_OK) goto fail;
+    if ((rs = rt_alloc(ctx, (void **)&cnt, sizeof(int32_t) * S)) != RT_OK) goto fail;
+    RT_HIP(hipMemcpyAsync(sx, xs, sizeof(double) * 3 * S, hipMemcpyDeviceToDevice, st));
+    RT_HIP(hipMemsetAsync(ctx->status, 0, sizeof(int32_t), st));
+    {
+        // start below the mean spacing; the solver doubles h until bracketed
+        double h0 = 0.05 * eta_star * ctx->p.box / cbrt((double)n);
+        k_src_h<<<nblk(S, 64), 64, 0, st>>>(S, T, ctx->xs, n, sx, eta_star, ctx->p.kappa,
+                                           ctx->p.box, h0, ctx->src_h, ctx->status);
+        k_src_gas<false><<<nblk(S, 64), 64, 0, st>>>(S, T, ctx->xs, n, sx, ctx->src_h,
+                                                    ctx->p.kappa, ctx->p.box, ctx->geo, cnt,
+                                                    nullptr, nullptr, nullptr, nullptr);
+        int32_t stw = 0;
+        RT_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * S, hipMemcpyDeviceToHost, st));
+        RT_HIP(hipMemcpyAsync(&stw, ctx->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        RT_HIP(hipStreamSynchronize(st));
+        if (stw & ST_NOCONV) { rs = rt_fail(ctx, RT_ENOCONV, "source smoothing length did not converge"); goto fail; }
+        if (stw & ST_BIGH) { rs = rt_fail(ctx, RT_EINVAL, "source compact support reaches half the box"); goto fail; }
+        hptr[0] = 0;
+        for (int32_t s = 0; s < S; ++s) {
+            if (hc[s] == 0) { rs = rt_fail(ctx, RT_EINVAL, "source without gas neighbours"); goto fail; }
+            hptr[s + 1] = hptr[s] + hc[s];
+        }
+        const int64_t m = hptr[S];
+        if ((rs = rt_alloc(ctx, (void **)&ctx->src_ptr, sizeof(int32_t) * (S + 1))) != RT_OK) goto fail;
+        if ((rs = rt_alloc(ctx, (void **)&ctx->src_gas, sizeof(int32_t) * m)) != RT_OK) goto fail;
+        if ((rs = rt_alloc(ctx, (void **)&ctx->src_coef, sizeof(double) * m)) != RT_OK) goto fail;
+        if ((rs = rt_alloc(ctx, (void **)&sxi, sizeof(double) * m)) != RT_OK) goto fail;
+        RT_HIP(hipMemcpyAsync(ctx->src_ptr, hptr.data(), sizeof(int32_t) * (S + 1),
+                              hipMemcpyHostToDevice, st));
+        k_src_gas<true><<<nblk(S, 64), 64, 0, st>>>(S, T, ctx->xs, n, sx, ctx->src_h, ctx->p.kappa,
+                                                   ctx->p.box, ctx->geo, nullptr, ctx->src_ptr,
+                                                   ctx->src_gas, sxi, ctx->src_coef);
+        // gas-major copy for the per-step injection (deterministic gather)
+        std::vector<int32_t> g(m), srcv(m);
+        std::vector<double> xi(m), co(m);
+        RT_HIP(hipMemcpyAsync(g.data(), ctx->src_gas, sizeof(int32_t) * m, hipMemcpyDeviceToHost, st));
+        RT_HIP(hipMemcpyAsync(xi.data(), sxi, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+        RT_HIP(hipMemcpyAsync(co.data(), ctx->src_coef, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+        RT_HIP(hipStreamSynchronize(st));
+        for (int32_t s = 0; s < S; ++s)
+            for (int32_t e = hptr[s]; e < hptr[s + 1]; ++e) srcv[e] = s;
+        std::vector<int64_t> ord(m);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return g[a] < g[b]; });
+        std::vector<int32_t> ig, igp, isr(m);
+        std::vector<double> ico(m), ixi(m);
+        for (int64_t e = 0; e < m; ++e) {
+            int64_t o = ord[e];
+            if (e == 0 || g[o] != g[ord[e - 1]]) {
+                ig.push_back(g[o]);
+                igp.push_back((int32_t)e);
+            }
+            isr[e] = srcv[o];
+            ico[e] = co[o];
+            ixi[e] = xi[o];
+        }
+        igp.push_back((int32_t)m);
+        ctx->n_inj = m;
+        ctx->n_inj_gas = (int32_t)ig.size();
+        if ((rs = rt_alloc(ctx, (void **)&ctx->inj_gptr, sizeof(int32_t) * igp.size())) != RT_OK) goto fail;
+        if ((rs = rt_alloc(ctx, (void **)&ctx->inj_gas, sizeof(int32_t) * ig.size())) != RT_OK) goto fail;
+        if ((rs = rt_alloc(ctx, (void **)&ctx->inj_src, sizeof(int32_t) * m)) != RT_OK) goto fail;
+        if ((rs = rt_alloc(ctx, (void **)&ctx->inj_coef, sizeof(double) * m)) != RT_OK) goto fail;
+        if ((rs = rt_alloc(ctx, (void **)&ctx->inj_xi, sizeof(double) * m)) != RT_OK) goto fail;
+        RT_HIP(hipMemcpyAsync(ctx->inj_gptr, igp.data(), sizeof(int32_t) * igp.size(), hipMemcpyHostToDevice, st));
+        RT_HIP(hipMemcpyAsync(ctx->inj_gas, ig.data(), sizeof(int32_t) * ig.size(), hipMemcpyHostToDevice, st));
+        RT_HIP(hipMemcpyAsync(ctx->inj_src, isr.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
+        RT_HIP(hipMemcpyAsync(ctx->inj_coef, ico.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+        RT_HIP(hipMemcpyAsync(ctx->inj_xi, ixi.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+        RT_HIP(hipStreamSynchronize(st));
+    }
+    ctx->S = S;
+    rt_free(sx); rt_free(cnt); rt_free(sxi);
+    return RT_OK;
+fail:
+    (void)hipStreamSynchronize(st);
+    rt_free(sx); rt_free(cnt); rt_free(sxi);
+    return rs;
+}

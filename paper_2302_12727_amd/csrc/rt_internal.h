@@ -1,0 +1,239 @@
+// Internal declarations of the gfx950 photon-transport library.
+// Device helpers shared by the build, step and adjoint translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/rt.h"
+
+namespace gearrt {
+
+constexpr int kWave = 64;     // wavefront width on CDNA
+constexpr int kBlock = 256;   // threads per block of the per-particle kernels
+constexpr int kLeaf = 32;     // particles per leaf of the search tree
+constexpr int kRec = 12;      // doubles per particle geometry record
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSigma3 = 16.0 / kPi;   // cubic spline normalisation in 3D
+
+// Device status word bits.
+enum : int32_t { ST_NOCONV = 1, ST_SINGULAR = 2, ST_BIGH = 4, ST_NONFINITE = 8 };
+
+// Geometry record, one per particle (Morton order), 96 bytes:
+//   0..2  x, y, z       position in [0, box)
+//   3     1/H           inverse compact support radius, H = kappa h
+//   4     h             smoothing length
+//   5     V             particle volume 1/omega
+//   6..11 Bv            V * S^{-1}, S = sum_j s s^T w(r/H) (upper triangle
+//                       00 01 02 11 12 22); A_kl = (w_k Bv_k + w_l Bv_l) s
+//                       and the gradient matrix is S^{-1} = Bv / V.
+enum { R_X = 0, R_IH = 3, R_H = 4, R_V = 5, R_B = 6 };
+
+// Same record in FP32 for the compensated-FP32 path (positions stay FP64 in
+// the FP64 record: separations are formed in FP64 and rounded once).
+enum { F_IH = 0, F_H = 1, F_V = 2, F_B = 3, F_REC = 10 };  // padded to 10 floats
+
+struct TimerRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+
+}  // namespace gearrt
+
+struct rt_ctx {
+    rt_params p{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    int device = 0;
+    int built = 0;
+
+    // sorted particles and geometry
+    double *xs = nullptr;        // [n][3] Morton-ordered positions
+    double *geo = nullptr;       // [n][kRec]
+    float *geo32 = nullptr;      // [n][F_REC] (FP32C only)
+    int32_t *perm32 = nullptr;   // [n]
+    uint64_t *keys = nullptr;    // [n] sorted Morton keys
+    double *dt_dev = nullptr;    // [1]
+    int32_t *h_iters = nullptr;  // [n]
+
+    // search tree over leaves of kLeaf consecutive sorted particles (heap layout)
+    int64_t nleaf = 0, P = 0;    // P = leaves padded to a power of two
+    double *node_lo = nullptr;   // [2P][3]
+    double *node_hi = nullptr;   // [2P][3]
+    double *node_hmax = nullptr; // [2P] max H below the node
+
+    // wave-sliced neighbour table: wave w owns slots [wave_base[w], wave_base[w+1]),
+    // slot (lane, j) at wave_base[w] + 64 j + lane
+    int64_t nwaves = 0, slots = 0, n_entries = 0, n_gather_entries = 0;
+    int32_t max_nbr = 0;
+    int32_t *n_nbr = nullptr;    // [n]
+    int32_t *n_gath = nullptr;   // [n]
+    int64_t *wave_base = nullptr;// [nwaves + 1]
+    int32_t *nbr = nullptr;      // [slots]
+
+    // sources
+    int32_t S = 0;
+    double *src_h = nullptr;     // [S]
+    int64_t n_inj = 0;           // injection entries
+    int32_t n_inj_gas = 0;       // distinct gas particles receiving energy
+    int32_t *inj_gptr = nullptr; // [n_inj_gas + 1] gas-major CSR
+    int32_t *inj_gas = nullptr;  // [n_inj_gas]
+    int32_t *inj_src = nullptr;  // [n_inj]
+    double *inj_coef = nullptr;  // [n_inj] xi_sg / V_g
+    double *inj_xi = nullptr;    // [n_inj] xi_sg
+    int32_t *src_ptr = nullptr;  // [S + 1] source-major CSR into the arrays below
+    int32_t *src_gas = nullptr;  // [n_inj]
+    double *src_coef = nullptr;  // [n_inj]
+
+    // scratch
+    int32_t *status = nullptr;   // device status word
+    double *partials = nullptr;  // [nblocks][2 G] block partial sums
+    int64_t nblocks = 0;
+    void *scan_tmp = nullptr;
+    size_t scan_tmp_bytes = 0;
+    void *adj_buf = nullptr;     // adjoint scratch (see rt_adjoint.hip)
+    size_t adj_bytes = 0;
+
+    int64_t device_bytes = 0;
+    int32_t h_iter_max = 0;
+
+    // timing: event pairs recorded around launches while timing is on
+    int timing = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<gearrt::TimerRec> trecs;
+    hipEvent_t ev_open = nullptr;
+};
+
+namespace gearrt {
+
+// ---------------------------------------------------------------------------
+// device helpers
+
+// Dimensionless cubic B-spline w(q), q = r/H, written branch-free:
+// (1-q)^3 - 4 (1/2-q)^3 for q <= 1/2, (1-q)^3 for 1/2 < q < 1, 0 beyond.
+__device__ __forceinline__ double kern_w(double q) {
+    double a = fmax(1.0 - q, 0.0);
+    double b = fmax(0.5 - q, 0.0);
+    return a * a * a - 4.0 * (b * b * b);
+}
+__device__ __forceinline__ float kern_wf(float q) {
+    float a = fmaxf(1.0f - q, 0.0f);
+    float b = fmaxf(0.5f - q, 0.0f);
+    return a * a * a - 4.0f * (b * b * b);
+}
+// dw/dq
+__device__ __forceinline__ double kern_dw(double q) {
+    double a = fmax(1.0 - q, 0.0);
+    double b = fmax(0.5 - q, 0.0);
+    return -3.0 * a * a + 12.0 * (b * b);
+}
+
+// Periodic nearest-image separation component.
+__device__ __forceinline__ double min_image(double d, double box, double ibox) {
+    return d - box * rint(d * ibox);
+}
+
+// Squared distance from point p to the axis-aligned box [lo, hi] in a periodic
+// domain of side `box` (boxes are given in [0, box) coordinates).
+__device__ __forceinline__ double box_dist2(const double *lo, const double *hi, double px,
+                                            double py, double pz, double box) {
+    double p[3] = {px, py, pz};
+    double d2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double in = fmax(0.0, fmax(lo[a] - p[a], p[a] - hi[a]));
+        double up = fmax(0.0, p[a] + box - hi[a]);     // image p + box
+        double dn = fmax(0.0, lo[a] - p[a] + box);     // image p - box
+        double d = fmin(in, fmin(up, dn));
+        d2 += d * d;
+    }
+    return d2;
+}
+
+// Stackless depth-first traversal of the heap-ordered complete binary tree:
+// node v has children 2v, 2v+1; leaves are P .. 2P-1.  `accept(v)` decides
+// whether to open node v; `leaf(l)` is called for accepted leaf l.
+template <class Accept, class Leaf>
+__device__ __forceinline__ void traverse(int64_t P, Accept &&accept, Leaf &&leaf) {
+    int64_t v = 1;
+    while (true) {
+        if (accept(v)) {
+            if (v >= P) {
+                leaf(v - P);
+            } else {
+                v = 2 * v;
+                continue;
+            }
+        }
+        while (v & 1) v >>= 1;   // climb while v is a right child
+        if (v == 0) break;       // passed the root
+        v = v + 1;               // right sibling
+    }
+}
+
+// XCD-aware block mapping: blocks are dispatched round-robin over the 8 XCDs
+// of the chip; remap so that each XCD works on one contiguous range of
+// particles (its L2 then holds that range's neighbour data).  The grid has
+// 8 * ceil(nb / 8) blocks; blocks mapped past nb return.
+__device__ __forceinline__ int64_t xcd_block(int64_t nb) {
+    int64_t b = blockIdx.x;
+    int64_t per = (nb + 7) / 8;
+    return (b & 7) * per + (b >> 3);
+}
+inline int64_t xcd_grid(int64_t nb) { return 8 * ((nb + 7) / 8); }
+
+// Wave-level sum of a double (all 64 lanes active or inactive lanes contributing 0).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+}  // namespace gearrt
+
+// ---------------------------------------------------------------------------
+// host-side helpers shared by the translation units
+
+#define RT_HIP(expr)                                                              \
+    do {                                                                          \
+        hipError_t _e = (expr);                                                   \
+        if (_e != hipSuccess) {                                                   \
+            ctx->err = std::string(#expr) + ": " + hipGetErrorString(_e);         \
+            return RT_EHIP;                                                       \
+        }                                                                         \
+    } while (0)
+
+rt_status rt_fail(rt_ctx *ctx, rt_status st, const std::string &msg);
+rt_status rt_alloc(rt_ctx *ctx, void **ptr, size_t bytes);
+void rt_free(void *ptr);
+void rt_timer_begin(rt_ctx *ctx, const char *name);
+void rt_timer_end(rt_ctx *ctx, const char *name);
+
+// build (rt_build.hip)
+rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_t *perm,
+                        double *h, double *V, double *dt);
+rt_status rt_sources_impl(rt_ctx *ctx, int32_t n_src, const double *xs, double eta_star);
+
+// step (rt_step.hip)
+rt_status rt_inject_impl(rt_ctx *ctx, void *U, const double *L, const double *dt);
+rt_status rt_gradient_impl(rt_ctx *ctx, const void *U, void *dU);
+rt_status rt_transport_impl(rt_ctx *ctx, const void *U, const void *dU, const double *dt,
+                            void *U_out, double *Q, int64_t *counts, double *ledger,
+                            uint8_t *mask);
+rt_status rt_total_impl(rt_ctx *ctx, const void *U, double *Q);
+rt_status rt_ensure_partials(rt_ctx *ctx);
+
+// adjoint (rt_adjoint.hip)
+rt_status rt_adjoint_impl(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
+                          const void *dU, const uint8_t *mask, const void *lam_next,
+                          void *lam, double *dL_dL);

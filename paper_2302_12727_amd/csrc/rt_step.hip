@@ -1,0 +1,476 @@
+// Per-step kernels of the photon transport (Part III "One RT time step"):
+// injection, least-squares gradients, the pair transport loop with its fused
+// update, and the photon budget.
+//
+// Every kernel is a gather over the wave-sliced neighbour table: lane i owns
+// particle i (Morton order), reads slot j of its list at
+// wave_base[i/64] + 64 j + i%64 (coalesced), and accumulates in registers, so
+// results are deterministic and no atomics touch floating-point state.
+#include "rt_internal.h"
+
+using namespace gearrt;
+
+namespace {
+
+inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Injection: E_g += dt sum_s xi_sg L_s / V_g, one thread per receiving particle.
+template <typename T>
+__global__ void k_inject(int32_t ngas, int G, const int32_t *__restrict__ gptr,
+                         const int32_t *__restrict__ gas, const int32_t *__restrict__ src,
+                         const double *__restrict__ coef, const double *__restrict__ L,
+                         const double *__restrict__ dtp, T *__restrict__ U) {
+    int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ngas) return;
+    const int64_t g = gas[t];
+    const double dt = dtp[0];
+    for (int grp = 0; grp < G; ++grp) {
+        double s = 0.0;
+        for (int32_t e = gptr[t]; e < gptr[t + 1]; ++e) s += coef[e] * L[(int64_t)src[e] * G + grp];
+        T *E = U + (g * G + grp) * 4;
+        E[0] = (T)((double)E[0] + dt * s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gradient (eq:gradient):  grad q_i = sum_j (q_j - q_i) psi~_j(x_i)
+//   = S_i^{-1} sum_j (q_j - q_i) w(r_ij / H_i) s_ij   (the kernel normalisation
+// and V_i cancel against B_i, see the geometry record).
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_gradient64(
+    int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
+    const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_gath,
+    const double *__restrict__ U, double *__restrict__ D, double box) {
+    const int64_t blk = xcd_block(nb);
+    if (blk >= nb) return;
+    const int64_t i = blk * kBlock + threadIdx.x;
+    if (i >= n) return;
+    constexpr int NQ = 4 * G;
+    const double ibox = 1.0 / box;
+    const double *rec = geo + (int64_t)kRec * i;
+    const double px = rec[0], py = rec[1], pz = rec[2], iH = rec[R_IH], iV = 1.0 / rec[R_V];
+    double Ui[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) Ui[q] = U[i * NQ + q];
+    double acc[NQ][3];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
+    const int64_t base = wave_base[i >> 6] + (i & 63);
+    const int32_t ng = n_gath[i];
+    for (int32_t k = 0; k < ng; ++k) {
+        const int64_t j = nbr[base + 64 * (int64_t)k];
+        const double *rj = geo + (int64_t)kRec * j;
+        const double sx = min_image(rj[0] - px, box, ibox);
+        const double sy = min_image(rj[1] - py, box, ibox);
+        const double sz = min_image(rj[2] - pz, box, ibox);
+        const double w = kern_w(sqrt(sx * sx + sy * sy + sz * sz) * iH);
+        const double wx = w * sx, wy = w * sy, wz = w * sz;
+        const double *Uj = U + j * NQ;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const double d = Uj[q] - Ui[q];
+            acc[q][0] += d * wx;
+            acc[q][1] += d * wy;
+            acc[q][2] += d * wz;
+        }
+    }
+    const double b00 = rec[R_B] * iV, b01 = rec[R_B + 1] * iV, b02 = rec[R_B + 2] * iV;
+    const double b11 = rec[R_B + 3] * iV, b12 = rec[R_B + 4] * iV, b22 = rec[R_B + 5] * iV;
+    double *Di = D + i * NQ * 3;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        Di[3 * q + 0] = b00 * acc[q][0] + b01 * acc[q][1] + b02 * acc[q][2];
+        Di[3 * q + 1] = b01 * acc[q][0] + b11 * acc[q][1] + b12 * acc[q][2];
+        Di[3 * q + 2] = b02 * acc[q][0] + b12 * acc[q][1] + b22 * acc[q][2];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Transport (eq:rt-meshless, eq:transport-update-explicit).
+//
+// Face guard (reading of "negative energy densities are set to zero"): E < 0
+// becomes 0 with F = 0, and a flux beyond the free-streaming limit is scaled
+// to |F| = cE.  Returns bit0 / bit1 when the respective guard fired.
+__device__ __forceinline__ int guard64(double &E, double &Fx, double &Fy, double &Fz, double c) {
+    int fired = 0;
+    if (E < 0.0) {
+        E = 0.0;
+        fired = 1;
+    }
+    if (E == 0.0) {
+        Fx = Fy = Fz = 0.0;
+        return fired;
+    }
+    const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+    const double lim = c * E;
+    if (F2 > lim * lim) {
+        const double sc = lim / sqrt(F2);
+        Fx *= sc;
+        Fy *= sc;
+        Fz *= sc;
+        fired |= 2;
+    }
+    return fired;
+}
+
+// Flux of a state through the (unnormalised) surface A, using the M1 closure
+// (eq:eddington-group) rewritten without the 0/0 of n = F/|F|:
+//   with f^2 = |F|^2/(cE)^2, s = sqrt(4 - 3 f^2):
+//   (3 chi - 1)/(2 f^2) = 3/(2 + s),  (1 - chi)/2 = 1/3 - f^2/(2 + s),
+//   c^2 P A = c^2 E (1-chi)/2 A + 3/(2+s) (F.A) F / E.
+// out[0] = F.A, out[1..3] = c^2 P A.  A state with E = 0 has no flux.
+__device__ __forceinline__ void m1_flux64(double E, double Fx, double Fy, double Fz, double Ax,
+                                          double Ay, double Az, double c, double c2, double ic2,
+                                          double out[4]) {
+    const double FA = Fx * Ax + Fy * Ay + Fz * Az;
+    if (E > 0.0) {
+        const double iE = 1.0 / E;
+        const double f2 = (Fx * Fx + Fy * Fy + Fz * Fz) * (iE * iE) * ic2;
+        const double s = sqrt(fmax(4.0 - 3.0 * f2, 0.0));
+        const double id = 1.0 / (2.0 + s);
+        const double a = c2 * E * (1.0 / 3.0 - f2 * id);
+        const double b = 3.0 * id * FA * iE;
+        out[0] = FA;
+        out[1] = a * Ax + b * Fx;
+        out[2] = a * Ay + b * Fy;
+        out[3] = a * Az + b * Fz;
+    } else {
+        out[0] = out[1] = out[2] = out[3] = 0.0;
+    }
+}
+
+__device__ __forceinline__ double minmod(double a, double b) {
+    const double m = (fabs(a) <= fabs(b)) ? a : b;
+    return (a * b > 0.0) ? m : 0.0;
+}
+
+// Per-pair flux accumulation shared by the FP64 transport and its adjoint
+// recompute: returns |A| and A in out-params, or |A| = 0 if the pair has no
+// surface.
+struct PairGeo {
+    double sx, sy, sz, Ax, Ay, Az, An, fk, fl;
+};
+
+__device__ __forceinline__ void pair_geometry64(const double *__restrict__ rk,
+                                                const double *__restrict__ rl, double box,
+                                                double ibox, PairGeo &pg) {
+    pg.sx = min_image(rl[0] - rk[0], box, ibox);
+    pg.sy = min_image(rl[1] - rk[1], box, ibox);
+    pg.sz = min_image(rl[2] - rk[2], box, ibox);
+    const double r = sqrt(pg.sx * pg.sx + pg.sy * pg.sy + pg.sz * pg.sz);
+    const double wk = kern_w(r * rk[R_IH]);
+    const double wl = kern_w(r * rl[R_IH]);
+    // A_kl = (w_k Bv_k + w_l Bv_l) s   (eq:HopkinsAij, see the record layout)
+    const double m00 = wk * rk[R_B + 0] + wl * rl[R_B + 0];
+    const double m01 = wk * rk[R_B + 1] + wl * rl[R_B + 1];
+    const double m02 = wk * rk[R_B + 2] + wl * rl[R_B + 2];
+    const double m11 = wk * rk[R_B + 3] + wl * rl[R_B + 3];
+    const double m12 = wk * rk[R_B + 4] + wl * rl[R_B + 4];
+    const double m22 = wk * rk[R_B + 5] + wl * rl[R_B + 5];
+    pg.Ax = m00 * pg.sx + m01 * pg.sy + m02 * pg.sz;
+    pg.Ay = m01 * pg.sx + m11 * pg.sy + m12 * pg.sz;
+    pg.Az = m02 * pg.sx + m12 * pg.sy + m22 * pg.sz;
+    pg.An = sqrt(pg.Ax * pg.Ax + pg.Ay * pg.Ay + pg.Az * pg.Az);
+    // interface x_kl = x_k + h_k/(h_k+h_l) s  (eq:rt-riemann-problem)
+    const double ih = 1.0 / (rk[R_H] + rl[R_H]);
+    pg.fk = rk[R_H] * ih;
+    pg.fl = rl[R_H] * ih;
+}
+
+template <int NP>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NP], double *__restrict__ out,
+                                                   double *smem) {
+    // smem: [kBlock/64][NP]
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        double x = wave_sum(v[p]);
+        if (lane == 0) smem[wv * NP + p] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < NP) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += smem[w * NP + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_transport64(
+    int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
+    const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
+    const double *__restrict__ U, const double *__restrict__ D, const double *__restrict__ dtp,
+    double c, double box, double *__restrict__ Uout, double *__restrict__ partials,
+    unsigned long long *__restrict__ counts, uint8_t *__restrict__ mask) {
+    constexpr int NQ = 4 * G;
+    __shared__ double smem[(kBlock / 64) * 2 * G];
+    __shared__ unsigned long long scnt[4];
+    const int64_t blk = xcd_block(nb);
+    if (blk >= nb) return;                      // whole block: no barrier is skipped
+    const int64_t i = blk * kBlock + threadIdx.x;
+    const bool active = i < n;
+    const double ibox = 1.0 / box, c2 = c * c, ic2 = 1.0 / c2, hc = 0.5 * c;
+    if (threadIdx.x < 4) scnt[threadIdx.x] = 0;
+
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    int cE = 0, cF = 0;
+    double Ui[NQ];
+    const double *rk = geo + (int64_t)kRec * (active ? i : 0);
+    if (active) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) Ui[q] = U[i * NQ + q];
+        const int64_t base = wave_base[i >> 6] + (i & 63);
+        const int32_t nn = n_nbr[i];
+        const double *Di = D + i * NQ * 3;
+        for (int32_t k = 0; k < nn; ++k) {
+            const int64_t j = nbr[base + 64 * (int64_t)k];
+            const double *rl = geo + (int64_t)kRec * j;
+            PairGeo pg;
+            pair_geometry64(rk, rl, box, ibox, pg);
+            if (!(pg.An > 0.0)) continue;
+            const double *Uj = U + j * NQ;
+            const double *Dj = D + j * NQ * 3;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                double qL[4], qR[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int q = 4 * g + m;
+                    const double dk = Di[3 * q] * pg.sx + Di[3 * q + 1] * pg.sy + Di[3 * q + 2] * pg.sz;
+                    const double dl = Dj[3 * q] * pg.sx + Dj[3 * q + 1] * pg.sy + Dj[3 * q + 2] * pg.sz;
+                    const double mm = minmod(dk, dl);
+                    qL[m] = Ui[q] + pg.fk * mm;
+                    qR[m] = Uj[q] - pg.fl * mm;
+                }
+                const int f1 = guard64(qL[0], qL[1], qL[2], qL[3], c);
+                const int f2 = guard64(qR[0], qR[1], qR[2], qR[3], c);
+                cE += (f1 & 1) + (f2 & 1);
+                cF += (f1 >> 1) + (f2 >> 1);
+                double FL[4], FR[4];
+                m1_flux64(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, c2, ic2, FL);
+                m1_flux64(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, c2, ic2, FR);
+                const double dis = hc * pg.An;
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    acc[4 * g + m] += 0.5 * (FL[m] + FR[m]) - dis * (qR[m] - qL[m]);
+            }
+        }
+    }
+    // update, post-update guard, ledger, photon budget
+    double red[2 * G];
+    int gE = 0, gF = 0;
+    if (active) {
+        const double dtV = dtp[0] / rk[R_V];
+        const double V = rk[R_V];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            double q0 = Ui[4 * g + 0] - dtV * acc[4 * g + 0];
+            double q1 = Ui[4 * g + 1] - dtV * acc[4 * g + 1];
+            double q2 = Ui[4 * g + 2] - dtV * acc[4 * g + 2];
+            double q3 = Ui[4 * g + 3] - dtV * acc[4 * g + 3];
+            const double Epre = q0;
+            const int f = guard64(q0, q1, q2, q3, c);
+            gE += f & 1;
+            gF += f >> 1;
+            if (mask) mask[i * G + g] = (uint8_t)f;
+            double *o = Uout + i * NQ + 4 * g;
+            o[0] = q0;
+            o[1] = q1;
+            o[2] = q2;
+            o[3] = q3;
+            red[g] = V * q0;
+            red[G + g] = (f & 1) ? -Epre * V : 0.0;
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < 2 * G; ++p) red[p] = 0.0;
+    }
+    if (partials) block_reduce_store<2 * G>(red, partials + blk * 2 * G, smem);
+    if (counts) {
+        int64_t v0 = wave_sum_i64(cE), v1 = wave_sum_i64(cF), v2 = wave_sum_i64(gE),
+                v3 = wave_sum_i64(gF);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&scnt[0], (unsigned long long)v0);
+            atomicAdd(&scnt[1], (unsigned long long)v1);
+            atomicAdd(&scnt[2], (unsigned long long)v2);
+            atomicAdd(&scnt[3], (unsigned long long)v3);
+        }
+        __syncthreads();
+        if (threadIdx.x < 4 && scnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], scnt[threadIdx.x]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Photon budget Q_g = sum_k V_k E_kg: block partials, then one block combines
+// them with compensated (two-sum) arithmetic in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_total_partials(int64_t n, int G,
+                                                           const double *__restrict__ geo,
+                                                           const T *__restrict__ U,
+                                                           double *__restrict__ partials) {
+    __shared__ double smem[kBlock];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (int g = 0; g < G; ++g) {
+        double v = (i < n) ? geo[(int64_t)kRec * i + R_V] * (double)U[(i * G + g) * 4] : 0.0;
+        smem[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = kBlock / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) smem[threadIdx.x] += smem[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * 2 * G + g] = smem[0];
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// part [nb][2G]: columns 0..G-1 photon totals, G..2G-1 ledger.  Q[g] = sum (written),
+// ledger[g] += sum.
+__global__ __launch_bounds__(kBlock) void k_finalize(int64_t nb, int G,
+                                                     const double *__restrict__ part,
+                                                     double *__restrict__ Q,
+                                                     double *__restrict__ ledger) {
+    __shared__ double ss[kBlock], sc[kBlock];
+    for (int col = 0; col < 2 * G; ++col) {
+        double *dst = col < G ? Q : ledger;
+        if (!dst) continue;
+        double s = 0.0, e = 0.0;
+        for (int64_t b = threadIdx.x; b < nb; b += kBlock) {
+            double t, err;
+            two_sum(s, part[b * 2 * G + col], t, err);
+            s = t;
+            e += err;
+        }
+        ss[threadIdx.x] = s;
+        sc[threadIdx.x] = e;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                double t, err;
+                two_sum(ss[threadIdx.x], ss[threadIdx.x + w], t, err);
+                ss[threadIdx.x] = t;
+                sc[threadIdx.x] += sc[threadIdx.x + w] + err;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            double v = ss[0] + sc[0];
+            if (col < G) Q[col] = v;
+            else ledger[col - G] += v;
+        }
+        __syncthreads();
+    }
+}
+
+template <int G>
+void launch_transport64(rt_ctx *ctx, const double *U, const double *D, const double *dt,
+                        double *Uout, double *partials, int64_t *counts, uint8_t *mask) {
+    const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
+    k_transport64<G><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
+        n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, U, D, dt, ctx->p.c_red,
+        ctx->p.box, Uout, partials, (unsigned long long *)counts, mask);
+}
+
+template <int G>
+void launch_gradient64(rt_ctx *ctx, const double *U, double *D) {
+    const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
+    k_gradient64<G><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
+        n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_gath, U, D, ctx->p.box);
+}
+
+#define RT_DISPATCH_G(G_, FN, ...)                                  \
+    switch (G_) {                                                   \
+        case 1: FN<1>(__VA_ARGS__); break;                          \
+        case 2: FN<2>(__VA_ARGS__); break;                          \
+        case 3: FN<3>(__VA_ARGS__); break;                          \
+        case 4: FN<4>(__VA_ARGS__); break;                          \
+        case 5: FN<5>(__VA_ARGS__); break;                          \
+        case 6: FN<6>(__VA_ARGS__); break;                          \
+        case 7: FN<7>(__VA_ARGS__); break;                          \
+        case 8: FN<8>(__VA_ARGS__); break;                          \
+        default: break;                                             \
+    }
+
+}  // namespace
+
+rt_status rt_ensure_partials(rt_ctx *ctx) {
+    const int64_t nb = (ctx->p.n + kBlock - 1) / kBlock;
+    if (ctx->partials && ctx->nblocks >= nb) return RT_OK;
+    rt_free(ctx->partials);
+    ctx->partials = nullptr;
+    rt_status rs = rt_alloc(ctx, (void **)&ctx->partials, sizeof(double) * 2 * ctx->p.groups * nb);
+    if (rs != RT_OK) return rs;
+    ctx->nblocks = nb;
+    return RT_OK;
+}
+
+rt_status rt_inject_impl(rt_ctx *ctx, void *U, const double *L, const double *dt) {
+    if (ctx->S == 0 || ctx->n_inj_gas == 0) return RT_OK;
+    rt_timer_begin(ctx, "inject");
+    if (ctx->p.precision == RT_FP64)
+        k_inject<double><<<nblk(ctx->n_inj_gas), kBlock, 0, ctx->stream>>>(
+            ctx->n_inj_gas, ctx->p.groups, ctx->inj_gptr, ctx->inj_gas, ctx->inj_src,
+            ctx->inj_coef, L, dt, (double *)U);
+    else
+        k_inject<float><<<nblk(ctx->n_inj_gas), kBlock, 0, ctx->stream>>>(
+            ctx->n_inj_gas, ctx->p.groups, ctx->inj_gptr, ctx->inj_gas, ctx->inj_src,
+            ctx->inj_coef, L, dt, (float *)U);
+    rt_timer_end(ctx, "inject");
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+rt_status rt_gradient_impl(rt_ctx *ctx, const void *U, void *dU) {
+    rt_timer_begin(ctx, "gradient");
+    if (ctx->p.precision == RT_FP64) {
+        RT_DISPATCH_G(ctx->p.groups, launch_gradient64, ctx, (const double *)U, (double *)dU);
+    } else {
+        return rt_fail(ctx, RT_EINVAL, "FP32C gradient not available");
+    }
+    rt_timer_end(ctx, "gradient");
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+rt_status rt_transport_impl(rt_ctx *ctx, const void *U, const void *dU, const double *dt,
+                            void *U_out, double *Q, int64_t *counts, double *ledger,
+                            uint8_t *mask) {
+    const int64_t nb = (ctx->p.n + kBlock - 1) / kBlock;
+    double *part = (Q || ledger) ? ctx->partials : nullptr;
+    rt_timer_begin(ctx, "transport");
+    if (ctx->p.precision == RT_FP64) {
+        RT_DISPATCH_G(ctx->p.groups, launch_transport64, ctx, (const double *)U,
+                      (const double *)dU, dt, (double *)U_out, part, counts, mask);
+    } else {
+        return rt_fail(ctx, RT_EINVAL, "FP32C transport not available");
+    }
+    rt_timer_end(ctx, "transport");
+    RT_HIP(hipGetLastError());
+    if (part) {
+        k_finalize<<<1, kBlock, 0, ctx->stream>>>(nb, ctx->p.groups, part, Q, ledger);
+        RT_HIP(hipGetLastError());
+    }
+    return RT_OK;
+}
+
+rt_status rt_total_impl(rt_ctx *ctx, const void *U, double *Q) {
+    const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
+    if (ctx->p.precision == RT_FP64)
+        k_total_partials<double><<<(unsigned)nb, kBlock, 0, ctx->stream>>>(
+            n, ctx->p.groups, ctx->geo, (const double *)U, ctx->partials);
+    else
+        k_total_partials<float><<<(unsigned)nb, kBlock, 0, ctx->stream>>>(
+            n, ctx->p.groups, ctx->geo, (const float *)U, ctx->partials);
+    k_finalize<<<1, kBlock, 0, ctx->stream>>>(nb, ctx->p.groups, ctx->partials, Q, nullptr);
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}

@@ -1,0 +1,297 @@
+"""Python binding of the gfx950 photon-transport library (libgearrt.so).
+
+Argument marshalling only: every array lives in device memory as a torch
+tensor, the calls below pass raw device pointers and torch's current HIP
+stream to the C ABI declared in include/rt.h, and every step of the transport
+runs in the library's HIP kernels.  There is no CPU fallback: importing this
+module without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgearrt.so")
+
+RT_OK, RT_EINVAL, RT_ENOMEM, RT_EHIP, RT_ENOCONV, RT_ESINGULAR, RT_ESTATE = 0, -1, -2, -3, -4, -5, -6
+RT_FP64, RT_FP32C = 0, 1
+STATUS_NAMES = {0: "RT_OK", -1: "RT_EINVAL", -2: "RT_ENOMEM", -3: "RT_EHIP",
+                -4: "RT_ENOCONV", -5: "RT_ESINGULAR", -6: "RT_ESTATE"}
+
+KAPPA = 1.825742
+ETA = 1.2348
+
+EXPORTED = ["rt_create", "rt_destroy", "rt_last_error", "rt_set_stream", "rt_build_cells",
+            "rt_set_sources", "rt_inject", "rt_gradient", "rt_transport", "rt_photon_total",
+            "rt_adjoint", "rt_sync", "rt_get_stats", "rt_get_geometry", "rt_get_neighbours",
+            "rt_get_sources", "rt_timing", "rt_get_timing"]
+
+
+class RTError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class rt_params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("groups", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("box", ctypes.c_double), ("eta", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("c_red", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("hip_stream", ctypes.c_void_p)]
+
+
+class rt_stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_entries", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
+                ("n_gather", ctypes.c_int64), ("sell_slots", ctypes.c_int64),
+                ("max_neighbours", ctypes.c_int32), ("h_iter_max", ctypes.c_int32),
+                ("n_inject", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def load_library() -> ctypes.CDLL:
+    """Load libgearrt.so (built by __graft_entry__.build()); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    i32 = ctypes.c_int32
+    L.rt_create.argtypes = [ctypes.POINTER(rt_params), ctypes.POINTER(_VP)]
+    L.rt_destroy.argtypes = [_VP]
+    L.rt_destroy.restype = None
+    L.rt_last_error.argtypes = [_VP]
+    L.rt_last_error.restype = ctypes.c_char_p
+    L.rt_set_stream.argtypes = [_VP, _VP]
+    L.rt_build_cells.argtypes = [_VP] * 7
+    L.rt_set_sources.argtypes = [_VP, i32, _VP, ctypes.c_double]
+    L.rt_inject.argtypes = [_VP] * 4
+    L.rt_gradient.argtypes = [_VP] * 3
+    L.rt_transport.argtypes = [_VP] * 9
+    L.rt_photon_total.argtypes = [_VP] * 3
+    L.rt_adjoint.argtypes = [_VP] * 9
+    L.rt_sync.argtypes = [_VP]
+    L.rt_get_stats.argtypes = [_VP, ctypes.POINTER(rt_stats)]
+    L.rt_get_geometry.argtypes = [_VP] * 4
+    L.rt_get_neighbours.argtypes = [_VP] * 3
+    L.rt_get_sources.argtypes = [_VP] * 5
+    L.rt_timing.argtypes = [_VP, i32]
+    L.rt_get_timing.argtypes = [_VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_int64)]
+    _lib = L
+    return L
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, name: str, dtype, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live in device memory")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+class RT:
+    """One library context (rt_ctx) for a static particle set."""
+
+    def __init__(self, n: int, groups: int, precision: str = "fp64", box: float = 1.0,
+                 eta: float = ETA, kappa: float = KAPPA, c_red: float = 1.0, cfl: float = 0.9,
+                 device: Optional[torch.device] = None):
+        self.L = load_library()
+        self.n, self.G = int(n), int(groups)
+        self.precision = precision
+        self.sdtype = torch.float64 if precision == "fp64" else torch.float32
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        self.params = rt_params(self.n, self.G, RT_FP64 if precision == "fp64" else RT_FP32C,
+                                box, eta, kappa, c_red, cfl, stream)
+        h = _VP()
+        st = self.L.rt_create(ctypes.byref(self.params), ctypes.byref(h))
+        if st != RT_OK:
+            raise RTError(st, self.L.rt_last_error(None).decode())
+        self.ctx = h
+        self.S = 0
+        self.dt = None
+        self.perm = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                self.L.rt_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    # -- plumbing -----------------------------------------------------------
+    def _check(self, st: int):
+        if st != RT_OK:
+            raise RTError(st, self.L.rt_last_error(self.ctx).decode())
+
+    def _bind_stream(self):
+        self.L.rt_set_stream(self.ctx, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def state(self, fill: float = 0.0) -> torch.Tensor:
+        return torch.full((self.n, self.G, 4), fill, dtype=self.sdtype, device=self.device)
+
+    def grad_buffer(self) -> torch.Tensor:
+        return torch.empty((self.n, self.G, 4, 3), dtype=self.sdtype, device=self.device)
+
+    # -- the C entry points ---------------------------------------------------
+    def rt_build_cells(self, x: torch.Tensor, h_in: Optional[torch.Tensor] = None):
+        """Returns (perm, h, V, dt): Morton permutation and sorted-order h, V,
+        and the global time step (device scalar)."""
+        _need(x, "x", torch.float64, (self.n, 3))
+        if h_in is not None:
+            _need(h_in, "h_in", torch.float64, (self.n,))
+        perm = torch.empty(self.n, dtype=torch.int64, device=self.device)
+        h = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        V = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        dt = torch.empty(1, dtype=torch.float64, device=self.device)
+        self._bind_stream()
+        self._check(self.L.rt_build_cells(self.ctx, _ptr(x), _ptr(h_in), _ptr(perm), _ptr(h),
+                                          _ptr(V), _ptr(dt)))
+        self.perm, self.h, self.V, self.dt = perm, h, V, dt
+        return perm, h, V, dt
+
+    def rt_set_sources(self, xs: torch.Tensor, eta_star: float = ETA):
+        S = 0 if xs is None else int(xs.shape[0])
+        if S:
+            _need(xs, "xs", torch.float64, (S, 3))
+        self._bind_stream()
+        self._check(self.L.rt_set_sources(self.ctx, S, _ptr(xs) if S else None, eta_star))
+        self.S = S
+
+    def rt_inject(self, U: torch.Tensor, L: torch.Tensor, dt: Optional[torch.Tensor] = None):
+        _need(U, "U", self.sdtype, (self.n, self.G, 4))
+        _need(L, "L", torch.float64, (self.S, self.G))
+        dt = self.dt if dt is None else dt
+        self._bind_stream()
+        self._check(self.L.rt_inject(self.ctx, _ptr(U), _ptr(L), _ptr(dt)))
+
+    def rt_gradient(self, U: torch.Tensor, dU: Optional[torch.Tensor] = None) -> torch.Tensor:
+        _need(U, "U", self.sdtype, (self.n, self.G, 4))
+        dU = self.grad_buffer() if dU is None else dU
+        _need(dU, "dU", self.sdtype, (self.n, self.G, 4, 3))
+        self._bind_stream()
+        self._check(self.L.rt_gradient(self.ctx, _ptr(U), _ptr(dU)))
+        return dU
+
+    def rt_transport(self, U, dU, dt=None, U_out=None, photon_total=None, counts=None,
+                     ledger=None, guard_mask=None) -> torch.Tensor:
+        _need(U, "U", self.sdtype, (self.n, self.G, 4))
+        _need(dU, "dU", self.sdtype, (self.n, self.G, 4, 3))
+        dt = self.dt if dt is None else dt
+        _need(dt, "dt", torch.float64, (1,))
+        U_out = torch.empty_like(U) if U_out is None else U_out
+        _need(U_out, "U_out", self.sdtype, (self.n, self.G, 4))
+        if photon_total is not None:
+            _need(photon_total, "photon_total", torch.float64, (self.G,))
+        if counts is not None:
+            _need(counts, "counts", torch.int64, (4,))
+        if ledger is not None:
+            _need(ledger, "ledger", torch.float64, (self.G,))
+        if guard_mask is not None:
+            _need(guard_mask, "guard_mask", torch.uint8, (self.n, self.G))
+        self._bind_stream()
+        self._check(self.L.rt_transport(self.ctx, _ptr(U), _ptr(dU), _ptr(dt), _ptr(U_out),
+                                        _ptr(photon_total), _ptr(counts), _ptr(ledger),
+                                        _ptr(guard_mask)))
+        return U_out
+
+    def rt_photon_total(self, U: torch.Tensor) -> torch.Tensor:
+        _need(U, "U", self.sdtype, (self.n, self.G, 4))
+        Q = torch.empty(self.G, dtype=torch.float64, device=self.device)
+        self._bind_stream()
+        self._check(self.L.rt_photon_total(self.ctx, _ptr(U), _ptr(Q)))
+        return Q
+
+    def rt_adjoint(self, U_pre, L, lam_next, lam=None, dU=None, guard_mask=None, dL_dL=None,
+                   dt=None) -> torch.Tensor:
+        _need(U_pre, "U_pre", self.sdtype, (self.n, self.G, 4))
+        _need(lam_next, "lam_next", self.sdtype, (self.n, self.G, 4))
+        lam = torch.empty_like(lam_next) if lam is None else lam
+        _need(lam, "lam", self.sdtype, (self.n, self.G, 4))
+        if self.S:
+            _need(L, "L", torch.float64, (self.S, self.G))
+        if dU is not None:
+            _need(dU, "dU", self.sdtype, (self.n, self.G, 4, 3))
+        if guard_mask is not None:
+            _need(guard_mask, "guard_mask", torch.uint8, (self.n, self.G))
+        if dL_dL is not None:
+            _need(dL_dL, "dL_dL", torch.float64, (self.S, self.G))
+        dt = self.dt if dt is None else dt
+        self._bind_stream()
+        self._check(self.L.rt_adjoint(self.ctx, _ptr(U_pre), _ptr(L) if self.S else None,
+                                      _ptr(dt), _ptr(dU), _ptr(guard_mask), _ptr(lam_next),
+                                      _ptr(lam), _ptr(dL_dL)))
+        return lam
+
+    def rt_sync(self):
+        self._check(self.L.rt_sync(self.ctx))
+
+    # -- queries --------------------------------------------------------------
+    def rt_get_stats(self) -> dict:
+        s = rt_stats()
+        self._check(self.L.rt_get_stats(self.ctx, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in rt_stats._fields_}
+
+    def rt_get_geometry(self):
+        B = torch.empty((self.n, 6), dtype=torch.float64, device=self.device)
+        nn = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        ng = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        self._check(self.L.rt_get_geometry(self.ctx, _ptr(B), _ptr(nn), _ptr(ng)))
+        return B, nn, ng
+
+    def rt_get_neighbours(self):
+        st = self.rt_get_stats()
+        ptr = torch.empty(self.n + 1, dtype=torch.int64, device=self.device)
+        idx = torch.empty(max(st["n_entries"], 1), dtype=torch.int32, device=self.device)
+        self._check(self.L.rt_get_neighbours(self.ctx, _ptr(ptr), _ptr(idx)))
+        return ptr, idx[:st["n_entries"]]
+
+    def rt_get_sources(self):
+        st = self.rt_get_stats()
+        m = max(st["n_inject"], 1)
+        gas = torch.empty(m, dtype=torch.int32, device=self.device)
+        src = torch.empty(m, dtype=torch.int32, device=self.device)
+        xi = torch.empty(m, dtype=torch.float64, device=self.device)
+        hs = torch.empty(max(self.S, 1), dtype=torch.float64, device=self.device)
+        self._check(self.L.rt_get_sources(self.ctx, _ptr(gas), _ptr(src), _ptr(xi), _ptr(hs)))
+        k = st["n_inject"]
+        return gas[:k], src[:k], xi[:k], hs[:self.S]
+
+    def rt_timing(self, on: bool):
+        self._bind_stream()
+        self._check(self.L.rt_timing(self.ctx, 1 if on else 0))
+
+    def rt_get_timing(self, kernel: str):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        self._check(self.L.rt_get_timing(self.ctx, kernel.encode(), ctypes.byref(ms),
+                                         ctypes.byref(cnt)))
+        return ms.value, cnt.value
+
+    # -- composition of the entry points (no arithmetic) ----------------------
+    def step(self, U: torch.Tensor, L: Optional[torch.Tensor] = None, dU=None, U_out=None,
+             **kw) -> torch.Tensor:
+        """One RT step in the operator-splitting order injection -> gradient ->
+        transport (Part III "One RT time step").  U is injected in place."""
+        if self.S:
+            self.rt_inject(U, L)
+        dU = self.rt_gradient(U, dU)
+        return self.rt_transport(U, dU, U_out=U_out, **kw)
