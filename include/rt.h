@@ -20,8 +20,13 @@
  *    library's Morton order once rt_build_cells has run: position i of those
  *    arrays is input particle perm[i].
  *  - The state U of one particle is G photon groups x (E, Fx, Fy, Fz), i.e.
- *    U[n][G][4]; its gradient is dU[n][G][4][3] (d/dx, d/dy, d/dz).  The
- *    element type is double for RT_FP64 and float for RT_FP32C.
+ *    U[n][G][4].  The element type is double for RT_FP64 and float for
+ *    RT_FP32C.
+ *  - The gradient record UD[n][G][16] holds per particle and group the state
+ *    followed by the gradient of each of its components:
+ *    UD[i][g][0..4) = U[i][g][0..4) and UD[i][g][4 + 3 m + a] = d U[i][g][m] / d x_a.
+ *    One group of one particle is one 128-byte line in FP64, so a neighbour's
+ *    data is fetched in whole cache lines.
  *  - Errors: argument checks fail synchronously with RT_EINVAL and a message
  *    (rt_last_error).  Conditions found on the device (smoothing length not
  *    converged, singular E matrix, non-finite state) raise bits of a device
@@ -108,8 +113,9 @@ rt_status rt_inject(rt_ctx *ctx, void *U, const double *L, const double *dt);
 
 /* Least-squares gradients (eq:gradient) of every component of U:
  *   dU_i = sum_{j: r_ij < H_i} (U_j - U_i) psi_tilde_j(x_i).
- * U [n][G][4] in, dU [n][G][4][3] out.  U and dU must not overlap. */
-rt_status rt_gradient(rt_ctx *ctx, const void *U, void *dU);
+ * U [n][G][4] in; UD [n][G][16] out (state and gradients, see above).
+ * U and UD must not overlap. */
+rt_status rt_gradient(rt_ctx *ctx, const void *U, void *UD);
 
 /* One transport step (eq:transport-update-explicit with one global dt):
  *   U_out_k = U_k - dt/V_k sum_l Flux_kl . A_kl
@@ -118,7 +124,8 @@ rt_status rt_gradient(rt_ctx *ctx, const void *U, void *dU);
  * x_kl = x_k + h_k/(h_k + h_l)(x_l - x_k) (eq:rt-riemann-problem), and the M1
  * closure (eq:eddington-group).  Face states and the updated state are
  * guarded: E < 0 is set to 0 (with F = 0) and |F| > c E is scaled to c E.
- *   U, dU     in (dU = rt_gradient(U));  U_out out, must not overlap U.
+ *   UD        in: gradient record of the state, written by rt_gradient.
+ *   U_out     [n][G][4] out, must not overlap UD.
  *   dt        [1] device.
  *   photon_total [G] out or NULL: Q_g = sum_k V_k E_kg of U_out (FP64,
  *             compensated, deterministic).
@@ -129,8 +136,8 @@ rt_status rt_gradient(rt_ctx *ctx, const void *U, void *dU);
  *             clipping E < 0 of the updated state).
  *   guard_mask [n][G] uint8 out or NULL: per updated state, bit0 = E clipped,
  *             bit1 = F rescaled (consumed by rt_adjoint). */
-rt_status rt_transport(rt_ctx *ctx, const void *U, const void *dU, const double *dt,
-                       void *U_out, double *photon_total, int64_t *counts, double *ledger,
+rt_status rt_transport(rt_ctx *ctx, const void *UD, const double *dt, void *U_out,
+                       double *photon_total, int64_t *counts, double *ledger,
                        uint8_t *guard_mask);
 
 /* Q_g = sum_k V_k E_kg of U, [G] out (FP64, compensated, deterministic). */
@@ -144,14 +151,15 @@ rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q);
  *   U_pre    [n][G][4] state before injection of this step.
  *   L        [S][G] luminosities used by the step (NULL if no sources).
  *   dt       [1] device.
- *   dU       gradient of the post-injection state, or NULL (recomputed).
+ *   UD       gradient record of the post-injection state (rt_gradient after
+ *            rt_inject), or NULL (recomputed into library scratch).
  *   guard_mask from the forward rt_transport of this step, or NULL
  *            (recomputed).
  *   lam_next [n][G][4] dLoss/dU_next.  lam [n][G][4] out: dLoss/dU_pre; may
  *            alias lam_next.
  *   dL_dL    [S][G] double, accumulated (+=) dLoss/dL, or NULL. */
 rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
-                     const void *dU, const uint8_t *guard_mask, const void *lam_next,
+                     const void *UD, const uint8_t *guard_mask, const void *lam_next,
                      void *lam, double *dL_dL);
 
 /* Wait for the stream; return the first device-side error raised since the

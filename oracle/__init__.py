@@ -169,15 +169,15 @@ def glf(qL, qR, nh, c: float) -> np.ndarray:
 
 def _knn_covering(tree: cKDTree, pts: np.ndarray, radius_fn, k0: int = 96,
                   kmax: int = 1 << 14):
-    """k-nearest candidate rows for every query point such that the last
-    candidate distance reaches radius_fn(rows, d, idx) (rows that fail are
-    queried again with twice the k).  Returns a list of (rows, d, idx)."""
+    """k-nearest candidate rows for every query point such that the row
+    satisfies radius_fn(rows, d, idx) (rows that fail are queried again with
+    twice the k).  Returns a list of (rows, d, idx) blocks."""
     n_pts = tree.n
     out = []
     rows = np.arange(pts.shape[0])
     k = min(k0, n_pts)
     while rows.size:
-        d, idx = tree.query(pts[rows], k=k)
+        d, idx = tree.query(pts[rows], k=k, workers=-1)
         d = d.reshape(rows.size, k)
         idx = idx.reshape(rows.size, k).astype(np.int64)
         ok = radius_fn(rows, d, idx)
@@ -191,7 +191,8 @@ def _knn_covering(tree: cKDTree, pts: np.ndarray, radius_fn, k0: int = 96,
     return out
 
 
-def solve_h(tree: cKDTree, pts: np.ndarray, eta: float = ETA, kappa: float = KAPPA):
+def solve_h(tree: cKDTree, pts: np.ndarray, eta: float = ETA, kappa: float = KAPPA,
+            return_blocks: bool = False):
     """Smoothing lengths of the query points over the particles in `tree`
     (eq:number-of-neighbors; root of h^3 sum_j W(r_j, kappa h) = eta^3)."""
     L = lib()
@@ -213,31 +214,40 @@ def solve_h(tree: cKDTree, pts: np.ndarray, eta: float = ETA, kappa: float = KAP
         iters[rows[ok]] = it[ok]
         return ok
 
-    _knn_covering(tree, pts, fn)
+    blocks = _knn_covering(tree, pts, fn)
+    if return_blocks:
+        return h, iters, blocks
     return h, iters
 
 
-def gather_lists(tree: cKDTree, x: np.ndarray, H: np.ndarray):
-    """CSR of G(i) = {j != i : r_ij < H_i}, rows sorted by partner index."""
+def gather_lists(tree: cKDTree, x: np.ndarray, H: np.ndarray, blocks=None):
+    """CSR of G(i) = {j != i : r_ij < H_i}, rows sorted by partner index.
+    `blocks` are candidate rows whose last distance reaches H (reused from the
+    smoothing-length solve when available)."""
     n = x.shape[0]
-    rows_all, cols_all = [], []
-
-    def fn(rows, d, idx):
-        return d[:, -1] >= H[rows]
-
-    for rows, d, idx in _knn_covering(tree, x, fn):
+    if blocks is None:
+        blocks = _knn_covering(tree, x, lambda rows, d, idx: d[:, -1] >= H[rows])
+    counts = np.zeros(n, dtype=np.int64)
+    parts = []
+    big = np.iinfo(np.int64).max
+    for rows, d, idx in blocks:
+        if not np.all(d[:, -1] >= H[rows]):
+            raise OracleError(-1, "candidate rows do not cover the compact support")
         m = (d < H[rows][:, None]) & (idx != rows[:, None])
-        r_, c_ = np.nonzero(m)
-        rows_all.append(rows[r_])
-        cols_all.append(idx[r_, c_])
-    r = np.concatenate(rows_all) if rows_all else np.zeros(0, np.int64)
-    cidx = np.concatenate(cols_all) if cols_all else np.zeros(0, np.int64)
-    order = np.lexsort((cidx, r))
-    r, cidx = r[order], cidx[order]
+        sel = np.where(m, idx, big)
+        sel.sort(axis=1)
+        c = m.sum(axis=1)
+        counts[rows] = c
+        parts.append((rows, sel, c))
     ptr = np.zeros(n + 1, dtype=np.int64)
-    np.add.at(ptr, r + 1, 1)
-    ptr = np.cumsum(ptr)
-    return _i64a(ptr), _i64a(cidx)
+    ptr[1:] = np.cumsum(counts)
+    out = np.zeros(ptr[-1], dtype=np.int64)
+    for rows, sel, c in parts:
+        w = sel.shape[1]
+        keep = np.arange(w)[None, :] < c[:, None]
+        dst = ptr[rows][:, None] + np.arange(w)[None, :]
+        out[dst[keep]] = sel[keep]
+    return _i64a(ptr), _i64a(out)
 
 
 def symmetric_lists(n: int, gptr: np.ndarray, gidx: np.ndarray):
@@ -300,14 +310,14 @@ def build_geometry(x, eta: float = ETA, kappa: float = KAPPA, c: float = 1.0,
     n = x.shape[0]
     boxv = np.full(3, float(box))
     tree = cKDTree(x, boxsize=box)
-    iters = None
+    iters, blocks = None, None
     if h is None:
-        h, iters = solve_h(tree, x, eta, kappa)
+        h, iters, blocks = solve_h(tree, x, eta, kappa, return_blocks=True)
     h = _f64(h)
     H = kappa * h
     if np.any(H >= 0.5 * box):
         raise OracleError(-1, "compact support exceeds half the box")
-    gptr, gidx = gather_lists(tree, x, H)
+    gptr, gidx = gather_lists(tree, x, H, blocks)
     sptr, sidx = symmetric_lists(n, gptr, gidx)
     omega = np.zeros(n)
     V = np.zeros(n)
@@ -341,15 +351,11 @@ def build_sources(geom: Geometry, xs, eta_star: float = ETA) -> Sources:
     if S == 0:
         z = np.zeros(0, np.int64)
         return Sources(xs, np.zeros(0), z, z, np.zeros(0), np.zeros(0, np.int32))
-    hs, _ = solve_h(geom.tree, xs, eta_star, geom.kappa)
+    hs, _, blocks = solve_h(geom.tree, xs, eta_star, geom.kappa, return_blocks=True)
     Hs = geom.kappa * hs
     src, gas, xi, qnz = [], [], [], []
-
-    def fn(rows, d, idx):
-        return d[:, -1] >= Hs[rows]
-
     cand = {}
-    for rows, d, idx in _knn_covering(geom.tree, xs, fn):
+    for rows, d, idx in blocks:
         for r_, dd, ii in zip(rows, d, idx):
             cand[int(r_)] = ii[dd < Hs[r_]]
     for s in range(S):

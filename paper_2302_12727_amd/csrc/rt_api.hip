@@ -154,27 +154,26 @@ static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
     return x < y + nb && y < x + na;
 }
 
-rt_status rt_gradient(rt_ctx *ctx, const void *U, void *dU) {
+rt_status rt_gradient(rt_ctx *ctx, const void *U, void *UD) {
     if (!ctx) return RT_EINVAL;
     if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
-    if (!U || !dU) return rt_fail(ctx, RT_EINVAL, "U and dU are required");
+    if (!U || !UD) return rt_fail(ctx, RT_EINVAL, "U and UD are required");
     size_t es = ctx->p.precision == RT_FP64 ? 8 : 4;
     size_t nu = es * 4 * ctx->p.groups * ctx->p.n;
-    if (overlap(U, nu, dU, 3 * nu)) return rt_fail(ctx, RT_EINVAL, "U and dU overlap");
-    return rt_gradient_impl(ctx, U, dU);
+    if (overlap(U, nu, UD, 4 * nu)) return rt_fail(ctx, RT_EINVAL, "U and UD overlap");
+    return rt_gradient_impl(ctx, U, UD);
 }
 
-rt_status rt_transport(rt_ctx *ctx, const void *U, const void *dU, const double *dt,
-                       void *U_out, double *photon_total, int64_t *counts, double *ledger,
+rt_status rt_transport(rt_ctx *ctx, const void *UD, const double *dt, void *U_out,
+                       double *photon_total, int64_t *counts, double *ledger,
                        uint8_t *guard_mask) {
     if (!ctx) return RT_EINVAL;
     if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
-    if (!U || !dU || !dt || !U_out) return rt_fail(ctx, RT_EINVAL, "U, dU, dt and U_out are required");
+    if (!UD || !dt || !U_out) return rt_fail(ctx, RT_EINVAL, "UD, dt and U_out are required");
     size_t es = ctx->p.precision == RT_FP64 ? 8 : 4;
     size_t nu = es * 4 * ctx->p.groups * ctx->p.n;
-    if (overlap(U, nu, U_out, nu)) return rt_fail(ctx, RT_EINVAL, "U and U_out overlap");
-    if (overlap(dU, 3 * nu, U_out, nu)) return rt_fail(ctx, RT_EINVAL, "dU and U_out overlap");
-    return rt_transport_impl(ctx, U, dU, dt, U_out, photon_total, counts, ledger, guard_mask);
+    if (overlap(UD, 4 * nu, U_out, nu)) return rt_fail(ctx, RT_EINVAL, "UD and U_out overlap");
+    return rt_transport_impl(ctx, UD, dt, U_out, photon_total, counts, ledger, guard_mask);
 }
 
 rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q) {
@@ -185,14 +184,14 @@ rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q) {
 }
 
 rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
-                     const void *dU, const uint8_t *guard_mask, const void *lam_next,
+                     const void *UD, const uint8_t *guard_mask, const void *lam_next,
                      void *lam, double *dL_dL) {
     if (!ctx) return RT_EINVAL;
     if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
     if (!U_pre || !dt || !lam_next || !lam)
         return rt_fail(ctx, RT_EINVAL, "U_pre, dt, lam_next and lam are required");
     if (ctx->S > 0 && !L) return rt_fail(ctx, RT_EINVAL, "L is required when sources are set");
-    return rt_adjoint_impl(ctx, U_pre, L, dt, dU, guard_mask, lam_next, lam, dL_dL);
+    return rt_adjoint_impl(ctx, U_pre, L, dt, UD, guard_mask, lam_next, lam, dL_dL);
 }
 
 rt_status rt_sync(rt_ctx *ctx) {
@@ -231,6 +230,7 @@ rt_status rt_get_geometry(rt_ctx *ctx, double *B, int32_t *n_nbr, int32_t *n_gat
     if (B) {
         // B_i = E_i^{-1} = Bv_i / (V_i^2 sigma / H_i^3)
         std::vector<double> rec((size_t)n * kRec), out((size_t)n * 6);
+        RT_HIP(hipStreamSynchronize(ctx->stream));
         RT_HIP(hipMemcpy(rec.data(), ctx->geo, sizeof(double) * kRec * n, hipMemcpyDeviceToHost));
         for (int64_t i = 0; i < n; ++i) {
             const double *r = &rec[(size_t)i * kRec];

@@ -358,6 +358,7 @@ __global__ void k_geometry(int64_t n, const double *__restrict__ xs, const doubl
         rec[R_B + 3] = f * c11;
         rec[R_B + 4] = f * c12;
         rec[R_B + 5] = f * c22;
+        rec[12] = rec[13] = rec[14] = rec[15] = 0.0;
         if (geo32) {
             float *r32 = geo32 + (int64_t)F_REC * i;
             r32[F_IH] = (float)iH;

@@ -16,14 +16,14 @@ namespace gearrt {
 constexpr int kWave = 64;     // wavefront width on CDNA
 constexpr int kBlock = 256;   // threads per block of the per-particle kernels
 constexpr int kLeaf = 32;     // particles per leaf of the search tree
-constexpr int kRec = 12;      // doubles per particle geometry record
+constexpr int kRec = 16;      // doubles per particle geometry record (one 128-byte line)
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kSigma3 = 16.0 / kPi;   // cubic spline normalisation in 3D
 
 // Device status word bits.
 enum : int32_t { ST_NOCONV = 1, ST_SINGULAR = 2, ST_BIGH = 4, ST_NONFINITE = 8 };
 
-// Geometry record, one per particle (Morton order), 96 bytes:
+// Geometry record, one per particle (Morton order), 128 bytes (12 used):
 //   0..2  x, y, z       position in [0, box)
 //   3     1/H           inverse compact support radius, H = kappa h
 //   4     h             smoothing length
@@ -133,6 +133,36 @@ __device__ __forceinline__ double kern_dw(double q) {
     return -3.0 * a * a + 12.0 * (b * b);
 }
 
+// 1/x for normal x > 0: the hardware estimate (v_rcp_f64, about 2^-23
+// relative) refined by two Newton-Raphson steps r <- r + r (1 - x r), which
+// square the error each: about one ulp.
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+// 1/sqrt(x) for normal x > 0: hardware estimate (v_rsq_f64) and two Newton
+// steps y <- y (3 - x y^2)/2.
+__device__ __forceinline__ double rsq64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    double t = __builtin_fma(-h * y, y, 0.5);
+    y = __builtin_fma(y, t, y);
+    t = __builtin_fma(-h * y, y, 0.5);
+    return __builtin_fma(y, t, y);
+}
+// sqrt(x) for x >= 0: g = x / sqrt(x) from rsq64 and one Newton correction of
+// the root, g <- g + (x - g^2) / (2 g); sqrt(0) = 0.
+__device__ __forceinline__ double sqrt64(double x) {
+    double y = rsq64(x);
+    double g = x * y;
+    double d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, 0.5 * y, g);
+    return x > 0.0 ? g : 0.0;
+}
+
 // Periodic nearest-image separation component.
 __device__ __forceinline__ double min_image(double d, double box, double ibox) {
     return d - box * rint(d * ibox);
@@ -226,14 +256,13 @@ rt_status rt_sources_impl(rt_ctx *ctx, int32_t n_src, const double *xs, double e
 
 // step (rt_step.hip)
 rt_status rt_inject_impl(rt_ctx *ctx, void *U, const double *L, const double *dt);
-rt_status rt_gradient_impl(rt_ctx *ctx, const void *U, void *dU);
-rt_status rt_transport_impl(rt_ctx *ctx, const void *U, const void *dU, const double *dt,
-                            void *U_out, double *Q, int64_t *counts, double *ledger,
-                            uint8_t *mask);
+rt_status rt_gradient_impl(rt_ctx *ctx, const void *U, void *UD);
+rt_status rt_transport_impl(rt_ctx *ctx, const void *UD, const double *dt, void *U_out,
+                            double *Q, int64_t *counts, double *ledger, uint8_t *mask);
 rt_status rt_total_impl(rt_ctx *ctx, const void *U, double *Q);
 rt_status rt_ensure_partials(rt_ctx *ctx);
 
 // adjoint (rt_adjoint.hip)
 rt_status rt_adjoint_impl(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
-                          const void *dU, const uint8_t *mask, const void *lam_next,
+                          const void *UD, const uint8_t *mask, const void *lam_next,
                           void *lam, double *dL_dL);

@@ -39,9 +39,10 @@ __global__ void k_inject(int32_t ngas, int G, const int32_t *__restrict__ gptr,
 // and V_i cancel against B_i, see the geometry record).
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_gradient64(
-    int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
-    const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_gath,
-    const double *__restrict__ U, double *__restrict__ D, double box) {
+    int64_t n, int64_t nb, const double *__restrict__ geo, const double *__restrict__ xs,
+    const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
+    const int32_t *__restrict__ n_gath, const double *__restrict__ U, double *__restrict__ UD,
+    double box) {
     const int64_t blk = xcd_block(nb);
     if (blk >= nb) return;
     const int64_t i = blk * kBlock + threadIdx.x;
@@ -49,7 +50,8 @@ __global__ __launch_bounds__(kBlock) void k_gradient64(
     constexpr int NQ = 4 * G;
     const double ibox = 1.0 / box;
     const double *rec = geo + (int64_t)kRec * i;
-    const double px = rec[0], py = rec[1], pz = rec[2], iH = rec[R_IH], iV = 1.0 / rec[R_V];
+    const double px = xs[3 * i], py = xs[3 * i + 1], pz = xs[3 * i + 2];
+    const double iH = rec[R_IH], iV = 1.0 / rec[R_V];
     double Ui[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) Ui[q] = U[i * NQ + q];
@@ -60,11 +62,10 @@ __global__ __launch_bounds__(kBlock) void k_gradient64(
     const int32_t ng = n_gath[i];
     for (int32_t k = 0; k < ng; ++k) {
         const int64_t j = nbr[base + 64 * (int64_t)k];
-        const double *rj = geo + (int64_t)kRec * j;
-        const double sx = min_image(rj[0] - px, box, ibox);
-        const double sy = min_image(rj[1] - py, box, ibox);
-        const double sz = min_image(rj[2] - pz, box, ibox);
-        const double w = kern_w(sqrt(sx * sx + sy * sy + sz * sz) * iH);
+        const double sx = min_image(xs[3 * j] - px, box, ibox);
+        const double sy = min_image(xs[3 * j + 1] - py, box, ibox);
+        const double sz = min_image(xs[3 * j + 2] - pz, box, ibox);
+        const double w = kern_w(sqrt64(sx * sx + sy * sy + sz * sz) * iH);
         const double wx = w * sx, wy = w * sy, wz = w * sz;
         const double *Uj = U + j * NQ;
 #pragma unroll
@@ -77,12 +78,18 @@ __global__ __launch_bounds__(kBlock) void k_gradient64(
     }
     const double b00 = rec[R_B] * iV, b01 = rec[R_B + 1] * iV, b02 = rec[R_B + 2] * iV;
     const double b11 = rec[R_B + 3] * iV, b12 = rec[R_B + 4] * iV, b22 = rec[R_B + 5] * iV;
-    double *Di = D + i * NQ * 3;
+    // group-major record: per group the state then its gradients (one line)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        Di[3 * q + 0] = b00 * acc[q][0] + b01 * acc[q][1] + b02 * acc[q][2];
-        Di[3 * q + 1] = b01 * acc[q][0] + b11 * acc[q][1] + b12 * acc[q][2];
-        Di[3 * q + 2] = b02 * acc[q][0] + b12 * acc[q][1] + b22 * acc[q][2];
+    for (int g = 0; g < G; ++g) {
+        double *o = UD + (i * G + g) * 16;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int q = 4 * g + m;
+            o[m] = Ui[q];
+            o[4 + 3 * m + 0] = b00 * acc[q][0] + b01 * acc[q][1] + b02 * acc[q][2];
+            o[4 + 3 * m + 1] = b01 * acc[q][0] + b11 * acc[q][1] + b12 * acc[q][2];
+            o[4 + 3 * m + 2] = b02 * acc[q][0] + b12 * acc[q][1] + b22 * acc[q][2];
+        }
     }
 }
 
@@ -105,7 +112,7 @@ __device__ __forceinline__ int guard64(double &E, double &Fx, double &Fy, double
     const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
     const double lim = c * E;
     if (F2 > lim * lim) {
-        const double sc = lim / sqrt(F2);
+        const double sc = lim * rsq64(F2);
         Fx *= sc;
         Fy *= sc;
         Fz *= sc;
@@ -123,21 +130,19 @@ __device__ __forceinline__ int guard64(double &E, double &Fx, double &Fy, double
 __device__ __forceinline__ void m1_flux64(double E, double Fx, double Fy, double Fz, double Ax,
                                           double Ay, double Az, double c, double c2, double ic2,
                                           double out[4]) {
+    // Guarded states have E >= 0 and F = 0 when E = 0; with 1/E replaced by 0
+    // there every term below vanishes, so no branch is needed.
     const double FA = Fx * Ax + Fy * Ay + Fz * Az;
-    if (E > 0.0) {
-        const double iE = 1.0 / E;
-        const double f2 = (Fx * Fx + Fy * Fy + Fz * Fz) * (iE * iE) * ic2;
-        const double s = sqrt(fmax(4.0 - 3.0 * f2, 0.0));
-        const double id = 1.0 / (2.0 + s);
-        const double a = c2 * E * (1.0 / 3.0 - f2 * id);
-        const double b = 3.0 * id * FA * iE;
-        out[0] = FA;
-        out[1] = a * Ax + b * Fx;
-        out[2] = a * Ay + b * Fy;
-        out[3] = a * Az + b * Fz;
-    } else {
-        out[0] = out[1] = out[2] = out[3] = 0.0;
-    }
+    const double iE = E > 0.0 ? rcp64(E) : 0.0;
+    const double f2 = (Fx * Fx + Fy * Fy + Fz * Fz) * (iE * iE) * ic2;
+    const double s = sqrt64(fmax(4.0 - 3.0 * f2, 0.0));
+    const double id = rcp64(2.0 + s);
+    const double a = c2 * E * (1.0 / 3.0 - f2 * id);
+    const double b = 3.0 * id * FA * iE;
+    out[0] = FA;
+    out[1] = a * Ax + b * Fx;
+    out[2] = a * Ay + b * Fy;
+    out[3] = a * Az + b * Fz;
 }
 
 __device__ __forceinline__ double minmod(double a, double b) {
@@ -158,7 +163,7 @@ __device__ __forceinline__ void pair_geometry64(const double *__restrict__ rk,
     pg.sx = min_image(rl[0] - rk[0], box, ibox);
     pg.sy = min_image(rl[1] - rk[1], box, ibox);
     pg.sz = min_image(rl[2] - rk[2], box, ibox);
-    const double r = sqrt(pg.sx * pg.sx + pg.sy * pg.sy + pg.sz * pg.sz);
+    const double r = sqrt64(pg.sx * pg.sx + pg.sy * pg.sy + pg.sz * pg.sz);
     const double wk = kern_w(r * rk[R_IH]);
     const double wl = kern_w(r * rl[R_IH]);
     // A_kl = (w_k Bv_k + w_l Bv_l) s   (eq:HopkinsAij, see the record layout)
@@ -171,9 +176,9 @@ __device__ __forceinline__ void pair_geometry64(const double *__restrict__ rk,
     pg.Ax = m00 * pg.sx + m01 * pg.sy + m02 * pg.sz;
     pg.Ay = m01 * pg.sx + m11 * pg.sy + m12 * pg.sz;
     pg.Az = m02 * pg.sx + m12 * pg.sy + m22 * pg.sz;
-    pg.An = sqrt(pg.Ax * pg.Ax + pg.Ay * pg.Ay + pg.Az * pg.Az);
+    pg.An = sqrt64(pg.Ax * pg.Ax + pg.Ay * pg.Ay + pg.Az * pg.Az);
     // interface x_kl = x_k + h_k/(h_k+h_l) s  (eq:rt-riemann-problem)
-    const double ih = 1.0 / (rk[R_H] + rl[R_H]);
+    const double ih = rcp64(rk[R_H] + rl[R_H]);
     pg.fk = rk[R_H] * ih;
     pg.fl = rl[R_H] * ih;
 }
@@ -196,66 +201,130 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NP], double *__re
     }
 }
 
+// LDS transpose of neighbour records.  A lane-per-particle gather makes every
+// wave-wide load touch 64 different cache lines (one address-unit cycle each);
+// instead the wave fetches the 64 records it needs in this iteration with
+// coalesced loads (8 lanes per 128-byte line, 8 lines per instruction), writes
+// them to its own LDS buffer, and each lane then reads its neighbour's record
+// from LDS.  Records are padded to 17 doubles in LDS against bank conflicts.
+constexpr int kStage = 17;
+
+// Order LDS traffic of one wavefront: everything before is complete and
+// visible to the other lanes of the wave before anything after is issued.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Copy one 16-double line per lane's neighbour (line base pointers src + 16 *
+// row[m]) into the wave's stage buffer: 8 loads, each lane moving 16 bytes.
+__device__ __forceinline__ void stage_lines(const double *__restrict__ src, const int64_t (&row)[8],
+                                            double *sb, int lane) {
+    const int piece = lane & 7, slot = lane >> 3;
+    double2 v[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+        v[m] = *reinterpret_cast<const double2 *>(src + 16 * row[m] + 2 * piece);
+    wave_lds_sync();
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        double *d = sb + (8 * m + slot) * kStage + 2 * piece;
+        d[0] = v[m].x;
+        d[1] = v[m].y;
+    }
+    wave_lds_sync();
+}
+
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_transport64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
-    const double *__restrict__ U, const double *__restrict__ D, const double *__restrict__ dtp,
-    double c, double box, double *__restrict__ Uout, double *__restrict__ partials,
+    const double *__restrict__ UD, const double *__restrict__ dtp, double c, double box,
+    double *__restrict__ Uout, double *__restrict__ partials,
     unsigned long long *__restrict__ counts, uint8_t *__restrict__ mask) {
     constexpr int NQ = 4 * G;
+    __shared__ double stage[kBlock / 64][64 * kStage];
     __shared__ double smem[(kBlock / 64) * 2 * G];
     __shared__ unsigned long long scnt[4];
     const int64_t blk = xcd_block(nb);
     if (blk >= nb) return;                      // whole block: no barrier is skipped
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t i = blk * kBlock + threadIdx.x;
     const bool active = i < n;
+    const int64_t ic = active ? i : n - 1;      // in-range index for inactive lanes
+    const int64_t w = i >> 6;
+    const bool wave_live = (w << 6) < n;        // wave-uniform
     const double ibox = 1.0 / box, c2 = c * c, ic2 = 1.0 / c2, hc = 0.5 * c;
     if (threadIdx.x < 4) scnt[threadIdx.x] = 0;
+    double *sb = stage[wv];
 
+    // own particle: geometry record, state and gradients (registers)
+    const double *rk = geo + (int64_t)kRec * ic;
+    double Ui[NQ], Di[NQ * 3];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const double *r = UD + (ic * G + g) * 16;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            Ui[4 * g + m] = r[m];
+            Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
+            Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
+            Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
+        }
+    }
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     int cE = 0, cF = 0;
-    double Ui[NQ];
-    const double *rk = geo + (int64_t)kRec * (active ? i : 0);
-    if (active) {
+
+    if (wave_live) {
+        const int64_t base = wave_base[w] + lane;
+        const int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
+        const int32_t nn = active ? n_nbr[i] : 0;
+        for (int32_t k = 0; k < kmax; ++k) {
+            const bool valid = k < nn;
+            const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
+            int64_t row[8];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) Ui[q] = U[i * NQ + q];
-        const int64_t base = wave_base[i >> 6] + (i & 63);
-        const int32_t nn = n_nbr[i];
-        const double *Di = D + i * NQ * 3;
-        for (int32_t k = 0; k < nn; ++k) {
-            const int64_t j = nbr[base + 64 * (int64_t)k];
-            const double *rl = geo + (int64_t)kRec * j;
+            for (int m = 0; m < 8; ++m) row[m] = __shfl(j, 8 * m + (lane >> 3), 64);
+            // pair geometry from the staged geometry records
+            stage_lines(geo, row, sb, lane);
+            double rl[12];
+#pragma unroll
+            for (int q = 0; q < 12; ++q) rl[q] = sb[lane * kStage + q];
             PairGeo pg;
             pair_geometry64(rk, rl, box, ibox, pg);
-            if (!(pg.An > 0.0)) continue;
-            const double *Uj = U + j * NQ;
-            const double *Dj = D + j * NQ * 3;
+            const bool use = valid && pg.An > 0.0;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
+                int64_t rowg[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g;
+                stage_lines(UD, rowg, sb, lane);
+                const double *Rl = sb + lane * kStage;
                 double qL[4], qR[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const int q = 4 * g + m;
                     const double dk = Di[3 * q] * pg.sx + Di[3 * q + 1] * pg.sy + Di[3 * q + 2] * pg.sz;
-                    const double dl = Dj[3 * q] * pg.sx + Dj[3 * q + 1] * pg.sy + Dj[3 * q + 2] * pg.sz;
+                    const double dl = Rl[4 + 3 * m] * pg.sx + Rl[5 + 3 * m] * pg.sy + Rl[6 + 3 * m] * pg.sz;
                     const double mm = minmod(dk, dl);
                     qL[m] = Ui[q] + pg.fk * mm;
-                    qR[m] = Uj[q] - pg.fl * mm;
+                    qR[m] = Rl[m] - pg.fl * mm;
                 }
                 const int f1 = guard64(qL[0], qL[1], qL[2], qL[3], c);
                 const int f2 = guard64(qR[0], qR[1], qR[2], qR[3], c);
-                cE += (f1 & 1) + (f2 & 1);
-                cF += (f1 >> 1) + (f2 >> 1);
                 double FL[4], FR[4];
                 m1_flux64(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, c2, ic2, FL);
                 m1_flux64(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, c2, ic2, FR);
                 const double dis = hc * pg.An;
+                if (use) {
+                    cE += (f1 & 1) + (f2 & 1);
+                    cF += (f1 >> 1) + (f2 >> 1);
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    acc[4 * g + m] += 0.5 * (FL[m] + FR[m]) - dis * (qR[m] - qL[m]);
+                    for (int m = 0; m < 4; ++m)
+                        acc[4 * g + m] += 0.5 * (FL[m] + FR[m]) - dis * (qR[m] - qL[m]);
+                }
             }
         }
     }
@@ -372,19 +441,19 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int64_t nb, int G,
 }
 
 template <int G>
-void launch_transport64(rt_ctx *ctx, const double *U, const double *D, const double *dt,
-                        double *Uout, double *partials, int64_t *counts, uint8_t *mask) {
+void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double *Uout,
+                        double *partials, int64_t *counts, uint8_t *mask) {
     const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
     k_transport64<G><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
-        n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, U, D, dt, ctx->p.c_red,
+        n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
         ctx->p.box, Uout, partials, (unsigned long long *)counts, mask);
 }
 
 template <int G>
-void launch_gradient64(rt_ctx *ctx, const double *U, double *D) {
+void launch_gradient64(rt_ctx *ctx, const double *U, double *UD) {
     const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
     k_gradient64<G><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
-        n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_gath, U, D, ctx->p.box);
+        n, nb, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box);
 }
 
 #define RT_DISPATCH_G(G_, FN, ...)                                  \
@@ -429,10 +498,10 @@ rt_status rt_inject_impl(rt_ctx *ctx, void *U, const double *L, const double *dt
     return RT_OK;
 }
 
-rt_status rt_gradient_impl(rt_ctx *ctx, const void *U, void *dU) {
+rt_status rt_gradient_impl(rt_ctx *ctx, const void *U, void *UD) {
     rt_timer_begin(ctx, "gradient");
     if (ctx->p.precision == RT_FP64) {
-        RT_DISPATCH_G(ctx->p.groups, launch_gradient64, ctx, (const double *)U, (double *)dU);
+        RT_DISPATCH_G(ctx->p.groups, launch_gradient64, ctx, (const double *)U, (double *)UD);
     } else {
         return rt_fail(ctx, RT_EINVAL, "FP32C gradient not available");
     }
@@ -441,15 +510,14 @@ rt_status rt_gradient_impl(rt_ctx *ctx, const void *U, void *dU) {
     return RT_OK;
 }
 
-rt_status rt_transport_impl(rt_ctx *ctx, const void *U, const void *dU, const double *dt,
-                            void *U_out, double *Q, int64_t *counts, double *ledger,
-                            uint8_t *mask) {
+rt_status rt_transport_impl(rt_ctx *ctx, const void *UD, const double *dt, void *U_out,
+                            double *Q, int64_t *counts, double *ledger, uint8_t *mask) {
     const int64_t nb = (ctx->p.n + kBlock - 1) / kBlock;
     double *part = (Q || ledger) ? ctx->partials : nullptr;
     rt_timer_begin(ctx, "transport");
     if (ctx->p.precision == RT_FP64) {
-        RT_DISPATCH_G(ctx->p.groups, launch_transport64, ctx, (const double *)U,
-                      (const double *)dU, dt, (double *)U_out, part, counts, mask);
+        RT_DISPATCH_G(ctx->p.groups, launch_transport64, ctx, (const double *)UD, dt,
+                      (double *)U_out, part, counts, mask);
     } else {
         return rt_fail(ctx, RT_EINVAL, "FP32C transport not available");
     }

@@ -74,7 +74,7 @@ def load_library() -> ctypes.CDLL:
     L.rt_set_sources.argtypes = [_VP, i32, _VP, ctypes.c_double]
     L.rt_inject.argtypes = [_VP] * 4
     L.rt_gradient.argtypes = [_VP] * 3
-    L.rt_transport.argtypes = [_VP] * 9
+    L.rt_transport.argtypes = [_VP] * 8
     L.rt_photon_total.argtypes = [_VP] * 3
     L.rt_adjoint.argtypes = [_VP] * 9
     L.rt_sync.argtypes = [_VP]
@@ -149,7 +149,17 @@ class RT:
         return torch.full((self.n, self.G, 4), fill, dtype=self.sdtype, device=self.device)
 
     def grad_buffer(self) -> torch.Tensor:
-        return torch.empty((self.n, self.G, 4, 3), dtype=self.sdtype, device=self.device)
+        """Gradient record UD [n, G, 16]: per group the state (4) then its
+        gradients (4 x 3)."""
+        return torch.empty((self.n, self.G, 16), dtype=self.sdtype, device=self.device)
+
+    def gradients_of(self, UD: torch.Tensor) -> torch.Tensor:
+        """The gradient part of UD as [n, G, 4, 3]."""
+        return UD[:, :, 4:].reshape(self.n, self.G, 4, 3)
+
+    def states_of(self, UD: torch.Tensor) -> torch.Tensor:
+        """The state part of UD as [n, G, 4]."""
+        return UD[:, :, :4]
 
     # -- the C entry points ---------------------------------------------------
     def rt_build_cells(self, x: torch.Tensor, h_in: Optional[torch.Tensor] = None):
@@ -183,21 +193,21 @@ class RT:
         self._bind_stream()
         self._check(self.L.rt_inject(self.ctx, _ptr(U), _ptr(L), _ptr(dt)))
 
-    def rt_gradient(self, U: torch.Tensor, dU: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def rt_gradient(self, U: torch.Tensor, UD: Optional[torch.Tensor] = None) -> torch.Tensor:
         _need(U, "U", self.sdtype, (self.n, self.G, 4))
-        dU = self.grad_buffer() if dU is None else dU
-        _need(dU, "dU", self.sdtype, (self.n, self.G, 4, 3))
+        UD = self.grad_buffer() if UD is None else UD
+        _need(UD, "UD", self.sdtype, (self.n, self.G, 16))
         self._bind_stream()
-        self._check(self.L.rt_gradient(self.ctx, _ptr(U), _ptr(dU)))
-        return dU
+        self._check(self.L.rt_gradient(self.ctx, _ptr(U), _ptr(UD)))
+        return UD
 
-    def rt_transport(self, U, dU, dt=None, U_out=None, photon_total=None, counts=None,
+    def rt_transport(self, UD, dt=None, U_out=None, photon_total=None, counts=None,
                      ledger=None, guard_mask=None) -> torch.Tensor:
-        _need(U, "U", self.sdtype, (self.n, self.G, 4))
-        _need(dU, "dU", self.sdtype, (self.n, self.G, 4, 3))
+        _need(UD, "UD", self.sdtype, (self.n, self.G, 16))
         dt = self.dt if dt is None else dt
         _need(dt, "dt", torch.float64, (1,))
-        U_out = torch.empty_like(U) if U_out is None else U_out
+        if U_out is None:
+            U_out = torch.empty((self.n, self.G, 4), dtype=self.sdtype, device=self.device)
         _need(U_out, "U_out", self.sdtype, (self.n, self.G, 4))
         if photon_total is not None:
             _need(photon_total, "photon_total", torch.float64, (self.G,))
@@ -208,7 +218,7 @@ class RT:
         if guard_mask is not None:
             _need(guard_mask, "guard_mask", torch.uint8, (self.n, self.G))
         self._bind_stream()
-        self._check(self.L.rt_transport(self.ctx, _ptr(U), _ptr(dU), _ptr(dt), _ptr(U_out),
+        self._check(self.L.rt_transport(self.ctx, _ptr(UD), _ptr(dt), _ptr(U_out),
                                         _ptr(photon_total), _ptr(counts), _ptr(ledger),
                                         _ptr(guard_mask)))
         return U_out
@@ -220,7 +230,7 @@ class RT:
         self._check(self.L.rt_photon_total(self.ctx, _ptr(U), _ptr(Q)))
         return Q
 
-    def rt_adjoint(self, U_pre, L, lam_next, lam=None, dU=None, guard_mask=None, dL_dL=None,
+    def rt_adjoint(self, U_pre, L, lam_next, lam=None, UD=None, guard_mask=None, dL_dL=None,
                    dt=None) -> torch.Tensor:
         _need(U_pre, "U_pre", self.sdtype, (self.n, self.G, 4))
         _need(lam_next, "lam_next", self.sdtype, (self.n, self.G, 4))
@@ -228,8 +238,8 @@ class RT:
         _need(lam, "lam", self.sdtype, (self.n, self.G, 4))
         if self.S:
             _need(L, "L", torch.float64, (self.S, self.G))
-        if dU is not None:
-            _need(dU, "dU", self.sdtype, (self.n, self.G, 4, 3))
+        if UD is not None:
+            _need(UD, "UD", self.sdtype, (self.n, self.G, 16))
         if guard_mask is not None:
             _need(guard_mask, "guard_mask", torch.uint8, (self.n, self.G))
         if dL_dL is not None:
@@ -237,7 +247,7 @@ class RT:
         dt = self.dt if dt is None else dt
         self._bind_stream()
         self._check(self.L.rt_adjoint(self.ctx, _ptr(U_pre), _ptr(L) if self.S else None,
-                                      _ptr(dt), _ptr(dU), _ptr(guard_mask), _ptr(lam_next),
+                                      _ptr(dt), _ptr(UD), _ptr(guard_mask), _ptr(lam_next),
                                       _ptr(lam), _ptr(dL_dL)))
         return lam
 
@@ -287,11 +297,11 @@ class RT:
         return ms.value, cnt.value
 
     # -- composition of the entry points (no arithmetic) ----------------------
-    def step(self, U: torch.Tensor, L: Optional[torch.Tensor] = None, dU=None, U_out=None,
+    def step(self, U: torch.Tensor, L: Optional[torch.Tensor] = None, UD=None, U_out=None,
              **kw) -> torch.Tensor:
         """One RT step in the operator-splitting order injection -> gradient ->
         transport (Part III "One RT time step").  U is injected in place."""
         if self.S:
             self.rt_inject(U, L)
-        dU = self.rt_gradient(U, dU)
-        return self.rt_transport(U, dU, U_out=U_out, **kw)
+        UD = self.rt_gradient(U, UD)
+        return self.rt_transport(UD, U_out=U_out, **kw)

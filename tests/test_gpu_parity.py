@@ -81,8 +81,9 @@ def test_c1_neighbour_sets_exact(c1):
 
 def test_c1_gradient(c1):
     w, geo, rt, p = c1
-    dU = rt.rt_gradient(dev(w.U0[p]))
-    got = unsort(dU.cpu().numpy(), p)
+    UD = rt.rt_gradient(dev(w.U0[p]))
+    assert np.array_equal(rt.states_of(UD).cpu().numpy(), w.U0[p])
+    got = unsort(rt.gradients_of(UD).cpu().numpy(), p)
     ref = oracle.gradient(geo, w.U0)
     scale = np.abs(ref).max(axis=(-1, -2), keepdims=True)
     assert (np.abs(got - ref) / scale).max() < 1e-12
