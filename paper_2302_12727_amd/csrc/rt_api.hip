@@ -149,6 +149,8 @@ rt_status rt_inject(rt_ctx *ctx, void *U, const double *L, const double *dt) {
     return rt_inject_impl(ctx, U, L, dt);
 }
 
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
 static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
     const char *x = (const char *)a, *y = (const char *)b;
     return x < y + nb && y < x + na;
@@ -161,6 +163,7 @@ rt_status rt_gradient(rt_ctx *ctx, const void *U, void *UD) {
     size_t es = ctx->p.precision == RT_FP64 ? 8 : 4;
     size_t nu = es * 4 * ctx->p.groups * ctx->p.n;
     if (overlap(U, nu, UD, 4 * nu)) return rt_fail(ctx, RT_EINVAL, "U and UD overlap");
+    if (!aligned16(UD)) return rt_fail(ctx, RT_EINVAL, "UD must be 16-byte aligned");
     return rt_gradient_impl(ctx, U, UD);
 }
 
@@ -173,6 +176,7 @@ rt_status rt_transport(rt_ctx *ctx, const void *UD, const double *dt, void *U_ou
     size_t es = ctx->p.precision == RT_FP64 ? 8 : 4;
     size_t nu = es * 4 * ctx->p.groups * ctx->p.n;
     if (overlap(UD, 4 * nu, U_out, nu)) return rt_fail(ctx, RT_EINVAL, "UD and U_out overlap");
+    if (!aligned16(UD)) return rt_fail(ctx, RT_EINVAL, "UD must be 16-byte aligned");
     return rt_transport_impl(ctx, UD, dt, U_out, photon_total, counts, ledger, guard_mask);
 }
 

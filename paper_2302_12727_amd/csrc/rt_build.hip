@@ -361,16 +361,20 @@ __global__ void k_geometry(int64_t n, const double *__restrict__ xs, const doubl
         rec[12] = rec[13] = rec[14] = rec[15] = 0.0;
         if (geo32) {
             float *r32 = geo32 + (int64_t)F_REC * i;
+            double *xd = reinterpret_cast<double *>(r32);
+            xd[0] = px;
+            xd[1] = py;
+            xd[2] = pz;
             r32[F_IH] = (float)iH;
             r32[F_H] = (float)hi_;
-            r32[F_V] = (float)V;
             r32[F_B + 0] = (float)(f * c00);
             r32[F_B + 1] = (float)(f * c01);
             r32[F_B + 2] = (float)(f * c02);
             r32[F_B + 3] = (float)(f * c11);
             r32[F_B + 4] = (float)(f * c12);
             r32[F_B + 5] = (float)(f * c22);
-            r32[F_B + 6] = 0.0f;
+            r32[F_V] = (float)V;
+            r32[15] = 0.0f;
         }
         V_out[i] = V;
         dx = cbrt(V * (3.0 / (4.0 * kPi)));

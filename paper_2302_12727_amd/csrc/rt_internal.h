@@ -33,9 +33,10 @@ enum : int32_t { ST_NOCONV = 1, ST_SINGULAR = 2, ST_BIGH = 4, ST_NONFINITE = 8 }
 //                       and the gradient matrix is S^{-1} = Bv / V.
 enum { R_X = 0, R_IH = 3, R_H = 4, R_V = 5, R_B = 6 };
 
-// Same record in FP32 for the compensated-FP32 path (positions stay FP64 in
-// the FP64 record: separations are formed in FP64 and rounded once).
-enum { F_IH = 0, F_H = 1, F_V = 2, F_B = 3, F_REC = 10 };  // padded to 10 floats
+// Record of the compensated-FP32 path, 64 bytes (16 floats): positions stay
+// FP64 (floats 0..5 hold x, y, z as doubles; separations are formed in FP64
+// and rounded once), then 1/H, h, Bv (6) and V in FP32.
+enum { F_IH = 6, F_H = 7, F_B = 8, F_V = 14, F_REC = 16 };
 
 struct TimerRec {
     std::string name;
@@ -260,6 +261,10 @@ rt_status rt_gradient_impl(rt_ctx *ctx, const void *U, void *UD);
 rt_status rt_transport_impl(rt_ctx *ctx, const void *UD, const double *dt, void *U_out,
                             double *Q, int64_t *counts, double *ledger, uint8_t *mask);
 rt_status rt_total_impl(rt_ctx *ctx, const void *U, double *Q);
+// compensated-FP32 launches (rt_step32.hip)
+void rt_gradient32(rt_ctx *ctx, const float *U, float *UD);
+void rt_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *Uout,
+                    double *partials, int64_t *counts, uint8_t *mask);
 rt_status rt_ensure_partials(rt_ctx *ctx);
 
 // adjoint (rt_adjoint.hip)

@@ -132,13 +132,15 @@ __device__ __forceinline__ void m1_flux64(double E, double Fx, double Fy, double
                                           double out[4]) {
     // Guarded states have E >= 0 and F = 0 when E = 0; with 1/E replaced by 0
     // there every term below vanishes, so no branch is needed.
+    // g = F/E keeps every product in range: f^2 = |g|^2/c^2, (F.A) F/E = (g.A) F.
     const double FA = Fx * Ax + Fy * Ay + Fz * Az;
     const double iE = E > 0.0 ? rcp64(E) : 0.0;
-    const double f2 = (Fx * Fx + Fy * Fy + Fz * Fz) * (iE * iE) * ic2;
+    const double gx = Fx * iE, gy = Fy * iE, gz = Fz * iE;
+    const double f2 = (gx * gx + gy * gy + gz * gz) * ic2;
     const double s = sqrt64(fmax(4.0 - 3.0 * f2, 0.0));
     const double id = rcp64(2.0 + s);
     const double a = c2 * E * (1.0 / 3.0 - f2 * id);
-    const double b = 3.0 * id * FA * iE;
+    const double b = 3.0 * id * (gx * Ax + gy * Ay + gz * Az);
     out[0] = FA;
     out[1] = a * Ax + b * Fx;
     out[2] = a * Ay + b * Fy;
@@ -503,7 +505,7 @@ rt_status rt_gradient_impl(rt_ctx *ctx, const void *U, void *UD) {
     if (ctx->p.precision == RT_FP64) {
         RT_DISPATCH_G(ctx->p.groups, launch_gradient64, ctx, (const double *)U, (double *)UD);
     } else {
-        return rt_fail(ctx, RT_EINVAL, "FP32C gradient not available");
+        rt_gradient32(ctx, (const float *)U, (float *)UD);
     }
     rt_timer_end(ctx, "gradient");
     RT_HIP(hipGetLastError());
@@ -519,7 +521,7 @@ rt_status rt_transport_impl(rt_ctx *ctx, const void *UD, const double *dt, void 
         RT_DISPATCH_G(ctx->p.groups, launch_transport64, ctx, (const double *)UD, dt,
                       (double *)U_out, part, counts, mask);
     } else {
-        return rt_fail(ctx, RT_EINVAL, "FP32C transport not available");
+        rt_transport32(ctx, (const float *)UD, dt, (float *)U_out, part, counts, mask);
     }
     rt_timer_end(ctx, "transport");
     RT_HIP(hipGetLastError());

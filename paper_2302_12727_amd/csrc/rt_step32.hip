@@ -1,0 +1,412 @@
+// Compensated-FP32 variants of the gradient and transport kernels.
+//
+// State, gradient records and all pair arithmetic are FP32; each particle sums
+// its pair fluxes with Kahan compensation (sum, comp) in FP32, and the final
+// update combines sum and compensation once in FP64 before rounding the new
+// state to FP32.  FP64 stays in the geometry (separations from FP64 positions,
+// the FP64 inversion of S_i in the build) and in the photon budget.
+#include "rt_internal.h"
+
+using namespace gearrt;
+
+namespace {
+
+constexpr int kStage32 = 17;   // floats per staged 16-float row (bank padding)
+
+// Hardware FP32 reciprocal and square root (about one ulp).  FP32 denormals are
+// flushed on this path: the square root of a product that underflowed is 0
+// (never 0 * inf), which the callers treat as "no surface" / "no flux".
+__device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt32(float x) { return __builtin_amdgcn_sqrtf(fmaxf(x, 0.0f)); }
+
+__device__ __forceinline__ void wave_lds_sync32() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Kahan-compensated running sum.
+struct Kahan {
+    float s, c;
+    __device__ __forceinline__ void add(float x) {
+        const float y = x - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+};
+
+// ---------------------------------------------------------------------------
+// Gradient (eq:gradient) in FP32, S_i^{-1} sum_j (q_j - q_i) w(r_ij/H_i) s_ij.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_gradient32(
+    int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ xs,
+    const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
+    const int32_t *__restrict__ n_gath, const float *__restrict__ U, float *__restrict__ UD,
+    double box) {
+    const int64_t blk = xcd_block(nb);
+    if (blk >= nb) return;
+    const int64_t i = blk * kBlock + threadIdx.x;
+    if (i >= n) return;
+    constexpr int NQ = 4 * G;
+    const double ibox = 1.0 / box;
+    const float *rec = geo32 + (int64_t)F_REC * i;
+    const double px = xs[3 * i], py = xs[3 * i + 1], pz = xs[3 * i + 2];
+    const float iH = rec[F_IH], iV = 1.0f / rec[F_V];
+    float Ui[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) Ui[q] = U[i * NQ + q];
+    float acc[NQ][3];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0f;
+    const int64_t base = wave_base[i >> 6] + (i & 63);
+    const int32_t ng = n_gath[i];
+    for (int32_t k = 0; k < ng; ++k) {
+        const int64_t j = nbr[base + 64 * (int64_t)k];
+        const float sx = (float)min_image(xs[3 * j] - px, box, ibox);
+        const float sy = (float)min_image(xs[3 * j + 1] - py, box, ibox);
+        const float sz = (float)min_image(xs[3 * j + 2] - pz, box, ibox);
+        const float w = kern_wf(sqrt32(sx * sx + sy * sy + sz * sz) * iH);
+        const float wx = w * sx, wy = w * sy, wz = w * sz;
+        const float *Uj = U + j * NQ;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const float d = Uj[q] - Ui[q];
+            acc[q][0] += d * wx;
+            acc[q][1] += d * wy;
+            acc[q][2] += d * wz;
+        }
+    }
+    const float b00 = rec[F_B] * iV, b01 = rec[F_B + 1] * iV, b02 = rec[F_B + 2] * iV;
+    const float b11 = rec[F_B + 3] * iV, b12 = rec[F_B + 4] * iV, b22 = rec[F_B + 5] * iV;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        float *o = UD + (i * G + g) * 16;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int q = 4 * g + m;
+            o[m] = Ui[q];
+            o[4 + 3 * m + 0] = b00 * acc[q][0] + b01 * acc[q][1] + b02 * acc[q][2];
+            o[4 + 3 * m + 1] = b01 * acc[q][0] + b11 * acc[q][1] + b12 * acc[q][2];
+            o[4 + 3 * m + 2] = b02 * acc[q][0] + b12 * acc[q][1] + b22 * acc[q][2];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Transport in FP32 with compensated accumulation.  Same scheme as the FP64
+// kernel (guards, M1 closure rewritten without n = F/|F|, GLF, minmod).
+__device__ __forceinline__ int guard32(float &E, float &Fx, float &Fy, float &Fz, float c) {
+    int fired = 0;
+    if (E < 0.0f) {
+        E = 0.0f;
+        fired = 1;
+    }
+    if (E == 0.0f) {
+        Fx = Fy = Fz = 0.0f;
+        return fired;
+    }
+    const float F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+    const float lim = c * E;
+    if (F2 > lim * lim) {
+        // |F| below 1e-19 (|F|^2 not a normal float) is scaled to the limit 0
+        const float Fn = sqrt32(F2);
+        const float sc = Fn > 0.0f ? lim * rcp32(Fn) : 0.0f;
+        Fx *= sc;
+        Fy *= sc;
+        Fz *= sc;
+        fired |= 2;
+    }
+    return fired;
+}
+
+// With g = F/E (|g| <= c after the guard) the closure needs no product that
+// can leave the FP32 range: f^2 = |g|^2/c^2 and (F.A) F / E = (g.A) F.  Energy
+// densities below 1e-30 carry no anisotropic term (their flux is below
+// 1e-30 |A| c^2 / 3).
+__device__ __forceinline__ void m1_flux32(float E, float Fx, float Fy, float Fz, float Ax,
+                                          float Ay, float Az, float c2, float ic2, float out[4]) {
+    const float FA = Fx * Ax + Fy * Ay + Fz * Az;
+    const float iE = E > 1e-30f ? rcp32(E) : 0.0f;
+    const float gx = Fx * iE, gy = Fy * iE, gz = Fz * iE;
+    const float f2 = (gx * gx + gy * gy + gz * gz) * ic2;
+    const float s = sqrt32(fmaxf(4.0f - 3.0f * f2, 0.0f));
+    const float id = rcp32(2.0f + s);
+    const float a = c2 * E * (1.0f / 3.0f - f2 * id);
+    const float b = 3.0f * id * (gx * Ax + gy * Ay + gz * Az);
+    out[0] = FA;
+    out[1] = a * Ax + b * Fx;
+    out[2] = a * Ay + b * Fy;
+    out[3] = a * Az + b * Fz;
+}
+
+__device__ __forceinline__ float minmod32(float a, float b) {
+    const float m = (fabsf(a) <= fabsf(b)) ? a : b;
+    return (a * b > 0.0f) ? m : 0.0f;
+}
+
+// Copy one 16-float (64-byte) row per lane's neighbour into the wave's stage
+// buffer: 4 loads, 4 lanes per row, 16 rows per load.
+__device__ __forceinline__ void stage_rows32(const float *__restrict__ src,
+                                             const int64_t (&row)[4], float *sb, int lane) {
+    const int piece = lane & 3, slot = lane >> 2;
+    float4 v[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        v[m] = *reinterpret_cast<const float4 *>(src + 16 * row[m] + 4 * piece);
+    wave_lds_sync32();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        float *d = sb + (16 * m + slot) * kStage32 + 4 * piece;
+        d[0] = v[m].x;
+        d[1] = v[m].y;
+        d[2] = v[m].z;
+        d[3] = v[m].w;
+    }
+    wave_lds_sync32();
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_transport32(
+    int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ geo,
+    const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
+    const int32_t *__restrict__ n_nbr, const float *__restrict__ UD,
+    const double *__restrict__ dtp, double c, double box, float *__restrict__ Uout,
+    double *__restrict__ partials, unsigned long long *__restrict__ counts,
+    uint8_t *__restrict__ mask) {
+    constexpr int NQ = 4 * G;
+    __shared__ float stage[kBlock / 64][64 * kStage32];
+    __shared__ double smem[(kBlock / 64) * 2 * G];
+    __shared__ unsigned long long scnt[4];
+    const int64_t blk = xcd_block(nb);
+    if (blk >= nb) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t i = blk * kBlock + threadIdx.x;
+    const bool active = i < n;
+    const int64_t ic = active ? i : n - 1;
+    const int64_t w = i >> 6;
+    const bool wave_live = (w << 6) < n;
+    const double ibox = 1.0 / box;
+    const float cf = (float)c, c2 = (float)(c * c), ic2 = (float)(1.0 / (c * c)), hc = 0.5f * cf;
+    if (threadIdx.x < 4) scnt[threadIdx.x] = 0;
+    float *sb = stage[wv];
+
+    const float *rk = geo32 + (int64_t)F_REC * ic;
+    const double *xk = reinterpret_cast<const double *>(rk);
+    const double pkx = xk[0], pky = xk[1], pkz = xk[2];
+    const float iHk = rk[F_IH], hk = rk[F_H];
+    float Bk[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) Bk[a] = rk[F_B + a];
+    float Ui[NQ], Di[NQ * 3];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const float *r = UD + (ic * G + g) * 16;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            Ui[4 * g + m] = r[m];
+            Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
+            Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
+            Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
+        }
+    }
+    Kahan acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q].s = acc[q].c = 0.0f;
+    int cE = 0, cF = 0;
+
+    if (wave_live) {
+        const int64_t base = wave_base[w] + lane;
+        const int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
+        const int32_t nn = active ? n_nbr[i] : 0;
+        for (int32_t k = 0; k < kmax; ++k) {
+            const bool valid = k < nn;
+            const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
+            int64_t row[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) row[m] = __shfl(j, 16 * m + (lane >> 2), 64);
+            stage_rows32(geo32, row, sb, lane);
+            const float *rl = sb + lane * kStage32;
+            // separation in FP64 from FP64 positions, rounded once
+            double xl[3];
+            {
+                // the staged row holds the three doubles as six floats
+                union { float f[2]; double d; } u;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    u.f[0] = rl[2 * a];
+                    u.f[1] = rl[2 * a + 1];
+                    xl[a] = u.d;
+                }
+            }
+            const float sx = (float)min_image(xl[0] - pkx, box, ibox);
+            const float sy = (float)min_image(xl[1] - pky, box, ibox);
+            const float sz = (float)min_image(xl[2] - pkz, box, ibox);
+            const float r = sqrt32(sx * sx + sy * sy + sz * sz);
+            const float wk = kern_wf(r * iHk);
+            const float wl = kern_wf(r * rl[F_IH]);
+            const float m00 = wk * Bk[0] + wl * rl[F_B + 0];
+            const float m01 = wk * Bk[1] + wl * rl[F_B + 1];
+            const float m02 = wk * Bk[2] + wl * rl[F_B + 2];
+            const float m11 = wk * Bk[3] + wl * rl[F_B + 3];
+            const float m12 = wk * Bk[4] + wl * rl[F_B + 4];
+            const float m22 = wk * Bk[5] + wl * rl[F_B + 5];
+            const float Ax = m00 * sx + m01 * sy + m02 * sz;
+            const float Ay = m01 * sx + m11 * sy + m12 * sz;
+            const float Az = m02 * sx + m12 * sy + m22 * sz;
+            const float An = sqrt32(Ax * Ax + Ay * Ay + Az * Az);
+            const float hl = rl[F_H];
+            const float ih = rcp32(hk + hl);
+            const float fk = hk * ih, fl = hl * ih;
+            const bool use = valid && An > 0.0f;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                int64_t rowg[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) rowg[m] = row[m] * G + g;
+                stage_rows32(UD, rowg, sb, lane);
+                const float *Rl = sb + lane * kStage32;
+                float qL[4], qR[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int q = 4 * g + m;
+                    const float dk = Di[3 * q] * sx + Di[3 * q + 1] * sy + Di[3 * q + 2] * sz;
+                    const float dl = Rl[4 + 3 * m] * sx + Rl[5 + 3 * m] * sy + Rl[6 + 3 * m] * sz;
+                    const float mm = minmod32(dk, dl);
+                    qL[m] = Ui[q] + fk * mm;
+                    qR[m] = Rl[m] - fl * mm;
+                }
+                const int f1 = guard32(qL[0], qL[1], qL[2], qL[3], cf);
+                const int f2 = guard32(qR[0], qR[1], qR[2], qR[3], cf);
+                float FL[4], FR[4];
+                m1_flux32(qL[0], qL[1], qL[2], qL[3], Ax, Ay, Az, c2, ic2, FL);
+                m1_flux32(qR[0], qR[1], qR[2], qR[3], Ax, Ay, Az, c2, ic2, FR);
+                const float dis = hc * An;
+                if (use) {
+                    cE += (f1 & 1) + (f2 & 1);
+                    cF += (f1 >> 1) + (f2 >> 1);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        acc[4 * g + m].add(0.5f * (FL[m] + FR[m]) - dis * (qR[m] - qL[m]));
+                }
+            }
+        }
+    }
+    double red[2 * G];
+    int gE = 0, gF = 0;
+    if (active) {
+        const double V = geo[(int64_t)kRec * i + R_V];
+        const double dtV = dtp[0] / V;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            double q0 = (double)Ui[4 * g + 0] - dtV * acc[4 * g + 0].value();
+            double q1 = (double)Ui[4 * g + 1] - dtV * acc[4 * g + 1].value();
+            double q2 = (double)Ui[4 * g + 2] - dtV * acc[4 * g + 2].value();
+            double q3 = (double)Ui[4 * g + 3] - dtV * acc[4 * g + 3].value();
+            const double Epre = q0;
+            int f = 0;
+            if (q0 < 0.0) {
+                q0 = q1 = q2 = q3 = 0.0;
+                f = 1;
+            } else if (q0 == 0.0) {
+                q1 = q2 = q3 = 0.0;
+            } else {
+                const double F2 = q1 * q1 + q2 * q2 + q3 * q3, lim = c * q0;
+                if (F2 > lim * lim) {
+                    const double sc = lim * rsq64(F2);
+                    q1 *= sc;
+                    q2 *= sc;
+                    q3 *= sc;
+                    f = 2;
+                }
+            }
+            gE += f & 1;
+            gF += f >> 1;
+            if (mask) mask[i * G + g] = (uint8_t)f;
+            float *o = Uout + i * NQ + 4 * g;
+            o[0] = (float)q0;
+            o[1] = (float)q1;
+            o[2] = (float)q2;
+            o[3] = (float)q3;
+            red[g] = V * (double)o[0];
+            red[G + g] = (f & 1) ? -Epre * V : 0.0;
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < 2 * G; ++p) red[p] = 0.0;
+    }
+    if (partials) {
+        const int ln = threadIdx.x & 63;
+#pragma unroll
+        for (int p = 0; p < 2 * G; ++p) {
+            double x = wave_sum(red[p]);
+            if (ln == 0) smem[wv * 2 * G + p] = x;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * G) {
+            double s = 0.0;
+            for (int u = 0; u < kBlock / 64; ++u) s += smem[u * 2 * G + threadIdx.x];
+            partials[blk * 2 * G + threadIdx.x] = s;
+        }
+    }
+    if (counts) {
+        int64_t v0 = wave_sum_i64(cE), v1 = wave_sum_i64(cF), v2 = wave_sum_i64(gE),
+                v3 = wave_sum_i64(gF);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&scnt[0], (unsigned long long)v0);
+            atomicAdd(&scnt[1], (unsigned long long)v1);
+            atomicAdd(&scnt[2], (unsigned long long)v2);
+            atomicAdd(&scnt[3], (unsigned long long)v3);
+        }
+        __syncthreads();
+        if (threadIdx.x < 4 && scnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], scnt[threadIdx.x]);
+    }
+}
+
+template <int G>
+void launch_gradient32(rt_ctx *ctx, const float *U, float *UD) {
+    const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
+    k_gradient32<G><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
+        n, nb, ctx->geo32, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box);
+}
+
+template <int G>
+void launch_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *Uout,
+                        double *partials, int64_t *counts, uint8_t *mask) {
+    const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
+    k_transport32<G><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
+        n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
+        ctx->p.box, Uout, partials, (unsigned long long *)counts, mask);
+}
+
+}  // namespace
+
+void rt_gradient32(rt_ctx *ctx, const float *U, float *UD) {
+    switch (ctx->p.groups) {
+        case 1: launch_gradient32<1>(ctx, U, UD); break;
+        case 2: launch_gradient32<2>(ctx, U, UD); break;
+        case 3: launch_gradient32<3>(ctx, U, UD); break;
+        case 4: launch_gradient32<4>(ctx, U, UD); break;
+        case 5: launch_gradient32<5>(ctx, U, UD); break;
+        case 6: launch_gradient32<6>(ctx, U, UD); break;
+        case 7: launch_gradient32<7>(ctx, U, UD); break;
+        case 8: launch_gradient32<8>(ctx, U, UD); break;
+        default: break;
+    }
+}
+
+void rt_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *Uout,
+                    double *partials, int64_t *counts, uint8_t *mask) {
+    switch (ctx->p.groups) {
+        case 1: launch_transport32<1>(ctx, UD, dt, Uout, partials, counts, mask); break;
+        case 2: launch_transport32<2>(ctx, UD, dt, Uout, partials, counts, mask); break;
+        case 3: launch_transport32<3>(ctx, UD, dt, Uout, partials, counts, mask); break;
+        case 4: launch_transport32<4>(ctx, UD, dt, Uout, partials, counts, mask); break;
+        case 5: launch_transport32<5>(ctx, UD, dt, Uout, partials, counts, mask); break;
+        case 6: launch_transport32<6>(ctx, UD, dt, Uout, partials, counts, mask); break;
+        case 7: launch_transport32<7>(ctx, UD, dt, Uout, partials, counts, mask); break;
+        case 8: launch_transport32<8>(ctx, UD, dt, Uout, partials, counts, mask); break;
+        default: break;
+    }
+}

@@ -1,0 +1,90 @@
+"""Compensated-FP32 path against the FP64 oracle.
+
+Tolerance: 1e-5 relative on (E, F) per particle and group, measured against
+the local scale max(E, |F|/c) over the particle and its neighbours (an FP32
+pair flux carries about 1e-7 of the larger state of its pair, so a faint state
+next to a bright one inherits error relative to the bright one); the error
+relative to each state's own magnitude is reported alongside.  Photon totals
+against the oracle's FP64 totals.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from tests.gpu_util import dev, err_summary, local_err, log, state_err, unsort
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2302_12727_amd import RT  # noqa: E402
+
+TOL32 = 1e-5
+
+
+def run32(w, steps, geo_h=None):
+    rt = RT(w.n, w.groups, precision="fp32c")
+    perm, h, V, dt = rt.rt_build_cells(dev(w.x), None if geo_h is None else dev(geo_h))
+    if w.xs.shape[0]:
+        rt.rt_set_sources(dev(w.xs))
+    p = perm.cpu().numpy()
+    U = dev(w.U0[p]).float()
+    L = dev(w.L) if w.xs.shape[0] else None
+    Q = torch.zeros(w.groups, dtype=torch.float64, device="cuda")
+    for _ in range(steps):
+        U = rt.step(U, L, photon_total=Q)
+    rt.rt_sync()
+    return unsort(U.double().cpu().numpy(), p), Q.cpu().numpy(), rt, p
+
+
+def test_fp32c_gradient_close():
+    w = workloads.config(0)
+    geo = oracle.build_geometry(w.x)
+    rt = RT(w.n, w.groups, precision="fp32c")
+    perm, *_ = rt.rt_build_cells(dev(w.x))
+    p = perm.cpu().numpy()
+    UD = rt.rt_gradient(dev(w.U0[p]).float())
+    got = unsort(rt.gradients_of(UD).double().cpu().numpy(), p)
+    ref = oracle.gradient(geo, w.U0)
+    scale = np.abs(ref).max(axis=(-1, -2), keepdims=True)
+    err = (np.abs(got - ref) / scale).max()
+    log(f"fp32c gradient max rel err {err:.3e}")
+    assert err < 1e-5
+
+
+def test_fp32c_lattice16_ten_steps():
+    w = workloads.config(0)
+    geo = oracle.build_geometry(w.x)
+    ref, _ = oracle.run(geo, None, w.U0, None, w.steps)
+    got, Q, _, _ = run32(w, w.steps)
+    err = state_err(got, ref)
+    Qo = oracle.photon_total(geo, ref)
+    log("fp32c lattice16 10 steps: " + err_summary(got, ref, geo.sptr, geo.sidx) +
+        f"; photon total rel {np.abs(Q / Qo - 1).max():.3e}")
+    assert err < TOL32
+    assert np.allclose(Q, Qo, rtol=1e-6)
+
+
+def test_fp32c_plummer_with_source():
+    w = workloads.config(2, scale=(1 << 15) / (1 << 22))
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs)
+    ref, _ = oracle.run(geo, srcs, w.U0, w.L, 5)
+    got, Q, _, _ = run32(w, 5)
+    log("fp32c plummer 5 steps: " + err_summary(got, ref, geo.sptr, geo.sidx))
+    assert local_err(got, ref, geo.sptr, geo.sidx) < TOL32
+    assert np.allclose(Q, oracle.photon_total(geo, ref), rtol=1e-6)
+
+
+def test_fp32c_mid_lattice_sources():
+    w = workloads.config(1, scale=(20 ** 3) / (128 ** 3))
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs)
+    ref, _ = oracle.run(geo, srcs, w.U0, w.L, 5)
+    got, Q, _, _ = run32(w, 5)
+    log("fp32c lattice20 S=16 5 steps: " + err_summary(got, ref, geo.sptr, geo.sidx))
+    assert local_err(got, ref, geo.sptr, geo.sidx) < TOL32
+    assert np.allclose(Q, oracle.photon_total(geo, ref), rtol=1e-6)
