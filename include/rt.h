@@ -134,11 +134,11 @@ rt_status rt_gradient(rt_ctx *ctx, const void *U, void *UD);
  *             faces), updated states with E clipped / F rescaled.
  *   ledger    [G] accumulated or NULL: sum_k V_k (energy density added by
  *             clipping E < 0 of the updated state).
- *   guard_mask [n][G] uint8 out or NULL: per updated state, bit0 = E clipped,
- *             bit1 = F rescaled (consumed by rt_adjoint). */
+ *   U_unguarded [n][G][4] out or NULL: the updated state before the
+ *             post-update guard (consumed by rt_adjoint). */
 rt_status rt_transport(rt_ctx *ctx, const void *UD, const double *dt, void *U_out,
                        double *photon_total, int64_t *counts, double *ledger,
-                       uint8_t *guard_mask);
+                       void *U_unguarded);
 
 /* Q_g = sum_k V_k E_kg of U, [G] out (FP64, compensated, deterministic). */
 rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q);
@@ -152,15 +152,17 @@ rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q);
  *   L        [S][G] luminosities used by the step (NULL if no sources).
  *   dt       [1] device.
  *   UD       gradient record of the post-injection state (rt_gradient after
- *            rt_inject), or NULL (recomputed into library scratch).
- *   guard_mask from the forward rt_transport of this step, or NULL
+ *            rt_inject), or NULL (recomputed into library scratch from U_pre).
+ *   U_unguarded  the forward's unguarded updated state of this step, or NULL
  *            (recomputed).
  *   lam_next [n][G][4] dLoss/dU_next.  lam [n][G][4] out: dLoss/dU_pre; may
  *            alias lam_next.
- *   dL_dL    [S][G] double, accumulated (+=) dLoss/dL, or NULL. */
+ *   dL_dL    [S][G] double, accumulated (+=) dLoss/dL, or NULL.
+ * U_pre is read only when UD is NULL.  Scratch (a few state-sized buffers) is
+ * allocated by the library on first use. */
 rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
-                     const void *UD, const uint8_t *guard_mask, const void *lam_next,
-                     void *lam, double *dL_dL);
+                     const void *UD, const void *U_unguarded, const void *lam_next, void *lam,
+                     double *dL_dL);
 
 /* Wait for the stream; return the first device-side error raised since the
  * last rt_sync (RT_ENOCONV, RT_ESINGULAR) or RT_OK, and clear it. */

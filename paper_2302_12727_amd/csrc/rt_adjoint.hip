@@ -1,7 +1,356 @@
-// Adjoint of one RT step (placeholder until the VJP kernels land).
-#include "rt_internal.h"
+// Adjoint (vector-Jacobian product) of one RT step.  The thesis has no
+// adjoint; this is the exact derivative of the step the forward kernels
+// compute, with the subgradient of the active branch at minmod switches and
+// guards.
+//
+// Forward step (per particle k, group g):
+//   U'   = U + dt sum_s coef_sg L_s e_E                  injection
+//   D    = S^{-1} sum_j (U'_j - U'_k) w_kj s_kj           gradient
+//   U''  = U'_k - dt/V_k sum_l P_kl(U'_k, D_k; U'_l, D_l) transport, P_kl = |A| Phi_kl
+//   U''' = guard(U'')
+// Reverse, given lam''' = dLoss/dU''':
+//   A: lam''   = guard^T lam'''                             (needs U'')
+//   B: mu_kl   = dt lam''_l / V_l - dt lam''_k / V_k
+//      lam'_k  = lam''_k + sum_l (dP_kl/dU'_k)^T mu_kl,  lamD_k = sum_l (dP_kl/dD_k)^T mu_kl
+//      (each lane differentiates its own-perspective pair flux with respect to
+//      its own inputs only: the pair's other half is taken by the neighbour's
+//      lane, with P_lk = -P_kl and mu_lk = -mu_kl)
+//   C: rho_i   = S_i^{-1} lamD_i;
+//      lam_p   = lam'_p - (sum_j w_pj s_pj) . rho_p + sum_i w(r_ip/H_i) s_ip . rho_i
+//   D: dLoss/dL_s += dt sum_g coef_sg lam_E,g
+#include "rt_pair.h"
 
-rt_status rt_adjoint_impl(rt_ctx *ctx, const void *, const double *, const double *,
-                          const void *, const uint8_t *, const void *, void *, double *) {
-    return rt_fail(ctx, RT_ESTATE, "adjoint not available");
+using namespace gearrt;
+
+namespace {
+
+inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_adj_guard64(int64_t n, const double *__restrict__ Uung,
+                                                        const double *__restrict__ lam_next,
+                                                        double *__restrict__ lam2, double c) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * G) return;
+    double q[4], l[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        q[m] = Uung[4 * t + m];
+        l[m] = lam_next[4 * t + m];
+    }
+    guard64_vjp(q, l, c);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) lam2[4 * t + m] = l[m];
+}
+
+// Pass B.  R[k][g] = (lam'_k (4) | rho_k (4 x 3)), the layout of a gradient record.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_adj_pair64(
+    int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
+    const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
+    const double *__restrict__ UD, const double *__restrict__ lam2,
+    const double *__restrict__ dtp, double c, double box, double *__restrict__ R) {
+    constexpr int NQ = 4 * G;
+    __shared__ double stage[kBlock / 64][64 * kStage];
+    const int64_t blk = xcd_block(nb);
+    if (blk >= nb) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t i = blk * kBlock + threadIdx.x;
+    const bool active = i < n;
+    const int64_t ic = active ? i : n - 1;
+    const int64_t w = i >> 6;
+    const bool wave_live = (w << 6) < n;
+    const double ibox = 1.0 / box, c2 = c * c, ic2 = 1.0 / c2, hc = 0.5 * c;
+    const double dt = dtp[0];
+    double *sb = stage[wv];
+
+    const double *rk = geo + (int64_t)kRec * ic;
+    const double dtVk = dt / rk[R_V];
+    double Ui[NQ], Di[NQ * 3], Li[NQ];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const double *r = UD + (ic * G + g) * 16;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            Ui[4 * g + m] = r[m];
+            Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
+            Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
+            Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
+            Li[4 * g + m] = lam2[(ic * G + g) * 4 + m];
+        }
+    }
+    double aU[NQ], aD[NQ * 3];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) aU[q] = aD[3 * q] = aD[3 * q + 1] = aD[3 * q + 2] = 0.0;
+
+    if (wave_live) {
+        const int64_t base = wave_base[w] + lane;
+        const int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
+        const int32_t nn = active ? n_nbr[i] : 0;
+        for (int32_t k = 0; k < kmax; ++k) {
+            const bool valid = k < nn;
+            const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
+            int64_t row[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) row[m] = __shfl(j, 8 * m + (lane >> 3), 64);
+            stage_lines(geo, row, sb, lane);
+            double rl[12];
+#pragma unroll
+            for (int q = 0; q < 12; ++q) rl[q] = sb[lane * kStage + q];
+            PairGeo pg;
+            pair_geometry64(rk, rl, box, ibox, pg);
+            const bool use = valid && pg.An > 0.0;
+            const double dtVl = dt / rl[R_V];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                int64_t rowg[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g;
+                stage_lines(UD, rowg, sb, lane);
+                double Rl[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) Rl[q] = sb[lane * kStage + q];
+                stage_rows4(lam2 + 4 * g, 4 * G, j, sb, lane);
+                double Ll[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) Ll[m] = sb[lane * kStage + m];
+                // forward recompute of this pair and group
+                double qLp[4], qRp[4], qL[4], qR[4];
+                bool own_slope[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int q = 4 * g + m;
+                    const double dk = Di[3 * q] * pg.sx + Di[3 * q + 1] * pg.sy + Di[3 * q + 2] * pg.sz;
+                    const double dl = Rl[4 + 3 * m] * pg.sx + Rl[5 + 3 * m] * pg.sy + Rl[6 + 3 * m] * pg.sz;
+                    const double mm = minmod(dk, dl);
+                    own_slope[m] = (dk * dl > 0.0) && (fabs(dk) <= fabs(dl));
+                    qLp[m] = qL[m] = Ui[q] + pg.fk * mm;
+                    qRp[m] = qR[m] = Rl[m] - pg.fl * mm;
+                }
+                guard64(qL[0], qL[1], qL[2], qL[3], c);
+                guard64(qR[0], qR[1], qR[2], qR[3], c);
+                // cotangent of P_kl and its pull-back to the face states
+                double nu[4], tL[4], tR[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) nu[m] = 0.5 * (dtVl * Ll[m] - dtVk * Li[4 * g + m]);
+                m1_flux64_vjp(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c2, ic2, nu, tL);
+                m1_flux64_vjp(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c2, ic2, nu, tR);
+                const double dis = c * pg.An;   // 2 * (c/2) |A| times nu = mu/2
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    tL[m] += dis * nu[m];
+                    tR[m] -= dis * nu[m];
+                }
+                guard64_vjp(qLp, tL, c);
+                guard64_vjp(qRp, tR, c);
+                if (use) {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int q = 4 * g + m;
+                        aU[q] += tL[m];
+                        const double lm = own_slope[m] ? pg.fk * tL[m] - pg.fl * tR[m] : 0.0;
+                        aD[3 * q] += lm * pg.sx;
+                        aD[3 * q + 1] += lm * pg.sy;
+                        aD[3 * q + 2] += lm * pg.sz;
+                    }
+                }
+            }
+        }
+    }
+    (void)hc;
+    if (!active) return;
+    const double iV = 1.0 / rk[R_V];
+    const double b00 = rk[R_B] * iV, b01 = rk[R_B + 1] * iV, b02 = rk[R_B + 2] * iV;
+    const double b11 = rk[R_B + 3] * iV, b12 = rk[R_B + 4] * iV, b22 = rk[R_B + 5] * iV;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        double *o = R + (i * G + g) * 16;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int q = 4 * g + m;
+            o[m] = Li[q] + aU[q];
+            o[4 + 3 * m + 0] = b00 * aD[3 * q] + b01 * aD[3 * q + 1] + b02 * aD[3 * q + 2];
+            o[4 + 3 * m + 1] = b01 * aD[3 * q] + b11 * aD[3 * q + 1] + b12 * aD[3 * q + 2];
+            o[4 + 3 * m + 2] = b02 * aD[3 * q] + b12 * aD[3 * q + 1] + b22 * aD[3 * q + 2];
+        }
+    }
+}
+
+// Pass C: transpose of the least-squares gradient, gathered over the
+// symmetric neighbour lists (i is a gather neighbour of p iff r < H_i).
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_adj_grad64(
+    int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
+    const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
+    const double *__restrict__ R, double *__restrict__ lam, double box) {
+    constexpr int NQ = 4 * G;
+    __shared__ double stage[kBlock / 64][64 * kStage];
+    const int64_t blk = xcd_block(nb);
+    if (blk >= nb) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t i = blk * kBlock + threadIdx.x;
+    const bool active = i < n;
+    const int64_t ic = active ? i : n - 1;
+    const int64_t w = i >> 6;
+    const bool wave_live = (w << 6) < n;
+    const double ibox = 1.0 / box;
+    double *sb = stage[wv];
+    const double *rp = geo + (int64_t)kRec * ic;
+    const double px = rp[0], py = rp[1], pz = rp[2], iHp = rp[R_IH];
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    double sgx = 0.0, sgy = 0.0, sgz = 0.0;
+    if (wave_live) {
+        const int64_t base = wave_base[w] + lane;
+        const int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
+        const int32_t nn = active ? n_nbr[i] : 0;
+        for (int32_t k = 0; k < kmax; ++k) {
+            const bool valid = k < nn;
+            const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
+            int64_t row[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) row[m] = __shfl(j, 8 * m + (lane >> 3), 64);
+            stage_lines(geo, row, sb, lane);
+            const double *rl = sb + lane * kStage;
+            const double sx = min_image(rl[0] - px, box, ibox);
+            const double sy = min_image(rl[1] - py, box, ibox);
+            const double sz = min_image(rl[2] - pz, box, ibox);
+            const double r = sqrt64(sx * sx + sy * sy + sz * sz);
+            const double wpi = valid ? kern_w(r * iHp) : 0.0;
+            const double wip = valid ? kern_w(r * rl[R_IH]) : 0.0;
+            sgx += wpi * sx;
+            sgy += wpi * sy;
+            sgz += wpi * sz;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                int64_t rowg[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g;
+                stage_lines(R, rowg, sb, lane);
+                const double *Rl = sb + lane * kStage;
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    acc[4 * g + m] -= wip * (Rl[4 + 3 * m] * sx + Rl[5 + 3 * m] * sy + Rl[6 + 3 * m] * sz);
+            }
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const double *Rp = R + (i * G + g) * 16;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            lam[(i * G + g) * 4 + m] =
+                Rp[m] - (sgx * Rp[4 + 3 * m] + sgy * Rp[5 + 3 * m] + sgz * Rp[6 + 3 * m]) +
+                acc[4 * g + m];
+    }
+}
+
+// Pass D: dLoss/dL_s += dt sum_{g in s} coef_sg lam_E,g, one block per source.
+__global__ __launch_bounds__(kBlock) void k_adj_inject(int32_t S, int G,
+                                                       const int32_t *__restrict__ ptr,
+                                                       const int32_t *__restrict__ gas,
+                                                       const double *__restrict__ coef,
+                                                       const double *__restrict__ lam,
+                                                       const double *__restrict__ dtp,
+                                                       double *__restrict__ dLdL) {
+    __shared__ double sm[kBlock];
+    const int32_t s = blockIdx.x;
+    for (int grp = 0; grp < G; ++grp) {
+        double v = 0.0;
+        for (int32_t e = ptr[s] + threadIdx.x; e < ptr[s + 1]; e += kBlock)
+            v += coef[e] * lam[((int64_t)gas[e] * G + grp) * 4];
+        sm[threadIdx.x] = v;
+        __syncthreads();
+        for (int h = kBlock / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) dLdL[s * G + grp] += dtp[0] * sm[0];
+        __syncthreads();
+    }
+}
+
+template <int G>
+void launch_adjoint64(rt_ctx *ctx, const double *UD, const double *Uung, const double *lam_next,
+                      double *lam2, double *R, double *lam, const double *dt) {
+    const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
+    hipStream_t st = ctx->stream;
+    k_adj_guard64<G><<<nblk(n * G), kBlock, 0, st>>>(n, Uung, lam_next, lam2, ctx->p.c_red);
+    k_adj_pair64<G><<<(unsigned)xcd_grid(nb), kBlock, 0, st>>>(
+        n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt, ctx->p.c_red,
+        ctx->p.box, R);
+    k_adj_grad64<G><<<(unsigned)xcd_grid(nb), kBlock, 0, st>>>(
+        n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, R, lam, ctx->p.box);
+}
+
+}  // namespace
+
+// Scratch of the adjoint: [lam''  | R | recomputed U' | UD | U'' | U_out]
+static rt_status adj_scratch(rt_ctx *ctx, size_t es, char **base) {
+    const size_t nu = (size_t)ctx->p.n * 4 * ctx->p.groups * es;
+    const size_t need = nu * (1 + 4 + 1 + 4 + 1 + 1) + 6 * 256;
+    if (!ctx->adj_buf || ctx->adj_bytes < need) {
+        rt_free(ctx->adj_buf);
+        ctx->adj_buf = nullptr;
+        rt_status rs = rt_alloc(ctx, &ctx->adj_buf, need);
+        if (rs != RT_OK) return rs;
+        ctx->adj_bytes = need;
+    }
+    *base = (char *)ctx->adj_buf;
+    return RT_OK;
+}
+
+rt_status rt_adjoint_impl(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
+                          const void *UD, const void *U_ung, const void *lam_next, void *lam,
+                          double *dL_dL) {
+    if (ctx->p.precision != RT_FP64) return rt_fail(ctx, RT_EINVAL, "FP32C adjoint not available");
+    const size_t es = 8;
+    const size_t nu = (size_t)ctx->p.n * 4 * ctx->p.groups * es;
+    char *b;
+    rt_status rs = adj_scratch(ctx, es, &b);
+    if (rs != RT_OK) return rs;
+    auto carve = [&](size_t bytes) {
+        char *p = b;
+        b += (bytes + 255) & ~size_t(255);
+        return (void *)p;
+    };
+    double *lam2 = (double *)carve(nu);
+    double *Rb = (double *)carve(4 * nu);
+    double *Ut = (double *)carve(nu);
+    double *UDs = (double *)carve(4 * nu);
+    double *Uu = (double *)carve(nu);
+    double *Uo = (double *)carve(nu);
+    rt_timer_begin(ctx, "adjoint");
+    if (!UD) {
+        if (!U_pre) return rt_fail(ctx, RT_EINVAL, "U_pre is required when UD is NULL");
+        RT_HIP(hipMemcpyAsync(Ut, U_pre, nu, hipMemcpyDeviceToDevice, ctx->stream));
+        if ((rs = rt_inject_impl(ctx, Ut, L, dt)) != RT_OK) return rs;
+        if ((rs = rt_gradient_impl(ctx, Ut, UDs)) != RT_OK) return rs;
+        UD = UDs;
+    }
+    if (!U_ung) {
+        if ((rs = rt_transport_impl(ctx, UD, dt, Uo, nullptr, nullptr, nullptr, Uu)) != RT_OK)
+            return rs;
+        U_ung = Uu;
+    }
+    switch (ctx->p.groups) {
+        case 1: launch_adjoint64<1>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
+        case 2: launch_adjoint64<2>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
+        case 3: launch_adjoint64<3>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
+        case 4: launch_adjoint64<4>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
+        case 5: launch_adjoint64<5>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
+        case 6: launch_adjoint64<6>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
+        case 7: launch_adjoint64<7>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
+        case 8: launch_adjoint64<8>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
+        default: break;
+    }
+    if (ctx->S > 0 && dL_dL)
+        k_adj_inject<<<ctx->S, kBlock, 0, ctx->stream>>>(ctx->S, ctx->p.groups, ctx->src_ptr,
+                                                         ctx->src_gas, ctx->src_coef,
+                                                         (const double *)lam, dt, dL_dL);
+    rt_timer_end(ctx, "adjoint");
+    RT_HIP(hipGetLastError());
+    return RT_OK;
 }

@@ -45,17 +45,22 @@ void rt_timer_begin(rt_ctx *ctx, const char *) {
             ctx->ev_pool.push_back(e);
         }
     }
-    ctx->ev_open = ctx->ev_pool[ctx->ev_used];
-    (void)hipEventRecord(ctx->ev_open, ctx->stream);
+    hipEvent_t a = ctx->ev_pool[ctx->ev_used++];
+    (void)hipEventRecord(a, ctx->stream);
+    ctx->ev_open.push_back(a);
 }
 
 void rt_timer_end(rt_ctx *ctx, const char *name) {
-    if (!ctx->timing || !ctx->ev_open) return;
-    hipEvent_t b = ctx->ev_pool[ctx->ev_used + 1];
+    if (!ctx->timing || ctx->ev_open.empty()) return;
+    if (ctx->ev_used + 1 > ctx->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        ctx->ev_pool.push_back(e);
+    }
+    hipEvent_t b = ctx->ev_pool[ctx->ev_used++];
     (void)hipEventRecord(b, ctx->stream);
-    ctx->trecs.push_back({name, ctx->ev_open, b});
-    ctx->ev_used += 2;
-    ctx->ev_open = nullptr;
+    ctx->trecs.push_back({name, ctx->ev_open.back(), b});
+    ctx->ev_open.pop_back();
 }
 
 static bool finite_pos(double v) { return v > 0.0 && v < 1e300; }
@@ -169,15 +174,17 @@ rt_status rt_gradient(rt_ctx *ctx, const void *U, void *UD) {
 
 rt_status rt_transport(rt_ctx *ctx, const void *UD, const double *dt, void *U_out,
                        double *photon_total, int64_t *counts, double *ledger,
-                       uint8_t *guard_mask) {
+                       void *U_unguarded) {
     if (!ctx) return RT_EINVAL;
     if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
     if (!UD || !dt || !U_out) return rt_fail(ctx, RT_EINVAL, "UD, dt and U_out are required");
     size_t es = ctx->p.precision == RT_FP64 ? 8 : 4;
     size_t nu = es * 4 * ctx->p.groups * ctx->p.n;
     if (overlap(UD, 4 * nu, U_out, nu)) return rt_fail(ctx, RT_EINVAL, "UD and U_out overlap");
+    if (U_unguarded && overlap(U_unguarded, nu, U_out, nu))
+        return rt_fail(ctx, RT_EINVAL, "U_unguarded and U_out overlap");
     if (!aligned16(UD)) return rt_fail(ctx, RT_EINVAL, "UD must be 16-byte aligned");
-    return rt_transport_impl(ctx, UD, dt, U_out, photon_total, counts, ledger, guard_mask);
+    return rt_transport_impl(ctx, UD, dt, U_out, photon_total, counts, ledger, U_unguarded);
 }
 
 rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q) {
@@ -188,14 +195,15 @@ rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q) {
 }
 
 rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
-                     const void *UD, const uint8_t *guard_mask, const void *lam_next,
-                     void *lam, double *dL_dL) {
+                     const void *UD, const void *U_unguarded, const void *lam_next, void *lam,
+                     double *dL_dL) {
     if (!ctx) return RT_EINVAL;
     if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
-    if (!U_pre || !dt || !lam_next || !lam)
-        return rt_fail(ctx, RT_EINVAL, "U_pre, dt, lam_next and lam are required");
+    if (!dt || !lam_next || !lam) return rt_fail(ctx, RT_EINVAL, "dt, lam_next and lam are required");
+    if (!UD && !U_pre) return rt_fail(ctx, RT_EINVAL, "U_pre is required when UD is NULL");
     if (ctx->S > 0 && !L) return rt_fail(ctx, RT_EINVAL, "L is required when sources are set");
-    return rt_adjoint_impl(ctx, U_pre, L, dt, UD, guard_mask, lam_next, lam, dL_dL);
+    if (UD && !aligned16(UD)) return rt_fail(ctx, RT_EINVAL, "UD must be 16-byte aligned");
+    return rt_adjoint_impl(ctx, U_pre, L, dt, UD, U_unguarded, lam_next, lam, dL_dL);
 }
 
 rt_status rt_sync(rt_ctx *ctx) {
@@ -293,6 +301,7 @@ rt_status rt_timing(rt_ctx *ctx, int32_t on) {
     if (on) {
         RT_HIP(hipStreamSynchronize(ctx->stream));
         ctx->trecs.clear();
+        ctx->ev_open.clear();
         ctx->ev_used = 0;
     }
     ctx->timing = on ? 1 : 0;

@@ -107,7 +107,7 @@ struct rt_ctx {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<gearrt::TimerRec> trecs;
-    hipEvent_t ev_open = nullptr;
+    std::vector<hipEvent_t> ev_open;   // stack of open timers (nested launches)
 };
 
 namespace gearrt {
@@ -259,15 +259,15 @@ rt_status rt_sources_impl(rt_ctx *ctx, int32_t n_src, const double *xs, double e
 rt_status rt_inject_impl(rt_ctx *ctx, void *U, const double *L, const double *dt);
 rt_status rt_gradient_impl(rt_ctx *ctx, const void *U, void *UD);
 rt_status rt_transport_impl(rt_ctx *ctx, const void *UD, const double *dt, void *U_out,
-                            double *Q, int64_t *counts, double *ledger, uint8_t *mask);
+                            double *Q, int64_t *counts, double *ledger, void *Uung);
 rt_status rt_total_impl(rt_ctx *ctx, const void *U, double *Q);
 // compensated-FP32 launches (rt_step32.hip)
 void rt_gradient32(rt_ctx *ctx, const float *U, float *UD);
 void rt_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *Uout,
-                    double *partials, int64_t *counts, uint8_t *mask);
+                    double *partials, int64_t *counts, float *Uung);
 rt_status rt_ensure_partials(rt_ctx *ctx);
 
 // adjoint (rt_adjoint.hip)
 rt_status rt_adjoint_impl(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
-                          const void *UD, const uint8_t *mask, const void *lam_next,
-                          void *lam, double *dL_dL);
+                          const void *UD, const void *U_ung, const void *lam_next, void *lam,
+                          double *dL_dL);

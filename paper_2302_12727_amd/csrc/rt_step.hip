@@ -6,7 +6,7 @@
 // particle i (Morton order), reads slot j of its list at
 // wave_base[i/64] + 64 j + i%64 (coalesced), and accumulates in registers, so
 // results are deterministic and no atomics touch floating-point state.
-#include "rt_internal.h"
+#include "rt_pair.h"
 
 using namespace gearrt;
 
@@ -93,157 +93,13 @@ __global__ __launch_bounds__(kBlock) void k_gradient64(
     }
 }
 
-// ---------------------------------------------------------------------------
-// Transport (eq:rt-meshless, eq:transport-update-explicit).
-//
-// Face guard (reading of "negative energy densities are set to zero"): E < 0
-// becomes 0 with F = 0, and a flux beyond the free-streaming limit is scaled
-// to |F| = cE.  Returns bit0 / bit1 when the respective guard fired.
-__device__ __forceinline__ int guard64(double &E, double &Fx, double &Fy, double &Fz, double c) {
-    int fired = 0;
-    if (E < 0.0) {
-        E = 0.0;
-        fired = 1;
-    }
-    if (E == 0.0) {
-        Fx = Fy = Fz = 0.0;
-        return fired;
-    }
-    const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
-    const double lim = c * E;
-    if (F2 > lim * lim) {
-        const double sc = lim * rsq64(F2);
-        Fx *= sc;
-        Fy *= sc;
-        Fz *= sc;
-        fired |= 2;
-    }
-    return fired;
-}
-
-// Flux of a state through the (unnormalised) surface A, using the M1 closure
-// (eq:eddington-group) rewritten without the 0/0 of n = F/|F|:
-//   with f^2 = |F|^2/(cE)^2, s = sqrt(4 - 3 f^2):
-//   (3 chi - 1)/(2 f^2) = 3/(2 + s),  (1 - chi)/2 = 1/3 - f^2/(2 + s),
-//   c^2 P A = c^2 E (1-chi)/2 A + 3/(2+s) (F.A) F / E.
-// out[0] = F.A, out[1..3] = c^2 P A.  A state with E = 0 has no flux.
-__device__ __forceinline__ void m1_flux64(double E, double Fx, double Fy, double Fz, double Ax,
-                                          double Ay, double Az, double c, double c2, double ic2,
-                                          double out[4]) {
-    // Guarded states have E >= 0 and F = 0 when E = 0; with 1/E replaced by 0
-    // there every term below vanishes, so no branch is needed.
-    // g = F/E keeps every product in range: f^2 = |g|^2/c^2, (F.A) F/E = (g.A) F.
-    const double FA = Fx * Ax + Fy * Ay + Fz * Az;
-    const double iE = E > 0.0 ? rcp64(E) : 0.0;
-    const double gx = Fx * iE, gy = Fy * iE, gz = Fz * iE;
-    const double f2 = (gx * gx + gy * gy + gz * gz) * ic2;
-    const double s = sqrt64(fmax(4.0 - 3.0 * f2, 0.0));
-    const double id = rcp64(2.0 + s);
-    const double a = c2 * E * (1.0 / 3.0 - f2 * id);
-    const double b = 3.0 * id * (gx * Ax + gy * Ay + gz * Az);
-    out[0] = FA;
-    out[1] = a * Ax + b * Fx;
-    out[2] = a * Ay + b * Fy;
-    out[3] = a * Az + b * Fz;
-}
-
-__device__ __forceinline__ double minmod(double a, double b) {
-    const double m = (fabs(a) <= fabs(b)) ? a : b;
-    return (a * b > 0.0) ? m : 0.0;
-}
-
-// Per-pair flux accumulation shared by the FP64 transport and its adjoint
-// recompute: returns |A| and A in out-params, or |A| = 0 if the pair has no
-// surface.
-struct PairGeo {
-    double sx, sy, sz, Ax, Ay, Az, An, fk, fl;
-};
-
-__device__ __forceinline__ void pair_geometry64(const double *__restrict__ rk,
-                                                const double *__restrict__ rl, double box,
-                                                double ibox, PairGeo &pg) {
-    pg.sx = min_image(rl[0] - rk[0], box, ibox);
-    pg.sy = min_image(rl[1] - rk[1], box, ibox);
-    pg.sz = min_image(rl[2] - rk[2], box, ibox);
-    const double r = sqrt64(pg.sx * pg.sx + pg.sy * pg.sy + pg.sz * pg.sz);
-    const double wk = kern_w(r * rk[R_IH]);
-    const double wl = kern_w(r * rl[R_IH]);
-    // A_kl = (w_k Bv_k + w_l Bv_l) s   (eq:HopkinsAij, see the record layout)
-    const double m00 = wk * rk[R_B + 0] + wl * rl[R_B + 0];
-    const double m01 = wk * rk[R_B + 1] + wl * rl[R_B + 1];
-    const double m02 = wk * rk[R_B + 2] + wl * rl[R_B + 2];
-    const double m11 = wk * rk[R_B + 3] + wl * rl[R_B + 3];
-    const double m12 = wk * rk[R_B + 4] + wl * rl[R_B + 4];
-    const double m22 = wk * rk[R_B + 5] + wl * rl[R_B + 5];
-    pg.Ax = m00 * pg.sx + m01 * pg.sy + m02 * pg.sz;
-    pg.Ay = m01 * pg.sx + m11 * pg.sy + m12 * pg.sz;
-    pg.Az = m02 * pg.sx + m12 * pg.sy + m22 * pg.sz;
-    pg.An = sqrt64(pg.Ax * pg.Ax + pg.Ay * pg.Ay + pg.Az * pg.Az);
-    // interface x_kl = x_k + h_k/(h_k+h_l) s  (eq:rt-riemann-problem)
-    const double ih = rcp64(rk[R_H] + rl[R_H]);
-    pg.fk = rk[R_H] * ih;
-    pg.fl = rl[R_H] * ih;
-}
-
-template <int NP>
-__device__ __forceinline__ void block_reduce_store(double (&v)[NP], double *__restrict__ out,
-                                                   double *smem) {
-    // smem: [kBlock/64][NP]
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        double x = wave_sum(v[p]);
-        if (lane == 0) smem[wv * NP + p] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x < NP) {
-        double s = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) s += smem[w * NP + threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-}
-
-// LDS transpose of neighbour records.  A lane-per-particle gather makes every
-// wave-wide load touch 64 different cache lines (one address-unit cycle each);
-// instead the wave fetches the 64 records it needs in this iteration with
-// coalesced loads (8 lanes per 128-byte line, 8 lines per instruction), writes
-// them to its own LDS buffer, and each lane then reads its neighbour's record
-// from LDS.  Records are padded to 17 doubles in LDS against bank conflicts.
-constexpr int kStage = 17;
-
-// Order LDS traffic of one wavefront: everything before is complete and
-// visible to the other lanes of the wave before anything after is issued.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-}
-
-// Copy one 16-double line per lane's neighbour (line base pointers src + 16 *
-// row[m]) into the wave's stage buffer: 8 loads, each lane moving 16 bytes.
-__device__ __forceinline__ void stage_lines(const double *__restrict__ src, const int64_t (&row)[8],
-                                            double *sb, int lane) {
-    const int piece = lane & 7, slot = lane >> 3;
-    double2 v[8];
-#pragma unroll
-    for (int m = 0; m < 8; ++m)
-        v[m] = *reinterpret_cast<const double2 *>(src + 16 * row[m] + 2 * piece);
-    wave_lds_sync();
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        double *d = sb + (8 * m + slot) * kStage + 2 * piece;
-        d[0] = v[m].x;
-        d[1] = v[m].y;
-    }
-    wave_lds_sync();
-}
-
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_transport64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
     const double *__restrict__ UD, const double *__restrict__ dtp, double c, double box,
     double *__restrict__ Uout, double *__restrict__ partials,
-    unsigned long long *__restrict__ counts, uint8_t *__restrict__ mask) {
+    unsigned long long *__restrict__ counts, double *__restrict__ Uung) {
     constexpr int NQ = 4 * G;
     __shared__ double stage[kBlock / 64][64 * kStage];
     __shared__ double smem[(kBlock / 64) * 2 * G];
@@ -343,10 +199,16 @@ __global__ __launch_bounds__(kBlock) void k_transport64(
             double q2 = Ui[4 * g + 2] - dtV * acc[4 * g + 2];
             double q3 = Ui[4 * g + 3] - dtV * acc[4 * g + 3];
             const double Epre = q0;
+            if (Uung) {
+                double *u = Uung + i * NQ + 4 * g;
+                u[0] = q0;
+                u[1] = q1;
+                u[2] = q2;
+                u[3] = q3;
+            }
             const int f = guard64(q0, q1, q2, q3, c);
             gE += f & 1;
             gF += f >> 1;
-            if (mask) mask[i * G + g] = (uint8_t)f;
             double *o = Uout + i * NQ + 4 * g;
             o[0] = q0;
             o[1] = q1;
@@ -444,11 +306,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int64_t nb, int G,
 
 template <int G>
 void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double *Uout,
-                        double *partials, int64_t *counts, uint8_t *mask) {
+                        double *partials, int64_t *counts, double *Uung) {
     const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
     k_transport64<G><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
         n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
-        ctx->p.box, Uout, partials, (unsigned long long *)counts, mask);
+        ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung);
 }
 
 template <int G>
@@ -513,15 +375,15 @@ rt_status rt_gradient_impl(rt_ctx *ctx, const void *U, void *UD) {
 }
 
 rt_status rt_transport_impl(rt_ctx *ctx, const void *UD, const double *dt, void *U_out,
-                            double *Q, int64_t *counts, double *ledger, uint8_t *mask) {
+                            double *Q, int64_t *counts, double *ledger, void *Uung) {
     const int64_t nb = (ctx->p.n + kBlock - 1) / kBlock;
     double *part = (Q || ledger) ? ctx->partials : nullptr;
     rt_timer_begin(ctx, "transport");
     if (ctx->p.precision == RT_FP64) {
         RT_DISPATCH_G(ctx->p.groups, launch_transport64, ctx, (const double *)UD, dt,
-                      (double *)U_out, part, counts, mask);
+                      (double *)U_out, part, counts, (double *)Uung);
     } else {
-        rt_transport32(ctx, (const float *)UD, dt, (float *)U_out, part, counts, mask);
+        rt_transport32(ctx, (const float *)UD, dt, (float *)U_out, part, counts, (float *)Uung);
     }
     rt_timer_end(ctx, "transport");
     RT_HIP(hipGetLastError());

@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_transport32(
     const int32_t *__restrict__ n_nbr, const float *__restrict__ UD,
     const double *__restrict__ dtp, double c, double box, float *__restrict__ Uout,
     double *__restrict__ partials, unsigned long long *__restrict__ counts,
-    uint8_t *__restrict__ mask) {
+    float *__restrict__ Uung) {
     constexpr int NQ = 4 * G;
     __shared__ float stage[kBlock / 64][64 * kStage32];
     __shared__ double smem[(kBlock / 64) * 2 * G];
@@ -304,6 +304,13 @@ __global__ __launch_bounds__(kBlock) void k_transport32(
             double q2 = (double)Ui[4 * g + 2] - dtV * acc[4 * g + 2].value();
             double q3 = (double)Ui[4 * g + 3] - dtV * acc[4 * g + 3].value();
             const double Epre = q0;
+            if (Uung) {
+                float *u = Uung + i * NQ + 4 * g;
+                u[0] = (float)q0;
+                u[1] = (float)q1;
+                u[2] = (float)q2;
+                u[3] = (float)q3;
+            }
             int f = 0;
             if (q0 < 0.0) {
                 q0 = q1 = q2 = q3 = 0.0;
@@ -322,7 +329,6 @@ __global__ __launch_bounds__(kBlock) void k_transport32(
             }
             gE += f & 1;
             gF += f >> 1;
-            if (mask) mask[i * G + g] = (uint8_t)f;
             float *o = Uout + i * NQ + 4 * g;
             o[0] = (float)q0;
             o[1] = (float)q1;
@@ -373,11 +379,11 @@ void launch_gradient32(rt_ctx *ctx, const float *U, float *UD) {
 
 template <int G>
 void launch_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *Uout,
-                        double *partials, int64_t *counts, uint8_t *mask) {
+                        double *partials, int64_t *counts, float *Uung) {
     const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
     k_transport32<G><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
         n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
-        ctx->p.box, Uout, partials, (unsigned long long *)counts, mask);
+        ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung);
 }
 
 }  // namespace
@@ -397,16 +403,16 @@ void rt_gradient32(rt_ctx *ctx, const float *U, float *UD) {
 }
 
 void rt_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *Uout,
-                    double *partials, int64_t *counts, uint8_t *mask) {
+                    double *partials, int64_t *counts, float *Uung) {
     switch (ctx->p.groups) {
-        case 1: launch_transport32<1>(ctx, UD, dt, Uout, partials, counts, mask); break;
-        case 2: launch_transport32<2>(ctx, UD, dt, Uout, partials, counts, mask); break;
-        case 3: launch_transport32<3>(ctx, UD, dt, Uout, partials, counts, mask); break;
-        case 4: launch_transport32<4>(ctx, UD, dt, Uout, partials, counts, mask); break;
-        case 5: launch_transport32<5>(ctx, UD, dt, Uout, partials, counts, mask); break;
-        case 6: launch_transport32<6>(ctx, UD, dt, Uout, partials, counts, mask); break;
-        case 7: launch_transport32<7>(ctx, UD, dt, Uout, partials, counts, mask); break;
-        case 8: launch_transport32<8>(ctx, UD, dt, Uout, partials, counts, mask); break;
+        case 1: launch_transport32<1>(ctx, UD, dt, Uout, partials, counts, Uung); break;
+        case 2: launch_transport32<2>(ctx, UD, dt, Uout, partials, counts, Uung); break;
+        case 3: launch_transport32<3>(ctx, UD, dt, Uout, partials, counts, Uung); break;
+        case 4: launch_transport32<4>(ctx, UD, dt, Uout, partials, counts, Uung); break;
+        case 5: launch_transport32<5>(ctx, UD, dt, Uout, partials, counts, Uung); break;
+        case 6: launch_transport32<6>(ctx, UD, dt, Uout, partials, counts, Uung); break;
+        case 7: launch_transport32<7>(ctx, UD, dt, Uout, partials, counts, Uung); break;
+        case 8: launch_transport32<8>(ctx, UD, dt, Uout, partials, counts, Uung); break;
         default: break;
     }
 }

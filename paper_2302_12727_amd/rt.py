@@ -202,7 +202,7 @@ class RT:
         return UD
 
     def rt_transport(self, UD, dt=None, U_out=None, photon_total=None, counts=None,
-                     ledger=None, guard_mask=None) -> torch.Tensor:
+                     ledger=None, U_unguarded=None) -> torch.Tensor:
         _need(UD, "UD", self.sdtype, (self.n, self.G, 16))
         dt = self.dt if dt is None else dt
         _need(dt, "dt", torch.float64, (1,))
@@ -215,12 +215,12 @@ class RT:
             _need(counts, "counts", torch.int64, (4,))
         if ledger is not None:
             _need(ledger, "ledger", torch.float64, (self.G,))
-        if guard_mask is not None:
-            _need(guard_mask, "guard_mask", torch.uint8, (self.n, self.G))
+        if U_unguarded is not None:
+            _need(U_unguarded, "U_unguarded", self.sdtype, (self.n, self.G, 4))
         self._bind_stream()
         self._check(self.L.rt_transport(self.ctx, _ptr(UD), _ptr(dt), _ptr(U_out),
                                         _ptr(photon_total), _ptr(counts), _ptr(ledger),
-                                        _ptr(guard_mask)))
+                                        _ptr(U_unguarded)))
         return U_out
 
     def rt_photon_total(self, U: torch.Tensor) -> torch.Tensor:
@@ -230,9 +230,10 @@ class RT:
         self._check(self.L.rt_photon_total(self.ctx, _ptr(U), _ptr(Q)))
         return Q
 
-    def rt_adjoint(self, U_pre, L, lam_next, lam=None, UD=None, guard_mask=None, dL_dL=None,
+    def rt_adjoint(self, U_pre, L, lam_next, lam=None, UD=None, U_unguarded=None, dL_dL=None,
                    dt=None) -> torch.Tensor:
-        _need(U_pre, "U_pre", self.sdtype, (self.n, self.G, 4))
+        if U_pre is not None:
+            _need(U_pre, "U_pre", self.sdtype, (self.n, self.G, 4))
         _need(lam_next, "lam_next", self.sdtype, (self.n, self.G, 4))
         lam = torch.empty_like(lam_next) if lam is None else lam
         _need(lam, "lam", self.sdtype, (self.n, self.G, 4))
@@ -240,14 +241,14 @@ class RT:
             _need(L, "L", torch.float64, (self.S, self.G))
         if UD is not None:
             _need(UD, "UD", self.sdtype, (self.n, self.G, 16))
-        if guard_mask is not None:
-            _need(guard_mask, "guard_mask", torch.uint8, (self.n, self.G))
+        if U_unguarded is not None:
+            _need(U_unguarded, "U_unguarded", self.sdtype, (self.n, self.G, 4))
         if dL_dL is not None:
             _need(dL_dL, "dL_dL", torch.float64, (self.S, self.G))
         dt = self.dt if dt is None else dt
         self._bind_stream()
         self._check(self.L.rt_adjoint(self.ctx, _ptr(U_pre), _ptr(L) if self.S else None,
-                                      _ptr(dt), _ptr(UD), _ptr(guard_mask), _ptr(lam_next),
+                                      _ptr(dt), _ptr(UD), _ptr(U_unguarded), _ptr(lam_next),
                                       _ptr(lam), _ptr(dL_dL)))
         return lam
 
