@@ -83,36 +83,14 @@ def cpu_baseline(cfg_index: int, min_seconds: float):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])
-    ap.add_argument("--config", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also launch a plain device copy of 1 GiB (HBM counter calibration)")
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus above 1 is not supported "
-              "(multi-GPU sharding is a design note, not an implementation)", file=sys.stderr)
-        sys.exit(2)
-
+def run_forward(w, precision, steps, warmup, dev, timing=True):
+    """Build the static geometry, then time `steps` whole RT steps."""
     import numpy as np
     import torch
-
-    import workloads
     from paper_2302_12727_amd import RT
 
-    dev = torch.device("cuda:0")
-    w = workloads.config(args.config)
     G = w.groups
-    log(f"workload {w.name}: n={w.n} G={G} S={w.xs.shape[0]} precision={args.precision}")
-
-    rt = RT(w.n, G, precision=args.precision, cfl=w.cfl, c_red=w.c_red, device=dev)
+    rt = RT(w.n, G, precision=precision, cfl=w.cfl, c_red=w.c_red, device=dev)
     x = torch.from_numpy(w.x).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -122,12 +100,10 @@ def main():
     rt.rt_sync()
     build_ms = (time.perf_counter() - t0) * 1e3
     st = rt.rt_get_stats()
-    pairs = st["n_pairs"]
-    log(f"build {build_ms:.1f} ms; pairs {pairs}; mean neighbours {st['n_entries'] / w.n:.2f}; "
-        f"max {st['max_neighbours']}; device MiB {st['device_bytes'] / 2**20:.0f}")
-
+    log(f"[{precision}] build {build_ms:.1f} ms; pairs {st['n_pairs']}; mean neighbours "
+        f"{st['n_entries'] / w.n:.2f}; max {st['max_neighbours']}")
     p = perm.cpu().numpy()
-    sd = torch.float64 if args.precision == "fp64" else torch.float32
+    sd = rt.sdtype
     U = torch.from_numpy(np.ascontiguousarray(w.U0[p])).to(dev).to(sd)
     Ub = torch.empty_like(U)
     UD = rt.grad_buffer()
@@ -143,24 +119,110 @@ def main():
         rt.rt_transport(UD, U_out=Ub, photon_total=Q, counts=counts, ledger=ledger)
         return Ub, U
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         U, Ub = step(U, Ub)
     Q0 = rt.rt_photon_total(U).cpu().numpy()
     ledger.zero_()
     torch.cuda.synchronize()
-
-    rt.rt_timing(True)
+    if timing:
+        rt.rt_timing(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         U, Ub = step(U, Ub)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t1
     rt.rt_timing(False)
     rt.rt_sync()
-    tr_ms, tr_n = rt.rt_get_timing("transport")
-    gr_ms, gr_n = rt.rt_get_timing("gradient")
-    in_ms, in_n = rt.rt_get_timing("inject")
+    out = {"rt": rt, "pairs": st["n_pairs"], "stats": st, "elapsed": elapsed,
+           "build_ms": build_ms, "dt": float(dt.item())}
+    for k in ("transport", "gradient", "inject"):
+        ms, nl = rt.rt_get_timing(k)
+        out[k + "_ms"] = ms / nl if nl else 0.0
+    Qe = Q.cpu().numpy()
+    out["photon_budget_residual"] = float(np.max(np.abs(
+        Qe - (Q0 + steps * out["dt"] * w.L.sum(axis=0) + ledger.cpu().numpy())) / Qe))
+    out["guard_counts"] = counts.cpu().tolist()
+    return out
+
+
+def run_adjoint(w, precision, dev):
+    """Forward rollout of w.steps steps with checkpoints every w.ckpt_every,
+    then its backward (segment recompute + adjoint); loss on the probe
+    particles against E_target from a run at perturbed luminosities."""
+    import numpy as np
+    import torch
+    from paper_2302_12727_amd import RT
+    from paper_2302_12727_amd.rollout import rollout
+
+    rt = RT(w.n, w.groups, precision=precision, cfl=w.cfl, c_red=w.c_red, device=dev)
+    perm, *_ = rt.rt_build_cells(torch.from_numpy(w.x).to(dev))
+    rt.rt_set_sources(torch.from_numpy(w.xs).to(dev))
+    rt.rt_sync()
+    p = perm.cpu().numpy()
+    inv = np.empty_like(p)
+    inv[p] = np.arange(w.n)
+    pr = torch.as_tensor(inv[w.probes], device=dev)
+    U0 = torch.from_numpy(np.ascontiguousarray(w.U0[p])).to(dev).to(rt.sdtype)
+    with torch.no_grad():
+        Ut = rollout(rt, torch.from_numpy(w.L_target).to(dev), U0, w.steps, w.ckpt_every)
+        Et = Ut[pr, :, 0].double().clone()
+    L = torch.from_numpy(w.L).to(dev).requires_grad_(True)
+    U0g = U0.clone().requires_grad_(True)
+    # warm-up of both directions
+    U = rollout(rt, L, U0g, 2, 1)
+    U[pr, :, 0].double().sum().backward()
+    L.grad = None
+    U0g.grad = None
+    torch.cuda.reset_peak_memory_stats(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U = rollout(rt, L, U0g, w.steps, w.ckpt_every)
+    loss = ((U[pr, :, 0].double() - Et) ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    st = rt.rt_get_stats()
+    return {"workload": w.name, "n": w.n, "groups": w.groups, "sources": int(w.xs.shape[0]),
+            "steps": w.steps, "ckpt_every": w.ckpt_every, "precision": precision,
+            "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
+            "adjoint_forward_ratio": (t2 - t1) / (t1 - t0),
+            "peak_hbm_GiB": (torch.cuda.max_memory_allocated(dev) + st["device_bytes"]) / 2 ** 30,
+            "loss": float(loss), "grad": (L.grad.cpu().numpy(), U0g.grad, p)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32c"])
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline leg (no FP32C leg, no adjoint leg)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also launch a plain device copy of 1 GiB (HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; --gpus above 1 is not supported "
+              "(multi-GPU sharding is a design note, not an implementation)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads
+
+    dev = torch.device("cuda:0")
+    w = workloads.config(args.config)
+    G = w.groups
+    log(f"workload {w.name}: n={w.n} G={G} S={w.xs.shape[0]} precision={args.precision}")
+    fw = run_forward(w, args.precision, args.steps, args.warmup, dev)
+    pairs, elapsed = fw["pairs"], fw["elapsed"]
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
@@ -169,7 +231,7 @@ def main():
         torch.cuda.synchronize()
 
     elem = 8 if args.precision == "fp64" else 4
-    tr_avg = tr_ms / max(tr_n, 1) * 1e-3
+    tr_avg = fw["transport_ms"] * 1e-3
     flops = transport_flops_per_pair(G) * pairs
     peak = PEAK_FP64_VALU if args.precision == "fp64" else PEAK_FP32_VALU
     achieved = flops / tr_avg
@@ -178,9 +240,11 @@ def main():
     if os.path.exists(tf):
         rec = json.load(open(tf))
         if rec.get("source_sha") == src_sha(os.path.join(ROOT, "paper_2302_12727_amd", "csrc",
-                                                         "rt_step.hip")):
+                                                         "rt_step.hip" if args.precision == "fp64"
+                                                         else "rt_step32.hip")):
             traffic = rec.get("hbm_bytes_per_launch")
-
+    label = ("2^21-particle 128^3 jittered lattice, 3 groups, 16 sources, c=1, CFL 0.9"
+             if args.config == 1 else w.name)
     out = {
         "metric": "RT pair interactions/s (FP64)" if args.precision == "fp64"
                   else "RT pair interactions/s (FP32-compensated)",
@@ -195,10 +259,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: 2^20-particle 128^3 jittered lattice, 3 groups, "
-                               f"16 sources, c=1, CFL 0.9" if args.config == 1 else w.name,
-                   "n": w.n, "groups": G, "sources": int(w.xs.shape[0]),
-                   "pairs": pairs, "precision": args.precision},
+        "config": {"workload": f"{w.name}: {label}", "n": w.n, "groups": G,
+                   "sources": int(w.xs.shape[0]), "pairs": pairs, "precision": args.precision},
         "roofline": {"bound": "alu", "kernel": "transport", "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic,
@@ -206,15 +268,28 @@ def main():
                      "algorithmic_bytes_per_launch": transport_bytes_per_particle(G, elem) * w.n,
                      "hbm_frac_at_algorithmic_bytes":
                          transport_bytes_per_particle(G, elem) * w.n / tr_avg / PEAK_HBM},
-        "kernel_ms": {"transport": tr_ms / max(tr_n, 1), "gradient": gr_ms / max(gr_n, 1),
-                      "inject": in_ms / max(in_n, 1) if in_n else 0.0},
-        "build_ms": build_ms,
-        # photon budget over the timed steps: Q_end = Q_0 + steps dt sum L + ledger
-        "photon_budget_residual": float(np.max(np.abs(
-            Q.cpu().numpy() - (Q0 + args.steps * float(dt.item()) * w.L.sum(axis=0)
-                               + ledger.cpu().numpy())) / Q.cpu().numpy())),
-        "guard_counts": counts.cpu().tolist(),
+        "kernel_ms": {"transport": fw["transport_ms"], "gradient": fw["gradient_ms"],
+                      "inject": fw["inject_ms"]},
+        "build_ms": fw["build_ms"],
+        "photon_budget_residual": fw["photon_budget_residual"],
+        "guard_counts": fw["guard_counts"],
     }
+    del fw
+    if not args.no_extra:
+        other = "fp32c" if args.precision == "fp64" else "fp64"
+        f2 = run_forward(w, other, args.steps, args.warmup, dev)
+        out[other] = {"value": f2["pairs"] * args.steps / f2["elapsed"],
+                      "ms_per_step": f2["elapsed"] / args.steps * 1e3,
+                      "kernel_ms": {"transport": f2["transport_ms"], "gradient": f2["gradient_ms"]},
+                      "speedup_vs_" + args.precision: out["ms_per_step"] /
+                      (f2["elapsed"] / args.steps * 1e3)}
+        del f2
+        wa = workloads.config(3)
+        ad = run_adjoint(wa, "fp64", dev)
+        ad.pop("grad")
+        ad["workload"] += " (128^3 jittered lattice, 3 groups, 64 sources, 4096 probes)"
+        out["adjoint"] = ad
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_seconds)
     print(json.dumps(out), flush=True)

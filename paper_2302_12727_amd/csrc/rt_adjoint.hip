@@ -248,11 +248,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad64(
 }
 
 // Pass D: dLoss/dL_s += dt sum_{g in s} coef_sg lam_E,g, one block per source.
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_inject(int32_t S, int G,
                                                        const int32_t *__restrict__ ptr,
                                                        const int32_t *__restrict__ gas,
                                                        const double *__restrict__ coef,
-                                                       const double *__restrict__ lam,
+                                                       const T *__restrict__ lam,
                                                        const double *__restrict__ dtp,
                                                        double *__restrict__ dLdL) {
     __shared__ double sm[kBlock];
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_inject(int32_t S, int G,
     for (int grp = 0; grp < G; ++grp) {
         double v = 0.0;
         for (int32_t e = ptr[s] + threadIdx.x; e < ptr[s + 1]; e += kBlock)
-            v += coef[e] * lam[((int64_t)gas[e] * G + grp) * 4];
+            v += coef[e] * (double)lam[((int64_t)gas[e] * G + grp) * 4];
         sm[threadIdx.x] = v;
         __syncthreads();
         for (int h = kBlock / 2; h > 0; h >>= 1) {
@@ -305,8 +306,7 @@ static rt_status adj_scratch(rt_ctx *ctx, size_t es, char **base) {
 rt_status rt_adjoint_impl(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
                           const void *UD, const void *U_ung, const void *lam_next, void *lam,
                           double *dL_dL) {
-    if (ctx->p.precision != RT_FP64) return rt_fail(ctx, RT_EINVAL, "FP32C adjoint not available");
-    const size_t es = 8;
+    const size_t es = ctx->p.precision == RT_FP64 ? 8 : 4;
     const size_t nu = (size_t)ctx->p.n * 4 * ctx->p.groups * es;
     char *b;
     rt_status rs = adj_scratch(ctx, es, &b);
@@ -316,12 +316,12 @@ rt_status rt_adjoint_impl(rt_ctx *ctx, const void *U_pre, const double *L, const
         b += (bytes + 255) & ~size_t(255);
         return (void *)p;
     };
-    double *lam2 = (double *)carve(nu);
-    double *Rb = (double *)carve(4 * nu);
-    double *Ut = (double *)carve(nu);
-    double *UDs = (double *)carve(4 * nu);
-    double *Uu = (double *)carve(nu);
-    double *Uo = (double *)carve(nu);
+    void *lam2 = carve(nu);
+    void *Rb = carve(4 * nu);
+    void *Ut = carve(nu);
+    void *UDs = carve(4 * nu);
+    void *Uu = carve(nu);
+    void *Uo = carve(nu);
     rt_timer_begin(ctx, "adjoint");
     if (!UD) {
         if (!U_pre) return rt_fail(ctx, RT_EINVAL, "U_pre is required when UD is NULL");
@@ -335,21 +335,30 @@ rt_status rt_adjoint_impl(rt_ctx *ctx, const void *U_pre, const double *L, const
             return rs;
         U_ung = Uu;
     }
-    switch (ctx->p.groups) {
-        case 1: launch_adjoint64<1>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
-        case 2: launch_adjoint64<2>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
-        case 3: launch_adjoint64<3>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
-        case 4: launch_adjoint64<4>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
-        case 5: launch_adjoint64<5>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
-        case 6: launch_adjoint64<6>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
-        case 7: launch_adjoint64<7>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
-        case 8: launch_adjoint64<8>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, lam2, Rb, (double *)lam, dt); break;
+    if (ctx->p.precision == RT_FP32C) {
+        rt_adjoint32(ctx, (const float *)UD, (const float *)U_ung, (const float *)lam_next,
+                     (float *)lam2, (float *)Rb, (float *)lam, dt);
+    } else switch (ctx->p.groups) {
+        case 1: launch_adjoint64<1>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
+        case 2: launch_adjoint64<2>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
+        case 3: launch_adjoint64<3>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
+        case 4: launch_adjoint64<4>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
+        case 5: launch_adjoint64<5>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
+        case 6: launch_adjoint64<6>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
+        case 7: launch_adjoint64<7>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
+        case 8: launch_adjoint64<8>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
         default: break;
     }
-    if (ctx->S > 0 && dL_dL)
-        k_adj_inject<<<ctx->S, kBlock, 0, ctx->stream>>>(ctx->S, ctx->p.groups, ctx->src_ptr,
-                                                         ctx->src_gas, ctx->src_coef,
-                                                         (const double *)lam, dt, dL_dL);
+    if (ctx->S > 0 && dL_dL) {
+        if (ctx->p.precision == RT_FP64)
+            k_adj_inject<double><<<ctx->S, kBlock, 0, ctx->stream>>>(
+                ctx->S, ctx->p.groups, ctx->src_ptr, ctx->src_gas, ctx->src_coef,
+                (const double *)lam, dt, dL_dL);
+        else
+            k_adj_inject<float><<<ctx->S, kBlock, 0, ctx->stream>>>(
+                ctx->S, ctx->p.groups, ctx->src_ptr, ctx->src_gas, ctx->src_coef,
+                (const float *)lam, dt, dL_dL);
+    }
     rt_timer_end(ctx, "adjoint");
     RT_HIP(hipGetLastError());
     return RT_OK;

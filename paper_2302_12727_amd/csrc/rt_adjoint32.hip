@@ -1,0 +1,274 @@
+// Compensated-FP32 adjoint of one RT step: the passes of the FP64 adjoint
+// (guard VJP, own-side pair VJPs, transpose of the gradient) with FP32 pair
+// arithmetic; the state cotangent of every particle is summed with Kahan
+// compensation.
+#include "rt_pair32.h"
+
+using namespace gearrt;
+
+namespace {
+
+inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_adj_guard32(int64_t n, const float *__restrict__ Uung,
+                                                        const float *__restrict__ lam_next,
+                                                        float *__restrict__ lam2, float c) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * G) return;
+    float q[4], l[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        q[m] = Uung[4 * t + m];
+        l[m] = lam_next[4 * t + m];
+    }
+    guard32_vjp(q, l, c);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) lam2[4 * t + m] = l[m];
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_adj_pair32(
+    int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ geo,
+    const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
+    const int32_t *__restrict__ n_nbr, const float *__restrict__ UD,
+    const float *__restrict__ lam2, const double *__restrict__ dtp, double c, double box,
+    float *__restrict__ R) {
+    constexpr int NQ = 4 * G;
+    __shared__ float stage[kBlock / 64][64 * kStage32];
+    const int64_t blk = xcd_block(nb);
+    if (blk >= nb) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t i = blk * kBlock + threadIdx.x;
+    const bool active = i < n;
+    const int64_t ic = active ? i : n - 1;
+    const int64_t w = i >> 6;
+    const bool wave_live = (w << 6) < n;
+    const double ibox = 1.0 / box;
+    const float cf = (float)c, c2 = (float)(c * c), ic2 = (float)(1.0 / (c * c));
+    const float dtf = (float)dtp[0];
+    float *sb = stage[wv];
+
+    const float *rk = geo32 + (int64_t)F_REC * ic;
+    const double *xk = reinterpret_cast<const double *>(rk);
+    const double pkx = xk[0], pky = xk[1], pkz = xk[2];
+    const float iHk = rk[F_IH], hk = rk[F_H];
+    float Bk[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) Bk[a] = rk[F_B + a];
+    const float dtVk = (float)(dtp[0] / geo[(int64_t)kRec * ic + R_V]);
+    float Ui[NQ], Di[NQ * 3], Li[NQ];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const float *r = UD + (ic * G + g) * 16;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            Ui[4 * g + m] = r[m];
+            Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
+            Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
+            Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
+            Li[4 * g + m] = lam2[(ic * G + g) * 4 + m];
+        }
+    }
+    Kahan aU[NQ];
+    float aD[NQ * 3];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        aU[q].s = aU[q].c = 0.0f;
+        aD[3 * q] = aD[3 * q + 1] = aD[3 * q + 2] = 0.0f;
+    }
+    if (wave_live) {
+        const int64_t base = wave_base[w] + lane;
+        const int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
+        const int32_t nn = active ? n_nbr[i] : 0;
+        for (int32_t k = 0; k < kmax; ++k) {
+            const bool valid = k < nn;
+            const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
+            int64_t row[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) row[m] = __shfl(j, 16 * m + (lane >> 2), 64);
+            stage_rows32(geo32, row, sb, lane);
+            PairGeo32 pg;
+            pair_geometry32(pkx, pky, pkz, iHk, hk, Bk, sb + lane * kStage32, box, ibox, pg);
+            const float dtVl = dtf * rcp32(sb[lane * kStage32 + F_V]);
+            const bool use = valid && pg.An > 0.0f;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                int64_t rowg[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) rowg[m] = row[m] * G + g;
+                stage_rows32(UD, rowg, sb, lane);
+                float Rl[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) Rl[q] = sb[lane * kStage32 + q];
+                const float4 Ll = *reinterpret_cast<const float4 *>(lam2 + ((int64_t)j * G + g) * 4);
+                float qLp[4], qRp[4], qL[4], qR[4];
+                bool own_slope[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int q = 4 * g + m;
+                    const float dk = Di[3 * q] * pg.sx + Di[3 * q + 1] * pg.sy + Di[3 * q + 2] * pg.sz;
+                    const float dl = Rl[4 + 3 * m] * pg.sx + Rl[5 + 3 * m] * pg.sy + Rl[6 + 3 * m] * pg.sz;
+                    const float mm = minmod32(dk, dl);
+                    own_slope[m] = (dk * dl > 0.0f) && (fabsf(dk) <= fabsf(dl));
+                    qLp[m] = qL[m] = Ui[q] + pg.fk * mm;
+                    qRp[m] = qR[m] = Rl[m] - pg.fl * mm;
+                }
+                guard32(qL[0], qL[1], qL[2], qL[3], cf);
+                guard32(qR[0], qR[1], qR[2], qR[3], cf);
+                const float Llm[4] = {Ll.x, Ll.y, Ll.z, Ll.w};
+                float nu[4], tL[4], tR[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) nu[m] = 0.5f * (dtVl * Llm[m] - dtVk * Li[4 * g + m]);
+                m1_flux32_vjp(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c2, ic2, nu, tL);
+                m1_flux32_vjp(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c2, ic2, nu, tR);
+                const float dis = cf * pg.An;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    tL[m] += dis * nu[m];
+                    tR[m] -= dis * nu[m];
+                }
+                guard32_vjp(qLp, tL, cf);
+                guard32_vjp(qRp, tR, cf);
+                if (use) {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int q = 4 * g + m;
+                        aU[q].add(tL[m]);
+                        const float lm = own_slope[m] ? pg.fk * tL[m] - pg.fl * tR[m] : 0.0f;
+                        aD[3 * q] += lm * pg.sx;
+                        aD[3 * q + 1] += lm * pg.sy;
+                        aD[3 * q + 2] += lm * pg.sz;
+                    }
+                }
+            }
+        }
+    }
+    if (!active) return;
+    const float iV = rcp32(rk[F_V]);
+    const float b00 = Bk[0] * iV, b01 = Bk[1] * iV, b02 = Bk[2] * iV;
+    const float b11 = Bk[3] * iV, b12 = Bk[4] * iV, b22 = Bk[5] * iV;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        float *o = R + (i * G + g) * 16;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int q = 4 * g + m;
+            o[m] = (float)((double)Li[q] + aU[q].value());
+            o[4 + 3 * m + 0] = b00 * aD[3 * q] + b01 * aD[3 * q + 1] + b02 * aD[3 * q + 2];
+            o[4 + 3 * m + 1] = b01 * aD[3 * q] + b11 * aD[3 * q + 1] + b12 * aD[3 * q + 2];
+            o[4 + 3 * m + 2] = b02 * aD[3 * q] + b12 * aD[3 * q + 1] + b22 * aD[3 * q + 2];
+        }
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_adj_grad32(
+    int64_t n, int64_t nb, const float *__restrict__ geo32, const int32_t *__restrict__ nbr,
+    const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
+    const float *__restrict__ R, float *__restrict__ lam, double box) {
+    constexpr int NQ = 4 * G;
+    __shared__ float stage[kBlock / 64][64 * kStage32];
+    const int64_t blk = xcd_block(nb);
+    if (blk >= nb) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t i = blk * kBlock + threadIdx.x;
+    const bool active = i < n;
+    const int64_t ic = active ? i : n - 1;
+    const int64_t w = i >> 6;
+    const bool wave_live = (w << 6) < n;
+    const double ibox = 1.0 / box;
+    float *sb = stage[wv];
+    const float *rp = geo32 + (int64_t)F_REC * ic;
+    const double *xp = reinterpret_cast<const double *>(rp);
+    const double px = xp[0], py = xp[1], pz = xp[2];
+    const float iHp = rp[F_IH];
+    Kahan acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q].s = acc[q].c = 0.0f;
+    float sgx = 0.0f, sgy = 0.0f, sgz = 0.0f;
+    if (wave_live) {
+        const int64_t base = wave_base[w] + lane;
+        const int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
+        const int32_t nn = active ? n_nbr[i] : 0;
+        for (int32_t k = 0; k < kmax; ++k) {
+            const bool valid = k < nn;
+            const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
+            int64_t row[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) row[m] = __shfl(j, 16 * m + (lane >> 2), 64);
+            stage_rows32(geo32, row, sb, lane);
+            const float *rl = sb + lane * kStage32;
+            double xl[3];
+            {
+                union { float f[2]; double d; } u;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    u.f[0] = rl[2 * a];
+                    u.f[1] = rl[2 * a + 1];
+                    xl[a] = u.d;
+                }
+            }
+            const float sx = (float)min_image(xl[0] - px, box, ibox);
+            const float sy = (float)min_image(xl[1] - py, box, ibox);
+            const float sz = (float)min_image(xl[2] - pz, box, ibox);
+            const float r = sqrt32(sx * sx + sy * sy + sz * sz);
+            const float wpi = valid ? kern_wf(r * iHp) : 0.0f;
+            const float wip = valid ? kern_wf(r * rl[F_IH]) : 0.0f;
+            sgx += wpi * sx;
+            sgy += wpi * sy;
+            sgz += wpi * sz;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                int64_t rowg[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) rowg[m] = row[m] * G + g;
+                stage_rows32(R, rowg, sb, lane);
+                const float *Rl = sb + lane * kStage32;
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    acc[4 * g + m].add(-wip * (Rl[4 + 3 * m] * sx + Rl[5 + 3 * m] * sy + Rl[6 + 3 * m] * sz));
+            }
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const float *Rp = R + (i * G + g) * 16;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            lam[(i * G + g) * 4 + m] = (float)(
+                (double)Rp[m] - (double)(sgx * Rp[4 + 3 * m] + sgy * Rp[5 + 3 * m] + sgz * Rp[6 + 3 * m]) +
+                acc[4 * g + m].value());
+    }
+}
+
+template <int G>
+void launch(rt_ctx *ctx, const float *UD, const float *Uung, const float *lam_next, float *lam2,
+            float *R, float *lam, const double *dt) {
+    const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
+    hipStream_t st = ctx->stream;
+    k_adj_guard32<G><<<nblk(n * G), kBlock, 0, st>>>(n, Uung, lam_next, lam2, (float)ctx->p.c_red);
+    k_adj_pair32<G><<<(unsigned)xcd_grid(nb), kBlock, 0, st>>>(
+        n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt,
+        ctx->p.c_red, ctx->p.box, R);
+    k_adj_grad32<G><<<(unsigned)xcd_grid(nb), kBlock, 0, st>>>(
+        n, nb, ctx->geo32, ctx->nbr, ctx->wave_base, ctx->n_nbr, R, lam, ctx->p.box);
+}
+
+}  // namespace
+
+void rt_adjoint32(rt_ctx *ctx, const float *UD, const float *Uung, const float *lam_next,
+                  float *lam2, float *R, float *lam, const double *dt) {
+    switch (ctx->p.groups) {
+        case 1: launch<1>(ctx, UD, Uung, lam_next, lam2, R, lam, dt); break;
+        case 2: launch<2>(ctx, UD, Uung, lam_next, lam2, R, lam, dt); break;
+        case 3: launch<3>(ctx, UD, Uung, lam_next, lam2, R, lam, dt); break;
+        case 4: launch<4>(ctx, UD, Uung, lam_next, lam2, R, lam, dt); break;
+        case 5: launch<5>(ctx, UD, Uung, lam_next, lam2, R, lam, dt); break;
+        case 6: launch<6>(ctx, UD, Uung, lam_next, lam2, R, lam, dt); break;
+        case 7: launch<7>(ctx, UD, Uung, lam_next, lam2, R, lam, dt); break;
+        case 8: launch<8>(ctx, UD, Uung, lam_next, lam2, R, lam, dt); break;
+        default: break;
+    }
+}

@@ -265,6 +265,8 @@ rt_status rt_total_impl(rt_ctx *ctx, const void *U, double *Q);
 void rt_gradient32(rt_ctx *ctx, const float *U, float *UD);
 void rt_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *Uout,
                     double *partials, int64_t *counts, float *Uung);
+void rt_adjoint32(rt_ctx *ctx, const float *UD, const float *Uung, const float *lam_next,
+                  float *lam2, float *R, float *lam, const double *dt);
 rt_status rt_ensure_partials(rt_ctx *ctx);
 
 // adjoint (rt_adjoint.hip)

@@ -1,0 +1,205 @@
+// FP32 device functions of one neighbour pair (compensated-FP32 path), shared
+// by the FP32 transport kernel and its adjoint.
+#pragma once
+
+#include "rt_internal.h"
+
+namespace gearrt {
+namespace {
+
+constexpr int kStage32 = 17;   // floats per staged 16-float row (bank padding)
+
+// Hardware FP32 reciprocal and square root (about one ulp).  FP32 denormals are
+// flushed on this path: the square root of a product that underflowed is 0
+// (never 0 * inf), which the callers treat as "no surface" / "no flux".
+__device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt32(float x) { return __builtin_amdgcn_sqrtf(fmaxf(x, 0.0f)); }
+
+__device__ __forceinline__ void wave_lds_sync32() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Kahan-compensated running sum.
+struct Kahan {
+    float s, c;
+    __device__ __forceinline__ void add(float x) {
+        const float y = x - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+};
+
+// Transport in FP32 with compensated accumulation.  Same scheme as the FP64
+// kernel (guards, M1 closure rewritten without n = F/|F|, GLF, minmod).
+__device__ __forceinline__ int guard32(float &E, float &Fx, float &Fy, float &Fz, float c) {
+    int fired = 0;
+    if (E < 0.0f) {
+        E = 0.0f;
+        fired = 1;
+    }
+    if (E == 0.0f) {
+        Fx = Fy = Fz = 0.0f;
+        return fired;
+    }
+    const float F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+    const float lim = c * E;
+    if (F2 > lim * lim) {
+        // |F| below 1e-19 (|F|^2 not a normal float) is scaled to the limit 0
+        const float Fn = sqrt32(F2);
+        const float sc = Fn > 0.0f ? lim * rcp32(Fn) : 0.0f;
+        Fx *= sc;
+        Fy *= sc;
+        Fz *= sc;
+        fired |= 2;
+    }
+    return fired;
+}
+
+// With g = F/E (|g| <= c after the guard) the closure needs no product that
+// can leave the FP32 range: f^2 = |g|^2/c^2 and (F.A) F / E = (g.A) F.  Energy
+// densities below 1e-30 carry no anisotropic term (their flux is below
+// 1e-30 |A| c^2 / 3).
+__device__ __forceinline__ void m1_flux32(float E, float Fx, float Fy, float Fz, float Ax,
+                                          float Ay, float Az, float c2, float ic2, float out[4]) {
+    const float FA = Fx * Ax + Fy * Ay + Fz * Az;
+    const float iE = E > 1e-30f ? rcp32(E) : 0.0f;
+    const float gx = Fx * iE, gy = Fy * iE, gz = Fz * iE;
+    const float f2 = (gx * gx + gy * gy + gz * gz) * ic2;
+    const float s = sqrt32(fmaxf(4.0f - 3.0f * f2, 0.0f));
+    const float id = rcp32(2.0f + s);
+    const float a = c2 * E * (1.0f / 3.0f - f2 * id);
+    const float b = 3.0f * id * (gx * Ax + gy * Ay + gz * Az);
+    out[0] = FA;
+    out[1] = a * Ax + b * Fx;
+    out[2] = a * Ay + b * Fy;
+    out[3] = a * Az + b * Fz;
+}
+
+__device__ __forceinline__ float minmod32(float a, float b) {
+    const float m = (fabsf(a) <= fabsf(b)) ? a : b;
+    return (a * b > 0.0f) ? m : 0.0f;
+}
+
+// Copy one 16-float (64-byte) row per lane's neighbour into the wave's stage
+// buffer: 4 loads, 4 lanes per row, 16 rows per load.
+__device__ __forceinline__ void stage_rows32(const float *__restrict__ src,
+                                             const int64_t (&row)[4], float *sb, int lane) {
+    const int piece = lane & 3, slot = lane >> 2;
+    float4 v[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        v[m] = *reinterpret_cast<const float4 *>(src + 16 * row[m] + 4 * piece);
+    wave_lds_sync32();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        float *d = sb + (16 * m + slot) * kStage32 + 4 * piece;
+        d[0] = v[m].x;
+        d[1] = v[m].y;
+        d[2] = v[m].z;
+        d[3] = v[m].w;
+    }
+    wave_lds_sync32();
+}
+
+
+// VJP of guard32 at its input state q (see guard64_vjp).
+__device__ __forceinline__ void guard32_vjp(const float q[4], float lam[4], float c) {
+    const float E = q[0];
+    if (E < 0.0f) {
+        lam[0] = lam[1] = lam[2] = lam[3] = 0.0f;
+        return;
+    }
+    if (E == 0.0f) {
+        lam[1] = lam[2] = lam[3] = 0.0f;
+        return;
+    }
+    const float F2 = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    const float lim = c * E;
+    if (F2 > lim * lim) {
+        const float Fn = sqrt32(F2);
+        if (!(Fn > 0.0f)) {          // forward set F = 0
+            lam[1] = lam[2] = lam[3] = 0.0f;
+            return;
+        }
+        const float iF = rcp32(Fn);
+        const float nx = q[1] * iF, ny = q[2] * iF, nz = q[3] * iF;
+        const float nl = nx * lam[1] + ny * lam[2] + nz * lam[3];
+        const float sc = lim * iF;
+        lam[0] += c * nl;
+        lam[1] = sc * (lam[1] - nx * nl);
+        lam[2] = sc * (lam[2] - ny * nl);
+        lam[3] = sc * (lam[3] - nz * nl);
+    }
+}
+
+// VJP of m1_flux32 (see m1_flux64_vjp for the formulas).
+__device__ __forceinline__ void m1_flux32_vjp(float E, float Fx, float Fy, float Fz, float Ax,
+                                              float Ay, float Az, float c2, float ic2,
+                                              const float nu[4], float out[4]) {
+    const float iE = E > 1e-30f ? rcp32(E) : 0.0f;
+    const float gx = Fx * iE, gy = Fy * iE, gz = Fz * iE;
+    const float f2 = (gx * gx + gy * gy + gz * gz) * ic2;
+    const float s = sqrt32(fmaxf(4.0f - 3.0f * f2, 0.0f));
+    const float is = rcp32(s);
+    const float id = rcp32(2.0f + s);
+    const float gA = gx * Ax + gy * Ay + gz * Az;
+    const float b = 3.0f * id * gA;
+    const float al = nu[1] * Ax + nu[2] * Ay + nu[3] * Az;
+    const float ng = nu[1] * gx + nu[2] * gy + nu[3] * gz;
+    const float k1 = id + 1.5f * id * id * f2 * is;
+    const float k2 = id + 3.0f * id * id * f2 * is;
+    const float t = 3.0f * ng;
+    const float tg = -2.0f * al * k1 + t * 3.0f * id * id * gA * is * ic2;
+    out[0] = al * c2 * (1.0f / 3.0f + f2 * k2) - t * gA * k2;
+    out[1] = nu[0] * Ax + tg * gx + t * id * Ax + b * nu[1];
+    out[2] = nu[0] * Ay + tg * gy + t * id * Ay + b * nu[2];
+    out[3] = nu[0] * Az + tg * gz + t * id * Az + b * nu[3];
+}
+
+// Geometry of one pair from the staged FP32 record rl of the neighbour and the
+// own FP64 position / FP32 record fields.
+struct PairGeo32 {
+    float sx, sy, sz, Ax, Ay, Az, An, fk, fl;
+};
+
+__device__ __forceinline__ void pair_geometry32(double pkx, double pky, double pkz, float iHk,
+                                                float hk, const float (&Bk)[6],
+                                                const float *__restrict__ rl, double box,
+                                                double ibox, PairGeo32 &pg) {
+    double xl[3];
+    {
+        union { float f[2]; double d; } u;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            u.f[0] = rl[2 * a];
+            u.f[1] = rl[2 * a + 1];
+            xl[a] = u.d;
+        }
+    }
+    pg.sx = (float)min_image(xl[0] - pkx, box, ibox);
+    pg.sy = (float)min_image(xl[1] - pky, box, ibox);
+    pg.sz = (float)min_image(xl[2] - pkz, box, ibox);
+    const float r = sqrt32(pg.sx * pg.sx + pg.sy * pg.sy + pg.sz * pg.sz);
+    const float wk = kern_wf(r * iHk);
+    const float wl = kern_wf(r * rl[F_IH]);
+    const float m00 = wk * Bk[0] + wl * rl[F_B + 0];
+    const float m01 = wk * Bk[1] + wl * rl[F_B + 1];
+    const float m02 = wk * Bk[2] + wl * rl[F_B + 2];
+    const float m11 = wk * Bk[3] + wl * rl[F_B + 3];
+    const float m12 = wk * Bk[4] + wl * rl[F_B + 4];
+    const float m22 = wk * Bk[5] + wl * rl[F_B + 5];
+    pg.Ax = m00 * pg.sx + m01 * pg.sy + m02 * pg.sz;
+    pg.Ay = m01 * pg.sx + m11 * pg.sy + m12 * pg.sz;
+    pg.Az = m02 * pg.sx + m12 * pg.sy + m22 * pg.sz;
+    pg.An = sqrt32(pg.Ax * pg.Ax + pg.Ay * pg.Ay + pg.Az * pg.Az);
+    const float hl = rl[F_H];
+    const float ih = rcp32(hk + hl);
+    pg.fk = hk * ih;
+    pg.fl = hl * ih;
+}
+
+}  // namespace
+}  // namespace gearrt

@@ -5,36 +5,11 @@
 // update combines sum and compensation once in FP64 before rounding the new
 // state to FP32.  FP64 stays in the geometry (separations from FP64 positions,
 // the FP64 inversion of S_i in the build) and in the photon budget.
-#include "rt_internal.h"
+#include "rt_pair32.h"
 
 using namespace gearrt;
 
 namespace {
-
-constexpr int kStage32 = 17;   // floats per staged 16-float row (bank padding)
-
-// Hardware FP32 reciprocal and square root (about one ulp).  FP32 denormals are
-// flushed on this path: the square root of a product that underflowed is 0
-// (never 0 * inf), which the callers treat as "no surface" / "no flux".
-__device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float sqrt32(float x) { return __builtin_amdgcn_sqrtf(fmaxf(x, 0.0f)); }
-
-__device__ __forceinline__ void wave_lds_sync32() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-}
-
-// Kahan-compensated running sum.
-struct Kahan {
-    float s, c;
-    __device__ __forceinline__ void add(float x) {
-        const float y = x - c;
-        const float t = s + y;
-        c = (t - s) - y;
-        s = t;
-    }
-    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
-};
 
 // ---------------------------------------------------------------------------
 // Gradient (eq:gradient) in FP32, S_i^{-1} sum_j (q_j - q_i) w(r_ij/H_i) s_ij.
@@ -91,79 +66,6 @@ __global__ __launch_bounds__(kBlock) void k_gradient32(
             o[4 + 3 * m + 2] = b02 * acc[q][0] + b12 * acc[q][1] + b22 * acc[q][2];
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// Transport in FP32 with compensated accumulation.  Same scheme as the FP64
-// kernel (guards, M1 closure rewritten without n = F/|F|, GLF, minmod).
-__device__ __forceinline__ int guard32(float &E, float &Fx, float &Fy, float &Fz, float c) {
-    int fired = 0;
-    if (E < 0.0f) {
-        E = 0.0f;
-        fired = 1;
-    }
-    if (E == 0.0f) {
-        Fx = Fy = Fz = 0.0f;
-        return fired;
-    }
-    const float F2 = Fx * Fx + Fy * Fy + Fz * Fz;
-    const float lim = c * E;
-    if (F2 > lim * lim) {
-        // |F| below 1e-19 (|F|^2 not a normal float) is scaled to the limit 0
-        const float Fn = sqrt32(F2);
-        const float sc = Fn > 0.0f ? lim * rcp32(Fn) : 0.0f;
-        Fx *= sc;
-        Fy *= sc;
-        Fz *= sc;
-        fired |= 2;
-    }
-    return fired;
-}
-
-// With g = F/E (|g| <= c after the guard) the closure needs no product that
-// can leave the FP32 range: f^2 = |g|^2/c^2 and (F.A) F / E = (g.A) F.  Energy
-// densities below 1e-30 carry no anisotropic term (their flux is below
-// 1e-30 |A| c^2 / 3).
-__device__ __forceinline__ void m1_flux32(float E, float Fx, float Fy, float Fz, float Ax,
-                                          float Ay, float Az, float c2, float ic2, float out[4]) {
-    const float FA = Fx * Ax + Fy * Ay + Fz * Az;
-    const float iE = E > 1e-30f ? rcp32(E) : 0.0f;
-    const float gx = Fx * iE, gy = Fy * iE, gz = Fz * iE;
-    const float f2 = (gx * gx + gy * gy + gz * gz) * ic2;
-    const float s = sqrt32(fmaxf(4.0f - 3.0f * f2, 0.0f));
-    const float id = rcp32(2.0f + s);
-    const float a = c2 * E * (1.0f / 3.0f - f2 * id);
-    const float b = 3.0f * id * (gx * Ax + gy * Ay + gz * Az);
-    out[0] = FA;
-    out[1] = a * Ax + b * Fx;
-    out[2] = a * Ay + b * Fy;
-    out[3] = a * Az + b * Fz;
-}
-
-__device__ __forceinline__ float minmod32(float a, float b) {
-    const float m = (fabsf(a) <= fabsf(b)) ? a : b;
-    return (a * b > 0.0f) ? m : 0.0f;
-}
-
-// Copy one 16-float (64-byte) row per lane's neighbour into the wave's stage
-// buffer: 4 loads, 4 lanes per row, 16 rows per load.
-__device__ __forceinline__ void stage_rows32(const float *__restrict__ src,
-                                             const int64_t (&row)[4], float *sb, int lane) {
-    const int piece = lane & 3, slot = lane >> 2;
-    float4 v[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-        v[m] = *reinterpret_cast<const float4 *>(src + 16 * row[m] + 4 * piece);
-    wave_lds_sync32();
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        float *d = sb + (16 * m + slot) * kStage32 + 4 * piece;
-        d[0] = v[m].x;
-        d[1] = v[m].y;
-        d[2] = v[m].z;
-        d[3] = v[m].w;
-    }
-    wave_lds_sync32();
 }
 
 template <int G>
