@@ -47,8 +47,18 @@ def transport_bytes_per_particle(G: int, elem: int) -> int:
     return 96 + (16 + 4) * G * elem
 
 
-def src_sha(path: str) -> str:
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+def src_sha(*paths: str) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def transport_sources(precision: str):
+    """Sources that define the transport kernel of one precision."""
+    d = os.path.join(ROOT, "paper_2302_12727_amd", "csrc")
+    names = (["rt_step.hip", "rt_pair.h"] if precision == "fp64" else ["rt_step32.hip", "rt_pair32.h"])
+    return [os.path.join(d, f) for f in names + ["rt_internal.h"]]
 
 
 def log(msg: str):
@@ -83,8 +93,10 @@ def cpu_baseline(cfg_index: int, min_seconds: float):
     }
 
 
-def run_forward(w, precision, steps, warmup, dev, timing=True):
-    """Build the static geometry, then time `steps` whole RT steps."""
+def run_forward(w, precision, steps, warmup, dev, timing=True, keep_state=False):
+    """Build the static geometry, then time `steps` whole RT steps (after
+    `warmup` untimed ones).  keep_state: also return the final state (input
+    order, FP64 host array)."""
     import numpy as np
     import torch
     from paper_2302_12727_amd import RT
@@ -143,7 +155,78 @@ def run_forward(w, precision, steps, warmup, dev, timing=True):
     out["photon_budget_residual"] = float(np.max(np.abs(
         Qe - (Q0 + steps * out["dt"] * w.L.sum(axis=0) + ledger.cpu().numpy())) / Qe))
     out["guard_counts"] = counts.cpu().tolist()
+    out["Q"] = Qe
+    if keep_state:
+        Uh = U.double().cpu().numpy()
+        out["U"] = np.empty_like(Uh)
+        out["U"][p] = Uh
     return out
+
+
+def compare_precisions(w, dev):
+    """FP64 and FP32C over the same steps of workload w from the same state:
+    throughput of both, and the FP32C error against FP64 for every output."""
+    import numpy as np
+    f64 = run_forward(w, "fp64", w.steps, 0, dev, keep_state=True)
+    f32 = run_forward(w, "fp32c", w.steps, 0, dev, keep_state=True)
+    a, b = f32["U"], f64["U"]
+    # per-state scale max(E, |F|/c), floored at 1e-6 of the mean energy (states
+    # that a guard emptied have E = F = 0 in one precision and a rounding-level
+    # remainder in the other)
+    mag = np.maximum(np.abs(b[..., 0]), np.sqrt((b[..., 1:] ** 2).sum(-1)) / w.c_red)
+    mag = np.maximum(mag, 1e-6 * np.abs(b[..., 0]).mean())
+    errs = {}
+    for name, d in (("E", np.abs(a[..., 0] - b[..., 0])),
+                    ("F", np.sqrt(((a[..., 1:] - b[..., 1:]) ** 2).sum(-1)) / w.c_red)):
+        per = d / mag
+        q = np.quantile(per, [0.5, 0.99, 0.999, 1.0])
+        errs[name] = {"normwise": float(d.max() / mag.max()), "per_state_median": float(q[0]),
+                      "per_state_p99": float(q[1]), "per_state_p999": float(q[2]),
+                      "per_state_max": float(q[3])}
+    errs["photon_total"] = float(np.abs(f32["Q"] / f64["Q"] - 1).max())
+    errs["fp32c_own_photon_budget_residual"] = f32["photon_budget_residual"]
+    h = f64["rt"].h
+    res = {"workload": w.name, "n": w.n, "groups": w.groups, "steps": w.steps,
+           "pairs": f64["pairs"], "h_span": float((h.max() / h.min()).item()),
+           "fp64": {"value": f64["pairs"] * w.steps / f64["elapsed"],
+                    "ms_per_step": f64["elapsed"] / w.steps * 1e3,
+                    "transport_ms": f64["transport_ms"], "gradient_ms": f64["gradient_ms"]},
+           "fp32c": {"value": f32["pairs"] * w.steps / f32["elapsed"],
+                     "ms_per_step": f32["elapsed"] / w.steps * 1e3,
+                     "transport_ms": f32["transport_ms"], "gradient_ms": f32["gradient_ms"]},
+           "speedup": f64["elapsed"] / f32["elapsed"],
+           "fp32c_vs_fp64_after_all_steps": errs}
+    del f64, f32
+    return res
+
+
+def large_adjoint(dev):
+    """2^24 Plummer mix, 4 groups, 256 sources, 50 steps, checkpoints every
+    10: the FP32C rollout and its adjoint (time ratio, peak HBM), and its
+    gradients against those of the FP64 adjoint."""
+    import numpy as np
+    import torch
+    import workloads
+    w = workloads.config(4)
+    res = {}
+    grads = {}
+    for prec in ("fp32c", "fp64"):
+        torch.cuda.empty_cache()
+        ad = run_adjoint(w, prec, dev)
+        grads[prec] = ad.pop("grad")
+        res[prec] = ad
+        log(f"large adjoint [{prec}]: ratio {ad['adjoint_forward_ratio']:.2f}, "
+            f"peak {ad['peak_hbm_GiB']:.1f} GiB")
+    gL32, gU32, p = grads["fp32c"]
+    gL64, gU64, _ = grads["fp64"]
+    d = (gU32.double() - gU64).abs()
+    q = torch.quantile(d.flatten()[:: d.numel() // (1 << 24) + 1] / gU64.abs().max(),
+                       torch.tensor([0.5, 0.99], dtype=torch.float64, device=d.device))
+    res["fp32c_gradient_error"] = {
+        "dL_normwise": float(np.abs(gL32 - gL64).max() / np.abs(gL64).max()),
+        "dU0_normwise": float(d.max() / gU64.abs().max()),
+        "dU0_median": float(q[0]), "dU0_p99": float(q[1])}
+    return res
 
 
 def run_adjoint(w, precision, dev):
@@ -185,12 +268,13 @@ def run_adjoint(w, precision, dev):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     st = rt.rt_get_stats()
+    gU0 = U0g.grad.double()
     return {"workload": w.name, "n": w.n, "groups": w.groups, "sources": int(w.xs.shape[0]),
             "steps": w.steps, "ckpt_every": w.ckpt_every, "precision": precision,
             "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
             "adjoint_forward_ratio": (t2 - t1) / (t1 - t0),
             "peak_hbm_GiB": (torch.cuda.max_memory_allocated(dev) + st["device_bytes"]) / 2 ** 30,
-            "loss": float(loss), "grad": (L.grad.cpu().numpy(), U0g.grad, p)}
+            "loss": float(loss.detach()), "grad": (L.grad.cpu().numpy(), gU0, p)}
 
 
 def main():
@@ -204,6 +288,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="only the headline leg (no FP32C leg, no adjoint leg)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--large-adjoint", action="store_true",
+                    help="also run the 2^24-particle FP32C/FP64 adjoint case (about a minute)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also launch a plain device copy of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -239,9 +325,7 @@ def main():
     tf = os.path.join(ROOT, "profiles", f"transport_traffic_{w.name}_{args.precision}.json")
     if os.path.exists(tf):
         rec = json.load(open(tf))
-        if rec.get("source_sha") == src_sha(os.path.join(ROOT, "paper_2302_12727_amd", "csrc",
-                                                         "rt_step.hip" if args.precision == "fp64"
-                                                         else "rt_step32.hip")):
+        if rec.get("source_sha") == src_sha(*transport_sources(args.precision)):
             traffic = rec.get("hbm_bytes_per_launch")
     label = ("2^21-particle 128^3 jittered lattice, 3 groups, 16 sources, c=1, CFL 0.9"
              if args.config == 1 else w.name)
@@ -289,6 +373,11 @@ def main():
         ad.pop("grad")
         ad["workload"] += " (128^3 jittered lattice, 3 groups, 64 sources, 4096 probes)"
         out["adjoint"] = ad
+        torch.cuda.empty_cache()
+        out["plummer_fp32c_vs_fp64"] = compare_precisions(workloads.config(2), dev)
+        torch.cuda.empty_cache()
+    if args.large_adjoint:
+        out["large_adjoint"] = large_adjoint(dev)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_seconds)

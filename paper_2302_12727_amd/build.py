@@ -23,29 +23,33 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, bdir: str = BUILD, defines=()) -> str:
+    obj = os.path.join(bdir, src.replace(".hip", ".o"))
+    cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, lib: str = LIB, defines=()) -> str:
+    """Compile every source and link `lib`.  `defines` (NAME=VALUE strings) set
+    the tuning macros of the kernels (tile shapes, groups per wave); a build
+    with non-default macros goes to its own object folder and library path."""
+    bdir = BUILD if not defines else os.path.join(BUILD, "_".join(sorted(defines)).replace("=", "-"))
+    os.makedirs(bdir, exist_ok=True)
     t0 = time.time()
     with ThreadPoolExecutor(max_workers=4) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, bdir, defines), SOURCES))
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB} in {time.time() - t0:.1f} s", file=sys.stderr)
-    return LIB
+        print(f"built {lib} in {time.time() - t0:.1f} s", file=sys.stderr)
+    return lib
 
 
 if __name__ == "__main__":

@@ -43,24 +43,29 @@ __global__ __launch_bounds__(kBlock) void k_adj_guard64(int64_t n, const double 
     for (int m = 0; m < 4; ++m) lam2[4 * t + m] = l[m];
 }
 
-// Pass B.  R[k][g] = (lam'_k (4) | rho_k (4 x 3)), the layout of a gradient record.
-template <int G>
+// Pass B.  R[k][g] = (lam'_k (4) | rho_k (4 x 3)), the layout of a gradient
+// record.  As in the forward transport, a wave owns 64 particles and GW of the
+// G groups.
+template <int G, int GW>
 __global__ __launch_bounds__(kBlock) void k_adj_pair64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
     const double *__restrict__ UD, const double *__restrict__ lam2,
     const double *__restrict__ dtp, double c, double box, double *__restrict__ R) {
-    constexpr int NQ = 4 * G;
+    static_assert(G % GW == 0, "group slices must tile the groups");
+    constexpr int NS = G / GW, NQ = 4 * GW;
     __shared__ double stage[kBlock / 64][64 * kStage];
-    const int64_t blk = xcd_block(nb);
-    if (blk >= nb) return;
+    const int64_t bg = xcd_block(nb * NS);
+    if (bg >= nb * NS) return;
+    const int64_t blk = bg / NS;
+    const int g0 = (int)(bg - blk * NS) * GW;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t i = blk * kBlock + threadIdx.x;
     const bool active = i < n;
     const int64_t ic = active ? i : n - 1;
     const int64_t w = i >> 6;
     const bool wave_live = (w << 6) < n;
-    const double ibox = 1.0 / box, c2 = c * c, ic2 = 1.0 / c2, hc = 0.5 * c;
+    const double ibox = 1.0 / box;
     const double dt = dtp[0];
     double *sb = stage[wv];
 
@@ -68,15 +73,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair64(
     const double dtVk = dt / rk[R_V];
     double Ui[NQ], Di[NQ * 3], Li[NQ];
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const double *r = UD + (ic * G + g) * 16;
+    for (int g = 0; g < GW; ++g) {
+        const double *r = UD + (ic * G + g0 + g) * 16;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             Ui[4 * g + m] = r[m];
             Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
             Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
             Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
-            Li[4 * g + m] = lam2[(ic * G + g) * 4 + m];
+            Li[4 * g + m] = lam2[(ic * G + g0 + g) * 4 + m];
         }
     }
     double aU[NQ], aD[NQ * 3];
@@ -102,15 +107,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair64(
             const bool use = valid && pg.An > 0.0;
             const double dtVl = dt / rl[R_V];
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
+            for (int g = 0; g < GW; ++g) {
                 int64_t rowg[8];
 #pragma unroll
-                for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g;
+                for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g0 + g;
                 stage_lines(UD, rowg, sb, lane);
                 double Rl[16];
 #pragma unroll
                 for (int q = 0; q < 16; ++q) Rl[q] = sb[lane * kStage + q];
-                stage_rows4(lam2 + 4 * g, 4 * G, j, sb, lane);
+                stage_rows4(lam2 + 4 * (g0 + g), 4 * G, j, sb, lane);
                 double Ll[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) Ll[m] = sb[lane * kStage + m];
@@ -133,8 +138,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair64(
                 double nu[4], tL[4], tR[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) nu[m] = 0.5 * (dtVl * Ll[m] - dtVk * Li[4 * g + m]);
-                m1_flux64_vjp(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c2, ic2, nu, tL);
-                m1_flux64_vjp(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c2, ic2, nu, tR);
+                m1_flux64_vjp(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, nu, tL);
+                m1_flux64_vjp(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, nu, tR);
                 const double dis = c * pg.An;   // 2 * (c/2) |A| times nu = mu/2
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
@@ -157,14 +162,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair64(
             }
         }
     }
-    (void)hc;
     if (!active) return;
     const double iV = 1.0 / rk[R_V];
     const double b00 = rk[R_B] * iV, b01 = rk[R_B + 1] * iV, b02 = rk[R_B + 2] * iV;
     const double b11 = rk[R_B + 3] * iV, b12 = rk[R_B + 4] * iV, b22 = rk[R_B + 5] * iV;
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        double *o = R + (i * G + g) * 16;
+    for (int g = 0; g < GW; ++g) {
+        double *o = R + (i * G + g0 + g) * 16;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int q = 4 * g + m;
@@ -177,7 +181,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair64(
 }
 
 // Pass C: transpose of the least-squares gradient, gathered over the
-// symmetric neighbour lists (i is a gather neighbour of p iff r < H_i).
+// symmetric neighbour lists (i is a gather neighbour of p iff r < H_i).  All
+// loads of one neighbour slot (position and 1/H, and the G records of rho)
+// are issued before the first is staged, so their latencies overlap.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_adj_grad64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
@@ -211,27 +217,51 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad64(
             int64_t row[8];
 #pragma unroll
             for (int m = 0; m < 8; ++m) row[m] = __shfl(j, 8 * m + (lane >> 3), 64);
-            stage_lines(geo, row, sb, lane);
+            // groups in chunks of at most GC records in flight
+            constexpr int GC = G < 4 ? G : 4;
+            double2 vp[2], vr[GC][8];
+            load_rows4(geo, kRec, j, lane, vp);
+#pragma unroll
+            for (int g = 0; g < GC; ++g) {
+                int64_t rowg[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g;
+                load_lines(R, rowg, lane, vr[g]);
+            }
+            store_rows4(vp, sb, lane);
             const double *rl = sb + lane * kStage;
             const double sx = min_image(rl[0] - px, box, ibox);
             const double sy = min_image(rl[1] - py, box, ibox);
             const double sz = min_image(rl[2] - pz, box, ibox);
+            const double iHl = rl[R_IH];
             const double r = sqrt64(sx * sx + sy * sy + sz * sz);
             const double wpi = valid ? kern_w(r * iHp) : 0.0;
-            const double wip = valid ? kern_w(r * rl[R_IH]) : 0.0;
+            const double wip = valid ? kern_w(r * iHl) : 0.0;
             sgx += wpi * sx;
             sgy += wpi * sy;
             sgz += wpi * sz;
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                int64_t rowg[8];
+            for (int c0 = 0; c0 < G; c0 += GC) {
+                if (c0 > 0) {
 #pragma unroll
-                for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g;
-                stage_lines(R, rowg, sb, lane);
-                const double *Rl = sb + lane * kStage;
+                    for (int g = 0; g < GC; ++g) {
+                        if (c0 + g >= G) break;
+                        int64_t rowg[8];
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    acc[4 * g + m] -= wip * (Rl[4 + 3 * m] * sx + Rl[5 + 3 * m] * sy + Rl[6 + 3 * m] * sz);
+                        for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + c0 + g;
+                        load_lines(R, rowg, lane, vr[g]);
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < GC; ++g) {
+                    if (c0 + g >= G) break;
+                    store_lines(vr[g], sb, lane);
+                    const double *Rl = sb + lane * kStage;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        acc[4 * (c0 + g) + m] -=
+                            wip * (Rl[4 + 3 * m] * sx + Rl[5 + 3 * m] * sy + Rl[6 + 3 * m] * sz);
+                }
             }
         }
     }
@@ -273,13 +303,22 @@ __global__ __launch_bounds__(kBlock) void k_adj_inject(int32_t S, int G,
     }
 }
 
+// Groups per wave of the adjoint pair pass.  Its per-group state is three
+// times the forward's, so one group per wave wins here (G = 3: 239 VGPRs and
+// 2 waves per SIMD, against occupancy 1 with all groups; the pass is 1.5x
+// faster).
+#ifndef RT_ADJ_GW
+#define RT_ADJ_GW 1
+#endif
+
 template <int G>
 void launch_adjoint64(rt_ctx *ctx, const double *UD, const double *Uung, const double *lam_next,
                       double *lam2, double *R, double *lam, const double *dt) {
     const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
     hipStream_t st = ctx->stream;
     k_adj_guard64<G><<<nblk(n * G), kBlock, 0, st>>>(n, Uung, lam_next, lam2, ctx->p.c_red);
-    k_adj_pair64<G><<<(unsigned)xcd_grid(nb), kBlock, 0, st>>>(
+    constexpr int GW = (RT_ADJ_GW == 0 || G % RT_ADJ_GW != 0) ? G : RT_ADJ_GW;
+    k_adj_pair64<G, GW><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, st>>>(
         n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt, ctx->p.c_red,
         ctx->p.box, R);
     k_adj_grad64<G><<<(unsigned)xcd_grid(nb), kBlock, 0, st>>>(

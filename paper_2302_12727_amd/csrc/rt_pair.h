@@ -35,25 +35,26 @@ __device__ __forceinline__ int guard64(double &E, double &Fx, double &Fy, double
 }
 
 // Flux of a state through the (unnormalised) surface A, using the M1 closure
-// (eq:eddington-group) rewritten without the 0/0 of n = F/|F|:
-//   with f^2 = |F|^2/(cE)^2, s = sqrt(4 - 3 f^2):
-//   (3 chi - 1)/(2 f^2) = 3/(2 + s),  (1 - chi)/2 = 1/3 - f^2/(2 + s),
-//   c^2 P A = c^2 E (1-chi)/2 A + 3/(2+s) (F.A) F / E.
-// out[0] = F.A, out[1..3] = c^2 P A.  A state with E = 0 has no flux.
+// (eq:eddington-group) rewritten without the 0/0 of n = F/|F| and without any
+// division by E.  With f = |F|/(cE), the Eddington factor gives
+//   (1 - chi)/2 = 1/3 - f^2/(2 + s),  (3 chi - 1)/(2 f^2) = 3/(2 + s),
+//   s = sqrt(4 - 3 f^2);
+// multiplying through by cE, with R = sqrt(4 (cE)^2 - 3 |F|^2) and
+// D = 2 cE + R:
+//   c^2 P A = (c^2 E/3 - c |F|^2/D) A + 3 c (F.A)/D F.
+// out[0] = F.A, out[1..3] = c^2 P A.  Guarded states have |F| <= cE, so
+// R >= cE; a state with E = 0 (and F = 0) has no flux (1/D replaced by 0).
 __device__ __forceinline__ void m1_flux64(double E, double Fx, double Fy, double Fz, double Ax,
-                                          double Ay, double Az, double c, double c2, double ic2,
-                                          double out[4]) {
-    // Guarded states have E >= 0 and F = 0 when E = 0; with 1/E replaced by 0
-    // there every term below vanishes, so no branch is needed.
-    // g = F/E keeps every product in range: f^2 = |g|^2/c^2, (F.A) F/E = (g.A) F.
+                                          double Ay, double Az, double c, double out[4]) {
     const double FA = Fx * Ax + Fy * Ay + Fz * Az;
-    const double iE = E > 0.0 ? rcp64(E) : 0.0;
-    const double gx = Fx * iE, gy = Fy * iE, gz = Fz * iE;
-    const double f2 = (gx * gx + gy * gy + gz * gz) * ic2;
-    const double s = sqrt64(fmax(4.0 - 3.0 * f2, 0.0));
-    const double id = rcp64(2.0 + s);
-    const double a = c2 * E * (1.0 / 3.0 - f2 * id);
-    const double b = 3.0 * id * (gx * Ax + gy * Ay + gz * Az);
+    const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+    const double cE = c * E;
+    const double R2 = __builtin_fma(-3.0, F2, 4.0 * cE * cE);
+    const double R = R2 > 0.0 ? R2 * rsq64(R2) : 0.0;
+    const double D = __builtin_fma(2.0, cE, R);
+    const double iD = D > 0.0 ? rcp64(D) : 0.0;
+    const double a = c * __builtin_fma(-F2, iD, cE * (1.0 / 3.0));
+    const double b = 3.0 * c * FA * iD;
     out[0] = FA;
     out[1] = a * Ax + b * Fx;
     out[2] = a * Ay + b * Fy;
@@ -98,9 +99,10 @@ __device__ __forceinline__ void pair_geometry64(const double *__restrict__ rk,
     pg.fl = rl[R_H] * ih;
 }
 
-template <int NP>
+// Block sum of NP per-lane values; value p goes to out[col(p)].
+template <int NP, class Col>
 __device__ __forceinline__ void block_reduce_store(double (&v)[NP], double *__restrict__ out,
-                                                   double *smem) {
+                                                   double *smem, Col col) {
     // smem: [kBlock/64][NP]
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -112,7 +114,7 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NP], double *__re
     if (threadIdx.x < NP) {
         double s = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) s += smem[w * NP + threadIdx.x];
-        out[threadIdx.x] = s;
+        out[col((int)threadIdx.x)] = s;
     }
 }
 
@@ -133,13 +135,17 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Copy one 16-double line per lane's neighbour (line base pointers src + 16 *
 // row[m]) into the wave's stage buffer: 8 loads, each lane moving 16 bytes.
-__device__ __forceinline__ void stage_lines(const double *__restrict__ src, const int64_t (&row)[8],
-                                            double *sb, int lane) {
-    const int piece = lane & 7, slot = lane >> 3;
-    double2 v[8];
+// The load and store halves are separate so that a kernel can put several
+// loads in flight before it stores the first of them.
+__device__ __forceinline__ void load_lines(const double *__restrict__ src, const int64_t (&row)[8],
+                                           int lane, double2 (&v)[8]) {
+    const int piece = lane & 7;
 #pragma unroll
     for (int m = 0; m < 8; ++m)
         v[m] = *reinterpret_cast<const double2 *>(src + 16 * row[m] + 2 * piece);
+}
+__device__ __forceinline__ void store_lines(const double2 (&v)[8], double *sb, int lane) {
+    const int piece = lane & 7, slot = lane >> 3;
     wave_lds_sync();
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
@@ -149,19 +155,26 @@ __device__ __forceinline__ void stage_lines(const double *__restrict__ src, cons
     }
     wave_lds_sync();
 }
-
+__device__ __forceinline__ void stage_lines(const double *__restrict__ src, const int64_t (&row)[8],
+                                            double *sb, int lane) {
+    double2 v[8];
+    load_lines(src, row, lane, v);
+    store_lines(v, sb, lane);
+}
 
 // Copy the 4-double row (row_stride doubles apart) of every lane's row index j
 // into the wave's stage buffer: 2 loads, 2 lanes per row, 32 rows per load.
-__device__ __forceinline__ void stage_rows4(const double *__restrict__ src, int64_t row_stride,
-                                            int64_t j, double *sb, int lane) {
+__device__ __forceinline__ void load_rows4(const double *__restrict__ src, int64_t row_stride,
+                                           int64_t j, int lane, double2 (&v)[2]) {
     const int piece = lane & 1, slot = lane >> 1;
-    double2 v[2];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         const int64_t r = __shfl(j, 32 * m + slot, 64);
         v[m] = *reinterpret_cast<const double2 *>(src + row_stride * r + 2 * piece);
     }
+}
+__device__ __forceinline__ void store_rows4(const double2 (&v)[2], double *sb, int lane) {
+    const int piece = lane & 1, slot = lane >> 1;
     wave_lds_sync();
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
@@ -170,6 +183,12 @@ __device__ __forceinline__ void stage_rows4(const double *__restrict__ src, int6
         d[1] = v[m].y;
     }
     wave_lds_sync();
+}
+__device__ __forceinline__ void stage_rows4(const double *__restrict__ src, int64_t row_stride,
+                                            int64_t j, double *sb, int lane) {
+    double2 v[2];
+    load_rows4(src, row_stride, j, lane, v);
+    store_rows4(v, sb, lane);
 }
 
 // Vector-Jacobian product of guard64 at its input state q (before the guard):
@@ -203,34 +222,33 @@ __device__ __forceinline__ void guard64_vjp(const double q[4], double lam[4], do
 }
 
 // Vector-Jacobian product of m1_flux64 with respect to the (guarded) face
-// state (E, F) for cotangent nu = (nu0, nu_v) of (F.A, c^2 P A).  With
-// g = F/E, f^2 = |g|^2/c^2, s = sqrt(4 - 3 f^2), id = 1/(2 + s):
-//   a = c^2 E/3 - c^2 E f^2 id,  b = 3 id (g.A),  flux_v = a A + b F,
-//   kappa1 = id + (3/2) id^2 f^2 / s,  kappa2 = id + 3 id^2 f^2 / s,
-//   d/dF = nu0 A - 2 (nu_v.A) kappa1 g + 3 (nu_v.g)(id A + 3 id^2 (g.A) g/(s c^2)) + b nu_v
-//   d/dE = (nu_v.A) c^2 (1/3 + f^2 kappa2) - 3 (nu_v.g)(g.A) kappa2
-// (at E = 0, where F = 0, the one-sided limit g = 0 is used).
+// state (E, F) for the cotangent nu = (nu0, nu_v) of (F.A, c^2 P A).  In the
+// form above, flux_v = a A + b F with a = c^2 E/3 - c |F|^2/D,
+// b = 3 c (F.A)/D, dD/dE = 2c + 4 c (cE)/R, dD/dF = -3 F/R.  With
+// alpha = nu_v.A, beta = nu_v.F and K = c (alpha |F|^2 - 3 (F.A) beta)/D^2:
+//   d/dE = alpha c^2/3 + K dD/dE
+//   d/dF = (nu0 + 3 c beta/D) A + 3 c (F.A)/D nu_v - (2 c alpha/D + 3 K/R) F
+// (at E = 0, where F = 0, 1/D and 1/R are replaced by 0: the one-sided limit).
 __device__ __forceinline__ void m1_flux64_vjp(double E, double Fx, double Fy, double Fz, double Ax,
-                                              double Ay, double Az, double c2, double ic2,
-                                              const double nu[4], double out[4]) {
-    const double iE = E > 0.0 ? rcp64(E) : 0.0;
-    const double gx = Fx * iE, gy = Fy * iE, gz = Fz * iE;
-    const double f2 = (gx * gx + gy * gy + gz * gz) * ic2;
-    const double s = sqrt64(fmax(4.0 - 3.0 * f2, 0.0));
-    const double is = rcp64(s);
-    const double id = rcp64(2.0 + s);
-    const double gA = gx * Ax + gy * Ay + gz * Az;
-    const double b = 3.0 * id * gA;
+                                              double Ay, double Az, double c, const double nu[4],
+                                              double out[4]) {
+    const double FA = Fx * Ax + Fy * Ay + Fz * Az;
+    const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+    const double cE = c * E;
+    const double R2 = __builtin_fma(-3.0, F2, 4.0 * cE * cE);
+    const double iR = R2 > 0.0 ? rsq64(R2) : 0.0;
+    const double D = __builtin_fma(2.0, cE, R2 * iR);
+    const double iD = D > 0.0 ? rcp64(D) : 0.0;
     const double al = nu[1] * Ax + nu[2] * Ay + nu[3] * Az;
-    const double ng = nu[1] * gx + nu[2] * gy + nu[3] * gz;
-    const double k1 = id + 1.5 * id * id * f2 * is;
-    const double k2 = id + 3.0 * id * id * f2 * is;
-    const double t = 3.0 * ng;
-    const double tg = -2.0 * al * k1 + t * 3.0 * id * id * gA * is * ic2;
-    out[0] = al * c2 * (1.0 / 3.0 + f2 * k2) - t * gA * k2;
-    out[1] = nu[0] * Ax + tg * gx + t * id * Ax + b * nu[1];
-    out[2] = nu[0] * Ay + tg * gy + t * id * Ay + b * nu[2];
-    out[3] = nu[0] * Az + tg * gz + t * id * Az + b * nu[3];
+    const double be = nu[1] * Fx + nu[2] * Fy + nu[3] * Fz;
+    const double K = c * iD * iD * __builtin_fma(al, F2, -3.0 * FA * be);
+    const double cA = __builtin_fma(3.0 * c * be, iD, nu[0]);
+    const double cn = 3.0 * c * FA * iD;
+    const double cF = __builtin_fma(2.0 * c * al, iD, 3.0 * K * iR);
+    out[0] = __builtin_fma(al, c * c * (1.0 / 3.0), K * __builtin_fma(4.0 * c * cE, iR, 2.0 * c));
+    out[1] = cA * Ax + cn * nu[1] - cF * Fx;
+    out[2] = cA * Ay + cn * nu[2] - cF * Fy;
+    out[3] = cA * Az + cn * nu[3] - cF * Fz;
 }
 
 }  // namespace

@@ -93,35 +93,43 @@ __global__ __launch_bounds__(kBlock) void k_gradient64(
     }
 }
 
-template <int G>
+// Transport (eq:transport-update-explicit with the GLF flux eq:riemann-GLF).
+// A wave owns 64 particles and GW of the G photon groups (G/GW waves share
+// the same particles): fewer groups per wave keep less state in registers
+// and so more waves resident, at the price of recomputing the pair geometry
+// once per group slice.
+template <int G, int GW>
 __global__ __launch_bounds__(kBlock) void k_transport64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
     const double *__restrict__ UD, const double *__restrict__ dtp, double c, double box,
     double *__restrict__ Uout, double *__restrict__ partials,
     unsigned long long *__restrict__ counts, double *__restrict__ Uung) {
-    constexpr int NQ = 4 * G;
+    static_assert(G % GW == 0, "group slices must tile the groups");
+    constexpr int NS = G / GW, NQ = 4 * G;
     __shared__ double stage[kBlock / 64][64 * kStage];
-    __shared__ double smem[(kBlock / 64) * 2 * G];
+    __shared__ double smem[(kBlock / 64) * 2 * GW];
     __shared__ unsigned long long scnt[4];
-    const int64_t blk = xcd_block(nb);
-    if (blk >= nb) return;                      // whole block: no barrier is skipped
+    const int64_t bg = xcd_block(nb * NS);
+    if (bg >= nb * NS) return;                  // whole block: no barrier is skipped
+    const int64_t blk = bg / NS;
+    const int g0 = (int)(bg - blk * NS) * GW;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t i = blk * kBlock + threadIdx.x;
     const bool active = i < n;
     const int64_t ic = active ? i : n - 1;      // in-range index for inactive lanes
     const int64_t w = i >> 6;
     const bool wave_live = (w << 6) < n;        // wave-uniform
-    const double ibox = 1.0 / box, c2 = c * c, ic2 = 1.0 / c2, hc = 0.5 * c;
+    const double ibox = 1.0 / box, hc = 0.5 * c;
     if (threadIdx.x < 4) scnt[threadIdx.x] = 0;
     double *sb = stage[wv];
 
     // own particle: geometry record, state and gradients (registers)
     const double *rk = geo + (int64_t)kRec * ic;
-    double Ui[NQ], Di[NQ * 3];
+    double Ui[4 * GW], Di[12 * GW];
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const double *r = UD + (ic * G + g) * 16;
+    for (int g = 0; g < GW; ++g) {
+        const double *r = UD + (ic * G + g0 + g) * 16;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             Ui[4 * g + m] = r[m];
@@ -130,9 +138,9 @@ __global__ __launch_bounds__(kBlock) void k_transport64(
             Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
         }
     }
-    double acc[NQ];
+    double acc[4 * GW];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    for (int q = 0; q < 4 * GW; ++q) acc[q] = 0.0;
     int cE = 0, cF = 0;
 
     if (wave_live) {
@@ -154,10 +162,10 @@ __global__ __launch_bounds__(kBlock) void k_transport64(
             pair_geometry64(rk, rl, box, ibox, pg);
             const bool use = valid && pg.An > 0.0;
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
+            for (int g = 0; g < GW; ++g) {
                 int64_t rowg[8];
 #pragma unroll
-                for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g;
+                for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g0 + g;
                 stage_lines(UD, rowg, sb, lane);
                 const double *Rl = sb + lane * kStage;
                 double qL[4], qR[4];
@@ -173,8 +181,8 @@ __global__ __launch_bounds__(kBlock) void k_transport64(
                 const int f1 = guard64(qL[0], qL[1], qL[2], qL[3], c);
                 const int f2 = guard64(qR[0], qR[1], qR[2], qR[3], c);
                 double FL[4], FR[4];
-                m1_flux64(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, c2, ic2, FL);
-                m1_flux64(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, c2, ic2, FR);
+                m1_flux64(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, FL);
+                m1_flux64(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, FR);
                 const double dis = hc * pg.An;
                 if (use) {
                     cE += (f1 & 1) + (f2 & 1);
@@ -187,20 +195,20 @@ __global__ __launch_bounds__(kBlock) void k_transport64(
         }
     }
     // update, post-update guard, ledger, photon budget
-    double red[2 * G];
+    double red[2 * GW];
     int gE = 0, gF = 0;
     if (active) {
         const double dtV = dtp[0] / rk[R_V];
         const double V = rk[R_V];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
+        for (int g = 0; g < GW; ++g) {
             double q0 = Ui[4 * g + 0] - dtV * acc[4 * g + 0];
             double q1 = Ui[4 * g + 1] - dtV * acc[4 * g + 1];
             double q2 = Ui[4 * g + 2] - dtV * acc[4 * g + 2];
             double q3 = Ui[4 * g + 3] - dtV * acc[4 * g + 3];
             const double Epre = q0;
             if (Uung) {
-                double *u = Uung + i * NQ + 4 * g;
+                double *u = Uung + i * NQ + 4 * (g0 + g);
                 u[0] = q0;
                 u[1] = q1;
                 u[2] = q2;
@@ -209,19 +217,22 @@ __global__ __launch_bounds__(kBlock) void k_transport64(
             const int f = guard64(q0, q1, q2, q3, c);
             gE += f & 1;
             gF += f >> 1;
-            double *o = Uout + i * NQ + 4 * g;
+            double *o = Uout + i * NQ + 4 * (g0 + g);
             o[0] = q0;
             o[1] = q1;
             o[2] = q2;
             o[3] = q3;
             red[g] = V * q0;
-            red[G + g] = (f & 1) ? -Epre * V : 0.0;
+            red[GW + g] = (f & 1) ? -Epre * V : 0.0;
         }
     } else {
 #pragma unroll
-        for (int p = 0; p < 2 * G; ++p) red[p] = 0.0;
+        for (int p = 0; p < 2 * GW; ++p) red[p] = 0.0;
     }
-    if (partials) block_reduce_store<2 * G>(red, partials + blk * 2 * G, smem);
+    // partials [nb][2G]: photon totals in columns 0..G-1, ledger in G..2G-1
+    if (partials)
+        block_reduce_store<2 * GW>(red, partials + blk * 2 * G, smem,
+                                   [&](int p) { return p < GW ? g0 + p : G + g0 + p - GW; });
     if (counts) {
         int64_t v0 = wave_sum_i64(cE), v1 = wave_sum_i64(cF), v2 = wave_sum_i64(gE),
                 v3 = wave_sum_i64(gF);
@@ -304,11 +315,20 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int64_t nb, int G,
     }
 }
 
+// Groups per wave of the FP64 transport (0: all G).  Measured on the 128^3
+// lattice with G = 3: all groups in one wave (about 250 VGPRs, 2 waves per
+// SIMD) beats one group per wave (164 VGPRs, 3 waves per SIMD, but the pair
+// geometry computed G times) by 12%.
+#ifndef RT_TRANSPORT_GW
+#define RT_TRANSPORT_GW 0
+#endif
+
 template <int G>
 void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double *Uout,
                         double *partials, int64_t *counts, double *Uung) {
+    constexpr int GW = (RT_TRANSPORT_GW == 0 || G % RT_TRANSPORT_GW != 0) ? G : RT_TRANSPORT_GW;
     const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
-    k_transport64<G><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
+    k_transport64<G, GW><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, ctx->stream>>>(
         n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
         ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung);
 }

@@ -56,13 +56,16 @@ _VP = ctypes.c_void_p
 
 
 def load_library() -> ctypes.CDLL:
-    """Load libgearrt.so (built by __graft_entry__.build()); raise if absent."""
+    """Load libgearrt.so (built by __graft_entry__.build()); raise if absent.
+    GEARRT_LIB names another build of the same library (for example one with
+    different tuning macros, see build.build(defines=...))."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
-    L = ctypes.CDLL(LIB_PATH)
+    path = os.environ.get("GEARRT_LIB", LIB_PATH)
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library {path} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(path)
     i32 = ctypes.c_int32
     L.rt_create.argtypes = [ctypes.POINTER(rt_params), ctypes.POINTER(_VP)]
     L.rt_destroy.argtypes = [_VP]
