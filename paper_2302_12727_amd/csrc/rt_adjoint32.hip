@@ -27,17 +27,22 @@ __global__ __launch_bounds__(kBlock) void k_adj_guard32(int64_t n, const float *
     for (int m = 0; m < 4; ++m) lam2[4 * t + m] = l[m];
 }
 
-template <int G>
+// A wave owns 64 particles and GW of the G groups (G/GW waves per 64
+// particles), as in the FP64 pair pass.
+template <int G, int GW>
 __global__ __launch_bounds__(kBlock) void k_adj_pair32(
     int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ geo,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_nbr, const float *__restrict__ UD,
     const float *__restrict__ lam2, const double *__restrict__ dtp, double c, double box,
     float *__restrict__ R) {
-    constexpr int NQ = 4 * G;
+    static_assert(G % GW == 0, "group slices must tile the groups");
+    constexpr int NS = G / GW, NQ = 4 * GW;
     __shared__ float stage[kBlock / 64][64 * kStage32];
-    const int64_t blk = xcd_block(nb);
-    if (blk >= nb) return;
+    const int64_t bg = xcd_block(nb * NS);
+    if (bg >= nb * NS) return;
+    const int64_t blk = bg / NS;
+    const int g0 = (int)(bg - blk * NS) * GW;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t i = blk * kBlock + threadIdx.x;
     const bool active = i < n;
@@ -59,15 +64,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair32(
     const float dtVk = (float)(dtp[0] / geo[(int64_t)kRec * ic + R_V]);
     float Ui[NQ], Di[NQ * 3], Li[NQ];
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const float *r = UD + (ic * G + g) * 16;
+    for (int g = 0; g < GW; ++g) {
+        const float *r = UD + (ic * G + g0 + g) * 16;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             Ui[4 * g + m] = r[m];
             Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
             Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
             Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
-            Li[4 * g + m] = lam2[(ic * G + g) * 4 + m];
+            Li[4 * g + m] = lam2[(ic * G + g0 + g) * 4 + m];
         }
     }
     Kahan aU[NQ];
@@ -93,15 +98,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair32(
             const float dtVl = dtf * rcp32(sb[lane * kStage32 + F_V]);
             const bool use = valid && pg.An > 0.0f;
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
+            for (int g = 0; g < GW; ++g) {
                 int64_t rowg[4];
 #pragma unroll
-                for (int m = 0; m < 4; ++m) rowg[m] = row[m] * G + g;
+                for (int m = 0; m < 4; ++m) rowg[m] = row[m] * G + g0 + g;
                 stage_rows32(UD, rowg, sb, lane);
                 float Rl[16];
 #pragma unroll
                 for (int q = 0; q < 16; ++q) Rl[q] = sb[lane * kStage32 + q];
-                const float4 Ll = *reinterpret_cast<const float4 *>(lam2 + ((int64_t)j * G + g) * 4);
+                const float4 Ll =
+                    *reinterpret_cast<const float4 *>(lam2 + ((int64_t)j * G + g0 + g) * 4);
                 float qLp[4], qRp[4], qL[4], qR[4];
                 bool own_slope[4];
 #pragma unroll
@@ -149,8 +155,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair32(
     const float b00 = Bk[0] * iV, b01 = Bk[1] * iV, b02 = Bk[2] * iV;
     const float b11 = Bk[3] * iV, b12 = Bk[4] * iV, b22 = Bk[5] * iV;
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        float *o = R + (i * G + g) * 16;
+    for (int g = 0; g < GW; ++g) {
+        float *o = R + (i * G + g0 + g) * 16;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int q = 4 * g + m;
@@ -197,7 +203,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad32(
             int64_t row[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) row[m] = __shfl(j, 16 * m + (lane >> 2), 64);
-            stage_rows32(geo32, row, sb, lane);
+            // all rows of this slot in flight before the first is staged
+            constexpr int GC = G < 6 ? G : 6;
+            float4 vp[4], vr[GC][4];
+            load_rows32(geo32, row, lane, vp);
+#pragma unroll
+            for (int g = 0; g < GC; ++g) {
+                int64_t rowg[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) rowg[m] = row[m] * G + g;
+                load_rows32(R, rowg, lane, vr[g]);
+            }
+            store_rows32(vp, sb, lane);
             const float *rl = sb + lane * kStage32;
             double xl[3];
             {
@@ -219,15 +236,27 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad32(
             sgy += wpi * sy;
             sgz += wpi * sz;
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                int64_t rowg[4];
+            for (int c0 = 0; c0 < G; c0 += GC) {
+                if (c0 > 0) {
 #pragma unroll
-                for (int m = 0; m < 4; ++m) rowg[m] = row[m] * G + g;
-                stage_rows32(R, rowg, sb, lane);
-                const float *Rl = sb + lane * kStage32;
+                    for (int g = 0; g < GC; ++g) {
+                        if (c0 + g >= G) break;
+                        int64_t rowg[4];
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    acc[4 * g + m].add(-wip * (Rl[4 + 3 * m] * sx + Rl[5 + 3 * m] * sy + Rl[6 + 3 * m] * sz));
+                        for (int m = 0; m < 4; ++m) rowg[m] = row[m] * G + c0 + g;
+                        load_rows32(R, rowg, lane, vr[g]);
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < GC; ++g) {
+                    if (c0 + g >= G) break;
+                    store_rows32(vr[g], sb, lane);
+                    const float *Rl = sb + lane * kStage32;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        acc[4 * (c0 + g) + m].add(
+                            -wip * (Rl[4 + 3 * m] * sx + Rl[5 + 3 * m] * sy + Rl[6 + 3 * m] * sz));
+                }
             }
         }
     }
@@ -243,13 +272,21 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad32(
     }
 }
 
+// Groups per wave of the pair pass (0: all G); one group per wave keeps the
+// pass at 135 VGPRs and 3 waves per SIMD for any G (all four groups of a
+// G = 4 set in one wave need 276 registers: 1 wave per SIMD).
+#ifndef RT_ADJ32_GW
+#define RT_ADJ32_GW 1
+#endif
+
 template <int G>
 void launch(rt_ctx *ctx, const float *UD, const float *Uung, const float *lam_next, float *lam2,
             float *R, float *lam, const double *dt) {
     const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
     hipStream_t st = ctx->stream;
+    constexpr int GW = (RT_ADJ32_GW == 0 || G % RT_ADJ32_GW != 0) ? G : RT_ADJ32_GW;
     k_adj_guard32<G><<<nblk(n * G), kBlock, 0, st>>>(n, Uung, lam_next, lam2, (float)ctx->p.c_red);
-    k_adj_pair32<G><<<(unsigned)xcd_grid(nb), kBlock, 0, st>>>(
+    k_adj_pair32<G, GW><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, st>>>(
         n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt,
         ctx->p.c_red, ctx->p.box, R);
     k_adj_grad32<G><<<(unsigned)xcd_grid(nb), kBlock, 0, st>>>(

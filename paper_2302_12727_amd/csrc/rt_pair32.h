@@ -84,14 +84,17 @@ __device__ __forceinline__ float minmod32(float a, float b) {
 }
 
 // Copy one 16-float (64-byte) row per lane's neighbour into the wave's stage
-// buffer: 4 loads, 4 lanes per row, 16 rows per load.
-__device__ __forceinline__ void stage_rows32(const float *__restrict__ src,
-                                             const int64_t (&row)[4], float *sb, int lane) {
-    const int piece = lane & 3, slot = lane >> 2;
-    float4 v[4];
+// buffer: 4 loads, 4 lanes per row, 16 rows per load.  Load and store halves
+// are separate so that several rows can be in flight before the first store.
+__device__ __forceinline__ void load_rows32(const float *__restrict__ src, const int64_t (&row)[4],
+                                            int lane, float4 (&v)[4]) {
+    const int piece = lane & 3;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
         v[m] = *reinterpret_cast<const float4 *>(src + 16 * row[m] + 4 * piece);
+}
+__device__ __forceinline__ void store_rows32(const float4 (&v)[4], float *sb, int lane) {
+    const int piece = lane & 3, slot = lane >> 2;
     wave_lds_sync32();
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -103,7 +106,12 @@ __device__ __forceinline__ void stage_rows32(const float *__restrict__ src,
     }
     wave_lds_sync32();
 }
-
+__device__ __forceinline__ void stage_rows32(const float *__restrict__ src,
+                                             const int64_t (&row)[4], float *sb, int lane) {
+    float4 v[4];
+    load_rows32(src, row, lane, v);
+    store_rows32(v, sb, lane);
+}
 
 // VJP of guard32 at its input state q (see guard64_vjp).
 __device__ __forceinline__ void guard32_vjp(const float q[4], float lam[4], float c) {
