@@ -98,8 +98,10 @@ __global__ __launch_bounds__(kBlock) void k_gradient64(
 // the same particles): fewer groups per wave keep less state in registers
 // and so more waves resident, at the price of recomputing the pair geometry
 // once per group slice.
+// The compiler is held to the 256 registers of 2 waves per SIMD: this kernel
+// sits at about 250 VGPRs, and at 1 wave per SIMD it runs 1.6x slower.
 template <int G, int GW>
-__global__ __launch_bounds__(kBlock) void k_transport64(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_transport64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
     const double *__restrict__ UD, const double *__restrict__ dtp, double c, double box,
@@ -315,18 +317,23 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int64_t nb, int G,
     }
 }
 
-// Groups per wave of the FP64 transport (0: all G).  Measured on the 128^3
-// lattice with G = 3: all groups in one wave (about 250 VGPRs, 2 waves per
-// SIMD) beats one group per wave (164 VGPRs, 3 waves per SIMD, but the pair
-// geometry computed G times) by 12%.
+// Groups per wave of the FP64 transport (0: the default slice below).  All
+// groups in one wave compute the pair geometry once; each group costs about
+// 40 registers, and with more than 3 groups a wave no longer fits the 256
+// registers of 2 waves per SIMD (G = 3: 254 VGPRs), so larger G is cut into
+// slices of 2 groups (or 3, or one group per wave as the last resort).
 #ifndef RT_TRANSPORT_GW
 #define RT_TRANSPORT_GW 0
 #endif
+constexpr int transport_slice(int G) {
+    return G <= 3 ? G : (G % 2 == 0 ? 2 : (G % 3 == 0 ? 3 : 1));
+}
 
 template <int G>
 void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double *Uout,
                         double *partials, int64_t *counts, double *Uung) {
-    constexpr int GW = (RT_TRANSPORT_GW == 0 || G % RT_TRANSPORT_GW != 0) ? G : RT_TRANSPORT_GW;
+    constexpr int GW =
+        (RT_TRANSPORT_GW == 0 || G % RT_TRANSPORT_GW != 0) ? transport_slice(G) : RT_TRANSPORT_GW;
     const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
     k_transport64<G, GW><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, ctx->stream>>>(
         n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
