@@ -18,7 +18,6 @@ per-kernel times.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -45,20 +44,6 @@ def transport_bytes_per_particle(G: int, elem: int) -> int:
     (96 B used of its 128-B line), gradient record read (state 4 G and
     gradients 12 G elements), U_out written (4 G elements)."""
     return 96 + (16 + 4) * G * elem
-
-
-def src_sha(*paths: str) -> str:
-    h = hashlib.sha256()
-    for p in paths:
-        h.update(open(p, "rb").read())
-    return h.hexdigest()[:16]
-
-
-def transport_sources(precision: str):
-    """Sources that define the transport kernel of one precision."""
-    d = os.path.join(ROOT, "paper_2302_12727_amd", "csrc")
-    names = (["rt_step.hip", "rt_pair.h"] if precision == "fp64" else ["rt_step32.hip", "rt_pair32.h"])
-    return [os.path.join(d, f) for f in names + ["rt_internal.h"]]
 
 
 def log(msg: str):
@@ -325,7 +310,8 @@ def main():
     tf = os.path.join(ROOT, "profiles", f"transport_traffic_{w.name}_{args.precision}.json")
     if os.path.exists(tf):
         rec = json.load(open(tf))
-        if rec.get("source_sha") == src_sha(*transport_sources(args.precision)):
+        from paper_2302_12727_amd.traffic import source_sha, transport_sources
+        if rec.get("source_sha") == source_sha(*transport_sources(args.precision)):
             traffic = rec.get("hbm_bytes_per_launch")
     label = ("2^21-particle 128^3 jittered lattice, 3 groups, 16 sources, c=1, CFL 0.9"
              if args.config == 1 else w.name)
