@@ -334,6 +334,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "transport", "achieved": achieved / 1e12,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic,
+                     "traffic_TBps": (traffic / tr_avg / 1e12) if traffic else None,
                      "flops_per_pair": transport_flops_per_pair(G),
                      "algorithmic_bytes_per_launch": transport_bytes_per_particle(G, elem) * w.n,
                      "hbm_frac_at_algorithmic_bytes":
