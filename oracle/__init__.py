@@ -115,6 +115,16 @@ def lib():
         L.orc_dt.argtypes = [ctypes.c_int64, _d, ctypes.c_double, ctypes.c_double]
         L.orc_num_threads.restype = ctypes.c_int32
         L.orc_num_threads.argtypes = []
+        L.orc_bins.restype = None
+        L.orc_bins.argtypes = [ctypes.c_int64, _d, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_int32, _i64, _i64, _i32]
+        L.orc_inject_binned.restype = None
+        L.orc_inject_binned.argtypes = [ctypes.c_int64, ctypes.c_int32, _i64, _i64, _d, _d, _d,
+                                        ctypes.c_double, _i32, ctypes.c_int64, _d]
+        L.orc_transport_binned.restype = None
+        L.orc_transport_binned.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d, _d, _d,
+                                           _d, _i64, _i64, ctypes.c_double, ctypes.c_double,
+                                           _i32, ctypes.c_int64, _d, _d, _d, _d, _i64, _d]
         _lib = L
     return _lib
 
@@ -457,6 +467,58 @@ def run(geom: Geometry, srcs: Optional[Sources], U0: np.ndarray, L, steps: int,
         if keep:
             states.append(U.copy())
     return U, {"counts": counts, "ledger": ledger, "states": states}
+
+
+# individual time steps (Part II "Individual time steps", Part III
+# eq:transport-update-explicit with min{dt_k, dt_l}, factor-4 limiter)
+
+def time_bins(geom: Geometry, nmax: int) -> np.ndarray:
+    """b_i: dt_i = dt_min 2^b_i, the largest n <= nmax with dt_min 2^n within
+    particle i's own CFL step, lowered to |b_k - b_l| <= 2 for interacting
+    pairs.  dt_min = geom.dt (the smallest CFL step)."""
+    b = np.zeros(geom.n, dtype=np.int32)
+    lib().orc_bins(geom.n, _p(geom.V), geom.cfl, geom.c, geom.dt, int(nmax),
+                   _p(geom.sptr, _i64), _p(geom.sidx, _i64), _p(b, _i32))
+    return b
+
+
+def active(bins: np.ndarray, tick: int) -> np.ndarray:
+    """Particles that end a step at the end of tick `tick`."""
+    return ((tick + 1) % (np.int64(1) << bins.astype(np.int64))) == 0
+
+
+def run_binned(geom: Geometry, srcs: Optional[Sources], U0: np.ndarray, L, ticks: int,
+               bins: np.ndarray, t0: int = 0, dU=None, acc=None):
+    """`ticks` ticks of the individual-time-step scheme from tick t0.  Every
+    particle starts with the gradient of U0 (unless dU is given); in tick t the
+    particles that end a step inject (with their own dt), recompute their
+    gradient, and apply their flux sums, while every pair whose smaller bin ends
+    a step exchanges dt_kl |A| Phi.  Returns (U, info) with info["acc"] (the
+    pending flux sums) and info["dU"] (the stored gradients)."""
+    U = _f64(U0).copy()
+    n, G = U.shape[0], U.shape[1]
+    bins = np.ascontiguousarray(bins, dtype=np.int32)
+    dU = gradient(geom, U) if dU is None else _f64(dU).copy()
+    acc = np.zeros_like(U) if acc is None else _f64(acc).copy()
+    counts = np.zeros(4, dtype=np.int64)
+    ledger = np.zeros(G)
+    Lm = _f64(L) if (srcs is not None and srcs.src.size) else None
+    for t in range(t0, t0 + ticks):
+        act = active(bins, t)
+        if Lm is not None:
+            lib().orc_inject_binned(srcs.src.size, G, _p(srcs.src, _i64), _p(srcs.gas, _i64),
+                                    _p(srcs.xi), _p(geom.V), _p(Lm), geom.dt, _p(bins, _i32),
+                                    t, _p(U))
+        if act.any():
+            dU[act] = gradient(geom, U)[act]
+        out = np.zeros_like(U)
+        lib().orc_transport_binned(n, G, _p(geom.x), _p(geom.h), _p(geom.H), _p(geom.V),
+                                   _p(_f64(geom.B)), _p(geom.box), _p(geom.sptr, _i64),
+                                   _p(geom.sidx, _i64), geom.c, geom.dt, _p(bins, _i32), t,
+                                   _p(U), _p(dU), _p(acc), _p(out), _p(counts, _i64),
+                                   _p(ledger))
+        U = out
+    return U, {"acc": acc, "dU": dU, "counts": counts, "ledger": ledger}
 
 
 def num_threads() -> int:

@@ -542,6 +542,136 @@ double orc_dt(int64_t n, const double *V, double cfl, double c)
     return cfl * m / c;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Individual time steps (Part II "Individual time steps",
+ * eq:meshless-explicit-individual-timesteps; Part III eq:transport-update-
+ * explicit, whose exchanges are time integrated with min{dt_k, dt_l}; the
+ * limiter of Part III "Dynamic Sub-Cycling": interacting particles differ by at
+ * most a factor 4 in time step).
+ *
+ * Time bins: dt_i = dtmin 2^b_i, b_i the largest n <= nmax with
+ * dtmin 2^n <= C_cfl dx_i / c (eq:rt-cfl), then lowered until every
+ * interacting pair has |b_k - b_l| <= 2 (the greatest such assignment).     */
+void orc_bins(int64_t n, const double *V, double cfl, double c, double dtmin, int32_t nmax,
+              const int64_t *sptr, const int64_t *sidx, int32_t *bin)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double tau = cfl * cbrt(V[i] / (4.0 * ORC_PI / 3.0)) / c;
+        int32_t b = 0;
+        while (b < nmax && dtmin * ldexp(1.0, b + 1) <= tau) ++b;
+        bin[i] = b;
+    }
+    int changed = 1;
+    while (changed) {
+        changed = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t m = bin[i];
+            for (int64_t e = sptr[i]; e < sptr[i + 1]; ++e) {
+                int32_t lim = bin[sidx[e]] + 2;
+                if (lim < m) m = lim;
+            }
+            if (m < bin[i]) { bin[i] = m; changed = 1; }
+        }
+    }
+}
+
+/* Particle i ends a step at the end of tick t (time (t+1) dtmin) when
+ * (t+1) is a multiple of 2^b_i.                                             */
+static int orc_active(int64_t t, int32_t b) { return ((t + 1) % ((int64_t)1 << b)) == 0; }
+
+/* Injection for the particles that end a step in tick t, each with its own
+ * dt_g: E_g += dt_g sum_s xi_sg L_s / V_g.                                  */
+void orc_inject_binned(int64_t nent, int32_t G, const int64_t *src, const int64_t *gas,
+                       const double *xi, const double *V, const double *L, double dtmin,
+                       const int32_t *bin, int64_t t, double *U)
+{
+    for (int64_t e = 0; e < nent; ++e) {
+        int64_t s = src[e], g = gas[e];
+        if (!orc_active(t, bin[g])) continue;
+        double dtg = dtmin * ldexp(1.0, bin[g]);
+        for (int32_t grp = 0; grp < G; ++grp)
+            U[(g * G + grp) * 4] += dtg * xi[e] * L[s * G + grp] / V[g];
+    }
+}
+
+/* Transport of tick t.  Every pair whose smaller bin ends a step in this tick
+ * exchanges dt_kl |A| Phi_kl, dt_kl = dtmin 2^min(b_k, b_l), computed from the
+ * current states U and the stored gradients dU (as orc_transport), into the
+ * flux sums acc of both particles (each particle sums its own side).  A
+ * particle that ends a step applies U_k - acc_k / V_k, is guarded as in
+ * orc_transport, and clears acc_k; the others keep accumulating.  Uout gets
+ * the new states of the active particles and U of the others.              */
+void orc_transport_binned(int64_t n, int32_t G, const double *x, const double *h,
+                          const double *H, const double *V, const double *B,
+                          const double *box, const int64_t *sptr, const int64_t *sidx,
+                          double c, double dtmin, const int32_t *bin, int64_t t,
+                          const double *U, const double *dU, double *acc, double *Uout,
+                          int64_t *counts, double *ledger)
+{
+    const int64_t nq = 4 * (int64_t)G;
+    int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+    double *led = (double *)calloc((size_t)n * (size_t)G, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : c0, c1, c2, c3)
+    for (int64_t k = 0; k < n; ++k) {
+        double *ak = acc + k * nq;
+        for (int64_t e = sptr[k]; e < sptr[k + 1]; ++e) {
+            int64_t l = sidx[e];
+            int32_t bmin = bin[k] < bin[l] ? bin[k] : bin[l];
+            if (!orc_active(t, bmin)) continue;
+            double dtkl = dtmin * ldexp(1.0, bmin);
+            double A[3], s[3];
+            orc_surface(x + 3 * k, x + 3 * l, H[k], H[l], V[k], V[l], B + 9 * k,
+                        B + 9 * l, box, A);
+            double An = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+            if (!(An > 0.0)) continue;
+            double nh[3] = {A[0] / An, A[1] / An, A[2] / An};
+            sep(x + 3 * k, x + 3 * l, box, s);
+            double wk = h[k] / (h[k] + h[l]);
+            double wl = h[l] / (h[k] + h[l]);
+            for (int32_t g = 0; g < G; ++g) {
+                double qL[4], qR[4], phi[4];
+                for (int m = 0; m < 4; ++m) {
+                    const double *gk = dU + (k * nq + 4 * g + m) * 3;
+                    const double *gl = dU + (l * nq + 4 * g + m) * 3;
+                    double dk = gk[0] * s[0] + gk[1] * s[1] + gk[2] * s[2];
+                    double dl = gl[0] * s[0] + gl[1] * s[1] + gl[2] * s[2];
+                    double mm = orc_minmod(dk, dl);
+                    qL[m] = U[k * nq + 4 * g + m] + wk * mm;
+                    qR[m] = U[l * nq + 4 * g + m] - wl * mm;
+                }
+                int fl = guard_state(qL, c), fr = guard_state(qR, c);
+                c0 += (fl & 1) + (fr & 1);
+                c1 += ((fl >> 1) & 1) + ((fr >> 1) & 1);
+                orc_glf(qL, qR, nh, c, phi);
+                for (int m = 0; m < 4; ++m) ak[4 * g + m] += dtkl * An * phi[m];
+            }
+        }
+        for (int32_t g = 0; g < G; ++g) {
+            double q[4];
+            if (!orc_active(t, bin[k])) {
+                for (int m = 0; m < 4; ++m) Uout[k * nq + 4 * g + m] = U[k * nq + 4 * g + m];
+                continue;
+            }
+            for (int m = 0; m < 4; ++m) q[m] = U[k * nq + 4 * g + m] - ak[4 * g + m] / V[k];
+            double Epre = q[0];
+            int f = guard_state(q, c);
+            if (f & 1) { c2++; led[k * G + g] = -Epre * V[k]; }
+            c3 += (f >> 1) & 1;
+            for (int m = 0; m < 4; ++m) {
+                Uout[k * nq + 4 * g + m] = q[m];
+                ak[4 * g + m] = 0.0;
+            }
+        }
+    }
+    counts[0] += c0; counts[1] += c1; counts[2] += c2; counts[3] += c3;
+    for (int32_t g = 0; g < G; ++g) {
+        double s = 0.0;
+        for (int64_t k = 0; k < n; ++k) s += led[k * G + g];
+        ledger[g] += s;
+    }
+    free(led);
+}
+
 int32_t orc_num_threads(void)
 {
 #ifdef _OPENMP
