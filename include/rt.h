@@ -143,6 +143,45 @@ rt_status rt_transport(rt_ctx *ctx, const void *UD, const double *dt, void *U_ou
 /* Q_g = sum_k V_k E_kg of U, [G] out (FP64, compensated, deterministic). */
 rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q);
 
+/* Individual power-of-two time steps (Part II "Individual time steps",
+ * eq:meshless-explicit-individual-timesteps; Part III eq:transport-update-
+ * explicit with min{dt_k, dt_l}; the factor-4 limiter of Part III "Dynamic
+ * Sub-Cycling").  FP64 contexts only.
+ *
+ * rt_time_bins: particle i gets dt_i = dt 2^b_i, dt the step rt_build_cells
+ * returned (the smallest CFL step), b_i the largest n <= max_bin (0 .. 30)
+ * with dt 2^n <= C_cfl dx_i / c, then lowered until every interacting pair is
+ * at most 2 bins apart.  The bins are kept in the context (all 0 after
+ * rt_build_cells: the global step).
+ *   bins        [n] int32 out (Morton order) or NULL.
+ *   cycle_ticks [host] out or NULL: 2^max_i b_i, the ticks after which every
+ *               particle has ended a step at the same time.
+ * Synchronous (returns when the bins are set). */
+rt_status rt_time_bins(rt_ctx *ctx, int32_t max_bin, int32_t *bins, int64_t *cycle_ticks);
+
+/* One tick t (t = 0, 1, ...) of the individual-time-step scheme: the time
+ * advances by dt; particle i ends a step at the end of tick t when (t + 1) is a
+ * multiple of 2^b_i.  In the tick, the particles that end a step inject with
+ * their own dt_i (sources set) and recompute their gradient record from the
+ * current states; every pair whose smaller bin ends a step exchanges
+ * dt 2^min(b_k, b_l) |A| Phi_kl (the GLF flux of rt_transport) into the flux
+ * sums of both particles; the particles that end a step apply
+ * U - (flux sum) / V, guard the result as rt_transport does, and clear their
+ * sums.
+ *   U    [n][G][4] double in/out: the states.
+ *   L    [S][G] luminosities (NULL without sources).
+ *   UD   [n][G][16] double in/out, 16-byte aligned: the stored gradient
+ *        records.  Before tick 0 fill it with rt_gradient of the initial U;
+ *        keep it between ticks.
+ *   acc  [n][G][4] double in/out: the pending flux sums (zero before tick 0;
+ *        all zero again after a tick where every particle ends a step).
+ *   photon_total [G] out or NULL: sum_k V_k E_k of the states after the tick
+ *        (the pending sums are not in it: with them, sum_k (V_k E_k - acc_k,E)
+ *        is conserved up to injection and the ledger).
+ *   counts, ledger: as rt_transport, accumulated. */
+rt_status rt_tick(rt_ctx *ctx, double *U, const double *L, int64_t tick, double *UD,
+                  double *acc, double *photon_total, int64_t *counts, double *ledger);
+
 /* Adjoint (vector-Jacobian product) of one full step
  *   U_next = transport(inject(U_pre, L), gradient(inject(U_pre, L)))
  * with respect to U_pre and L.  (The thesis has no adjoint; this is the exact

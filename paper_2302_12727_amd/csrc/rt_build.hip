@@ -662,6 +662,7 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     rt_free(sort_tmp);
     if ((rs = rt_ensure_partials(ctx)) != RT_OK) return rs;
     ctx->built = 1;
+    ctx->bin_top = -1;   // the records were rewritten with all time bins 0
     return RT_OK;
 fail:
     (void)hipStreamSynchronize(st);

@@ -101,6 +101,7 @@ struct rt_ctx {
 
     int64_t device_bytes = 0;
     int32_t h_iter_max = 0;
+    int32_t bin_top = -1;        // largest time bin after rt_time_bins (-1: none)
 
     // timing: event pairs recorded around launches while timing is on
     int timing = 0;
@@ -268,6 +269,13 @@ void rt_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *Uout,
 void rt_adjoint32(rt_ctx *ctx, const float *UD, const float *Uung, const float *lam_next,
                   float *lam2, float *R, float *lam, const double *dt);
 rt_status rt_ensure_partials(rt_ctx *ctx);
+
+// individual time steps (rt_bins.hip; the binned gradient and transport in rt_step.hip)
+rt_status rt_time_bins_impl(rt_ctx *ctx, int32_t max_bin, int32_t *bins, int64_t *cycle);
+rt_status rt_tick_impl(rt_ctx *ctx, double *U, const double *L, int64_t tick, double *UD,
+                       double *acc, double *Q, int64_t *counts, double *ledger);
+rt_status rt_tick_step_impl(rt_ctx *ctx, double *U, double *UD, const double *dt, int64_t tick,
+                            double *accm, double *Q, int64_t *counts, double *ledger);
 
 // adjoint (rt_adjoint.hip)
 rt_status rt_adjoint_impl(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,

@@ -37,16 +37,20 @@ __global__ void k_inject(int32_t ngas, int G, const int32_t *__restrict__ gptr,
 // Gradient (eq:gradient):  grad q_i = sum_j (q_j - q_i) psi~_j(x_i)
 //   = S_i^{-1} sum_j (q_j - q_i) w(r_ij / H_i) s_ij   (the kernel normalisation
 // and V_i cancel against B_i, see the geometry record).
-template <int G>
+// BIN: only the particles that end a step in tick `tick` (time bin in slot 12
+// of the geometry record) recompute their gradient record.
+template <int G, bool BIN = false>
 __global__ __launch_bounds__(kBlock) void k_gradient64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const double *__restrict__ xs,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_gath, const double *__restrict__ U, double *__restrict__ UD,
-    double box) {
+    double box, int64_t tick = 0) {
     const int64_t blk = xcd_block(nb);
     if (blk >= nb) return;
     const int64_t i = blk * kBlock + threadIdx.x;
     if (i >= n) return;
+    if (BIN && ((tick + 1) & ((int64_t(1) << (int32_t)geo[(int64_t)kRec * i + 12]) - 1)) != 0)
+        return;
     constexpr int NQ = 4 * G;
     const double ibox = 1.0 / box;
     const double *rec = geo + (int64_t)kRec * i;
@@ -100,13 +104,21 @@ __global__ __launch_bounds__(kBlock) void k_gradient64(
 // once per group slice.
 // The compiler is held to the 256 registers of 2 waves per SIMD: this kernel
 // sits at about 250 VGPRs, and at 1 wave per SIMD it runs 1.6x slower.
-template <int G, int GW>
+//
+// BIN: one tick of the individual-time-step scheme (time bins in slot 12 of
+// the geometry records, the smallest bin of each particle's neighbourhood in
+// slot 13): only pairs whose smaller bin ends a step in this tick contribute,
+// each with dt 2^min(b_k, b_l); the sums go to the pending flux sums accm, and
+// the particles that end a step apply and clear theirs (Part III
+// eq:transport-update-explicit with min{dt_k, dt_l}).
+template <int G, int GW, bool BIN = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_transport64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
     const double *__restrict__ UD, const double *__restrict__ dtp, double c, double box,
     double *__restrict__ Uout, double *__restrict__ partials,
-    unsigned long long *__restrict__ counts, double *__restrict__ Uung) {
+    unsigned long long *__restrict__ counts, double *__restrict__ Uung, int64_t tick = 0,
+    double *__restrict__ accm = nullptr) {
     static_assert(G % GW == 0, "group slices must tile the groups");
     constexpr int NS = G / GW, NQ = 4 * G;
     __shared__ double stage[kBlock / 64][64 * kStage];
@@ -144,11 +156,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
 #pragma unroll
     for (int q = 0; q < 4 * GW; ++q) acc[q] = 0.0;
     int cE = 0, cF = 0;
+    // time bins: this particle ends a step in this tick (ends), or some pair of
+    // its neighbourhood does (touched)
+    const int64_t t1 = tick + 1;
+    const int32_t bk = BIN ? (int32_t)rk[12] : 0;
+    const bool ends = !BIN || (t1 & ((int64_t(1) << bk) - 1)) == 0;
+    const bool touched = !BIN || (t1 & ((int64_t(1) << (int32_t)rk[13]) - 1)) == 0;
 
     if (wave_live) {
         const int64_t base = wave_base[w] + lane;
-        const int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
-        const int32_t nn = active ? n_nbr[i] : 0;
+        int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
+        const int32_t nn = (active && touched) ? n_nbr[i] : 0;
+        if (BIN && __ballot(nn > 0) == 0) kmax = 0;   // no due pair in this wave
         for (int32_t k = 0; k < kmax; ++k) {
             const bool valid = k < nn;
             const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
@@ -162,7 +181,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
             for (int q = 0; q < 12; ++q) rl[q] = sb[lane * kStage + q];
             PairGeo pg;
             pair_geometry64(rk, rl, box, ibox, pg);
-            const bool use = valid && pg.An > 0.0;
+            bool use = valid && pg.An > 0.0;
+            double wkl = 1.0;                   // time integration of this exchange
+            if (BIN) {
+                const int32_t bl = (int32_t)sb[lane * kStage + 12];
+                const int32_t bmin = bk < bl ? bk : bl;
+                use = use && (t1 & ((int64_t(1) << bmin) - 1)) == 0;
+                wkl = ldexp(dtp[0], bmin);
+            }
 #pragma unroll
             for (int g = 0; g < GW; ++g) {
                 int64_t rowg[8];
@@ -191,7 +217,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                     cF += (f1 >> 1) + (f2 >> 1);
 #pragma unroll
                     for (int m = 0; m < 4; ++m)
-                        acc[4 * g + m] += 0.5 * (FL[m] + FR[m]) - dis * (qR[m] - qL[m]);
+                        acc[4 * g + m] += wkl * (0.5 * (FL[m] + FR[m]) - dis * (qR[m] - qL[m]));
                 }
             }
         }
@@ -199,9 +225,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     // update, post-update guard, ledger, photon budget
     double red[2 * GW];
     int gE = 0, gF = 0;
-    if (active) {
-        const double dtV = dtp[0] / rk[R_V];
+    if (BIN && active && !ends) {
+        // no update in this tick: keep the pending sums, count the current state
         const double V = rk[R_V];
+#pragma unroll
+        for (int g = 0; g < GW; ++g) {
+            if (touched) {
+                double *a = accm + (i * G + g0 + g) * 4;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) a[m] += acc[4 * g + m];
+            }
+            red[g] = V * Ui[4 * g];
+            red[GW + g] = 0.0;
+        }
+    } else if (active) {
+        const double V = rk[R_V];
+        // the update: U - dt/V sum (global step), or U - (pending + this tick)/V
+        const double dtV = BIN ? 1.0 / V : dtp[0] / V;
+        if (BIN) {
+#pragma unroll
+            for (int g = 0; g < GW; ++g) {
+                double *a = accm + (i * G + g0 + g) * 4;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    acc[4 * g + m] += a[m];
+                    a[m] = 0.0;
+                }
+            }
+        }
 #pragma unroll
         for (int g = 0; g < GW; ++g) {
             double q0 = Ui[4 * g + 0] - dtV * acc[4 * g + 0];
@@ -347,6 +398,18 @@ void launch_gradient64(rt_ctx *ctx, const double *U, double *UD) {
         n, nb, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box);
 }
 
+template <int G>
+void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, double *Uout,
+                   double *partials, int64_t *counts, int64_t tick, double *accm) {
+    const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
+    k_gradient64<G, true><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
+        n, nb, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box, tick);
+    constexpr int GW = transport_slice(G);
+    k_transport64<G, GW, true><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, ctx->stream>>>(
+        n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
+        ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, tick, accm);
+}
+
 #define RT_DISPATCH_G(G_, FN, ...)                                  \
     switch (G_) {                                                   \
         case 1: FN<1>(__VA_ARGS__); break;                          \
@@ -413,6 +476,23 @@ rt_status rt_transport_impl(rt_ctx *ctx, const void *UD, const double *dt, void 
         rt_transport32(ctx, (const float *)UD, dt, (float *)U_out, part, counts, (float *)Uung);
     }
     rt_timer_end(ctx, "transport");
+    RT_HIP(hipGetLastError());
+    if (part) {
+        k_finalize<<<1, kBlock, 0, ctx->stream>>>(nb, ctx->p.groups, part, Q, ledger);
+        RT_HIP(hipGetLastError());
+    }
+    return RT_OK;
+}
+
+// Gradient and transport of one tick of the individual-time-step scheme
+// (FP64; injection and the refresh of the stored states are in rt_bins.hip).
+rt_status rt_tick_step_impl(rt_ctx *ctx, double *U, double *UD, const double *dt, int64_t tick,
+                            double *accm, double *Q, int64_t *counts, double *ledger) {
+    const int64_t nb = (ctx->p.n + kBlock - 1) / kBlock;
+    double *part = (Q || ledger) ? ctx->partials : nullptr;
+    rt_timer_begin(ctx, "tick");
+    RT_DISPATCH_G(ctx->p.groups, launch_tick64, ctx, U, UD, dt, U, part, counts, tick, accm);
+    rt_timer_end(ctx, "tick");
     RT_HIP(hipGetLastError());
     if (part) {
         k_finalize<<<1, kBlock, 0, ctx->stream>>>(nb, ctx->p.groups, part, Q, ledger);

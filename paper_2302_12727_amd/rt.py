@@ -28,7 +28,7 @@ ETA = 1.2348
 EXPORTED = ["rt_create", "rt_destroy", "rt_last_error", "rt_set_stream", "rt_build_cells",
             "rt_set_sources", "rt_inject", "rt_gradient", "rt_transport", "rt_photon_total",
             "rt_adjoint", "rt_sync", "rt_get_stats", "rt_get_geometry", "rt_get_neighbours",
-            "rt_get_sources", "rt_timing", "rt_get_timing"]
+            "rt_get_sources", "rt_timing", "rt_get_timing", "rt_time_bins", "rt_tick"]
 
 
 class RTError(RuntimeError):
@@ -80,6 +80,8 @@ def load_library() -> ctypes.CDLL:
     L.rt_transport.argtypes = [_VP] * 8
     L.rt_photon_total.argtypes = [_VP] * 3
     L.rt_adjoint.argtypes = [_VP] * 9
+    L.rt_time_bins.argtypes = [_VP, i32, _VP, ctypes.POINTER(ctypes.c_int64)]
+    L.rt_tick.argtypes = [_VP, _VP, _VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP]
     L.rt_sync.argtypes = [_VP]
     L.rt_get_stats.argtypes = [_VP, ctypes.POINTER(rt_stats)]
     L.rt_get_geometry.argtypes = [_VP] * 4
@@ -225,6 +227,35 @@ class RT:
                                         _ptr(photon_total), _ptr(counts), _ptr(ledger),
                                         _ptr(U_unguarded)))
         return U_out
+
+    def rt_time_bins(self, max_bin: int, bins: Optional[torch.Tensor] = None):
+        """Individual time bins (dt_i = dt 2^b_i, limited to 2 bins between
+        interacting particles).  Returns (bins [n] int32, ticks per full cycle)."""
+        if bins is None:
+            bins = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        _need(bins, "bins", torch.int32, (self.n,))
+        cyc = ctypes.c_int64(0)
+        self._bind_stream()
+        self._check(self.L.rt_time_bins(self.ctx, int(max_bin), _ptr(bins), ctypes.byref(cyc)))
+        return bins, int(cyc.value)
+
+    def rt_tick(self, U, L, tick: int, UD, acc, photon_total=None, counts=None, ledger=None):
+        """One tick of the individual-time-step scheme (U, UD, acc in/out)."""
+        _need(U, "U", torch.float64, (self.n, self.G, 4))
+        _need(UD, "UD", torch.float64, (self.n, self.G, 16))
+        _need(acc, "acc", torch.float64, (self.n, self.G, 4))
+        if L is not None:
+            _need(L, "L", torch.float64, (self.S, self.G))
+        if photon_total is not None:
+            _need(photon_total, "photon_total", torch.float64, (self.G,))
+        if counts is not None:
+            _need(counts, "counts", torch.int64, (4,))
+        if ledger is not None:
+            _need(ledger, "ledger", torch.float64, (self.G,))
+        self._bind_stream()
+        self._check(self.L.rt_tick(self.ctx, _ptr(U), _ptr(L), int(tick), _ptr(UD), _ptr(acc),
+                                   _ptr(photon_total), _ptr(counts), _ptr(ledger)))
+        return U
 
     def rt_photon_total(self, U: torch.Tensor) -> torch.Tensor:
         _need(U, "U", self.sdtype, (self.n, self.G, 4))
