@@ -185,6 +185,61 @@ def compare_precisions(w, dev):
     return res
 
 
+def compare_time_bins(w, dev, max_bin: int = 8, cycles: int = 2):
+    """Individual time bins against the global step on workload w: the same
+    number of ticks (the same simulated time) both ways, wall time and
+    pair interactions per second (counting, with bins, only the pairs due in
+    each tick), and how far the two states are apart at the end."""
+    import numpy as np
+    import torch
+    from paper_2302_12727_amd import RT
+
+    rt = RT(w.n, w.groups, cfl=w.cfl, c_red=w.c_red, device=dev)
+    perm, *_ = rt.rt_build_cells(torch.from_numpy(w.x).to(dev))
+    if w.xs.shape[0]:
+        rt.rt_set_sources(torch.from_numpy(w.xs).to(dev))
+    rt.rt_sync()
+    p = perm.cpu().numpy()
+    L = torch.from_numpy(w.L).to(dev) if w.xs.shape[0] else None
+    U0 = torch.from_numpy(np.ascontiguousarray(w.U0[p])).to(dev)
+    ptr, idx = rt.rt_get_neighbours()
+    ptr, idx = ptr.cpu().numpy(), idx.cpu().numpy()
+    rows = np.repeat(np.arange(w.n), np.diff(ptr))
+    res = {"workload": w.name, "n": w.n, "groups": w.groups, "max_bin": max_bin}
+
+    def run(ticks):
+        U = U0.clone()
+        UD = rt.rt_gradient(U)
+        acc = torch.zeros_like(U)
+        rt.rt_tick(U, L, 0, UD, acc)              # warm-up tick, then restart
+        U = U0.clone()
+        UD = rt.rt_gradient(U)
+        acc.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(ticks):
+            rt.rt_tick(U, L, t, UD, acc)
+        torch.cuda.synchronize()
+        return U, time.perf_counter() - t0
+
+    bins, cycle = rt.rt_time_bins(max_bin)
+    b = bins.cpu().numpy().astype(np.int64)
+    ticks = cycles * cycle
+    Ub, tb = run(ticks)
+    # unordered pairs due over the run: a pair is due every 2^min(b_k, b_l) ticks
+    due = float((ticks >> np.minimum(b[rows], b[idx])).sum()) / 2.0
+    rt.rt_time_bins(0)
+    Ug, tg = run(ticks)
+    pairs = float(rows.size) / 2.0
+    d = (Ub - Ug)[..., 0].abs().max().item() / Ug[..., 0].abs().max().item()
+    res.update({"bin_counts": np.bincount(b).tolist(), "cycle_ticks": cycle, "ticks": ticks,
+                "binned_ms": tb * 1e3, "global_ms": tg * 1e3, "speedup": tg / tb,
+                "binned_due_pairs_per_s": due / tb, "global_pairs_per_s": pairs * ticks / tg,
+                "due_pair_fraction": due / (pairs * ticks),
+                "E_difference_binned_vs_global": d})
+    return res
+
+
 def large_adjoint(dev):
     """2^24 Plummer mix, 4 groups, 256 sources, 50 steps, checkpoints every
     10: the FP32C rollout and its adjoint (time ratio, peak HBM), and its
@@ -362,6 +417,8 @@ def main():
         out["adjoint"] = ad
         torch.cuda.empty_cache()
         out["plummer_fp32c_vs_fp64"] = compare_precisions(workloads.config(2), dev)
+        torch.cuda.empty_cache()
+        out["plummer_time_bins"] = compare_time_bins(workloads.config(2), dev)
         torch.cuda.empty_cache()
     if args.large_adjoint:
         out["large_adjoint"] = large_adjoint(dev)
