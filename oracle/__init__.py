@@ -115,6 +115,12 @@ def lib():
         L.orc_dt.argtypes = [ctypes.c_int64, _d, ctypes.c_double, ctypes.c_double]
         L.orc_num_threads.restype = ctypes.c_int32
         L.orc_num_threads.argtypes = []
+        L.orc_hll.restype = None
+        L.orc_hll.argtypes = [_d, _d, _d, ctypes.c_double, _d, ctypes.c_int32, ctypes.c_int32, _d]
+        L.orc_transport_hll.restype = None
+        L.orc_transport_hll.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d, _d, _d, _d,
+                                        _i64, _i64, ctypes.c_double, ctypes.c_double, _d, _d,
+                                        _d, _i64, _d, _d, ctypes.c_int32, ctypes.c_int32]
         L.orc_bins.restype = None
         L.orc_bins.argtypes = [ctypes.c_int64, _d, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, ctypes.c_int32, _i64, _i64, _i32]
@@ -411,19 +417,81 @@ def gradient(geom: Geometry, U: np.ndarray) -> np.ndarray:
     return dU
 
 
-def transport(geom: Geometry, U: np.ndarray, dU: np.ndarray, dt: Optional[float] = None):
-    """Returns (U_new, counts[4], ledger[G])."""
+def transport(geom: Geometry, U: np.ndarray, dU: np.ndarray, dt: Optional[float] = None,
+              hll: Optional[np.ndarray] = None):
+    """Returns (U_new, counts[4], ledger[G]).  hll: an eigenvalue table
+    (hll_table()) selects the HLL solver instead of GLF."""
     U, dU = _f64(U), _f64(dU)
     n, G = U.shape[0], U.shape[1]
     dt = geom.dt if dt is None else dt
     out = np.zeros_like(U)
     counts = np.zeros(4, dtype=np.int64)
     ledger = np.zeros(G)
-    lib().orc_transport(n, G, _p(geom.x), _p(geom.h), _p(geom.H), _p(geom.V),
-                        _p(_f64(geom.B)), _p(geom.box), _p(geom.sptr, _i64),
-                        _p(geom.sidx, _i64), geom.c, dt, _p(U), _p(dU), _p(out),
-                        _p(counts, _i64), _p(ledger))
+    args = (n, G, _p(geom.x), _p(geom.h), _p(geom.H), _p(geom.V), _p(_f64(geom.B)),
+            _p(geom.box), _p(geom.sptr, _i64), _p(geom.sidx, _i64), geom.c, dt, _p(U), _p(dU),
+            _p(out), _p(counts, _i64), _p(ledger))
+    if hll is None:
+        lib().orc_transport(*args)
+    else:
+        tab = _f64(hll)
+        lib().orc_transport_hll(*args, _p(tab), tab.shape[0], tab.shape[1])
     return out, counts, ledger
+
+
+# HLL solver (eq:riemann-HLL): extreme eigenvalues of the M1 flux Jacobian
+
+def m1_flux_printed(U: np.ndarray, n: np.ndarray, c: float = 1.0) -> np.ndarray:
+    """(F.n, c^2 P n) of one state with the closure as printed
+    (eq:eddington-group), in any dtype (complex steps included)."""
+    E, F = U[0], U[1:]
+    Fn = np.sqrt(F @ F)
+    f = Fn / (c * E)
+    chi = (3 + 4 * f * f) / (5 + 2 * np.sqrt(4 - 3 * f * f))
+    nf = F / Fn
+    D = (1 - chi) / 2 * np.eye(3) + (3 * chi - 1) / 2 * np.outer(nf, nf)
+    return np.concatenate([[F @ n], c * c * E * (D @ n)])
+
+
+def m1_jacobian(f: float, mu: float, c: float = 1.0) -> np.ndarray:
+    """d(F.n, c^2 P n)/d(E, F) at E = 1, F = c f e_x, n = (mu, sqrt(1-mu^2), 0),
+    by complex steps (exact to rounding), for 0 < f < 1."""
+    n = np.array([mu, np.sqrt(max(0.0, 1.0 - mu * mu)), 0.0])
+    U = np.array([1.0, c * f, 0.0, 0.0])
+    J = np.zeros((4, 4))
+    hstep = 1e-30
+    for k in range(4):
+        Uc = U.astype(complex)
+        Uc[k] += 1j * hstep
+        J[:, k] = m1_flux_printed(Uc, n, c).imag / hstep
+    return J
+
+
+def hll_table(nf: int = 65, nmu: int = 65) -> np.ndarray:
+    """[nf][nmu][2] = (l_min, l_max) / c at f = i/(nf-1), mu = -1 + 2 j/(nmu-1):
+    the extreme eigenvalues of m1_jacobian (numpy's general eigensolver); at
+    f = 0 they are -+1/sqrt(3) for every mu, at f = 1 all four eigenvalues are
+    mu (the free-streaming limit)."""
+    tab = np.zeros((nf, nmu, 2))
+    for i in range(nf):
+        f = i / (nf - 1)
+        for j in range(nmu):
+            mu = -1.0 + 2.0 * j / (nmu - 1)
+            if i == 0:
+                tab[i, j] = (-1.0 / np.sqrt(3.0), 1.0 / np.sqrt(3.0))
+            elif i == nf - 1:
+                tab[i, j] = (mu, mu)
+            else:
+                ev = np.linalg.eigvals(m1_jacobian(f, mu)).real
+                tab[i, j] = (ev.min(), ev.max())
+    return tab
+
+
+def hll_flux(qL, qR, nh, tab, c: float = 1.0) -> np.ndarray:
+    phi = np.zeros(4)
+    t = _f64(tab)
+    lib().orc_hll(_p(_f64(qL)), _p(_f64(qR)), _p(_f64(nh)), c, _p(t), t.shape[0], t.shape[1],
+                  _p(phi))
+    return phi
 
 
 def photon_total(geom: Geometry, U: np.ndarray) -> np.ndarray:
@@ -443,25 +511,25 @@ def surface(geom: Geometry, k: int, l: int) -> np.ndarray:
 
 
 def step(geom: Geometry, srcs: Optional[Sources], U: np.ndarray, L=None,
-         dt: Optional[float] = None):
+         dt: Optional[float] = None, hll: Optional[np.ndarray] = None):
     """One RT step in the operator-splitting order inject -> gradient ->
     transport.  Returns (U_new, info)."""
     U = _f64(U).copy()
     if srcs is not None and srcs.src.size:
         inject(geom, srcs, U, L, dt)
     dU = gradient(geom, U)
-    out, counts, ledger = transport(geom, U, dU, dt)
+    out, counts, ledger = transport(geom, U, dU, dt, hll=hll)
     return out, {"counts": counts, "ledger": ledger, "U_injected": U, "dU": dU}
 
 
 def run(geom: Geometry, srcs: Optional[Sources], U0: np.ndarray, L, steps: int,
-        keep: bool = False):
+        keep: bool = False, hll: Optional[np.ndarray] = None):
     U = _f64(U0).copy()
     counts = np.zeros(4, dtype=np.int64)
     ledger = np.zeros(U.shape[1])
     states = [U.copy()] if keep else None
     for _ in range(steps):
-        U, info = step(geom, srcs, U, L)
+        U, info = step(geom, srcs, U, L, hll=hll)
         counts += info["counts"]
         ledger += info["ledger"]
         if keep:

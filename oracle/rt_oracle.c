@@ -367,6 +367,64 @@ void orc_glf(const double *qL, const double *qR, const double *nh, double c, dou
     for (int m = 0; m < 4; ++m) phi[m] = 0.5 * (fL[m] + fR[m]) - 0.5 * c * (qR[m] - qL[m]);
 }
 
+/* HLL Riemann solver, eq:riemann-HLL:
+ *   Phi = (l+ Flux_L - l- Flux_R + l+ l- (U_R - U_L)) / (l+ - l-),
+ *   l+ = max(0, l_max), l- = min(0, l_min),
+ * l_min, l_max the extreme eigenvalues of the flux Jacobian along nh.  They
+ * depend on the reduced flux f = |F|/(cE) and the angle between F and the
+ * interface only, and are tabulated and interpolated, as the thesis does
+ * (table in units of c).  Readings: the table is uniform in f on [0, 1] (nf
+ * nodes) and in mu = cos(theta) on [-1, 1] (nmu nodes), [i][j][2] = (l_min,
+ * l_max) at (f_i, mu_j), interpolated bilinearly; a state with no flux
+ * (E = 0 or F = 0) is looked up at f = 0; l_max is the larger of the two face
+ * states' and l_min the smaller (the wave speeds must bound both states).    */
+static void hll_speeds(const double *q, const double *nh, double c, const double *tab,
+                       int32_t nf, int32_t nmu, double *lmin, double *lmax)
+{
+    double E = q[0];
+    double Fn = sqrt(q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    double f = 0.0, mu = 0.0;
+    if (E > 0.0 && Fn > 0.0) {
+        f = Fn / (c * E);
+        if (f > 1.0) f = 1.0;
+        mu = (q[1] * nh[0] + q[2] * nh[1] + q[3] * nh[2]) / Fn;
+        if (mu > 1.0) mu = 1.0;
+        if (mu < -1.0) mu = -1.0;
+    }
+    double x = f * (nf - 1), y = 0.5 * (mu + 1.0) * (nmu - 1);
+    int32_t i = (int32_t)x, j = (int32_t)y;
+    if (i > nf - 2) i = nf - 2;
+    if (j > nmu - 2) j = nmu - 2;
+    double tx = x - i, ty = y - j;
+    for (int k = 0; k < 2; ++k) {
+        double v00 = tab[((int64_t)i * nmu + j) * 2 + k];
+        double v10 = tab[((int64_t)(i + 1) * nmu + j) * 2 + k];
+        double v01 = tab[((int64_t)i * nmu + j + 1) * 2 + k];
+        double v11 = tab[((int64_t)(i + 1) * nmu + j + 1) * 2 + k];
+        double v = (1.0 - tx) * (1.0 - ty) * v00 + tx * (1.0 - ty) * v10 +
+                   (1.0 - tx) * ty * v01 + tx * ty * v11;
+        if (k == 0) *lmin = c * v; else *lmax = c * v;
+    }
+}
+
+void orc_hll(const double *qL, const double *qR, const double *nh, double c,
+             const double *tab, int32_t nf, int32_t nmu, double *phi)
+{
+    double fL[4], fR[4], a0, a1, b0, b1;
+    orc_m1_flux(qL, nh, c, fL);
+    orc_m1_flux(qR, nh, c, fR);
+    hll_speeds(qL, nh, c, tab, nf, nmu, &a0, &a1);
+    hll_speeds(qR, nh, c, tab, nf, nmu, &b0, &b1);
+    double lmax = a1 > b1 ? a1 : b1, lmin = a0 < b0 ? a0 : b0;
+    double lp = lmax > 0.0 ? lmax : 0.0, lm = lmin < 0.0 ? lmin : 0.0;
+    if (!(lp - lm > 0.0)) {
+        for (int m = 0; m < 4; ++m) phi[m] = 0.5 * (fL[m] + fR[m]);
+        return;
+    }
+    for (int m = 0; m < 4; ++m)
+        phi[m] = (lp * fL[m] - lm * fR[m] + lp * lm * (qR[m] - qL[m])) / (lp - lm);
+}
+
 /* Effective surface of the Hopkins formulation, eq:HopkinsAij:
  *   A_kl = V_k psi_tilde_l(x_k) - V_l psi_tilde_k(x_l).                      */
 void orc_surface(const double *xk, const double *xl, double Hk, double Hl, double Vk,
@@ -399,11 +457,41 @@ void orc_surface(const double *xk, const double *xl, double Hk, double Hl, doubl
  * [1] face states with F rescaled, [2] updated states with E clipped,
  * [3] updated states with F rescaled.  ledger[G]: sum_k V_k * (energy density
  * added by clipping E < 0 of the updated state).                            */
+static void transport_core(int64_t n, int32_t G, const double *x, const double *h,
+                           const double *H, const double *V, const double *B,
+                           const double *box, const int64_t *sptr, const int64_t *sidx,
+                           double c, double dt, const double *U, const double *dU,
+                           double *Uout, int64_t *counts, double *ledger,
+                           const double *tab, int32_t nf, int32_t nmu);
+
 void orc_transport(int64_t n, int32_t G, const double *x, const double *h,
                    const double *H, const double *V, const double *B,
                    const double *box, const int64_t *sptr, const int64_t *sidx,
                    double c, double dt, const double *U, const double *dU, double *Uout,
                    int64_t *counts, double *ledger)
+{
+    transport_core(n, G, x, h, H, V, B, box, sptr, sidx, c, dt, U, dU, Uout, counts, ledger,
+                   NULL, 0, 0);
+}
+
+/* The same step with the HLL solver (table as orc_hll) instead of GLF.      */
+void orc_transport_hll(int64_t n, int32_t G, const double *x, const double *h,
+                       const double *H, const double *V, const double *B,
+                       const double *box, const int64_t *sptr, const int64_t *sidx,
+                       double c, double dt, const double *U, const double *dU, double *Uout,
+                       int64_t *counts, double *ledger, const double *tab, int32_t nf,
+                       int32_t nmu)
+{
+    transport_core(n, G, x, h, H, V, B, box, sptr, sidx, c, dt, U, dU, Uout, counts, ledger,
+                   tab, nf, nmu);
+}
+
+static void transport_core(int64_t n, int32_t G, const double *x, const double *h,
+                           const double *H, const double *V, const double *B,
+                           const double *box, const int64_t *sptr, const int64_t *sidx,
+                           double c, double dt, const double *U, const double *dU,
+                           double *Uout, int64_t *counts, double *ledger,
+                           const double *tab, int32_t nf, int32_t nmu)
 {
     const int64_t nq = 4 * (int64_t)G;
     int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
@@ -436,7 +524,8 @@ void orc_transport(int64_t n, int32_t G, const double *x, const double *h,
                 int fl = guard_state(qL, c), fr = guard_state(qR, c);
                 c0 += (fl & 1) + (fr & 1);
                 c1 += ((fl >> 1) & 1) + ((fr >> 1) & 1);
-                orc_glf(qL, qR, nh, c, phi);
+                if (tab) orc_hll(qL, qR, nh, c, tab, nf, nmu, phi);
+                else orc_glf(qL, qR, nh, c, phi);
                 for (int m = 0; m < 4; ++m) acc[4 * g + m] += An * phi[m];
             }
         }

@@ -1,0 +1,107 @@
+"""Pins of the oracle's HLL solver (Part III eq:riemann-HLL) and of its
+eigenvalue table.
+
+- table at mu = cos(theta) = +-1 against the closed form of the 1D M1 system
+  (the longitudinal 2x2 Jacobian [[0, 1], [c^2 (chi - f chi'), c chi']] has
+  eigenvalues c (chi' +- sqrt(chi'^2 + 4 (chi - f chi'))) / 2), differentiated
+  by hand here, independently of the complex-step Jacobian;
+- f = 0 nodes at -+1/sqrt(3); mirror symmetry l_min(f, mu) = -l_max(f, -mu);
+  |l| <= 1 (no signal faster than c);
+- HLL with wave speeds -+c is the GLF solver (the thesis states it); a
+  two-identical-state Riemann problem returns the state's flux; with both
+  speeds positive the flux is the upwind one;
+- one HLL transport step conserves photons (no sources; the face guards act
+  on the same face states from both sides of a pair, so only the post-update
+  guard, which does not fire here, could change the total).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+
+@pytest.fixture(scope="module")
+def tab(orc):
+    return oracle.hll_table()
+
+
+def chi_and_slope(f):
+    s = np.sqrt(4 - 3 * f * f)
+    chi = (3 + 4 * f * f) / (5 + 2 * s)
+    dchi = (8 * f * (5 + 2 * s) + (3 + 4 * f * f) * 6 * f / s) / (5 + 2 * s) ** 2
+    return chi, dchi
+
+
+def test_table_along_the_flux_is_the_1d_system(tab):
+    nf, nmu = tab.shape[:2]
+    worst = 0.0
+    for i in range(1, nf - 1):
+        f = i / (nf - 1)
+        chi, d = chi_and_slope(f)
+        r = np.sqrt(d * d + 4 * (chi - f * d))
+        lo, hi = (d - r) / 2, (d + r) / 2
+        worst = max(worst, abs(tab[i, -1, 0] - lo), abs(tab[i, -1, 1] - hi))
+        worst = max(worst, abs(tab[i, 0, 0] + hi), abs(tab[i, 0, 1] + lo))
+    assert worst < 1e-12
+
+
+def test_table_limits_symmetry_and_bounds(tab):
+    assert np.allclose(tab[0, :, 0], -1 / np.sqrt(3), rtol=0, atol=1e-15)
+    assert np.allclose(tab[0, :, 1], 1 / np.sqrt(3), rtol=0, atol=1e-15)
+    assert np.abs(tab[:, :, 0] + tab[:, ::-1, 1]).max() < 1e-13
+    assert (tab[:, :, 0] <= tab[:, :, 1] + 1e-15).all()
+    assert np.abs(tab).max() <= 1 + 1e-13
+
+
+def random_state(g, f):
+    E = g.lognormal()
+    d = g.normal(size=3)
+    d /= np.linalg.norm(d)
+    return np.concatenate([[E], f * E * d])
+
+
+def test_hll_with_speed_of_light_is_glf(orc):
+    g = workloads.rng(31)
+    box = np.full((2, 2, 2), -1.0)
+    box[..., 1] = 1.0
+    for _ in range(50):
+        qL, qR = random_state(g, g.uniform()), random_state(g, g.uniform())
+        nh = g.normal(size=3)
+        nh /= np.linalg.norm(nh)
+        ref = np.zeros(4)
+        oracle.lib().orc_glf(oracle._p(qL), oracle._p(qR), oracle._p(nh), 1.0, oracle._p(ref))
+        got = oracle.hll_flux(qL, qR, nh, box)
+        assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_hll_consistency_and_upwinding(tab):
+    g = workloads.rng(32)
+    for _ in range(50):
+        q = random_state(g, g.uniform())
+        nh = g.normal(size=3)
+        nh /= np.linalg.norm(nh)
+        fl = np.zeros(4)
+        oracle.lib().orc_m1_flux(oracle._p(q), oracle._p(nh), 1.0, oracle._p(fl))
+        got = oracle.hll_flux(q, q, nh, tab)
+        assert np.abs(got - fl).max() <= 1e-14 * np.abs(fl).max() + 1e-300
+    # nearly free streaming along the normal: both wave speeds positive
+    nh = np.array([1.0, 0.0, 0.0])
+    qL = np.array([1.0, 0.995, 0.0, 0.0])
+    qR = np.array([2.0, 1.98, 0.05, 0.0])
+    fl = np.zeros(4)
+    oracle.lib().orc_m1_flux(oracle._p(qL), oracle._p(nh), 1.0, oracle._p(fl))
+    assert np.array_equal(oracle.hll_flux(qL, qR, nh, tab), fl)
+
+
+def test_hll_step_conserves_photons(tab):
+    w = workloads.lattice_workload(10, 2, 0, 1, seed=77, name="hll")
+    U0 = w.U0.copy()
+    U0[..., 1:] *= 0.3        # far from the free-streaming limit
+    geo = oracle.build_geometry(w.x)
+    out, info = oracle.step(geo, None, U0, hll=tab)
+    assert not info["counts"][2:].any()       # the post-update guard did not fire
+    Q0, Q1 = oracle.photon_total(geo, U0), oracle.photon_total(geo, out)
+    assert np.abs(Q1 / Q0 - 1).max() < 1e-13
+    glf, _ = oracle.step(geo, None, U0)
+    assert np.abs(out - glf).max() > 1e-6 * np.abs(glf).max()   # a different solver
