@@ -78,10 +78,10 @@ def cpu_baseline(cfg_index: int, min_seconds: float):
     }
 
 
-def run_forward(w, precision, steps, warmup, dev, timing=True, keep_state=False):
+def run_forward(w, precision, steps, warmup, dev, timing=True, keep_state=False, solver="glf"):
     """Build the static geometry, then time `steps` whole RT steps (after
     `warmup` untimed ones).  keep_state: also return the final state (input
-    order, FP64 host array)."""
+    order, FP64 host array).  solver: the Riemann solver, "glf" or "hll"."""
     import numpy as np
     import torch
     from paper_2302_12727_amd import RT
@@ -96,8 +96,9 @@ def run_forward(w, precision, steps, warmup, dev, timing=True, keep_state=False)
         rt.rt_set_sources(torch.from_numpy(w.xs).to(dev))
     rt.rt_sync()
     build_ms = (time.perf_counter() - t0) * 1e3
+    rt.rt_set_riemann(solver)
     st = rt.rt_get_stats()
-    log(f"[{precision}] build {build_ms:.1f} ms; pairs {st['n_pairs']}; mean neighbours "
+    log(f"[{precision} {solver}] build {build_ms:.1f} ms; pairs {st['n_pairs']}; mean neighbours "
         f"{st['n_entries'] / w.n:.2f}; max {st['max_neighbours']}")
     p = perm.cpu().numpy()
     sd = rt.sdtype
@@ -400,6 +401,7 @@ def main():
         "photon_budget_residual": fw["photon_budget_residual"],
         "guard_counts": fw["guard_counts"],
     }
+    fw_transport_ms = fw["transport_ms"]
     del fw
     if not args.no_extra:
         other = "fp32c" if args.precision == "fp64" else "fp64"
@@ -410,6 +412,15 @@ def main():
                       "speedup_vs_" + args.precision: out["ms_per_step"] /
                       (f2["elapsed"] / args.steps * 1e3)}
         del f2
+        if args.precision == "fp64":
+            fh = run_forward(w, "fp64", args.steps, args.warmup, dev, solver="hll")
+            out["hll"] = {"value": fh["pairs"] * args.steps / fh["elapsed"],
+                          "ms_per_step": fh["elapsed"] / args.steps * 1e3,
+                          "kernel_ms": {"transport": fh["transport_ms"],
+                                        "gradient": fh["gradient_ms"]},
+                          "transport_time_vs_glf": fh["transport_ms"] / fw_transport_ms,
+                          "photon_budget_residual": fh["photon_budget_residual"]}
+            del fh
         wa = workloads.config(3)
         ad = run_adjoint(wa, "fp64", dev)
         ad.pop("grad")

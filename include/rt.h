@@ -120,7 +120,8 @@ rt_status rt_gradient(rt_ctx *ctx, const void *U, void *UD);
 /* One transport step (eq:transport-update-explicit with one global dt):
  *   U_out_k = U_k - dt/V_k sum_l Flux_kl . A_kl
  * over all neighbours l, with A_kl of eq:HopkinsAij, the GLF solver of
- * eq:riemann-GLF on minmod-limited states extrapolated to
+ * eq:riemann-GLF (or HLL, see rt_set_riemann) on minmod-limited states
+ * extrapolated to
  * x_kl = x_k + h_k/(h_k + h_l)(x_l - x_k) (eq:rt-riemann-problem), and the M1
  * closure (eq:eddington-group).  Face states and the updated state are
  * guarded: E < 0 is set to 0 (with F = 0) and |F| > c E is scaled to c E.
@@ -142,6 +143,34 @@ rt_status rt_transport(rt_ctx *ctx, const void *UD, const double *dt, void *U_ou
 
 /* Q_g = sum_k V_k E_kg of U, [G] out (FP64, compensated, deterministic). */
 rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q);
+
+/* Riemann solver of rt_transport (Part III "Riemann solvers").
+ *   RT_GLF  global Lax-Friedrichs, eq:riemann-GLF (the default).
+ *   RT_HLL  HLL, eq:riemann-HLL:
+ *             Phi = (l+ F_L - l- F_R + l+ l- (U_R - U_L)) / (l+ - l-),
+ *             l+ = max(0, l_max), l- = min(0, l_min),
+ *           l_max the larger and l_min the smaller of the extreme eigenvalues
+ *           of the M1 flux Jacobian along the face normal A/|A| over the two
+ *           face states; (F_L + F_R)/2 when l+ = l- = 0.  The eigenvalues
+ *           depend on f = |F|/(cE) (clamped to 1) and mu = F.A/(|F||A|) only;
+ *           the library tabulates them in units of c on RT_HLL_NF nodes
+ *           uniform in f on [0, 1] times RT_HLL_NMU nodes uniform in mu on
+ *           [-1, 1] and interpolates bilinearly (a state with E <= 0 or F = 0
+ *           is looked up at f = 0).
+ * HLL is implemented for the global step of FP64 contexts: rt_set_riemann
+ * returns RT_EINVAL on an FP32C context, and rt_tick and rt_adjoint return
+ * RT_ESTATE while HLL is selected.  The table (RT_HLL_NF x RT_HLL_NMU x 2
+ * doubles) is computed on the host and uploaded on the first selection of
+ * RT_HLL (synchronous). */
+typedef enum { RT_GLF = 0, RT_HLL = 1 } rt_riemann;
+#define RT_HLL_NF 65
+#define RT_HLL_NMU 65
+rt_status rt_set_riemann(rt_ctx *ctx, int32_t solver);
+
+/* The HLL wave-speed table, [RT_HLL_NF][RT_HLL_NMU][2] doubles (l_min, l_max)
+ * in units of c at f_i = i/(RT_HLL_NF - 1), mu_j = -1 + 2j/(RT_HLL_NMU - 1).
+ *   tab [host] out.  ctx may be NULL (host code only, no device needed). */
+rt_status rt_get_hll_table(rt_ctx *ctx, double *tab);
 
 /* Individual power-of-two time steps (Part II "Individual time steps",
  * eq:meshless-explicit-individual-timesteps; Part III eq:transport-update-

@@ -113,7 +113,7 @@ void rt_destroy(rt_ctx *ctx) {
                     ctx->n_gath, ctx->wave_base, ctx->nbr, ctx->src_h, ctx->inj_gptr,
                     ctx->inj_gas, ctx->inj_src, ctx->inj_coef, ctx->inj_xi, ctx->src_ptr,
                     ctx->src_gas, ctx->src_coef, ctx->status, ctx->partials, ctx->scan_tmp,
-                    ctx->adj_buf};
+                    ctx->adj_buf, ctx->hll_table};
     for (void *b : bufs) rt_free(b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -194,6 +194,22 @@ rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q) {
     return rt_total_impl(ctx, U, Q);
 }
 
+rt_status rt_set_riemann(rt_ctx *ctx, int32_t solver) {
+    if (!ctx) return RT_EINVAL;
+    if (solver != RT_GLF && solver != RT_HLL)
+        return rt_fail(ctx, RT_EINVAL, "solver must be RT_GLF or RT_HLL");
+    if (solver == RT_HLL && ctx->p.precision != RT_FP64)
+        return rt_fail(ctx, RT_EINVAL, "the HLL solver is implemented for FP64 contexts only");
+    return rt_set_riemann_impl(ctx, solver);
+}
+
+rt_status rt_get_hll_table(rt_ctx *ctx, double *tab) {
+    if (!tab) return rt_fail(ctx, RT_EINVAL, "tab is NULL");
+    std::vector<double> t = rt_hll_speed_table(RT_HLL_NF, RT_HLL_NMU);
+    memcpy(tab, t.data(), sizeof(double) * t.size());
+    return RT_OK;
+}
+
 rt_status rt_time_bins(rt_ctx *ctx, int32_t max_bin, int32_t *bins, int64_t *cycle_ticks) {
     if (!ctx) return RT_EINVAL;
     if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
@@ -211,6 +227,8 @@ rt_status rt_tick(rt_ctx *ctx, double *U, const double *L, int64_t tick, double 
         return rt_fail(ctx, RT_EINVAL, "time bins are implemented for FP64 contexts only");
     if (!U || !UD || !acc) return rt_fail(ctx, RT_EINVAL, "U, UD and acc are required");
     if (tick < 0) return rt_fail(ctx, RT_EINVAL, "tick must be >= 0");
+    if (ctx->solver != RT_GLF)
+        return rt_fail(ctx, RT_ESTATE, "individual time steps use the GLF solver");
     if (ctx->S > 0 && !L) return rt_fail(ctx, RT_EINVAL, "L is required when sources are set");
     size_t nu = sizeof(double) * 4 * ctx->p.groups * ctx->p.n;
     if (overlap(UD, 4 * nu, U, nu) || overlap(UD, 4 * nu, acc, nu) || overlap(U, nu, acc, nu))
@@ -228,6 +246,8 @@ rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const doub
     if (!UD && !U_pre) return rt_fail(ctx, RT_EINVAL, "U_pre is required when UD is NULL");
     if (ctx->S > 0 && !L) return rt_fail(ctx, RT_EINVAL, "L is required when sources are set");
     if (UD && !aligned16(UD)) return rt_fail(ctx, RT_EINVAL, "UD must be 16-byte aligned");
+    if (ctx->solver != RT_GLF)
+        return rt_fail(ctx, RT_ESTATE, "the adjoint is implemented for the GLF solver");
     return rt_adjoint_impl(ctx, U_pre, L, dt, UD, U_unguarded, lam_next, lam, dL_dL);
 }
 

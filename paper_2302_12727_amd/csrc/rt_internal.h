@@ -102,6 +102,8 @@ struct rt_ctx {
     int64_t device_bytes = 0;
     int32_t h_iter_max = 0;
     int32_t bin_top = -1;        // largest time bin after rt_time_bins (-1: none)
+    int32_t solver = RT_GLF;     // Riemann solver of the transport
+    double *hll_table = nullptr; // [RT_HLL_NF][RT_HLL_NMU][2] wave speeds / c
 
     // timing: event pairs recorded around launches while timing is on
     int timing = 0;
@@ -276,6 +278,10 @@ rt_status rt_tick_impl(rt_ctx *ctx, double *U, const double *L, int64_t tick, do
                        double *acc, double *Q, int64_t *counts, double *ledger);
 rt_status rt_tick_step_impl(rt_ctx *ctx, double *U, double *UD, const double *dt, int64_t tick,
                             double *accm, double *Q, int64_t *counts, double *ledger);
+
+// HLL wave speeds (rt_hll.hip): the host table and the solver switch
+std::vector<double> rt_hll_speed_table(int nf, int nmu);
+rt_status rt_set_riemann_impl(rt_ctx *ctx, int32_t solver);
 
 // adjoint (rt_adjoint.hip)
 rt_status rt_adjoint_impl(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,

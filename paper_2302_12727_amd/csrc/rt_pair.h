@@ -61,6 +61,53 @@ __device__ __forceinline__ void m1_flux64(double E, double Fx, double Fy, double
     out[3] = a * Az + b * Fz;
 }
 
+// HLL wave speeds of one face state (eq:riemann-HLL): the extreme eigenvalues
+// of the M1 flux Jacobian along A/|A|, interpolated bilinearly in the table
+// tab[RT_HLL_NF][RT_HLL_NMU] = (l_min, l_max)/c over f = |F|/(cE), clamped to
+// 1, and mu = F.A/(|F||A|), clamped to [-1, 1]; a state with E <= 0 or F = 0
+// is looked up at f = 0.  iAn = 1/|A|.  Every index stays in the table
+// whatever the inputs (NaN compares false and fmin/fmax drop it).
+__device__ __forceinline__ void hll_speeds64(double E, double Fx, double Fy, double Fz,
+                                             double Ax, double Ay, double Az, double iAn,
+                                             double c, const double2 *__restrict__ tab,
+                                             double &lo, double &hi) {
+    const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+    const double FA = Fx * Ax + Fy * Ay + Fz * Az;
+    double f = 0.0, mu = 0.0;
+    if (E > 0.0 && F2 > 0.0) {
+        const double iF = rsq64(F2);
+        f = fmin(F2 * iF * rcp64(c * E), 1.0);
+        mu = fmin(fmax(FA * iF * iAn, -1.0), 1.0);
+    }
+    const double x = f * (RT_HLL_NF - 1), y = (mu + 1.0) * (0.5 * (RT_HLL_NMU - 1));
+    const int i = max(min((int)x, RT_HLL_NF - 2), 0);
+    const int j = max(min((int)y, RT_HLL_NMU - 2), 0);
+    const double tx = x - i, ty = y - j;
+    const double2 *t = tab + i * RT_HLL_NMU + j;
+    const double2 v00 = t[0], v01 = t[1], v10 = t[RT_HLL_NMU], v11 = t[RT_HLL_NMU + 1];
+    const double ux = 1.0 - tx, uy = 1.0 - ty;
+    lo = c * (ux * (uy * v00.x + ty * v01.x) + tx * (uy * v10.x + ty * v11.x));
+    hi = c * (ux * (uy * v00.y + ty * v01.y) + tx * (uy * v10.y + ty * v11.y));
+}
+
+// Weights of the numerical flux Phi.A = w1 F_L.A + w2 F_R.A + w3 (U_R - U_L)
+// of the HLL solver (eq:riemann-HLL) from the face states' wave speeds; the
+// GLF solver (eq:riemann-GLF) is w1 = w2 = 1/2, w3 = -c |A|/2.
+__device__ __forceinline__ void hll_weights(double loL, double hiL, double loR, double hiR,
+                                            double An, double &w1, double &w2, double &w3) {
+    const double lp = fmax(fmax(hiL, hiR), 0.0), lm = fmin(fmin(loL, loR), 0.0);
+    const double den = lp - lm;
+    if (den > 0.0) {
+        const double id = rcp64(den);
+        w1 = lp * id;
+        w2 = -lm * id;
+        w3 = lp * lm * An * id;
+    } else {
+        w1 = w2 = 0.5;
+        w3 = 0.0;
+    }
+}
+
 __device__ __forceinline__ double minmod(double a, double b) {
     const double m = (fabs(a) <= fabs(b)) ? a : b;
     return (a * b > 0.0) ? m : 0.0;

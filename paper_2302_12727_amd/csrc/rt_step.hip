@@ -105,20 +105,23 @@ __global__ __launch_bounds__(kBlock) void k_gradient64(
 // The compiler is held to the 256 registers of 2 waves per SIMD: this kernel
 // sits at about 250 VGPRs, and at 1 wave per SIMD it runs 1.6x slower.
 //
+// HLL: the HLL solver (eq:riemann-HLL) with the wave-speed table hll in
+// place of GLF.
+//
 // BIN: one tick of the individual-time-step scheme (time bins in slot 12 of
 // the geometry records, the smallest bin of each particle's neighbourhood in
 // slot 13): only pairs whose smaller bin ends a step in this tick contribute,
 // each with dt 2^min(b_k, b_l); the sums go to the pending flux sums accm, and
 // the particles that end a step apply and clear theirs (Part III
 // eq:transport-update-explicit with min{dt_k, dt_l}).
-template <int G, int GW, bool BIN = false>
+template <int G, int GW, bool BIN = false, bool HLL = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_transport64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
     const double *__restrict__ UD, const double *__restrict__ dtp, double c, double box,
     double *__restrict__ Uout, double *__restrict__ partials,
     unsigned long long *__restrict__ counts, double *__restrict__ Uung, int64_t tick = 0,
-    double *__restrict__ accm = nullptr) {
+    double *__restrict__ accm = nullptr, const double2 *__restrict__ hll = nullptr) {
     static_assert(G % GW == 0, "group slices must tile the groups");
     constexpr int NS = G / GW, NQ = 4 * G;
     __shared__ double stage[kBlock / 64][64 * kStage];
@@ -189,6 +192,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                 use = use && (t1 & ((int64_t(1) << bmin) - 1)) == 0;
                 wkl = ldexp(dtp[0], bmin);
             }
+            const double iAn = (HLL && pg.An > 0.0) ? rcp64(pg.An) : 0.0;
 #pragma unroll
             for (int g = 0; g < GW; ++g) {
                 int64_t rowg[8];
@@ -208,16 +212,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
                 }
                 const int f1 = guard64(qL[0], qL[1], qL[2], qL[3], c);
                 const int f2 = guard64(qR[0], qR[1], qR[2], qR[3], c);
+                double w1 = 0.5, w2 = 0.5, w3 = -hc * pg.An;   // GLF
+                if (HLL) {
+                    double loL, hiL, loR, hiR;
+                    hll_speeds64(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, iAn, c, hll,
+                                 loL, hiL);
+                    hll_speeds64(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, iAn, c, hll,
+                                 loR, hiR);
+                    hll_weights(loL, hiL, loR, hiR, pg.An, w1, w2, w3);
+                }
                 double FL[4], FR[4];
                 m1_flux64(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, FL);
                 m1_flux64(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, FR);
-                const double dis = hc * pg.An;
                 if (use) {
                     cE += (f1 & 1) + (f2 & 1);
                     cF += (f1 >> 1) + (f2 >> 1);
 #pragma unroll
                     for (int m = 0; m < 4; ++m)
-                        acc[4 * g + m] += wkl * (0.5 * (FL[m] + FR[m]) - dis * (qR[m] - qL[m]));
+                        acc[4 * g + m] += wkl * (w1 * FL[m] + w2 * FR[m] + w3 * (qR[m] - qL[m]));
                 }
             }
         }
@@ -379,16 +391,31 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int64_t nb, int G,
 constexpr int transport_slice(int G) {
     return G <= 3 ? G : (G % 2 == 0 ? 2 : (G % 3 == 0 ? 3 : 1));
 }
+// The HLL solver holds about 10 more registers per group in flight (the wave
+// speeds of both face states), so 3 groups per wave no longer fit: odd G runs
+// one group per wave.
+#ifndef RT_HLL_GW
+#define RT_HLL_GW 0
+#endif
+constexpr int hll_slice(int G) { return G <= 2 ? G : (G % 2 == 0 ? 2 : 1); }
 
 template <int G>
 void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double *Uout,
                         double *partials, int64_t *counts, double *Uung) {
     constexpr int GW =
         (RT_TRANSPORT_GW == 0 || G % RT_TRANSPORT_GW != 0) ? transport_slice(G) : RT_TRANSPORT_GW;
+    constexpr int HW = (RT_HLL_GW == 0 || G % RT_HLL_GW != 0) ? hll_slice(G) : RT_HLL_GW;
     const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
-    k_transport64<G, GW><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, ctx->stream>>>(
-        n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
-        ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung);
+    if (ctx->solver == RT_HLL)
+        k_transport64<G, HW, false, true><<<(unsigned)xcd_grid(nb * (G / HW)), kBlock, 0,
+                                            ctx->stream>>>(
+            n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
+            ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, 0, nullptr,
+            (const double2 *)ctx->hll_table);
+    else
+        k_transport64<G, GW><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, ctx->stream>>>(
+            n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
+            ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung);
 }
 
 template <int G>

@@ -12,6 +12,7 @@ import ctypes
 import os
 from typing import Optional
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -19,6 +20,8 @@ LIB_PATH = os.path.join(HERE, "libgearrt.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EHIP, RT_ENOCONV, RT_ESINGULAR, RT_ESTATE = 0, -1, -2, -3, -4, -5, -6
 RT_FP64, RT_FP32C = 0, 1
+RT_GLF, RT_HLL = 0, 1
+RT_HLL_NF, RT_HLL_NMU = 65, 65
 STATUS_NAMES = {0: "RT_OK", -1: "RT_EINVAL", -2: "RT_ENOMEM", -3: "RT_EHIP",
                 -4: "RT_ENOCONV", -5: "RT_ESINGULAR", -6: "RT_ESTATE"}
 
@@ -28,7 +31,8 @@ ETA = 1.2348
 EXPORTED = ["rt_create", "rt_destroy", "rt_last_error", "rt_set_stream", "rt_build_cells",
             "rt_set_sources", "rt_inject", "rt_gradient", "rt_transport", "rt_photon_total",
             "rt_adjoint", "rt_sync", "rt_get_stats", "rt_get_geometry", "rt_get_neighbours",
-            "rt_get_sources", "rt_timing", "rt_get_timing", "rt_time_bins", "rt_tick"]
+            "rt_get_sources", "rt_timing", "rt_get_timing", "rt_time_bins", "rt_tick",
+            "rt_set_riemann", "rt_get_hll_table"]
 
 
 class RTError(RuntimeError):
@@ -82,6 +86,8 @@ def load_library() -> ctypes.CDLL:
     L.rt_adjoint.argtypes = [_VP] * 9
     L.rt_time_bins.argtypes = [_VP, i32, _VP, ctypes.POINTER(ctypes.c_int64)]
     L.rt_tick.argtypes = [_VP, _VP, _VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP]
+    L.rt_set_riemann.argtypes = [_VP, i32]
+    L.rt_get_hll_table.argtypes = [_VP, _VP]
     L.rt_sync.argtypes = [_VP]
     L.rt_get_stats.argtypes = [_VP, ctypes.POINTER(rt_stats)]
     L.rt_get_geometry.argtypes = [_VP] * 4
@@ -109,6 +115,17 @@ def _need(t: torch.Tensor, name: str, dtype, shape=None):
         raise ValueError(f"{name} must be contiguous")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def hll_speed_table() -> np.ndarray:
+    """The library's HLL wave-speed table, [RT_HLL_NF][RT_HLL_NMU][2]
+    (l_min, l_max) in units of c, as a host float64 array (host code only)."""
+    L = load_library()
+    tab = np.zeros((RT_HLL_NF, RT_HLL_NMU, 2), dtype=np.float64)
+    st = L.rt_get_hll_table(None, ctypes.c_void_p(tab.ctypes.data))
+    if st != RT_OK:
+        raise RTError(st, L.rt_last_error(None).decode())
+    return tab
 
 
 class RT:
@@ -256,6 +273,15 @@ class RT:
         self._check(self.L.rt_tick(self.ctx, _ptr(U), _ptr(L), int(tick), _ptr(UD), _ptr(acc),
                                    _ptr(photon_total), _ptr(counts), _ptr(ledger)))
         return U
+
+    def rt_set_riemann(self, solver: str):
+        """Riemann solver of rt_transport: "glf" or "hll"."""
+        code = {"glf": RT_GLF, "hll": RT_HLL}[solver]
+        self._check(self.L.rt_set_riemann(self.ctx, code))
+
+    def rt_get_hll_table(self):
+        """The library's HLL wave-speed table (see hll_speed_table)."""
+        return hll_speed_table()
 
     def rt_photon_total(self, U: torch.Tensor) -> torch.Tensor:
         _need(U, "U", self.sdtype, (self.n, self.G, 4))
