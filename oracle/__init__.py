@@ -115,6 +115,9 @@ def lib():
         L.orc_dt.argtypes = [ctypes.c_int64, _d, ctypes.c_double, ctypes.c_double]
         L.orc_num_threads.restype = ctypes.c_int32
         L.orc_num_threads.argtypes = []
+        L.orc_absorb.restype = None
+        L.orc_absorb.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d, _d, _d,
+                                 _d, ctypes.c_double, ctypes.c_double, _d, _d]
         L.orc_hll.restype = None
         L.orc_hll.argtypes = [_d, _d, _d, ctypes.c_double, _d, ctypes.c_int32, ctypes.c_int32, _d]
         L.orc_transport_hll.restype = None
@@ -499,6 +502,24 @@ def photon_total(geom: Geometry, U: np.ndarray) -> np.ndarray:
     Q = np.zeros(U.shape[1])
     lib().orc_photon_total(U.shape[0], U.shape[1], _p(geom.V), _p(U), _p(Q))
     return Q
+
+
+def absorb(geom: Geometry, U: np.ndarray, n_old: np.ndarray, sigma: np.ndarray, dt: float,
+           n_new: Optional[np.ndarray] = None, c: Optional[float] = None):
+    """Photon removal of the thermochemistry step (rt_oracle.c orc_absorb).
+    n_old, n_new [n][J] species densities, sigma [G][J].  Returns (U_new,
+    absorbed[G])."""
+    U = _f64(U)
+    n_old = _f64(n_old)
+    sigma = _f64(sigma)
+    G, J = sigma.shape
+    out = np.empty_like(U)
+    absorbed = np.zeros(G)
+    nn = None if n_new is None else _f64(n_new)
+    lib().orc_absorb(U.shape[0], G, J, _p(geom.V), _p(U), _p(n_old),
+                     None if nn is None else _p(nn), _p(sigma),
+                     geom.c if c is None else c, dt, _p(out), _p(absorbed))
+    return out, absorbed
 
 
 def surface(geom: Geometry, k: int, l: int) -> np.ndarray:

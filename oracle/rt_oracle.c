@@ -761,6 +761,40 @@ void orc_transport_binned(int64_t n, int32_t G, const double *x, const double *h
     free(led);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Photon removal of the thermochemistry step (Part III "Third step:
+ * Thermochemistry"): forward Euler over dt with the number densities of the
+ * absorbing species averaged over the step,
+ *   E_kg(t+dt) = E_kg(t) (1 - c dt sum_j sigma_gj (n_kj(t) + n_kj(t+dt))/2),
+ * and the same factor on F_kg.  sigma[G][J] is the number-weighted group
+ * cross section (eq:sigma_N), n_old/n_new [n][J] the densities at the two
+ * ends of the step (n_new NULL: constant densities).  Reading: a factor
+ * below zero (more than all photons absorbed in one step) is taken as zero.
+ * absorbed[G] += sum_k V_k (E_kg(t) - E_kg(t+dt)).                          */
+void orc_absorb(int64_t n, int32_t G, int32_t J, const double *V, const double *U,
+                const double *n_old, const double *n_new, const double *sigma, double c,
+                double dt, double *Uout, double *absorbed)
+{
+    for (int32_t g = 0; g < G; ++g) {
+        double lost = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            double kappa = 0.0;
+            for (int32_t j = 0; j < J; ++j) {
+                double nbar = n_new ? 0.5 * (n_old[k * J + j] + n_new[k * J + j])
+                                    : n_old[k * J + j];
+                kappa += sigma[g * J + j] * nbar;
+            }
+            double f = 1.0 - c * dt * kappa;
+            if (f < 0.0) f = 0.0;
+            const double *q = U + (k * G + g) * 4;
+            double *o = Uout + (k * G + g) * 4;
+            for (int m = 0; m < 4; ++m) o[m] = q[m] * f;
+            lost += V[k] * (q[0] - o[0]);
+        }
+        absorbed[g] += lost;
+    }
+}
+
 int32_t orc_num_threads(void)
 {
 #ifdef _OPENMP
