@@ -241,6 +241,42 @@ def compare_time_bins(w, dev, max_bin: int = 8, cycles: int = 2):
     return res
 
 
+def absorb_leg(w, dev, precision="fp64", reps=50, J=3):
+    """The photon removal of the thermochemistry step on workload w's states
+    with synthetic species densities at both ends of the step: average launch
+    time over `reps` launches, against the HBM roofline at its algorithmic
+    bytes (U read and written, both density arrays, the volumes)."""
+    import numpy as np
+    import torch
+    from paper_2302_12727_amd import RT
+
+    rt = RT(w.n, w.groups, precision=precision, cfl=w.cfl, c_red=w.c_red, device=dev)
+    perm, *_ = rt.rt_build_cells(torch.from_numpy(w.x).to(dev))
+    rt.rt_sync()
+    p = perm.cpu().numpy()
+    U = torch.from_numpy(np.ascontiguousarray(w.U0[p])).to(dev).to(rt.sdtype)
+    g = np.random.default_rng(7)
+    n_old = torch.from_numpy(g.uniform(0.0, 1.0, size=(w.n, J))).to(dev)
+    n_new = n_old * 0.9
+    # small optical depth per step, so that the states stay non-zero over the launches
+    sigma = torch.full((w.groups, J), 1e-4 / J, dtype=torch.float64, device=dev)
+    absorbed = torch.zeros(w.groups, dtype=torch.float64, device=dev)
+    rt.rt_absorb(U, n_old, sigma, n_new=n_new, absorbed=absorbed)        # warm-up
+    torch.cuda.synchronize()
+    rt.rt_timing(True)
+    for _ in range(reps):
+        rt.rt_absorb(U, n_old, sigma, n_new=n_new, absorbed=absorbed)
+    torch.cuda.synchronize()
+    rt.rt_timing(False)
+    ms, nl = rt.rt_get_timing("absorb")
+    elem = 8 if precision == "fp64" else 4
+    nbytes = w.n * (2 * 4 * w.groups * elem + 2 * J * 8 + 8)
+    t = ms / nl * 1e-3
+    return {"workload": w.name, "n": w.n, "groups": w.groups, "species": J,
+            "precision": precision, "ms": ms / nl, "algorithmic_bytes": nbytes,
+            "achieved_TBps": nbytes / t / 1e12, "hbm_frac": nbytes / t / PEAK_HBM}
+
+
 def large_adjoint(dev):
     """2^24 Plummer mix, 4 groups, 256 sources, 50 steps, checkpoints every
     10: the FP32C rollout and its adjoint (time ratio, peak HBM), and its
@@ -421,6 +457,8 @@ def main():
                           "transport_time_vs_glf": fh["transport_ms"] / fw_transport_ms,
                           "photon_budget_residual": fh["photon_budget_residual"]}
             del fh
+        out["absorb"] = absorb_leg(w, dev)
+        torch.cuda.empty_cache()
         wa = workloads.config(3)
         ad = run_adjoint(wa, "fp64", dev)
         ad.pop("grad")

@@ -172,6 +172,46 @@ rt_status rt_set_riemann(rt_ctx *ctx, int32_t solver);
  *   tab [host] out.  ctx may be NULL (host code only, no device needed). */
 rt_status rt_get_hll_table(rt_ctx *ctx, double *tab);
 
+/* Photo-absorption constants of photon groups (Part III "Discretization of
+ * Frequencies": eq:sigma_N and the energy-weighted average beside it, and the
+ * mean photon energy), for cross sections of H0, He0 and He+ from the fits
+ * eq:sigma-parametrizaiton with the parameters of tab:cross-sections (zero
+ * below each species' ionization energy, eq:nuIonHI - eq:nuIonHeII) and a
+ * blackbody spectrum eq:blackbody.  Host code: needs no context or device.
+ *   G         groups, 1 .. 64.
+ *   edges_eV  [G + 1] [host] increasing group edges in eV, edges_eV[0] > 0;
+ *             edges_eV[G] may be +infinity.
+ *   T_bb      blackbody temperature in K, > 0.
+ *   sigma_N, sigma_E [G][3] [host] out: number- and energy-weighted group
+ *             cross sections in cm^2, species H0, He0, He+.
+ *   eps       [G] [host] out: mean photon energy of each group in erg.
+ *   frac      [G] [host] out or NULL: the fraction of the photons above
+ *             edges_eV[0] in each group (a source of Ndot photons/s above
+ *             edges_eV[0] has group luminosities eps_i frac_i Ndot).
+ * Errors: RT_EINVAL (edges, temperature, a group without photons). */
+rt_status rt_photon_groups(int32_t G, const double *edges_eV, double T_bb, double *sigma_N,
+                           double *sigma_E, double *eps, double *frac);
+
+/* Photon removal of the thermochemistry step (Part III "Third step:
+ * Thermochemistry"), in place on U: forward Euler over dt with the number
+ * densities of the absorbing species averaged over the step,
+ *   U_kg <- U_kg max(0, 1 - c dt sum_j sigma_gj (n_old_kj + n_new_kj)/2)
+ * for E and F alike, c = c_red of the context.  A factor below zero (more
+ * photons absorbed than present) is clamped to zero.
+ *   U       [n][G][4] in/out, the context's state type.
+ *   J       absorbing species, 1 .. 8.
+ *   n_old   [n][J] double, densities at the start of the step (Morton order).
+ *   n_new   [n][J] double or NULL (constant densities): at the end of the step.
+ *   sigma   [G][J] double: group cross sections, in units consistent with n,
+ *           c and dt (e.g. sigma_N of rt_photon_groups, rescaled).
+ *   dt      [1] device.
+ *   photon_total [G] out or NULL: Q_g of the updated U.
+ *   absorbed [G] accumulated or NULL: sum_k V_k (E_kg before - E_kg after).
+ * n_old, n_new and sigma must not overlap U. */
+rt_status rt_absorb(rt_ctx *ctx, void *U, int32_t J, const double *n_old, const double *n_new,
+                    const double *sigma, const double *dt, double *photon_total,
+                    double *absorbed);
+
 /* Individual power-of-two time steps (Part II "Individual time steps",
  * eq:meshless-explicit-individual-timesteps; Part III eq:transport-update-
  * explicit with min{dt_k, dt_l}; the factor-4 limiter of Part III "Dynamic

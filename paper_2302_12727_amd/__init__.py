@@ -5,6 +5,7 @@ arXiv:2302.12727 (Part III) on the Hopkins finite volume particle method
 (Part II), as a C-ABI HIP library (include/rt.h, libgearrt.so) with a thin
 torch binding (`rt.RT`) and a differentiable rollout (`rollout.RTRollout`).
 """
-from .rt import RT, RTError, load_library, hll_speed_table, KAPPA, ETA  # noqa: F401
+from .rt import RT, RTError, load_library, hll_speed_table, photon_groups, KAPPA, ETA  # noqa: F401
 
-__all__ = ["RT", "RTError", "load_library", "hll_speed_table", "KAPPA", "ETA"]
+__all__ = ["RT", "RTError", "load_library", "hll_speed_table", "photon_groups", "KAPPA",
+           "ETA"]

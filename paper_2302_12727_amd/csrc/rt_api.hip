@@ -113,7 +113,7 @@ void rt_destroy(rt_ctx *ctx) {
                     ctx->n_gath, ctx->wave_base, ctx->nbr, ctx->src_h, ctx->inj_gptr,
                     ctx->inj_gas, ctx->inj_src, ctx->inj_coef, ctx->inj_xi, ctx->src_ptr,
                     ctx->src_gas, ctx->src_coef, ctx->status, ctx->partials, ctx->scan_tmp,
-                    ctx->adj_buf, ctx->hll_table};
+                    ctx->adj_buf, ctx->hll_table, ctx->vol};
     for (void *b : bufs) rt_free(b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -208,6 +208,41 @@ rt_status rt_get_hll_table(rt_ctx *ctx, double *tab) {
     std::vector<double> t = rt_hll_speed_table(RT_HLL_NF, RT_HLL_NMU);
     memcpy(tab, t.data(), sizeof(double) * t.size());
     return RT_OK;
+}
+
+rt_status rt_photon_groups(int32_t G, const double *edges_eV, double T_bb, double *sigma_N,
+                           double *sigma_E, double *eps, double *frac) {
+    if (G < 1 || G > 64) return rt_fail(nullptr, RT_EINVAL, "G must be in 1 .. 64");
+    if (!edges_eV || !sigma_N || !sigma_E || !eps)
+        return rt_fail(nullptr, RT_EINVAL, "edges_eV, sigma_N, sigma_E and eps are required");
+    if (!finite_pos(T_bb)) return rt_fail(nullptr, RT_EINVAL, "T_bb must be positive");
+    if (!finite_pos(edges_eV[0])) return rt_fail(nullptr, RT_EINVAL, "edges_eV[0] must be positive");
+    for (int32_t i = 0; i < G; ++i) {
+        if (!(edges_eV[i + 1] > edges_eV[i]))
+            return rt_fail(nullptr, RT_EINVAL, "edges_eV must increase");
+        if (i + 1 < G && !finite_pos(edges_eV[i + 1]))
+            return rt_fail(nullptr, RT_EINVAL, "only the last edge may be infinite");
+    }
+    std::string err;
+    rt_status rs = rt_photon_groups_impl(G, edges_eV, T_bb, sigma_N, sigma_E, eps, frac, err);
+    if (rs != RT_OK) return rt_fail(nullptr, rs, err);
+    return RT_OK;
+}
+
+rt_status rt_absorb(rt_ctx *ctx, void *U, int32_t J, const double *n_old, const double *n_new,
+                    const double *sigma, const double *dt, double *photon_total,
+                    double *absorbed) {
+    if (!ctx) return RT_EINVAL;
+    if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
+    if (!U || !n_old || !sigma || !dt)
+        return rt_fail(ctx, RT_EINVAL, "U, n_old, sigma and dt are required");
+    if (J < 1 || J > 8) return rt_fail(ctx, RT_EINVAL, "J must be in 1 .. 8");
+    size_t es = ctx->p.precision == RT_FP64 ? 8 : 4;
+    size_t nu = es * 4 * ctx->p.groups * ctx->p.n, nn = sizeof(double) * J * ctx->p.n;
+    if (overlap(U, nu, n_old, nn) || (n_new && overlap(U, nu, n_new, nn)) ||
+        overlap(U, nu, sigma, sizeof(double) * J * ctx->p.groups))
+        return rt_fail(ctx, RT_EINVAL, "n_old, n_new and sigma must not overlap U");
+    return rt_absorb_impl(ctx, U, J, n_old, n_new, sigma, dt, photon_total, absorbed);
 }
 
 rt_status rt_time_bins(rt_ctx *ctx, int32_t max_bin, int32_t *bins, int64_t *cycle_ticks) {

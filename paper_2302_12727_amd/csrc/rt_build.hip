@@ -509,7 +509,8 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     rt_free(ctx->xs); rt_free(ctx->geo); rt_free(ctx->geo32); rt_free(ctx->perm32);
     rt_free(ctx->keys); rt_free(ctx->h_iters); rt_free(ctx->node_lo); rt_free(ctx->node_hi);
     rt_free(ctx->node_hmax); rt_free(ctx->n_nbr); rt_free(ctx->n_gath); rt_free(ctx->wave_base);
-    rt_free(ctx->nbr);
+    rt_free(ctx->nbr); rt_free(ctx->vol);
+    ctx->vol = nullptr;
     ctx->xs = nullptr; ctx->geo = nullptr; ctx->geo32 = nullptr; ctx->perm32 = nullptr;
     ctx->keys = nullptr; ctx->h_iters = nullptr; ctx->node_lo = nullptr; ctx->node_hi = nullptr;
     ctx->node_hmax = nullptr; ctx->n_nbr = nullptr; ctx->n_gath = nullptr;
@@ -661,6 +662,10 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     rt_free(keys_in); rt_free(idx_in); rt_free(Htmp); rt_free(width); rt_free(dxpart);
     rt_free(sort_tmp);
     if ((rs = rt_ensure_partials(ctx)) != RT_OK) return rs;
+    // compact copy of the volumes for the per-particle kernels that need
+    // nothing else of the geometry record
+    if ((rs = rt_alloc(ctx, (void **)&ctx->vol, sizeof(double) * n)) != RT_OK) return rs;
+    RT_HIP(hipMemcpyAsync(ctx->vol, V, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     ctx->built = 1;
     ctx->bin_top = -1;   // the records were rewritten with all time bins 0
     return RT_OK;

@@ -55,6 +55,7 @@ struct rt_ctx {
     // sorted particles and geometry
     double *xs = nullptr;        // [n][3] Morton-ordered positions
     double *geo = nullptr;       // [n][kRec]
+    double *vol = nullptr;       // [n] V_i (copy of the record's slot R_V)
     float *geo32 = nullptr;      // [n][F_REC] (FP32C only)
     int32_t *perm32 = nullptr;   // [n]
     uint64_t *keys = nullptr;    // [n] sorted Morton keys
@@ -271,6 +272,14 @@ void rt_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *Uout,
 void rt_adjoint32(rt_ctx *ctx, const float *UD, const float *Uung, const float *lam_next,
                   float *lam2, float *R, float *lam, const double *dt);
 rt_status rt_ensure_partials(rt_ctx *ctx);
+void rt_finalize_partials(rt_ctx *ctx, int64_t nb, double *Q, double *ledger);
+
+// photo-absorption (rt_absorb.hip): group constants on the host, removal kernel
+rt_status rt_photon_groups_impl(int32_t G, const double *edges_eV, double T_bb, double *sigma_N,
+                                double *sigma_E, double *eps, double *frac, std::string &err);
+rt_status rt_absorb_impl(rt_ctx *ctx, void *U, int32_t J, const double *n_old,
+                         const double *n_new, const double *sigma, const double *dt, double *Q,
+                         double *absorbed);
 
 // individual time steps (rt_bins.hip; the binned gradient and transport in rt_step.hip)
 rt_status rt_time_bins_impl(rt_ctx *ctx, int32_t max_bin, int32_t *bins, int64_t *cycle);

@@ -452,6 +452,12 @@ void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, d
 
 }  // namespace
 
+// Combine nb rows of ctx->partials into Q (columns 0..G-1, written) and
+// ledger (columns G..2G-1, accumulated); either may be NULL.
+void rt_finalize_partials(rt_ctx *ctx, int64_t nb, double *Q, double *ledger) {
+    k_finalize<<<1, kBlock, 0, ctx->stream>>>(nb, ctx->p.groups, ctx->partials, Q, ledger);
+}
+
 rt_status rt_ensure_partials(rt_ctx *ctx) {
     const int64_t nb = (ctx->p.n + kBlock - 1) / kBlock;
     if (ctx->partials && ctx->nblocks >= nb) return RT_OK;

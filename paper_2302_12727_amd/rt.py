@@ -32,7 +32,7 @@ EXPORTED = ["rt_create", "rt_destroy", "rt_last_error", "rt_set_stream", "rt_bui
             "rt_set_sources", "rt_inject", "rt_gradient", "rt_transport", "rt_photon_total",
             "rt_adjoint", "rt_sync", "rt_get_stats", "rt_get_geometry", "rt_get_neighbours",
             "rt_get_sources", "rt_timing", "rt_get_timing", "rt_time_bins", "rt_tick",
-            "rt_set_riemann", "rt_get_hll_table"]
+            "rt_set_riemann", "rt_get_hll_table", "rt_photon_groups", "rt_absorb"]
 
 
 class RTError(RuntimeError):
@@ -86,6 +86,8 @@ def load_library() -> ctypes.CDLL:
     L.rt_adjoint.argtypes = [_VP] * 9
     L.rt_time_bins.argtypes = [_VP, i32, _VP, ctypes.POINTER(ctypes.c_int64)]
     L.rt_tick.argtypes = [_VP, _VP, _VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP]
+    L.rt_photon_groups.argtypes = [i32, _VP, ctypes.c_double, _VP, _VP, _VP, _VP]
+    L.rt_absorb.argtypes = [_VP, _VP, i32, _VP, _VP, _VP, _VP, _VP, _VP]
     L.rt_set_riemann.argtypes = [_VP, i32]
     L.rt_get_hll_table.argtypes = [_VP, _VP]
     L.rt_sync.argtypes = [_VP]
@@ -126,6 +128,21 @@ def hll_speed_table() -> np.ndarray:
     if st != RT_OK:
         raise RTError(st, L.rt_last_error(None).decode())
     return tab
+
+
+def photon_groups(edges_eV, T_bb: float):
+    """Group constants of the library (host code): returns (sigma_N [G][3],
+    sigma_E [G][3] in cm^2 for H0, He0, He+; eps [G] in erg; frac [G])."""
+    L = load_library()
+    e = np.ascontiguousarray(edges_eV, dtype=np.float64)
+    G = e.size - 1
+    sN, sE = np.zeros((G, 3)), np.zeros((G, 3))
+    eps, frac = np.zeros(G), np.zeros(G)
+    vp = lambda a: ctypes.c_void_p(a.ctypes.data)
+    st = L.rt_photon_groups(G, vp(e), float(T_bb), vp(sN), vp(sE), vp(eps), vp(frac))
+    if st != RT_OK:
+        raise RTError(st, L.rt_last_error(None).decode())
+    return sN, sE, eps, frac
 
 
 class RT:
@@ -214,6 +231,29 @@ class RT:
         dt = self.dt if dt is None else dt
         self._bind_stream()
         self._check(self.L.rt_inject(self.ctx, _ptr(U), _ptr(L), _ptr(dt)))
+
+    def rt_absorb(self, U: torch.Tensor, n_old: torch.Tensor, sigma: torch.Tensor,
+                  n_new: Optional[torch.Tensor] = None, dt: Optional[torch.Tensor] = None,
+                  photon_total: Optional[torch.Tensor] = None,
+                  absorbed: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Photon removal of the thermochemistry step, in place on U."""
+        _need(U, "U", self.sdtype, (self.n, self.G, 4))
+        _need(sigma, "sigma", torch.float64)
+        if sigma.dim() != 2 or sigma.shape[0] != self.G:
+            raise ValueError(f"sigma must have shape ({self.G}, J)")
+        J = int(sigma.shape[1])
+        _need(n_old, "n_old", torch.float64, (self.n, J))
+        if n_new is not None:
+            _need(n_new, "n_new", torch.float64, (self.n, J))
+        if photon_total is not None:
+            _need(photon_total, "photon_total", torch.float64, (self.G,))
+        if absorbed is not None:
+            _need(absorbed, "absorbed", torch.float64, (self.G,))
+        dt = self.dt if dt is None else dt
+        self._bind_stream()
+        self._check(self.L.rt_absorb(self.ctx, _ptr(U), J, _ptr(n_old), _ptr(n_new),
+                                     _ptr(sigma), _ptr(dt), _ptr(photon_total), _ptr(absorbed)))
+        return U
 
     def rt_gradient(self, U: torch.Tensor, UD: Optional[torch.Tensor] = None) -> torch.Tensor:
         _need(U, "U", self.sdtype, (self.n, self.G, 4))
