@@ -115,6 +115,9 @@ def lib():
         L.orc_dt.argtypes = [ctypes.c_int64, _d, ctypes.c_double, ctypes.c_double]
         L.orc_num_threads.restype = ctypes.c_int32
         L.orc_num_threads.argtypes = []
+        L.orc_drift.restype = None
+        L.orc_drift.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d, _d, ctypes.c_double,
+                                _d, _i64, _d]
         L.orc_absorb.restype = None
         L.orc_absorb.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d, _d, _d,
                                  _d, ctypes.c_double, ctypes.c_double, _d, _d]
@@ -502,6 +505,22 @@ def photon_total(geom: Geometry, U: np.ndarray) -> np.ndarray:
     Q = np.zeros(U.shape[1])
     lib().orc_photon_total(U.shape[0], U.shape[1], _p(geom.V), _p(U), _p(Q))
     return Q
+
+
+def drift(geom: Geometry, U: np.ndarray, dx: np.ndarray, dU: Optional[np.ndarray] = None):
+    """Drift correction (rt_oracle.c orc_drift): U extrapolated by the
+    displacements dx [n][3] with its gradients (computed when dU is None).
+    Returns (U_new, counts[4], ledger[G])."""
+    U = _f64(U)
+    dU = gradient(geom, U) if dU is None else _f64(dU)
+    dx = _f64(dx)
+    n, G = U.shape[:2]
+    out = np.empty_like(U)
+    counts = np.zeros(4, dtype=np.int64)
+    ledger = np.zeros(G)
+    lib().orc_drift(n, G, _p(U), _p(dU), _p(dx), _p(geom.V), geom.c, _p(out),
+                    _p(counts, _i64), _p(ledger))
+    return out, counts, ledger
 
 
 def absorb(geom: Geometry, U: np.ndarray, n_old: np.ndarray, sigma: np.ndarray, dt: float,

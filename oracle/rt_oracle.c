@@ -762,6 +762,35 @@ void orc_transport_binned(int64_t n, int32_t G, const double *x, const double *h
 }
 
 /* ------------------------------------------------------------------------ */
+/* Drift correction (Part III "Dealing With Particle Drifts"): a particle
+ * moved by dx carries U(x + dx) = U(x) + grad U(x) . dx per component, with
+ * the gradients of eq:gradient (dU [n][G][4][3], as orc_gradient writes
+ * them).  Reading: the moved state is guarded like the updated state of a
+ * transport step (guard_state); counts[2], counts[3] and ledger[G] are
+ * accumulated as there.                                                     */
+void orc_drift(int64_t n, int32_t G, const double *U, const double *dU, const double *dx,
+               const double *V, double c, double *Uout, int64_t *counts, double *ledger)
+{
+    for (int32_t g = 0; g < G; ++g) {
+        double led = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            double q[4];
+            for (int m = 0; m < 4; ++m) {
+                const double *gr = dU + ((k * G + g) * 4 + m) * 3;
+                q[m] = U[(k * G + g) * 4 + m] + gr[0] * dx[3 * k] + gr[1] * dx[3 * k + 1] +
+                       gr[2] * dx[3 * k + 2];
+            }
+            double Epre = q[0];
+            int f = guard_state(q, c);
+            if (f & 1) { counts[2]++; led += -Epre * V[k]; }
+            counts[3] += (f >> 1) & 1;
+            for (int m = 0; m < 4; ++m) Uout[(k * G + g) * 4 + m] = q[m];
+        }
+        ledger[g] += led;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Photon removal of the thermochemistry step (Part III "Third step:
  * Thermochemistry"): forward Euler over dt with the number densities of the
  * absorbing species averaged over the step,
