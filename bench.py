@@ -243,9 +243,12 @@ def compare_time_bins(w, dev, max_bin: int = 8, cycles: int = 2):
 
 def absorb_leg(w, dev, precision="fp64", reps=50, J=3):
     """The photon removal of the thermochemistry step on workload w's states
-    with synthetic species densities at both ends of the step: average launch
-    time over `reps` launches, against the HBM roofline at its algorithmic
-    bytes (U read and written, both density arrays, the volumes)."""
+    with synthetic species densities at both ends of the step, then the drift
+    correction of the same states with synthetic displacements: average
+    launch times over `reps` launches each, against the HBM roofline at their
+    algorithmic bytes (removal: U read and written, both density arrays, the
+    volumes; drift: the gradient records and displacements read, the moved
+    states written)."""
     import numpy as np
     import torch
     from paper_2302_12727_amd import RT
@@ -272,9 +275,27 @@ def absorb_leg(w, dev, precision="fp64", reps=50, J=3):
     elem = 8 if precision == "fp64" else 4
     nbytes = w.n * (2 * 4 * w.groups * elem + 2 * J * 8 + 8)
     t = ms / nl * 1e-3
-    return {"workload": w.name, "n": w.n, "groups": w.groups, "species": J,
-            "precision": precision, "ms": ms / nl, "algorithmic_bytes": nbytes,
-            "achieved_TBps": nbytes / t / 1e12, "hbm_frac": nbytes / t / PEAK_HBM}
+    res = {"workload": w.name, "n": w.n, "groups": w.groups, "species": J,
+           "precision": precision, "ms": ms / nl, "algorithmic_bytes": nbytes,
+           "achieved_TBps": nbytes / t / 1e12, "hbm_frac": nbytes / t / PEAK_HBM}
+    # the drift correction on the same states: gradient records and
+    # displacements in, moved states out
+    UD = rt.rt_gradient(U)
+    dx = torch.from_numpy(g.uniform(-1e-3, 1e-3, size=(w.n, 3))).to(dev)
+    Ud = torch.empty_like(U)
+    rt.rt_drift(UD, dx, U_out=Ud)
+    torch.cuda.synchronize()
+    rt.rt_timing(True)
+    for _ in range(reps):
+        rt.rt_drift(UD, dx, U_out=Ud)
+    torch.cuda.synchronize()
+    rt.rt_timing(False)
+    ms, nl = rt.rt_get_timing("drift")
+    nbytes = w.n * (w.groups * (16 + 4) * elem + 3 * 8)
+    t = ms / nl * 1e-3
+    res["drift"] = {"ms": ms / nl, "algorithmic_bytes": nbytes,
+                    "achieved_TBps": nbytes / t / 1e12, "hbm_frac": nbytes / t / PEAK_HBM}
+    return res
 
 
 def large_adjoint(dev):

@@ -212,6 +212,25 @@ rt_status rt_absorb(rt_ctx *ctx, void *U, int32_t J, const double *n_old, const 
                     const double *sigma, const double *dt, double *photon_total,
                     double *absorbed);
 
+/* Drift correction (Part III "Dealing With Particle Drifts"): the state of a
+ * particle moved by dx_i (its velocity times the drift time) is extrapolated
+ * with its own gradients,
+ *   U_out_i = U_i + grad U_i . dx_i     for every group and component,
+ * then guarded as rt_transport guards the updated state (E < 0 -> 0 with
+ * F = 0, |F| > cE -> scaled to cE).  Not conservative, as the thesis notes.
+ * The geometry stays where it was: rebuild it with rt_build_cells at the new
+ * positions before the next gradient or transport.
+ *   UD      [n][G][16] in: gradient record of the state (rt_gradient),
+ *           16-byte aligned.
+ *   dx      [n][3] double: displacements (Morton order).
+ *   U_out   [n][G][4] out, must not overlap UD or dx.
+ *   photon_total [G] out or NULL: Q_g of U_out.
+ *   counts  [RT_NCOUNTS] accumulated or NULL: moved states with E clipped
+ *           (slot RT_CNT_CELL_E) or F rescaled (RT_CNT_CELL_F).
+ *   ledger  [G] accumulated or NULL: sum_k V_k (energy added by the E clip). */
+rt_status rt_drift(rt_ctx *ctx, const void *UD, const double *dx, void *U_out,
+                   double *photon_total, int64_t *counts, double *ledger);
+
 /* Individual power-of-two time steps (Part II "Individual time steps",
  * eq:meshless-explicit-individual-timesteps; Part III eq:transport-update-
  * explicit with min{dt_k, dt_l}; the factor-4 limiter of Part III "Dynamic

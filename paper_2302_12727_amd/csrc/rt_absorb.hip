@@ -134,8 +134,10 @@ rt_status rt_photon_groups_impl(int32_t G, const double *edges, double T_bb, dou
 
 namespace {
 
-// One thread per state (particle k, group g) of the [n][G] states, each
-// thread a fixed stride of states: U_kg *= max(0, 1 - c dt sum_j sigma_gj
+// One thread per state (particle k, group g) of the [n][G] states: block b
+// owns the kBlock G states from b kBlock G on, in G rounds of kBlock
+// consecutive states (consecutive lanes read consecutive states), all rounds'
+// loads issued before the first use.  U_kg *= max(0, 1 - c dt sum_j sigma_gj
 // nbar_kj), nbar the average of the densities at the two ends of the step.
 // Block partials [nb][2G]: photon totals after the removal (columns 0..G-1)
 // and the removed energy sum_k V_k dE_kg (columns G..2G-1).
@@ -152,11 +154,14 @@ __global__ __launch_bounds__(kBlock) void k_absorb(int64_t n, int J, const doubl
     __syncthreads();
     const double cdt = c * dtp[0];
     const int64_t ns = n * G;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t s0 = (int64_t)blockIdx.x * kBlock * G + threadIdx.x;
     double red[2 * G];
 #pragma unroll
     for (int p = 0; p < 2 * G; ++p) red[p] = 0.0;
-    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < ns; s += stride) {
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+        const int64_t s = s0 + (int64_t)r * kBlock;
+        if (s >= ns) break;
         const int64_t k = s / G;
         const int g = (int)(s - k * G);
         double kap = 0.0;
@@ -198,10 +203,8 @@ rt_status rt_absorb_impl(rt_ctx *ctx, void *U, int32_t J, const double *n_old,
                          double *absorbed) {
     const int64_t n = ctx->p.n;
     const int G = ctx->p.groups;
-    // about 8 states per thread; never more blocks than the partials buffer
-    // (sized for one block per kBlock particles) holds
-    int64_t nb = (n * G + 8 * kBlock - 1) / (8 * kBlock);
-    nb = std::max<int64_t>(1, std::min(nb, ctx->nblocks));
+    // one block per kBlock particles: the rows of the partials buffer
+    const int64_t nb = (n + kBlock - 1) / kBlock;
     rt_timer_begin(ctx, "absorb");
 #define RT_ABSORB_CASE(GG)                                                                  \
     case GG:                                                                                \

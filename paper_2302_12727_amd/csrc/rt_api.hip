@@ -245,6 +245,19 @@ rt_status rt_absorb(rt_ctx *ctx, void *U, int32_t J, const double *n_old, const 
     return rt_absorb_impl(ctx, U, J, n_old, n_new, sigma, dt, photon_total, absorbed);
 }
 
+rt_status rt_drift(rt_ctx *ctx, const void *UD, const double *dx, void *U_out,
+                   double *photon_total, int64_t *counts, double *ledger) {
+    if (!ctx) return RT_EINVAL;
+    if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
+    if (!UD || !dx || !U_out) return rt_fail(ctx, RT_EINVAL, "UD, dx and U_out are required");
+    size_t es = ctx->p.precision == RT_FP64 ? 8 : 4;
+    size_t nu = es * 4 * ctx->p.groups * ctx->p.n, nx = sizeof(double) * 3 * ctx->p.n;
+    if (overlap(UD, 4 * nu, U_out, nu) || overlap(dx, nx, U_out, nu))
+        return rt_fail(ctx, RT_EINVAL, "U_out must not overlap UD or dx");
+    if (!aligned16(UD)) return rt_fail(ctx, RT_EINVAL, "UD must be 16-byte aligned");
+    return rt_drift_impl(ctx, UD, dx, U_out, photon_total, counts, ledger);
+}
+
 rt_status rt_time_bins(rt_ctx *ctx, int32_t max_bin, int32_t *bins, int64_t *cycle_ticks) {
     if (!ctx) return RT_EINVAL;
     if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");

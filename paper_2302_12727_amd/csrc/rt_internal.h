@@ -288,6 +288,10 @@ rt_status rt_tick_impl(rt_ctx *ctx, double *U, const double *L, int64_t tick, do
 rt_status rt_tick_step_impl(rt_ctx *ctx, double *U, double *UD, const double *dt, int64_t tick,
                             double *accm, double *Q, int64_t *counts, double *ledger);
 
+// drift correction (rt_drift.hip)
+rt_status rt_drift_impl(rt_ctx *ctx, const void *UD, const double *dx, void *U_out, double *Q,
+                        int64_t *counts, double *ledger);
+
 // HLL wave speeds (rt_hll.hip): the host table and the solver switch
 std::vector<double> rt_hll_speed_table(int nf, int nmu);
 rt_status rt_set_riemann_impl(rt_ctx *ctx, int32_t solver);

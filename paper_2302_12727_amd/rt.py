@@ -32,7 +32,7 @@ EXPORTED = ["rt_create", "rt_destroy", "rt_last_error", "rt_set_stream", "rt_bui
             "rt_set_sources", "rt_inject", "rt_gradient", "rt_transport", "rt_photon_total",
             "rt_adjoint", "rt_sync", "rt_get_stats", "rt_get_geometry", "rt_get_neighbours",
             "rt_get_sources", "rt_timing", "rt_get_timing", "rt_time_bins", "rt_tick",
-            "rt_set_riemann", "rt_get_hll_table", "rt_photon_groups", "rt_absorb"]
+            "rt_set_riemann", "rt_get_hll_table", "rt_photon_groups", "rt_absorb", "rt_drift"]
 
 
 class RTError(RuntimeError):
@@ -88,6 +88,7 @@ def load_library() -> ctypes.CDLL:
     L.rt_tick.argtypes = [_VP, _VP, _VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP]
     L.rt_photon_groups.argtypes = [i32, _VP, ctypes.c_double, _VP, _VP, _VP, _VP]
     L.rt_absorb.argtypes = [_VP, _VP, i32, _VP, _VP, _VP, _VP, _VP, _VP]
+    L.rt_drift.argtypes = [_VP] * 7
     L.rt_set_riemann.argtypes = [_VP, i32]
     L.rt_get_hll_table.argtypes = [_VP, _VP]
     L.rt_sync.argtypes = [_VP]
@@ -254,6 +255,27 @@ class RT:
         self._check(self.L.rt_absorb(self.ctx, _ptr(U), J, _ptr(n_old), _ptr(n_new),
                                      _ptr(sigma), _ptr(dt), _ptr(photon_total), _ptr(absorbed)))
         return U
+
+    def rt_drift(self, UD: torch.Tensor, dx: torch.Tensor, U_out: Optional[torch.Tensor] = None,
+                 photon_total: Optional[torch.Tensor] = None,
+                 counts: Optional[torch.Tensor] = None,
+                 ledger: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Drift correction: the states of UD extrapolated by the displacements dx."""
+        _need(UD, "UD", self.sdtype, (self.n, self.G, 16))
+        _need(dx, "dx", torch.float64, (self.n, 3))
+        U_out = torch.empty((self.n, self.G, 4), dtype=self.sdtype, device=self.device) \
+            if U_out is None else U_out
+        _need(U_out, "U_out", self.sdtype, (self.n, self.G, 4))
+        if photon_total is not None:
+            _need(photon_total, "photon_total", torch.float64, (self.G,))
+        if counts is not None:
+            _need(counts, "counts", torch.int64, (4,))
+        if ledger is not None:
+            _need(ledger, "ledger", torch.float64, (self.G,))
+        self._bind_stream()
+        self._check(self.L.rt_drift(self.ctx, _ptr(UD), _ptr(dx), _ptr(U_out), _ptr(photon_total),
+                                    _ptr(counts), _ptr(ledger)))
+        return U_out
 
     def rt_gradient(self, U: torch.Tensor, UD: Optional[torch.Tensor] = None) -> torch.Tensor:
         _need(U, "U", self.sdtype, (self.n, self.G, 4))

@@ -5,6 +5,9 @@ FP64 oracle element by element -- smoothing lengths (1e-13 relative), the
 symmetric neighbour sets (exact), the photon totals (1e-12 relative) and every
 state after two whole steps (1e-12 relative per state, as in the small cases).
 
+The same C2 lattice also carries one whole step with the HLL solver and the
+drift correction of every state, element by element against the oracle.
+
 C4 (the adjoint workload: the same lattice with 64 sources, 20 steps,
 checkpoints every 5, loss on 4096 probes): dLoss/dL of the adjoint rollout
 against central finite differences of the GPU forward on 8 luminosities,
@@ -102,6 +105,37 @@ def test_c2_two_steps_every_element(c2):
     log(f"C2 two steps, {n} particles x 3 groups: max state err {err:.2e}, photon total {qerr:.2e}")
     assert err < 1e-12
     assert qerr < 1e-12
+
+
+def test_c2_hll_step_every_element(c2):
+    """The HLL solver (eq:riemann-HLL) at full size: one whole step."""
+    w, geo, srcs = c2
+    rt, p = build(w, h=geo.h)
+    rt.rt_set_riemann("hll")
+    U = rt.step(dev(w.U0[p]), dev(w.L))
+    got = unsort(U.cpu().numpy(), p)
+    ref, _ = oracle.step(geo, srcs, w.U0, w.L, hll=oracle.hll_table())
+    err = state_err(got, ref)
+    log(f"C2 HLL step, {w.n} particles x 3 groups: max state err {err:.2e}")
+    assert err < 1e-12
+
+
+def test_c2_drift_every_element(c2):
+    """The drift correction at full size, errors against the scale of the
+    summed terms (as in the drift tests)."""
+    w, geo, _ = c2
+    rt, p = build(w, h=geo.h)
+    dx = workloads.rng(211).uniform(-0.2 / 128, 0.2 / 128, size=(w.n, 3))
+    UD = rt.rt_gradient(dev(w.U0[p]))
+    got = unsort(rt.rt_drift(UD, dev(dx[p])).cpu().numpy(), p)
+    dU = oracle.gradient(geo, w.U0)
+    ref, _, _ = oracle.drift(geo, w.U0, dx, dU=dU)
+    term = (np.abs(dU) * np.abs(dx)[:, None, None, :]).sum(-1)
+    scale = np.maximum(np.maximum(np.abs(w.U0).max(-1), term.max(-1)),
+                       1e-6 * np.abs(w.U0[..., 0]).mean())
+    err = float((np.abs(got - ref).max(-1) / scale).max())
+    log(f"C2 drift, {w.n} particles x 3 groups: max err {err:.2e}")
+    assert err < 1e-12
 
 
 def test_c4_gradient_vs_finite_differences():
