@@ -136,7 +136,8 @@ def lib():
         L.orc_transport_binned.restype = None
         L.orc_transport_binned.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d, _d, _d,
                                            _d, _i64, _i64, ctypes.c_double, ctypes.c_double,
-                                           _i32, ctypes.c_int64, _d, _d, _d, _d, _i64, _d]
+                                           _i32, ctypes.c_int64, _d, _d, _d, _d, _i64, _d,
+                                           _d, ctypes.c_int32, ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -596,13 +597,15 @@ def active(bins: np.ndarray, tick: int) -> np.ndarray:
 
 
 def run_binned(geom: Geometry, srcs: Optional[Sources], U0: np.ndarray, L, ticks: int,
-               bins: np.ndarray, t0: int = 0, dU=None, acc=None):
+               bins: np.ndarray, t0: int = 0, dU=None, acc=None,
+               hll: Optional[np.ndarray] = None):
     """`ticks` ticks of the individual-time-step scheme from tick t0.  Every
     particle starts with the gradient of U0 (unless dU is given); in tick t the
     particles that end a step inject (with their own dt), recompute their
     gradient, and apply their flux sums, while every pair whose smaller bin ends
-    a step exchanges dt_kl |A| Phi.  Returns (U, info) with info["acc"] (the
-    pending flux sums) and info["dU"] (the stored gradients)."""
+    a step exchanges dt_kl |A| Phi (GLF, or HLL with the table `hll`).
+    Returns (U, info) with info["acc"] (the pending flux sums) and info["dU"]
+    (the stored gradients)."""
     U = _f64(U0).copy()
     n, G = U.shape[0], U.shape[1]
     bins = np.ascontiguousarray(bins, dtype=np.int32)
@@ -611,6 +614,7 @@ def run_binned(geom: Geometry, srcs: Optional[Sources], U0: np.ndarray, L, ticks
     counts = np.zeros(4, dtype=np.int64)
     ledger = np.zeros(G)
     Lm = _f64(L) if (srcs is not None and srcs.src.size) else None
+    tab = None if hll is None else _f64(hll)
     for t in range(t0, t0 + ticks):
         act = active(bins, t)
         if Lm is not None:
@@ -624,7 +628,9 @@ def run_binned(geom: Geometry, srcs: Optional[Sources], U0: np.ndarray, L, ticks
                                    _p(_f64(geom.B)), _p(geom.box), _p(geom.sptr, _i64),
                                    _p(geom.sidx, _i64), geom.c, geom.dt, _p(bins, _i32), t,
                                    _p(U), _p(dU), _p(acc), _p(out), _p(counts, _i64),
-                                   _p(ledger))
+                                   _p(ledger), None if tab is None else _p(tab),
+                                   0 if tab is None else tab.shape[0],
+                                   0 if tab is None else tab.shape[1])
         U = out
     return U, {"acc": acc, "dU": dU, "counts": counts, "ledger": ledger}
 

@@ -695,7 +695,8 @@ void orc_transport_binned(int64_t n, int32_t G, const double *x, const double *h
                           const double *box, const int64_t *sptr, const int64_t *sidx,
                           double c, double dtmin, const int32_t *bin, int64_t t,
                           const double *U, const double *dU, double *acc, double *Uout,
-                          int64_t *counts, double *ledger)
+                          int64_t *counts, double *ledger, const double *tab, int32_t nf,
+                          int32_t nmu)
 {
     const int64_t nq = 4 * (int64_t)G;
     int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
@@ -731,7 +732,8 @@ void orc_transport_binned(int64_t n, int32_t G, const double *x, const double *h
                 int fl = guard_state(qL, c), fr = guard_state(qR, c);
                 c0 += (fl & 1) + (fr & 1);
                 c1 += ((fl >> 1) & 1) + ((fr >> 1) & 1);
-                orc_glf(qL, qR, nh, c, phi);
+                if (tab) orc_hll(qL, qR, nh, c, tab, nf, nmu, phi);
+                else orc_glf(qL, qR, nh, c, phi);
                 for (int m = 0; m < 4; ++m) ak[4 * g + m] += dtkl * An * phi[m];
             }
         }

@@ -105,3 +105,24 @@ def test_hll_step_conserves_photons(tab):
     assert np.abs(Q1 / Q0 - 1).max() < 1e-13
     glf, _ = oracle.step(geo, None, U0)
     assert np.abs(out - glf).max() > 1e-6 * np.abs(glf).max()   # a different solver
+
+
+def test_binned_hll_reduces_to_the_global_step(tab):
+    # individual time steps with every particle in bin 0 are the global step,
+    # and with every particle in bin 1 two ticks are one global step of 2 dt
+    w = workloads.lattice_workload(9, 2, 2, 3, seed=78, name="hllbins")
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs)
+    def state_err(got, ref):      # per state, floored for states a guard emptied
+        scale = np.maximum(np.abs(ref).max(axis=-1), 1e-6 * np.abs(ref[..., 0]).mean())
+        return float((np.abs(got - ref).max(axis=-1) / scale).max())
+
+    ref, _ = oracle.run(geo, srcs, w.U0, w.L, 3, hll=tab)
+    got, info = oracle.run_binned(geo, srcs, w.U0, w.L, 3, np.zeros(geo.n, np.int32), hll=tab)
+    assert state_err(got, ref) < 1e-12
+    assert not info["acc"].any()
+    ref2, _ = oracle.step(geo, srcs, w.U0, w.L, dt=2.0 * geo.dt, hll=tab)
+    got2, _ = oracle.run_binned(geo, srcs, w.U0, w.L, 2, np.ones(geo.n, np.int32), hll=tab)
+    assert state_err(got2, ref2) < 1e-12
+    glf, _ = oracle.run_binned(geo, srcs, w.U0, w.L, 3, np.zeros(geo.n, np.int32))
+    assert np.abs(glf - got).max() > 1e-6 * np.abs(got).max()
