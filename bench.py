@@ -478,6 +478,12 @@ def main():
                           "transport_time_vs_glf": fh["transport_ms"] / fw_transport_ms,
                           "photon_budget_residual": fh["photon_budget_residual"]}
             del fh
+            fh = run_forward(w, "fp32c", args.steps, args.warmup, dev, solver="hll")
+            out["hll"]["fp32c"] = {"value": fh["pairs"] * args.steps / fh["elapsed"],
+                                   "ms_per_step": fh["elapsed"] / args.steps * 1e3,
+                                   "kernel_ms": {"transport": fh["transport_ms"],
+                                                 "gradient": fh["gradient_ms"]}}
+            del fh
         out["absorb"] = absorb_leg(w, dev)
         torch.cuda.empty_cache()
         wa = workloads.config(3)

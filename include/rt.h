@@ -157,10 +157,10 @@ rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q);
  *           uniform in f on [0, 1] times RT_HLL_NMU nodes uniform in mu on
  *           [-1, 1] and interpolates bilinearly (a state with E <= 0 or F = 0
  *           is looked up at f = 0).
- * HLL is implemented for the global step of FP64 contexts: rt_set_riemann
- * returns RT_EINVAL on an FP32C context, and rt_tick and rt_adjoint return
- * RT_ESTATE while HLL is selected.  The table (RT_HLL_NF x RT_HLL_NMU x 2
- * doubles) is computed on the host and uploaded on the first selection of
+ * HLL is implemented in rt_transport (FP64 and FP32C, the FP32C kernel
+ * interpolating an FP32 copy of the table) and in rt_tick; rt_adjoint
+ * returns RT_ESTATE while HLL is selected.  The table (RT_HLL_NF x RT_HLL_NMU
+ * x 2 doubles) is computed on the host and uploaded on the first selection of
  * RT_HLL (synchronous). */
 typedef enum { RT_GLF = 0, RT_HLL = 1 } rt_riemann;
 #define RT_HLL_NF 65
@@ -252,7 +252,8 @@ rt_status rt_time_bins(rt_ctx *ctx, int32_t max_bin, int32_t *bins, int64_t *cyc
  * multiple of 2^b_i.  In the tick, the particles that end a step inject with
  * their own dt_i (sources set) and recompute their gradient record from the
  * current states; every pair whose smaller bin ends a step exchanges
- * dt 2^min(b_k, b_l) |A| Phi_kl (the GLF flux of rt_transport) into the flux
+ * dt 2^min(b_k, b_l) |A| Phi_kl (the flux of rt_transport, GLF or HLL as
+ * selected by rt_set_riemann) into the flux
  * sums of both particles; the particles that end a step apply
  * U - (flux sum) / V, guard the result as rt_transport does, and clear their
  * sums.

@@ -113,7 +113,7 @@ void rt_destroy(rt_ctx *ctx) {
                     ctx->n_gath, ctx->wave_base, ctx->nbr, ctx->src_h, ctx->inj_gptr,
                     ctx->inj_gas, ctx->inj_src, ctx->inj_coef, ctx->inj_xi, ctx->src_ptr,
                     ctx->src_gas, ctx->src_coef, ctx->status, ctx->partials, ctx->scan_tmp,
-                    ctx->adj_buf, ctx->hll_table, ctx->vol};
+                    ctx->adj_buf, ctx->hll_table, ctx->hll_table32, ctx->vol};
     for (void *b : bufs) rt_free(b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -198,8 +198,6 @@ rt_status rt_set_riemann(rt_ctx *ctx, int32_t solver) {
     if (!ctx) return RT_EINVAL;
     if (solver != RT_GLF && solver != RT_HLL)
         return rt_fail(ctx, RT_EINVAL, "solver must be RT_GLF or RT_HLL");
-    if (solver == RT_HLL && ctx->p.precision != RT_FP64)
-        return rt_fail(ctx, RT_EINVAL, "the HLL solver is implemented for FP64 contexts only");
     return rt_set_riemann_impl(ctx, solver);
 }
 
@@ -275,8 +273,6 @@ rt_status rt_tick(rt_ctx *ctx, double *U, const double *L, int64_t tick, double 
         return rt_fail(ctx, RT_EINVAL, "time bins are implemented for FP64 contexts only");
     if (!U || !UD || !acc) return rt_fail(ctx, RT_EINVAL, "U, UD and acc are required");
     if (tick < 0) return rt_fail(ctx, RT_EINVAL, "tick must be >= 0");
-    if (ctx->solver != RT_GLF)
-        return rt_fail(ctx, RT_ESTATE, "individual time steps use the GLF solver");
     if (ctx->S > 0 && !L) return rt_fail(ctx, RT_EINVAL, "L is required when sources are set");
     size_t nu = sizeof(double) * 4 * ctx->p.groups * ctx->p.n;
     if (overlap(UD, 4 * nu, U, nu) || overlap(UD, 4 * nu, acc, nu) || overlap(U, nu, acc, nu))

@@ -85,9 +85,14 @@ std::vector<double> rt_hll_speed_table(int nf, int nmu) {
 rt_status rt_set_riemann_impl(rt_ctx *ctx, int32_t solver) {
     if (solver == RT_HLL && !ctx->hll_table) {
         std::vector<double> tab = rt_hll_speed_table(RT_HLL_NF, RT_HLL_NMU);
+        std::vector<float> tab32(tab.begin(), tab.end());
         rt_status rs = rt_alloc(ctx, (void **)&ctx->hll_table, sizeof(double) * tab.size());
         if (rs != RT_OK) return rs;
+        rs = rt_alloc(ctx, (void **)&ctx->hll_table32, sizeof(float) * tab32.size());
+        if (rs != RT_OK) return rs;
         RT_HIP(hipMemcpy(ctx->hll_table, tab.data(), sizeof(double) * tab.size(),
+                         hipMemcpyHostToDevice));
+        RT_HIP(hipMemcpy(ctx->hll_table32, tab32.data(), sizeof(float) * tab32.size(),
                          hipMemcpyHostToDevice));
     }
     ctx->solver = solver;

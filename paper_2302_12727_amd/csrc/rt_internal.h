@@ -105,6 +105,7 @@ struct rt_ctx {
     int32_t bin_top = -1;        // largest time bin after rt_time_bins (-1: none)
     int32_t solver = RT_GLF;     // Riemann solver of the transport
     double *hll_table = nullptr; // [RT_HLL_NF][RT_HLL_NMU][2] wave speeds / c
+    float *hll_table32 = nullptr;// the same in FP32 (FP32C contexts)
 
     // timing: event pairs recorded around launches while timing is on
     int timing = 0;

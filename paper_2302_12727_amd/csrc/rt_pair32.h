@@ -78,6 +78,51 @@ __device__ __forceinline__ void m1_flux32(float E, float Fx, float Fy, float Fz,
     out[3] = a * Az + b * Fz;
 }
 
+// HLL wave speeds of one face state in FP32 (eq:riemann-HLL; see
+// hll_speeds64): bilinear in tab[RT_HLL_NF][RT_HLL_NMU] = (l_min, l_max)/c over
+// f = |F|/(cE), clamped to 1, and mu = F.A/(|F||A|), clamped to [-1, 1], both
+// formed from g = F/E as the FP32 closure is; a state with E <= 1e-30 or
+// F = 0 is looked up at f = 0.  Every index stays in the table.
+__device__ __forceinline__ void hll_speeds32(float E, float Fx, float Fy, float Fz, float Ax,
+                                             float Ay, float Az, float iAn, float c, float ic2,
+                                             const float2 *__restrict__ tab, float &lo,
+                                             float &hi) {
+    const float iE = E > 1e-30f ? rcp32(E) : 0.0f;
+    const float gx = Fx * iE, gy = Fy * iE, gz = Fz * iE;
+    const float g2 = gx * gx + gy * gy + gz * gz;
+    float f = 0.0f, mu = 0.0f;
+    if (g2 > 0.0f) {
+        const float ig = __builtin_amdgcn_rsqf(g2);
+        f = fminf(sqrt32(g2 * ic2), 1.0f);
+        mu = fminf(fmaxf((gx * Ax + gy * Ay + gz * Az) * ig * iAn, -1.0f), 1.0f);
+    }
+    const float x = f * (RT_HLL_NF - 1), y = (mu + 1.0f) * (0.5f * (RT_HLL_NMU - 1));
+    const int i = max(min((int)x, RT_HLL_NF - 2), 0);
+    const int j = max(min((int)y, RT_HLL_NMU - 2), 0);
+    const float tx = x - i, ty = y - j;
+    const float2 *t = tab + i * RT_HLL_NMU + j;
+    const float2 v00 = t[0], v01 = t[1], v10 = t[RT_HLL_NMU], v11 = t[RT_HLL_NMU + 1];
+    const float ux = 1.0f - tx, uy = 1.0f - ty;
+    lo = c * (ux * (uy * v00.x + ty * v01.x) + tx * (uy * v10.x + ty * v11.x));
+    hi = c * (ux * (uy * v00.y + ty * v01.y) + tx * (uy * v10.y + ty * v11.y));
+}
+
+// HLL weights of Phi.A = w1 F_L.A + w2 F_R.A + w3 (U_R - U_L) (see hll_weights).
+__device__ __forceinline__ void hll_weights32(float loL, float hiL, float loR, float hiR,
+                                              float An, float &w1, float &w2, float &w3) {
+    const float lp = fmaxf(fmaxf(hiL, hiR), 0.0f), lm = fminf(fminf(loL, loR), 0.0f);
+    const float den = lp - lm;
+    if (den > 0.0f) {
+        const float id = rcp32(den);
+        w1 = lp * id;
+        w2 = -lm * id;
+        w3 = lp * lm * An * id;
+    } else {
+        w1 = w2 = 0.5f;
+        w3 = 0.0f;
+    }
+}
+
 __device__ __forceinline__ float minmod32(float a, float b) {
     const float m = (fabsf(a) <= fabsf(b)) ? a : b;
     return (a * b > 0.0f) ? m : 0.0f;

@@ -434,10 +434,17 @@ void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, d
     const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
     k_gradient64<G, true><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
         n, nb, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box, tick);
-    constexpr int GW = transport_slice(G);
-    k_transport64<G, GW, true><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, ctx->stream>>>(
-        n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
-        ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, tick, accm);
+    constexpr int GW = transport_slice(G), HW = hll_slice(G);
+    if (ctx->solver == RT_HLL)
+        k_transport64<G, HW, true, true><<<(unsigned)xcd_grid(nb * (G / HW)), kBlock, 0,
+                                           ctx->stream>>>(
+            n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
+            ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, tick, accm,
+            (const double2 *)ctx->hll_table);
+    else
+        k_transport64<G, GW, true><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, ctx->stream>>>(
+            n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
+            ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, tick, accm);
 }
 
 #define RT_DISPATCH_G(G_, FN, ...)                                  \

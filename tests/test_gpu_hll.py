@@ -6,7 +6,10 @@ Jacobian), the library its own (closed-form quadratic); the tables agree to
 about 1e-14, so the states agree to the FP64 bar of 1e-12 per state, as for
 GLF.  Cases: the 16^3 lattice (strong fluxes, guards firing), 3 groups with
 sources (one group per wave), ragged sizes, a clustered Plummer set, photon
-conservation without guards, the switch back to GLF, and the refusals.
+conservation without guards, the switch back to GLF, individual time bins
+(mid-cycle states and pending flux sums against the oracle's binned HLL
+scheme), the compensated-FP32 kernel (1e-5 of each neighbourhood's scale, the
+FP32C bar), and the refusals.
 """
 import numpy as np
 import pytest
@@ -14,7 +17,7 @@ import torch
 
 import oracle
 import workloads
-from tests.gpu_util import dev, log, state_err, unsort
+from tests.gpu_util import dev, local_err, log, state_err, unsort
 
 pytestmark = pytest.mark.gpu
 
@@ -140,12 +143,58 @@ def test_refusals():
     w = workloads.lattice_workload(7, 1, 0, 1, seed=950, name="refuse")
     rt, p = gpu_case(w)
     U = dev(w.U0[p])
-    UD = rt.rt_gradient(U)
-    with pytest.raises(RTError, match="RT_ESTATE"):
-        rt.rt_tick(U, None, 0, UD, torch.zeros_like(U))
     with pytest.raises(RTError, match="RT_ESTATE"):
         rt.rt_adjoint(U, None, torch.ones_like(U))
-    rt32 = RT(w.n, w.groups, precision="fp32c")
-    rt32.rt_build_cells(dev(w.x))
     with pytest.raises(RTError, match="RT_EINVAL"):
-        rt32.rt_set_riemann("hll")
+        rt._check(rt.L.rt_set_riemann(rt.ctx, 7))
+
+
+@pytest.mark.parametrize("case", ["lattice16", "plummer"])
+def test_fp32c(tab, case):
+    """The compensated-FP32 kernel with HLL against the FP64 oracle's HLL steps,
+    at the FP32C bar (1e-5 of each neighbourhood's scale)."""
+    if case == "lattice16":
+        w, steps = workloads.config(0), 10
+    else:
+        w, steps = workloads.config(2, scale=(1 << 13) / (1 << 22)), 2
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs) if w.xs.shape[0] else None
+    rt = RT(w.n, w.groups, precision="fp32c")
+    perm, *_ = rt.rt_build_cells(dev(w.x))
+    if w.xs.shape[0]:
+        rt.rt_set_sources(dev(w.xs))
+    rt.rt_set_riemann("hll")
+    p = perm.cpu().numpy()
+    U = dev(w.U0[p]).float()
+    L = dev(w.L) if w.xs.shape[0] else None
+    for _ in range(steps):
+        U = rt.step(U, L)
+    rt.rt_sync()
+    got = unsort(U.double().cpu().numpy(), p)
+    ref, _ = oracle.run(geo, srcs, w.U0, w.L if w.xs.shape[0] else None, steps, hll=tab)
+    err = local_err(got, ref, geo.sptr, geo.sidx)
+    log(f"HLL FP32C {case} {steps} steps: max err {err:.2e} of the neighbourhood scale")
+    assert err < 1e-5
+
+
+def test_time_bins_with_hll(tab):
+    w = workloads.config(2, scale=(1 << 13) / (1 << 22))     # 8192 Plummer + background
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs)
+    rt, p = gpu_case(w)
+    bins, cycle = rt.rt_time_bins(6)
+    ticks = cycle + cycle // 2 + 1                            # mid-cycle: pending sums exist
+    U = dev(w.U0[p])
+    L = dev(w.L)
+    UD = rt.rt_gradient(U)
+    acc = torch.zeros_like(U)
+    for t in range(ticks):
+        rt.rt_tick(U, L, t, UD, acc)
+    rt.rt_sync()
+    ref, info = oracle.run_binned(geo, srcs, w.U0, w.L, ticks, oracle.time_bins(geo, 6), hll=tab)
+    err = state_err(unsort(U.cpu().numpy(), p), ref)
+    acc_err = float(np.abs(unsort(acc.cpu().numpy(), p) - info["acc"]).max()
+                    / (np.abs(ref).max() * geo.V.max()))
+    log(f"HLL time bins, {ticks} ticks: max state err {err:.2e}, pending sums {acc_err:.2e}")
+    assert err < 1e-12
+    assert info["acc"].any() and acc_err < 1e-12
