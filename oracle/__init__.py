@@ -127,6 +127,18 @@ def lib():
         L.orc_transport_hll.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d, _d, _d, _d,
                                         _i64, _i64, ctypes.c_double, ctypes.c_double, _d, _d,
                                         _d, _i64, _d, _d, ctypes.c_int32, ctypes.c_int32]
+        L.orc_transport_ivanova.restype = None
+        L.orc_transport_ivanova.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d, _d, _d,
+                                            _d, _i64, _i64, ctypes.c_double, ctypes.c_double, _d,
+                                            _d, _d, _i64, _d, _d, ctypes.c_int32, ctypes.c_int32,
+                                            _d]
+        L.orc_ivanova_sums.restype = None
+        L.orc_ivanova_sums.argtypes = [ctypes.c_int64, _d, _d, _d, _i64, _i64, _d]
+        L.orc_grad_psi.restype = None
+        L.orc_grad_psi.argtypes = [_d, _d, ctypes.c_double, ctypes.c_double, _d, _d, _d]
+        L.orc_surface_ivanova.restype = None
+        L.orc_surface_ivanova.argtypes = [_d, _d, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, _d, _d, _d, _d]
         L.orc_bins.restype = None
         L.orc_bins.argtypes = [ctypes.c_int64, _d, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, ctypes.c_int32, _i64, _i64, _i32]
@@ -424,10 +436,36 @@ def gradient(geom: Geometry, U: np.ndarray) -> np.ndarray:
     return dU
 
 
+def ivanova_sums(geom: Geometry) -> np.ndarray:
+    """[n][3]: sum_k grad W_k(x_i) over the gather neighbours of each particle
+    (the normalisation-gradient term of the Ivanova surfaces)."""
+    g = np.zeros((geom.n, 3))
+    lib().orc_ivanova_sums(geom.n, _p(geom.x), _p(geom.H), _p(geom.box),
+                           _p(geom.gptr, _i64), _p(geom.gidx, _i64), _p(g))
+    return g
+
+
+def grad_psi(geom: Geometry, gsum: np.ndarray, i: int, j: int) -> np.ndarray:
+    """grad psi_j(x_i) of the Ivanova surfaces (analytic, H_i held fixed)."""
+    out = np.zeros(3)
+    lib().orc_grad_psi(_p(_f64(geom.x[i])), _p(_f64(geom.x[j])), geom.H[i], geom.V[i],
+                       _p(_f64(gsum[i])), _p(geom.box), _p(out))
+    return out
+
+
+def surface_ivanova(geom: Geometry, gsum: np.ndarray, k: int, l: int) -> np.ndarray:
+    A = np.zeros(3)
+    lib().orc_surface_ivanova(_p(_f64(geom.x[k])), _p(_f64(geom.x[l])), geom.H[k], geom.H[l],
+                              geom.V[k], geom.V[l], _p(_f64(gsum[k])), _p(_f64(gsum[l])),
+                              _p(geom.box), _p(A))
+    return A
+
+
 def transport(geom: Geometry, U: np.ndarray, dU: np.ndarray, dt: Optional[float] = None,
-              hll: Optional[np.ndarray] = None):
+              hll: Optional[np.ndarray] = None, ivanova: bool = False):
     """Returns (U_new, counts[4], ledger[G]).  hll: an eigenvalue table
-    (hll_table()) selects the HLL solver instead of GLF."""
+    (hll_table()) selects the HLL solver instead of GLF; ivanova: the Ivanova
+    surfaces (eq:IvanovaAij) instead of the Hopkins ones."""
     U, dU = _f64(U), _f64(dU)
     n, G = U.shape[0], U.shape[1]
     dt = geom.dt if dt is None else dt
@@ -437,7 +475,13 @@ def transport(geom: Geometry, U: np.ndarray, dU: np.ndarray, dt: Optional[float]
     args = (n, G, _p(geom.x), _p(geom.h), _p(geom.H), _p(geom.V), _p(_f64(geom.B)),
             _p(geom.box), _p(geom.sptr, _i64), _p(geom.sidx, _i64), geom.c, dt, _p(U), _p(dU),
             _p(out), _p(counts, _i64), _p(ledger))
-    if hll is None:
+    if ivanova:
+        gsum = ivanova_sums(geom)
+        tab = None if hll is None else _f64(hll)
+        lib().orc_transport_ivanova(*args, None if tab is None else _p(tab),
+                                    0 if tab is None else tab.shape[0],
+                                    0 if tab is None else tab.shape[1], _p(gsum))
+    elif hll is None:
         lib().orc_transport(*args)
     else:
         tab = _f64(hll)
@@ -552,25 +596,26 @@ def surface(geom: Geometry, k: int, l: int) -> np.ndarray:
 
 
 def step(geom: Geometry, srcs: Optional[Sources], U: np.ndarray, L=None,
-         dt: Optional[float] = None, hll: Optional[np.ndarray] = None):
+         dt: Optional[float] = None, hll: Optional[np.ndarray] = None,
+         ivanova: bool = False):
     """One RT step in the operator-splitting order inject -> gradient ->
     transport.  Returns (U_new, info)."""
     U = _f64(U).copy()
     if srcs is not None and srcs.src.size:
         inject(geom, srcs, U, L, dt)
     dU = gradient(geom, U)
-    out, counts, ledger = transport(geom, U, dU, dt, hll=hll)
+    out, counts, ledger = transport(geom, U, dU, dt, hll=hll, ivanova=ivanova)
     return out, {"counts": counts, "ledger": ledger, "U_injected": U, "dU": dU}
 
 
 def run(geom: Geometry, srcs: Optional[Sources], U0: np.ndarray, L, steps: int,
-        keep: bool = False, hll: Optional[np.ndarray] = None):
+        keep: bool = False, hll: Optional[np.ndarray] = None, ivanova: bool = False):
     U = _f64(U0).copy()
     counts = np.zeros(4, dtype=np.int64)
     ledger = np.zeros(U.shape[1])
     states = [U.copy()] if keep else None
     for _ in range(steps):
-        U, info = step(geom, srcs, U, L, hll=hll)
+        U, info = step(geom, srcs, U, L, hll=hll, ivanova=ivanova)
         counts += info["counts"]
         ledger += info["ledger"]
         if keep:

@@ -441,6 +441,65 @@ void orc_surface(const double *xk, const double *xl, double Hk, double Hl, doubl
 }
 
 /* ------------------------------------------------------------------------ */
+/* Ivanova effective surfaces, Part II eq:IvanovaAij:
+ *   A_ij = V_i grad psi_j(x_i) - V_j grad psi_i(x_j),
+ * with the analytic gradients of the partition of unity of the appendix
+ * "Full Expressions For Partitions of Unity And Their Gradients":
+ *   grad psi_j(x_i) = grad W_j(x_i) / omega_i
+ *                     - W(r_ij, H_i) sum_k grad W_k(x_i) / omega_i^2,
+ *   grad W_j(x_i)   = (sigma / H_i^4) w'(r_ij / H_i) (x_i - x_j) / r_ij,
+ * the kernel evaluated with particle i's compact support radius H_i (the
+ * appendix holds h at h(x_i) = h_i), the sum over the gather neighbours of i
+ * (r_ik < H_i; the self term has no gradient), and 1/omega_i = V_i.         */
+static void grad_W(const double *xi, const double *xj, double Hi, const double *box,
+                   double *out)
+{
+    double s[3];
+    sep(xi, xj, box, s);                      /* s = x_j - x_i */
+    double r = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    if (!(r > 0.0)) { out[0] = out[1] = out[2] = 0.0; return; }
+    double f = (16.0 / ORC_PI) / (Hi * Hi * Hi * Hi) * orc_dw(r / Hi) / r;
+    for (int a = 0; a < 3; ++a) out[a] = -f * s[a];
+}
+
+/* gsum[i] = sum_k grad W_k(x_i) over the gather neighbours of i            */
+void orc_ivanova_sums(int64_t n, const double *x, const double *H, const double *box,
+                      const int64_t *gptr, const int64_t *gidx, double *gsum)
+{
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        double g[3] = {0.0, 0.0, 0.0}, d[3];
+        for (int64_t e = gptr[i]; e < gptr[i + 1]; ++e) {
+            grad_W(x + 3 * i, x + 3 * gidx[e], H[i], box, d);
+            for (int a = 0; a < 3; ++a) g[a] += d[a];
+        }
+        for (int a = 0; a < 3; ++a) gsum[3 * i + a] = g[a];
+    }
+}
+
+/* grad psi_j(x_i) (zero beyond the support of W(., H_i))                    */
+void orc_grad_psi(const double *xi, const double *xj, double Hi, double Vi,
+                  const double *gsum_i, const double *box, double *out)
+{
+    double s[3], gW[3];
+    sep(xi, xj, box, s);
+    double r = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    grad_W(xi, xj, Hi, box, gW);
+    double W = orc_W(r, Hi);
+    for (int a = 0; a < 3; ++a) out[a] = Vi * gW[a] - Vi * Vi * W * gsum_i[a];
+}
+
+void orc_surface_ivanova(const double *xk, const double *xl, double Hk, double Hl, double Vk,
+                         double Vl, const double *gk, const double *gl, const double *box,
+                         double *A)
+{
+    double pl[3], pk[3];
+    orc_grad_psi(xk, xl, Hk, Vk, gk, box, pl);     /* grad psi_l(x_k) */
+    orc_grad_psi(xl, xk, Hl, Vl, gl, box, pk);     /* grad psi_k(x_l) */
+    for (int a = 0; a < 3; ++a) A[a] = Vk * pl[a] - Vl * pk[a];
+}
+
+/* ------------------------------------------------------------------------ */
 /* One transport step, Part III "Second step: transport":
  *   U_k(t + dt) = U_k(t) - (1/V_k) sum_l dt Flux_kl . A_kl
  * (eq:transport-update-explicit with one global time step) where Flux_kl is
@@ -462,7 +521,7 @@ static void transport_core(int64_t n, int32_t G, const double *x, const double *
                            const double *box, const int64_t *sptr, const int64_t *sidx,
                            double c, double dt, const double *U, const double *dU,
                            double *Uout, int64_t *counts, double *ledger,
-                           const double *tab, int32_t nf, int32_t nmu);
+                           const double *tab, int32_t nf, int32_t nmu, const double *gsum);
 
 void orc_transport(int64_t n, int32_t G, const double *x, const double *h,
                    const double *H, const double *V, const double *B,
@@ -471,7 +530,7 @@ void orc_transport(int64_t n, int32_t G, const double *x, const double *h,
                    int64_t *counts, double *ledger)
 {
     transport_core(n, G, x, h, H, V, B, box, sptr, sidx, c, dt, U, dU, Uout, counts, ledger,
-                   NULL, 0, 0);
+                   NULL, 0, 0, NULL);
 }
 
 /* The same step with the HLL solver (table as orc_hll) instead of GLF.      */
@@ -483,7 +542,20 @@ void orc_transport_hll(int64_t n, int32_t G, const double *x, const double *h,
                        int32_t nmu)
 {
     transport_core(n, G, x, h, H, V, B, box, sptr, sidx, c, dt, U, dU, Uout, counts, ledger,
-                   tab, nf, nmu);
+                   tab, nf, nmu, NULL);
+}
+
+/* The same step with the Ivanova surfaces (gsum from orc_ivanova_sums) in
+ * place of the Hopkins ones, GLF (tab NULL) or HLL.                         */
+void orc_transport_ivanova(int64_t n, int32_t G, const double *x, const double *h,
+                           const double *H, const double *V, const double *B,
+                           const double *box, const int64_t *sptr, const int64_t *sidx,
+                           double c, double dt, const double *U, const double *dU,
+                           double *Uout, int64_t *counts, double *ledger, const double *tab,
+                           int32_t nf, int32_t nmu, const double *gsum)
+{
+    transport_core(n, G, x, h, H, V, B, box, sptr, sidx, c, dt, U, dU, Uout, counts, ledger,
+                   tab, nf, nmu, gsum);
 }
 
 static void transport_core(int64_t n, int32_t G, const double *x, const double *h,
@@ -491,7 +563,7 @@ static void transport_core(int64_t n, int32_t G, const double *x, const double *
                            const double *box, const int64_t *sptr, const int64_t *sidx,
                            double c, double dt, const double *U, const double *dU,
                            double *Uout, int64_t *counts, double *ledger,
-                           const double *tab, int32_t nf, int32_t nmu)
+                           const double *tab, int32_t nf, int32_t nmu, const double *gsum)
 {
     const int64_t nq = 4 * (int64_t)G;
     int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
@@ -502,8 +574,12 @@ static void transport_core(int64_t n, int32_t G, const double *x, const double *
         for (int64_t e = sptr[k]; e < sptr[k + 1]; ++e) {
             int64_t l = sidx[e];
             double A[3], s[3];
-            orc_surface(x + 3 * k, x + 3 * l, H[k], H[l], V[k], V[l], B + 9 * k,
-                        B + 9 * l, box, A);
+            if (gsum)
+                orc_surface_ivanova(x + 3 * k, x + 3 * l, H[k], H[l], V[k], V[l],
+                                    gsum + 3 * k, gsum + 3 * l, box, A);
+            else
+                orc_surface(x + 3 * k, x + 3 * l, H[k], H[l], V[k], V[l], B + 9 * k,
+                            B + 9 * l, box, A);
             double An = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
             if (!(An > 0.0)) continue;
             double nh[3] = {A[0] / An, A[1] / An, A[2] / An};
