@@ -78,10 +78,12 @@ def cpu_baseline(cfg_index: int, min_seconds: float):
     }
 
 
-def run_forward(w, precision, steps, warmup, dev, timing=True, keep_state=False, solver="glf"):
+def run_forward(w, precision, steps, warmup, dev, timing=True, keep_state=False, solver="glf",
+                surfaces="hopkins"):
     """Build the static geometry, then time `steps` whole RT steps (after
     `warmup` untimed ones).  keep_state: also return the final state (input
-    order, FP64 host array).  solver: the Riemann solver, "glf" or "hll"."""
+    order, FP64 host array).  solver: the Riemann solver, "glf" or "hll";
+    surfaces: "hopkins" or "ivanova"."""
     import numpy as np
     import torch
     from paper_2302_12727_amd import RT
@@ -97,8 +99,10 @@ def run_forward(w, precision, steps, warmup, dev, timing=True, keep_state=False,
     rt.rt_sync()
     build_ms = (time.perf_counter() - t0) * 1e3
     rt.rt_set_riemann(solver)
+    if surfaces != "hopkins":
+        rt.rt_set_surfaces(surfaces)
     st = rt.rt_get_stats()
-    log(f"[{precision} {solver}] build {build_ms:.1f} ms; pairs {st['n_pairs']}; mean neighbours "
+    log(f"[{precision} {solver} {surfaces}] build {build_ms:.1f} ms; pairs {st['n_pairs']}; mean neighbours "
         f"{st['n_entries'] / w.n:.2f}; max {st['max_neighbours']}")
     p = perm.cpu().numpy()
     sd = rt.sdtype
@@ -484,6 +488,15 @@ def main():
                                    "kernel_ms": {"transport": fh["transport_ms"],
                                                  "gradient": fh["gradient_ms"]}}
             del fh
+        if args.precision == "fp64":
+            fi = run_forward(w, "fp64", args.steps, args.warmup, dev, surfaces="ivanova")
+            out["ivanova"] = {"value": fi["pairs"] * args.steps / fi["elapsed"],
+                              "ms_per_step": fi["elapsed"] / args.steps * 1e3,
+                              "kernel_ms": {"transport": fi["transport_ms"],
+                                            "gradient": fi["gradient_ms"]},
+                              "transport_time_vs_hopkins": fi["transport_ms"] / fw_transport_ms,
+                              "photon_budget_residual": fi["photon_budget_residual"]}
+            del fi
         out["absorb"] = absorb_leg(w, dev)
         torch.cuda.empty_cache()
         wa = workloads.config(3)

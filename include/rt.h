@@ -167,6 +167,22 @@ typedef enum { RT_GLF = 0, RT_HLL = 1 } rt_riemann;
 #define RT_HLL_NMU 65
 rt_status rt_set_riemann(rt_ctx *ctx, int32_t solver);
 
+/* Effective surfaces A_kl of the transport (Part II).
+ *   RT_HOPKINS  eq:HopkinsAij, A_kl = V_k psi~_l(x_k) - V_l psi~_k(x_l) with the
+ *               least-squares psi~ (the default).
+ *   RT_IVANOVA  eq:IvanovaAij, A_kl = V_k grad psi_l(x_k) - V_l grad psi_k(x_l)
+ *               with the analytic gradients of the partition of unity,
+ *               grad psi_l(x_k) = V_k grad W_l(x_k) - V_k^2 W(r_kl, H_k) g_k,
+ *               g_k = sum_m grad W_m(x_k) over the gather neighbours, the kernel
+ *               taken with H_k (the thesis' appendix on partition-of-unity
+ *               gradients).
+ * FP64 contexts after rt_build_cells (RT_ESTATE before, RT_EINVAL on FP32C);
+ * selecting RT_IVANOVA computes g (n x 4 doubles, kept and recomputed by
+ * later builds).  rt_tick and rt_adjoint return RT_ESTATE while RT_IVANOVA is
+ * selected.  The gradient step (eq:gradient) is the same for both. */
+typedef enum { RT_HOPKINS = 0, RT_IVANOVA = 1 } rt_surfaces;
+rt_status rt_set_surfaces(rt_ctx *ctx, int32_t kind);
+
 /* The HLL wave-speed table, [RT_HLL_NF][RT_HLL_NMU][2] doubles (l_min, l_max)
  * in units of c at f_i = i/(RT_HLL_NF - 1), mu_j = -1 + 2j/(RT_HLL_NMU - 1).
  *   tab [host] out.  ctx may be NULL (host code only, no device needed). */

@@ -13,7 +13,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgearrt.so")
 SOURCES = ["rt_api.hip", "rt_build.hip", "rt_step.hip", "rt_step32.hip", "rt_adjoint.hip",
            "rt_adjoint32.hip", "rt_bins.hip", "rt_hll.hip",
-           "rt_absorb.hip", "rt_drift.hip"]
+           "rt_absorb.hip", "rt_drift.hip",
+           "rt_ivanova.hip"]
 ARCH = os.environ.get("GEARRT_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

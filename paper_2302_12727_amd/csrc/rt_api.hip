@@ -113,7 +113,7 @@ void rt_destroy(rt_ctx *ctx) {
                     ctx->n_gath, ctx->wave_base, ctx->nbr, ctx->src_h, ctx->inj_gptr,
                     ctx->inj_gas, ctx->inj_src, ctx->inj_coef, ctx->inj_xi, ctx->src_ptr,
                     ctx->src_gas, ctx->src_coef, ctx->status, ctx->partials, ctx->scan_tmp,
-                    ctx->adj_buf, ctx->hll_table, ctx->hll_table32, ctx->vol};
+                    ctx->adj_buf, ctx->hll_table, ctx->hll_table32, ctx->vol, ctx->ivan};
     for (void *b : bufs) rt_free(b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -201,6 +201,16 @@ rt_status rt_set_riemann(rt_ctx *ctx, int32_t solver) {
     return rt_set_riemann_impl(ctx, solver);
 }
 
+rt_status rt_set_surfaces(rt_ctx *ctx, int32_t kind) {
+    if (!ctx) return RT_EINVAL;
+    if (kind != RT_HOPKINS && kind != RT_IVANOVA)
+        return rt_fail(ctx, RT_EINVAL, "kind must be RT_HOPKINS or RT_IVANOVA");
+    if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
+    if (kind == RT_IVANOVA && ctx->p.precision != RT_FP64)
+        return rt_fail(ctx, RT_EINVAL, "the Ivanova surfaces are implemented for FP64 contexts");
+    return rt_set_surfaces_impl(ctx, kind);
+}
+
 rt_status rt_get_hll_table(rt_ctx *ctx, double *tab) {
     if (!tab) return rt_fail(ctx, RT_EINVAL, "tab is NULL");
     std::vector<double> t = rt_hll_speed_table(RT_HLL_NF, RT_HLL_NMU);
@@ -273,6 +283,8 @@ rt_status rt_tick(rt_ctx *ctx, double *U, const double *L, int64_t tick, double 
         return rt_fail(ctx, RT_EINVAL, "time bins are implemented for FP64 contexts only");
     if (!U || !UD || !acc) return rt_fail(ctx, RT_EINVAL, "U, UD and acc are required");
     if (tick < 0) return rt_fail(ctx, RT_EINVAL, "tick must be >= 0");
+    if (ctx->surfaces != RT_HOPKINS)
+        return rt_fail(ctx, RT_ESTATE, "individual time steps use the Hopkins surfaces");
     if (ctx->S > 0 && !L) return rt_fail(ctx, RT_EINVAL, "L is required when sources are set");
     size_t nu = sizeof(double) * 4 * ctx->p.groups * ctx->p.n;
     if (overlap(UD, 4 * nu, U, nu) || overlap(UD, 4 * nu, acc, nu) || overlap(U, nu, acc, nu))
@@ -290,8 +302,9 @@ rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const doub
     if (!UD && !U_pre) return rt_fail(ctx, RT_EINVAL, "U_pre is required when UD is NULL");
     if (ctx->S > 0 && !L) return rt_fail(ctx, RT_EINVAL, "L is required when sources are set");
     if (UD && !aligned16(UD)) return rt_fail(ctx, RT_EINVAL, "UD must be 16-byte aligned");
-    if (ctx->solver != RT_GLF)
-        return rt_fail(ctx, RT_ESTATE, "the adjoint is implemented for the GLF solver");
+    if (ctx->solver != RT_GLF || ctx->surfaces != RT_HOPKINS)
+        return rt_fail(ctx, RT_ESTATE,
+                       "the adjoint is implemented for the GLF solver and Hopkins surfaces");
     return rt_adjoint_impl(ctx, U_pre, L, dt, UD, U_unguarded, lam_next, lam, dL_dL);
 }
 

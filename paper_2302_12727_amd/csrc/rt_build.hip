@@ -509,8 +509,9 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     rt_free(ctx->xs); rt_free(ctx->geo); rt_free(ctx->geo32); rt_free(ctx->perm32);
     rt_free(ctx->keys); rt_free(ctx->h_iters); rt_free(ctx->node_lo); rt_free(ctx->node_hi);
     rt_free(ctx->node_hmax); rt_free(ctx->n_nbr); rt_free(ctx->n_gath); rt_free(ctx->wave_base);
-    rt_free(ctx->nbr); rt_free(ctx->vol);
+    rt_free(ctx->nbr); rt_free(ctx->vol); rt_free(ctx->ivan);
     ctx->vol = nullptr;
+    ctx->ivan = nullptr;
     ctx->xs = nullptr; ctx->geo = nullptr; ctx->geo32 = nullptr; ctx->perm32 = nullptr;
     ctx->keys = nullptr; ctx->h_iters = nullptr; ctx->node_lo = nullptr; ctx->node_hi = nullptr;
     ctx->node_hmax = nullptr; ctx->n_nbr = nullptr; ctx->n_gath = nullptr;
@@ -667,6 +668,7 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     if ((rs = rt_alloc(ctx, (void **)&ctx->vol, sizeof(double) * n)) != RT_OK) return rs;
     RT_HIP(hipMemcpyAsync(ctx->vol, V, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     ctx->built = 1;
+    if (ctx->surfaces == RT_IVANOVA && (rs = rt_ivanova_impl(ctx)) != RT_OK) return rs;
     ctx->bin_top = -1;   // the records were rewritten with all time bins 0
     return RT_OK;
 fail:

@@ -106,6 +106,8 @@ struct rt_ctx {
     int32_t solver = RT_GLF;     // Riemann solver of the transport
     double *hll_table = nullptr; // [RT_HLL_NF][RT_HLL_NMU][2] wave speeds / c
     float *hll_table32 = nullptr;// the same in FP32 (FP32C contexts)
+    int32_t surfaces = RT_HOPKINS; // effective surfaces of the transport
+    double *ivan = nullptr;      // [n][4] sum_k grad W_k(x_i) (Ivanova surfaces)
 
     // timing: event pairs recorded around launches while timing is on
     int timing = 0;
@@ -292,6 +294,10 @@ rt_status rt_tick_step_impl(rt_ctx *ctx, double *U, double *UD, const double *dt
 // drift correction (rt_drift.hip)
 rt_status rt_drift_impl(rt_ctx *ctx, const void *UD, const double *dx, void *U_out, double *Q,
                         int64_t *counts, double *ledger);
+
+// Ivanova surfaces (rt_ivanova.hip): per-particle kernel-gradient sums
+rt_status rt_ivanova_impl(rt_ctx *ctx);
+rt_status rt_set_surfaces_impl(rt_ctx *ctx, int32_t kind);
 
 // HLL wave speeds (rt_hll.hip): the host table and the solver switch
 std::vector<double> rt_hll_speed_table(int nf, int nmu);

@@ -146,6 +146,38 @@ __device__ __forceinline__ void pair_geometry64(const double *__restrict__ rk,
     pg.fl = rl[R_H] * ih;
 }
 
+// Ivanova effective surface (eq:IvanovaAij with the analytic gradients of the
+// partition of unity): A_kl = V_k grad psi_l(x_k) - V_l grad psi_k(x_l) with
+// grad psi_l(x_k) = V_k grad W_l(x_k) - V_k^2 W(r, H_k) g_k and
+// grad W_l(x_k) = (sigma / H_k^4) w'(r / H_k) (x_k - x_l) / r, so that with
+// s = x_l - x_k
+//   A_kl = -(V_k^2 sigma w'_k / H_k^4 + V_l^2 sigma w'_l / H_l^4) s / r
+//          - V_k^3 sigma w_k / H_k^3 g_k + V_l^3 sigma w_l / H_l^3 g_l.
+// gk, gl: the kernel-gradient sums g of both particles.
+__device__ __forceinline__ void pair_geometry_ivanova64(const double *__restrict__ rk,
+                                                        const double *__restrict__ rl,
+                                                        const double (&gk)[3],
+                                                        const double (&gl)[3], double box,
+                                                        double ibox, PairGeo &pg) {
+    pg.sx = min_image(rl[0] - rk[0], box, ibox);
+    pg.sy = min_image(rl[1] - rk[1], box, ibox);
+    pg.sz = min_image(rl[2] - rk[2], box, ibox);
+    const double r = sqrt64(pg.sx * pg.sx + pg.sy * pg.sy + pg.sz * pg.sz);
+    const double ir = r > 0.0 ? rcp64(r) : 0.0;
+    const double iHk = rk[R_IH], iHl = rl[R_IH], Vk = rk[R_V], Vl = rl[R_V];
+    const double qk = r * iHk, ql = r * iHl;
+    const double sk = kSigma3 * Vk * Vk * iHk * iHk * iHk, sl = kSigma3 * Vl * Vl * iHl * iHl * iHl;
+    const double a = -(sk * iHk * kern_dw(qk) + sl * iHl * kern_dw(ql)) * ir;
+    const double bk = sk * Vk * kern_w(qk), bl = sl * Vl * kern_w(ql);
+    pg.Ax = a * pg.sx - bk * gk[0] + bl * gl[0];
+    pg.Ay = a * pg.sy - bk * gk[1] + bl * gl[1];
+    pg.Az = a * pg.sz - bk * gk[2] + bl * gl[2];
+    pg.An = sqrt64(pg.Ax * pg.Ax + pg.Ay * pg.Ay + pg.Az * pg.Az);
+    const double ih = rcp64(rk[R_H] + rl[R_H]);
+    pg.fk = rk[R_H] * ih;
+    pg.fl = rl[R_H] * ih;
+}
+
 // Block sum of NP per-lane values; value p goes to out[col(p)].
 template <int NP, class Col>
 __device__ __forceinline__ void block_reduce_store(double (&v)[NP], double *__restrict__ out,

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_gradient64(
 // eq:transport-update-explicit with min{dt_k, dt_l}).
 // With one group per wave the HLL instantiation fits 3 waves per SIMD (168
 // registers), measured 4% faster than 2 (the GLF one is slower there).
-template <int G, int GW, bool BIN = false, bool HLL = false>
+template <int G, int GW, bool BIN = false, bool HLL = false, bool IVA = false, int Q = 1>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     (HLL && GW == 1) ? 3 : 2, (HLL && GW == 1) ? 3 : 2))) void k_transport64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
@@ -124,9 +124,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     const double *__restrict__ UD, const double *__restrict__ dtp, double c, double box,
     double *__restrict__ Uout, double *__restrict__ partials,
     unsigned long long *__restrict__ counts, double *__restrict__ Uung, int64_t tick = 0,
-    double *__restrict__ accm = nullptr, const double2 *__restrict__ hll = nullptr) {
+    double *__restrict__ accm = nullptr, const double2 *__restrict__ hll = nullptr,
+    const double *__restrict__ ivan = nullptr) {
     static_assert(G % GW == 0, "group slices must tile the groups");
+    static_assert(!(IVA && BIN), "the binned tick uses the Hopkins surfaces");
+    static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     constexpr int NS = G / GW, NQ = 4 * G;
+    constexpr int PW = 64 / Q, PB = kBlock / Q;   // particles per wave, per block
     __shared__ double stage[kBlock / 64][64 * kStage];
     __shared__ double smem[(kBlock / 64) * 2 * GW];
     __shared__ unsigned long long scnt[4];
@@ -135,11 +139,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     const int64_t blk = bg / NS;
     const int g0 = (int)(bg - blk * NS) * GW;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t i = blk * kBlock + threadIdx.x;
+    // Q lanes share a particle, each taking every Q-th of its neighbour slots
+    const int sub = lane % Q;
+    const int64_t i0 = blk * PB + wv * PW;      // first particle of the wave
+    const int64_t i = i0 + lane / Q;
     const bool active = i < n;
+    const bool owner = active && sub == 0;      // writes the particle's results
     const int64_t ic = active ? i : n - 1;      // in-range index for inactive lanes
-    const int64_t w = i >> 6;
-    const bool wave_live = (w << 6) < n;        // wave-uniform
+    const int64_t w = i0 >> 6;                  // neighbour-table wave (PW divides 64)
+    const bool wave_live = i0 < n;              // wave-uniform
     const double ibox = 1.0 / box, hc = 0.5 * c;
     if (threadIdx.x < 4) scnt[threadIdx.x] = 0;
     double *sb = stage[wv];
@@ -162,6 +170,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
     for (int q = 0; q < 4 * GW; ++q) acc[q] = 0.0;
     int cE = 0, cF = 0;
+    double gk[3] = {0.0, 0.0, 0.0};   // IVA: own kernel-gradient sum
+    if (IVA) {
+        gk[0] = ivan[4 * ic];
+        gk[1] = ivan[4 * ic + 1];
+        gk[2] = ivan[4 * ic + 2];
+    }
     // time bins: this particle ends a step in this tick (ends), or some pair of
     // its neighbourhood does (touched)
     const int64_t t1 = tick + 1;
@@ -170,11 +184,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     const bool touched = !BIN || (t1 & ((int64_t(1) << (int32_t)rk[13]) - 1)) == 0;
 
     if (wave_live) {
-        const int64_t base = wave_base[w] + lane;
+        const int64_t base = wave_base[w] + (i & 63);
         int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
         const int32_t nn = (active && touched) ? n_nbr[i] : 0;
+        if (Q > 1) {                            // the longest list of this wave's particles
+            kmax = nn;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
+        }
         if (BIN && __ballot(nn > 0) == 0) kmax = 0;   // no due pair in this wave
-        for (int32_t k = 0; k < kmax; ++k) {
+        for (int32_t kk = 0; kk < kmax; kk += Q) {
+            const int32_t k = kk + sub;
             const bool valid = k < nn;
             const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
             int64_t row[8];
@@ -186,7 +206,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
             for (int q = 0; q < 12; ++q) rl[q] = sb[lane * kStage + q];
             PairGeo pg;
-            pair_geometry64(rk, rl, box, ibox, pg);
+            if (IVA) {
+                stage_rows4(ivan, 4, j, sb, lane);
+                const double gl[3] = {sb[lane * kStage], sb[lane * kStage + 1],
+                                      sb[lane * kStage + 2]};
+                pair_geometry_ivanova64(rk, rl, gk, gl, box, ibox, pg);
+            } else {
+                pair_geometry64(rk, rl, box, ibox, pg);
+            }
             bool use = valid && pg.An > 0.0;
             double wkl = 1.0;                   // time integration of this exchange
             if (BIN) {
@@ -237,10 +264,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             }
         }
     }
+    // sum of the Q partial sums of each particle (a fixed butterfly: the same
+    // bits on every lane of the particle)
+    if (Q > 1) {
+#pragma unroll
+        for (int q = 0; q < 4 * GW; ++q)
+#pragma unroll
+            for (int o = 1; o < Q; o <<= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+    }
     // update, post-update guard, ledger, photon budget
     double red[2 * GW];
     int gE = 0, gF = 0;
-    if (BIN && active && !ends) {
+    if (BIN && owner && !ends) {
         // no update in this tick: keep the pending sums, count the current state
         const double V = rk[R_V];
 #pragma unroll
@@ -253,7 +288,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             red[g] = V * Ui[4 * g];
             red[GW + g] = 0.0;
         }
-    } else if (active) {
+    } else if (owner) {
         const double V = rk[R_V];
         // the update: U - dt/V sum (global step), or U - (pending + this tick)/V
         const double dtV = BIN ? 1.0 / V : dtp[0] / V;
@@ -402,23 +437,41 @@ constexpr int transport_slice(int G) {
 #endif
 constexpr int hll_slice(int G) { return G <= 2 ? G : (G % 2 == 0 ? 2 : 1); }
 
+// Lanes per particle of the FP64 transport (1, 2 or 4): with Q > 1 a wave
+// covers 64/Q particles whose neighbour lists overlap more, so the records
+// one iteration stages repeat more often in the caches.  Q = 4 cut the
+// calibrated fetch of the 3-group 128^3 lattice 14x (35 GB to 2.5 GB per
+// launch) and the time by 11% against Q = 1.
+#ifndef RT_TRANSPORT_Q
+#define RT_TRANSPORT_Q 4
+#endif
+constexpr int kQ = RT_TRANSPORT_Q;
+// rows of block partials the FP64 transport writes (one per block)
+inline int64_t transport_rows(int64_t n) { return (n + kBlock / kQ - 1) / (kBlock / kQ); }
+
 template <int G>
 void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double *Uout,
                         double *partials, int64_t *counts, double *Uung) {
     constexpr int GW =
         (RT_TRANSPORT_GW == 0 || G % RT_TRANSPORT_GW != 0) ? transport_slice(G) : RT_TRANSPORT_GW;
     constexpr int HW = (RT_HLL_GW == 0 || G % RT_HLL_GW != 0) ? hll_slice(G) : RT_HLL_GW;
-    const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
-    if (ctx->solver == RT_HLL)
-        k_transport64<G, HW, false, true><<<(unsigned)xcd_grid(nb * (G / HW)), kBlock, 0,
-                                            ctx->stream>>>(
-            n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
-            ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, 0, nullptr,
-            (const double2 *)ctx->hll_table);
-    else
-        k_transport64<G, GW><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, ctx->stream>>>(
-            n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
-            ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung);
+    const int64_t n = ctx->p.n, nb = transport_rows(n);
+    const double2 *tab = (const double2 *)ctx->hll_table;
+    const bool iva = ctx->surfaces == RT_IVANOVA;
+#define RT_TRANSPORT_LAUNCH(W, HLL_, IVA_)                                                    \
+    k_transport64<G, W, false, HLL_, IVA_, kQ><<<(unsigned)xcd_grid(nb * (G / W)), kBlock, 0, \
+                                                 ctx->stream>>>(                            \
+        n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,          \
+        ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, 0, nullptr, tab,      \
+        ctx->ivan)
+    if (ctx->solver == RT_HLL) {
+        if (iva) RT_TRANSPORT_LAUNCH(HW, true, true);
+        else RT_TRANSPORT_LAUNCH(HW, true, false);
+    } else {
+        if (iva) RT_TRANSPORT_LAUNCH(GW, false, true);
+        else RT_TRANSPORT_LAUNCH(GW, false, false);
+    }
+#undef RT_TRANSPORT_LAUNCH
 }
 
 template <int G>
@@ -435,15 +488,17 @@ void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, d
     k_gradient64<G, true><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
         n, nb, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box, tick);
     constexpr int GW = transport_slice(G), HW = hll_slice(G);
+    const int64_t nt = transport_rows(n);
     if (ctx->solver == RT_HLL)
-        k_transport64<G, HW, true, true><<<(unsigned)xcd_grid(nb * (G / HW)), kBlock, 0,
-                                           ctx->stream>>>(
-            n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
+        k_transport64<G, HW, true, true, false, kQ><<<(unsigned)xcd_grid(nt * (G / HW)), kBlock,
+                                                      0, ctx->stream>>>(
+            n, nt, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
             ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, tick, accm,
             (const double2 *)ctx->hll_table);
     else
-        k_transport64<G, GW, true><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, ctx->stream>>>(
-            n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
+        k_transport64<G, GW, true, false, false, kQ><<<(unsigned)xcd_grid(nt * (G / GW)), kBlock,
+                                                       0, ctx->stream>>>(
+            n, nt, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
             ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, tick, accm);
 }
 
@@ -469,7 +524,9 @@ void rt_finalize_partials(rt_ctx *ctx, int64_t nb, double *Q, double *ledger) {
 }
 
 rt_status rt_ensure_partials(rt_ctx *ctx) {
-    const int64_t nb = (ctx->p.n + kBlock - 1) / kBlock;
+    // enough rows for every kernel that writes them (the FP64 transport runs
+    // up to 4 lanes per particle, so up to 4 blocks per kBlock particles)
+    const int64_t nb = (4 * ctx->p.n + kBlock - 1) / kBlock;
     if (ctx->partials && ctx->nblocks >= nb) return RT_OK;
     rt_free(ctx->partials);
     ctx->partials = nullptr;
@@ -509,7 +566,9 @@ rt_status rt_gradient_impl(rt_ctx *ctx, const void *U, void *UD) {
 
 rt_status rt_transport_impl(rt_ctx *ctx, const void *UD, const double *dt, void *U_out,
                             double *Q, int64_t *counts, double *ledger, void *Uung) {
-    const int64_t nb = (ctx->p.n + kBlock - 1) / kBlock;
+    // rows of block partials: the FP64 kernel's blocks, or one per kBlock particles
+    const int64_t nb = ctx->p.precision == RT_FP64 ? transport_rows(ctx->p.n)
+                                                   : (ctx->p.n + kBlock - 1) / kBlock;
     double *part = (Q || ledger) ? ctx->partials : nullptr;
     rt_timer_begin(ctx, "transport");
     if (ctx->p.precision == RT_FP64) {
@@ -531,7 +590,7 @@ rt_status rt_transport_impl(rt_ctx *ctx, const void *UD, const double *dt, void 
 // (FP64; injection and the refresh of the stored states are in rt_bins.hip).
 rt_status rt_tick_step_impl(rt_ctx *ctx, double *U, double *UD, const double *dt, int64_t tick,
                             double *accm, double *Q, int64_t *counts, double *ledger) {
-    const int64_t nb = (ctx->p.n + kBlock - 1) / kBlock;
+    const int64_t nb = transport_rows(ctx->p.n);
     double *part = (Q || ledger) ? ctx->partials : nullptr;
     rt_timer_begin(ctx, "tick");
     RT_DISPATCH_G(ctx->p.groups, launch_tick64, ctx, U, UD, dt, U, part, counts, tick, accm);

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libgearrt.so")
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EHIP, RT_ENOCONV, RT_ESINGULAR, RT_ESTATE = 0, -1, -2, -3, -4, -5, -6
 RT_FP64, RT_FP32C = 0, 1
 RT_GLF, RT_HLL = 0, 1
+RT_HOPKINS, RT_IVANOVA = 0, 1
 RT_HLL_NF, RT_HLL_NMU = 65, 65
 STATUS_NAMES = {0: "RT_OK", -1: "RT_EINVAL", -2: "RT_ENOMEM", -3: "RT_EHIP",
                 -4: "RT_ENOCONV", -5: "RT_ESINGULAR", -6: "RT_ESTATE"}
@@ -32,7 +33,8 @@ EXPORTED = ["rt_create", "rt_destroy", "rt_last_error", "rt_set_stream", "rt_bui
             "rt_set_sources", "rt_inject", "rt_gradient", "rt_transport", "rt_photon_total",
             "rt_adjoint", "rt_sync", "rt_get_stats", "rt_get_geometry", "rt_get_neighbours",
             "rt_get_sources", "rt_timing", "rt_get_timing", "rt_time_bins", "rt_tick",
-            "rt_set_riemann", "rt_get_hll_table", "rt_photon_groups", "rt_absorb", "rt_drift"]
+            "rt_set_riemann", "rt_get_hll_table", "rt_photon_groups", "rt_absorb", "rt_drift",
+            "rt_set_surfaces"]
 
 
 class RTError(RuntimeError):
@@ -90,6 +92,7 @@ def load_library() -> ctypes.CDLL:
     L.rt_absorb.argtypes = [_VP, _VP, i32, _VP, _VP, _VP, _VP, _VP, _VP]
     L.rt_drift.argtypes = [_VP] * 7
     L.rt_set_riemann.argtypes = [_VP, i32]
+    L.rt_set_surfaces.argtypes = [_VP, i32]
     L.rt_get_hll_table.argtypes = [_VP, _VP]
     L.rt_sync.argtypes = [_VP]
     L.rt_get_stats.argtypes = [_VP, ctypes.POINTER(rt_stats)]
@@ -340,6 +343,12 @@ class RT:
         """Riemann solver of rt_transport: "glf" or "hll"."""
         code = {"glf": RT_GLF, "hll": RT_HLL}[solver]
         self._check(self.L.rt_set_riemann(self.ctx, code))
+
+    def rt_set_surfaces(self, kind: str):
+        """Effective surfaces of rt_transport: "hopkins" or "ivanova"."""
+        code = {"hopkins": RT_HOPKINS, "ivanova": RT_IVANOVA}[kind]
+        self._bind_stream()
+        self._check(self.L.rt_set_surfaces(self.ctx, code))
 
     def rt_get_hll_table(self):
         """The library's HLL wave-speed table (see hll_speed_table)."""

@@ -1,0 +1,154 @@
+"""The Ivanova effective surfaces on the GPU (Part II eq:IvanovaAij) against
+the oracle's transport with the same surfaces, element by element: 1e-12 per
+state (FP64), as for the Hopkins surfaces.
+
+Cases: the 16^3 lattice (guards firing), 3 groups with sources and the HLL
+solver, ragged sizes, a clustered Plummer set, photon conservation without
+guards, a rebuild at moved positions (the kernel-gradient sums are
+recomputed), the switch back to Hopkins, and the refusals.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from tests.gpu_util import dev, log, state_err, unsort
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2302_12727_amd import RT, RTError  # noqa: E402
+
+TOL = 1e-12
+
+
+def gpu_case(w, cfl=0.9, solver="glf", x=None):
+    rt = RT(w.n, w.groups, cfl=cfl)
+    perm, *_ = rt.rt_build_cells(dev(w.x if x is None else x))
+    if w.xs.shape[0]:
+        rt.rt_set_sources(dev(w.xs))
+    rt.rt_set_riemann(solver)
+    rt.rt_set_surfaces("ivanova")
+    rt.rt_sync()
+    return rt, perm.cpu().numpy()
+
+
+def run_gpu(rt, p, w, steps, U0=None):
+    U = dev((w.U0 if U0 is None else U0)[p])
+    L = dev(w.L) if w.xs.shape[0] else None
+    counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+    Q = torch.zeros(w.groups, dtype=torch.float64, device="cuda")
+    for _ in range(steps):
+        U = rt.step(U, L, photon_total=Q, counts=counts)
+    rt.rt_sync()
+    return unsort(U.cpu().numpy(), p), Q.cpu().numpy(), counts.cpu().numpy()
+
+
+def test_c1_ten_steps():
+    w = workloads.config(0)
+    geo = oracle.build_geometry(w.x)
+    rt, p = gpu_case(w)
+    ref, info = oracle.run(geo, None, w.U0, None, w.steps, ivanova=True)
+    got, Q, counts = run_gpu(rt, p, w, w.steps)
+    err = state_err(got, ref)
+    log(f"Ivanova C1 10 steps: max state err {err:.2e}; counts gpu {counts} oracle {info['counts']}")
+    assert err < TOL
+    assert np.allclose(Q, oracle.photon_total(geo, ref), rtol=1e-12, atol=0)
+    assert counts[0] == info["counts"][0] and counts[2] == info["counts"][2]
+    hop, _ = oracle.run(geo, None, w.U0, None, w.steps)
+    assert state_err(got, hop) > 1e-6
+
+
+def test_groups_sources_and_hll():
+    w = workloads.config(1, scale=(20 ** 3) / (128 ** 3))     # 20^3, G=3, 16 sources
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs)
+    rt, p = gpu_case(w, solver="hll")
+    ref, _ = oracle.run(geo, srcs, w.U0, w.L, 3, hll=oracle.hll_table(), ivanova=True)
+    got, Q, _ = run_gpu(rt, p, w, 3)
+    err = state_err(got, ref)
+    log(f"Ivanova + HLL lattice20 G=3 3 steps: max state err {err:.2e}")
+    assert err < TOL
+    assert np.allclose(Q, oracle.photon_total(geo, ref), rtol=1e-12)
+
+
+@pytest.mark.parametrize("n_side,groups", [(7, 2), (9, 1), (11, 4), (9, 5)])
+def test_ragged_sizes(n_side, groups):
+    w = workloads.lattice_workload(n_side, groups, 2, 3, seed=960 + n_side, name="ragged")
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs)
+    rt, p = gpu_case(w)
+    ref, _ = oracle.run(geo, srcs, w.U0, w.L, 3, ivanova=True)
+    got = run_gpu(rt, p, w, 3)[0]
+    assert state_err(got, ref) < TOL
+
+
+def test_plummer():
+    w = workloads.config(2, scale=(1 << 13) / (1 << 22))
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs)
+    rt, p = gpu_case(w)
+    ref, _ = oracle.run(geo, srcs, w.U0, w.L, 2, ivanova=True)
+    got = run_gpu(rt, p, w, 2)[0]
+    err = state_err(got, ref)
+    log(f"Ivanova plummer n={w.n} 2 steps: max state err {err:.2e}")
+    assert err < TOL
+
+
+def test_conservation_without_guards():
+    x = workloads.jittered_lattice(16, 0.1, 5)
+    g = workloads.rng(6)
+    E = 1.0 + 0.3 * np.sin(2 * np.pi * x[:, 0]) * np.cos(2 * np.pi * x[:, 1])
+    U0 = np.zeros((x.shape[0], 1, 4))
+    U0[:, 0, 0] = E
+    U0[:, 0, 1:] = 0.05 * E[:, None] * g.normal(size=(x.shape[0], 3))
+    w = workloads.Workload("smooth", x, U0, np.zeros((0, 3)), np.zeros((0, 1)), 5, 1)
+    rt, p = gpu_case(w, cfl=0.3)
+    Q0 = rt.rt_photon_total(dev(U0[p])).item()
+    _, Q, counts = run_gpu(rt, p, w, 5)
+    assert counts.sum() == 0
+    assert abs(Q[0] - Q0) <= 1e-13 * Q0
+
+
+def test_rebuild_keeps_the_surfaces():
+    w = workloads.lattice_workload(9, 2, 0, 1, seed=971, name="rebuild")
+    x1 = np.mod(w.x + workloads.rng(972).uniform(-0.01, 0.01, size=w.x.shape), 1.0)
+    rt, _ = gpu_case(w)
+    perm, *_ = rt.rt_build_cells(dev(x1))                    # moved particles
+    p = perm.cpu().numpy()
+    got = run_gpu(rt, p, w, 2)[0]
+    ref, _ = oracle.run(oracle.build_geometry(x1), None, w.U0, None, 2, ivanova=True)
+    assert state_err(got, ref) < TOL
+
+
+def test_switch_back_to_hopkins():
+    w = workloads.lattice_workload(9, 2, 2, 2, seed=981, name="switch")
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs)
+    rt, p = gpu_case(w)
+    run_gpu(rt, p, w, 1)
+    rt.rt_set_surfaces("hopkins")
+    got = run_gpu(rt, p, w, 2)[0]
+    ref, _ = oracle.run(geo, srcs, w.U0, w.L, 2)
+    assert state_err(got, ref) < TOL
+
+
+def test_refusals():
+    w = workloads.lattice_workload(7, 1, 0, 1, seed=990, name="refuse")
+    fresh = RT(w.n, w.groups)
+    with pytest.raises(RTError, match="RT_ESTATE"):
+        fresh.rt_set_surfaces("ivanova")                     # before the build
+    rt, p = gpu_case(w)
+    U = dev(w.U0[p])
+    UD = rt.rt_gradient(U)
+    with pytest.raises(RTError, match="RT_ESTATE"):
+        rt.rt_tick(U, None, 0, UD, torch.zeros_like(U))
+    with pytest.raises(RTError, match="RT_ESTATE"):
+        rt.rt_adjoint(U, None, torch.ones_like(U))
+    rt32 = RT(w.n, w.groups, precision="fp32c")
+    rt32.rt_build_cells(dev(w.x))
+    with pytest.raises(RTError, match="RT_EINVAL"):
+        rt32.rt_set_surfaces("ivanova")
