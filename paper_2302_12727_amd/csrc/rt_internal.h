@@ -272,6 +272,7 @@ rt_status rt_total_impl(rt_ctx *ctx, const void *U, double *Q);
 void rt_gradient32(rt_ctx *ctx, const float *U, float *UD);
 void rt_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *Uout,
                     double *partials, int64_t *counts, float *Uung);
+int64_t rt_transport32_rows(int64_t n);   // rows of block partials rt_transport32 writes
 void rt_adjoint32(rt_ctx *ctx, const float *UD, const float *Uung, const float *lam_next,
                   float *lam2, float *R, float *lam, const double *dt);
 rt_status rt_ensure_partials(rt_ctx *ctx);

@@ -568,7 +568,7 @@ rt_status rt_transport_impl(rt_ctx *ctx, const void *UD, const double *dt, void 
                             double *Q, int64_t *counts, double *ledger, void *Uung) {
     // rows of block partials: the FP64 kernel's blocks, or one per kBlock particles
     const int64_t nb = ctx->p.precision == RT_FP64 ? transport_rows(ctx->p.n)
-                                                   : (ctx->p.n + kBlock - 1) / kBlock;
+                                                   : rt_transport32_rows(ctx->p.n);
     double *part = (Q || ledger) ? ctx->partials : nullptr;
     rt_timer_begin(ctx, "transport");
     if (ctx->p.precision == RT_FP64) {

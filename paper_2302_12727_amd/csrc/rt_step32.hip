@@ -72,7 +72,11 @@ __global__ __launch_bounds__(kBlock) void k_gradient32(
 // table in place of GLF.  Up to 3 groups the HLL instantiation is held to 3
 // waves per SIMD (168 registers, 2 spilled), measured 10% faster than the 2
 // its 184 registers would give.
-template <int G, bool HLL = false>
+//
+// Q lanes share a particle, each taking every Q-th neighbour slot (see the
+// FP64 transport); the per-lane compensated sums are combined in FP64 by a
+// fixed butterfly.
+template <int G, bool HLL = false, int Q = 1>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((HLL && G <= 3) ? 3 : 1))) void k_transport32(
     int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ geo,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
@@ -80,18 +84,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((HLL && 
     const double *__restrict__ dtp, double c, double box, float *__restrict__ Uout,
     double *__restrict__ partials, unsigned long long *__restrict__ counts,
     float *__restrict__ Uung, const float2 *__restrict__ hll = nullptr) {
-    constexpr int NQ = 4 * G;
+    static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
+    constexpr int NQ = 4 * G, PW = 64 / Q, PB = kBlock / Q;
     __shared__ float stage[kBlock / 64][64 * kStage32];
     __shared__ double smem[(kBlock / 64) * 2 * G];
     __shared__ unsigned long long scnt[4];
     const int64_t blk = xcd_block(nb);
     if (blk >= nb) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t i = blk * kBlock + threadIdx.x;
+    const int sub = lane % Q;
+    const int64_t i0 = blk * PB + wv * PW;      // first particle of the wave
+    const int64_t i = i0 + lane / Q;
     const bool active = i < n;
+    const bool owner = active && sub == 0;
     const int64_t ic = active ? i : n - 1;
-    const int64_t w = i >> 6;
-    const bool wave_live = (w << 6) < n;
+    const int64_t w = i0 >> 6;
+    const bool wave_live = i0 < n;
     const double ibox = 1.0 / box;
     const float cf = (float)c, c2 = (float)(c * c), ic2 = (float)(1.0 / (c * c)), hc = 0.5f * cf;
     if (threadIdx.x < 4) scnt[threadIdx.x] = 0;
@@ -122,10 +130,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((HLL && 
     int cE = 0, cF = 0;
 
     if (wave_live) {
-        const int64_t base = wave_base[w] + lane;
-        const int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
+        const int64_t base = wave_base[w] + (i & 63);
+        int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
         const int32_t nn = active ? n_nbr[i] : 0;
-        for (int32_t k = 0; k < kmax; ++k) {
+        if (Q > 1) {                            // the longest list of this wave's particles
+            kmax = nn;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
+        }
+        for (int32_t kk = 0; kk < kmax; kk += Q) {
+            const int32_t k = kk + sub;
             const bool valid = k < nn;
             const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
             int64_t row[4];
@@ -207,17 +221,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((HLL && 
             }
         }
     }
+    double av[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) av[q] = acc[q].value();
+    if (Q > 1) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int o = 1; o < Q; o <<= 1) av[q] += __shfl_xor(av[q], o, 64);
+    }
     double red[2 * G];
     int gE = 0, gF = 0;
-    if (active) {
+    if (owner) {
         const double V = geo[(int64_t)kRec * i + R_V];
         const double dtV = dtp[0] / V;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            double q0 = (double)Ui[4 * g + 0] - dtV * acc[4 * g + 0].value();
-            double q1 = (double)Ui[4 * g + 1] - dtV * acc[4 * g + 1].value();
-            double q2 = (double)Ui[4 * g + 2] - dtV * acc[4 * g + 2].value();
-            double q3 = (double)Ui[4 * g + 3] - dtV * acc[4 * g + 3].value();
+            double q0 = (double)Ui[4 * g + 0] - dtV * av[4 * g + 0];
+            double q1 = (double)Ui[4 * g + 1] - dtV * av[4 * g + 1];
+            double q2 = (double)Ui[4 * g + 2] - dtV * av[4 * g + 2];
+            double q3 = (double)Ui[4 * g + 3] - dtV * av[4 * g + 3];
             const double Epre = q0;
             if (Uung) {
                 float *u = Uung + i * NQ + 4 * g;
@@ -292,17 +315,24 @@ void launch_gradient32(rt_ctx *ctx, const float *U, float *UD) {
         n, nb, ctx->geo32, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box);
 }
 
+// Lanes per particle of the FP32C transport (1, 2 or 4).  On the 3-group
+// 128^3 lattice Q = 4 ran GLF 6% and HLL 5% faster than Q = 1.
+#ifndef RT_TRANSPORT32_Q
+#define RT_TRANSPORT32_Q 4
+#endif
+constexpr int kQ32 = RT_TRANSPORT32_Q;
+
 template <int G>
 void launch_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *Uout,
                         double *partials, int64_t *counts, float *Uung) {
-    const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
+    const int64_t n = ctx->p.n, nb = rt_transport32_rows(n);
     if (ctx->solver == RT_HLL)
-        k_transport32<G, true><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
+        k_transport32<G, true, kQ32><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
             n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt,
             ctx->p.c_red, ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung,
             (const float2 *)ctx->hll_table32);
     else
-        k_transport32<G><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
+        k_transport32<G, false, kQ32><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
             n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt,
             ctx->p.c_red, ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung);
 }
@@ -322,6 +352,8 @@ void rt_gradient32(rt_ctx *ctx, const float *U, float *UD) {
         default: break;
     }
 }
+
+int64_t rt_transport32_rows(int64_t n) { return (n + kBlock / kQ32 - 1) / (kBlock / kQ32); }
 
 void rt_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *Uout,
                     double *partials, int64_t *counts, float *Uung) {
