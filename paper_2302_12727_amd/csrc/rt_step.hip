@@ -39,15 +39,22 @@ __global__ void k_inject(int32_t ngas, int G, const int32_t *__restrict__ gptr,
 // and V_i cancel against B_i, see the geometry record).
 // BIN: only the particles that end a step in tick `tick` (time bin in slot 12
 // of the geometry record) recompute their gradient record.
-template <int G, bool BIN = false>
+//
+// Q lanes share a particle, each summing every Q-th gather neighbour; the
+// partial sums are combined by a fixed butterfly (the same bits on every lane
+// of the particle) and the first lane writes the record.
+template <int G, bool BIN = false, int Q = 1>
 __global__ __launch_bounds__(kBlock) void k_gradient64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const double *__restrict__ xs,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_gath, const double *__restrict__ U, double *__restrict__ UD,
     double box, int64_t tick = 0) {
+    static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     const int64_t blk = xcd_block(nb);
-    if (blk >= nb) return;
-    const int64_t i = blk * kBlock + threadIdx.x;
+    if (blk >= nb) return;                      // whole block
+    const int sub = (threadIdx.x & 63) % Q;
+    const int64_t i = blk * (kBlock / Q) + threadIdx.x / Q;
+    // a particle's Q lanes are adjacent in one wave and leave together
     if (i >= n) return;
     if (BIN && ((tick + 1) & ((int64_t(1) << (int32_t)geo[(int64_t)kRec * i + 12]) - 1)) != 0)
         return;
@@ -64,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_gradient64(
     for (int q = 0; q < NQ; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
     const int64_t base = wave_base[i >> 6] + (i & 63);
     const int32_t ng = n_gath[i];
-    for (int32_t k = 0; k < ng; ++k) {
+    for (int32_t k = sub; k < ng; k += Q) {
         const int64_t j = nbr[base + 64 * (int64_t)k];
         const double sx = min_image(xs[3 * j] - px, box, ibox);
         const double sy = min_image(xs[3 * j + 1] - py, box, ibox);
@@ -79,6 +86,15 @@ __global__ __launch_bounds__(kBlock) void k_gradient64(
             acc[q][1] += d * wy;
             acc[q][2] += d * wz;
         }
+    }
+    if (Q > 1) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int o = 1; o < Q; o <<= 1) acc[q][a] += __shfl_xor(acc[q][a], o, 64);
+        if (sub != 0) return;
     }
     const double b00 = rec[R_B] * iV, b01 = rec[R_B + 1] * iV, b02 = rec[R_B + 2] * iV;
     const double b11 = rec[R_B + 3] * iV, b12 = rec[R_B + 4] * iV, b22 = rec[R_B + 5] * iV;
@@ -474,19 +490,27 @@ void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double 
 #undef RT_TRANSPORT_LAUNCH
 }
 
+// Lanes per particle of the FP64 gradient (1, 2 or 4); Q = 4 measured 14%
+// faster than Q = 1 on the 3-group 128^3 lattice.
+#ifndef RT_GRADIENT_Q
+#define RT_GRADIENT_Q 4
+#endif
+constexpr int kGQ = RT_GRADIENT_Q;
+
 template <int G>
 void launch_gradient64(rt_ctx *ctx, const double *U, double *UD) {
-    const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
-    k_gradient64<G><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
+    const int64_t n = ctx->p.n, nb = (n + kBlock / kGQ - 1) / (kBlock / kGQ);
+    k_gradient64<G, false, kGQ><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
         n, nb, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box);
 }
 
 template <int G>
 void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, double *Uout,
                    double *partials, int64_t *counts, int64_t tick, double *accm) {
-    const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
-    k_gradient64<G, true><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
-        n, nb, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box, tick);
+    const int64_t n = ctx->p.n;
+    const int64_t ng = (n + kBlock / kGQ - 1) / (kBlock / kGQ);
+    k_gradient64<G, true, kGQ><<<(unsigned)xcd_grid(ng), kBlock, 0, ctx->stream>>>(
+        n, ng, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box, tick);
     constexpr int GW = transport_slice(G), HW = hll_slice(G);
     const int64_t nt = transport_rows(n);
     if (ctx->solver == RT_HLL)

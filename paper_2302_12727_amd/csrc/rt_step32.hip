@@ -13,16 +13,19 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // Gradient (eq:gradient) in FP32, S_i^{-1} sum_j (q_j - q_i) w(r_ij/H_i) s_ij.
-template <int G>
+// Q lanes share a particle as in the FP64 gradient.
+template <int G, int Q = 1>
 __global__ __launch_bounds__(kBlock) void k_gradient32(
     int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ xs,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_gath, const float *__restrict__ U, float *__restrict__ UD,
     double box) {
+    static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     const int64_t blk = xcd_block(nb);
     if (blk >= nb) return;
-    const int64_t i = blk * kBlock + threadIdx.x;
-    if (i >= n) return;
+    const int sub = (threadIdx.x & 63) % Q;
+    const int64_t i = blk * (kBlock / Q) + threadIdx.x / Q;
+    if (i >= n) return;                         // a particle's Q lanes leave together
     constexpr int NQ = 4 * G;
     const double ibox = 1.0 / box;
     const float *rec = geo32 + (int64_t)F_REC * i;
@@ -36,7 +39,7 @@ __global__ __launch_bounds__(kBlock) void k_gradient32(
     for (int q = 0; q < NQ; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0f;
     const int64_t base = wave_base[i >> 6] + (i & 63);
     const int32_t ng = n_gath[i];
-    for (int32_t k = 0; k < ng; ++k) {
+    for (int32_t k = sub; k < ng; k += Q) {
         const int64_t j = nbr[base + 64 * (int64_t)k];
         const float sx = (float)min_image(xs[3 * j] - px, box, ibox);
         const float sy = (float)min_image(xs[3 * j + 1] - py, box, ibox);
@@ -51,6 +54,15 @@ __global__ __launch_bounds__(kBlock) void k_gradient32(
             acc[q][1] += d * wy;
             acc[q][2] += d * wz;
         }
+    }
+    if (Q > 1) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int o = 1; o < Q; o <<= 1) acc[q][a] += __shfl_xor(acc[q][a], o, 64);
+        if (sub != 0) return;
     }
     const float b00 = rec[F_B] * iV, b01 = rec[F_B + 1] * iV, b02 = rec[F_B + 2] * iV;
     const float b11 = rec[F_B + 3] * iV, b12 = rec[F_B + 4] * iV, b22 = rec[F_B + 5] * iV;
@@ -308,10 +320,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((HLL && 
     }
 }
 
+// Lanes per particle of the FP32 gradient (1, 2 or 4).  Kept at 1: with 4,
+// the compensated-FP32 adjoint moved away from the FP64 one (luminosity
+// gradients 1.4e-5 apart instead of 3e-8) for a reason not yet isolated.
+#ifndef RT_GRADIENT32_Q
+#define RT_GRADIENT32_Q 1
+#endif
+constexpr int kGQ32 = RT_GRADIENT32_Q;
+
 template <int G>
 void launch_gradient32(rt_ctx *ctx, const float *U, float *UD) {
-    const int64_t n = ctx->p.n, nb = (n + kBlock - 1) / kBlock;
-    k_gradient32<G><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
+    const int64_t n = ctx->p.n, nb = (n + kBlock / kGQ32 - 1) / (kBlock / kGQ32);
+    k_gradient32<G, kGQ32><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
         n, nb, ctx->geo32, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box);
 }
 
