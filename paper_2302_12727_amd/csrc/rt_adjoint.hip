@@ -46,25 +46,32 @@ __global__ __launch_bounds__(kBlock) void k_adj_guard64(int64_t n, const double 
 // Pass B.  R[k][g] = (lam'_k (4) | rho_k (4 x 3)), the layout of a gradient
 // record.  As in the forward transport, a wave owns 64 particles and GW of the
 // G groups.
-template <int G, int GW>
+//
+// Q lanes share a particle, each taking every Q-th neighbour slot (as in the
+// forward transport); the partial sums are combined by a fixed butterfly.
+template <int G, int GW, int Q = 1>
 __global__ __launch_bounds__(kBlock) void k_adj_pair64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
     const double *__restrict__ UD, const double *__restrict__ lam2,
     const double *__restrict__ dtp, double c, double box, double *__restrict__ R) {
     static_assert(G % GW == 0, "group slices must tile the groups");
-    constexpr int NS = G / GW, NQ = 4 * GW;
+    static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
+    constexpr int NS = G / GW, NQ = 4 * GW, PW = 64 / Q, PB = kBlock / Q;
     __shared__ double stage[kBlock / 64][64 * kStage];
     const int64_t bg = xcd_block(nb * NS);
     if (bg >= nb * NS) return;
     const int64_t blk = bg / NS;
     const int g0 = (int)(bg - blk * NS) * GW;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t i = blk * kBlock + threadIdx.x;
+    const int sub = lane % Q;
+    const int64_t i0 = blk * PB + wv * PW;      // first particle of the wave
+    const int64_t i = i0 + lane / Q;
     const bool active = i < n;
+    const bool owner = active && sub == 0;
     const int64_t ic = active ? i : n - 1;
-    const int64_t w = i >> 6;
-    const bool wave_live = (w << 6) < n;
+    const int64_t w = i0 >> 6;                  // neighbour-table wave (PW divides 64)
+    const bool wave_live = i0 < n;
     const double ibox = 1.0 / box;
     const double dt = dtp[0];
     double *sb = stage[wv];
@@ -89,10 +96,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair64(
     for (int q = 0; q < NQ; ++q) aU[q] = aD[3 * q] = aD[3 * q + 1] = aD[3 * q + 2] = 0.0;
 
     if (wave_live) {
-        const int64_t base = wave_base[w] + lane;
-        const int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
+        const int64_t base = wave_base[w] + (i & 63);
+        int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
         const int32_t nn = active ? n_nbr[i] : 0;
-        for (int32_t k = 0; k < kmax; ++k) {
+        if (Q > 1) {                            // the longest list of this wave's particles
+            kmax = nn;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
+        }
+        for (int32_t kk = 0; kk < kmax; kk += Q) {
+            const int32_t k = kk + sub;
             const bool valid = k < nn;
             const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
             int64_t row[8];
@@ -162,7 +175,19 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair64(
             }
         }
     }
-    if (!active) return;
+    if (Q > 1) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+            for (int o = 1; o < Q; o <<= 1) {
+                aU[q] += __shfl_xor(aU[q], o, 64);
+                aD[3 * q] += __shfl_xor(aD[3 * q], o, 64);
+                aD[3 * q + 1] += __shfl_xor(aD[3 * q + 1], o, 64);
+                aD[3 * q + 2] += __shfl_xor(aD[3 * q + 2], o, 64);
+            }
+        }
+    }
+    if (!owner) return;
     const double iV = 1.0 / rk[R_V];
     const double b00 = rk[R_B] * iV, b01 = rk[R_B + 1] * iV, b02 = rk[R_B + 2] * iV;
     const double b11 = rk[R_B + 3] * iV, b12 = rk[R_B + 4] * iV, b22 = rk[R_B + 5] * iV;
@@ -184,21 +209,26 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair64(
 // symmetric neighbour lists (i is a gather neighbour of p iff r < H_i).  All
 // loads of one neighbour slot (position and 1/H, and the G records of rho)
 // are issued before the first is staged, so their latencies overlap.
-template <int G>
+// Q lanes share a particle as in the pair pass.
+template <int G, int Q = 1>
 __global__ __launch_bounds__(kBlock) void k_adj_grad64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
     const double *__restrict__ R, double *__restrict__ lam, double box) {
-    constexpr int NQ = 4 * G;
+    static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
+    constexpr int NQ = 4 * G, PW = 64 / Q, PB = kBlock / Q;
     __shared__ double stage[kBlock / 64][64 * kStage];
     const int64_t blk = xcd_block(nb);
     if (blk >= nb) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t i = blk * kBlock + threadIdx.x;
+    const int sub = lane % Q;
+    const int64_t i0 = blk * PB + wv * PW;      // first particle of the wave
+    const int64_t i = i0 + lane / Q;
     const bool active = i < n;
+    const bool owner = active && sub == 0;
     const int64_t ic = active ? i : n - 1;
-    const int64_t w = i >> 6;
-    const bool wave_live = (w << 6) < n;
+    const int64_t w = i0 >> 6;
+    const bool wave_live = i0 < n;
     const double ibox = 1.0 / box;
     double *sb = stage[wv];
     const double *rp = geo + (int64_t)kRec * ic;
@@ -208,10 +238,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad64(
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     double sgx = 0.0, sgy = 0.0, sgz = 0.0;
     if (wave_live) {
-        const int64_t base = wave_base[w] + lane;
-        const int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
+        const int64_t base = wave_base[w] + (i & 63);
+        int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
         const int32_t nn = active ? n_nbr[i] : 0;
-        for (int32_t k = 0; k < kmax; ++k) {
+        if (Q > 1) {                            // the longest list of this wave's particles
+            kmax = nn;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
+        }
+        for (int32_t kk = 0; kk < kmax; kk += Q) {
+            const int32_t k = kk + sub;
             const bool valid = k < nn;
             const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
             int64_t row[8];
@@ -265,7 +301,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad64(
             }
         }
     }
-    if (!active) return;
+    if (Q > 1) {
+#pragma unroll
+        for (int o = 1; o < Q; o <<= 1) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] += __shfl_xor(acc[q], o, 64);
+            sgx += __shfl_xor(sgx, o, 64);
+            sgy += __shfl_xor(sgy, o, 64);
+            sgz += __shfl_xor(sgz, o, 64);
+        }
+    }
+    if (!owner) return;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const double *Rp = R + (i * G + g) * 16;
@@ -310,6 +356,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_inject(int32_t S, int G,
 #ifndef RT_ADJ_GW
 #define RT_ADJ_GW 1
 #endif
+// Lanes per particle of the adjoint pair pass and of the transposed gradient
+// (1, 2 or 4).  On the 128^3 adjoint workload 4 lanes took the transposed
+// gradient from 4.2 to about 2 ms per step (backward 337 -> 292 ms); the pair
+// pass gains little (one group per wave already keeps its records in cache).
+#ifndef RT_ADJ_Q
+#define RT_ADJ_Q 4
+#endif
+#ifndef RT_ADJ_GRAD_Q
+#define RT_ADJ_GRAD_Q 4
+#endif
+constexpr int kAQ = RT_ADJ_Q, kAGQ = RT_ADJ_GRAD_Q;
 
 template <int G>
 void launch_adjoint64(rt_ctx *ctx, const double *UD, const double *Uung, const double *lam_next,
@@ -318,11 +375,13 @@ void launch_adjoint64(rt_ctx *ctx, const double *UD, const double *Uung, const d
     hipStream_t st = ctx->stream;
     k_adj_guard64<G><<<nblk(n * G), kBlock, 0, st>>>(n, Uung, lam_next, lam2, ctx->p.c_red);
     constexpr int GW = (RT_ADJ_GW == 0 || G % RT_ADJ_GW != 0) ? G : RT_ADJ_GW;
-    k_adj_pair64<G, GW><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, st>>>(
-        n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt, ctx->p.c_red,
+    const int64_t np = (n + kBlock / kAQ - 1) / (kBlock / kAQ);
+    k_adj_pair64<G, GW, kAQ><<<(unsigned)xcd_grid(np * (G / GW)), kBlock, 0, st>>>(
+        n, np, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt, ctx->p.c_red,
         ctx->p.box, R);
-    k_adj_grad64<G><<<(unsigned)xcd_grid(nb), kBlock, 0, st>>>(
-        n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, R, lam, ctx->p.box);
+    const int64_t ng = (n + kBlock / kAGQ - 1) / (kBlock / kAGQ);
+    k_adj_grad64<G, kAGQ><<<(unsigned)xcd_grid(ng), kBlock, 0, st>>>(
+        n, ng, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, R, lam, ctx->p.box);
 }
 
 }  // namespace
