@@ -168,21 +168,27 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair32(
     }
 }
 
-template <int G>
+// Q lanes share a particle, each taking every Q-th neighbour slot; the
+// per-lane compensated sums are combined in FP64 by a fixed butterfly.
+template <int G, int Q = 1>
 __global__ __launch_bounds__(kBlock) void k_adj_grad32(
     int64_t n, int64_t nb, const float *__restrict__ geo32, const int32_t *__restrict__ nbr,
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
     const float *__restrict__ R, float *__restrict__ lam, double box) {
-    constexpr int NQ = 4 * G;
+    static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
+    constexpr int NQ = 4 * G, PW = 64 / Q, PB = kBlock / Q;
     __shared__ float stage[kBlock / 64][64 * kStage32];
     const int64_t blk = xcd_block(nb);
     if (blk >= nb) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t i = blk * kBlock + threadIdx.x;
+    const int sub = lane % Q;
+    const int64_t i0 = blk * PB + wv * PW;      // first particle of the wave
+    const int64_t i = i0 + lane / Q;
     const bool active = i < n;
+    const bool owner = active && sub == 0;
     const int64_t ic = active ? i : n - 1;
-    const int64_t w = i >> 6;
-    const bool wave_live = (w << 6) < n;
+    const int64_t w = i0 >> 6;
+    const bool wave_live = i0 < n;
     const double ibox = 1.0 / box;
     float *sb = stage[wv];
     const float *rp = geo32 + (int64_t)F_REC * ic;
@@ -194,10 +200,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad32(
     for (int q = 0; q < NQ; ++q) acc[q].s = acc[q].c = 0.0f;
     float sgx = 0.0f, sgy = 0.0f, sgz = 0.0f;
     if (wave_live) {
-        const int64_t base = wave_base[w] + lane;
-        const int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
+        const int64_t base = wave_base[w] + (i & 63);
+        int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
         const int32_t nn = active ? n_nbr[i] : 0;
-        for (int32_t k = 0; k < kmax; ++k) {
+        if (Q > 1) {                            // the longest list of this wave's particles
+            kmax = nn;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
+        }
+        for (int32_t kk = 0; kk < kmax; kk += Q) {
+            const int32_t k = kk + sub;
             const bool valid = k < nn;
             const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
             int64_t row[4];
@@ -260,7 +272,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad32(
             }
         }
     }
-    if (!active) return;
+    double av[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) av[q] = acc[q].value();
+    if (Q > 1) {
+#pragma unroll
+        for (int o = 1; o < Q; o <<= 1) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) av[q] += __shfl_xor(av[q], o, 64);
+            sgx += __shfl_xor(sgx, o, 64);
+            sgy += __shfl_xor(sgy, o, 64);
+            sgz += __shfl_xor(sgz, o, 64);
+        }
+    }
+    if (!owner) return;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const float *Rp = R + (i * G + g) * 16;
@@ -268,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad32(
         for (int m = 0; m < 4; ++m)
             lam[(i * G + g) * 4 + m] = (float)(
                 (double)Rp[m] - (double)(sgx * Rp[4 + 3 * m] + sgy * Rp[5 + 3 * m] + sgz * Rp[6 + 3 * m]) +
-                acc[4 * g + m].value());
+                av[4 * g + m]);
     }
 }
 
@@ -278,6 +303,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad32(
 #ifndef RT_ADJ32_GW
 #define RT_ADJ32_GW 1
 #endif
+// Lanes per particle of the FP32 transposed gradient (1, 2 or 4); 4 took the
+// FP32C backward of the 128^3 adjoint workload from 188 to 166 ms.
+#ifndef RT_ADJ32_GRAD_Q
+#define RT_ADJ32_GRAD_Q 4
+#endif
+constexpr int kAGQ32 = RT_ADJ32_GRAD_Q;
 
 template <int G>
 void launch(rt_ctx *ctx, const float *UD, const float *Uung, const float *lam_next, float *lam2,
@@ -289,8 +320,9 @@ void launch(rt_ctx *ctx, const float *UD, const float *Uung, const float *lam_ne
     k_adj_pair32<G, GW><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, st>>>(
         n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt,
         ctx->p.c_red, ctx->p.box, R);
-    k_adj_grad32<G><<<(unsigned)xcd_grid(nb), kBlock, 0, st>>>(
-        n, nb, ctx->geo32, ctx->nbr, ctx->wave_base, ctx->n_nbr, R, lam, ctx->p.box);
+    const int64_t ng = (n + kBlock / kAGQ32 - 1) / (kBlock / kAGQ32);
+    k_adj_grad32<G, kAGQ32><<<(unsigned)xcd_grid(ng), kBlock, 0, st>>>(
+        n, ng, ctx->geo32, ctx->nbr, ctx->wave_base, ctx->n_nbr, R, lam, ctx->p.box);
 }
 
 }  // namespace
