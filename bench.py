@@ -354,8 +354,11 @@ def run_adjoint(w, precision, dev):
         Et = Ut[pr, :, 0].double().clone()
     L = torch.from_numpy(w.L).to(dev).requires_grad_(True)
     U0g = U0.clone().requires_grad_(True)
-    # warm-up of both directions
-    U = rollout(rt, L, U0g, 2, 1)
+    # warm-up of both directions with the timed configuration, so that the
+    # checkpoint and record buffers are held by torch's caching allocator
+    # before the timed region (their first allocation made the forward time
+    # vary by up to 40%)
+    U = rollout(rt, L, U0g, w.steps, w.ckpt_every)
     U[pr, :, 0].double().sum().backward()
     L.grad = None
     U0g.grad = None
