@@ -104,10 +104,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair64(
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
         }
+        // the next iteration's neighbour index is loaded one iteration ahead
+        int32_t jn = sub < nn ? nbr[base + 64 * (int64_t)sub] : (int32_t)ic;
         for (int32_t kk = 0; kk < kmax; kk += Q) {
             const int32_t k = kk + sub;
             const bool valid = k < nn;
-            const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
+            const int32_t j = jn;
+            jn = k + Q < nn ? nbr[base + 64 * (int64_t)(k + Q)] : (int32_t)ic;
             int64_t row[8];
 #pragma unroll
             for (int m = 0; m < 8; ++m) row[m] = __shfl(j, 8 * m + (lane >> 3), 64);
@@ -246,10 +249,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad64(
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
         }
+        // the next iteration's neighbour index is loaded one iteration ahead
+        int32_t jn = sub < nn ? nbr[base + 64 * (int64_t)sub] : (int32_t)ic;
         for (int32_t kk = 0; kk < kmax; kk += Q) {
             const int32_t k = kk + sub;
             const bool valid = k < nn;
-            const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
+            const int32_t j = jn;
+            jn = k + Q < nn ? nbr[base + 64 * (int64_t)(k + Q)] : (int32_t)ic;
             int64_t row[8];
 #pragma unroll
             for (int m = 0; m < 8; ++m) row[m] = __shfl(j, 8 * m + (lane >> 3), 64);

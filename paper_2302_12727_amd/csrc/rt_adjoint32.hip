@@ -86,9 +86,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair32(
         const int64_t base = wave_base[w] + lane;
         const int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
         const int32_t nn = active ? n_nbr[i] : 0;
+        // the next iteration's neighbour index is loaded one iteration ahead
+        int32_t jn = 0 < nn ? nbr[base] : (int32_t)ic;
         for (int32_t k = 0; k < kmax; ++k) {
             const bool valid = k < nn;
-            const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
+            const int32_t j = jn;
+            jn = k + 1 < nn ? nbr[base + 64 * (int64_t)(k + 1)] : (int32_t)ic;
             int64_t row[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) row[m] = __shfl(j, 16 * m + (lane >> 2), 64);
@@ -208,10 +211,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad32(
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
         }
+        // the next iteration's neighbour index is loaded one iteration ahead
+        int32_t jn = sub < nn ? nbr[base + 64 * (int64_t)sub] : (int32_t)ic;
         for (int32_t kk = 0; kk < kmax; kk += Q) {
             const int32_t k = kk + sub;
             const bool valid = k < nn;
-            const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
+            const int32_t j = jn;
+            jn = k + Q < nn ? nbr[base + 64 * (int64_t)(k + Q)] : (int32_t)ic;
             int64_t row[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) row[m] = __shfl(j, 16 * m + (lane >> 2), 64);

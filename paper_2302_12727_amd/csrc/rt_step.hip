@@ -71,8 +71,11 @@ __global__ __launch_bounds__(kBlock) void k_gradient64(
     for (int q = 0; q < NQ; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
     const int64_t base = wave_base[i >> 6] + (i & 63);
     const int32_t ng = n_gath[i];
+    // the next neighbour index is loaded one iteration ahead
+    int64_t jn = sub < ng ? nbr[base + 64 * (int64_t)sub] : 0;
     for (int32_t k = sub; k < ng; k += Q) {
-        const int64_t j = nbr[base + 64 * (int64_t)k];
+        const int64_t j = jn;
+        if (k + Q < ng) jn = nbr[base + 64 * (int64_t)(k + Q)];
         const double sx = min_image(xs[3 * j] - px, box, ibox);
         const double sy = min_image(xs[3 * j + 1] - py, box, ibox);
         const double sz = min_image(xs[3 * j + 2] - pz, box, ibox);
@@ -209,10 +212,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
         }
         if (BIN && __ballot(nn > 0) == 0) kmax = 0;   // no due pair in this wave
+        // the neighbour index of the next iteration is loaded one iteration
+        // ahead, so its latency overlaps this iteration's record loads
+        int32_t jn = sub < nn ? nbr[base + 64 * (int64_t)sub] : (int32_t)ic;
         for (int32_t kk = 0; kk < kmax; kk += Q) {
             const int32_t k = kk + sub;
             const bool valid = k < nn;
-            const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
+            const int32_t j = jn;
+            jn = k + Q < nn ? nbr[base + 64 * (int64_t)(k + Q)] : (int32_t)ic;
             int64_t row[8];
 #pragma unroll
             for (int m = 0; m < 8; ++m) row[m] = __shfl(j, 8 * m + (lane >> 3), 64);

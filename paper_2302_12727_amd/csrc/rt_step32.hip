@@ -39,8 +39,11 @@ __global__ __launch_bounds__(kBlock) void k_gradient32(
     for (int q = 0; q < NQ; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0f;
     const int64_t base = wave_base[i >> 6] + (i & 63);
     const int32_t ng = n_gath[i];
+    // the next neighbour index is loaded one iteration ahead
+    int64_t jn = sub < ng ? nbr[base + 64 * (int64_t)sub] : 0;
     for (int32_t k = sub; k < ng; k += Q) {
-        const int64_t j = nbr[base + 64 * (int64_t)k];
+        const int64_t j = jn;
+        if (k + Q < ng) jn = nbr[base + 64 * (int64_t)(k + Q)];
         const float sx = (float)min_image(xs[3 * j] - px, box, ibox);
         const float sy = (float)min_image(xs[3 * j + 1] - py, box, ibox);
         const float sz = (float)min_image(xs[3 * j + 2] - pz, box, ibox);
@@ -89,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_gradient32(
 // FP64 transport); the per-lane compensated sums are combined in FP64 by a
 // fixed butterfly.
 template <int G, bool HLL = false, int Q = 1>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((HLL && G <= 3) ? 3 : 1))) void k_transport32(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ? 3 : 1))) void k_transport32(
     int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ geo,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_nbr, const float *__restrict__ UD,
@@ -150,10 +153,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((HLL && 
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
         }
+        // the next iteration's neighbour index is loaded one iteration ahead
+        int32_t jn = sub < nn ? nbr[base + 64 * (int64_t)sub] : (int32_t)ic;
         for (int32_t kk = 0; kk < kmax; kk += Q) {
             const int32_t k = kk + sub;
             const bool valid = k < nn;
-            const int32_t j = valid ? nbr[base + 64 * (int64_t)k] : (int32_t)ic;
+            const int32_t j = jn;
+            jn = k + Q < nn ? nbr[base + 64 * (int64_t)(k + Q)] : (int32_t)ic;
             int64_t row[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) row[m] = __shfl(j, 16 * m + (lane >> 2), 64);
