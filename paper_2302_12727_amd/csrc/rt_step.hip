@@ -14,6 +14,20 @@ namespace {
 
 inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
+// FP64 transport with the GLF solver: the particle's own state and gradients
+// in LDS instead of registers (OWN), which frees the registers to hold the
+// next stage's neighbour lines in flight while the current stage is computed
+// (PIPE).  The HLL instantiations keep both off: they run 3 waves per SIMD
+// at 168 registers, which the in-flight lines would not fit.
+#ifndef RT_TRANSPORT_OWN_LDS
+#define RT_TRANSPORT_OWN_LDS 1
+#endif
+#ifndef RT_TRANSPORT_PIPE
+#define RT_TRANSPORT_PIPE 1
+#endif
+constexpr bool kOwnL = RT_TRANSPORT_OWN_LDS != 0;
+constexpr bool kPipe = RT_TRANSPORT_PIPE != 0;
+
 // ---------------------------------------------------------------------------
 // Injection: E_g += dt sum_s xi_sg L_s / V_g, one thread per receiving particle.
 template <typename T>
@@ -121,8 +135,17 @@ __global__ __launch_bounds__(kBlock) void k_gradient64(
 // the same particles): fewer groups per wave keep less state in registers
 // and so more waves resident, at the price of recomputing the pair geometry
 // once per group slice.
-// The compiler is held to the 256 registers of 2 waves per SIMD: this kernel
-// sits at about 250 VGPRs, and at 1 wave per SIMD it runs 1.6x slower.
+// The compiler is held to the 256 registers of 2 waves per SIMD (at 1 wave
+// per SIMD the kernel runs 1.6x slower).
+//
+// OWNL: the particle's own state and gradients (48 doubles at 3 groups) are
+// read from the block's LDS instead of being held in registers.  PIPE: with
+// the registers this frees, each stage's neighbour lines are loaded one stage
+// ahead (the next group's lines while a group is computed; the next
+// iteration's geometry and first group lines while the last group is), so no
+// stage waits for its own loads.  Measured on the 3-group 128^3 lattice: 2%
+// faster with the Hopkins surfaces, 9% with the Ivanova ones (whose
+// register-held form spilled).
 //
 // HLL: the HLL solver (eq:riemann-HLL) with the wave-speed table hll in
 // place of GLF.
@@ -135,9 +158,10 @@ __global__ __launch_bounds__(kBlock) void k_gradient64(
 // eq:transport-update-explicit with min{dt_k, dt_l}).
 // With one group per wave the HLL instantiation fits 3 waves per SIMD (168
 // registers), measured 4% faster than 2 (the GLF one is slower there).
-template <int G, int GW, bool BIN = false, bool HLL = false, bool IVA = false, int Q = 1>
+template <int G, int GW, bool BIN = false, bool HLL = false, bool IVA = false, int Q = 1,
+          bool OWNL = false, bool PIPE = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
-    (HLL && GW == 1) ? 3 : 2, (HLL && GW == 1) ? 3 : 2))) void k_transport64(
+    (HLL && GW == 1 && !OWNL) ? 3 : 2, (HLL && GW == 1 && !OWNL) ? 3 : 2))) void k_transport64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
     const double *__restrict__ UD, const double *__restrict__ dtp, double c, double box,
@@ -150,7 +174,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     constexpr int NS = G / GW, NQ = 4 * G;
     constexpr int PW = 64 / Q, PB = kBlock / Q;   // particles per wave, per block
+    constexpr int OS = 16 * GW + 1;               // own record in LDS (padded, doubles)
     __shared__ double stage[kBlock / 64][64 * kStage];
+    __shared__ double own[OWNL ? PB * OS : 1];
     __shared__ double smem[(kBlock / 64) * 2 * GW];
     __shared__ unsigned long long scnt[4];
     const int64_t bg = xcd_block(nb * NS);
@@ -171,20 +197,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     if (threadIdx.x < 4) scnt[threadIdx.x] = 0;
     double *sb = stage[wv];
 
-    // own particle: geometry record, state and gradients (registers)
+    // own particle: geometry record, state and gradients (registers, or with
+    // OWNL the wave's LDS, each lane of the particle copying every Q-th value)
     const double *rk = geo + (int64_t)kRec * ic;
-    double Ui[4 * GW], Di[12 * GW];
+    double Ui[OWNL ? 1 : 4 * GW], Di[OWNL ? 1 : 12 * GW];
+    double *ow = own + (OWNL ? (threadIdx.x / Q) * OS : 0);
+    if constexpr (OWNL) {
 #pragma unroll
-    for (int g = 0; g < GW; ++g) {
-        const double *r = UD + (ic * G + g0 + g) * 16;
+        for (int e = sub; e < 16 * GW; e += Q) ow[e] = UD[(ic * G + g0 + (e >> 4)) * 16 + (e & 15)];
+        wave_lds_sync();
+    } else {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            Ui[4 * g + m] = r[m];
-            Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
-            Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
-            Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
+        for (int g = 0; g < GW; ++g) {
+            const double *r = UD + (ic * G + g0 + g) * 16;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                Ui[4 * g + m] = r[m];
+                Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
+                Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
+                Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
+            }
         }
     }
+    // q = 4 g + m: the state value, and its gradient component a
+    auto ui = [&](int q) -> double {
+        if constexpr (OWNL) return ow[16 * (q >> 2) + (q & 3)];
+        else return Ui[q];
+    };
+    auto di = [&](int q, int a) -> double {
+        if constexpr (OWNL) return ow[16 * (q >> 2) + 4 + 3 * (q & 3) + a];
+        else return Di[3 * q + a];
+    };
     double acc[4 * GW];
 #pragma unroll
     for (int q = 0; q < 4 * GW; ++q) acc[q] = 0.0;
@@ -215,6 +258,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
         // the neighbour index of the next iteration is loaded one iteration
         // ahead, so its latency overlaps this iteration's record loads
         int32_t jn = sub < nn ? nbr[base + 64 * (int64_t)sub] : (int32_t)ic;
+        // PIPE: while a stage computes, the lines of the next group (pb), or
+        // of the next iteration's geometry (pa) and first group (pb), are in
+        // flight in registers
+        double2 pa[PIPE ? 8 : 1], pb[PIPE ? 8 : 1];
+        if constexpr (PIPE) {
+            if (kmax > 0) {
+                int64_t rn[8], rg[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    rn[m] = __shfl(jn, 8 * m + (lane >> 3), 64);
+                    rg[m] = rn[m] * G + g0;
+                }
+                load_lines(geo, rn, lane, *reinterpret_cast<double2(*)[8]>(pa));
+                load_lines(UD, rg, lane, *reinterpret_cast<double2(*)[8]>(pb));
+            }
+        }
         for (int32_t kk = 0; kk < kmax; kk += Q) {
             const int32_t k = kk + sub;
             const bool valid = k < nn;
@@ -224,7 +283,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
             for (int m = 0; m < 8; ++m) row[m] = __shfl(j, 8 * m + (lane >> 3), 64);
             // pair geometry from the staged geometry records
-            stage_lines(geo, row, sb, lane);
+            if constexpr (PIPE) {
+                store_lines(*reinterpret_cast<double2(*)[8]>(pa), sb, lane);
+            } else {
+                stage_lines(geo, row, sb, lane);
+            }
             double rl[12];
 #pragma unroll
             for (int q = 0; q < 12; ++q) rl[q] = sb[lane * kStage + q];
@@ -248,19 +311,39 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             const double iAn = (HLL && pg.An > 0.0) ? rcp64(pg.An) : 0.0;
 #pragma unroll
             for (int g = 0; g < GW; ++g) {
-                int64_t rowg[8];
+                if constexpr (PIPE) {
+                    double2(&vb)[8] = *reinterpret_cast<double2(*)[8]>(pb);
+                    store_lines(vb, sb, lane);
+                    if (g + 1 < GW) {
+                        int64_t rowg[8];
 #pragma unroll
-                for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g0 + g;
-                stage_lines(UD, rowg, sb, lane);
+                        for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g0 + g + 1;
+                        load_lines(UD, rowg, lane, vb);
+                    } else if (kk + Q < kmax) {
+                        int64_t rn[8], rg[8];
+#pragma unroll
+                        for (int m = 0; m < 8; ++m) {
+                            rn[m] = __shfl(jn, 8 * m + (lane >> 3), 64);
+                            rg[m] = rn[m] * G + g0;
+                        }
+                        load_lines(geo, rn, lane, *reinterpret_cast<double2(*)[8]>(pa));
+                        load_lines(UD, rg, lane, vb);
+                    }
+                } else {
+                    int64_t rowg[8];
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g0 + g;
+                    stage_lines(UD, rowg, sb, lane);
+                }
                 const double *Rl = sb + lane * kStage;
                 double qL[4], qR[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const int q = 4 * g + m;
-                    const double dk = Di[3 * q] * pg.sx + Di[3 * q + 1] * pg.sy + Di[3 * q + 2] * pg.sz;
+                    const double dk = di(q, 0) * pg.sx + di(q, 1) * pg.sy + di(q, 2) * pg.sz;
                     const double dl = Rl[4 + 3 * m] * pg.sx + Rl[5 + 3 * m] * pg.sy + Rl[6 + 3 * m] * pg.sz;
                     const double mm = minmod(dk, dl);
-                    qL[m] = Ui[q] + pg.fk * mm;
+                    qL[m] = ui(q) + pg.fk * mm;
                     qR[m] = Rl[m] - pg.fl * mm;
                 }
                 const int f1 = guard64(qL[0], qL[1], qL[2], qL[3], c);
@@ -308,7 +391,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
                 for (int m = 0; m < 4; ++m) a[m] += acc[4 * g + m];
             }
-            red[g] = V * Ui[4 * g];
+            red[g] = V * ui(4 * g);
             red[GW + g] = 0.0;
         }
     } else if (owner) {
@@ -328,10 +411,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
         }
 #pragma unroll
         for (int g = 0; g < GW; ++g) {
-            double q0 = Ui[4 * g + 0] - dtV * acc[4 * g + 0];
-            double q1 = Ui[4 * g + 1] - dtV * acc[4 * g + 1];
-            double q2 = Ui[4 * g + 2] - dtV * acc[4 * g + 2];
-            double q3 = Ui[4 * g + 3] - dtV * acc[4 * g + 3];
+            double q0 = ui(4 * g + 0) - dtV * acc[4 * g + 0];
+            double q1 = ui(4 * g + 1) - dtV * acc[4 * g + 1];
+            double q2 = ui(4 * g + 2) - dtV * acc[4 * g + 2];
+            double q3 = ui(4 * g + 3) - dtV * acc[4 * g + 3];
             const double Epre = q0;
             if (Uung) {
                 double *u = Uung + i * NQ + 4 * (g0 + g);
@@ -482,8 +565,8 @@ void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double 
     const double2 *tab = (const double2 *)ctx->hll_table;
     const bool iva = ctx->surfaces == RT_IVANOVA;
 #define RT_TRANSPORT_LAUNCH(W, HLL_, IVA_)                                                    \
-    k_transport64<G, W, false, HLL_, IVA_, kQ><<<(unsigned)xcd_grid(nb * (G / W)), kBlock, 0, \
-                                                 ctx->stream>>>(                            \
+    k_transport64<G, W, false, HLL_, IVA_, kQ, kOwnL && !HLL_, kPipe && !HLL_>                \
+        <<<(unsigned)xcd_grid(nb * (G / W)), kBlock, 0, ctx->stream>>>(                       \
         n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,          \
         ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, 0, nullptr, tab,      \
         ctx->ivan)
@@ -527,7 +610,7 @@ void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, d
             ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, tick, accm,
             (const double2 *)ctx->hll_table);
     else
-        k_transport64<G, GW, true, false, false, kQ><<<(unsigned)xcd_grid(nt * (G / GW)), kBlock,
+        k_transport64<G, GW, true, false, false, kQ, kOwnL, kPipe><<<(unsigned)xcd_grid(nt * (G / GW)), kBlock,
                                                        0, ctx->stream>>>(
             n, nt, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
             ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, tick, accm);
