@@ -13,6 +13,13 @@ The M1 flux through the effective surface A is written with g = F/E
 (c^2 P A = c^2 E (1-chi)/2 A + 3/(2+sqrt(4-3f^2)) (g.A) F), which avoids the
 0/0 of n = F/|F| and its infinite derivative at F = 0.  Geometry (h, V, B,
 surfaces) is static and not differentiated.
+
+With `hll` (the wave-speed table of oracle.hll_table(), shape (NF, NMU, 2))
+the transport uses the HLL solver (Part III eq:riemann-HLL) as the C oracle
+does: the face states' extreme eigenvalues interpolated bilinearly in (f, mu)
+from the table (which is not differentiated), and the solver's weights.  At
+the kinks (the max/min of the speeds, the clamps of f and mu, the table
+cells) the derivative is that of the branch the forward takes.
 """
 from __future__ import annotations
 
@@ -60,10 +67,54 @@ def flux_through(q: torch.Tensor, A: torch.Tensor, c: float) -> torch.Tensor:
     return torch.cat([out0[..., None], outv], dim=-1)
 
 
-class TorchStep:
-    """One RT step on the oracle's geometry (oracle.Geometry, oracle.Sources)."""
+def hll_speeds(q: torch.Tensor, A: torch.Tensor, An: torch.Tensor, c: float,
+               tab: torch.Tensor):
+    """(lambda_min, lambda_max) of guarded states q [..., 4] across surfaces A
+    [..., 3] (|A| = An): the table (NF, NMU, 2) at f = |F|/(cE) <= 1 and
+    mu = F.A/(|F||A|) in [-1, 1], bilinear; f = mu = 0 where E or F is 0."""
+    nf, nmu = tab.shape[0], tab.shape[1]
+    E = q[..., 0]
+    F = q[..., 1:]
+    F2 = (F * F).sum(-1)
+    ok = (E > 0) & (F2 > 0)
+    Fn = torch.sqrt(torch.where(ok, F2, torch.ones_like(F2)))
+    Es = torch.where(ok, E, torch.ones_like(E))
+    fr = Fn / (c * Es)
+    f = torch.where(ok, torch.where(fr <= 1.0, fr, torch.ones_like(fr)), torch.zeros_like(fr))
+    mr = (F * A).sum(-1) / (Fn * An)
+    mc = torch.where(mr > 1.0, torch.ones_like(mr), torch.where(mr < -1.0, -torch.ones_like(mr), mr))
+    mu = torch.where(ok, mc, torch.zeros_like(mc))
+    x = f * (nf - 1)
+    y = (mu + 1.0) * (0.5 * (nmu - 1))
+    i = torch.clamp(torch.floor(x.detach()).long(), 0, nf - 2)
+    j = torch.clamp(torch.floor(y.detach()).long(), 0, nmu - 2)
+    tx = (x - i)[..., None]
+    ty = (y - j)[..., None]
+    v = ((1 - tx) * ((1 - ty) * tab[i, j] + ty * tab[i, j + 1])
+         + tx * ((1 - ty) * tab[i + 1, j] + ty * tab[i + 1, j + 1]))
+    return c * v[..., 0], c * v[..., 1]
 
-    def __init__(self, geo, srcs=None):
+
+def hll_weights(loL, hiL, loR, hiR, An):
+    """(w1, w2, w3) of Phi.A = w1 F_L.A + w2 F_R.A + w3 (U_R - U_L)."""
+    mx = torch.where(hiL >= hiR, hiL, hiR)
+    mn = torch.where(loL <= loR, loL, loR)
+    lp = torch.where(mx > 0, mx, torch.zeros_like(mx))
+    lm = torch.where(mn < 0, mn, torch.zeros_like(mn))
+    den = lp - lm
+    ok = den > 0
+    iden = torch.where(ok, 1.0 / torch.where(ok, den, torch.ones_like(den)), torch.zeros_like(den))
+    half = torch.full_like(den, 0.5)
+    return (torch.where(ok, lp * iden, half), torch.where(ok, -lm * iden, half),
+            torch.where(ok, lp * lm * An * iden, torch.zeros_like(den)))
+
+
+class TorchStep:
+    """One RT step on the oracle's geometry (oracle.Geometry, oracle.Sources);
+    `hll` selects the HLL solver with that wave-speed table (else GLF)."""
+
+    def __init__(self, geo, srcs=None, hll=None):
+        self.hll = None if hll is None else torch.as_tensor(np.asarray(hll, dtype=np.float64))
         f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64)
         n = geo.n
         self.n, self.c = n, float(geo.c)
@@ -123,8 +174,16 @@ class TorchStep:
         qL = guard(U[self.sk] + self.wk[:, None, None] * m, c)
         qR = guard(U[self.sl] - self.wl[:, None, None] * m, c)
         A = self.A[:, None, :]
-        P = 0.5 * (flux_through(qL, A, c) + flux_through(qR, A, c)) \
-            - 0.5 * c * self.An[:, None, None] * (qR - qL)
+        if self.hll is None:
+            P = 0.5 * (flux_through(qL, A, c) + flux_through(qR, A, c)) \
+                - 0.5 * c * self.An[:, None, None] * (qR - qL)
+        else:
+            An = self.An[:, None]
+            loL, hiL = hll_speeds(qL, A, An, c, self.hll)
+            loR, hiR = hll_speeds(qR, A, An, c, self.hll)
+            w1, w2, w3 = hll_weights(loL, hiL, loR, hiR, An)
+            P = w1[..., None] * flux_through(qL, A, c) + w2[..., None] * flux_through(qR, A, c) \
+                + w3[..., None] * (qR - qL)
         acc = torch.zeros_like(U).index_add(0, self.sk, P)
         return guard(U - dt / self.V[:, None, None] * acc, c)
 

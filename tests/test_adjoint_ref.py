@@ -77,3 +77,64 @@ def test_autograd_matches_finite_differences(small):
             return loss_np(geo, srcs, Ux, w.L, w.steps, probes, Et)
         ok, fds = fd_matches(f, w.U0[i, grp, m], gU[i, grp, m], np.abs(w.U0[i, grp]).max())
         assert ok, (i, grp, m, gU[i, grp, m], fds)
+
+
+# ---------------------------------------------------------------------------
+# The same two pins with the HLL solver (Part III eq:riemann-HLL): forward
+# against the C oracle's HLL transport, autograd against its central
+# differences.
+@pytest.fixture(scope="module")
+def small_hll():
+    w = workloads.lattice_workload(10, 2, 3, 3, seed=331, name="adj-small-hll")
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs)
+    tab = oracle.hll_table()
+    ts = TorchStep(geo, srcs, hll=tab)
+    g = workloads.rng(332)
+    probes = np.sort(g.choice(w.n, 64, replace=False))
+    Et = g.lognormal(size=(64, w.groups))
+    return w, geo, srcs, ts, probes, Et, tab
+
+
+def loss_np_hll(geo, srcs, U0, L, steps, probes, Et, tab):
+    U, _ = oracle.run(geo, srcs, U0, L, steps, hll=tab)
+    return float(((U[probes, :, 0] - Et) ** 2).sum())
+
+
+def test_hll_forward_matches_oracle(small_hll):
+    w, geo, srcs, ts, _, _, tab = small_hll
+    ref, _ = oracle.run(geo, srcs, w.U0, w.L, 3, hll=tab)
+    got = ts.run(torch.from_numpy(w.U0), torch.from_numpy(w.L), geo.dt, 3).numpy()
+    scale = np.abs(ref).max(axis=-1, keepdims=True)
+    assert (np.abs(got - ref) / scale).max() < 1e-12
+    glf, _ = oracle.run(geo, srcs, w.U0, w.L, 3)
+    assert (np.abs(got - glf) / scale).max() > 1e-6          # the solver matters here
+
+
+def test_hll_autograd_matches_finite_differences(small_hll):
+    w, geo, srcs, ts, probes, Et, tab = small_hll
+    U0 = torch.from_numpy(w.U0.copy()).requires_grad_(True)
+    L = torch.from_numpy(w.L.copy()).requires_grad_(True)
+    U = ts.run(U0, L, geo.dt, w.steps)
+    loss = ((U[probes, :, 0] - torch.from_numpy(Et)) ** 2).sum()
+    gL, gU = torch.autograd.grad(loss, (L, U0))
+    gL, gU = gL.numpy(), gU.numpy()
+    for s in range(w.L.shape[0]):
+        for grp in range(w.groups):
+            def f(v):
+                Lx = w.L.copy()
+                Lx[s, grp] = v
+                return loss_np_hll(geo, srcs, w.U0, Lx, w.steps, probes, Et, tab)
+            ok, fds = fd_matches(f, w.L[s, grp], gL[s, grp], w.L[s, grp])
+            assert ok, (s, grp, gL[s, grp], fds)
+    g = workloads.rng(17)
+    for _ in range(12):
+        i = int(g.choice(probes))
+        grp, m = int(g.integers(w.groups)), int(g.integers(4))
+
+        def f(v):
+            Ux = w.U0.copy()
+            Ux[i, grp, m] = v
+            return loss_np_hll(geo, srcs, Ux, w.L, w.steps, probes, Et, tab)
+        ok, fds = fd_matches(f, w.U0[i, grp, m], gU[i, grp, m], np.abs(w.U0[i, grp]).max())
+        assert ok, (i, grp, m, gU[i, grp, m], fds)
