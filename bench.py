@@ -331,10 +331,11 @@ def large_adjoint(dev):
     return res
 
 
-def run_adjoint(w, precision, dev):
+def run_adjoint(w, precision, dev, solver="glf"):
     """Forward rollout of w.steps steps with checkpoints every w.ckpt_every,
     then its backward (segment recompute + adjoint); loss on the probe
-    particles against E_target from a run at perturbed luminosities."""
+    particles against E_target from a run at perturbed luminosities.
+    solver: the Riemann solver, "glf" or "hll"."""
     import numpy as np
     import torch
     from paper_2302_12727_amd import RT
@@ -343,6 +344,8 @@ def run_adjoint(w, precision, dev):
     rt = RT(w.n, w.groups, precision=precision, cfl=w.cfl, c_red=w.c_red, device=dev)
     perm, *_ = rt.rt_build_cells(torch.from_numpy(w.x).to(dev))
     rt.rt_set_sources(torch.from_numpy(w.xs).to(dev))
+    if solver != "glf":
+        rt.rt_set_riemann(solver)
     rt.rt_sync()
     p = perm.cpu().numpy()
     inv = np.empty_like(p)
@@ -376,6 +379,7 @@ def run_adjoint(w, precision, dev):
     gU0 = U0g.grad.double()
     return {"workload": w.name, "n": w.n, "groups": w.groups, "sources": int(w.xs.shape[0]),
             "steps": w.steps, "ckpt_every": w.ckpt_every, "precision": precision,
+            "solver": solver,
             "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
             "adjoint_forward_ratio": (t2 - t1) / (t1 - t0),
             "peak_hbm_GiB": (torch.cuda.max_memory_allocated(dev) + st["device_bytes"]) / 2 ** 30,
@@ -508,6 +512,12 @@ def main():
         ad["workload"] += " (128^3 jittered lattice, 3 groups, 64 sources, 4096 probes)"
         out["adjoint"] = ad
         torch.cuda.empty_cache()
+        if args.precision == "fp64":
+            ah = run_adjoint(wa, "fp64", dev, solver="hll")
+            ah.pop("grad")
+            out["hll"]["adjoint"] = {k: ah[k] for k in ("forward_ms", "backward_ms",
+                                                        "adjoint_forward_ratio", "peak_hbm_GiB")}
+            torch.cuda.empty_cache()
         out["plummer_fp32c_vs_fp64"] = compare_precisions(workloads.config(2), dev)
         torch.cuda.empty_cache()
         out["plummer_time_bins"] = compare_time_bins(workloads.config(2), dev)

@@ -158,8 +158,11 @@ rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q);
  *           [-1, 1] and interpolates bilinearly (a state with E <= 0 or F = 0
  *           is looked up at f = 0).
  * HLL is implemented in rt_transport (FP64 and FP32C, the FP32C kernel
- * interpolating an FP32 copy of the table) and in rt_tick; rt_adjoint
- * returns RT_ESTATE while HLL is selected.  The table (RT_HLL_NF x RT_HLL_NMU
+ * interpolating an FP32 copy of the table), in rt_tick and in the FP64
+ * rt_adjoint (the derivative of the interpolated speeds, with the branch the
+ * forward takes at the max/min of the speeds, the clamps of f and mu and the
+ * table cells); the FP32C rt_adjoint returns RT_ESTATE while HLL is
+ * selected.  The table (RT_HLL_NF x RT_HLL_NMU
  * x 2 doubles) is computed on the host and uploaded on the first selection of
  * RT_HLL (synchronous). */
 typedef enum { RT_GLF = 0, RT_HLL = 1 } rt_riemann;
@@ -303,7 +306,9 @@ rt_status rt_tick(rt_ctx *ctx, double *U, const double *L, int64_t tick, double 
  *            alias lam_next.
  *   dL_dL    [S][G] double, accumulated (+=) dLoss/dL, or NULL.
  * U_pre is read only when UD is NULL.  Scratch (a few state-sized buffers) is
- * allocated by the library on first use. */
+ * allocated by the library on first use.  The step differentiated uses the
+ * selected Riemann solver (GLF, or HLL in FP64 contexts) and the Hopkins
+ * surfaces: RT_ESTATE with RT_IVANOVA selected, or with HLL in FP32C. */
 rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
                      const void *UD, const void *U_unguarded, const void *lam_next, void *lam,
                      double *dL_dL);

@@ -26,6 +26,14 @@ namespace {
 
 inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
+// Waves per SIMD the HLL pair pass is held to.  At 2 it spills about 30
+// registers, at 1 it keeps them (in accumulation registers); on the 3-group
+// 128^3 lattice the backward of 20 steps took 496 ms at 2 and 577 ms at 1.
+#ifndef RT_ADJ_HLL_WAVES
+#define RT_ADJ_HLL_WAVES 2
+#endif
+constexpr int kAdjHllWaves = RT_ADJ_HLL_WAVES;
+
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_adj_guard64(int64_t n, const double *__restrict__ Uung,
                                                         const double *__restrict__ lam_next,
@@ -49,12 +57,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_guard64(int64_t n, const double 
 //
 // Q lanes share a particle, each taking every Q-th neighbour slot (as in the
 // forward transport); the partial sums are combined by a fixed butterfly.
-template <int G, int GW, int Q = 1>
-__global__ __launch_bounds__(kBlock) void k_adj_pair64(
+//
+// HLL: the pair flux of the HLL solver, P = w1 F_L.A + w2 F_R.A + w3 (U_R -
+// U_L) with weights from the face states' wave speeds (the table hll); its
+// cotangent m = 2 nu pulls back through the two M1 fluxes, the jump term, the
+// weights and, through the speeds, the table lookups (hll_weights_vjp,
+// hll_speeds64_vjp).
+template <int G, int GW, int Q = 1, bool HLL = false>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(HLL ? kAdjHllWaves : 1)))
+void k_adj_pair64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
     const double *__restrict__ UD, const double *__restrict__ lam2,
-    const double *__restrict__ dtp, double c, double box, double *__restrict__ R) {
+    const double *__restrict__ dtp, double c, double box, double *__restrict__ R,
+    const double2 *__restrict__ hll = nullptr) {
     static_assert(G % GW == 0, "group slices must tile the groups");
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     constexpr int NS = G / GW, NQ = 4 * GW, PW = 64 / Q, PB = kBlock / Q;
@@ -156,11 +172,40 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair64(
                 for (int m = 0; m < 4; ++m) nu[m] = 0.5 * (dtVl * Ll[m] - dtVk * Li[4 * g + m]);
                 m1_flux64_vjp(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, nu, tL);
                 m1_flux64_vjp(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, nu, tR);
-                const double dis = c * pg.An;   // 2 * (c/2) |A| times nu = mu/2
+                if constexpr (HLL) {
+                    const double iAn = pg.An > 0.0 ? rcp64(pg.An) : 0.0;
+                    double loL, hiL, loR, hiR, w1, w2, w3;
+                    hll_speeds64(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, iAn, c, hll, loL,
+                                 hiL);
+                    hll_speeds64(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, iAn, c, hll, loR,
+                                 hiR);
+                    hll_weights(loL, hiL, loR, hiR, pg.An, w1, w2, w3);
+                    double FL[4], FR[4];
+                    m1_flux64(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, FL);
+                    m1_flux64(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, FR);
+                    double S1 = 0.0, S2 = 0.0, S3 = 0.0;   // m . (F_L, F_R, U_R - U_L)
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    tL[m] += dis * nu[m];
-                    tR[m] -= dis * nu[m];
+                    for (int m = 0; m < 4; ++m) {
+                        S1 += nu[m] * FL[m];
+                        S2 += nu[m] * FR[m];
+                        S3 += nu[m] * (qR[m] - qL[m]);
+                        tL[m] = 2.0 * (w1 * tL[m] - w3 * nu[m]);
+                        tR[m] = 2.0 * (w2 * tR[m] + w3 * nu[m]);
+                    }
+                    double gloL, ghiL, gloR, ghiR;
+                    hll_weights_vjp(loL, hiL, loR, hiR, pg.An, 2.0 * S1, 2.0 * S2, 2.0 * S3,
+                                    gloL, ghiL, gloR, ghiR);
+                    hll_speeds64_vjp(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, iAn, c, hll,
+                                     gloL, ghiL, tL);
+                    hll_speeds64_vjp(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, iAn, c, hll,
+                                     gloR, ghiR, tR);
+                } else {
+                    const double dis = c * pg.An;   // 2 * (c/2) |A| times nu = mu/2
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        tL[m] += dis * nu[m];
+                        tR[m] -= dis * nu[m];
+                    }
                 }
                 guard64_vjp(qLp, tL, c);
                 guard64_vjp(qRp, tR, c);
@@ -382,9 +427,14 @@ void launch_adjoint64(rt_ctx *ctx, const double *UD, const double *Uung, const d
     k_adj_guard64<G><<<nblk(n * G), kBlock, 0, st>>>(n, Uung, lam_next, lam2, ctx->p.c_red);
     constexpr int GW = (RT_ADJ_GW == 0 || G % RT_ADJ_GW != 0) ? G : RT_ADJ_GW;
     const int64_t np = (n + kBlock / kAQ - 1) / (kBlock / kAQ);
-    k_adj_pair64<G, GW, kAQ><<<(unsigned)xcd_grid(np * (G / GW)), kBlock, 0, st>>>(
-        n, np, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt, ctx->p.c_red,
-        ctx->p.box, R);
+    if (ctx->solver == RT_HLL)
+        k_adj_pair64<G, GW, kAQ, true><<<(unsigned)xcd_grid(np * (G / GW)), kBlock, 0, st>>>(
+            n, np, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt, ctx->p.c_red,
+            ctx->p.box, R, (const double2 *)ctx->hll_table);
+    else
+        k_adj_pair64<G, GW, kAQ><<<(unsigned)xcd_grid(np * (G / GW)), kBlock, 0, st>>>(
+            n, np, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt, ctx->p.c_red,
+            ctx->p.box, R);
     const int64_t ng = (n + kBlock / kAGQ - 1) / (kBlock / kAGQ);
     k_adj_grad64<G, kAGQ><<<(unsigned)xcd_grid(ng), kBlock, 0, st>>>(
         n, ng, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, R, lam, ctx->p.box);

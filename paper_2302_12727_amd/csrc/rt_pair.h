@@ -108,6 +108,70 @@ __device__ __forceinline__ void hll_weights(double loL, double hiL, double loR, 
     }
 }
 
+// Vector-Jacobian products of the HLL wave speeds and weights (the adjoint of
+// eq:riemann-HLL), with the derivative of the branch the forward takes at each
+// kink: the speed a max/min selects (the first on ties), f and mu passed
+// through while inside [0, 1] and [-1, 1], the table cell of the forward, and
+// nothing where E or F is zero (f = mu = 0 there).
+//
+// hll_weights_vjp: cotangents of (loL, hiL, loR, hiR) from the cotangent sums
+// S1 = m.F_L.A, S2 = m.F_R.A, S3 = m.(U_R - U_L) of the flux cotangent m.
+__device__ __forceinline__ void hll_weights_vjp(double loL, double hiL, double loR, double hiR,
+                                                double An, double S1, double S2, double S3,
+                                                double &gloL, double &ghiL, double &gloR,
+                                                double &ghiR) {
+    gloL = ghiL = gloR = ghiR = 0.0;
+    const double mx = hiL >= hiR ? hiL : hiR, mn = loL <= loR ? loL : loR;
+    const double lp = mx > 0.0 ? mx : 0.0, lm = mn < 0.0 ? mn : 0.0;
+    const double den = lp - lm;
+    if (!(den > 0.0)) return;
+    const double id = rcp64(den), id2 = id * id;
+    // w1 = lp/den, w2 = -lm/den, w3 = lp lm |A|/den
+    const double glp = (-lm * S1 + lm * S2 - An * lm * lm * S3) * id2;
+    const double glm = (lp * S1 - lp * S2 + An * lp * lp * S3) * id2;
+    if (mx > 0.0) (hiL >= hiR ? ghiL : ghiR) = glp;
+    if (mn < 0.0) (loL <= loR ? gloL : gloR) = glm;
+}
+// hll_speeds64_vjp: adds to t (cotangent of the face state) the pull-back of
+// the cotangents glo, ghi of the speeds hll_speeds64 returns for that state.
+__device__ __forceinline__ void hll_speeds64_vjp(double E, double Fx, double Fy, double Fz,
+                                                 double Ax, double Ay, double Az, double iAn,
+                                                 double c, const double2 *__restrict__ tab,
+                                                 double glo, double ghi, double (&t)[4]) {
+    const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+    if (!(E > 0.0 && F2 > 0.0)) return;
+    const double FA = Fx * Ax + Fy * Ay + Fz * Az;
+    const double iF = rsq64(F2), iE = rcp64(c * E);
+    const double fr = F2 * iF * iE, mr = FA * iF * iAn;
+    const double f = fmin(fr, 1.0), mu = fmin(fmax(mr, -1.0), 1.0);
+    const double x = f * (RT_HLL_NF - 1), y = (mu + 1.0) * (0.5 * (RT_HLL_NMU - 1));
+    const int i = max(min((int)x, RT_HLL_NF - 2), 0);
+    const int j = max(min((int)y, RT_HLL_NMU - 2), 0);
+    const double tx = x - i, ty = y - j;
+    const double2 *tb = tab + i * RT_HLL_NMU + j;
+    const double2 v00 = tb[0], v01 = tb[1], v10 = tb[RT_HLL_NMU], v11 = tb[RT_HLL_NMU + 1];
+    const double ux = 1.0 - tx, uy = 1.0 - ty;
+    // d(lo, hi)/dx and d(lo, hi)/dy of the bilinear form (times c)
+    const double gx = glo * (uy * (v10.x - v00.x) + ty * (v11.x - v01.x)) +
+                      ghi * (uy * (v10.y - v00.y) + ty * (v11.y - v01.y));
+    const double gy = glo * (ux * (v01.x - v00.x) + tx * (v11.x - v10.x)) +
+                      ghi * (ux * (v01.y - v00.y) + tx * (v11.y - v10.y));
+    const double gf = c * gx * (RT_HLL_NF - 1), gm = c * gy * (0.5 * (RT_HLL_NMU - 1));
+    if (fr <= 1.0) {            // f = |F|/(cE): df/dE = -f/E, df/dF = F/(|F| c E)
+        const double k = gf * iF * iE;
+        t[0] -= gf * fr * c * iE;
+        t[1] += k * Fx;
+        t[2] += k * Fy;
+        t[3] += k * Fz;
+    }
+    if (mr >= -1.0 && mr <= 1.0) {   // mu = F.A/(|F||A|): dmu/dF = A/(|F||A|) - mu F/|F|^2
+        const double a = gm * iF * iAn, b = gm * mr * iF * iF;
+        t[1] += a * Ax - b * Fx;
+        t[2] += a * Ay - b * Fy;
+        t[3] += a * Az - b * Fz;
+    }
+}
+
 __device__ __forceinline__ double minmod(double a, double b) {
     const double m = (fabs(a) <= fabs(b)) ? a : b;
     return (a * b > 0.0) ? m : 0.0;
