@@ -181,8 +181,9 @@ rt_status rt_set_riemann(rt_ctx *ctx, int32_t solver);
  *               gradients).
  * FP64 contexts after rt_build_cells (RT_ESTATE before, RT_EINVAL on FP32C);
  * selecting RT_IVANOVA computes g (n x 4 doubles, kept and recomputed by
- * later builds).  rt_tick and rt_adjoint return RT_ESTATE while RT_IVANOVA is
- * selected.  The gradient step (eq:gradient) is the same for both. */
+ * later builds).  rt_tick returns RT_ESTATE while RT_IVANOVA is selected;
+ * rt_adjoint differentiates the step with either surfaces (they are static).
+ * The gradient step (eq:gradient) is the same for both. */
 typedef enum { RT_HOPKINS = 0, RT_IVANOVA = 1 } rt_surfaces;
 rt_status rt_set_surfaces(rt_ctx *ctx, int32_t kind);
 
@@ -307,8 +308,8 @@ rt_status rt_tick(rt_ctx *ctx, double *U, const double *L, int64_t tick, double 
  *   dL_dL    [S][G] double, accumulated (+=) dLoss/dL, or NULL.
  * U_pre is read only when UD is NULL.  Scratch (a few state-sized buffers) is
  * allocated by the library on first use.  The step differentiated uses the
- * selected Riemann solver (GLF, or HLL in FP64 contexts) and the Hopkins
- * surfaces: RT_ESTATE with RT_IVANOVA selected, or with HLL in FP32C. */
+ * selected Riemann solver (GLF, or HLL in FP64 contexts) and the selected
+ * effective surfaces; RT_ESTATE with HLL in an FP32C context. */
 rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
                      const void *UD, const void *U_unguarded, const void *lam_next, void *lam,
                      double *dL_dL);

@@ -20,6 +20,10 @@ does: the face states' extreme eigenvalues interpolated bilinearly in (f, mu)
 from the table (which is not differentiated), and the solver's weights.  At
 the kinks (the max/min of the speeds, the clamps of f and mu, the table
 cells) the derivative is that of the branch the forward takes.
+
+With `ivanova` the effective surfaces are the Ivanova ones (Part II
+eq:IvanovaAij), taken pair by pair from the C oracle (static geometry, not
+differentiated).
 """
 from __future__ import annotations
 
@@ -111,9 +115,10 @@ def hll_weights(loL, hiL, loR, hiR, An):
 
 class TorchStep:
     """One RT step on the oracle's geometry (oracle.Geometry, oracle.Sources);
-    `hll` selects the HLL solver with that wave-speed table (else GLF)."""
+    `hll` selects the HLL solver with that wave-speed table (else GLF),
+    `ivanova` the Ivanova surfaces (else Hopkins)."""
 
-    def __init__(self, geo, srcs=None, hll=None):
+    def __init__(self, geo, srcs=None, hll=None, ivanova=False):
         self.hll = None if hll is None else torch.as_tensor(np.asarray(hll, dtype=np.float64))
         f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64)
         n = geo.n
@@ -142,6 +147,11 @@ class TorchStep:
         tl = torch.einsum("eab,eb->ea", B[sk], s) * (Wk * V[sk])[:, None]
         tk = torch.einsum("eab,eb->ea", B[sl], -s) * (Wl * V[sl])[:, None]
         A = V[sk][:, None] * tl - V[sl][:, None] * tk
+        if ivanova:
+            from . import ivanova_sums, surface_ivanova
+            gsum = ivanova_sums(geo)
+            A = f(np.array([surface_ivanova(geo, gsum, int(k), int(l))
+                            for k, l in zip(sk.numpy(), sl.numpy())]).reshape(-1, 3))
         self.sk, self.sl, self.s, self.A = sk, sl, s, A
         self.An = torch.linalg.norm(A, dim=1)
         self.wk = h[sk] / (h[sk] + h[sl])

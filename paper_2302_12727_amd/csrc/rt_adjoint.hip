@@ -63,14 +63,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_guard64(int64_t n, const double 
 // cotangent m = 2 nu pulls back through the two M1 fluxes, the jump term, the
 // weights and, through the speeds, the table lookups (hll_weights_vjp,
 // hll_speeds64_vjp).
-template <int G, int GW, int Q = 1, bool HLL = false>
+//
+// IVA: the Ivanova surfaces (eq:IvanovaAij) in the recomputed pair geometry;
+// they are static, so the pull-back is otherwise the same.
+template <int G, int GW, int Q = 1, bool HLL = false, bool IVA = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(HLL ? kAdjHllWaves : 1)))
 void k_adj_pair64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
     const double *__restrict__ UD, const double *__restrict__ lam2,
     const double *__restrict__ dtp, double c, double box, double *__restrict__ R,
-    const double2 *__restrict__ hll = nullptr) {
+    const double2 *__restrict__ hll = nullptr, const double *__restrict__ ivan = nullptr) {
     static_assert(G % GW == 0, "group slices must tile the groups");
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     constexpr int NS = G / GW, NQ = 4 * GW, PW = 64 / Q, PB = kBlock / Q;
@@ -94,6 +97,12 @@ void k_adj_pair64(
 
     const double *rk = geo + (int64_t)kRec * ic;
     const double dtVk = dt / rk[R_V];
+    double gk[3] = {0.0, 0.0, 0.0};   // IVA: own kernel-gradient sum
+    if (IVA) {
+        gk[0] = ivan[4 * ic];
+        gk[1] = ivan[4 * ic + 1];
+        gk[2] = ivan[4 * ic + 2];
+    }
     double Ui[NQ], Di[NQ * 3], Li[NQ];
 #pragma unroll
     for (int g = 0; g < GW; ++g) {
@@ -135,7 +144,14 @@ void k_adj_pair64(
 #pragma unroll
             for (int q = 0; q < 12; ++q) rl[q] = sb[lane * kStage + q];
             PairGeo pg;
-            pair_geometry64(rk, rl, box, ibox, pg);
+            if (IVA) {
+                stage_rows4(ivan, 4, j, sb, lane);
+                const double gl[3] = {sb[lane * kStage], sb[lane * kStage + 1],
+                                      sb[lane * kStage + 2]};
+                pair_geometry_ivanova64(rk, rl, gk, gl, box, ibox, pg);
+            } else {
+                pair_geometry64(rk, rl, box, ibox, pg);
+            }
             const bool use = valid && pg.An > 0.0;
             const double dtVl = dt / rl[R_V];
 #pragma unroll
@@ -427,14 +443,20 @@ void launch_adjoint64(rt_ctx *ctx, const double *UD, const double *Uung, const d
     k_adj_guard64<G><<<nblk(n * G), kBlock, 0, st>>>(n, Uung, lam_next, lam2, ctx->p.c_red);
     constexpr int GW = (RT_ADJ_GW == 0 || G % RT_ADJ_GW != 0) ? G : RT_ADJ_GW;
     const int64_t np = (n + kBlock / kAQ - 1) / (kBlock / kAQ);
-    if (ctx->solver == RT_HLL)
-        k_adj_pair64<G, GW, kAQ, true><<<(unsigned)xcd_grid(np * (G / GW)), kBlock, 0, st>>>(
-            n, np, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt, ctx->p.c_red,
-            ctx->p.box, R, (const double2 *)ctx->hll_table);
-    else
-        k_adj_pair64<G, GW, kAQ><<<(unsigned)xcd_grid(np * (G / GW)), kBlock, 0, st>>>(
-            n, np, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt, ctx->p.c_red,
-            ctx->p.box, R);
+    const double2 *tab = (const double2 *)ctx->hll_table;
+    const bool iva = ctx->surfaces == RT_IVANOVA;
+#define RT_ADJ_PAIR_LAUNCH(HLL_, IVA_)                                                          \
+    k_adj_pair64<G, GW, kAQ, HLL_, IVA_><<<(unsigned)xcd_grid(np * (G / GW)), kBlock, 0, st>>>( \
+        n, np, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt, ctx->p.c_red,      \
+        ctx->p.box, R, tab, ctx->ivan)
+    if (ctx->solver == RT_HLL) {
+        if (iva) RT_ADJ_PAIR_LAUNCH(true, true);
+        else RT_ADJ_PAIR_LAUNCH(true, false);
+    } else {
+        if (iva) RT_ADJ_PAIR_LAUNCH(false, true);
+        else RT_ADJ_PAIR_LAUNCH(false, false);
+    }
+#undef RT_ADJ_PAIR_LAUNCH
     const int64_t ng = (n + kBlock / kAGQ - 1) / (kBlock / kAGQ);
     k_adj_grad64<G, kAGQ><<<(unsigned)xcd_grid(ng), kBlock, 0, st>>>(
         n, ng, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, R, lam, ctx->p.box);

@@ -138,3 +138,36 @@ def test_hll_autograd_matches_finite_differences(small_hll):
             return loss_np_hll(geo, srcs, Ux, w.L, w.steps, probes, Et, tab)
         ok, fds = fd_matches(f, w.U0[i, grp, m], gU[i, grp, m], np.abs(w.U0[i, grp]).max())
         assert ok, (i, grp, m, gU[i, grp, m], fds)
+
+
+# ---------------------------------------------------------------------------
+# The Ivanova surfaces (Part II eq:IvanovaAij): forward against the C
+# oracle's transport with those surfaces, autograd against its central
+# differences in the luminosities.
+def test_ivanova_forward_and_gradient():
+    w = workloads.lattice_workload(9, 2, 3, 3, seed=341, name="adj-small-iva")
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs)
+    ts = TorchStep(geo, srcs, ivanova=True)
+    ref, _ = oracle.run(geo, srcs, w.U0, w.L, 3, ivanova=True)
+    got = ts.run(torch.from_numpy(w.U0), torch.from_numpy(w.L), geo.dt, 3).numpy()
+    scale = np.abs(ref).max(axis=-1, keepdims=True)
+    assert (np.abs(got - ref) / scale).max() < 1e-12
+    hop, _ = oracle.run(geo, srcs, w.U0, w.L, 3)
+    assert (np.abs(got - hop) / scale).max() > 1e-6
+    g = workloads.rng(342)
+    probes = np.sort(g.choice(w.n, 48, replace=False))
+    Et = g.lognormal(size=(48, w.groups))
+    L = torch.from_numpy(w.L.copy()).requires_grad_(True)
+    U = ts.run(torch.from_numpy(w.U0), L, geo.dt, 3)
+    (gL,) = torch.autograd.grad(((U[probes, :, 0] - torch.from_numpy(Et)) ** 2).sum(), (L,))
+    gL = gL.numpy()
+    for s in range(w.L.shape[0]):
+        for grp in range(w.groups):
+            def f(v):
+                Lx = w.L.copy()
+                Lx[s, grp] = v
+                U, _ = oracle.run(geo, srcs, w.U0, Lx, 3, ivanova=True)
+                return float(((U[probes, :, 0] - Et) ** 2).sum())
+            ok, fds = fd_matches(f, w.L[s, grp], gL[s, grp], w.L[s, grp])
+            assert ok, (s, grp, gL[s, grp], fds)

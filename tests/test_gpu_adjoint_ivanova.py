@@ -1,0 +1,132 @@
+"""Adjoint of the transport step with the Ivanova surfaces (Part II
+eq:IvanovaAij) on the GPU, against the differentiable torch reference with
+the same surfaces (oracle/torch_ref.py, whose forward is pinned to the C
+oracle's Ivanova transport and whose gradient to its central differences)
+and against central differences of the GPU forward.  Tolerances as for the
+Hopkins adjoint: 1e-9 relative against the reference, 1e-6 against central
+differences.  The surfaces are static, so only the recomputed pair geometry
+changes; the GLF and HLL solvers are both covered.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from oracle.torch_ref import TorchStep
+from tests.gpu_util import dev, log, unsort
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2302_12727_amd import RT  # noqa: E402
+from paper_2302_12727_amd.rollout import rollout  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def case():
+    w = workloads.lattice_workload(10, 2, 3, 6, seed=575, name="adj-iva")
+    log(f"Ivanova adjoint case lattice10 G=2 S=3 n={w.n}")
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs)
+    rt = RT(w.n, w.groups)
+    perm, *_ = rt.rt_build_cells(dev(w.x), dev(geo.h))
+    rt.rt_set_sources(dev(w.xs))
+    rt.rt_set_surfaces("ivanova")
+    rt.rt_sync()
+    p = perm.cpu().numpy()
+    g = workloads.rng(576)
+    probes = np.sort(g.choice(w.n, 96, replace=False))
+    Et = g.lognormal(size=(96, w.groups))
+    return w, geo, srcs, rt, p, probes, Et
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("solver", ["glf", "hll"])
+def test_single_step_vjp(case, solver):
+    w, geo, srcs, rt, p, _, _ = case
+    ts = TorchStep(geo, srcs, hll=oracle.hll_table() if solver == "hll" else None, ivanova=True)
+    rt.rt_set_riemann(solver)
+    g = workloads.rng(29)
+    lam_next = g.normal(size=w.U0.shape)
+    U = torch.from_numpy(w.U0.copy()).requires_grad_(True)
+    L = torch.from_numpy(w.L.copy()).requires_grad_(True)
+    gU, gL = torch.autograd.grad(ts.step(U, L, geo.dt), (U, L),
+                                 grad_outputs=torch.from_numpy(lam_next))
+    dLdL = torch.zeros(w.L.shape, dtype=torch.float64, device="cuda")
+    lam = rt.rt_adjoint(dev(w.U0[p]), dev(w.L), dev(lam_next[p]), dL_dL=dLdL)
+    rt.rt_set_riemann("glf")
+    got = unsort(lam.cpu().numpy(), p)
+    e1, e2 = rel(got, gU.numpy()), rel(dLdL.cpu().numpy(), gL.numpy())
+    log(f"Ivanova {solver} single-step VJP: dU rel err {e1:.2e}, dL rel err {e2:.2e}")
+    assert e1 < 1e-9 and e2 < 1e-9
+    # the surfaces matter: the Hopkins reference differs
+    hop = TorchStep(geo, srcs, hll=oracle.hll_table() if solver == "hll" else None)
+    U2 = torch.from_numpy(w.U0.copy()).requires_grad_(True)
+    (gU_h,) = torch.autograd.grad(hop.step(U2, torch.from_numpy(w.L), geo.dt), (U2,),
+                                  grad_outputs=torch.from_numpy(lam_next))
+    assert rel(got, gU_h.numpy()) > 1e-4
+
+
+def test_rollout_gradient_vs_reference(case):
+    w, geo, srcs, rt, p, probes, Et = case
+    ts = TorchStep(geo, srcs, ivanova=True)
+    steps = w.steps
+    U0 = torch.from_numpy(w.U0.copy()).requires_grad_(True)
+    L = torch.from_numpy(w.L.copy()).requires_grad_(True)
+    U = ts.run(U0, L, geo.dt, steps)
+    loss = ((U[probes, :, 0] - torch.from_numpy(Et)) ** 2).sum()
+    gU_ref, gL_ref = torch.autograd.grad(loss, (U0, L))
+    inv = np.empty_like(p)
+    inv[p] = np.arange(w.n)
+    pr = torch.as_tensor(inv[probes], device="cuda")
+    U0d = dev(w.U0[p]).requires_grad_(True)
+    Ld = dev(w.L).requires_grad_(True)
+    Ud = rollout(rt, Ld, U0d, steps, ckpt_every=2)
+    lossd = ((Ud[pr, :, 0] - dev(Et)) ** 2).sum()
+    lossd.backward()
+    assert float(lossd.detach()) == pytest.approx(float(loss), rel=1e-12)
+    gU = unsort(U0d.grad.cpu().numpy(), p)
+    e1, e2 = rel(gU, gU_ref.numpy()), rel(Ld.grad.cpu().numpy(), gL_ref.numpy())
+    log(f"Ivanova {steps}-step rollout (checkpoint every 2): dU0 rel err {e1:.2e}, "
+        f"dL rel err {e2:.2e}")
+    assert e1 < 1e-9 and e2 < 1e-9
+
+
+def test_rollout_gradient_vs_finite_differences(case):
+    w, geo, srcs, rt, p, probes, Et = case
+    steps = w.steps
+    inv = np.empty_like(p)
+    inv[p] = np.arange(w.n)
+    pr = torch.as_tensor(inv[probes], device="cuda")
+    Etd = dev(Et)
+    U0d = dev(w.U0[p])
+
+    def loss_of(L):
+        with torch.no_grad():
+            U = rollout(rt, L, U0d, steps, ckpt_every=3)
+            return float(((U[pr, :, 0] - Etd) ** 2).sum())
+
+    Ld = dev(w.L).requires_grad_(True)
+    U = rollout(rt, Ld, U0d.clone().requires_grad_(True), steps, ckpt_every=3)
+    ((U[pr, :, 0] - Etd) ** 2).sum().backward()
+    gL = Ld.grad.cpu().numpy()
+    worst = 0.0
+    for s in range(w.L.shape[0]):
+        for grp in range(w.groups):
+            best = np.inf
+            for r in (1e-4, 1e-5, 1e-6):
+                eps = r * w.L[s, grp]
+                Lp, Lm = w.L.copy(), w.L.copy()
+                Lp[s, grp] += eps
+                Lm[s, grp] -= eps
+                fd = (loss_of(dev(Lp)) - loss_of(dev(Lm))) / (2 * eps)
+                best = min(best, abs(fd - gL[s, grp]) / abs(fd))
+            worst = max(worst, best)
+            assert best < 1e-6, (s, grp, gL[s, grp])
+    log(f"Ivanova dLoss/dL vs central differences: worst rel err {worst:.2e}")

@@ -5,7 +5,8 @@ state (FP64), as for the Hopkins surfaces.
 Cases: the 16^3 lattice (guards firing), 3 groups with sources and the HLL
 solver, ragged sizes, a clustered Plummer set, photon conservation without
 guards, a rebuild at moved positions (the kernel-gradient sums are
-recomputed), the switch back to Hopkins, and the refusals.
+recomputed), the switch back to Hopkins, and the refusals.  The adjoint with
+these surfaces: tests/test_gpu_adjoint_ivanova.py.
 """
 import numpy as np
 import pytest
@@ -146,8 +147,6 @@ def test_refusals():
     UD = rt.rt_gradient(U)
     with pytest.raises(RTError, match="RT_ESTATE"):
         rt.rt_tick(U, None, 0, UD, torch.zeros_like(U))
-    with pytest.raises(RTError, match="RT_ESTATE"):
-        rt.rt_adjoint(U, None, torch.ones_like(U))
     rt32 = RT(w.n, w.groups, precision="fp32c")
     rt32.rt_build_cells(dev(w.x))
     with pytest.raises(RTError, match="RT_EINVAL"):
