@@ -149,7 +149,7 @@ def lib():
         L.orc_transport_binned.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d, _d, _d,
                                            _d, _i64, _i64, ctypes.c_double, ctypes.c_double,
                                            _i32, ctypes.c_int64, _d, _d, _d, _d, _i64, _d,
-                                           _d, ctypes.c_int32, ctypes.c_int32]
+                                           _d, ctypes.c_int32, ctypes.c_int32, _d]
         _lib = L
     return _lib
 
@@ -643,12 +643,13 @@ def active(bins: np.ndarray, tick: int) -> np.ndarray:
 
 def run_binned(geom: Geometry, srcs: Optional[Sources], U0: np.ndarray, L, ticks: int,
                bins: np.ndarray, t0: int = 0, dU=None, acc=None,
-               hll: Optional[np.ndarray] = None):
+               hll: Optional[np.ndarray] = None, ivanova: bool = False):
     """`ticks` ticks of the individual-time-step scheme from tick t0.  Every
     particle starts with the gradient of U0 (unless dU is given); in tick t the
     particles that end a step inject (with their own dt), recompute their
     gradient, and apply their flux sums, while every pair whose smaller bin ends
-    a step exchanges dt_kl |A| Phi (GLF, or HLL with the table `hll`).
+    a step exchanges dt_kl |A| Phi (GLF, or HLL with the table `hll`; the
+    Hopkins surfaces, or the Ivanova ones with `ivanova`).
     Returns (U, info) with info["acc"] (the pending flux sums) and info["dU"]
     (the stored gradients)."""
     U = _f64(U0).copy()
@@ -660,6 +661,7 @@ def run_binned(geom: Geometry, srcs: Optional[Sources], U0: np.ndarray, L, ticks
     ledger = np.zeros(G)
     Lm = _f64(L) if (srcs is not None and srcs.src.size) else None
     tab = None if hll is None else _f64(hll)
+    gsum = ivanova_sums(geom) if ivanova else None
     for t in range(t0, t0 + ticks):
         act = active(bins, t)
         if Lm is not None:
@@ -675,7 +677,8 @@ def run_binned(geom: Geometry, srcs: Optional[Sources], U0: np.ndarray, L, ticks
                                    _p(U), _p(dU), _p(acc), _p(out), _p(counts, _i64),
                                    _p(ledger), None if tab is None else _p(tab),
                                    0 if tab is None else tab.shape[0],
-                                   0 if tab is None else tab.shape[1])
+                                   0 if tab is None else tab.shape[1],
+                                   None if gsum is None else _p(gsum))
         U = out
     return U, {"acc": acc, "dU": dU, "counts": counts, "ledger": ledger}
 

@@ -765,14 +765,15 @@ void orc_inject_binned(int64_t nent, int32_t G, const int64_t *src, const int64_
  * flux sums acc of both particles (each particle sums its own side).  A
  * particle that ends a step applies U_k - acc_k / V_k, is guarded as in
  * orc_transport, and clears acc_k; the others keep accumulating.  Uout gets
- * the new states of the active particles and U of the others.              */
+ * the new states of the active particles and U of the others.  gsum (from
+ * orc_ivanova_sums) selects the Ivanova surfaces, NULL the Hopkins ones.    */
 void orc_transport_binned(int64_t n, int32_t G, const double *x, const double *h,
                           const double *H, const double *V, const double *B,
                           const double *box, const int64_t *sptr, const int64_t *sidx,
                           double c, double dtmin, const int32_t *bin, int64_t t,
                           const double *U, const double *dU, double *acc, double *Uout,
                           int64_t *counts, double *ledger, const double *tab, int32_t nf,
-                          int32_t nmu)
+                          int32_t nmu, const double *gsum)
 {
     const int64_t nq = 4 * (int64_t)G;
     int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
@@ -786,8 +787,12 @@ void orc_transport_binned(int64_t n, int32_t G, const double *x, const double *h
             if (!orc_active(t, bmin)) continue;
             double dtkl = dtmin * ldexp(1.0, bmin);
             double A[3], s[3];
-            orc_surface(x + 3 * k, x + 3 * l, H[k], H[l], V[k], V[l], B + 9 * k,
-                        B + 9 * l, box, A);
+            if (gsum)
+                orc_surface_ivanova(x + 3 * k, x + 3 * l, H[k], H[l], V[k], V[l],
+                                    gsum + 3 * k, gsum + 3 * l, box, A);
+            else
+                orc_surface(x + 3 * k, x + 3 * l, H[k], H[l], V[k], V[l], B + 9 * k,
+                            B + 9 * l, box, A);
             double An = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
             if (!(An > 0.0)) continue;
             double nh[3] = {A[0] / An, A[1] / An, A[2] / An};

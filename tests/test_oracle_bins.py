@@ -100,3 +100,40 @@ def test_budget_with_pending_sums_every_tick(clustered):
         assert np.abs(lhs / rhs - 1).max() < 1e-12, t
         if (t + 1) % (1 << top) == 0:
             assert not acc.any(), t
+
+
+# ---------------------------------------------------------------------------
+# The same reductions with the Ivanova surfaces (Part II eq:IvanovaAij), and
+# the budget over a cycle of several bins (the surfaces are antisymmetric,
+# so the pending sums still close it).
+def test_ivanova_bins_zero_and_one(clustered):
+    w, geo, srcs = clustered
+    ref, _ = oracle.run(geo, srcs, w.U0, w.L, 3, ivanova=True)
+    got, info = oracle.run_binned(geo, srcs, w.U0, w.L, 3, np.zeros(geo.n, np.int32),
+                                  ivanova=True)
+    assert state_err(got, ref) < 1e-12
+    assert not info["acc"].any()
+    ref2, _ = oracle.step(geo, srcs, w.U0, w.L, dt=2.0 * geo.dt, ivanova=True)
+    got2, _ = oracle.run_binned(geo, srcs, w.U0, w.L, 2, np.ones(geo.n, np.int32), ivanova=True)
+    assert state_err(got2, ref2) < 1e-12
+    hop, _ = oracle.run_binned(geo, srcs, w.U0, w.L, 3, np.zeros(geo.n, np.int32))
+    assert state_err(got, hop) > 1e-6
+
+
+def test_ivanova_budget_with_pending_sums(clustered):
+    w, geo, srcs = clustered
+    bins = oracle.time_bins(geo, 2)
+    top = int(bins.max())
+    U = w.U0.copy()
+    Q0 = oracle.photon_total(geo, U)
+    dU, acc = None, None
+    ledger = np.zeros(w.groups)
+    for t in range(1 << top):
+        U, info = oracle.run_binned(geo, srcs, U, w.L, 1, bins, t0=t, dU=dU, acc=acc,
+                                    ivanova=True)
+        dU, acc = info["dU"], info["acc"]
+        ledger += info["ledger"]
+        lhs = oracle.photon_total(geo, U) - acc[:, :, 0].sum(axis=0)
+        rhs = Q0 + (t + 1) * geo.dt * w.L.sum(axis=0) + ledger
+        assert np.abs(lhs / rhs - 1).max() < 1e-12, t
+    assert not acc.any()
