@@ -181,9 +181,9 @@ rt_status rt_set_riemann(rt_ctx *ctx, int32_t solver);
  *               gradients).
  * FP64 contexts after rt_build_cells (RT_ESTATE before, RT_EINVAL on FP32C);
  * selecting RT_IVANOVA computes g (n x 4 doubles, kept and recomputed by
- * later builds).  rt_tick returns RT_ESTATE while RT_IVANOVA is selected;
- * rt_adjoint differentiates the step with either surfaces (they are static).
- * The gradient step (eq:gradient) is the same for both. */
+ * later builds).  rt_transport, rt_tick and rt_adjoint take either surfaces
+ * (rt_adjoint differentiates the step with them held static).  The gradient
+ * step (eq:gradient) is the same for both. */
 typedef enum { RT_HOPKINS = 0, RT_IVANOVA = 1 } rt_surfaces;
 rt_status rt_set_surfaces(rt_ctx *ctx, int32_t kind);
 
@@ -273,7 +273,8 @@ rt_status rt_time_bins(rt_ctx *ctx, int32_t max_bin, int32_t *bins, int64_t *cyc
  * their own dt_i (sources set) and recompute their gradient record from the
  * current states; every pair whose smaller bin ends a step exchanges
  * dt 2^min(b_k, b_l) |A| Phi_kl (the flux of rt_transport, GLF or HLL as
- * selected by rt_set_riemann) into the flux
+ * selected by rt_set_riemann, through the surfaces selected by
+ * rt_set_surfaces) into the flux
  * sums of both particles; the particles that end a step apply
  * U - (flux sum) / V, guard the result as rt_transport does, and clear their
  * sums.

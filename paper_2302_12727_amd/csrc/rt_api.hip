@@ -283,8 +283,6 @@ rt_status rt_tick(rt_ctx *ctx, double *U, const double *L, int64_t tick, double 
         return rt_fail(ctx, RT_EINVAL, "time bins are implemented for FP64 contexts only");
     if (!U || !UD || !acc) return rt_fail(ctx, RT_EINVAL, "U, UD and acc are required");
     if (tick < 0) return rt_fail(ctx, RT_EINVAL, "tick must be >= 0");
-    if (ctx->surfaces != RT_HOPKINS)
-        return rt_fail(ctx, RT_ESTATE, "individual time steps use the Hopkins surfaces");
     if (ctx->S > 0 && !L) return rt_fail(ctx, RT_EINVAL, "L is required when sources are set");
     size_t nu = sizeof(double) * 4 * ctx->p.groups * ctx->p.n;
     if (overlap(UD, 4 * nu, U, nu) || overlap(UD, 4 * nu, acc, nu) || overlap(U, nu, acc, nu))

@@ -170,7 +170,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     double *__restrict__ accm = nullptr, const double2 *__restrict__ hll = nullptr,
     const double *__restrict__ ivan = nullptr) {
     static_assert(G % GW == 0, "group slices must tile the groups");
-    static_assert(!(IVA && BIN), "the binned tick uses the Hopkins surfaces");
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     constexpr int NS = G / GW, NQ = 4 * G;
     constexpr int PW = 64 / Q, PB = kBlock / Q;   // particles per wave, per block
@@ -291,6 +290,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             double rl[12];
 #pragma unroll
             for (int q = 0; q < 12; ++q) rl[q] = sb[lane * kStage + q];
+            // the neighbour's time bin (slot 12 of its record), read before the
+            // Ivanova staging reuses the buffer
+            const int32_t bl = BIN ? (int32_t)sb[lane * kStage + 12] : 0;
             PairGeo pg;
             if (IVA) {
                 stage_rows4(ivan, 4, j, sb, lane);
@@ -303,7 +305,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             bool use = valid && pg.An > 0.0;
             double wkl = 1.0;                   // time integration of this exchange
             if (BIN) {
-                const int32_t bl = (int32_t)sb[lane * kStage + 12];
                 const int32_t bmin = bk < bl ? bk : bl;
                 use = use && (t1 & ((int64_t(1) << bmin) - 1)) == 0;
                 wkl = ldexp(dtp[0], bmin);
@@ -603,17 +604,22 @@ void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, d
         n, ng, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box, tick);
     constexpr int GW = transport_slice(G), HW = hll_slice(G);
     const int64_t nt = transport_rows(n);
-    if (ctx->solver == RT_HLL)
-        k_transport64<G, HW, true, true, false, kQ><<<(unsigned)xcd_grid(nt * (G / HW)), kBlock,
-                                                      0, ctx->stream>>>(
-            n, nt, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
-            ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, tick, accm,
-            (const double2 *)ctx->hll_table);
-    else
-        k_transport64<G, GW, true, false, false, kQ, kOwnL, kPipe><<<(unsigned)xcd_grid(nt * (G / GW)), kBlock,
-                                                       0, ctx->stream>>>(
-            n, nt, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,
-            ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, tick, accm);
+    const double2 *tab = (const double2 *)ctx->hll_table;
+    const bool iva = ctx->surfaces == RT_IVANOVA;
+#define RT_TICK_LAUNCH(W, HLL_, IVA_)                                                          \
+    k_transport64<G, W, true, HLL_, IVA_, kQ, kOwnL && !HLL_, kPipe && !HLL_>                  \
+        <<<(unsigned)xcd_grid(nt * (G / W)), kBlock, 0, ctx->stream>>>(                        \
+            n, nt, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,       \
+            ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, tick, accm, tab, \
+            ctx->ivan)
+    if (ctx->solver == RT_HLL) {
+        if (iva) RT_TICK_LAUNCH(HW, true, true);
+        else RT_TICK_LAUNCH(HW, true, false);
+    } else {
+        if (iva) RT_TICK_LAUNCH(GW, false, true);
+        else RT_TICK_LAUNCH(GW, false, false);
+    }
+#undef RT_TICK_LAUNCH
 }
 
 #define RT_DISPATCH_G(G_, FN, ...)                                  \

@@ -7,6 +7,8 @@ factor-4 limiter).
 - two full cycles of a clustered set with sources: states and pending flux
   sums against the oracle (1e-12 per state; sums against the state scale);
 - the photon budget including the pending sums closes every tick (1e-12);
+- the Ivanova surfaces (GLF and HLL): two cycles and a mid-cycle state with
+  pending sums against the oracle's binned scheme with those surfaces;
 - FP32C contexts are refused.
 """
 import numpy as np
@@ -124,6 +126,33 @@ def test_budget_with_pending_sums_every_tick(case):
         worst = max(worst, float(np.abs(lhs / rhs - 1).max()))
     log(f"budget with pending sums over {2 * cycle} ticks: worst {worst:.2e}")
     assert worst < 1e-12
+
+
+@pytest.mark.parametrize("solver", ["glf", "hll"])
+def test_ivanova_against_oracle(case, solver):
+    """Individual time bins with the Ivanova surfaces (Part II eq:IvanovaAij):
+    two cycles, then a mid-cycle state with pending sums."""
+    w, geo, srcs, rt, p = case
+    tab = oracle.hll_table() if solver == "hll" else None
+    rt.rt_set_surfaces("ivanova")
+    rt.rt_set_riemann(solver)
+    try:
+        bins, cycle = rt.rt_time_bins(MAX_BIN)
+        ob = oracle.time_bins(geo, MAX_BIN)
+        for ticks in (2 * cycle, cycle + cycle // 2 + 1):
+            U, acc, Q, _ = gpu_ticks(rt, w, p, ticks)
+            ref, info = oracle.run_binned(geo, srcs, w.U0, w.L, ticks, ob, hll=tab, ivanova=True)
+            err = state_err(unsort(U.cpu().numpy(), p), ref)
+            scale = np.abs(ref).max() * geo.V.max()
+            aerr = float(np.abs(unsort(acc.cpu().numpy(), p) - info["acc"]).max() / scale)
+            log(f"Ivanova {solver} {ticks} ticks: max state err {err:.2e}, pending sums {aerr:.2e}")
+            assert err < 1e-12 and aerr < 1e-12
+            assert np.allclose(Q.cpu().numpy(), oracle.photon_total(geo, ref), rtol=1e-12, atol=0)
+        hop, _ = oracle.run_binned(geo, srcs, w.U0, w.L, ticks, ob, hll=tab)
+        assert state_err(unsort(U.cpu().numpy(), p), hop) > 1e-6
+    finally:
+        rt.rt_set_surfaces("hopkins")
+        rt.rt_set_riemann("glf")
 
 
 def test_fp32c_context_refused():

@@ -6,7 +6,8 @@ Cases: the 16^3 lattice (guards firing), 3 groups with sources and the HLL
 solver, ragged sizes, a clustered Plummer set, photon conservation without
 guards, a rebuild at moved positions (the kernel-gradient sums are
 recomputed), the switch back to Hopkins, and the refusals.  The adjoint with
-these surfaces: tests/test_gpu_adjoint_ivanova.py.
+these surfaces: tests/test_gpu_adjoint_ivanova.py; the individual time bins
+with them: tests/test_gpu_bins.py.
 """
 import numpy as np
 import pytest
@@ -142,11 +143,6 @@ def test_refusals():
     fresh = RT(w.n, w.groups)
     with pytest.raises(RTError, match="RT_ESTATE"):
         fresh.rt_set_surfaces("ivanova")                     # before the build
-    rt, p = gpu_case(w)
-    U = dev(w.U0[p])
-    UD = rt.rt_gradient(U)
-    with pytest.raises(RTError, match="RT_ESTATE"):
-        rt.rt_tick(U, None, 0, UD, torch.zeros_like(U))
     rt32 = RT(w.n, w.groups, precision="fp32c")
     rt32.rt_build_cells(dev(w.x))
     with pytest.raises(RTError, match="RT_EINVAL"):
