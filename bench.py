@@ -504,6 +504,12 @@ def main():
                               "transport_time_vs_hopkins": fi["transport_ms"] / fw_transport_ms,
                               "photon_budget_residual": fi["photon_budget_residual"]}
             del fi
+            fi = run_forward(w, "fp32c", args.steps, args.warmup, dev, surfaces="ivanova")
+            out["ivanova"]["fp32c"] = {"value": fi["pairs"] * args.steps / fi["elapsed"],
+                                       "ms_per_step": fi["elapsed"] / args.steps * 1e3,
+                                       "kernel_ms": {"transport": fi["transport_ms"],
+                                                     "gradient": fi["gradient_ms"]}}
+            del fi
         out["absorb"] = absorb_leg(w, dev)
         torch.cuda.empty_cache()
         wa = workloads.config(3)

@@ -179,11 +179,13 @@ rt_status rt_set_riemann(rt_ctx *ctx, int32_t solver);
  *               g_k = sum_m grad W_m(x_k) over the gather neighbours, the kernel
  *               taken with H_k (the thesis' appendix on partition-of-unity
  *               gradients).
- * FP64 contexts after rt_build_cells (RT_ESTATE before, RT_EINVAL on FP32C);
- * selecting RT_IVANOVA computes g (n x 4 doubles, kept and recomputed by
- * later builds).  rt_transport, rt_tick and rt_adjoint take either surfaces
- * (rt_adjoint differentiates the step with them held static).  The gradient
- * step (eq:gradient) is the same for both. */
+ * After rt_build_cells (RT_ESTATE before), FP64 and FP32C contexts (the
+ * FP32C kernel forms A in FP32 from g rounded to FP32); selecting RT_IVANOVA
+ * computes g (n x 4 doubles, kept and recomputed by
+ * later builds).  rt_transport, rt_tick and the FP64 rt_adjoint take either
+ * surfaces (rt_adjoint differentiates the step with them held static; the
+ * FP32C rt_adjoint returns RT_ESTATE with RT_IVANOVA).  The gradient step
+ * (eq:gradient) is the same for both. */
 typedef enum { RT_HOPKINS = 0, RT_IVANOVA = 1 } rt_surfaces;
 rt_status rt_set_surfaces(rt_ctx *ctx, int32_t kind);
 
@@ -310,7 +312,7 @@ rt_status rt_tick(rt_ctx *ctx, double *U, const double *L, int64_t tick, double 
  * U_pre is read only when UD is NULL.  Scratch (a few state-sized buffers) is
  * allocated by the library on first use.  The step differentiated uses the
  * selected Riemann solver (GLF, or HLL in FP64 contexts) and the selected
- * effective surfaces; RT_ESTATE with HLL in an FP32C context. */
+ * effective surfaces; RT_ESTATE with HLL or RT_IVANOVA in an FP32C context. */
 rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
                      const void *UD, const void *U_unguarded, const void *lam_next, void *lam,
                      double *dL_dL);

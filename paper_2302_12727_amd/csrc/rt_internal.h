@@ -140,6 +140,11 @@ __device__ __forceinline__ double kern_dw(double q) {
     double b = fmax(0.5 - q, 0.0);
     return -3.0 * a * a + 12.0 * (b * b);
 }
+__device__ __forceinline__ float kern_dwf(float q) {
+    float a = fmaxf(1.0f - q, 0.0f);
+    float b = fmaxf(0.5f - q, 0.0f);
+    return -3.0f * a * a + 12.0f * (b * b);
+}
 
 // 1/x for normal x > 0: the hardware estimate (v_rcp_f64, about 2^-23
 // relative) refined by two Newton-Raphson steps r <- r + r (1 - x r), which

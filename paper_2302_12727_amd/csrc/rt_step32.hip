@@ -91,14 +91,19 @@ __global__ __launch_bounds__(kBlock) void k_gradient32(
 // Q lanes share a particle, each taking every Q-th neighbour slot (see the
 // FP64 transport); the per-lane compensated sums are combined in FP64 by a
 // fixed butterfly.
-template <int G, bool HLL = false, int Q = 1>
+//
+// IVA: the Ivanova surfaces (eq:IvanovaAij) in FP32 from the records' V and
+// 1/H and the kernel-gradient sums ivan (FP64, rounded to FP32 on load), the
+// separation from the FP64 positions as for the Hopkins surfaces.
+template <int G, bool HLL = false, int Q = 1, bool IVA = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ? 3 : 1))) void k_transport32(
     int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ geo,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_nbr, const float *__restrict__ UD,
     const double *__restrict__ dtp, double c, double box, float *__restrict__ Uout,
     double *__restrict__ partials, unsigned long long *__restrict__ counts,
-    float *__restrict__ Uung, const float2 *__restrict__ hll = nullptr) {
+    float *__restrict__ Uung, const float2 *__restrict__ hll = nullptr,
+    const double *__restrict__ ivan = nullptr) {
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     constexpr int NQ = 4 * G, PW = 64 / Q, PB = kBlock / Q;
     __shared__ float stage[kBlock / 64][64 * kStage32];
@@ -124,6 +129,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
     const double *xk = reinterpret_cast<const double *>(rk);
     const double pkx = xk[0], pky = xk[1], pkz = xk[2];
     const float iHk = rk[F_IH], hk = rk[F_H];
+    float gk[3] = {0.0f, 0.0f, 0.0f};   // IVA: own kernel-gradient sum
+    if (IVA) {
+        gk[0] = (float)ivan[4 * ic];
+        gk[1] = (float)ivan[4 * ic + 1];
+        gk[2] = (float)ivan[4 * ic + 2];
+    }
     float Bk[6];
 #pragma unroll
     for (int a = 0; a < 6; ++a) Bk[a] = rk[F_B + a];
@@ -181,17 +192,35 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
             const float sy = (float)min_image(xl[1] - pky, box, ibox);
             const float sz = (float)min_image(xl[2] - pkz, box, ibox);
             const float r = sqrt32(sx * sx + sy * sy + sz * sz);
-            const float wk = kern_wf(r * iHk);
-            const float wl = kern_wf(r * rl[F_IH]);
-            const float m00 = wk * Bk[0] + wl * rl[F_B + 0];
-            const float m01 = wk * Bk[1] + wl * rl[F_B + 1];
-            const float m02 = wk * Bk[2] + wl * rl[F_B + 2];
-            const float m11 = wk * Bk[3] + wl * rl[F_B + 3];
-            const float m12 = wk * Bk[4] + wl * rl[F_B + 4];
-            const float m22 = wk * Bk[5] + wl * rl[F_B + 5];
-            const float Ax = m00 * sx + m01 * sy + m02 * sz;
-            const float Ay = m01 * sx + m11 * sy + m12 * sz;
-            const float Az = m02 * sx + m12 * sy + m22 * sz;
+            float Ax, Ay, Az;
+            if (IVA) {
+                // A_kl = -(V_k^2 sigma w'_k/H_k^4 + V_l^2 sigma w'_l/H_l^4) s/r
+                //        - V_k^3 sigma w_k/H_k^3 g_k + V_l^3 sigma w_l/H_l^3 g_l
+                const double *gd = ivan + 4 * (int64_t)j;
+                const float glx = (float)gd[0], gly = (float)gd[1], glz = (float)gd[2];
+                const float iHl = rl[F_IH], Vk = rk[F_V], Vl = rl[F_V];
+                const float qk = r * iHk, ql = r * iHl;
+                const float sk = (float)kSigma3 * Vk * Vk * iHk * iHk * iHk;
+                const float sl = (float)kSigma3 * Vl * Vl * iHl * iHl * iHl;
+                const float ir = r > 0.0f ? rcp32(r) : 0.0f;
+                const float a = -(sk * iHk * kern_dwf(qk) + sl * iHl * kern_dwf(ql)) * ir;
+                const float bk = sk * Vk * kern_wf(qk), bl = sl * Vl * kern_wf(ql);
+                Ax = a * sx - bk * gk[0] + bl * glx;
+                Ay = a * sy - bk * gk[1] + bl * gly;
+                Az = a * sz - bk * gk[2] + bl * glz;
+            } else {
+                const float wk = kern_wf(r * iHk);
+                const float wl = kern_wf(r * rl[F_IH]);
+                const float m00 = wk * Bk[0] + wl * rl[F_B + 0];
+                const float m01 = wk * Bk[1] + wl * rl[F_B + 1];
+                const float m02 = wk * Bk[2] + wl * rl[F_B + 2];
+                const float m11 = wk * Bk[3] + wl * rl[F_B + 3];
+                const float m12 = wk * Bk[4] + wl * rl[F_B + 4];
+                const float m22 = wk * Bk[5] + wl * rl[F_B + 5];
+                Ax = m00 * sx + m01 * sy + m02 * sz;
+                Ay = m01 * sx + m11 * sy + m12 * sz;
+                Az = m02 * sx + m12 * sy + m22 * sz;
+            }
             const float An = sqrt32(Ax * Ax + Ay * Ay + Az * Az);
             const float hl = rl[F_H];
             const float ih = rcp32(hk + hl);
@@ -352,15 +381,21 @@ template <int G>
 void launch_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *Uout,
                         double *partials, int64_t *counts, float *Uung) {
     const int64_t n = ctx->p.n, nb = rt_transport32_rows(n);
-    if (ctx->solver == RT_HLL)
-        k_transport32<G, true, kQ32><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
-            n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt,
-            ctx->p.c_red, ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung,
-            (const float2 *)ctx->hll_table32);
-    else
-        k_transport32<G, false, kQ32><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
-            n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt,
-            ctx->p.c_red, ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung);
+    const float2 *tab = (const float2 *)ctx->hll_table32;
+    const bool iva = ctx->surfaces == RT_IVANOVA;
+#define RT_TRANSPORT32_LAUNCH(HLL_, IVA_)                                                     \
+    k_transport32<G, HLL_, kQ32, IVA_><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(   \
+        n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt,            \
+        ctx->p.c_red, ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, tab,    \
+        ctx->ivan)
+    if (ctx->solver == RT_HLL) {
+        if (iva) RT_TRANSPORT32_LAUNCH(true, true);
+        else RT_TRANSPORT32_LAUNCH(true, false);
+    } else {
+        if (iva) RT_TRANSPORT32_LAUNCH(false, true);
+        else RT_TRANSPORT32_LAUNCH(false, false);
+    }
+#undef RT_TRANSPORT32_LAUNCH
 }
 
 }  // namespace

@@ -7,7 +7,8 @@ solver, ragged sizes, a clustered Plummer set, photon conservation without
 guards, a rebuild at moved positions (the kernel-gradient sums are
 recomputed), the switch back to Hopkins, and the refusals.  The adjoint with
 these surfaces: tests/test_gpu_adjoint_ivanova.py; the individual time bins
-with them: tests/test_gpu_bins.py.
+with them: tests/test_gpu_bins.py.  The FP32C kernel with them: against the
+FP64 oracle at the FP32C bar (1e-5 of each neighbourhood's scale).
 """
 import numpy as np
 import pytest
@@ -15,7 +16,7 @@ import torch
 
 import oracle
 import workloads
-from tests.gpu_util import dev, log, state_err, unsort
+from tests.gpu_util import dev, local_err, log, state_err, unsort
 
 pytestmark = pytest.mark.gpu
 
@@ -138,6 +139,43 @@ def test_switch_back_to_hopkins():
     assert state_err(got, ref) < TOL
 
 
+@pytest.mark.parametrize("case,solver", [("lattice16", "glf"), ("plummer", "glf"),
+                                         ("lattice16", "hll")])
+def test_fp32c(case, solver):
+    """The compensated-FP32 kernel with the Ivanova surfaces against the FP64
+    oracle's steps with them, at the FP32C bar (1e-5 of each neighbourhood's
+    scale), and the photon total at 1e-6."""
+    if case == "lattice16":
+        w, steps = workloads.config(0), 10
+    else:
+        w, steps = workloads.config(2, scale=(1 << 13) / (1 << 22)), 2
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs) if w.xs.shape[0] else None
+    rt = RT(w.n, w.groups, precision="fp32c")
+    perm, *_ = rt.rt_build_cells(dev(w.x))
+    if w.xs.shape[0]:
+        rt.rt_set_sources(dev(w.xs))
+    rt.rt_set_surfaces("ivanova")
+    rt.rt_set_riemann(solver)
+    p = perm.cpu().numpy()
+    U = dev(w.U0[p]).float()
+    L = dev(w.L) if w.xs.shape[0] else None
+    Q = torch.zeros(w.groups, dtype=torch.float64, device="cuda")
+    for _ in range(steps):
+        U = rt.step(U, L, photon_total=Q)
+    rt.rt_sync()
+    got = unsort(U.double().cpu().numpy(), p)
+    tab = oracle.hll_table() if solver == "hll" else None
+    ref, _ = oracle.run(geo, srcs, w.U0, w.L if w.xs.shape[0] else None, steps, hll=tab,
+                        ivanova=True)
+    err = local_err(got, ref, geo.sptr, geo.sidx)
+    log(f"Ivanova {solver} FP32C {case} {steps} steps: max err {err:.2e} of the neighbourhood scale")
+    assert err < 1e-5
+    assert np.allclose(Q.cpu().numpy(), oracle.photon_total(geo, ref), rtol=1e-6, atol=0)
+    hop, _ = oracle.run(geo, srcs, w.U0, w.L if w.xs.shape[0] else None, steps, hll=tab)
+    assert local_err(got, hop, geo.sptr, geo.sidx) > 1e-4
+
+
 def test_refusals():
     w = workloads.lattice_workload(7, 1, 0, 1, seed=990, name="refuse")
     fresh = RT(w.n, w.groups)
@@ -145,5 +183,7 @@ def test_refusals():
         fresh.rt_set_surfaces("ivanova")                     # before the build
     rt32 = RT(w.n, w.groups, precision="fp32c")
     rt32.rt_build_cells(dev(w.x))
-    with pytest.raises(RTError, match="RT_EINVAL"):
-        rt32.rt_set_surfaces("ivanova")
+    rt32.rt_set_surfaces("ivanova")
+    U = dev(w.U0).float()
+    with pytest.raises(RTError, match="RT_ESTATE"):           # no FP32C adjoint with them
+        rt32.rt_adjoint(U, None, torch.ones_like(U))
