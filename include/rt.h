@@ -158,11 +158,10 @@ rt_status rt_photon_total(rt_ctx *ctx, const void *U, double *Q);
  *           [-1, 1] and interpolates bilinearly (a state with E <= 0 or F = 0
  *           is looked up at f = 0).
  * HLL is implemented in rt_transport (FP64 and FP32C, the FP32C kernel
- * interpolating an FP32 copy of the table), in rt_tick and in the FP64
- * rt_adjoint (the derivative of the interpolated speeds, with the branch the
- * forward takes at the max/min of the speeds, the clamps of f and mu and the
- * table cells); the FP32C rt_adjoint returns RT_ESTATE while HLL is
- * selected.  The table (RT_HLL_NF x RT_HLL_NMU
+ * interpolating an FP32 copy of the table), in rt_tick and in rt_adjoint
+ * (FP64 and FP32C: the derivative of the interpolated speeds, with the branch
+ * the forward takes at the max/min of the speeds, the clamps of f and mu and
+ * the table cells).  The table (RT_HLL_NF x RT_HLL_NMU
  * x 2 doubles) is computed on the host and uploaded on the first selection of
  * RT_HLL (synchronous). */
 typedef enum { RT_GLF = 0, RT_HLL = 1 } rt_riemann;
@@ -182,10 +181,9 @@ rt_status rt_set_riemann(rt_ctx *ctx, int32_t solver);
  * After rt_build_cells (RT_ESTATE before), FP64 and FP32C contexts (the
  * FP32C kernel forms A in FP32 from g rounded to FP32); selecting RT_IVANOVA
  * computes g (n x 4 doubles, kept and recomputed by
- * later builds).  rt_transport, rt_tick and the FP64 rt_adjoint take either
- * surfaces (rt_adjoint differentiates the step with them held static; the
- * FP32C rt_adjoint returns RT_ESTATE with RT_IVANOVA).  The gradient step
- * (eq:gradient) is the same for both. */
+ * later builds).  rt_transport, rt_tick and rt_adjoint take either surfaces
+ * (rt_adjoint differentiates the step with them held static).  The gradient
+ * step (eq:gradient) is the same for both. */
 typedef enum { RT_HOPKINS = 0, RT_IVANOVA = 1 } rt_surfaces;
 rt_status rt_set_surfaces(rt_ctx *ctx, int32_t kind);
 
@@ -311,8 +309,7 @@ rt_status rt_tick(rt_ctx *ctx, double *U, const double *L, int64_t tick, double 
  *   dL_dL    [S][G] double, accumulated (+=) dLoss/dL, or NULL.
  * U_pre is read only when UD is NULL.  Scratch (a few state-sized buffers) is
  * allocated by the library on first use.  The step differentiated uses the
- * selected Riemann solver (GLF, or HLL in FP64 contexts) and the selected
- * effective surfaces; RT_ESTATE with HLL or RT_IVANOVA in an FP32C context. */
+ * selected Riemann solver and effective surfaces. */
 rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
                      const void *UD, const void *U_unguarded, const void *lam_next, void *lam,
                      double *dL_dL);

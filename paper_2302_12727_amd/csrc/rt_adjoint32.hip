@@ -28,14 +28,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_guard32(int64_t n, const float *
 }
 
 // A wave owns 64 particles and GW of the G groups (G/GW waves per 64
-// particles), as in the FP64 pair pass.
-template <int G, int GW>
+// particles), as in the FP64 pair pass.  HLL and IVA as in the FP64 pair
+// pass (the FP32 table, the FP32 Ivanova surfaces of the FP32C transport).
+template <int G, int GW, bool HLL = false, bool IVA = false>
 __global__ __launch_bounds__(kBlock) void k_adj_pair32(
     int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ geo,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_nbr, const float *__restrict__ UD,
     const float *__restrict__ lam2, const double *__restrict__ dtp, double c, double box,
-    float *__restrict__ R) {
+    float *__restrict__ R, const float2 *__restrict__ hll = nullptr,
+    const double *__restrict__ ivan = nullptr) {
     static_assert(G % GW == 0, "group slices must tile the groups");
     constexpr int NS = G / GW, NQ = 4 * GW;
     __shared__ float stage[kBlock / 64][64 * kStage32];
@@ -58,6 +60,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair32(
     const double *xk = reinterpret_cast<const double *>(rk);
     const double pkx = xk[0], pky = xk[1], pkz = xk[2];
     const float iHk = rk[F_IH], hk = rk[F_H];
+    float gk[3] = {0.0f, 0.0f, 0.0f};   // IVA: own kernel-gradient sum
+    if (IVA) {
+        gk[0] = (float)ivan[4 * ic];
+        gk[1] = (float)ivan[4 * ic + 1];
+        gk[2] = (float)ivan[4 * ic + 2];
+    }
     float Bk[6];
 #pragma unroll
     for (int a = 0; a < 6; ++a) Bk[a] = rk[F_B + a];
@@ -98,6 +106,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair32(
             stage_rows32(geo32, row, sb, lane);
             PairGeo32 pg;
             pair_geometry32(pkx, pky, pkz, iHk, hk, Bk, sb + lane * kStage32, box, ibox, pg);
+            if (IVA) {                          // the same pair with the Ivanova surface
+                const float *rl = sb + lane * kStage32;
+                const double *gd = ivan + 4 * (int64_t)j;
+                const float gl[3] = {(float)gd[0], (float)gd[1], (float)gd[2]};
+                const float r = sqrt32(pg.sx * pg.sx + pg.sy * pg.sy + pg.sz * pg.sz);
+                ivanova_surface32(pg.sx, pg.sy, pg.sz, r, iHk, rk[F_V], gk, rl[F_IH], rl[F_V], gl,
+                                  pg.Ax, pg.Ay, pg.Az);
+                pg.An = sqrt32(pg.Ax * pg.Ax + pg.Ay * pg.Ay + pg.Az * pg.Az);
+            }
             const float dtVl = dtf * rcp32(sb[lane * kStage32 + F_V]);
             const bool use = valid && pg.An > 0.0f;
 #pragma unroll
@@ -131,11 +148,40 @@ __global__ __launch_bounds__(kBlock) void k_adj_pair32(
                 for (int m = 0; m < 4; ++m) nu[m] = 0.5f * (dtVl * Llm[m] - dtVk * Li[4 * g + m]);
                 m1_flux32_vjp(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c2, ic2, nu, tL);
                 m1_flux32_vjp(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c2, ic2, nu, tR);
-                const float dis = cf * pg.An;
+                if constexpr (HLL) {
+                    const float iAn = pg.An > 0.0f ? rcp32(pg.An) : 0.0f;
+                    float loL, hiL, loR, hiR, w1, w2, w3;
+                    hll_speeds32(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, iAn, cf, ic2, hll,
+                                 loL, hiL);
+                    hll_speeds32(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, iAn, cf, ic2, hll,
+                                 loR, hiR);
+                    hll_weights32(loL, hiL, loR, hiR, pg.An, w1, w2, w3);
+                    float FL[4], FR[4];
+                    m1_flux32(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c2, ic2, FL);
+                    m1_flux32(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c2, ic2, FR);
+                    float S1 = 0.0f, S2 = 0.0f, S3 = 0.0f;   // m . (F_L, F_R, U_R - U_L)
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    tL[m] += dis * nu[m];
-                    tR[m] -= dis * nu[m];
+                    for (int m = 0; m < 4; ++m) {
+                        S1 += nu[m] * FL[m];
+                        S2 += nu[m] * FR[m];
+                        S3 += nu[m] * (qR[m] - qL[m]);
+                        tL[m] = 2.0f * (w1 * tL[m] - w3 * nu[m]);
+                        tR[m] = 2.0f * (w2 * tR[m] + w3 * nu[m]);
+                    }
+                    float gloL, ghiL, gloR, ghiR;
+                    hll_weights32_vjp(loL, hiL, loR, hiR, pg.An, 2.0f * S1, 2.0f * S2, 2.0f * S3,
+                                      gloL, ghiL, gloR, ghiR);
+                    hll_speeds32_vjp(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, iAn, cf, ic2,
+                                     hll, gloL, ghiL, tL);
+                    hll_speeds32_vjp(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, iAn, cf, ic2,
+                                     hll, gloR, ghiR, tR);
+                } else {
+                    const float dis = cf * pg.An;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        tL[m] += dis * nu[m];
+                        tR[m] -= dis * nu[m];
+                    }
                 }
                 guard32_vjp(qLp, tL, cf);
                 guard32_vjp(qRp, tR, cf);
@@ -323,9 +369,20 @@ void launch(rt_ctx *ctx, const float *UD, const float *Uung, const float *lam_ne
     hipStream_t st = ctx->stream;
     constexpr int GW = (RT_ADJ32_GW == 0 || G % RT_ADJ32_GW != 0) ? G : RT_ADJ32_GW;
     k_adj_guard32<G><<<nblk(n * G), kBlock, 0, st>>>(n, Uung, lam_next, lam2, (float)ctx->p.c_red);
-    k_adj_pair32<G, GW><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, st>>>(
-        n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt,
-        ctx->p.c_red, ctx->p.box, R);
+    const float2 *tab = (const float2 *)ctx->hll_table32;
+    const bool iva = ctx->surfaces == RT_IVANOVA;
+#define RT_ADJ32_PAIR_LAUNCH(HLL_, IVA_)                                                       \
+    k_adj_pair32<G, GW, HLL_, IVA_><<<(unsigned)xcd_grid(nb * (G / GW)), kBlock, 0, st>>>(    \
+        n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt,       \
+        ctx->p.c_red, ctx->p.box, R, tab, ctx->ivan)
+    if (ctx->solver == RT_HLL) {
+        if (iva) RT_ADJ32_PAIR_LAUNCH(true, true);
+        else RT_ADJ32_PAIR_LAUNCH(true, false);
+    } else {
+        if (iva) RT_ADJ32_PAIR_LAUNCH(false, true);
+        else RT_ADJ32_PAIR_LAUNCH(false, false);
+    }
+#undef RT_ADJ32_PAIR_LAUNCH
     const int64_t ng = (n + kBlock / kAGQ32 - 1) / (kBlock / kAGQ32);
     k_adj_grad32<G, kAGQ32><<<(unsigned)xcd_grid(ng), kBlock, 0, st>>>(
         n, ng, ctx->geo32, ctx->nbr, ctx->wave_base, ctx->n_nbr, R, lam, ctx->p.box);

@@ -298,9 +298,6 @@ rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const doub
     if (!UD && !U_pre) return rt_fail(ctx, RT_EINVAL, "U_pre is required when UD is NULL");
     if (ctx->S > 0 && !L) return rt_fail(ctx, RT_EINVAL, "L is required when sources are set");
     if (UD && !aligned16(UD)) return rt_fail(ctx, RT_EINVAL, "UD must be 16-byte aligned");
-    if (ctx->p.precision != RT_FP64 && (ctx->solver == RT_HLL || ctx->surfaces == RT_IVANOVA))
-        return rt_fail(ctx, RT_ESTATE,
-                       "the adjoint with the HLL solver or the Ivanova surfaces is implemented in FP64");
     return rt_adjoint_impl(ctx, U_pre, L, dt, UD, U_unguarded, lam_next, lam, dL_dL);
 }
 

@@ -188,6 +188,79 @@ __device__ __forceinline__ void guard32_vjp(const float q[4], float lam[4], floa
     }
 }
 
+// VJPs of the FP32 HLL weights and speeds (see hll_weights_vjp and
+// hll_speeds64_vjp): the branch the forward takes at every kink; here f and mu
+// come from g = F/E, so a state with E <= 1e-30 or g = 0 passes nothing.
+__device__ __forceinline__ void hll_weights32_vjp(float loL, float hiL, float loR, float hiR,
+                                                  float An, float S1, float S2, float S3,
+                                                  float &gloL, float &ghiL, float &gloR,
+                                                  float &ghiR) {
+    gloL = ghiL = gloR = ghiR = 0.0f;
+    const float mx = hiL >= hiR ? hiL : hiR, mn = loL <= loR ? loL : loR;
+    const float lp = mx > 0.0f ? mx : 0.0f, lm = mn < 0.0f ? mn : 0.0f;
+    const float den = lp - lm;
+    if (!(den > 0.0f)) return;
+    const float id = rcp32(den), id2 = id * id;
+    const float glp = (-lm * S1 + lm * S2 - An * lm * lm * S3) * id2;
+    const float glm = (lp * S1 - lp * S2 + An * lp * lp * S3) * id2;
+    if (mx > 0.0f) (hiL >= hiR ? ghiL : ghiR) = glp;
+    if (mn < 0.0f) (loL <= loR ? gloL : gloR) = glm;
+}
+__device__ __forceinline__ void hll_speeds32_vjp(float E, float Fx, float Fy, float Fz, float Ax,
+                                                 float Ay, float Az, float iAn, float c,
+                                                 float ic2, const float2 *__restrict__ tab,
+                                                 float glo, float ghi, float (&t)[4]) {
+    const float iE = E > 1e-30f ? rcp32(E) : 0.0f;
+    const float gx = Fx * iE, gy = Fy * iE, gz = Fz * iE;
+    const float g2 = gx * gx + gy * gy + gz * gz;
+    if (!(g2 > 0.0f)) return;
+    const float ig = __builtin_amdgcn_rsqf(g2);
+    const float fr = sqrt32(g2 * ic2);
+    const float mr = (gx * Ax + gy * Ay + gz * Az) * ig * iAn;
+    const float f = fminf(fr, 1.0f), mu = fminf(fmaxf(mr, -1.0f), 1.0f);
+    const float x = f * (RT_HLL_NF - 1), y = (mu + 1.0f) * (0.5f * (RT_HLL_NMU - 1));
+    const int i = max(min((int)x, RT_HLL_NF - 2), 0);
+    const int j = max(min((int)y, RT_HLL_NMU - 2), 0);
+    const float tx = x - i, ty = y - j;
+    const float2 *tb = tab + i * RT_HLL_NMU + j;
+    const float2 v00 = tb[0], v01 = tb[1], v10 = tb[RT_HLL_NMU], v11 = tb[RT_HLL_NMU + 1];
+    const float ux = 1.0f - tx, uy = 1.0f - ty;
+    const float gxx = glo * (uy * (v10.x - v00.x) + ty * (v11.x - v01.x)) +
+                      ghi * (uy * (v10.y - v00.y) + ty * (v11.y - v01.y));
+    const float gyy = glo * (ux * (v01.x - v00.x) + tx * (v11.x - v10.x)) +
+                      ghi * (ux * (v01.y - v00.y) + tx * (v11.y - v10.y));
+    const float gf = c * gxx * (RT_HLL_NF - 1), gm = c * gyy * (0.5f * (RT_HLL_NMU - 1));
+    if (fr <= 1.0f) {            // f = |g|/c: df/dE = -f/E, df/dF = g/(|g| c E)
+        const float k = gf * ig * iE * (c * ic2);   // (1/c) g/|g| / E
+        t[0] -= gf * fr * iE;
+        t[1] += k * gx;
+        t[2] += k * gy;
+        t[3] += k * gz;
+    }
+    if (mr >= -1.0f && mr <= 1.0f) {   // dmu/dF = (A/|A| - mu g/|g|) / |F|
+        const float a = gm * ig * iE * iAn, b = gm * mr * ig * ig * iE;
+        t[1] += a * Ax - b * gx;
+        t[2] += a * Ay - b * gy;
+        t[3] += a * Az - b * gz;
+    }
+}
+// Ivanova surface (eq:IvanovaAij) in FP32 for the pair k, l: separation s,
+// distance r, the particles' 1/H, V and kernel-gradient sums g.
+__device__ __forceinline__ void ivanova_surface32(float sx, float sy, float sz, float r, float iHk,
+                                                  float Vk, const float (&gk)[3], float iHl,
+                                                  float Vl, const float (&gl)[3], float &Ax,
+                                                  float &Ay, float &Az) {
+    const float qk = r * iHk, ql = r * iHl;
+    const float sk = (float)kSigma3 * Vk * Vk * iHk * iHk * iHk;
+    const float sl = (float)kSigma3 * Vl * Vl * iHl * iHl * iHl;
+    const float ir = r > 0.0f ? rcp32(r) : 0.0f;
+    const float a = -(sk * iHk * kern_dwf(qk) + sl * iHl * kern_dwf(ql)) * ir;
+    const float bk = sk * Vk * kern_wf(qk), bl = sl * Vl * kern_wf(ql);
+    Ax = a * sx - bk * gk[0] + bl * gl[0];
+    Ay = a * sy - bk * gk[1] + bl * gl[1];
+    Az = a * sz - bk * gk[2] + bl * gl[2];
+}
+
 // VJP of m1_flux32 (see m1_flux64_vjp for the formulas).
 __device__ __forceinline__ void m1_flux32_vjp(float E, float Fx, float Fy, float Fz, float Ax,
                                               float Ay, float Az, float c2, float ic2,

@@ -194,20 +194,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
             const float r = sqrt32(sx * sx + sy * sy + sz * sz);
             float Ax, Ay, Az;
             if (IVA) {
-                // A_kl = -(V_k^2 sigma w'_k/H_k^4 + V_l^2 sigma w'_l/H_l^4) s/r
-                //        - V_k^3 sigma w_k/H_k^3 g_k + V_l^3 sigma w_l/H_l^3 g_l
                 const double *gd = ivan + 4 * (int64_t)j;
-                const float glx = (float)gd[0], gly = (float)gd[1], glz = (float)gd[2];
-                const float iHl = rl[F_IH], Vk = rk[F_V], Vl = rl[F_V];
-                const float qk = r * iHk, ql = r * iHl;
-                const float sk = (float)kSigma3 * Vk * Vk * iHk * iHk * iHk;
-                const float sl = (float)kSigma3 * Vl * Vl * iHl * iHl * iHl;
-                const float ir = r > 0.0f ? rcp32(r) : 0.0f;
-                const float a = -(sk * iHk * kern_dwf(qk) + sl * iHl * kern_dwf(ql)) * ir;
-                const float bk = sk * Vk * kern_wf(qk), bl = sl * Vl * kern_wf(ql);
-                Ax = a * sx - bk * gk[0] + bl * glx;
-                Ay = a * sy - bk * gk[1] + bl * gly;
-                Az = a * sz - bk * gk[2] + bl * glz;
+                const float gl[3] = {(float)gd[0], (float)gd[1], (float)gd[2]};
+                ivanova_surface32(sx, sy, sz, r, iHk, rk[F_V], gk, rl[F_IH], rl[F_V], gl, Ax, Ay,
+                                  Az);
             } else {
                 const float wk = kern_wf(r * iHk);
                 const float wl = kern_wf(r * rl[F_IH]);

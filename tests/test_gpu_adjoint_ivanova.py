@@ -130,3 +130,40 @@ def test_rollout_gradient_vs_finite_differences(case):
             worst = max(worst, best)
             assert best < 1e-6, (s, grp, gL[s, grp])
     log(f"Ivanova dLoss/dL vs central differences: worst rel err {worst:.2e}")
+
+
+@pytest.mark.parametrize("solver", ["glf", "hll"])
+def test_fp32c_adjoint_against_fp64_adjoint(case, solver):
+    """The same rollout and loss in both precisions with the Ivanova surfaces:
+    the compensated-FP32 gradients against the FP64 ones (bounds of the
+    Hopkins comparison)."""
+    w, geo, srcs, rt64, p, probes, Et = case
+    inv = np.empty_like(p)
+    inv[p] = np.arange(w.n)
+    pr = torch.as_tensor(inv[probes], device="cuda")
+    rt32 = RT(w.n, w.groups, precision="fp32c")
+    perm32, *_ = rt32.rt_build_cells(dev(w.x), dev(geo.h))
+    rt32.rt_set_sources(dev(w.xs))
+    rt32.rt_set_surfaces("ivanova")
+    rt32.rt_set_riemann(solver)
+    rt64.rt_set_riemann(solver)
+    assert np.array_equal(perm32.cpu().numpy(), p)
+    grads = {}
+    try:
+        for name, rt, dt in (("fp64", rt64, torch.float64), ("fp32c", rt32, torch.float32)):
+            U0 = dev(w.U0[p]).to(dt).requires_grad_(True)
+            L = dev(w.L).requires_grad_(True)
+            U = rollout(rt, L, U0, w.steps, ckpt_every=3)
+            ((U[pr, :, 0].double() - dev(Et)) ** 2).sum().backward()
+            grads[name] = (U0.grad.double().cpu().numpy(), L.grad.cpu().numpy())
+    finally:
+        rt64.rt_set_riemann("glf")
+    eU = rel(grads["fp32c"][0], grads["fp64"][0])
+    eL = rel(grads["fp32c"][1], grads["fp64"][1])
+    d = np.abs(grads["fp32c"][0] - grads["fp64"][0]) / np.abs(grads["fp64"][0]).max()
+    q = np.quantile(d, [0.5, 0.99, 0.999])
+    log(f"Ivanova {solver} fp32c adjoint vs fp64 adjoint: dU0 rel err max {eU:.2e} "
+        f"(median {q[0]:.1e}, p99 {q[1]:.1e}, p99.9 {q[2]:.1e}), dL rel err {eL:.2e}")
+    assert eL < 1e-4
+    assert q[1] < 1e-5 and eU < 1e-3
+

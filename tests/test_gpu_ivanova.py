@@ -181,9 +181,4 @@ def test_refusals():
     fresh = RT(w.n, w.groups)
     with pytest.raises(RTError, match="RT_ESTATE"):
         fresh.rt_set_surfaces("ivanova")                     # before the build
-    rt32 = RT(w.n, w.groups, precision="fp32c")
-    rt32.rt_build_cells(dev(w.x))
-    rt32.rt_set_surfaces("ivanova")
-    U = dev(w.U0).float()
-    with pytest.raises(RTError, match="RT_ESTATE"):           # no FP32C adjoint with them
-        rt32.rt_adjoint(U, None, torch.ones_like(U))
+
