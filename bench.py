@@ -190,7 +190,7 @@ def compare_precisions(w, dev):
     return res
 
 
-def compare_time_bins(w, dev, max_bin: int = 8, cycles: int = 2):
+def compare_time_bins(w, dev, max_bin: int = 8, cycles: int = 2, precision: str = "fp64"):
     """Individual time bins against the global step on workload w: the same
     number of ticks (the same simulated time) both ways, wall time and
     pair interactions per second (counting, with bins, only the pairs due in
@@ -199,23 +199,24 @@ def compare_time_bins(w, dev, max_bin: int = 8, cycles: int = 2):
     import torch
     from paper_2302_12727_amd import RT
 
-    rt = RT(w.n, w.groups, cfl=w.cfl, c_red=w.c_red, device=dev)
+    rt = RT(w.n, w.groups, precision=precision, cfl=w.cfl, c_red=w.c_red, device=dev)
     perm, *_ = rt.rt_build_cells(torch.from_numpy(w.x).to(dev))
     if w.xs.shape[0]:
         rt.rt_set_sources(torch.from_numpy(w.xs).to(dev))
     rt.rt_sync()
     p = perm.cpu().numpy()
     L = torch.from_numpy(w.L).to(dev) if w.xs.shape[0] else None
-    U0 = torch.from_numpy(np.ascontiguousarray(w.U0[p])).to(dev)
+    U0 = torch.from_numpy(np.ascontiguousarray(w.U0[p])).to(dev).to(rt.sdtype)
     ptr, idx = rt.rt_get_neighbours()
     ptr, idx = ptr.cpu().numpy(), idx.cpu().numpy()
     rows = np.repeat(np.arange(w.n), np.diff(ptr))
-    res = {"workload": w.name, "n": w.n, "groups": w.groups, "max_bin": max_bin}
+    res = {"workload": w.name, "n": w.n, "groups": w.groups, "max_bin": max_bin,
+           "precision": precision}
 
     def run(ticks):
         U = U0.clone()
         UD = rt.rt_gradient(U)
-        acc = torch.zeros_like(U)
+        acc = torch.zeros(U.shape, dtype=torch.float64, device=U.device)
         rt.rt_tick(U, L, 0, UD, acc)              # warm-up tick, then restart
         U = U0.clone()
         UD = rt.rt_gradient(U)
@@ -527,6 +528,11 @@ def main():
         out["plummer_fp32c_vs_fp64"] = compare_precisions(workloads.config(2), dev)
         torch.cuda.empty_cache()
         out["plummer_time_bins"] = compare_time_bins(workloads.config(2), dev)
+        torch.cuda.empty_cache()
+        tb = compare_time_bins(workloads.config(2), dev, precision="fp32c")
+        out["plummer_time_bins"]["fp32c"] = {k: tb[k] for k in (
+            "binned_ms", "global_ms", "speedup", "binned_due_pairs_per_s", "global_pairs_per_s",
+            "E_difference_binned_vs_global")}
         torch.cuda.empty_cache()
     if args.large_adjoint:
         out["large_adjoint"] = large_adjoint(dev)

@@ -254,7 +254,7 @@ rt_status rt_drift(rt_ctx *ctx, const void *UD, const double *dx, void *U_out,
 /* Individual power-of-two time steps (Part II "Individual time steps",
  * eq:meshless-explicit-individual-timesteps; Part III eq:transport-update-
  * explicit with min{dt_k, dt_l}; the factor-4 limiter of Part III "Dynamic
- * Sub-Cycling").  FP64 contexts only.
+ * Sub-Cycling").  FP64 and FP32C contexts.
  *
  * rt_time_bins: particle i gets dt_i = dt 2^b_i, dt the step rt_build_cells
  * returned (the smallest CFL step), b_i the largest n <= max_bin (0 .. 30)
@@ -278,18 +278,21 @@ rt_status rt_time_bins(rt_ctx *ctx, int32_t max_bin, int32_t *bins, int64_t *cyc
  * sums of both particles; the particles that end a step apply
  * U - (flux sum) / V, guard the result as rt_transport does, and clear their
  * sums.
- *   U    [n][G][4] double in/out: the states.
+ *   U    [n][G][4] in/out: the states (double in FP64 contexts, float in
+ *        FP32C ones).
  *   L    [S][G] luminosities (NULL without sources).
- *   UD   [n][G][16] double in/out, 16-byte aligned: the stored gradient
- *        records.  Before tick 0 fill it with rt_gradient of the initial U;
- *        keep it between ticks.
- *   acc  [n][G][4] double in/out: the pending flux sums (zero before tick 0;
- *        all zero again after a tick where every particle ends a step).
+ *   UD   [n][G][16] in/out, 16-byte aligned, the state's type: the stored
+ *        gradient records.  Before tick 0 fill it with rt_gradient of the
+ *        initial U; keep it between ticks.
+ *   acc  [n][G][4] double in/out (both precisions): the pending flux sums
+ *        (zero before tick 0; all zero again after a tick where every
+ *        particle ends a step).  In FP32C the exchanges of a tick are summed
+ *        with compensation in FP32 and added to acc in FP64.
  *   photon_total [G] out or NULL: sum_k V_k E_k of the states after the tick
  *        (the pending sums are not in it: with them, sum_k (V_k E_k - acc_k,E)
  *        is conserved up to injection and the ledger).
  *   counts, ledger: as rt_transport, accumulated. */
-rt_status rt_tick(rt_ctx *ctx, double *U, const double *L, int64_t tick, double *UD,
+rt_status rt_tick(rt_ctx *ctx, void *U, const double *L, int64_t tick, void *UD,
                   double *acc, double *photon_total, int64_t *counts, double *ledger);
 
 /* Adjoint (vector-Jacobian product) of one full step

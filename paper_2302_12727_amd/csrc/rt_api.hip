@@ -267,23 +267,20 @@ rt_status rt_drift(rt_ctx *ctx, const void *UD, const double *dx, void *U_out,
 rt_status rt_time_bins(rt_ctx *ctx, int32_t max_bin, int32_t *bins, int64_t *cycle_ticks) {
     if (!ctx) return RT_EINVAL;
     if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
-    if (ctx->p.precision != RT_FP64)
-        return rt_fail(ctx, RT_EINVAL, "time bins are implemented for FP64 contexts only");
     if (max_bin < 0 || max_bin > 30) return rt_fail(ctx, RT_EINVAL, "max_bin must be in 0 .. 30");
     return rt_time_bins_impl(ctx, max_bin, bins, cycle_ticks);
 }
 
-rt_status rt_tick(rt_ctx *ctx, double *U, const double *L, int64_t tick, double *UD,
+rt_status rt_tick(rt_ctx *ctx, void *U, const double *L, int64_t tick, void *UD,
                   double *acc, double *photon_total, int64_t *counts, double *ledger) {
     if (!ctx) return RT_EINVAL;
     if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
-    if (ctx->p.precision != RT_FP64)
-        return rt_fail(ctx, RT_EINVAL, "time bins are implemented for FP64 contexts only");
     if (!U || !UD || !acc) return rt_fail(ctx, RT_EINVAL, "U, UD and acc are required");
     if (tick < 0) return rt_fail(ctx, RT_EINVAL, "tick must be >= 0");
     if (ctx->S > 0 && !L) return rt_fail(ctx, RT_EINVAL, "L is required when sources are set");
-    size_t nu = sizeof(double) * 4 * ctx->p.groups * ctx->p.n;
-    if (overlap(UD, 4 * nu, U, nu) || overlap(UD, 4 * nu, acc, nu) || overlap(U, nu, acc, nu))
+    const size_t es = ctx->p.precision == RT_FP64 ? sizeof(double) : sizeof(float);
+    const size_t nu = es * 4 * ctx->p.groups * ctx->p.n, na = sizeof(double) * 4 * ctx->p.groups * ctx->p.n;
+    if (overlap(UD, 4 * nu, U, nu) || overlap(UD, 4 * nu, acc, na) || overlap(U, nu, acc, na))
         return rt_fail(ctx, RT_EINVAL, "U, UD and acc must not overlap");
     if (!aligned16(UD)) return rt_fail(ctx, RT_EINVAL, "UD must be 16-byte aligned");
     return rt_tick_impl(ctx, U, L, tick, UD, acc, photon_total, counts, ledger);

@@ -51,11 +51,12 @@ __global__ void k_bins_limit(int64_t n, const int32_t *__restrict__ nbr,
 }
 
 // bins into the geometry records (slot 12) with the smallest bin of the
-// neighbourhood (slot 13)
+// neighbourhood (slot 13), and into the FP32 records (slot F_BIN) of FP32C
+// contexts
 __global__ void k_bins_store(int64_t n, const int32_t *__restrict__ nbr,
                              const int64_t *__restrict__ wave_base,
                              const int32_t *__restrict__ n_nbr, const int32_t *__restrict__ bin,
-                             double *__restrict__ geo) {
+                             double *__restrict__ geo, float *__restrict__ geo32) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t base = wave_base[i >> 6] + (i & 63);
@@ -64,6 +65,7 @@ __global__ void k_bins_store(int64_t n, const int32_t *__restrict__ nbr,
     for (int32_t k = 0; k < nn; ++k) m = min(m, bin[nbr[base + 64 * (int64_t)k]]);
     geo[(int64_t)kRec * i + 12] = (double)bin[i];
     geo[(int64_t)kRec * i + 13] = (double)m;
+    if (geo32) geo32[(int64_t)F_REC * i + F_BIN] = (float)bin[i];
 }
 
 __global__ void k_bins_max(int64_t n, const int32_t *__restrict__ bin, int32_t *__restrict__ top) {
@@ -72,11 +74,12 @@ __global__ void k_bins_max(int64_t n, const int32_t *__restrict__ bin, int32_t *
 }
 
 // injection for the particles that end a step in this tick, each with its dt
+template <typename T>
 __global__ void k_inject_binned(int32_t ngas, int G, const int32_t *__restrict__ gptr,
                                 const int32_t *__restrict__ gas, const int32_t *__restrict__ src,
                                 const double *__restrict__ coef, const double *__restrict__ L,
                                 const double *__restrict__ dtp, const double *__restrict__ geo,
-                                int64_t tick, double *__restrict__ U) {
+                                int64_t tick, T *__restrict__ U) {
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ngas) return;
     const int64_t g = gas[t];
@@ -86,14 +89,15 @@ __global__ void k_inject_binned(int32_t ngas, int G, const int32_t *__restrict__
     for (int grp = 0; grp < G; ++grp) {
         double s = 0.0;
         for (int32_t e = gptr[t]; e < gptr[t + 1]; ++e) s += coef[e] * L[(int64_t)src[e] * G + grp];
-        double *E = U + (g * G + grp) * 4;
-        E[0] = E[0] + dtg * s;
+        T *E = U + (g * G + grp) * 4;
+        E[0] = (T)((double)E[0] + dtg * s);
     }
 }
 
 // the stored state of the particles that ended a step follows their update
+template <typename T>
 __global__ void k_refresh(int64_t n, int G, const double *__restrict__ geo, int64_t tick,
-                          const double *__restrict__ U, double *__restrict__ UD) {
+                          const T *__restrict__ U, T *__restrict__ UD) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * G) return;
     const int64_t i = t / G;
@@ -131,7 +135,8 @@ rt_status rt_time_bins_impl(rt_ctx *ctx, int32_t max_bin, int32_t *bins_out, int
         b2 = tmp;
         ++sweeps;
     }
-    k_bins_store<<<nblk(n), kBlock, 0, st>>>(n, ctx->nbr, ctx->wave_base, ctx->n_nbr, b, ctx->geo);
+    k_bins_store<<<nblk(n), kBlock, 0, st>>>(n, ctx->nbr, ctx->wave_base, ctx->n_nbr, b, ctx->geo,
+                                             ctx->geo32);
     RT_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
     k_bins_max<<<nblk(n), kBlock, 0, st>>>(n, b, flag);
     int32_t top = 0;
@@ -146,19 +151,34 @@ rt_status rt_time_bins_impl(rt_ctx *ctx, int32_t max_bin, int32_t *bins_out, int
     return RT_OK;
 }
 
-rt_status rt_tick_impl(rt_ctx *ctx, double *U, const double *L, int64_t tick, double *UD,
+rt_status rt_tick_impl(rt_ctx *ctx, void *U, const double *L, int64_t tick, void *UD,
                        double *acc, double *Q, int64_t *counts, double *ledger) {
     const int64_t n = ctx->p.n;
     const int G = ctx->p.groups;
+    const bool f64 = ctx->p.precision == RT_FP64;
     if (ctx->S > 0 && ctx->n_inj_gas > 0 && L) {
-        k_inject_binned<<<nblk(ctx->n_inj_gas), kBlock, 0, ctx->stream>>>(
-            ctx->n_inj_gas, G, ctx->inj_gptr, ctx->inj_gas, ctx->inj_src, ctx->inj_coef, L,
-            ctx->dt_dev, ctx->geo, tick, U);
+        if (f64)
+            k_inject_binned<double><<<nblk(ctx->n_inj_gas), kBlock, 0, ctx->stream>>>(
+                ctx->n_inj_gas, G, ctx->inj_gptr, ctx->inj_gas, ctx->inj_src, ctx->inj_coef, L,
+                ctx->dt_dev, ctx->geo, tick, (double *)U);
+        else
+            k_inject_binned<float><<<nblk(ctx->n_inj_gas), kBlock, 0, ctx->stream>>>(
+                ctx->n_inj_gas, G, ctx->inj_gptr, ctx->inj_gas, ctx->inj_src, ctx->inj_coef, L,
+                ctx->dt_dev, ctx->geo, tick, (float *)U);
         RT_HIP(hipGetLastError());
     }
-    rt_status rs = rt_tick_step_impl(ctx, U, UD, ctx->dt_dev, tick, acc, Q, counts, ledger);
+    rt_status rs = f64 ? rt_tick_step_impl(ctx, (double *)U, (double *)UD, ctx->dt_dev, tick, acc,
+                                           Q, counts, ledger)
+                       : rt_tick_step32_impl(ctx, (float *)U, (float *)UD, ctx->dt_dev, tick,
+                                             acc, Q, counts, ledger);
     if (rs != RT_OK) return rs;
-    k_refresh<<<nblk(n * G), kBlock, 0, ctx->stream>>>(n, G, ctx->geo, tick, U, UD);
+    if (f64)
+        k_refresh<double><<<nblk(n * G), kBlock, 0, ctx->stream>>>(n, G, ctx->geo, tick,
+                                                                   (const double *)U,
+                                                                   (double *)UD);
+    else
+        k_refresh<float><<<nblk(n * G), kBlock, 0, ctx->stream>>>(n, G, ctx->geo, tick,
+                                                                  (const float *)U, (float *)UD);
     RT_HIP(hipGetLastError());
     return RT_OK;
 }

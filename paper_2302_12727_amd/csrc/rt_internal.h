@@ -36,7 +36,7 @@ enum { R_X = 0, R_IH = 3, R_H = 4, R_V = 5, R_B = 6 };
 // Record of the compensated-FP32 path, 64 bytes (16 floats): positions stay
 // FP64 (floats 0..5 hold x, y, z as doubles; separations are formed in FP64
 // and rounded once), then 1/H, h, Bv (6) and V in FP32.
-enum { F_IH = 6, F_H = 7, F_B = 8, F_V = 14, F_REC = 16 };
+enum { F_IH = 6, F_H = 7, F_B = 8, F_V = 14, F_BIN = 15, F_REC = 16 };
 
 struct TimerRec {
     std::string name;
@@ -292,10 +292,13 @@ rt_status rt_absorb_impl(rt_ctx *ctx, void *U, int32_t J, const double *n_old,
 
 // individual time steps (rt_bins.hip; the binned gradient and transport in rt_step.hip)
 rt_status rt_time_bins_impl(rt_ctx *ctx, int32_t max_bin, int32_t *bins, int64_t *cycle);
-rt_status rt_tick_impl(rt_ctx *ctx, double *U, const double *L, int64_t tick, double *UD,
+rt_status rt_tick_impl(rt_ctx *ctx, void *U, const double *L, int64_t tick, void *UD,
                        double *acc, double *Q, int64_t *counts, double *ledger);
+// the gradient and transport of one tick (rt_step.hip, rt_step32.hip)
 rt_status rt_tick_step_impl(rt_ctx *ctx, double *U, double *UD, const double *dt, int64_t tick,
                             double *accm, double *Q, int64_t *counts, double *ledger);
+rt_status rt_tick_step32_impl(rt_ctx *ctx, float *U, float *UD, const double *dt, int64_t tick,
+                              double *accm, double *Q, int64_t *counts, double *ledger);
 
 // drift correction (rt_drift.hip)
 rt_status rt_drift_impl(rt_ctx *ctx, const void *UD, const double *dx, void *U_out, double *Q,

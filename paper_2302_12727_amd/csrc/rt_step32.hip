@@ -13,19 +13,22 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // Gradient (eq:gradient) in FP32, S_i^{-1} sum_j (q_j - q_i) w(r_ij/H_i) s_ij.
-// Q lanes share a particle as in the FP64 gradient.
-template <int G, int Q = 1>
+// Q lanes share a particle as in the FP64 gradient.  BIN: only the particles
+// that end a step in tick `tick` (time bin in slot F_BIN) recompute theirs.
+template <int G, int Q = 1, bool BIN = false>
 __global__ __launch_bounds__(kBlock) void k_gradient32(
     int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ xs,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_gath, const float *__restrict__ U, float *__restrict__ UD,
-    double box) {
+    double box, int64_t tick = 0) {
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     const int64_t blk = xcd_block(nb);
     if (blk >= nb) return;
     const int sub = (threadIdx.x & 63) % Q;
     const int64_t i = blk * (kBlock / Q) + threadIdx.x / Q;
     if (i >= n) return;                         // a particle's Q lanes leave together
+    if (BIN && ((tick + 1) & ((int64_t(1) << (int32_t)geo32[(int64_t)F_REC * i + F_BIN]) - 1)) != 0)
+        return;
     constexpr int NQ = 4 * G;
     const double ibox = 1.0 / box;
     const float *rec = geo32 + (int64_t)F_REC * i;
@@ -95,7 +98,12 @@ __global__ __launch_bounds__(kBlock) void k_gradient32(
 // IVA: the Ivanova surfaces (eq:IvanovaAij) in FP32 from the records' V and
 // 1/H and the kernel-gradient sums ivan (FP64, rounded to FP32 on load), the
 // separation from the FP64 positions as for the Hopkins surfaces.
-template <int G, bool HLL = false, int Q = 1, bool IVA = false>
+//
+// BIN: one tick of the individual-time-step scheme, as in the FP64 transport
+// (bins from the FP64 records' slots 12 and 13 and the FP32 records' F_BIN;
+// each due pair's exchange weighted by dt 2^min(b_k, b_l) in the compensated
+// sums; pending sums accm in FP64).
+template <int G, bool HLL = false, int Q = 1, bool IVA = false, bool BIN = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ? 3 : 1))) void k_transport32(
     int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ geo,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
@@ -103,7 +111,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
     const double *__restrict__ dtp, double c, double box, float *__restrict__ Uout,
     double *__restrict__ partials, unsigned long long *__restrict__ counts,
     float *__restrict__ Uung, const float2 *__restrict__ hll = nullptr,
-    const double *__restrict__ ivan = nullptr) {
+    const double *__restrict__ ivan = nullptr, int64_t tick = 0,
+    double *__restrict__ accm = nullptr) {
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     constexpr int NQ = 4 * G, PW = 64 / Q, PB = kBlock / Q;
     __shared__ float stage[kBlock / 64][64 * kStage32];
@@ -154,16 +163,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q].s = acc[q].c = 0.0f;
     int cE = 0, cF = 0;
+    // time bins: this particle ends a step in this tick (ends), or some pair of
+    // its neighbourhood does (touched)
+    const int64_t t1 = tick + 1;
+    const int32_t bk = BIN ? (int32_t)geo[(int64_t)kRec * ic + 12] : 0;
+    const bool ends = !BIN || (t1 & ((int64_t(1) << bk) - 1)) == 0;
+    const bool touched =
+        !BIN || (t1 & ((int64_t(1) << (int32_t)geo[(int64_t)kRec * ic + 13]) - 1)) == 0;
 
     if (wave_live) {
         const int64_t base = wave_base[w] + (i & 63);
         int32_t kmax = (int32_t)((wave_base[w + 1] - wave_base[w]) >> 6);
-        const int32_t nn = active ? n_nbr[i] : 0;
+        const int32_t nn = (active && touched) ? n_nbr[i] : 0;
         if (Q > 1) {                            // the longest list of this wave's particles
             kmax = nn;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
         }
+        if (BIN && __ballot(nn > 0) == 0) kmax = 0;   // no due pair in this wave
         // the next iteration's neighbour index is loaded one iteration ahead
         int32_t jn = sub < nn ? nbr[base + 64 * (int64_t)sub] : (int32_t)ic;
         for (int32_t kk = 0; kk < kmax; kk += Q) {
@@ -215,7 +232,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
             const float hl = rl[F_H];
             const float ih = rcp32(hk + hl);
             const float fk = hk * ih, fl = hl * ih;
-            const bool use = valid && An > 0.0f;
+            bool use = valid && An > 0.0f;
+            float wkl = 1.0f;                   // time integration of this exchange
+            if (BIN) {
+                const int32_t bl = (int32_t)rl[F_BIN];
+                const int32_t bmin = bk < bl ? bk : bl;
+                use = use && (t1 & ((int64_t(1) << bmin) - 1)) == 0;
+                wkl = (float)ldexp(dtp[0], bmin);
+            }
             const float iAn = (HLL && An > 0.0f) ? rcp32(An) : 0.0f;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
@@ -253,7 +277,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
                     cF += (f1 >> 1) + (f2 >> 1);
 #pragma unroll
                     for (int m = 0; m < 4; ++m)
-                        acc[4 * g + m].add(w1 * FL[m] + w2 * FR[m] + w3 * (qR[m] - qL[m]));
+                        acc[4 * g + m].add(wkl * (w1 * FL[m] + w2 * FR[m] + w3 * (qR[m] - qL[m])));
                 }
             }
         }
@@ -269,9 +293,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
     }
     double red[2 * G];
     int gE = 0, gF = 0;
-    if (owner) {
+    if (BIN && owner && !ends) {
+        // no update in this tick: keep the pending sums, count the current state
         const double V = geo[(int64_t)kRec * i + R_V];
-        const double dtV = dtp[0] / V;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (touched) {
+                double *a = accm + (i * G + g) * 4;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) a[m] += av[4 * g + m];
+            }
+            red[g] = V * (double)Ui[4 * g];
+            red[G + g] = 0.0;
+        }
+    } else if (owner) {
+        const double V = geo[(int64_t)kRec * i + R_V];
+        // the update: U - dt/V sum (global step), or U - (pending + this tick)/V
+        const double dtV = BIN ? 1.0 / V : dtp[0] / V;
+        if (BIN) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                double *a = accm + (i * G + g) * 4;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    av[4 * g + m] += a[m];
+                    a[m] = 0.0;
+                }
+            }
+        }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             double q0 = (double)Ui[4 * g + 0] - dtV * av[4 * g + 0];
@@ -388,6 +437,32 @@ void launch_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *U
 #undef RT_TRANSPORT32_LAUNCH
 }
 
+template <int G>
+void launch_tick32(rt_ctx *ctx, float *U, float *UD, const double *dt, double *partials,
+                   int64_t *counts, int64_t tick, double *accm) {
+    const int64_t n = ctx->p.n;
+    const int64_t ng = (n + kBlock / kGQ32 - 1) / (kBlock / kGQ32);
+    k_gradient32<G, kGQ32, true><<<(unsigned)xcd_grid(ng), kBlock, 0, ctx->stream>>>(
+        n, ng, ctx->geo32, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box,
+        tick);
+    const int64_t nb = rt_transport32_rows(n);
+    const float2 *tab = (const float2 *)ctx->hll_table32;
+    const bool iva = ctx->surfaces == RT_IVANOVA;
+#define RT_TICK32_LAUNCH(HLL_, IVA_)                                                           \
+    k_transport32<G, HLL_, kQ32, IVA_, true><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>( \
+        n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt,             \
+        ctx->p.c_red, ctx->p.box, U, partials, (unsigned long long *)counts, nullptr, tab,     \
+        ctx->ivan, tick, accm)
+    if (ctx->solver == RT_HLL) {
+        if (iva) RT_TICK32_LAUNCH(true, true);
+        else RT_TICK32_LAUNCH(true, false);
+    } else {
+        if (iva) RT_TICK32_LAUNCH(false, true);
+        else RT_TICK32_LAUNCH(false, false);
+    }
+#undef RT_TICK32_LAUNCH
+}
+
 }  // namespace
 
 void rt_gradient32(rt_ctx *ctx, const float *U, float *UD) {
@@ -419,4 +494,26 @@ void rt_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *Uout,
         case 8: launch_transport32<8>(ctx, UD, dt, Uout, partials, counts, Uung); break;
         default: break;
     }
+}
+
+rt_status rt_tick_step32_impl(rt_ctx *ctx, float *U, float *UD, const double *dt, int64_t tick,
+                              double *accm, double *Q, int64_t *counts, double *ledger) {
+    const int64_t nb = rt_transport32_rows(ctx->p.n);
+    double *part = (Q || ledger) ? ctx->partials : nullptr;
+    rt_timer_begin(ctx, "tick");
+    switch (ctx->p.groups) {
+        case 1: launch_tick32<1>(ctx, U, UD, dt, part, counts, tick, accm); break;
+        case 2: launch_tick32<2>(ctx, U, UD, dt, part, counts, tick, accm); break;
+        case 3: launch_tick32<3>(ctx, U, UD, dt, part, counts, tick, accm); break;
+        case 4: launch_tick32<4>(ctx, U, UD, dt, part, counts, tick, accm); break;
+        case 5: launch_tick32<5>(ctx, U, UD, dt, part, counts, tick, accm); break;
+        case 6: launch_tick32<6>(ctx, U, UD, dt, part, counts, tick, accm); break;
+        case 7: launch_tick32<7>(ctx, U, UD, dt, part, counts, tick, accm); break;
+        case 8: launch_tick32<8>(ctx, U, UD, dt, part, counts, tick, accm); break;
+        default: break;
+    }
+    rt_timer_end(ctx, "tick");
+    RT_HIP(hipGetLastError());
+    if (part) rt_finalize_partials(ctx, nb, Q, ledger);
+    return RT_OK;
 }

@@ -323,8 +323,8 @@ class RT:
 
     def rt_tick(self, U, L, tick: int, UD, acc, photon_total=None, counts=None, ledger=None):
         """One tick of the individual-time-step scheme (U, UD, acc in/out)."""
-        _need(U, "U", torch.float64, (self.n, self.G, 4))
-        _need(UD, "UD", torch.float64, (self.n, self.G, 16))
+        _need(U, "U", self.sdtype, (self.n, self.G, 4))
+        _need(UD, "UD", self.sdtype, (self.n, self.G, 16))
         _need(acc, "acc", torch.float64, (self.n, self.G, 4))
         if L is not None:
             _need(L, "L", torch.float64, (self.S, self.G))

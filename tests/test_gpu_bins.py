@@ -9,7 +9,8 @@ factor-4 limiter).
 - the photon budget including the pending sums closes every tick (1e-12);
 - the Ivanova surfaces (GLF and HLL): two cycles and a mid-cycle state with
   pending sums against the oracle's binned scheme with those surfaces;
-- FP32C contexts are refused.
+- FP32C contexts (GLF, HLL, Ivanova): two cycles and a mid-cycle state against
+  the FP64 oracle at the FP32C bar, and the budget with pending sums (1e-6).
 """
 import numpy as np
 import pytest
@@ -17,14 +18,14 @@ import torch
 
 import oracle
 import workloads
-from tests.gpu_util import dev, log, state_err, unsort
+from tests.gpu_util import dev, local_err, log, state_err, unsort
 
 pytestmark = pytest.mark.gpu
 
 if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_2302_12727_amd import RT, RTError  # noqa: E402
+from paper_2302_12727_amd import RT  # noqa: E402
 
 MAX_BIN = 6
 
@@ -155,9 +156,77 @@ def test_ivanova_against_oracle(case, solver):
         rt.rt_set_riemann("glf")
 
 
-def test_fp32c_context_refused():
-    w = workloads.config(0, scale=0.2)
-    rt = RT(w.n, w.groups, precision="fp32c")
-    rt.rt_build_cells(dev(w.x))
-    with pytest.raises(RTError):
-        rt.rt_time_bins(2)
+@pytest.fixture(scope="module")
+def case32(case):
+    w, geo, srcs, _, p = case
+    rt = RT(w.n, w.groups, precision="fp32c", cfl=w.cfl, c_red=w.c_red)
+    perm, *_ = rt.rt_build_cells(dev(w.x), dev(geo.h))
+    rt.rt_set_sources(dev(w.xs))
+    rt.rt_sync()
+    assert np.array_equal(perm.cpu().numpy(), p)
+    return rt
+
+
+def gpu_ticks32(rt, w, p, ticks):
+    U = dev(w.U0[p]).float()
+    L = dev(w.L)
+    UD = rt.rt_gradient(U)
+    acc = torch.zeros(U.shape, dtype=torch.float64, device="cuda")
+    Q = torch.zeros(w.groups, dtype=torch.float64, device="cuda")
+    ledger = torch.zeros(w.groups, dtype=torch.float64, device="cuda")
+    for t in range(ticks):
+        rt.rt_tick(U, L, t, UD, acc, photon_total=Q, ledger=ledger)
+    rt.rt_sync()
+    return U, acc, Q, ledger
+
+
+@pytest.mark.parametrize("variant", ["glf", "hll", "ivanova"])
+def test_fp32c_against_oracle(case, case32, variant):
+    """Individual time bins in an FP32C context against the FP64 oracle's binned
+    scheme: two cycles and a mid-cycle state, at the FP32C bar (1e-5 of each
+    neighbourhood's scale; pending sums against V times the state scale)."""
+    w, geo, srcs, _, p = case
+    rt = case32
+    tab = oracle.hll_table() if variant == "hll" else None
+    rt.rt_set_riemann("hll" if variant == "hll" else "glf")
+    rt.rt_set_surfaces("ivanova" if variant == "ivanova" else "hopkins")
+    try:
+        bins, cycle = rt.rt_time_bins(MAX_BIN)
+        ob = oracle.time_bins(geo, MAX_BIN)
+        assert np.array_equal(unsort(bins.cpu().numpy(), p), ob)
+        for ticks in (2 * cycle, cycle + cycle // 2 + 1):
+            U, acc, Q, _ = gpu_ticks32(rt, w, p, ticks)
+            ref, info = oracle.run_binned(geo, srcs, w.U0, w.L, ticks, ob, hll=tab,
+                                          ivanova=variant == "ivanova")
+            err = local_err(unsort(U.double().cpu().numpy(), p), ref, geo.sptr, geo.sidx)
+            scale = np.abs(ref).max() * geo.V.max()
+            aerr = float(np.abs(unsort(acc.cpu().numpy(), p) - info["acc"]).max() / scale)
+            log(f"FP32C {variant} {ticks} ticks: max err {err:.2e} of the neighbourhood scale, "
+                f"pending sums {aerr:.2e}")
+            assert err < 1e-5 and aerr < 1e-5
+            assert np.allclose(Q.cpu().numpy(), oracle.photon_total(geo, ref), rtol=1e-6, atol=0)
+    finally:
+        rt.rt_set_riemann("glf")
+        rt.rt_set_surfaces("hopkins")
+
+
+def test_fp32c_budget_with_pending_sums_every_tick(case, case32):
+    w, geo, srcs, _, p = case
+    rt = case32
+    bins, cycle = rt.rt_time_bins(3)
+    U = dev(w.U0[p]).float()
+    L = dev(w.L)
+    UD = rt.rt_gradient(U)
+    acc = torch.zeros(U.shape, dtype=torch.float64, device="cuda")
+    Q = torch.zeros(w.groups, dtype=torch.float64, device="cuda")
+    ledger = torch.zeros(w.groups, dtype=torch.float64, device="cuda")
+    Q0 = rt.rt_photon_total(U).cpu().numpy()
+    dt = float(rt.dt.item())
+    worst = 0.0
+    for t in range(2 * cycle):
+        rt.rt_tick(U, L, t, UD, acc, photon_total=Q, ledger=ledger)
+        lhs = Q.cpu().numpy() - acc[:, :, 0].sum(dim=0).cpu().numpy()
+        rhs = Q0 + (t + 1) * dt * w.L.sum(axis=0) + ledger.cpu().numpy()
+        worst = max(worst, float(np.abs(lhs / rhs - 1).max()))
+    log(f"FP32C budget with pending sums over {2 * cycle} ticks: worst {worst:.2e}")
+    assert worst < 1e-6
