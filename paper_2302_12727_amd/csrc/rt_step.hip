@@ -537,12 +537,15 @@ constexpr int transport_slice(int G) {
     return G <= 3 ? G : (G % 2 == 0 ? 2 : (G % 3 == 0 ? 3 : 1));
 }
 // The HLL solver holds about 10 more registers per group in flight (the wave
-// speeds of both face states), so 3 groups per wave no longer fit: odd G runs
-// one group per wave.
+// speeds of both face states).  With the particle's own state in LDS (OWNL)
+// all groups fit one wave up to G = 3 (256 VGPRs, no spill), measured 15%
+// faster on the 3-group 128^3 lattice than one group per wave at 3 waves per
+// SIMD (6.2 against 7.3 ms); larger odd G runs one group per wave, held in
+// registers at 3 waves per SIMD.
 #ifndef RT_HLL_GW
 #define RT_HLL_GW 0
 #endif
-constexpr int hll_slice(int G) { return G <= 2 ? G : (G % 2 == 0 ? 2 : 1); }
+constexpr int hll_slice(int G) { return G <= 3 ? G : (G % 2 == 0 ? 2 : 1); }
 
 // Lanes per particle of the FP64 transport (1, 2 or 4): with Q > 1 a wave
 // covers 64/Q particles whose neighbour lists overlap more, so the records
@@ -566,7 +569,8 @@ void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double 
     const double2 *tab = (const double2 *)ctx->hll_table;
     const bool iva = ctx->surfaces == RT_IVANOVA;
 #define RT_TRANSPORT_LAUNCH(W, HLL_, IVA_)                                                    \
-    k_transport64<G, W, false, HLL_, IVA_, kQ, kOwnL && !HLL_, kPipe && !HLL_>                \
+    k_transport64<G, W, false, HLL_, IVA_, kQ, kOwnL && (!HLL_ || W > 1),                     \
+                  kPipe && (!HLL_ || W > 1)>                                                  \
         <<<(unsigned)xcd_grid(nb * (G / W)), kBlock, 0, ctx->stream>>>(                       \
         n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,          \
         ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, 0, nullptr, tab,      \
@@ -607,7 +611,8 @@ void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, d
     const double2 *tab = (const double2 *)ctx->hll_table;
     const bool iva = ctx->surfaces == RT_IVANOVA;
 #define RT_TICK_LAUNCH(W, HLL_, IVA_)                                                          \
-    k_transport64<G, W, true, HLL_, IVA_, kQ, kOwnL && !HLL_, kPipe && !HLL_>                  \
+    k_transport64<G, W, true, HLL_, IVA_, kQ, kOwnL && (!HLL_ || W > 1),                      \
+                  kPipe && (!HLL_ || W > 1)>                                                  \
         <<<(unsigned)xcd_grid(nt * (G / W)), kBlock, 0, ctx->stream>>>(                        \
             n, nt, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,       \
             ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, tick, accm, tab, \
