@@ -105,6 +105,11 @@ __global__ void k_merge_level(int64_t first, int64_t count, double *__restrict__
     hmax[v] = fmax(hmax[a], hmax[b]);
 }
 
+// Candidate-list capacity of the smoothing-length solve (entries per
+// particle) and the most device memory the lists may take.
+constexpr int kHList = 128;
+constexpr int64_t kHListBytes = int64_t(16) << 30;
+
 struct Tree {
     const double *lo, *hi, *hmax;
     int64_t P;
@@ -113,14 +118,20 @@ struct Tree {
 // ---------------------------------------------------------------------------
 // Smoothing length: root of g(h) = h^3 sum_j W(r_j, kappa h) - eta^3
 // (eq:number-of-neighbors), i.e. (sigma/kappa^3) sum_j w(r_j / (kappa h)) = eta^3,
-// by Newton-Raphson safeguarded with bisection.  Each evaluation of g and
-// dg/dh walks the tree with radius kappa h.
-__device__ void h_eval(const Tree &T, const double *__restrict__ xs, int64_t n, double px,
-                       double py, double pz, double h, double kappa, double box, double ibox,
-                       double &sw, double &sdw) {
+// by Newton-Raphson safeguarded with bisection.  An evaluation of g and dg/dh
+// either walks the tree with radius kappa h or reads the particle's candidate
+// list: the r^2 < (kappa h_l)^2 of the last walk, at h_l >= h, in walk order
+// (entry k of particle i at list[k n + i]).  A walk at the smaller radius
+// opens a subset of the same nodes in the same order, and a particle of a node
+// it skips lies beyond kappa h, so both routes sum the same terms in the same
+// order and give the same bits.  A particle whose list would overflow walks.
+__device__ int h_eval(const Tree &T, const double *__restrict__ xs, int64_t n, double px,
+                      double py, double pz, double h, double kappa, double box, double ibox,
+                      double *__restrict__ list, int cap, double &sw, double &sdw) {
     const double H = kappa * h, H2 = H * H, iH = 1.0 / H;
     const double acc2 = H2 * (1.0 + 1e-12);
     double a = 0.0, b = 0.0;
+    int cnt = 0;
     traverse(
         T.P,
         [&](int64_t v) { return box_dist2(T.lo + 3 * v, T.hi + 3 * v, px, py, pz, box) < acc2; },
@@ -132,6 +143,8 @@ __device__ void h_eval(const Tree &T, const double *__restrict__ xs, int64_t n, 
                 double sz = min_image(xs[3 * j + 2] - pz, box, ibox);
                 double r2 = sx * sx + sy * sy + sz * sz;
                 if (r2 < H2) {
+                    if (cnt < cap) list[(int64_t)cnt * n] = r2;
+                    ++cnt;
                     double q = sqrt(r2) * iH;
                     a += kern_w(q);
                     b += kern_dw(q) * q;
@@ -140,26 +153,48 @@ __device__ void h_eval(const Tree &T, const double *__restrict__ xs, int64_t n, 
         });
     sw = a;
     sdw = b;
+    return cnt;
+}
+
+__device__ void h_eval_list(const double *__restrict__ list, int64_t n, int cnt, double h,
+                            double kappa, double &sw, double &sdw) {
+    const double H = kappa * h, H2 = H * H, iH = 1.0 / H;
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < cnt; ++k) {
+        const double r2 = list[(int64_t)k * n];
+        if (r2 < H2) {
+            double q = sqrt(r2) * iH;
+            a += kern_w(q);
+            b += kern_dw(q) * q;
+        }
+    }
+    sw = a;
+    sdw = b;
 }
 
 __device__ double h_solve_point(const Tree &T, const double *__restrict__ xs, int64_t n,
                                 double px, double py, double pz, double h0, double eta,
-                                double kappa, double box, double hcap, int32_t &iters,
-                                int32_t &flags) {
+                                double kappa, double box, double hcap, double *__restrict__ list,
+                                int cap, int32_t &iters, int32_t &flags) {
     const double pref = kSigma3 / (kappa * kappa * kappa);
     const double eta3 = eta * eta * eta;
     const double eps4 = 4.0 * 2.220446049250313e-16;
     const double ibox = 1.0 / box;
-    double lo = 0.0, hi = INFINITY, h = h0;
+    // iterates stay at or below hcap (compact support at most half the box);
+    // a root beyond it is an error
+    double lo = 0.0, hi = INFINITY, h = fmin(h0, hcap);
+    double hl = 0.0;     // the list holds the walk at hl (0: no list)
+    int lcnt = 0;
     int32_t it = 0;
-    bool ok = false;
+    bool ok = false, big = false;
     for (it = 0; it < 200; ++it) {
-        if (h > hcap) {      // compact support would exceed half the box
-            flags |= ST_BIGH;
-            break;
-        }
         double sw, sdw;
-        h_eval(T, xs, n, px, py, pz, h, kappa, box, ibox, sw, sdw);
+        if (h <= hl) {
+            h_eval_list(list, n, lcnt, h, kappa, sw, sdw);
+        } else {
+            lcnt = h_eval(T, xs, n, px, py, pz, h, kappa, box, ibox, list, cap, sw, sdw);
+            hl = lcnt <= cap ? h : 0.0;
+        }
         double g = pref * sw - eta3;
         double dg = -pref * sdw / h;
         if (g == 0.0) {
@@ -169,13 +204,26 @@ __device__ double h_solve_point(const Tree &T, const double *__restrict__ xs, in
         if (g < 0.0) lo = h; else hi = h;
         double hn;
         if (hi == INFINITY) {
+            if (h >= hcap) {                     // g < 0 at the cap
+                big = true;
+                break;
+            }
             hn = 2.0 * h;                        // expand until bracketed
             if (dg > 0.0) {
                 double nt = h - g / dg;
                 if (nt > h && nt < 4.0 * h) hn = nt;
             }
+            hn = fmin(hn, hcap);
         } else {
+            // the step test comes before the bracket test: a Newton step that
+            // rounds to h itself lands on a bracket end and would otherwise be
+            // replaced by a bisection from a far end
             hn = (dg > 0.0) ? h - g / dg : -1.0;
+            if (dg > 0.0 && fabs(hn - h) <= eps4 * h) {
+                h = hn;
+                ok = true;
+                break;
+            }
             if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
             if (fabs(hn - h) <= eps4 * h || hi - lo <= eps4 * hi) {
                 h = hn;
@@ -186,13 +234,24 @@ __device__ double h_solve_point(const Tree &T, const double *__restrict__ xs, in
         h = hn;
     }
     iters = it;
-    if (!ok) flags |= ST_NOCONV;
+    if (big) flags |= ST_BIGH;
+    else if (!ok) flags |= ST_NOCONV;
     return h;
 }
 
+// Starting point of the solve: the smaller of two density estimates (a walk
+// costs about its radius cubed, so starting low is cheap and starting high is
+// not):
+//  - the particles per volume of the particle's leaf box (on a lattice about
+//    0.7 of the root);
+//  - from the fourth-nearest of the kGuessWin particles on either side in
+//    Morton order, which bounds from above the distance to the fourth-nearest
+//    particle, scaled by 0.8.  It stays local where a leaf straddles regions
+//    of very different density and the leaf box overestimates h up to 35-fold.
+constexpr int kGuessWin = 16;
 __global__ void k_h_guess(int64_t n, int64_t P, const double *__restrict__ lo,
-                          const double *__restrict__ hi, double eta, double box,
-                          double *__restrict__ h) {
+                          const double *__restrict__ hi, const double *__restrict__ xs,
+                          double eta, double box, double *__restrict__ h) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t l = i / kLeaf, v = P + l;
@@ -202,18 +261,40 @@ __global__ void k_h_guess(int64_t n, int64_t P, const double *__restrict__ lo,
 #pragma unroll
     for (int a = 0; a < 3; ++a) ext *= fmax(hi[3 * v + a] - lo[3 * v + a], floor_ext);
     double g = eta * cbrt(ext / (double)cnt);
-    h[i] = fmin(g, 0.25 * box);
+    // four smallest r^2 in the Morton window, ascending
+    const double ibox = 1.0 / box;
+    const double px = xs[3 * i], py = xs[3 * i + 1], pz = xs[3 * i + 2];
+    double d0 = INFINITY, d1 = INFINITY, d2 = INFINITY, d3 = INFINITY;
+    const int64_t j0 = max((int64_t)0, i - kGuessWin), j1 = min(n, i + kGuessWin + 1);
+    for (int64_t j = j0; j < j1; ++j) {
+        if (j == i) continue;
+        double sx = min_image(xs[3 * j] - px, box, ibox);
+        double sy = min_image(xs[3 * j + 1] - py, box, ibox);
+        double sz = min_image(xs[3 * j + 2] - pz, box, ibox);
+        double r2 = sx * sx + sy * sy + sz * sz;
+        if (r2 < d3) {
+            d3 = r2;
+            if (d3 < d2) { double t = d2; d2 = d3; d3 = t; }
+            if (d2 < d1) { double t = d1; d1 = d2; d2 = t; }
+            if (d1 < d0) { double t = d0; d0 = d1; d1 = t; }
+        }
+    }
+    // n_local = 5 / ((4 pi / 3) r4^3)  ->  h = eta n_local^(-1/3)
+    const double gm = eta * sqrt(d3) * 0.94269861348;      // cbrt((4 pi / 3) / 5)
+    h[i] = fmin(fmin(g, 0.8 * gm), 0.25 * box);
 }
 
 __global__ void k_h_solve(int64_t n, Tree T, const double *__restrict__ xs, double eta,
                           double kappa, double box, double *__restrict__ h,
-                          int32_t *__restrict__ iters, int32_t *__restrict__ status) {
+                          double *__restrict__ list, int cap, int32_t *__restrict__ iters,
+                          int32_t *__restrict__ status) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int32_t it = 0, fl = 0;
     double hcap = 0.5 * box / kappa;
     double hv = h_solve_point(T, xs, n, xs[3 * i], xs[3 * i + 1], xs[3 * i + 2],
-                              fmin(h[i], 0.5 * hcap), eta, kappa, box, hcap, it, fl);
+                              fmin(h[i], 0.5 * hcap), eta, kappa, box, hcap,
+                              cap > 0 ? list + i : nullptr, cap, it, fl);
     h[i] = hv;
     iters[i] = it;
     if (fl) atomicOr(status, fl);
@@ -422,7 +503,7 @@ __global__ void k_src_h(int32_t S, Tree T, const double *__restrict__ xs, int64_
     int32_t it = 0, fl = 0;
     double hcap = 0.5 * box / kappa;
     src_h[s] = h_solve_point(T, xs, n, src_x[3 * s], src_x[3 * s + 1], src_x[3 * s + 2], h0,
-                             eta, kappa, box, hcap, it, fl);
+                             eta, kappa, box, hcap, nullptr, 0, it, fl);
     if (fl) atomicOr(status, fl);
 }
 
@@ -576,10 +657,28 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
         RT_HIP(hipMemsetAsync(ctx->status, 0, sizeof(int32_t), st));
         RT_HIP(hipMemsetAsync(ctx->h_iters, 0, sizeof(int32_t) * n, st));
         if (!h_in) {
+            // candidate lists of kHList entries per particle while they fit in
+            // kHListBytes (else every evaluation walks the tree)
+            int cap = (int)std::min<int64_t>(kHList, kHListBytes / (8 * n));
+            double *hlist = nullptr;
+            if (cap < kHList / 2 || hipMalloc((void **)&hlist, sizeof(double) * cap * n) != hipSuccess) {
+                (void)hipGetLastError();
+                hlist = nullptr;
+                cap = 0;
+            }
             k_h_guess<<<nblk(n), kBlock, 0, st>>>(n, ctx->P, ctx->node_lo, ctx->node_hi,
-                                                  ctx->p.eta, ctx->p.box, h);
+                                                  ctx->xs, ctx->p.eta, ctx->p.box, h);
             k_h_solve<<<nblk(n), kBlock, 0, st>>>(n, T, ctx->xs, ctx->p.eta, ctx->p.kappa,
-                                                  ctx->p.box, h, ctx->h_iters, ctx->status);
+                                                  ctx->p.box, h, hlist, cap, ctx->h_iters,
+                                                  ctx->status);
+            if (hlist) {
+                const hipError_t e = hipStreamSynchronize(st);
+                rt_free(hlist);
+                if (e != hipSuccess) {
+                    rs = rt_fail(ctx, RT_EHIP, std::string("smoothing-length solve: ") + hipGetErrorString(e));
+                    goto fail;
+                }
+            }
         }
         k_scale<<<nblk(n), kBlock, 0, st>>>(n, h, ctx->p.kappa, Htmp);
         int32_t stw = 0;
