@@ -26,13 +26,21 @@ namespace {
 
 inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
-// Waves per SIMD the HLL pair pass is held to.  At 2 it spills about 30
-// registers, at 1 it keeps them (in accumulation registers); on the 3-group
-// 128^3 lattice the backward of 20 steps took 496 ms at 2 and 577 ms at 1.
+// Waves per SIMD the HLL pair pass is held to.  With its own state in
+// registers it spilled about 30 at 2 waves and none at 1 (in accumulation
+// registers); on the 3-group 128^3 lattice the backward of 20 steps took 496
+// ms at 2 and 577 ms at 1.  With the own state in LDS it fits 256 registers
+// at 2 waves without spills: 410 ms.
 #ifndef RT_ADJ_HLL_WAVES
 #define RT_ADJ_HLL_WAVES 2
 #endif
 constexpr int kAdjHllWaves = RT_ADJ_HLL_WAVES;
+// The HLL pair pass keeps the own state, gradients and cotangent in LDS
+// rather than in registers (21 doubles per particle, 45.5 KB per block).
+#ifndef RT_ADJ_HLL_OWN
+#define RT_ADJ_HLL_OWN 1
+#endif
+constexpr bool kAdjHllOwn = RT_ADJ_HLL_OWN != 0;
 
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_adj_guard64(int64_t n, const double *__restrict__ Uung,
@@ -66,7 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_guard64(int64_t n, const double 
 //
 // IVA: the Ivanova surfaces (eq:IvanovaAij) in the recomputed pair geometry;
 // they are static, so the pull-back is otherwise the same.
-template <int G, int GW, int Q = 1, bool HLL = false, bool IVA = false>
+template <int G, int GW, int Q = 1, bool HLL = false, bool IVA = false, bool OWNL = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(HLL ? kAdjHllWaves : 1)))
 void k_adj_pair64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
@@ -77,7 +85,9 @@ void k_adj_pair64(
     static_assert(G % GW == 0, "group slices must tile the groups");
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     constexpr int NS = G / GW, NQ = 4 * GW, PW = 64 / Q, PB = kBlock / Q;
+    constexpr int OS = 20 * GW + 1;             // OWNL: (U, D, lam'') per group in LDS
     __shared__ double stage[kBlock / 64][64 * kStage];
+    __shared__ double own[OWNL ? PB * OS : 1];
     const int64_t bg = xcd_block(nb * NS);
     if (bg >= nb * NS) return;
     const int64_t blk = bg / NS;
@@ -103,19 +113,43 @@ void k_adj_pair64(
         gk[1] = ivan[4 * ic + 1];
         gk[2] = ivan[4 * ic + 2];
     }
-    double Ui[NQ], Di[NQ * 3], Li[NQ];
+    double Ui[OWNL ? 1 : NQ], Di[OWNL ? 1 : NQ * 3], Li[OWNL ? 1 : NQ];
+    double *ow = own + (OWNL ? (threadIdx.x / Q) * OS : 0);
+    if constexpr (OWNL) {
+        // per group: the 16 values of the gradient record, then lam''
 #pragma unroll
-    for (int g = 0; g < GW; ++g) {
-        const double *r = UD + (ic * G + g0 + g) * 16;
+        for (int e = sub; e < 20 * GW; e += Q) {
+            const int g = e / 20, f = e - 20 * g;
+            ow[e] = f < 16 ? UD[(ic * G + g0 + g) * 16 + f] : lam2[(ic * G + g0 + g) * 4 + f - 16];
+        }
+        wave_lds_sync();
+    } else {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            Ui[4 * g + m] = r[m];
-            Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
-            Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
-            Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
-            Li[4 * g + m] = lam2[(ic * G + g0 + g) * 4 + m];
+        for (int g = 0; g < GW; ++g) {
+            const double *r = UD + (ic * G + g0 + g) * 16;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                Ui[4 * g + m] = r[m];
+                Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
+                Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
+                Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
+                Li[4 * g + m] = lam2[(ic * G + g0 + g) * 4 + m];
+            }
         }
     }
+    // q = 4 g + m: own state, gradient component a, cotangent
+    auto ui = [&](int q) -> double {
+        if constexpr (OWNL) return ow[20 * (q >> 2) + (q & 3)];
+        else return Ui[q];
+    };
+    auto di = [&](int q, int a) -> double {
+        if constexpr (OWNL) return ow[20 * (q >> 2) + 4 + 3 * (q & 3) + a];
+        else return Di[3 * q + a];
+    };
+    auto li = [&](int q) -> double {
+        if constexpr (OWNL) return ow[20 * (q >> 2) + 16 + (q & 3)];
+        else return Li[q];
+    };
     double aU[NQ], aD[NQ * 3];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) aU[q] = aD[3 * q] = aD[3 * q + 1] = aD[3 * q + 2] = 0.0;
@@ -173,11 +207,11 @@ void k_adj_pair64(
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const int q = 4 * g + m;
-                    const double dk = Di[3 * q] * pg.sx + Di[3 * q + 1] * pg.sy + Di[3 * q + 2] * pg.sz;
+                    const double dk = di(q, 0) * pg.sx + di(q, 1) * pg.sy + di(q, 2) * pg.sz;
                     const double dl = Rl[4 + 3 * m] * pg.sx + Rl[5 + 3 * m] * pg.sy + Rl[6 + 3 * m] * pg.sz;
                     const double mm = minmod(dk, dl);
                     own_slope[m] = (dk * dl > 0.0) && (fabs(dk) <= fabs(dl));
-                    qLp[m] = qL[m] = Ui[q] + pg.fk * mm;
+                    qLp[m] = qL[m] = ui(q) + pg.fk * mm;
                     qRp[m] = qR[m] = Rl[m] - pg.fl * mm;
                 }
                 guard64(qL[0], qL[1], qL[2], qL[3], c);
@@ -185,9 +219,12 @@ void k_adj_pair64(
                 // cotangent of P_kl and its pull-back to the face states
                 double nu[4], tL[4], tR[4];
 #pragma unroll
-                for (int m = 0; m < 4; ++m) nu[m] = 0.5 * (dtVl * Ll[m] - dtVk * Li[4 * g + m]);
-                m1_flux64_vjp(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, nu, tL);
-                m1_flux64_vjp(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, nu, tR);
+                for (int m = 0; m < 4; ++m) nu[m] = 0.5 * (dtVl * Ll[m] - dtVk * li(4 * g + m));
+                double S1 = 0.0, S2 = 0.0;   // HLL: m . F_L, m . F_R
+                m1_flux64_vjp(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, nu, tL,
+                              HLL ? &S1 : nullptr);
+                m1_flux64_vjp(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, nu, tR,
+                              HLL ? &S2 : nullptr);
                 if constexpr (HLL) {
                     const double iAn = pg.An > 0.0 ? rcp64(pg.An) : 0.0;
                     double loL, hiL, loR, hiR, w1, w2, w3;
@@ -196,14 +233,9 @@ void k_adj_pair64(
                     hll_speeds64(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, iAn, c, hll, loR,
                                  hiR);
                     hll_weights(loL, hiL, loR, hiR, pg.An, w1, w2, w3);
-                    double FL[4], FR[4];
-                    m1_flux64(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, FL);
-                    m1_flux64(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, FR);
-                    double S1 = 0.0, S2 = 0.0, S3 = 0.0;   // m . (F_L, F_R, U_R - U_L)
+                    double S3 = 0.0;                       // m . (U_R - U_L)
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
-                        S1 += nu[m] * FL[m];
-                        S2 += nu[m] * FR[m];
                         S3 += nu[m] * (qR[m] - qL[m]);
                         tL[m] = 2.0 * (w1 * tL[m] - w3 * nu[m]);
                         tR[m] = 2.0 * (w2 * tR[m] + w3 * nu[m]);
@@ -261,7 +293,7 @@ void k_adj_pair64(
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int q = 4 * g + m;
-            o[m] = Li[q] + aU[q];
+            o[m] = li(q) + aU[q];
             o[4 + 3 * m + 0] = b00 * aD[3 * q] + b01 * aD[3 * q + 1] + b02 * aD[3 * q + 2];
             o[4 + 3 * m + 1] = b01 * aD[3 * q] + b11 * aD[3 * q + 1] + b12 * aD[3 * q + 2];
             o[4 + 3 * m + 2] = b02 * aD[3 * q] + b12 * aD[3 * q + 1] + b22 * aD[3 * q + 2];
@@ -446,7 +478,7 @@ void launch_adjoint64(rt_ctx *ctx, const double *UD, const double *Uung, const d
     const double2 *tab = (const double2 *)ctx->hll_table;
     const bool iva = ctx->surfaces == RT_IVANOVA;
 #define RT_ADJ_PAIR_LAUNCH(HLL_, IVA_)                                                          \
-    k_adj_pair64<G, GW, kAQ, HLL_, IVA_><<<(unsigned)xcd_grid(np * (G / GW)), kBlock, 0, st>>>( \
+    k_adj_pair64<G, GW, kAQ, HLL_, IVA_, (HLL_ && kAdjHllOwn)><<<(unsigned)xcd_grid(np * (G / GW)), kBlock, 0, st>>>( \
         n, np, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt, ctx->p.c_red,      \
         ctx->p.box, R, tab, ctx->ivan)
     if (ctx->solver == RT_HLL) {

@@ -372,9 +372,10 @@ __device__ __forceinline__ void guard64_vjp(const double q[4], double lam[4], do
 //   d/dE = alpha c^2/3 + K dD/dE
 //   d/dF = (nu0 + 3 c beta/D) A + 3 c (F.A)/D nu_v - (2 c alpha/D + 3 K/R) F
 // (at E = 0, where F = 0, 1/D and 1/R are replaced by 0: the one-sided limit).
+// nuF, if given, receives nu . flux = nu0 (F.A) + a alpha + b beta.
 __device__ __forceinline__ void m1_flux64_vjp(double E, double Fx, double Fy, double Fz, double Ax,
                                               double Ay, double Az, double c, const double nu[4],
-                                              double out[4]) {
+                                              double out[4], double *nuF = nullptr) {
     const double FA = Fx * Ax + Fy * Ay + Fz * Az;
     const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
     const double cE = c * E;
@@ -392,6 +393,10 @@ __device__ __forceinline__ void m1_flux64_vjp(double E, double Fx, double Fy, do
     out[1] = cA * Ax + cn * nu[1] - cF * Fx;
     out[2] = cA * Ay + cn * nu[2] - cF * Fy;
     out[3] = cA * Az + cn * nu[3] - cF * Fz;
+    if (nuF) {
+        const double a = c * __builtin_fma(-F2, iD, cE * (1.0 / 3.0));
+        *nuF = __builtin_fma(nu[0], FA, __builtin_fma(a, al, cn * be));
+    }
 }
 
 }  // namespace
