@@ -158,6 +158,11 @@ def test_plummer_mid():
     srcs = oracle.build_sources(geo, w.xs)
     rt, p = gpu_case(w)
     assert np.abs(unsort(rt.h.cpu().numpy(), p) / geo.h - 1).max() < 1e-13
+    # the Newton iteration ends within a few steps for every particle (a
+    # converged step must not fall back to bisecting the whole bracket)
+    it_max = rt.rt_get_stats()["h_iter_max"]
+    log(f"plummer smoothing-length iterations: max {it_max}")
+    assert it_max <= 16
     nn = unsort(rt.rt_get_geometry()[1].cpu().numpy(), p)
     assert np.array_equal(nn, np.diff(geo.sptr))
     ref_U, _ = oracle.run(geo, srcs, w.U0, w.L, 2)
@@ -192,3 +197,15 @@ def test_conservation_without_guards():
     _, Q, counts, _ = run_gpu(rt, p, w, 5)
     assert counts.sum() == 0
     assert abs(Q[0] - Q0) <= 1e-13 * Q0
+
+
+def test_support_beyond_half_box_is_refused():
+    """27 particles in the unit box: the root h of the neighbour-number
+    equation puts the compact support beyond half the box, which the build
+    refuses (the iterates themselves stop at the cap)."""
+    from paper_2302_12727_amd.rt import RTError
+    rng = np.random.default_rng(7)
+    x = rng.random((27, 3))
+    rt = RT(27, 1)
+    with pytest.raises(RTError, match="RT_EINVAL"):
+        rt.rt_build_cells(dev(x))
