@@ -495,24 +495,35 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
 }
 
 // part [nb][2G]: columns 0..G-1 photon totals, G..2G-1 ledger.  Q[g] = sum (written),
-// ledger[g] += sum.
-__global__ __launch_bounds__(kBlock) void k_finalize(int64_t nb, int G,
-                                                     const double *__restrict__ part,
+// ledger[g] += sum.  One block: thread t sums rows t, t + kBlock, ... of every
+// column (whole rows, so consecutive threads read consecutive rows), then the
+// 256 compensated partial sums of each column meet in a fixed tree.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_finalize(int64_t nb, const double *__restrict__ part,
                                                      double *__restrict__ Q,
                                                      double *__restrict__ ledger) {
+    constexpr int C = 2 * G;
     __shared__ double ss[kBlock], sc[kBlock];
-    for (int col = 0; col < 2 * G; ++col) {
-        double *dst = col < G ? Q : ledger;
-        if (!dst) continue;
-        double s = 0.0, e = 0.0;
-        for (int64_t b = threadIdx.x; b < nb; b += kBlock) {
+    double s[C], e[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) s[c] = e[c] = 0.0;
+#pragma unroll 4
+    for (int64_t b = threadIdx.x; b < nb; b += kBlock) {
+        const double *row = part + b * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
             double t, err;
-            two_sum(s, part[b * 2 * G + col], t, err);
-            s = t;
-            e += err;
+            two_sum(s[c], row[c], t, err);
+            s[c] = t;
+            e[c] += err;
         }
-        ss[threadIdx.x] = s;
-        sc[threadIdx.x] = e;
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        double *dst = c < G ? Q : ledger;
+        if (!dst) continue;
+        ss[threadIdx.x] = s[c];
+        sc[threadIdx.x] = e[c];
         __syncthreads();
         for (int w = kBlock / 2; w > 0; w >>= 1) {
             if (threadIdx.x < w) {
@@ -525,11 +536,16 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int64_t nb, int G,
         }
         if (threadIdx.x == 0) {
             double v = ss[0] + sc[0];
-            if (col < G) Q[col] = v;
-            else ledger[col - G] += v;
+            if (c < G) Q[c] = v;
+            else ledger[c - G] += v;
         }
         __syncthreads();
     }
+}
+
+template <int G>
+void launch_finalize(rt_ctx *ctx, int64_t nb, const double *part, double *Q, double *ledger) {
+    k_finalize<G><<<1, kBlock, 0, ctx->stream>>>(nb, part, Q, ledger);
 }
 
 // Groups per wave of the FP64 transport (0: the default slice below).  All
@@ -652,7 +668,7 @@ void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, d
 // Combine nb rows of ctx->partials into Q (columns 0..G-1, written) and
 // ledger (columns G..2G-1, accumulated); either may be NULL.
 void rt_finalize_partials(rt_ctx *ctx, int64_t nb, double *Q, double *ledger) {
-    k_finalize<<<1, kBlock, 0, ctx->stream>>>(nb, ctx->p.groups, ctx->partials, Q, ledger);
+    RT_DISPATCH_G(ctx->p.groups, launch_finalize, ctx, nb, ctx->partials, Q, ledger);
 }
 
 rt_status rt_ensure_partials(rt_ctx *ctx) {
@@ -712,7 +728,7 @@ rt_status rt_transport_impl(rt_ctx *ctx, const void *UD, const double *dt, void 
     rt_timer_end(ctx, "transport");
     RT_HIP(hipGetLastError());
     if (part) {
-        k_finalize<<<1, kBlock, 0, ctx->stream>>>(nb, ctx->p.groups, part, Q, ledger);
+        RT_DISPATCH_G(ctx->p.groups, launch_finalize, ctx, nb, part, Q, ledger);
         RT_HIP(hipGetLastError());
     }
     return RT_OK;
@@ -729,7 +745,7 @@ rt_status rt_tick_step_impl(rt_ctx *ctx, double *U, double *UD, const double *dt
     rt_timer_end(ctx, "tick");
     RT_HIP(hipGetLastError());
     if (part) {
-        k_finalize<<<1, kBlock, 0, ctx->stream>>>(nb, ctx->p.groups, part, Q, ledger);
+        RT_DISPATCH_G(ctx->p.groups, launch_finalize, ctx, nb, part, Q, ledger);
         RT_HIP(hipGetLastError());
     }
     return RT_OK;
@@ -743,7 +759,7 @@ rt_status rt_total_impl(rt_ctx *ctx, const void *U, double *Q) {
     else
         k_total_partials<float><<<(unsigned)nb, kBlock, 0, ctx->stream>>>(
             n, ctx->p.groups, ctx->geo, (const float *)U, ctx->partials);
-    k_finalize<<<1, kBlock, 0, ctx->stream>>>(nb, ctx->p.groups, ctx->partials, Q, nullptr);
+    RT_DISPATCH_G(ctx->p.groups, launch_finalize, ctx, nb, ctx->partials, Q, nullptr);
     RT_HIP(hipGetLastError());
     return RT_OK;
 }
