@@ -495,20 +495,40 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
 }
 
 // part [nb][2G]: columns 0..G-1 photon totals, G..2G-1 ledger.  Q[g] = sum (written),
-// ledger[g] += sum.  One block: thread t sums rows t, t + kBlock, ... of every
-// column (whole rows, so consecutive threads read consecutive rows), then the
-// 256 compensated partial sums of each column meet in a fixed tree.
+// ledger[g] += sum.  Two passes in a fixed order:
+//  1. block k of kFinBlocks takes the rows [k m, (k+1) m), m = ceil(nb / kFinBlocks):
+//     thread t sums rows t, t + kBlock, ... of it (whole rows, so consecutive
+//     threads read consecutive rows), one compensated sum per column, and the
+//     block's 256 sums of each column meet in a fixed tree;
+//  2. one block combines the kFinBlocks compensated sums of each column.
+constexpr int kFinBlocks = 32;
+
+// Fixed tree over the block of the compensated pairs (ss, sc); the result is
+// in ss[0] + sc[0].
+__device__ __forceinline__ void block_two_sum_tree(double *ss, double *sc) {
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            double t, err;
+            two_sum(ss[threadIdx.x], ss[threadIdx.x + w], t, err);
+            ss[threadIdx.x] = t;
+            sc[threadIdx.x] += sc[threadIdx.x + w] + err;
+        }
+        __syncthreads();
+    }
+}
+
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_finalize(int64_t nb, const double *__restrict__ part,
-                                                     double *__restrict__ Q,
-                                                     double *__restrict__ ledger) {
+__global__ __launch_bounds__(kBlock) void k_finalize_rows(int64_t nb, const double *__restrict__ part,
+                                                          double *__restrict__ fin) {
     constexpr int C = 2 * G;
     __shared__ double ss[kBlock], sc[kBlock];
+    const int64_t m = (nb + kFinBlocks - 1) / kFinBlocks;
+    const int64_t r0 = blockIdx.x * m, r1 = min(nb, r0 + m);
     double s[C], e[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) s[c] = e[c] = 0.0;
-#pragma unroll 4
-    for (int64_t b = threadIdx.x; b < nb; b += kBlock) {
+    for (int64_t b = r0 + threadIdx.x; b < r1; b += kBlock) {
         const double *row = part + b * C;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -520,20 +540,30 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int64_t nb, const double *_
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        double *dst = c < G ? Q : ledger;
-        if (!dst) continue;
         ss[threadIdx.x] = s[c];
         sc[threadIdx.x] = e[c];
-        __syncthreads();
-        for (int w = kBlock / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) {
-                double t, err;
-                two_sum(ss[threadIdx.x], ss[threadIdx.x + w], t, err);
-                ss[threadIdx.x] = t;
-                sc[threadIdx.x] += sc[threadIdx.x + w] + err;
-            }
-            __syncthreads();
+        block_two_sum_tree(ss, sc);
+        if (threadIdx.x == 0) {
+            fin[(blockIdx.x * C + c) * 2] = ss[0];
+            fin[(blockIdx.x * C + c) * 2 + 1] = sc[0];
         }
+        __syncthreads();
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ fin,
+                                                     double *__restrict__ Q,
+                                                     double *__restrict__ ledger) {
+    constexpr int C = 2 * G;
+    __shared__ double ss[kBlock], sc[kBlock];
+    for (int c = 0; c < C; ++c) {
+        double *dst = c < G ? Q : ledger;
+        if (!dst) continue;
+        const bool in = threadIdx.x < kFinBlocks;
+        ss[threadIdx.x] = in ? fin[(threadIdx.x * C + c) * 2] : 0.0;
+        sc[threadIdx.x] = in ? fin[(threadIdx.x * C + c) * 2 + 1] : 0.0;
+        block_two_sum_tree(ss, sc);
         if (threadIdx.x == 0) {
             double v = ss[0] + sc[0];
             if (c < G) Q[c] = v;
@@ -543,9 +573,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int64_t nb, const double *_
     }
 }
 
+// part is ctx->partials; the kFinBlocks x 2G compensated pairs of the first
+// pass go to the slack the buffer keeps after its rows.
 template <int G>
 void launch_finalize(rt_ctx *ctx, int64_t nb, const double *part, double *Q, double *ledger) {
-    k_finalize<G><<<1, kBlock, 0, ctx->stream>>>(nb, part, Q, ledger);
+    double *fin = ctx->partials + 2 * G * ctx->nblocks;
+    k_finalize_rows<G><<<kFinBlocks, kBlock, 0, ctx->stream>>>(nb, part, fin);
+    k_finalize<G><<<1, kBlock, 0, ctx->stream>>>(fin, Q, ledger);
 }
 
 // Groups per wave of the FP64 transport (0: the default slice below).  All
@@ -678,7 +712,9 @@ rt_status rt_ensure_partials(rt_ctx *ctx) {
     if (ctx->partials && ctx->nblocks >= nb) return RT_OK;
     rt_free(ctx->partials);
     ctx->partials = nullptr;
-    rt_status rs = rt_alloc(ctx, (void **)&ctx->partials, sizeof(double) * 2 * ctx->p.groups * nb);
+    // the rows, then the first pass of the finalize (kFinBlocks x 2G pairs)
+    rt_status rs = rt_alloc(ctx, (void **)&ctx->partials,
+                            sizeof(double) * 2 * ctx->p.groups * (nb + 2 * kFinBlocks));
     if (rs != RT_OK) return rs;
     ctx->nblocks = nb;
     return RT_OK;
