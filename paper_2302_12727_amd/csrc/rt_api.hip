@@ -113,7 +113,8 @@ void rt_destroy(rt_ctx *ctx) {
                     ctx->n_gath, ctx->wave_base, ctx->nbr, ctx->src_h, ctx->inj_gptr,
                     ctx->inj_gas, ctx->inj_src, ctx->inj_coef, ctx->inj_xi, ctx->src_ptr,
                     ctx->src_gas, ctx->src_coef, ctx->status, ctx->partials, ctx->scan_tmp,
-                    ctx->adj_buf, ctx->hll_table, ctx->hll_table32, ctx->vol, ctx->ivan};
+                    ctx->adj_buf, ctx->hll_table, ctx->hll_table32, ctx->vol, ctx->ivan,
+                    ctx->bin8};
     for (void *b : bufs) rt_free(b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;

@@ -56,7 +56,8 @@ __global__ void k_bins_limit(int64_t n, const int32_t *__restrict__ nbr,
 __global__ void k_bins_store(int64_t n, const int32_t *__restrict__ nbr,
                              const int64_t *__restrict__ wave_base,
                              const int32_t *__restrict__ n_nbr, const int32_t *__restrict__ bin,
-                             double *__restrict__ geo, float *__restrict__ geo32) {
+                             double *__restrict__ geo, float *__restrict__ geo32,
+                             uint8_t *__restrict__ bin8) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t base = wave_base[i >> 6] + (i & 63);
@@ -66,6 +67,7 @@ __global__ void k_bins_store(int64_t n, const int32_t *__restrict__ nbr,
     geo[(int64_t)kRec * i + 12] = (double)bin[i];
     geo[(int64_t)kRec * i + 13] = (double)m;
     if (geo32) geo32[(int64_t)F_REC * i + F_BIN] = (float)bin[i];
+    bin8[i] = (uint8_t)bin[i];
 }
 
 __global__ void k_bins_max(int64_t n, const int32_t *__restrict__ bin, int32_t *__restrict__ top) {
@@ -94,14 +96,18 @@ __global__ void k_inject_binned(int32_t ngas, int G, const int32_t *__restrict__
     }
 }
 
-// the stored state of the particles that ended a step follows their update
+// the stored state of the particles that ended a step follows their update;
+// the bins come from the compact copy (one byte per particle) once
+// rt_time_bins has run, else from the geometry records
 template <typename T>
-__global__ void k_refresh(int64_t n, int G, const double *__restrict__ geo, int64_t tick,
-                          const T *__restrict__ U, T *__restrict__ UD) {
+__global__ void k_refresh(int64_t n, int G, const uint8_t *__restrict__ bin8,
+                          const double *__restrict__ geo, int64_t tick, const T *__restrict__ U,
+                          T *__restrict__ UD) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * G) return;
     const int64_t i = t / G;
-    if (!ends_step(tick, (int32_t)geo[(int64_t)kRec * i + 12])) return;
+    const int32_t b = bin8 ? (int32_t)bin8[i] : (int32_t)geo[(int64_t)kRec * i + 12];
+    if (!ends_step(tick, b)) return;
 #pragma unroll
     for (int m = 0; m < 4; ++m) UD[t * 16 + m] = U[t * 4 + m];
 }
@@ -135,8 +141,12 @@ rt_status rt_time_bins_impl(rt_ctx *ctx, int32_t max_bin, int32_t *bins_out, int
         b2 = tmp;
         ++sweeps;
     }
+    if (!ctx->bin8 && (rs = rt_alloc(ctx, (void **)&ctx->bin8, (size_t)n)) != RT_OK) {
+        rt_free(work);
+        return rs;
+    }
     k_bins_store<<<nblk(n), kBlock, 0, st>>>(n, ctx->nbr, ctx->wave_base, ctx->n_nbr, b, ctx->geo,
-                                             ctx->geo32);
+                                             ctx->geo32, ctx->bin8);
     RT_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
     k_bins_max<<<nblk(n), kBlock, 0, st>>>(n, b, flag);
     int32_t top = 0;
@@ -173,11 +183,11 @@ rt_status rt_tick_impl(rt_ctx *ctx, void *U, const double *L, int64_t tick, void
                                              acc, Q, counts, ledger);
     if (rs != RT_OK) return rs;
     if (f64)
-        k_refresh<double><<<nblk(n * G), kBlock, 0, ctx->stream>>>(n, G, ctx->geo, tick,
+        k_refresh<double><<<nblk(n * G), kBlock, 0, ctx->stream>>>(n, G, ctx->bin8, ctx->geo, tick,
                                                                    (const double *)U,
                                                                    (double *)UD);
     else
-        k_refresh<float><<<nblk(n * G), kBlock, 0, ctx->stream>>>(n, G, ctx->geo, tick,
+        k_refresh<float><<<nblk(n * G), kBlock, 0, ctx->stream>>>(n, G, ctx->bin8, ctx->geo, tick,
                                                                   (const float *)U, (float *)UD);
     RT_HIP(hipGetLastError());
     return RT_OK;

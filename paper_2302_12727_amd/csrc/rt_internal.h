@@ -103,6 +103,7 @@ struct rt_ctx {
     int64_t device_bytes = 0;
     int32_t h_iter_max = 0;
     int32_t bin_top = -1;        // largest time bin after rt_time_bins (-1: none)
+    uint8_t *bin8 = nullptr;     // [n] time bins as set by rt_time_bins (0 after a build)
     int32_t solver = RT_GLF;     // Riemann solver of the transport
     double *hll_table = nullptr; // [RT_HLL_NF][RT_HLL_NMU][2] wave speeds / c
     float *hll_table32 = nullptr;// the same in FP32 (FP32C contexts)
