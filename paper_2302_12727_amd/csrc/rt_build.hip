@@ -108,6 +108,8 @@ __global__ void k_merge_level(int64_t first, int64_t count, double *__restrict__
 // Candidate-list capacity of the smoothing-length solve (entries per
 // particle) and the most device memory the lists may take.
 constexpr int kHList = 128;
+// Entries per particle of the neighbour lists the count pass keeps (same budget).
+constexpr int kNList = 128;
 constexpr int64_t kHListBytes = int64_t(16) << 30;
 
 struct Tree {
@@ -309,11 +311,17 @@ __global__ void k_scale(int64_t n, const double *__restrict__ a, double s, doubl
 // Neighbour lists N(i) = { j != i : r_ij < max(H_i, H_j) }: a pair exchanges
 // flux whenever one of the two kernels reaches the other particle (then
 // A_ij != 0).  The tree is opened when the node is within max(H_i, Hmax_node).
+// The count pass also keeps, while they fit in cap entries, the neighbours it
+// accepts in walk order (list[k n + i], a scatter neighbour with the sign bit
+// set); the fill pass then places them from that list, gather neighbours first,
+// in the order its own walk would, and walks only for the particles whose
+// list overflowed.
 template <bool FILL>
 __global__ void k_neighbours(int64_t n, Tree T, const double *__restrict__ xs,
                              const double *__restrict__ H, double box,
                              int32_t *__restrict__ n_nbr, int32_t *__restrict__ n_gath,
-                             const int64_t *__restrict__ wave_base, int32_t *__restrict__ nbr) {
+                             const int64_t *__restrict__ wave_base, int32_t *__restrict__ nbr,
+                             int32_t *__restrict__ list, int cap) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double ibox = 1.0 / box;
@@ -326,6 +334,20 @@ __global__ void k_neighbours(int64_t n, Tree T, const double *__restrict__ xs,
         base = wave_base[i >> 6] + (i & 63);
         gcount = n_gath[i];
         scount = n_nbr[i] - gcount;
+        if (gcount + scount <= cap) {
+            int32_t a = 0, b = 0;
+            for (int32_t k = 0; k < gcount + scount; ++k) {
+                const int32_t v = list[(int64_t)k * n + i];
+                if (v >= 0) {
+                    if (a < gcount) nbr[base + 64 * (int64_t)a] = v;
+                    ++a;
+                } else {
+                    if (b < scount) nbr[base + 64 * (int64_t)(gcount + b)] = v & 0x7fffffff;
+                    ++b;
+                }
+            }
+            return;
+        }
     }
     traverse(
         T.P,
@@ -346,9 +368,12 @@ __global__ void k_neighbours(int64_t n, Tree T, const double *__restrict__ xs,
                 // keep a lane inside its own column of the wave's slice
                 if (r2 < Hi2) {
                     if (FILL && cg < gcount) nbr[base + 64 * (int64_t)cg] = (int32_t)j;
+                    if (!FILL && cg + cs < cap) list[(int64_t)(cg + cs) * n + i] = (int32_t)j;
                     ++cg;
                 } else if (r2 < Hj * Hj) {
                     if (FILL && cs < scount) nbr[base + 64 * (int64_t)(gcount + cs)] = (int32_t)j;
+                    if (!FILL && cg + cs < cap)
+                        list[(int64_t)(cg + cs) * n + i] = (int32_t)j | INT32_MIN;
                     ++cs;
                 }
             }
@@ -607,6 +632,8 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
 
     uint64_t *keys_in = nullptr;
     int32_t *idx_in = nullptr;
+    int32_t *nlist = nullptr;   // neighbours of the count pass (see k_neighbours)
+    int ncap = 0;
     double *Htmp = nullptr, *dxpart = nullptr;
     int64_t *width = nullptr;
     void *sort_tmp = nullptr;
@@ -699,8 +726,15 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
             }
         }
         // neighbour table: counts, wave widths, offsets, fill
+        ncap = (int)std::min<int64_t>(kNList, kHListBytes / (4 * n));
+        if (ncap < kNList / 2 || hipMalloc((void **)&nlist, sizeof(int32_t) * ncap * n) != hipSuccess) {
+            (void)hipGetLastError();
+            nlist = nullptr;
+            ncap = 0;
+        }
         k_neighbours<false><<<nblk(n), kBlock, 0, st>>>(n, T, ctx->xs, Htmp, ctx->p.box,
-                                                        ctx->n_nbr, ctx->n_gath, nullptr, nullptr);
+                                                        ctx->n_nbr, ctx->n_gath, nullptr, nullptr,
+                                                        nlist, ncap);
         k_wave_width<<<nblk(ctx->nwaves + 1), kBlock, 0, st>>>(n, ctx->nwaves, ctx->n_nbr, width);
         size_t scan_bytes = 0;
         if (rocprim::exclusive_scan(nullptr, scan_bytes, width, ctx->wave_base,
@@ -728,7 +762,7 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
         RT_HIP(hipMemsetAsync(ctx->nbr, 0xff, sizeof(int32_t) * std::max<int64_t>(ctx->slots, 1), st));
         k_neighbours<true><<<nblk(n), kBlock, 0, st>>>(n, T, ctx->xs, Htmp, ctx->p.box,
                                                        ctx->n_nbr, ctx->n_gath, ctx->wave_base,
-                                                       ctx->nbr);
+                                                       ctx->nbr, nlist, ncap);
         // geometry records, volumes, time step
         RT_HIP(hipMemsetAsync(ctx->status, 0, sizeof(int32_t), st));
         k_geometry<<<nblk(n), kBlock, 0, st>>>(n, ctx->xs, h, ctx->p.kappa, ctx->p.box,
@@ -760,7 +794,7 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
         }
     }
     rt_free(keys_in); rt_free(idx_in); rt_free(Htmp); rt_free(width); rt_free(dxpart);
-    rt_free(sort_tmp);
+    rt_free(sort_tmp); rt_free(nlist);
     if ((rs = rt_ensure_partials(ctx)) != RT_OK) return rs;
     // compact copy of the volumes for the per-particle kernels that need
     // nothing else of the geometry record
@@ -774,7 +808,7 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
 fail:
     (void)hipStreamSynchronize(st);
     rt_free(keys_in); rt_free(idx_in); rt_free(Htmp); rt_free(width); rt_free(dxpart);
-    rt_free(sort_tmp);
+    rt_free(sort_tmp); rt_free(nlist);
     return rs;
 #undef ALLOC
 }
