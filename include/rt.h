@@ -28,9 +28,14 @@
  *    One group of one particle is one 128-byte line in FP64, so a neighbour's
  *    data is fetched in whole cache lines.
  *  - Errors: argument checks fail synchronously with RT_EINVAL and a message
- *    (rt_last_error).  Conditions found on the device (smoothing length not
- *    converged, singular E matrix, non-finite state) raise bits of a device
- *    status word that the next rt_sync turns into its return code.
+ *    (rt_last_error).  rt_build_cells and rt_set_sources report their own
+ *    device conditions (smoothing length not converged, singular E matrix)
+ *    in their return code.  The per-step kernels raise a bit of a device
+ *    status word instead: rt_gradient when a gradient record it writes holds
+ *    a NaN or an infinity (a non-finite input state), rt_transport and rt_tick
+ *    when an updated state does (before the post-update guard, which does not
+ *    catch NaN).  The next rt_sync turns the word into its return code and
+ *    clears it; the arrays are written all the same.
  *  - One context per stream; calls on a context are not re-entrant.
  */
 #ifndef GEARRT_RT_H
@@ -51,7 +56,8 @@ typedef enum {
     RT_EHIP = -3,       /* HIP runtime error                                 */
     RT_ENOCONV = -4,    /* smoothing length iteration did not converge       */
     RT_ESINGULAR = -5,  /* E_i not positive definite (coplanar neighbours)   */
-    RT_ESTATE = -6      /* call out of order (e.g. step before build)        */
+    RT_ESTATE = -6,     /* call out of order (e.g. step before build)        */
+    RT_ENONFINITE = -7  /* a state or gradient left the finite range (NaN/inf) */
 } rt_status;
 
 typedef enum { RT_FP64 = 0, RT_FP32C = 1 } rt_precision;
@@ -98,6 +104,15 @@ rt_status rt_set_stream(rt_ctx *ctx, void *hip_stream);
  * Errors: RT_ENOCONV, RT_ESINGULAR, RT_EINVAL (compact support >= box/2). */
 rt_status rt_build_cells(rt_ctx *ctx, const double *x, const double *h_in,
                          int64_t *perm, double *h, double *V, double *dt);
+
+/* Iteration cap of the smoothing-length solve of rt_build_cells and
+ * rt_set_sources (Part II "The neighbor search: determining the smoothing
+ * length"; the thesis fixes no tolerance or cap).  A particle whose
+ * Newton-Raphson/bisection iteration has not met the 4-ulp step test after
+ * max_iter evaluations makes the build return RT_ENOCONV.  Default 200
+ * (a C-level model of the iteration needs at most 8 on the synthetic sets);
+ * 1 .. 10000, else RT_EINVAL.  Applies to later builds. */
+rt_status rt_set_h_iterations(rt_ctx *ctx, int32_t max_iter);
 
 /* Point sources (Part III "First step: injection", "Weights for distribution
  * of energy density of a star onto particles").  xs [S][3] device positions.
@@ -317,8 +332,9 @@ rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const doub
                      const void *UD, const void *U_unguarded, const void *lam_next, void *lam,
                      double *dL_dL);
 
-/* Wait for the stream; return the first device-side error raised since the
- * last rt_sync (RT_ENOCONV, RT_ESINGULAR) or RT_OK, and clear it. */
+/* Wait for the stream; return the device-side error raised since the last
+ * rt_sync (RT_ENONFINITE, see the conventions above) or RT_OK, and clear the
+ * status word. */
 rt_status rt_sync(rt_ctx *ctx);
 
 /* ---- queries (synchronising; for tests and diagnostics) ---------------- */

@@ -138,6 +138,14 @@ rt_status rt_build_cells(rt_ctx *ctx, const double *x, const double *h_in, int64
     return rt_build_impl(ctx, x, h_in, perm, h, V, dt);
 }
 
+rt_status rt_set_h_iterations(rt_ctx *ctx, int32_t max_iter) {
+    if (!ctx) return RT_EINVAL;
+    if (max_iter < 1 || max_iter > 10000)
+        return rt_fail(ctx, RT_EINVAL, "max_iter must be in 1 .. 10000");
+    ctx->h_iter_cap = max_iter;
+    return RT_OK;
+}
+
 rt_status rt_set_sources(rt_ctx *ctx, int32_t n_src, const double *xs, double eta_star) {
     if (!ctx) return RT_EINVAL;
     if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
@@ -309,6 +317,8 @@ rt_status rt_sync(rt_ctx *ctx) {
     if (st & ST_NOCONV) return rt_fail(ctx, RT_ENOCONV, "smoothing length did not converge");
     if (st & ST_SINGULAR) return rt_fail(ctx, RT_ESINGULAR, "E_i not positive definite");
     if (st & ST_BIGH) return rt_fail(ctx, RT_EINVAL, "compact support reaches half the box");
+    if (st & ST_NONFINITE)
+        return rt_fail(ctx, RT_ENONFINITE, "a state or gradient record is NaN or infinite");
     return RT_OK;
 }
 

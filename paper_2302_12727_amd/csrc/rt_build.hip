@@ -177,7 +177,7 @@ __device__ void h_eval_list(const double *__restrict__ list, int64_t n, int cnt,
 __device__ double h_solve_point(const Tree &T, const double *__restrict__ xs, int64_t n,
                                 double px, double py, double pz, double h0, double eta,
                                 double kappa, double box, double hcap, double *__restrict__ list,
-                                int cap, int32_t &iters, int32_t &flags) {
+                                int cap, int32_t max_iter, int32_t &iters, int32_t &flags) {
     const double pref = kSigma3 / (kappa * kappa * kappa);
     const double eta3 = eta * eta * eta;
     const double eps4 = 4.0 * 2.220446049250313e-16;
@@ -189,7 +189,7 @@ __device__ double h_solve_point(const Tree &T, const double *__restrict__ xs, in
     int lcnt = 0;
     int32_t it = 0;
     bool ok = false, big = false;
-    for (it = 0; it < 200; ++it) {
+    for (it = 0; it < max_iter; ++it) {
         double sw, sdw;
         if (h <= hl) {
             h_eval_list(list, n, lcnt, h, kappa, sw, sdw);
@@ -288,15 +288,15 @@ __global__ void k_h_guess(int64_t n, int64_t P, const double *__restrict__ lo,
 
 __global__ void k_h_solve(int64_t n, Tree T, const double *__restrict__ xs, double eta,
                           double kappa, double box, double *__restrict__ h,
-                          double *__restrict__ list, int cap, int32_t *__restrict__ iters,
-                          int32_t *__restrict__ status) {
+                          double *__restrict__ list, int cap, int32_t max_iter,
+                          int32_t *__restrict__ iters, int32_t *__restrict__ status) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int32_t it = 0, fl = 0;
     double hcap = 0.5 * box / kappa;
     double hv = h_solve_point(T, xs, n, xs[3 * i], xs[3 * i + 1], xs[3 * i + 2],
                               fmin(h[i], 0.5 * hcap), eta, kappa, box, hcap,
-                              cap > 0 ? list + i : nullptr, cap, it, fl);
+                              cap > 0 ? list + i : nullptr, cap, max_iter, it, fl);
     h[i] = hv;
     iters[i] = it;
     if (fl) atomicOr(status, fl);
@@ -522,13 +522,14 @@ __global__ void k_copy_dt(const double *__restrict__ a, double *__restrict__ b) 
 //   xi_sg = mu_a psi_sg   (eq:isotropy-correction-with-zero).
 __global__ void k_src_h(int32_t S, Tree T, const double *__restrict__ xs, int64_t n,
                         const double *__restrict__ src_x, double eta, double kappa, double box,
-                        double h0, double *__restrict__ src_h, int32_t *__restrict__ status) {
+                        double h0, int32_t max_iter, double *__restrict__ src_h,
+                        int32_t *__restrict__ status) {
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
     int32_t it = 0, fl = 0;
     double hcap = 0.5 * box / kappa;
     src_h[s] = h_solve_point(T, xs, n, src_x[3 * s], src_x[3 * s + 1], src_x[3 * s + 2], h0,
-                             eta, kappa, box, hcap, nullptr, 0, it, fl);
+                             eta, kappa, box, hcap, nullptr, 0, max_iter, it, fl);
     if (fl) atomicOr(status, fl);
 }
 
@@ -696,8 +697,8 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
             k_h_guess<<<nblk(n), kBlock, 0, st>>>(n, ctx->P, ctx->node_lo, ctx->node_hi,
                                                   ctx->xs, ctx->p.eta, ctx->p.box, h);
             k_h_solve<<<nblk(n), kBlock, 0, st>>>(n, T, ctx->xs, ctx->p.eta, ctx->p.kappa,
-                                                  ctx->p.box, h, hlist, cap, ctx->h_iters,
-                                                  ctx->status);
+                                                  ctx->p.box, h, hlist, cap, ctx->h_iter_cap,
+                                                  ctx->h_iters, ctx->status);
             if (hlist) {
                 const hipError_t e = hipStreamSynchronize(st);
                 rt_free(hlist);
@@ -806,6 +807,9 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     if (ctx->bin8) RT_HIP(hipMemsetAsync(ctx->bin8, 0, (size_t)n, st));
     return RT_OK;
 fail:
+    // the conditions of the build are reported by its return code, not by a
+    // later rt_sync
+    (void)hipMemsetAsync(ctx->status, 0, sizeof(int32_t), st);
     (void)hipStreamSynchronize(st);
     rt_free(keys_in); rt_free(idx_in); rt_free(Htmp); rt_free(width); rt_free(dxpart);
     rt_free(sort_tmp); rt_free(nlist);
@@ -840,7 +844,8 @@ rt_status rt_sources_impl(rt_ctx *ctx, int32_t S, const double *xs, double eta_s
         // start below the mean spacing; the solver doubles h until bracketed
         double h0 = 0.05 * eta_star * ctx->p.box / cbrt((double)n);
         k_src_h<<<nblk(S, 64), 64, 0, st>>>(S, T, ctx->xs, n, sx, eta_star, ctx->p.kappa,
-                                           ctx->p.box, h0, ctx->src_h, ctx->status);
+                                           ctx->p.box, h0, ctx->h_iter_cap, ctx->src_h,
+                                           ctx->status);
         k_src_gas<false><<<nblk(S, 64), 64, 0, st>>>(S, T, ctx->xs, n, sx, ctx->src_h,
                                                     ctx->p.kappa, ctx->p.box, ctx->geo, cnt,
                                                     nullptr, nullptr, nullptr, nullptr);
@@ -908,6 +913,7 @@ rt_status rt_sources_impl(rt_ctx *ctx, int32_t S, const double *xs, double eta_s
     rt_free(sx); rt_free(cnt); rt_free(sxi);
     return RT_OK;
 fail:
+    (void)hipMemsetAsync(ctx->status, 0, sizeof(int32_t), st);
     (void)hipStreamSynchronize(st);
     rt_free(sx); rt_free(cnt); rt_free(sxi);
     return rs;

@@ -102,6 +102,7 @@ struct rt_ctx {
 
     int64_t device_bytes = 0;
     int32_t h_iter_max = 0;
+    int32_t h_iter_cap = 200;    // iteration cap of the smoothing-length solve
     int32_t bin_top = -1;        // largest time bin after rt_time_bins (-1: none)
     uint8_t *bin8 = nullptr;     // [n] time bins as set by rt_time_bins (0 after a build)
     int32_t solver = RT_GLF;     // Riemann solver of the transport

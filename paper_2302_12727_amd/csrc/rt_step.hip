@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     int64_t n, int64_t nb, const double *__restrict__ geo, const double *__restrict__ xs,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_gath, const double *__restrict__ U, double *__restrict__ UD,
-    double box, int64_t tick = 0) {
+    int32_t *__restrict__ status, double box, int64_t tick = 0) {
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     const int64_t blk = xcd_block(nb);
     if (blk >= nb) return;                      // whole block
@@ -122,19 +122,30 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     }
     const double b00 = rec[R_B] * iV, b01 = rec[R_B + 1] * iV, b02 = rec[R_B + 2] * iV;
     const double b11 = rec[R_B + 3] * iV, b12 = rec[R_B + 4] * iV, b22 = rec[R_B + 5] * iV;
-    // group-major record: per group the state then its gradients (one line)
+    // group-major record: per group the state then its gradients (one line);
+    // chk stays 0 unless a value written is NaN or infinite (0 x v is 0 for
+    // finite v and NaN otherwise)
+    double chk = 0.0;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         double *o = UD + (i * G + g) * 16;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int q = 4 * g + m;
+            const double d0 = b00 * acc[q][0] + b01 * acc[q][1] + b02 * acc[q][2];
+            const double d1 = b01 * acc[q][0] + b11 * acc[q][1] + b12 * acc[q][2];
+            const double d2 = b02 * acc[q][0] + b12 * acc[q][1] + b22 * acc[q][2];
             o[m] = Ui[q];
-            o[4 + 3 * m + 0] = b00 * acc[q][0] + b01 * acc[q][1] + b02 * acc[q][2];
-            o[4 + 3 * m + 1] = b01 * acc[q][0] + b11 * acc[q][1] + b12 * acc[q][2];
-            o[4 + 3 * m + 2] = b02 * acc[q][0] + b12 * acc[q][1] + b22 * acc[q][2];
+            o[4 + 3 * m + 0] = d0;
+            o[4 + 3 * m + 1] = d1;
+            o[4 + 3 * m + 2] = d2;
+            chk = __builtin_fma(Ui[q], 0.0, chk);
+            chk = __builtin_fma(d0, 0.0, chk);
+            chk = __builtin_fma(d1, 0.0, chk);
+            chk = __builtin_fma(d2, 0.0, chk);
         }
     }
+    if (chk != chk) atomicOr(status, ST_NONFINITE);
 }
 
 // Transport (eq:transport-update-explicit with the GLF flux eq:riemann-GLF).
@@ -173,9 +184,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
     const double *__restrict__ UD, const double *__restrict__ dtp, double c, double box,
     double *__restrict__ Uout, double *__restrict__ partials,
-    unsigned long long *__restrict__ counts, double *__restrict__ Uung, int64_t tick = 0,
-    double *__restrict__ accm = nullptr, const double2 *__restrict__ hll = nullptr,
-    const double *__restrict__ ivan = nullptr) {
+    unsigned long long *__restrict__ counts, double *__restrict__ Uung,
+    int32_t *__restrict__ status, int64_t tick = 0, double *__restrict__ accm = nullptr,
+    const double2 *__restrict__ hll = nullptr, const double *__restrict__ ivan = nullptr) {
     static_assert(G % GW == 0, "group slices must tile the groups");
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     constexpr int NS = G / GW, NQ = 4 * G;
@@ -389,6 +400,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     // update, post-update guard, ledger, photon budget
     double red[2 * GW];
     int gE = 0, gF = 0;
+    double chk = 0.0;   // NaN iff an updated state is NaN or infinite
     if (BIN && owner && !ends) {
         // no update in this tick: keep the pending sums, count the current state
         const double V = rk[R_V];
@@ -424,6 +436,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             double q2 = ui(4 * g + 2) - dtV * acc[4 * g + 2];
             double q3 = ui(4 * g + 3) - dtV * acc[4 * g + 3];
             const double Epre = q0;
+            chk = __builtin_fma(q0, 0.0, chk);
+            chk = __builtin_fma(q1, 0.0, chk);
+            chk = __builtin_fma(q2, 0.0, chk);
+            chk = __builtin_fma(q3, 0.0, chk);
             if (Uung) {
                 double *u = Uung + i * NQ + 4 * (g0 + g);
                 u[0] = q0;
@@ -446,6 +462,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int p = 0; p < 2 * GW; ++p) red[p] = 0.0;
     }
+    if (chk != chk) atomicOr(status, ST_NONFINITE);
     // partials [nb][2G]: photon totals in columns 0..G-1, ledger in G..2G-1
     if (partials)
         block_reduce_store<2 * GW>(red, partials + blk * 2 * G, smem,
@@ -630,8 +647,8 @@ void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double 
                   kPipe && (!HLL_ || W > 1)>                                                  \
         <<<(unsigned)xcd_grid(nb * (G / W)), kBlock, 0, ctx->stream>>>(                       \
         n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,          \
-        ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, 0, nullptr, tab,      \
-        ctx->ivan)
+        ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, ctx->status, 0,       \
+        nullptr, tab, ctx->ivan)
     if (ctx->solver == RT_HLL) {
         if (iva) RT_TRANSPORT_LAUNCH(HW, true, true);
         else RT_TRANSPORT_LAUNCH(HW, true, false);
@@ -653,7 +670,8 @@ template <int G>
 void launch_gradient64(rt_ctx *ctx, const double *U, double *UD) {
     const int64_t n = ctx->p.n, nb = (n + kBlock / kGQ - 1) / (kBlock / kGQ);
     k_gradient64<G, false, kGQ><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
-        n, nb, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box);
+        n, nb, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->status,
+        ctx->p.box);
 }
 
 template <int G>
@@ -662,7 +680,8 @@ void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, d
     const int64_t n = ctx->p.n;
     const int64_t ng = (n + kBlock / kGQ - 1) / (kBlock / kGQ);
     k_gradient64<G, true, kGQ><<<(unsigned)xcd_grid(ng), kBlock, 0, ctx->stream>>>(
-        n, ng, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box, tick);
+        n, ng, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->status,
+        ctx->p.box, tick);
     constexpr int GW = transport_slice(G), HW = hll_slice(G);
     const int64_t nt = transport_rows(n);
     const double2 *tab = (const double2 *)ctx->hll_table;
@@ -672,8 +691,8 @@ void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, d
                   kPipe && (!HLL_ || W > 1)>                                                  \
         <<<(unsigned)xcd_grid(nt * (G / W)), kBlock, 0, ctx->stream>>>(                        \
             n, nt, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,       \
-            ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, tick, accm, tab, \
-            ctx->ivan)
+            ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, ctx->status,    \
+            tick, accm, tab, ctx->ivan)
     if (ctx->solver == RT_HLL) {
         if (iva) RT_TICK_LAUNCH(HW, true, true);
         else RT_TICK_LAUNCH(HW, true, false);

@@ -20,7 +20,7 @@ __global__ __launch_bounds__(kBlock) void k_gradient32(
     int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ xs,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_gath, const float *__restrict__ U, float *__restrict__ UD,
-    double box, int64_t tick = 0) {
+    int32_t *__restrict__ status, double box, int64_t tick = 0) {
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     const int64_t blk = xcd_block(nb);
     if (blk >= nb) return;
@@ -72,18 +72,28 @@ __global__ __launch_bounds__(kBlock) void k_gradient32(
     }
     const float b00 = rec[F_B] * iV, b01 = rec[F_B + 1] * iV, b02 = rec[F_B + 2] * iV;
     const float b11 = rec[F_B + 3] * iV, b12 = rec[F_B + 4] * iV, b22 = rec[F_B + 5] * iV;
+    // chk stays 0 unless a value written is NaN or infinite
+    float chk = 0.0f;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         float *o = UD + (i * G + g) * 16;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int q = 4 * g + m;
+            const float d0 = b00 * acc[q][0] + b01 * acc[q][1] + b02 * acc[q][2];
+            const float d1 = b01 * acc[q][0] + b11 * acc[q][1] + b12 * acc[q][2];
+            const float d2 = b02 * acc[q][0] + b12 * acc[q][1] + b22 * acc[q][2];
             o[m] = Ui[q];
-            o[4 + 3 * m + 0] = b00 * acc[q][0] + b01 * acc[q][1] + b02 * acc[q][2];
-            o[4 + 3 * m + 1] = b01 * acc[q][0] + b11 * acc[q][1] + b12 * acc[q][2];
-            o[4 + 3 * m + 2] = b02 * acc[q][0] + b12 * acc[q][1] + b22 * acc[q][2];
+            o[4 + 3 * m + 0] = d0;
+            o[4 + 3 * m + 1] = d1;
+            o[4 + 3 * m + 2] = d2;
+            chk = __builtin_fmaf(Ui[q], 0.0f, chk);
+            chk = __builtin_fmaf(d0, 0.0f, chk);
+            chk = __builtin_fmaf(d1, 0.0f, chk);
+            chk = __builtin_fmaf(d2, 0.0f, chk);
         }
     }
+    if (chk != chk) atomicOr(status, ST_NONFINITE);
 }
 
 // HLL: the HLL solver (eq:riemann-HLL) with the FP32 copy of the wave-speed
@@ -110,9 +120,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
     const int32_t *__restrict__ n_nbr, const float *__restrict__ UD,
     const double *__restrict__ dtp, double c, double box, float *__restrict__ Uout,
     double *__restrict__ partials, unsigned long long *__restrict__ counts,
-    float *__restrict__ Uung, const float2 *__restrict__ hll = nullptr,
-    const double *__restrict__ ivan = nullptr, int64_t tick = 0,
-    double *__restrict__ accm = nullptr) {
+    float *__restrict__ Uung, int32_t *__restrict__ status,
+    const float2 *__restrict__ hll = nullptr, const double *__restrict__ ivan = nullptr,
+    int64_t tick = 0, double *__restrict__ accm = nullptr) {
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     constexpr int NQ = 4 * G, PW = 64 / Q, PB = kBlock / Q;
     __shared__ float stage[kBlock / 64][64 * kStage32];
@@ -293,6 +303,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
     }
     double red[2 * G];
     int gE = 0, gF = 0;
+    float chk = 0.0f;   // NaN iff an updated state is NaN or infinite
     if (BIN && owner && !ends) {
         // no update in this tick: keep the pending sums, count the current state
         const double V = geo[(int64_t)kRec * i + R_V];
@@ -354,17 +365,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
             gE += f & 1;
             gF += f >> 1;
             float *o = Uout + i * NQ + 4 * g;
-            o[0] = (float)q0;
-            o[1] = (float)q1;
-            o[2] = (float)q2;
-            o[3] = (float)q3;
-            red[g] = V * (double)o[0];
+            const float o0 = (float)q0, o1 = (float)q1, o2 = (float)q2, o3 = (float)q3;
+            o[0] = o0;
+            o[1] = o1;
+            o[2] = o2;
+            o[3] = o3;
+            // the unguarded state in its stored precision (NaN stays NaN
+            // through the guard; a state beyond the FP32 range rounds to inf)
+            chk = __builtin_fmaf((float)Epre, 0.0f, chk);
+            chk = __builtin_fmaf(o1, 0.0f, chk);
+            chk = __builtin_fmaf(o2, 0.0f, chk);
+            chk = __builtin_fmaf(o3, 0.0f, chk);
+            red[g] = V * (double)o0;
             red[G + g] = (f & 1) ? -Epre * V : 0.0;
         }
     } else {
 #pragma unroll
         for (int p = 0; p < 2 * G; ++p) red[p] = 0.0;
     }
+    if (chk != chk) atomicOr(status, ST_NONFINITE);
     if (partials) {
         const int ln = threadIdx.x & 63;
 #pragma unroll
@@ -406,7 +425,8 @@ template <int G>
 void launch_gradient32(rt_ctx *ctx, const float *U, float *UD) {
     const int64_t n = ctx->p.n, nb = (n + kBlock / kGQ32 - 1) / (kBlock / kGQ32);
     k_gradient32<G, kGQ32><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
-        n, nb, ctx->geo32, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box);
+        n, nb, ctx->geo32, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->status,
+        ctx->p.box);
 }
 
 // Lanes per particle of the FP32C transport (1, 2 or 4).  On the 3-group
@@ -425,8 +445,8 @@ void launch_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *U
 #define RT_TRANSPORT32_LAUNCH(HLL_, IVA_)                                                     \
     k_transport32<G, HLL_, kQ32, IVA_><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(   \
         n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt,            \
-        ctx->p.c_red, ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, tab,    \
-        ctx->ivan)
+        ctx->p.c_red, ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung,         \
+        ctx->status, tab, ctx->ivan)
     if (ctx->solver == RT_HLL) {
         if (iva) RT_TRANSPORT32_LAUNCH(true, true);
         else RT_TRANSPORT32_LAUNCH(true, false);
@@ -443,16 +463,16 @@ void launch_tick32(rt_ctx *ctx, float *U, float *UD, const double *dt, double *p
     const int64_t n = ctx->p.n;
     const int64_t ng = (n + kBlock / kGQ32 - 1) / (kBlock / kGQ32);
     k_gradient32<G, kGQ32, true><<<(unsigned)xcd_grid(ng), kBlock, 0, ctx->stream>>>(
-        n, ng, ctx->geo32, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->p.box,
-        tick);
+        n, ng, ctx->geo32, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->status,
+        ctx->p.box, tick);
     const int64_t nb = rt_transport32_rows(n);
     const float2 *tab = (const float2 *)ctx->hll_table32;
     const bool iva = ctx->surfaces == RT_IVANOVA;
 #define RT_TICK32_LAUNCH(HLL_, IVA_)                                                           \
     k_transport32<G, HLL_, kQ32, IVA_, true><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>( \
         n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt,             \
-        ctx->p.c_red, ctx->p.box, U, partials, (unsigned long long *)counts, nullptr, tab,     \
-        ctx->ivan, tick, accm)
+        ctx->p.c_red, ctx->p.box, U, partials, (unsigned long long *)counts, nullptr,          \
+        ctx->status, tab, ctx->ivan, tick, accm)
     if (ctx->solver == RT_HLL) {
         if (iva) RT_TICK32_LAUNCH(true, true);
         else RT_TICK32_LAUNCH(true, false);

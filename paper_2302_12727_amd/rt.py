@@ -19,12 +19,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgearrt.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EHIP, RT_ENOCONV, RT_ESINGULAR, RT_ESTATE = 0, -1, -2, -3, -4, -5, -6
+RT_ENONFINITE = -7
 RT_FP64, RT_FP32C = 0, 1
 RT_GLF, RT_HLL = 0, 1
 RT_HOPKINS, RT_IVANOVA = 0, 1
 RT_HLL_NF, RT_HLL_NMU = 65, 65
 STATUS_NAMES = {0: "RT_OK", -1: "RT_EINVAL", -2: "RT_ENOMEM", -3: "RT_EHIP",
-                -4: "RT_ENOCONV", -5: "RT_ESINGULAR", -6: "RT_ESTATE"}
+                -4: "RT_ENOCONV", -5: "RT_ESINGULAR", -6: "RT_ESTATE", -7: "RT_ENONFINITE"}
 
 KAPPA = 1.825742
 ETA = 1.2348
@@ -34,7 +35,7 @@ EXPORTED = ["rt_create", "rt_destroy", "rt_last_error", "rt_set_stream", "rt_bui
             "rt_adjoint", "rt_sync", "rt_get_stats", "rt_get_geometry", "rt_get_neighbours",
             "rt_get_sources", "rt_timing", "rt_get_timing", "rt_time_bins", "rt_tick",
             "rt_set_riemann", "rt_get_hll_table", "rt_photon_groups", "rt_absorb", "rt_drift",
-            "rt_set_surfaces"]
+            "rt_set_surfaces", "rt_set_h_iterations"]
 
 
 class RTError(RuntimeError):
@@ -81,6 +82,7 @@ def load_library() -> ctypes.CDLL:
     L.rt_set_stream.argtypes = [_VP, _VP]
     L.rt_build_cells.argtypes = [_VP] * 7
     L.rt_set_sources.argtypes = [_VP, i32, _VP, ctypes.c_double]
+    L.rt_set_h_iterations.argtypes = [_VP, i32]
     L.rt_inject.argtypes = [_VP] * 4
     L.rt_gradient.argtypes = [_VP] * 3
     L.rt_transport.argtypes = [_VP] * 8
@@ -338,6 +340,10 @@ class RT:
         self._check(self.L.rt_tick(self.ctx, _ptr(U), _ptr(L), int(tick), _ptr(UD), _ptr(acc),
                                    _ptr(photon_total), _ptr(counts), _ptr(ledger)))
         return U
+
+    def rt_set_h_iterations(self, max_iter: int):
+        """Iteration cap of the smoothing-length solve of later builds."""
+        self._check(self.L.rt_set_h_iterations(self.ctx, int(max_iter)))
 
     def rt_set_riemann(self, solver: str):
         """Riemann solver of rt_transport: "glf" or "hll"."""

@@ -1,0 +1,130 @@
+"""Device-side conditions reported through the C ABI as status codes.
+
+Every case here is an ordinary data condition that the kernels turn into a
+status, not a fault: a coplanar particle set (E_i singular), a
+smoothing-length solve capped below the iterations it needs (no convergence),
+NaN and infinite states (the non-finite bit of the status word), and negative
+energies in the input (clipped by the face and update guards exactly as the
+oracle clips them).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from tests.gpu_util import dev, log, state_err, unsort
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2302_12727_amd import RT  # noqa: E402
+from paper_2302_12727_amd.rt import (RT_EINVAL, RT_ENOCONV, RT_ENONFINITE,  # noqa: E402
+                                     RT_ESINGULAR, RTError)
+
+
+def coplanar_set(m: int = 32) -> np.ndarray:
+    """An m x m square lattice in the plane z = 1/2 of the unit box."""
+    g = (np.arange(m) + 0.5) / m
+    xy = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    return np.ascontiguousarray(np.concatenate([xy, np.full((xy.shape[0], 1), 0.5)], axis=1))
+
+
+def test_coplanar_set_is_singular():
+    x = coplanar_set()
+    log(f"case coplanar n={x.shape[0]}")
+    # the oracle refuses it for the same reason
+    with pytest.raises(oracle.OracleError) as eo:
+        oracle.build_geometry(x)
+    assert eo.value.code == oracle.RT_ESINGULAR
+    rt = RT(x.shape[0], 1)
+    with pytest.raises(RTError) as e:
+        rt.rt_build_cells(dev(x))
+    assert e.value.code == RT_ESINGULAR
+    # the build reported its condition itself: nothing is left for rt_sync
+    rt.rt_sync()
+
+
+def test_h_iteration_cap_gives_noconv():
+    w = workloads.config(0)
+    log(f"case h-iteration cap n={w.n}")
+    rt = RT(w.n, 1)
+    with pytest.raises(RTError) as e:
+        rt.rt_set_h_iterations(0)
+    assert e.value.code == RT_EINVAL
+    rt.rt_set_h_iterations(1)
+    with pytest.raises(RTError) as e:
+        rt.rt_build_cells(dev(w.x))
+    assert e.value.code == RT_ENOCONV
+    rt.rt_sync()
+    # the default cap builds the same set, with the oracle's smoothing lengths
+    rt.rt_set_h_iterations(200)
+    perm, h, _, _ = rt.rt_build_cells(dev(w.x))
+    geo = oracle.build_geometry(w.x)
+    hh = unsort(h.cpu().numpy(), perm.cpu().numpy())
+    assert np.abs(hh / geo.h - 1).max() < 1e-13
+    st = rt.rt_get_stats()
+    assert 1 <= st["h_iter_max"] <= 200
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_nonfinite_states_raise_status(precision):
+    w = workloads.config(0)
+    log(f"case non-finite {precision} n={w.n}")
+    rt = RT(w.n, 1, precision=precision)
+    perm, *_ = rt.rt_build_cells(dev(w.x))
+    p = perm.cpu().numpy()
+    sd = rt.sdtype
+    clean = dev(w.U0[p]).to(sd)
+    # a clean step leaves the status word clear
+    rt.step(clean.clone())
+    rt.rt_sync()
+    # NaN energy in the input: the gradient records hold NaN
+    U = clean.clone()
+    U[17, 0, 0] = float("nan")
+    rt.rt_gradient(U)
+    with pytest.raises(RTError) as e:
+        rt.rt_sync()
+    assert e.value.code == RT_ENONFINITE
+    rt.rt_sync()                      # the word was cleared
+    # an infinite flux in an otherwise finite gradient record: the transport
+    # update of that particle and its neighbours is non-finite
+    UD = rt.rt_gradient(clean)
+    rt.rt_sync()
+    UD[33, 0, 1] = float("inf")
+    rt.rt_transport(UD)
+    with pytest.raises(RTError) as e:
+        rt.rt_sync()
+    assert e.value.code == RT_ENONFINITE
+    # finite data again: no error
+    rt.step(clean.clone())
+    rt.rt_sync()
+
+
+def test_negative_energies_are_clipped_like_the_oracle():
+    w = workloads.config(0)
+    log(f"case negative energies n={w.n}")
+    U0 = w.U0.copy()
+    g = np.random.default_rng(5)
+    neg = g.choice(w.n, 64, replace=False)
+    U0[neg, 0, 0] = -g.uniform(0.1, 1.0, 64)
+    geo = oracle.build_geometry(w.x)
+    U_or, info = oracle.run(geo, None, U0, None, 3)
+    rt = RT(w.n, 1)
+    perm, *_ = rt.rt_build_cells(dev(w.x))
+    p = perm.cpu().numpy()
+    U = dev(U0[p])
+    counts = torch.zeros(4, dtype=torch.int64, device="cuda")
+    for _ in range(3):
+        U = rt.step(U, counts=counts)
+    rt.rt_sync()
+    got = unsort(U.cpu().numpy(), p)
+    err = state_err(got, U_or)
+    log(f"  negative-E inputs, 3 steps: max state error {err:.2e}; counts {counts.tolist()}")
+    assert err < 1e-12
+    assert (got[..., 0] >= 0).all()
+    assert counts[0].item() > 0            # face states clipped
+    oc = info["counts"]
+    assert counts[0].item() == oc[0] and counts[2].item() == oc[2]
