@@ -332,6 +332,25 @@ rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const doub
                      const void *UD, const void *U_unguarded, const void *lam_next, void *lam,
                      double *dL_dL);
 
+/* rt_adjoint for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments and result as rt_adjoint with UD and U_unguarded given (both
+ * required: recomputing them would need more scratch); it calls no hipMalloc,
+ * hipFree or allocating library routine.  Its scratch (5 state-sized arrays:
+ * the guarded cotangent and the pair-pass records) is a fixed 64 MiB device
+ * array of the library, one copy per GPU held until the process ends, so
+ * 256-byte-aligned n x G x 4 x sizeof(state element) x (1 + 4) bytes must fit
+ * in 64 MiB: n G up to about 419 thousand in FP64, 838 thousand in FP32C, else
+ * RT_EINVAL (before any device work).  Nothing in the array needs clearing
+ * between calls, but every call on one GPU uses the same array: calls that
+ * overlap on a GPU (two contexts or streams) race and must be serialized.
+ * RT_ESTATE before rt_build_cells; RT_EINVAL if the context's device is not
+ * current; RT_EHIP if the array's address could not be looked up when the
+ * context was created. */
+rt_status rt_adjoint_static(rt_ctx *ctx, const double *L, const double *dt, const void *UD,
+                            const void *U_unguarded, const void *lam_next, void *lam,
+                            double *dL_dL);
+
 /* Wait for the stream; return the device-side error raised since the last
  * rt_sync (RT_ENONFINITE, see the conventions above) or RT_OK, and clear the
  * status word. */

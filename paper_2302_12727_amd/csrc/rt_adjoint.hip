@@ -18,6 +18,8 @@
 //   C: rho_i   = S_i^{-1} lamD_i;
 //      lam_p   = lam'_p - (sum_j w_pj s_pj) . rho_p + sum_i w(r_ip/H_i) s_ip . rho_i
 //   D: dLoss/dL_s += dt sum_g coef_sg lam_E,g
+#include <mutex>
+
 #include "rt_pair.h"
 
 using namespace gearrt;
@@ -511,6 +513,41 @@ static rt_status adj_scratch(rt_ctx *ctx, size_t es, char **base) {
     return RT_OK;
 }
 
+// Passes A-D of one adjoint step on the gradient record UD and unguarded
+// state U_ung of the forward, with lam'' and R in caller-provided scratch.
+static void adjoint_passes(rt_ctx *ctx, const double *L, const double *dt, const void *UD,
+                           const void *U_ung, const void *lam_next, void *lam2, void *Rb,
+                           void *lam, double *dL_dL) {
+    (void)L;
+    if (ctx->p.precision == RT_FP32C) {
+        rt_adjoint32(ctx, (const float *)UD, (const float *)U_ung, (const float *)lam_next,
+                     (float *)lam2, (float *)Rb, (float *)lam, dt);
+    } else {
+#define RT_ADJ64(G_)                                                                          \
+    case G_:                                                                                  \
+        launch_adjoint64<G_>(ctx, (const double *)UD, (const double *)U_ung,                  \
+                             (const double *)lam_next, (double *)lam2, (double *)Rb,          \
+                             (double *)lam, dt);                                              \
+        break;
+        switch (ctx->p.groups) {
+            RT_ADJ64(1) RT_ADJ64(2) RT_ADJ64(3) RT_ADJ64(4)
+            RT_ADJ64(5) RT_ADJ64(6) RT_ADJ64(7) RT_ADJ64(8)
+            default: break;
+        }
+#undef RT_ADJ64
+    }
+    if (ctx->S > 0 && dL_dL) {
+        if (ctx->p.precision == RT_FP64)
+            k_adj_inject<double><<<ctx->S, kBlock, 0, ctx->stream>>>(
+                ctx->S, ctx->p.groups, ctx->src_ptr, ctx->src_gas, ctx->src_coef,
+                (const double *)lam, dt, dL_dL);
+        else
+            k_adj_inject<float><<<ctx->S, kBlock, 0, ctx->stream>>>(
+                ctx->S, ctx->p.groups, ctx->src_ptr, ctx->src_gas, ctx->src_coef,
+                (const float *)lam, dt, dL_dL);
+    }
+}
+
 rt_status rt_adjoint_impl(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
                           const void *UD, const void *U_ung, const void *lam_next, void *lam,
                           double *dL_dL) {
@@ -543,31 +580,84 @@ rt_status rt_adjoint_impl(rt_ctx *ctx, const void *U_pre, const double *L, const
             return rs;
         U_ung = Uu;
     }
-    if (ctx->p.precision == RT_FP32C) {
-        rt_adjoint32(ctx, (const float *)UD, (const float *)U_ung, (const float *)lam_next,
-                     (float *)lam2, (float *)Rb, (float *)lam, dt);
-    } else switch (ctx->p.groups) {
-        case 1: launch_adjoint64<1>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
-        case 2: launch_adjoint64<2>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
-        case 3: launch_adjoint64<3>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
-        case 4: launch_adjoint64<4>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
-        case 5: launch_adjoint64<5>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
-        case 6: launch_adjoint64<6>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
-        case 7: launch_adjoint64<7>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
-        case 8: launch_adjoint64<8>(ctx, (const double *)UD, (const double *)U_ung, (const double *)lam_next, (double *)lam2, (double *)Rb, (double *)lam, dt); break;
-        default: break;
-    }
-    if (ctx->S > 0 && dL_dL) {
-        if (ctx->p.precision == RT_FP64)
-            k_adj_inject<double><<<ctx->S, kBlock, 0, ctx->stream>>>(
-                ctx->S, ctx->p.groups, ctx->src_ptr, ctx->src_gas, ctx->src_coef,
-                (const double *)lam, dt, dL_dL);
-        else
-            k_adj_inject<float><<<ctx->S, kBlock, 0, ctx->stream>>>(
-                ctx->S, ctx->p.groups, ctx->src_ptr, ctx->src_gas, ctx->src_coef,
-                (const float *)lam, dt, dL_dL);
-    }
+    adjoint_passes(ctx, L, dt, UD, U_ung, lam_next, lam2, Rb, lam, dL_dL);
     rt_timer_end(ctx, "adjoint");
+    RT_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The adjoint for callers that cannot allocate device memory.  Its scratch,
+// lam'' (one state-sized array) and the pair-pass records R (four), lives in
+// the fixed array `scratch` instead of the context's lazily allocated buffer.
+// Each device holds its own copy of the array at its own address: host code
+// never names `scratch` where it needs the memory, it uses the address
+// rt_adjoint_static_init looked up for the device (g_scratch).  Every pass
+// writes the scratch it later reads, so nothing needs clearing between calls;
+// calls that overlap on one device share the array and race.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch[kMaxDevices];
+static hipError_t g_scratch_err[kMaxDevices];
+static bool g_scratch_done[kMaxDevices];
+
+// Look up the device address of `scratch` once per device, with the context's
+// device current (called by rt_create).
+void rt_adjoint_static_init(rt_ctx *ctx) {
+    const int d = ctx->device;
+    if (d < 0 || d >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_done[d]) return;
+    g_scratch_done[d] = true;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        g_scratch_err[d] = e;
+        return;
+    }
+    g_scratch[d] = p;
+}
+
+size_t rt_adjoint_static_bytes(const rt_ctx *ctx) {
+    const size_t es = ctx->p.precision == RT_FP64 ? 8 : 4;
+    const size_t nu = (size_t)ctx->p.n * 4 * ctx->p.groups * es;
+    return ((nu + 255) & ~size_t(255)) + ((4 * nu + 255) & ~size_t(255));
+}
+
+rt_status rt_adjoint_static_impl(rt_ctx *ctx, const double *L, const double *dt, const void *UD,
+                                 const void *U_ung, const void *lam_next, void *lam,
+                                 double *dL_dL) {
+    const size_t need = rt_adjoint_static_bytes(ctx);
+    if (need > kStaticScratchBytes)
+        return rt_fail(ctx, RT_EINVAL,
+                       "rt_adjoint_static: n x groups needs " + std::to_string(need) +
+                           " bytes of scratch, more than its fixed " +
+                           std::to_string(kStaticScratchBytes) + " (use rt_adjoint)");
+    int cur = -1;
+    RT_HIP(hipGetDevice(&cur));
+    if (cur != ctx->device)
+        return rt_fail(ctx, RT_EINVAL, "rt_adjoint_static: the context's device is not current");
+    void *base = nullptr;
+    hipError_t err = hipSuccess;
+    if (cur >= 0 && cur < kMaxDevices) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        base = g_scratch[cur];
+        err = g_scratch_err[cur];
+    }
+    if (!base)
+        return rt_fail(ctx, RT_EHIP, std::string("rt_adjoint_static: no scratch on this device") +
+                                         (err != hipSuccess ? std::string(": ") +
+                                                                  hipGetErrorString(err)
+                                                            : std::string()));
+    const size_t es = ctx->p.precision == RT_FP64 ? 8 : 4;
+    const size_t nu = (size_t)ctx->p.n * 4 * ctx->p.groups * es;
+    char *b = (char *)base;
+    void *lam2 = b;
+    void *Rb = b + ((nu + 255) & ~size_t(255));
+    adjoint_passes(ctx, L, dt, UD, U_ung, lam_next, lam2, Rb, lam, dL_dL);
     RT_HIP(hipGetLastError());
     return RT_OK;
 }

@@ -100,6 +100,7 @@ rt_status rt_create(const rt_params *p, rt_ctx **out) {
         rt_destroy(ctx);
         return rt_fail(nullptr, RT_EHIP, "hipMemset failed");
     }
+    rt_adjoint_static_init(ctx);
     *out = ctx;
     return RT_OK;
 }
@@ -305,6 +306,18 @@ rt_status rt_adjoint(rt_ctx *ctx, const void *U_pre, const double *L, const doub
     if (ctx->S > 0 && !L) return rt_fail(ctx, RT_EINVAL, "L is required when sources are set");
     if (UD && !aligned16(UD)) return rt_fail(ctx, RT_EINVAL, "UD must be 16-byte aligned");
     return rt_adjoint_impl(ctx, U_pre, L, dt, UD, U_unguarded, lam_next, lam, dL_dL);
+}
+
+rt_status rt_adjoint_static(rt_ctx *ctx, const double *L, const double *dt, const void *UD,
+                            const void *U_unguarded, const void *lam_next, void *lam,
+                            double *dL_dL) {
+    if (!ctx) return RT_EINVAL;
+    if (!ctx->built) return rt_fail(ctx, RT_ESTATE, "rt_build_cells has not run");
+    if (!dt || !UD || !U_unguarded || !lam_next || !lam)
+        return rt_fail(ctx, RT_EINVAL, "dt, UD, U_unguarded, lam_next and lam are required");
+    if (ctx->S > 0 && !L) return rt_fail(ctx, RT_EINVAL, "L is required when sources are set");
+    if (!aligned16(UD)) return rt_fail(ctx, RT_EINVAL, "UD must be 16-byte aligned");
+    return rt_adjoint_static_impl(ctx, L, dt, UD, U_unguarded, lam_next, lam, dL_dL);
 }
 
 rt_status rt_sync(rt_ctx *ctx) {

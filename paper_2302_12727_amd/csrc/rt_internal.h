@@ -318,3 +318,10 @@ rt_status rt_set_riemann_impl(rt_ctx *ctx, int32_t solver);
 rt_status rt_adjoint_impl(rt_ctx *ctx, const void *U_pre, const double *L, const double *dt,
                           const void *UD, const void *U_ung, const void *lam_next, void *lam,
                           double *dL_dL);
+// the allocation-free adjoint (rt_adjoint.hip): per-device scratch lookup (from
+// rt_create), the scratch bytes a context needs, and the entry point
+void rt_adjoint_static_init(rt_ctx *ctx);
+size_t rt_adjoint_static_bytes(const rt_ctx *ctx);
+rt_status rt_adjoint_static_impl(rt_ctx *ctx, const double *L, const double *dt, const void *UD,
+                                 const void *U_ung, const void *lam_next, void *lam,
+                                 double *dL_dL);

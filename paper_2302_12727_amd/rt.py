@@ -35,7 +35,7 @@ EXPORTED = ["rt_create", "rt_destroy", "rt_last_error", "rt_set_stream", "rt_bui
             "rt_adjoint", "rt_sync", "rt_get_stats", "rt_get_geometry", "rt_get_neighbours",
             "rt_get_sources", "rt_timing", "rt_get_timing", "rt_time_bins", "rt_tick",
             "rt_set_riemann", "rt_get_hll_table", "rt_photon_groups", "rt_absorb", "rt_drift",
-            "rt_set_surfaces", "rt_set_h_iterations"]
+            "rt_set_surfaces", "rt_set_h_iterations", "rt_adjoint_static"]
 
 
 class RTError(RuntimeError):
@@ -88,6 +88,7 @@ def load_library() -> ctypes.CDLL:
     L.rt_transport.argtypes = [_VP] * 8
     L.rt_photon_total.argtypes = [_VP] * 3
     L.rt_adjoint.argtypes = [_VP] * 9
+    L.rt_adjoint_static.argtypes = [_VP] * 8
     L.rt_time_bins.argtypes = [_VP, i32, _VP, ctypes.POINTER(ctypes.c_int64)]
     L.rt_tick.argtypes = [_VP, _VP, _VP, ctypes.c_int64, _VP, _VP, _VP, _VP, _VP]
     L.rt_photon_groups.argtypes = [i32, _VP, ctypes.c_double, _VP, _VP, _VP, _VP]
@@ -387,6 +388,26 @@ class RT:
         self._check(self.L.rt_adjoint(self.ctx, _ptr(U_pre), _ptr(L) if self.S else None,
                                       _ptr(dt), _ptr(UD), _ptr(U_unguarded), _ptr(lam_next),
                                       _ptr(lam), _ptr(dL_dL)))
+        return lam
+
+    def rt_adjoint_static(self, L, lam_next, UD, U_unguarded, lam=None, dL_dL=None,
+                          dt=None) -> torch.Tensor:
+        """rt_adjoint through the library's fixed scratch (no device
+        allocation by the library); UD and U_unguarded are required."""
+        _need(lam_next, "lam_next", self.sdtype, (self.n, self.G, 4))
+        lam = torch.empty_like(lam_next) if lam is None else lam
+        _need(lam, "lam", self.sdtype, (self.n, self.G, 4))
+        _need(UD, "UD", self.sdtype, (self.n, self.G, 16))
+        _need(U_unguarded, "U_unguarded", self.sdtype, (self.n, self.G, 4))
+        if self.S:
+            _need(L, "L", torch.float64, (self.S, self.G))
+        if dL_dL is not None:
+            _need(dL_dL, "dL_dL", torch.float64, (self.S, self.G))
+        dt = self.dt if dt is None else dt
+        self._bind_stream()
+        self._check(self.L.rt_adjoint_static(self.ctx, _ptr(L) if self.S else None, _ptr(dt),
+                                             _ptr(UD), _ptr(U_unguarded), _ptr(lam_next),
+                                             _ptr(lam), _ptr(dL_dL)))
         return lam
 
     def rt_sync(self):
