@@ -7,6 +7,9 @@ eigenvalue table.
   by hand here, independently of the complex-step Jacobian;
 - f = 0 nodes at -+1/sqrt(3); mirror symmetry l_min(f, mu) = -l_max(f, -mu);
   |l| <= 1 (no signal faster than c);
+- interior nodes against the spectrum of the flux Jacobian at random 3D
+  orientations, energies and speeds of light (rotation and scale
+  invariance), which must also hold the closed-form transverse mode;
 - HLL with wave speeds -+c is the GLF solver (the thesis states it); a
   two-identical-state Riemann problem returns the state's flux; with both
   speeds positive the flux is the upwind one;
@@ -52,6 +55,52 @@ def test_table_limits_symmetry_and_bounds(tab):
     assert np.abs(tab[:, :, 0] + tab[:, ::-1, 1]).max() < 1e-13
     assert (tab[:, :, 0] <= tab[:, :, 1] + 1e-15).all()
     assert np.abs(tab).max() <= 1 + 1e-13
+
+
+def rotation(g):
+    """A random proper rotation (QR of a Gaussian matrix, signs fixed)."""
+    q, r = np.linalg.qr(g.normal(size=(3, 3)))
+    q = q * np.sign(np.diag(r))
+    return q if np.linalg.det(q) > 0 else -q
+
+
+def test_table_interior_by_rotation_and_the_transverse_mode(tab):
+    """Interior nodes 0 < f < 1, -1 < mu < 1.  The table is built at one
+    orientation (F along x, the normal in the x-y plane, E = 1, c = 1); here
+    the flux Jacobian d(F.n, c^2 P n)/d(E, F) of the printed closure is taken
+    at a random 3D orientation, a random energy and c != 1 with |F| = c f E
+    and F.n = mu |F|.  Its eigenvalues divided by c must have the table's
+    extremes at that node, and one of them must be the transverse mode
+    3 f mu / (2 + sqrt(4 - 3 f^2)): a perturbation dF normal to the plane of F
+    and n keeps f and chi, turns F/|F| by dF/|F|, and so changes c^2 P n by
+    c^2 E (3 chi - 1)/2 mu dF / |F| = c mu (3 chi - 1)/(2 f) dF, which the
+    identity (3 chi - 1)/(2 f^2) = 3/(2 + sqrt(4 - 3 f^2)) turns into the
+    closed form.  A wrong mu -> n mapping of the table, or wrong units, fails."""
+    g = workloads.rng(41)
+    nf, nmu = tab.shape[:2]
+    hstep = 1e-30
+    for _ in range(80):
+        i, j = int(g.integers(1, nf - 1)), int(g.integers(1, nmu - 1))
+        f, mu = i / (nf - 1), -1.0 + 2.0 * j / (nmu - 1)
+        c = float(g.choice([1.0, 2.5, 0.3]))
+        E = float(g.lognormal())
+        R = rotation(g)
+        d_F, d_p, d_t = R[:, 0], R[:, 1], R[:, 2]
+        n = mu * d_F + np.sqrt(1.0 - mu * mu) * d_p
+        U = np.concatenate([[E], c * f * E * d_F])
+        J = np.zeros((4, 4))
+        for k in range(4):
+            Uc = U.astype(complex)
+            Uc[k] += 1j * hstep
+            J[:, k] = oracle.m1_flux_printed(Uc, n, c).imag / hstep
+        ev = np.linalg.eigvals(J)
+        assert np.abs(ev.imag).max() < 1e-8 * c
+        lam = np.sort(ev.real) / c
+        assert abs(lam[0] - tab[i, j, 0]) < 1e-11 and abs(lam[-1] - tab[i, j, 1]) < 1e-11
+        mt = 3.0 * f * mu / (2.0 + np.sqrt(4.0 - 3.0 * f * f))
+        assert np.abs(lam - mt).min() < 1e-11
+        v = np.concatenate([[0.0], d_t])
+        assert np.linalg.norm(J @ v - c * mt * v) < 1e-11 * c
 
 
 def random_state(g, f):
