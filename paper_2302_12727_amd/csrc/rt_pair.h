@@ -177,6 +177,51 @@ __device__ __forceinline__ double minmod(double a, double b) {
     return (a * b > 0.0) ? m : 0.0;
 }
 
+// minmod(a, b) as the median of (a, b, 0): for a and b of one sign the median
+// is the one nearer 0, otherwise 0; med3(a, b, 0) = max(min(a, b),
+// min(max(a, b), 0)) takes four min/max instructions and no compare or
+// select, and returns a, b or 0 exactly as minmod does.
+__device__ __forceinline__ double minmod_med(double a, double b) {
+    return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
+}
+
+// Face guard and M1 flux coefficients of one face state in one pass (the
+// transport's inner loop): the guard of guard64 applied to q in place (the
+// same bits returned), then FA = F.A and the coefficients of
+// c^2 P A = a A + b F of m1_flux64, sharing |F|^2 and cE between them.  An
+// E = 0 state with F != 0 takes the rescale branch with factor 0 (F -> 0, not
+// counted, as guard64 does); the branches of m1_flux64 at R2 = 0 and D = 0
+// (only E = 0 reaches them) become a floor at the smallest normal double,
+// where F = 0 makes a = b = 0 all the same.  c3 = 3c.
+__device__ __forceinline__ int face_m164(double (&q)[4], double Ax, double Ay, double Az,
+                                         double c, double c3, double &FA, double &a,
+                                         double &b) {
+    int fired = 0;
+    if (q[0] < 0.0) {
+        q[0] = 0.0;
+        fired = 1;
+    }
+    double F2 = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    const double cE = c * q[0];
+    const double lim2 = cE * cE;
+    if (F2 > lim2) {
+        const double sc = cE * rsq64(F2);
+        q[1] *= sc;
+        q[2] *= sc;
+        q[3] *= sc;
+        if (q[0] > 0.0) fired |= 2;
+        F2 = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    }
+    FA = q[1] * Ax + q[2] * Ay + q[3] * Az;
+    const double R2 = __builtin_fma(-3.0, F2, 4.0 * lim2);
+    const double R = R2 * rsq64(fmax(R2, 2.2250738585072014e-308));
+    const double D = __builtin_fma(2.0, cE, R);
+    const double iD = rcp64(fmax(D, 2.2250738585072014e-308));
+    a = c * __builtin_fma(-F2, iD, cE * (1.0 / 3.0));
+    b = c3 * FA * iD;
+    return fired;
+}
+
 // Per-pair flux accumulation shared by the FP64 transport and its adjoint
 // recompute: returns |A| and A in out-params, or |A| = 0 if the pair has no
 // surface.
@@ -297,6 +342,23 @@ __device__ __forceinline__ void store_lines(const double2 (&v)[8], double *sb, i
         d[1] = v[m].y;
     }
     wave_lds_sync();
+}
+// Pointers to this lane's 16-byte piece of line `sel` of rows r[m] of a table
+// of rows `stride` lines long, src + 16 (stride r[m] + sel) + 2 (lane % 8),
+// for the 8 rows the lane helps to move.  The row offset is formed in 32 bits
+// (stride r[m] < 2^31) and widened once: no 64-bit multiply per line, and the
+// lines sel + 1, sel + 2, ... of the same rows are constant offsets.
+__device__ __forceinline__ void row_ptrs(const double *__restrict__ src, const int32_t (&r)[8],
+                                         int stride, int sel, int lane, const double *(&p)[8]) {
+    const uint32_t extra = (uint32_t)sel * 16 + 2 * (lane & 7);
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+        p[m] = src + (((size_t)(uint32_t)(r[m] * stride) << 4) + extra);
+}
+// Load the pieces at p[m] + 16 g (line g beyond the one p points into).
+__device__ __forceinline__ void load_at(const double *const (&p)[8], int g, double2 (&v)[8]) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[m] = *reinterpret_cast<const double2 *>(p[m] + 16 * g);
 }
 __device__ __forceinline__ void stage_lines(const double *__restrict__ src, const int64_t (&row)[8],
                                             double *sb, int lane) {

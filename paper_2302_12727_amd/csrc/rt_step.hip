@@ -27,6 +27,22 @@ inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) 
 #endif
 constexpr bool kOwnL = RT_TRANSPORT_OWN_LDS != 0;
 constexpr bool kPipe = RT_TRANSPORT_PIPE != 0;
+// GLF with the Hopkins surfaces keeps its own state and gradients in
+// registers and loads each stage just before it (256 VGPRs, 5 spilled): since
+// the inner loop was trimmed to 731 VALU instructions per slot, this form
+// saves the 24 KB of LDS reads of the own state per wave-iteration and ran
+// 4% faster than the LDS-resident pipelined one (4.10 against 4.27-4.29 ms
+// on the 3-group 128^3 lattice, same box).  The Ivanova and HLL forms keep
+// the LDS-resident own state (their register forms spill more).
+#ifndef RT_TRANSPORT_GLF_REGS
+#define RT_TRANSPORT_GLF_REGS 1
+#endif
+constexpr bool own_lds(bool hll, bool iva, int w) {
+    return (hll || iva) ? (kOwnL && (!hll || w > 1)) : (kOwnL && RT_TRANSPORT_GLF_REGS == 0);
+}
+constexpr bool pipe_on(bool hll, bool iva, int w) {
+    return (hll || iva) ? (kPipe && (!hll || w > 1)) : (kPipe && RT_TRANSPORT_GLF_REGS == 0);
+}
 
 // ---------------------------------------------------------------------------
 // Injection: E_g += dt sum_s xi_sg L_s / V_g, one thread per receiving particle.
@@ -210,7 +226,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     const int64_t ic = active ? i : n - 1;      // in-range index for inactive lanes
     const int64_t w = i0 >> 6;                  // neighbour-table wave (PW divides 64)
     const bool wave_live = i0 < n;              // wave-uniform
-    const double ibox = 1.0 / box, hc = 0.5 * c;
+    const double ibox = 1.0 / box, hc = 0.5 * c, c3 = 3.0 * c;
     if (threadIdx.x < 4) scnt[threadIdx.x] = 0;
     double *sb = stage[wv];
 
@@ -279,16 +295,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
         // of the next iteration's geometry (pa) and first group (pb), are in
         // flight in registers
         double2 pa[PIPE ? 8 : 1], pb[PIPE ? 8 : 1];
+        // pointers to this lane's pieces of the gradient-record lines of the 8
+        // neighbour rows it helps to move (PIPE: the rows of the stage in
+        // flight, replaced when the next iteration's are loaded)
+        const double *udp[8];
         if constexpr (PIPE) {
             if (kmax > 0) {
-                int64_t rn[8], rg[8];
+                int32_t rn[8];
+                const double *gp[8];
 #pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    rn[m] = __shfl(jn, 8 * m + (lane >> 3), 64);
-                    rg[m] = rn[m] * G + g0;
-                }
-                load_lines(geo, rn, lane, *reinterpret_cast<double2(*)[8]>(pa));
-                load_lines(UD, rg, lane, *reinterpret_cast<double2(*)[8]>(pb));
+                for (int m = 0; m < 8; ++m) rn[m] = __shfl(jn, 8 * m + (lane >> 3), 64);
+                row_ptrs(geo, rn, 1, 0, lane, gp);
+                row_ptrs(UD, rn, G, g0, lane, udp);
+                load_at(gp, 0, *reinterpret_cast<double2(*)[8]>(pa));
+                load_at(udp, 0, *reinterpret_cast<double2(*)[8]>(pb));
             }
         }
         for (int32_t kk = 0; kk < kmax; kk += Q) {
@@ -296,14 +316,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             const bool valid = k < nn;
             const int32_t j = jn;
             jn = k + Q < nn ? nbr[base + 64 * (int64_t)(k + Q)] : (int32_t)ic;
-            int64_t row[8];
-#pragma unroll
-            for (int m = 0; m < 8; ++m) row[m] = __shfl(j, 8 * m + (lane >> 3), 64);
             // pair geometry from the staged geometry records
             if constexpr (PIPE) {
                 store_lines(*reinterpret_cast<double2(*)[8]>(pa), sb, lane);
             } else {
-                stage_lines(geo, row, sb, lane);
+                int32_t rw[8];
+                const double *gp[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) rw[m] = __shfl(j, 8 * m + (lane >> 3), 64);
+                row_ptrs(geo, rw, 1, 0, lane, gp);
+                row_ptrs(UD, rw, G, g0, lane, udp);
+                double2 v[8];
+                load_at(gp, 0, v);
+                store_lines(v, sb, lane);
             }
             double rl[12];
 #pragma unroll
@@ -334,25 +359,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
                     double2(&vb)[8] = *reinterpret_cast<double2(*)[8]>(pb);
                     store_lines(vb, sb, lane);
                     if (g + 1 < GW) {
-                        int64_t rowg[8];
-#pragma unroll
-                        for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g0 + g + 1;
-                        load_lines(UD, rowg, lane, vb);
+                        load_at(udp, g + 1, vb);
                     } else if (kk + Q < kmax) {
-                        int64_t rn[8], rg[8];
+                        int32_t rn[8];
+                        const double *gp[8];
 #pragma unroll
-                        for (int m = 0; m < 8; ++m) {
-                            rn[m] = __shfl(jn, 8 * m + (lane >> 3), 64);
-                            rg[m] = rn[m] * G + g0;
-                        }
-                        load_lines(geo, rn, lane, *reinterpret_cast<double2(*)[8]>(pa));
-                        load_lines(UD, rg, lane, vb);
+                        for (int m = 0; m < 8; ++m) rn[m] = __shfl(jn, 8 * m + (lane >> 3), 64);
+                        row_ptrs(geo, rn, 1, 0, lane, gp);
+                        row_ptrs(UD, rn, G, g0, lane, udp);
+                        load_at(gp, 0, *reinterpret_cast<double2(*)[8]>(pa));
+                        load_at(udp, 0, vb);
                     }
                 } else {
-                    int64_t rowg[8];
-#pragma unroll
-                    for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g0 + g;
-                    stage_lines(UD, rowg, sb, lane);
+                    double2 v[8];
+                    load_at(udp, g, v);
+                    store_lines(v, sb, lane);
                 }
                 const double *Rl = sb + lane * kStage;
                 double qL[4], qR[4];
@@ -361,12 +382,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
                     const int q = 4 * g + m;
                     const double dk = di(q, 0) * pg.sx + di(q, 1) * pg.sy + di(q, 2) * pg.sz;
                     const double dl = Rl[4 + 3 * m] * pg.sx + Rl[5 + 3 * m] * pg.sy + Rl[6 + 3 * m] * pg.sz;
-                    const double mm = minmod(dk, dl);
+                    const double mm = minmod_med(dk, dl);
                     qL[m] = ui(q) + pg.fk * mm;
                     qR[m] = Rl[m] - pg.fl * mm;
                 }
-                const int f1 = guard64(qL[0], qL[1], qL[2], qL[3], c);
-                const int f2 = guard64(qR[0], qR[1], qR[2], qR[3], c);
+                // face guards and M1 fluxes: F_X.A = (FA_X, a_X A + b_X F_X)
+                double FAL, aL, bL, FAR, aR, bR;
+                const int f1 = face_m164(qL, pg.Ax, pg.Ay, pg.Az, c, c3, FAL, aL, bL);
+                const int f2 = face_m164(qR, pg.Ax, pg.Ay, pg.Az, c, c3, FAR, aR, bR);
                 double w1 = 0.5, w2 = 0.5, w3 = -hc * pg.An;   // GLF
                 if (HLL) {
                     double loL, hiL, loR, hiR;
@@ -376,15 +399,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
                                  loR, hiR);
                     hll_weights(loL, hiL, loR, hiR, pg.An, w1, w2, w3);
                 }
-                double FL[4], FR[4];
-                m1_flux64(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, FL);
-                m1_flux64(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, FR);
                 if (use) {
                     cE += (f1 & 1) + (f2 & 1);
                     cF += (f1 >> 1) + (f2 >> 1);
+                    // Phi.A = w1 F_L.A + w2 F_R.A + w3 (U_R - U_L), the vector part
+                    // (w1 a_L + w2 a_R) A + w1 b_L F_L + w2 b_R F_R + w3 (F_R - F_L)
+                    const double al = __builtin_fma(w1, aL, w2 * aR);
+                    const double bl = w1 * bL, br = w2 * bR;
+                    acc[4 * g] += wkl * __builtin_fma(w3, qR[0] - qL[0],
+                                                      __builtin_fma(w1, FAL, w2 * FAR));
+                    const double Av[3] = {pg.Ax, pg.Ay, pg.Az};
 #pragma unroll
-                    for (int m = 0; m < 4; ++m)
-                        acc[4 * g + m] += wkl * (w1 * FL[m] + w2 * FR[m] + w3 * (qR[m] - qL[m]));
+                    for (int m = 1; m < 4; ++m)
+                        acc[4 * g + m] +=
+                            wkl * __builtin_fma(w3, qR[m] - qL[m],
+                                                __builtin_fma(al, Av[m - 1],
+                                                              __builtin_fma(bl, qL[m], br * qR[m])));
                 }
             }
         }
@@ -643,8 +673,8 @@ void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double 
     const double2 *tab = (const double2 *)ctx->hll_table;
     const bool iva = ctx->surfaces == RT_IVANOVA;
 #define RT_TRANSPORT_LAUNCH(W, HLL_, IVA_)                                                    \
-    k_transport64<G, W, false, HLL_, IVA_, kQ, kOwnL && (!HLL_ || W > 1),                     \
-                  kPipe && (!HLL_ || W > 1)>                                                  \
+    k_transport64<G, W, false, HLL_, IVA_, kQ, own_lds(HLL_, IVA_, W),                        \
+                  pipe_on(HLL_, IVA_, W)>                                                     \
         <<<(unsigned)xcd_grid(nb * (G / W)), kBlock, 0, ctx->stream>>>(                       \
         n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,          \
         ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, ctx->status, 0,       \
@@ -687,8 +717,8 @@ void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, d
     const double2 *tab = (const double2 *)ctx->hll_table;
     const bool iva = ctx->surfaces == RT_IVANOVA;
 #define RT_TICK_LAUNCH(W, HLL_, IVA_)                                                          \
-    k_transport64<G, W, true, HLL_, IVA_, kQ, kOwnL && (!HLL_ || W > 1),                      \
-                  kPipe && (!HLL_ || W > 1)>                                                  \
+    k_transport64<G, W, true, HLL_, IVA_, kQ, own_lds(HLL_, IVA_, W),                         \
+                  pipe_on(HLL_, IVA_, W)>                                                     \
         <<<(unsigned)xcd_grid(nt * (G / W)), kBlock, 0, ctx->stream>>>(                        \
             n, nt, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,       \
             ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, ctx->status,    \
@@ -729,7 +759,7 @@ rt_status rt_ensure_partials(rt_ctx *ctx) {
     // up to 4 lanes per particle, so up to 4 blocks per kBlock particles)
     const int64_t nb = (4 * ctx->p.n + kBlock - 1) / kBlock;
     if (ctx->partials && ctx->nblocks >= nb) return RT_OK;
-    rt_free(ctx->partials);
+    rt_free(ctx, ctx->partials);
     ctx->partials = nullptr;
     // the rows, then the first pass of the finalize (kFinBlocks x 2G pairs)
     rt_status rs = rt_alloc(ctx, (void **)&ctx->partials,
