@@ -1,6 +1,6 @@
 """Benchmark of the photon transport step on one MI355X.
 
-Workload (default): 2^20 particles on a 128^3 lattice with +-0.1 spacing
+Workload (default): 2^21 particles on a 128^3 lattice with +-0.1 spacing
 jitter in the periodic unit box, 3 photon groups, 16 point sources at random
 particles with log-uniform luminosities in [1e-2, 1], reduced speed of light
 c = 1, CFL 0.9, FP64.  One step = injection -> gradient -> transport (with the
@@ -12,8 +12,10 @@ Metric: RT pair interactions per second = (unordered interacting pairs,
 r < max(H_k, H_l)) x steps / wall time of the timed steps.
 
 Prints one JSON line (rank 0).  Extra keys: roofline of the transport kernel,
-cpu_baseline (the FP64 oracle on a bounded sample of the same recipe), and
-per-kernel times.
+cpu_baseline (the FP64 oracle on a bounded sample of the same recipe),
+per-kernel times, and the other legs: FP32C, HLL, Ivanova, photon removal and
+drift, the 128^3 adjoint, the 2^22 Plummer FP32C-vs-FP64 and time-bin legs,
+and the 2^24 Plummer FP32C/FP64 adjoint (c5_adjoint).
 """
 from __future__ import annotations
 
@@ -50,10 +52,53 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg_index: int, min_seconds: float):
+_configs = {}
+
+
+def config(index: int):
+    """The seeded workload of a configuration, drawn once per process (the
+    clustered sets take tens of seconds to draw; the legs only read them)."""
+    import workloads
+    if index not in _configs:
+        t0 = time.time()
+        _configs[index] = workloads.config(index)
+        log(f"workload {_configs[index].name} drawn in {time.time() - t0:.1f} s")
+    return _configs[index]
+
+
+def host_cpu():
+    """CPU model and physical core count of the host (lscpu), and the CPUs this
+    process may run on (its affinity set)."""
+    import subprocess
+    info = {"model": None, "physical_cores": None, "logical_cpus": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        kv = {}
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        info["model"] = kv.get("Model name")
+        if kv.get("Core(s) per socket") and kv.get("Socket(s)"):
+            info["physical_cores"] = int(kv["Core(s) per socket"]) * int(kv["Socket(s)"])
+    except Exception as e:   # lscpu missing: report what is known
+        log(f"lscpu failed: {e}")
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        info["affinity_cpus"] = os.cpu_count()
+    return info
+
+
+def cpu_baseline(cfg_index: int, seconds: float):
     """The FP64 oracle as it stands, on a bounded sample of the same recipe:
     the 64^3 lattice (same jitter, groups and sources; same neighbour count per
-    particle, 1/8 of the particles), timed over whole steps."""
+    particle, 1/8 of the particles), timed over whole steps (inject + gradient
+    + transport), input generation and geometry excluded.  Three repetitions
+    each with P threads (the physical cores this process may use: the host's
+    physical cores, capped by its affinity set and OMP_NUM_THREADS) and with
+    one thread; the medians are reported.  About `seconds` of CPU time in all."""
+    import numpy as np
     import oracle
     import workloads
     w = workloads.config(cfg_index, scale=(64 ** 3) / (128 ** 3))
@@ -61,20 +106,42 @@ def cpu_baseline(cfg_index: int, min_seconds: float):
     geo = oracle.build_geometry(w.x)
     srcs = oracle.build_sources(geo, w.xs)
     log(f"cpu baseline: oracle geometry of {w.n} particles in {time.time() - t0:.1f} s")
-    U = w.U0.copy()
-    steps, t = 0, 0.0
-    while t < min_seconds or steps < 2:
+    cpu = host_cpu()
+    caps = [c for c in (cpu["physical_cores"], cpu["affinity_cpus"],
+                        int(os.environ["OMP_NUM_THREADS"]) if os.environ.get("OMP_NUM_THREADS")
+                        else None) if c]
+    P = max(1, min(caps)) if caps else oracle.num_threads()
+
+    def rate(threads, steps):
+        oracle.set_num_threads(threads)
+        U = w.U0.copy()
         t1 = time.perf_counter()
-        U, _ = oracle.step(geo, srcs, U, w.L)
-        t += time.perf_counter() - t1
-        steps += 1
+        for _ in range(steps):
+            U, _ = oracle.step(geo, srcs, U, w.L)
+        return geo.n_pairs * steps / (time.perf_counter() - t1)
+
+    # size the repetitions from one probe step at each thread count
+    r1 = rate(1, 1)
+    rP = rate(P, 1)
+    budget = seconds / 6.0                     # 3 repetitions x 2 thread counts
+    s1 = max(1, int(budget * r1 / geo.n_pairs))
+    sP = max(1, int(budget * rP / geo.n_pairs))
+    one = [rate(1, s1) for _ in range(3)]
+    par = [rate(P, sP) for _ in range(3)]
+    oracle.set_num_threads(P)
     return {
-        "value": geo.n_pairs * steps / t,
+        "value": float(np.median(par)),
         "unit": "pair-interactions/s",
-        "cores": oracle.num_threads(),
+        "cores": P,
         "kind": "oracle",
-        "sample": f"{w.n} particles (64^3 jittered lattice, 3 groups, 16 sources, same recipe), "
-                  f"{steps} full steps (inject+gradient+transport) in {t:.1f} s",
+        "one_thread_value": float(np.median(one)),
+        "runs": {"P_threads": par, "one_thread": one},
+        "cpu_model": cpu["model"],
+        "host_physical_cores": cpu["physical_cores"],
+        "affinity_cpus": cpu["affinity_cpus"],
+        "sample": f"{w.n} particles (64^3 jittered lattice, 3 groups, 16 sources, same recipe); "
+                  f"median of 3 runs of {sP} whole steps (inject + gradient + transport) on "
+                  f"{P} threads and of 3 runs of {s1} steps on 1 thread",
     }
 
 
@@ -172,7 +239,15 @@ def compare_precisions(w, dev):
         q = np.quantile(per, [0.5, 0.99, 0.999, 1.0])
         errs[name] = {"normwise": float(d.max() / mag.max()), "per_state_median": float(q[0]),
                       "per_state_p99": float(q[1]), "per_state_p999": float(q[2]),
-                      "per_state_max": float(q[3])}
+                      "per_state_max": float(q[3]),
+                      "fraction_above_1e-5": float((per > 1e-5).mean()),
+                      "states_above_1e-5": int((per > 1e-5).sum()),
+                      # the target is 1e-5 relative per state; it is met only
+                      # if every state meets it
+                      "per_state_target_1e-5_met": bool(q[3] <= 1e-5)}
+    errs["reference"] = ("the FP64 GPU path over the same steps (itself within 1e-12 "
+                         "of the FP64 oracle per state)")
+    errs["per_state_scale"] = "max(E, |F|/c) of the FP64 state, floored at 1e-6 of the mean E"
     errs["photon_total"] = float(np.abs(f32["Q"] / f64["Q"] - 1).max())
     errs["fp32c_own_photon_budget_residual"] = f32["photon_budget_residual"]
     h = f64["rt"].h
@@ -309,8 +384,7 @@ def large_adjoint(dev):
     gradients against those of the FP64 adjoint."""
     import numpy as np
     import torch
-    import workloads
-    w = workloads.config(4)
+    w = config(4)
     res = {}
     grads = {}
     for prec in ("fp32c", "fp64"):
@@ -332,7 +406,7 @@ def large_adjoint(dev):
     return res
 
 
-def run_adjoint(w, precision, dev, solver="glf"):
+def run_adjoint(w, precision, dev, solver="glf", reps=3):
     """Forward rollout of w.steps steps with checkpoints every w.ckpt_every,
     then its backward (segment recompute + adjoint); loss on the probe
     particles against E_target from a run at perturbed luminosities.
@@ -340,7 +414,7 @@ def run_adjoint(w, precision, dev, solver="glf"):
     import numpy as np
     import torch
     from paper_2302_12727_amd import RT
-    from paper_2302_12727_amd.rollout import rollout
+    from paper_2302_12727_amd.rollout import RolloutBuffers, rollout
 
     rt = RT(w.n, w.groups, precision=precision, cfl=w.cfl, c_red=w.c_red, device=dev)
     perm, *_ = rt.rt_build_cells(torch.from_numpy(w.x).to(dev))
@@ -358,32 +432,44 @@ def run_adjoint(w, precision, dev, solver="glf"):
         Et = Ut[pr, :, 0].double().clone()
     L = torch.from_numpy(w.L).to(dev).requires_grad_(True)
     U0g = U0.clone().requires_grad_(True)
-    # warm-up of both directions with the timed configuration, so that the
-    # checkpoint and record buffers are held by torch's caching allocator
-    # before the timed region (their first allocation made the forward time
-    # vary by up to 40%)
-    U = rollout(rt, L, U0g, w.steps, w.ckpt_every)
+    # the checkpoints, the kept records and the working states are allocated
+    # once, outside the timed region, and reused by every repetition
+    bufs = RolloutBuffers(rt, w.steps, w.ckpt_every)
+    # warm-up of both directions with the timed configuration
+    U = rollout(rt, L, U0g, w.steps, w.ckpt_every, bufs=bufs)
     U[pr, :, 0].double().sum().backward()
-    L.grad = None
-    U0g.grad = None
     torch.cuda.reset_peak_memory_stats(dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    U = rollout(rt, L, U0g, w.steps, w.ckpt_every)
-    loss = ((U[pr, :, 0].double() - Et) ** 2).sum()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    loss.backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    # forward and backward timed with HIP events on the stream the library
+    # and torch share, median of `reps` repetitions
+    fwd, bwd = [], []
+    for _ in range(reps):
+        L.grad = None
+        U0g.grad = None
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        e0.record()
+        U = rollout(rt, L, U0g, w.steps, w.ckpt_every, bufs=bufs)
+        loss = ((U[pr, :, 0].double() - Et) ** 2).sum()
+        e1.record()
+        loss.backward()
+        e2.record()
+        torch.cuda.synchronize()
+        fwd.append(e0.elapsed_time(e1))
+        bwd.append(e1.elapsed_time(e2))
     st = rt.rt_get_stats()
     gU0 = U0g.grad.double()
+    f, b = float(np.median(fwd)), float(np.median(bwd))
     return {"workload": w.name, "n": w.n, "groups": w.groups, "sources": int(w.xs.shape[0]),
             "steps": w.steps, "ckpt_every": w.ckpt_every, "precision": precision,
             "solver": solver,
-            "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
-            "adjoint_forward_ratio": (t2 - t1) / (t1 - t0),
-            "peak_hbm_GiB": (torch.cuda.max_memory_allocated(dev) + st["device_bytes"]) / 2 ** 30,
+            "forward_ms": f, "backward_ms": b, "forward_ms_per_step": f / w.steps,
+            "adjoint_forward_ratio": b / f,
+            "runs_ms": {"forward": fwd, "backward": bwd},
+            "timing": f"HIP events on the compute stream, median of {reps} repetitions",
+            # the library's own high-water mark (geometry, tables, scratch,
+            # the build's transient lists) plus torch's (states, records,
+            # checkpoints): an upper bound of the device memory in use at once
+            "peak_hbm_GiB": (torch.cuda.max_memory_allocated(dev) + st["device_bytes_peak"]) / 2 ** 30,
             "loss": float(loss.detach()), "grad": (L.grad.cpu().numpy(), gU0, p)}
 
 
@@ -397,9 +483,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="only the headline leg (no FP32C leg, no adjoint leg)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--large-adjoint", action="store_true",
-                    help="also run the 2^24-particle FP32C/FP64 adjoint case (about a minute)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the 2^24-particle FP32C/FP64 adjoint leg (about 2-3 minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also launch a plain device copy of 1 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -411,10 +497,8 @@ def main():
 
     import torch
 
-    import workloads
-
     dev = torch.device("cuda:0")
-    w = workloads.config(args.config)
+    w = config(args.config)
     G = w.groups
     log(f"workload {w.name}: n={w.n} G={G} S={w.xs.shape[0]} precision={args.precision}")
     fw = run_forward(w, args.precision, args.steps, args.warmup, dev)
@@ -463,7 +547,14 @@ def main():
                      "flops_per_pair": transport_flops_per_pair(G),
                      "algorithmic_bytes_per_launch": transport_bytes_per_particle(G, elem) * w.n,
                      "hbm_frac_at_algorithmic_bytes":
-                         transport_bytes_per_particle(G, elem) * w.n / tr_avg / PEAK_HBM},
+                         transport_bytes_per_particle(G, elem) * w.n / tr_avg / PEAK_HBM,
+                     "hbm_frac": (traffic / tr_avg / PEAK_HBM) if traffic else None,
+                     # 'alu' is the binding roofline at the algorithmic counts
+                     # (flop/byte above the ridge); what the counters show
+                     # holding the kernel back is latency and LDS traffic
+                     "limiter": "memory latency and LDS staging (rocprofv3 counters): "
+                                "the SIMDs are about half VALU-busy",
+                     "target_frac": 0.5, "target_met": bool(achieved / peak >= 0.5)},
         "kernel_ms": {"transport": fw["transport_ms"], "gradient": fw["gradient_ms"],
                       "inject": fw["inject_ms"]},
         "build_ms": fw["build_ms"],
@@ -513,7 +604,7 @@ def main():
             del fi
         out["absorb"] = absorb_leg(w, dev)
         torch.cuda.empty_cache()
-        wa = workloads.config(3)
+        wa = config(3)
         ad = run_adjoint(wa, "fp64", dev)
         ad.pop("grad")
         ad["workload"] += " (128^3 jittered lattice, 3 groups, 64 sources, 4096 probes)"
@@ -525,17 +616,17 @@ def main():
             out["hll"]["adjoint"] = {k: ah[k] for k in ("forward_ms", "backward_ms",
                                                         "adjoint_forward_ratio", "peak_hbm_GiB")}
             torch.cuda.empty_cache()
-        out["plummer_fp32c_vs_fp64"] = compare_precisions(workloads.config(2), dev)
+        out["plummer_fp32c_vs_fp64"] = compare_precisions(config(2), dev)
         torch.cuda.empty_cache()
-        out["plummer_time_bins"] = compare_time_bins(workloads.config(2), dev)
+        out["plummer_time_bins"] = compare_time_bins(config(2), dev)
         torch.cuda.empty_cache()
-        tb = compare_time_bins(workloads.config(2), dev, precision="fp32c")
+        tb = compare_time_bins(config(2), dev, precision="fp32c")
         out["plummer_time_bins"]["fp32c"] = {k: tb[k] for k in (
             "binned_ms", "global_ms", "speedup", "binned_due_pairs_per_s", "global_pairs_per_s",
             "E_difference_binned_vs_global")}
         torch.cuda.empty_cache()
-    if args.large_adjoint:
-        out["large_adjoint"] = large_adjoint(dev)
+    if not args.no_extra and not args.no_c5:
+        out["c5_adjoint"] = large_adjoint(dev)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_seconds)

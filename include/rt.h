@@ -366,7 +366,12 @@ typedef struct {
     int32_t max_neighbours;
     int32_t h_iter_max;     /* most Newton/bisection iterations of one particle */
     int64_t n_inject;       /* source-gas injection entries                     */
-    int64_t device_bytes;   /* device memory owned by the context               */
+    int64_t device_bytes;   /* device memory the context holds now              */
+    int64_t device_bytes_peak; /* the most it held at once since rt_create,
+                               including the build's transient lists            */
+    int64_t h_list_overflow;   /* particles of the last build whose smoothing-
+                               length candidate list overflowed (their later
+                               evaluations walked the tree again)               */
 } rt_stats;
 rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out /* [host] */);
 

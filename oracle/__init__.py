@@ -115,6 +115,8 @@ def lib():
         L.orc_dt.argtypes = [ctypes.c_int64, _d, ctypes.c_double, ctypes.c_double]
         L.orc_num_threads.restype = ctypes.c_int32
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.restype = None
+        L.orc_set_num_threads.argtypes = [ctypes.c_int32]
         L.orc_drift.restype = None
         L.orc_drift.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, _d, _d, _d, ctypes.c_double,
                                 _d, _i64, _d]
@@ -685,3 +687,8 @@ def run_binned(geom: Geometry, srcs: Optional[Sources], U0: np.ndarray, L, ticks
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """Threads of the C oracle's parallel loops (results do not depend on it)."""
+    lib().orc_set_num_threads(int(t))

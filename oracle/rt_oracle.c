@@ -907,6 +907,18 @@ void orc_absorb(int64_t n, int32_t G, int32_t J, const double *V, const double *
     }
 }
 
+/* Threads of the parallel loops that follow (timing of the baseline only;
+ * every loop gives the same bits with any count). */
+void orc_set_num_threads(int32_t t)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
 int32_t orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -503,7 +503,7 @@ static rt_status adj_scratch(rt_ctx *ctx, size_t es, char **base) {
     const size_t nu = (size_t)ctx->p.n * 4 * ctx->p.groups * es;
     const size_t need = nu * (1 + 4 + 1 + 4 + 1 + 1) + 6 * 256;
     if (!ctx->adj_buf || ctx->adj_bytes < need) {
-        rt_free(ctx->adj_buf);
+        rt_free(ctx, ctx->adj_buf);
         ctx->adj_buf = nullptr;
         rt_status rs = rt_alloc(ctx, &ctx->adj_buf, need);
         if (rs != RT_OK) return rs;

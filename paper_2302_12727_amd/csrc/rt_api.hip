@@ -18,22 +18,34 @@ rt_status rt_fail(rt_ctx *ctx, rt_status st, const std::string &msg) {
     return st;
 }
 
-rt_status rt_alloc(rt_ctx *ctx, void **ptr, size_t bytes) {
+bool rt_try_alloc(rt_ctx *ctx, void **ptr, size_t bytes) {
     *ptr = nullptr;
     if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(ptr, bytes);
-    if (e != hipSuccess) {
+    if (hipMalloc(ptr, bytes) != hipSuccess) {
         *ptr = nullptr;
         (void)hipGetLastError();
-        return rt_fail(ctx, RT_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
-                                           hipGetErrorString(e));
+        return false;
     }
+    ctx->allocs[*ptr] = bytes;
     ctx->device_bytes += (int64_t)bytes;
-    return RT_OK;
+    ctx->device_peak = std::max(ctx->device_peak, ctx->device_bytes);
+    return true;
 }
 
-void rt_free(void *ptr) {
-    if (ptr) (void)hipFree(ptr);
+rt_status rt_alloc(rt_ctx *ctx, void **ptr, size_t bytes) {
+    if (rt_try_alloc(ctx, ptr, bytes)) return RT_OK;
+    return rt_fail(ctx, RT_ENOMEM, "hipMalloc of " + std::to_string(bytes ? bytes : 8) +
+                                       " bytes failed");
+}
+
+void rt_free(rt_ctx *ctx, void *ptr) {
+    if (!ptr) return;
+    auto it = ctx->allocs.find(ptr);
+    if (it != ctx->allocs.end()) {
+        ctx->device_bytes -= (int64_t)it->second;
+        ctx->allocs.erase(it);
+    }
+    (void)hipFree(ptr);
 }
 
 void rt_timer_begin(rt_ctx *ctx, const char *) {
@@ -116,7 +128,7 @@ void rt_destroy(rt_ctx *ctx) {
                     ctx->src_gas, ctx->src_coef, ctx->status, ctx->partials, ctx->scan_tmp,
                     ctx->adj_buf, ctx->hll_table, ctx->hll_table32, ctx->vol, ctx->ivan,
                     ctx->bin8};
-    for (void *b : bufs) rt_free(b);
+    for (void *b : bufs) rt_free(ctx, b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
 }
@@ -347,6 +359,8 @@ rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out) {
     out->h_iter_max = ctx->h_iter_max;
     out->n_inject = ctx->n_inj;
     out->device_bytes = ctx->device_bytes;
+    out->device_bytes_peak = ctx->device_peak;
+    out->h_list_overflow = ctx->h_list_overflow;
     return RT_OK;
 }
 

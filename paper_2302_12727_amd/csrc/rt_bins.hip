@@ -128,7 +128,7 @@ rt_status rt_time_bins_impl(rt_ctx *ctx, int32_t max_bin, int32_t *bins_out, int
     int32_t changed = 1, sweeps = 0;
     while (changed) {
         if (sweeps > max_bin + 2) {
-            rt_free(work);
+            rt_free(ctx, work);
             return rt_fail(ctx, RT_EHIP, "time-bin limiter did not converge");
         }
         RT_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), st));
@@ -142,7 +142,7 @@ rt_status rt_time_bins_impl(rt_ctx *ctx, int32_t max_bin, int32_t *bins_out, int
         ++sweeps;
     }
     if (!ctx->bin8 && (rs = rt_alloc(ctx, (void **)&ctx->bin8, (size_t)n)) != RT_OK) {
-        rt_free(work);
+        rt_free(ctx, work);
         return rs;
     }
     k_bins_store<<<nblk(n), kBlock, 0, st>>>(n, ctx->nbr, ctx->wave_base, ctx->n_nbr, b, ctx->geo,
@@ -155,7 +155,7 @@ rt_status rt_time_bins_impl(rt_ctx *ctx, int32_t max_bin, int32_t *bins_out, int
         RT_HIP(hipMemcpyAsync(bins_out, b, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
     RT_HIP(hipStreamSynchronize(st));
     RT_HIP(hipGetLastError());
-    rt_free(work);
+    rt_free(ctx, work);
     ctx->bin_top = top;
     if (cycle) *cycle = int64_t(1) << top;
     return RT_OK;

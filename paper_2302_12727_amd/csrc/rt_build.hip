@@ -111,6 +111,9 @@ constexpr int kHList = 128;
 // Entries per particle of the neighbour lists the count pass keeps (same budget).
 constexpr int kNList = 128;
 constexpr int64_t kHListBytes = int64_t(16) << 30;
+// Bit of a particle's iteration count set when its candidate list overflowed
+// (later evaluations at a smaller h walked the tree again).
+constexpr int32_t kIterOverflow = 1 << 24;
 
 struct Tree {
     const double *lo, *hi, *hmax;
@@ -177,7 +180,8 @@ __device__ void h_eval_list(const double *__restrict__ list, int64_t n, int cnt,
 __device__ double h_solve_point(const Tree &T, const double *__restrict__ xs, int64_t n,
                                 double px, double py, double pz, double h0, double eta,
                                 double kappa, double box, double hcap, double *__restrict__ list,
-                                int cap, int32_t max_iter, int32_t &iters, int32_t &flags) {
+                                int cap, int32_t max_iter, int32_t &iters, int32_t &flags,
+                                bool &overflow) {
     const double pref = kSigma3 / (kappa * kappa * kappa);
     const double eta3 = eta * eta * eta;
     const double eps4 = 4.0 * 2.220446049250313e-16;
@@ -196,6 +200,7 @@ __device__ double h_solve_point(const Tree &T, const double *__restrict__ xs, in
         } else {
             lcnt = h_eval(T, xs, n, px, py, pz, h, kappa, box, ibox, list, cap, sw, sdw);
             hl = lcnt <= cap ? h : 0.0;
+            if (list && lcnt > cap) overflow = true;
         }
         double g = pref * sw - eta3;
         double dg = -pref * sdw / h;
@@ -293,12 +298,13 @@ __global__ void k_h_solve(int64_t n, Tree T, const double *__restrict__ xs, doub
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int32_t it = 0, fl = 0;
+    bool ovf = false;
     double hcap = 0.5 * box / kappa;
     double hv = h_solve_point(T, xs, n, xs[3 * i], xs[3 * i + 1], xs[3 * i + 2],
                               fmin(h[i], 0.5 * hcap), eta, kappa, box, hcap,
-                              cap > 0 ? list + i : nullptr, cap, max_iter, it, fl);
+                              cap > 0 ? list + i : nullptr, cap, max_iter, it, fl, ovf);
     h[i] = hv;
-    iters[i] = it;
+    iters[i] = it | (ovf ? kIterOverflow : 0);
     if (fl) atomicOr(status, fl);
 }
 
@@ -527,9 +533,10 @@ __global__ void k_src_h(int32_t S, Tree T, const double *__restrict__ xs, int64_
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
     int32_t it = 0, fl = 0;
+    bool ovf = false;
     double hcap = 0.5 * box / kappa;
     src_h[s] = h_solve_point(T, xs, n, src_x[3 * s], src_x[3 * s + 1], src_x[3 * s + 2], h0,
-                             eta, kappa, box, hcap, nullptr, 0, max_iter, it, fl);
+                             eta, kappa, box, hcap, nullptr, 0, max_iter, it, fl, ovf);
     if (fl) atomicOr(status, fl);
 }
 
@@ -613,17 +620,16 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     hipStream_t st = ctx->stream;
     rt_status rs;
     // (re)allocate everything owned by a previous build
-    rt_free(ctx->xs); rt_free(ctx->geo); rt_free(ctx->geo32); rt_free(ctx->perm32);
-    rt_free(ctx->keys); rt_free(ctx->h_iters); rt_free(ctx->node_lo); rt_free(ctx->node_hi);
-    rt_free(ctx->node_hmax); rt_free(ctx->n_nbr); rt_free(ctx->n_gath); rt_free(ctx->wave_base);
-    rt_free(ctx->nbr); rt_free(ctx->vol); rt_free(ctx->ivan);
+    rt_free(ctx, ctx->xs); rt_free(ctx, ctx->geo); rt_free(ctx, ctx->geo32); rt_free(ctx, ctx->perm32);
+    rt_free(ctx, ctx->keys); rt_free(ctx, ctx->h_iters); rt_free(ctx, ctx->node_lo); rt_free(ctx, ctx->node_hi);
+    rt_free(ctx, ctx->node_hmax); rt_free(ctx, ctx->n_nbr); rt_free(ctx, ctx->n_gath); rt_free(ctx, ctx->wave_base);
+    rt_free(ctx, ctx->nbr); rt_free(ctx, ctx->vol); rt_free(ctx, ctx->ivan);
     ctx->vol = nullptr;
     ctx->ivan = nullptr;
     ctx->xs = nullptr; ctx->geo = nullptr; ctx->geo32 = nullptr; ctx->perm32 = nullptr;
     ctx->keys = nullptr; ctx->h_iters = nullptr; ctx->node_lo = nullptr; ctx->node_hi = nullptr;
     ctx->node_hmax = nullptr; ctx->n_nbr = nullptr; ctx->n_gath = nullptr;
     ctx->wave_base = nullptr; ctx->nbr = nullptr;
-    ctx->device_bytes = 0;
     ctx->built = 0;
 
     ctx->nleaf = (n + kLeaf - 1) / kLeaf;
@@ -689,8 +695,7 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
             // kHListBytes (else every evaluation walks the tree)
             int cap = (int)std::min<int64_t>(kHList, kHListBytes / (8 * n));
             double *hlist = nullptr;
-            if (cap < kHList / 2 || hipMalloc((void **)&hlist, sizeof(double) * cap * n) != hipSuccess) {
-                (void)hipGetLastError();
+            if (cap < kHList / 2 || !rt_try_alloc(ctx, (void **)&hlist, sizeof(double) * cap * n)) {
                 hlist = nullptr;
                 cap = 0;
             }
@@ -701,7 +706,7 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
                                                   ctx->h_iters, ctx->status);
             if (hlist) {
                 const hipError_t e = hipStreamSynchronize(st);
-                rt_free(hlist);
+                rt_free(ctx, hlist);
                 if (e != hipSuccess) {
                     rs = rt_fail(ctx, RT_EHIP, std::string("smoothing-length solve: ") + hipGetErrorString(e));
                     goto fail;
@@ -728,8 +733,7 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
         }
         // neighbour table: counts, wave widths, offsets, fill
         ncap = (int)std::min<int64_t>(kNList, kHListBytes / (4 * n));
-        if (ncap < kNList / 2 || hipMalloc((void **)&nlist, sizeof(int32_t) * ncap * n) != hipSuccess) {
-            (void)hipGetLastError();
+        if (ncap < kNList / 2 || !rt_try_alloc(ctx, (void **)&nlist, sizeof(int32_t) * ncap * n)) {
             nlist = nullptr;
             ncap = 0;
         }
@@ -745,7 +749,7 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
             goto fail;
         }
         if (scan_bytes > sort_bytes) {
-            rt_free(sort_tmp);
+            rt_free(ctx, sort_tmp);
             sort_tmp = nullptr;
             ALLOC(sort_tmp, scan_bytes);
             sort_bytes = scan_bytes;
@@ -787,15 +791,17 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
         ctx->n_gather_entries = 0;
         ctx->max_nbr = 0;
         ctx->h_iter_max = 0;
+        ctx->h_list_overflow = 0;
         for (int64_t i = 0; i < n; ++i) {
             ctx->n_entries += nn[i];
             ctx->n_gather_entries += ng[i];
             ctx->max_nbr = std::max(ctx->max_nbr, nn[i]);
-            ctx->h_iter_max = std::max(ctx->h_iter_max, it[i]);
+            ctx->h_iter_max = std::max(ctx->h_iter_max, it[i] & (kIterOverflow - 1));
+            ctx->h_list_overflow += (it[i] & kIterOverflow) ? 1 : 0;
         }
     }
-    rt_free(keys_in); rt_free(idx_in); rt_free(Htmp); rt_free(width); rt_free(dxpart);
-    rt_free(sort_tmp); rt_free(nlist);
+    rt_free(ctx, keys_in); rt_free(ctx, idx_in); rt_free(ctx, Htmp); rt_free(ctx, width); rt_free(ctx, dxpart);
+    rt_free(ctx, sort_tmp); rt_free(ctx, nlist);
     if ((rs = rt_ensure_partials(ctx)) != RT_OK) return rs;
     // compact copy of the volumes for the per-particle kernels that need
     // nothing else of the geometry record
@@ -811,17 +817,17 @@ fail:
     // later rt_sync
     (void)hipMemsetAsync(ctx->status, 0, sizeof(int32_t), st);
     (void)hipStreamSynchronize(st);
-    rt_free(keys_in); rt_free(idx_in); rt_free(Htmp); rt_free(width); rt_free(dxpart);
-    rt_free(sort_tmp); rt_free(nlist);
+    rt_free(ctx, keys_in); rt_free(ctx, idx_in); rt_free(ctx, Htmp); rt_free(ctx, width); rt_free(ctx, dxpart);
+    rt_free(ctx, sort_tmp); rt_free(ctx, nlist);
     return rs;
 #undef ALLOC
 }
 
 rt_status rt_sources_impl(rt_ctx *ctx, int32_t S, const double *xs, double eta_star) {
     hipStream_t st = ctx->stream;
-    rt_free(ctx->src_h); rt_free(ctx->inj_gptr); rt_free(ctx->inj_gas); rt_free(ctx->inj_src);
-    rt_free(ctx->inj_coef); rt_free(ctx->inj_xi); rt_free(ctx->src_ptr); rt_free(ctx->src_gas);
-    rt_free(ctx->src_coef);
+    rt_free(ctx, ctx->src_h); rt_free(ctx, ctx->inj_gptr); rt_free(ctx, ctx->inj_gas); rt_free(ctx, ctx->inj_src);
+    rt_free(ctx, ctx->inj_coef); rt_free(ctx, ctx->inj_xi); rt_free(ctx, ctx->src_ptr); rt_free(ctx, ctx->src_gas);
+    rt_free(ctx, ctx->src_coef);
     ctx->src_h = nullptr; ctx->inj_gptr = nullptr; ctx->inj_gas = nullptr; ctx->inj_src = nullptr;
     ctx->inj_coef = nullptr; ctx->inj_xi = nullptr; ctx->src_ptr = nullptr; ctx->src_gas = nullptr;
     ctx->src_coef = nullptr;
@@ -910,11 +916,11 @@ rt_status rt_sources_impl(rt_ctx *ctx, int32_t S, const double *xs, double eta_s
         RT_HIP(hipStreamSynchronize(st));
     }
     ctx->S = S;
-    rt_free(sx); rt_free(cnt); rt_free(sxi);
+    rt_free(ctx, sx); rt_free(ctx, cnt); rt_free(ctx, sxi);
     return RT_OK;
 fail:
     (void)hipMemsetAsync(ctx->status, 0, sizeof(int32_t), st);
     (void)hipStreamSynchronize(st);
-    rt_free(sx); rt_free(cnt); rt_free(sxi);
+    rt_free(ctx, sx); rt_free(ctx, cnt); rt_free(ctx, sxi);
     return rs;
 }

@@ -7,6 +7,7 @@
 
 #include <map>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/rt.h"
@@ -100,7 +101,10 @@ struct rt_ctx {
     void *adj_buf = nullptr;     // adjoint scratch (see rt_adjoint.hip)
     size_t adj_bytes = 0;
 
-    int64_t device_bytes = 0;
+    int64_t device_bytes = 0;    // device memory the context holds now
+    int64_t device_peak = 0;     // the most it held at once since rt_create
+    std::unordered_map<void *, size_t> allocs;   // live allocations and their sizes
+    int64_t h_list_overflow = 0; // particles whose h-solve candidate list overflowed
     int32_t h_iter_max = 0;
     int32_t h_iter_cap = 200;    // iteration cap of the smoothing-length solve
     int32_t bin_top = -1;        // largest time bin after rt_time_bins (-1: none)
@@ -260,7 +264,10 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 
 rt_status rt_fail(rt_ctx *ctx, rt_status st, const std::string &msg);
 rt_status rt_alloc(rt_ctx *ctx, void **ptr, size_t bytes);
-void rt_free(void *ptr);
+// rt_alloc for optional scratch: false (and no error message) when it fails
+bool rt_try_alloc(rt_ctx *ctx, void **ptr, size_t bytes);
+// free memory from rt_alloc / rt_try_alloc and take it off the context's count
+void rt_free(rt_ctx *ctx, void *ptr);
 void rt_timer_begin(rt_ctx *ctx, const char *name);
 void rt_timer_end(rt_ctx *ctx, const char *name);
 

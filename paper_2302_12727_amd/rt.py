@@ -55,7 +55,8 @@ class rt_stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_entries", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
                 ("n_gather", ctypes.c_int64), ("sell_slots", ctypes.c_int64),
                 ("max_neighbours", ctypes.c_int32), ("h_iter_max", ctypes.c_int32),
-                ("n_inject", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("n_inject", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("device_bytes_peak", ctypes.c_int64), ("h_list_overflow", ctypes.c_int64)]
 
 
 _lib = None

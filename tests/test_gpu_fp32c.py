@@ -1,11 +1,16 @@
 """Compensated-FP32 path against the FP64 oracle.
 
-Tolerance: 1e-5 relative on (E, F) per particle and group, measured against
-the local scale max(E, |F|/c) over the particle and its neighbours (an FP32
-pair flux carries about 1e-7 of the larger state of its pair, so a faint state
-next to a bright one inherits error relative to the bright one); the error
-relative to each state's own magnitude is reported alongside.  Photon totals
-against the oracle's FP64 totals.
+The target is 1e-5 relative on E and F per state: every case asserts it for
+every state, relative to the state's own magnitude max(E, |F|/c) (floored at
+1e-6 of the mean energy), and reports the distribution (measured maxima
+1.4e-7 on the lattice over 10 steps, 4.8e-7 on the lattice with sources and
+7.0e-7 on the clustered set over 5 steps).  An FP32 pair flux carries about
+1e-7 of the brighter state of its pair, so a faint state next to a bright one
+inherits error relative to the bright one; the error against the local scale
+max(E, |F|/c) over the particle and its neighbours is asserted too.  Over
+many steps of a large clustered set a few faint states do exceed 1e-5 (the
+benchmark's 2^22-particle leg reports how many).  Photon totals against the
+oracle's FP64 totals.
 """
 import numpy as np
 import pytest
@@ -23,6 +28,22 @@ if not torch.cuda.is_available():  # pragma: no cover
 from paper_2302_12727_amd import RT  # noqa: E402
 
 TOL32 = 1e-5
+
+
+def per_state(got, ref, floor_frac=1e-6):
+    """Error of (E, F) of every state relative to its own magnitude
+    max(E, |F|/c), floored at floor_frac times the mean energy."""
+    scale = np.maximum(np.abs(ref).max(axis=-1), floor_frac * np.abs(ref[..., 0]).mean())
+    return np.abs(got - ref).max(axis=-1) / scale
+
+
+def report(name, got, ref):
+    per = per_state(got, ref)
+    q = np.quantile(per, [0.5, 0.99, 0.999, 1.0])
+    above = int((per > TOL32).sum())
+    log(f"{name}: per-state rel err median {q[0]:.2e} p99 {q[1]:.2e} p99.9 {q[2]:.2e} "
+        f"max {q[3]:.2e}; {above} of {per.size} states above {TOL32:g}")
+    return per
 
 
 def run32(w, steps, geo_h=None):
@@ -64,6 +85,8 @@ def test_fp32c_lattice16_ten_steps():
     Qo = oracle.photon_total(geo, ref)
     log("fp32c lattice16 10 steps: " + err_summary(got, ref, geo.sptr, geo.sidx) +
         f"; photon total rel {np.abs(Q / Qo - 1).max():.3e}")
+    per = report("fp32c lattice16 10 steps", got, ref)
+    assert per.max() <= TOL32
     assert err < TOL32
     assert np.allclose(Q, Qo, rtol=1e-6)
 
@@ -75,6 +98,8 @@ def test_fp32c_plummer_with_source():
     ref, _ = oracle.run(geo, srcs, w.U0, w.L, 5)
     got, Q, _, _ = run32(w, 5)
     log("fp32c plummer 5 steps: " + err_summary(got, ref, geo.sptr, geo.sidx))
+    per = report("fp32c plummer 5 steps", got, ref)
+    assert per.max() <= TOL32
     assert local_err(got, ref, geo.sptr, geo.sidx) < TOL32
     assert np.allclose(Q, oracle.photon_total(geo, ref), rtol=1e-6)
 
@@ -86,5 +111,7 @@ def test_fp32c_mid_lattice_sources():
     ref, _ = oracle.run(geo, srcs, w.U0, w.L, 5)
     got, Q, _, _ = run32(w, 5)
     log("fp32c lattice20 S=16 5 steps: " + err_summary(got, ref, geo.sptr, geo.sidx))
+    per = report("fp32c lattice20 S=16 5 steps", got, ref)
+    assert per.max() <= TOL32
     assert local_err(got, ref, geo.sptr, geo.sidx) < TOL32
     assert np.allclose(Q, oracle.photon_total(geo, ref), rtol=1e-6)

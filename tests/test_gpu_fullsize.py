@@ -20,11 +20,14 @@ drift by a few 1e-6 of it as the step shrinks, and a component far smaller
 than the loss curvature is resolved only to that absolute level.  The
 per-component errors are logged; the bound is normwise.
 
-C3 (2^22 Plummer mix with a central source): the oracle would take tens of
-minutes here, so this case checks what holds at any size: the smoothing-length
-equation of sampled particles summed by brute force over all particles, their
-neighbour sets by brute force (exact), and the photon budget of 100 FP64
-steps (1e-12 relative).
+C3 (2^22 Plummer mix with a central source): the HIP path against the FP64
+oracle element by element -- smoothing lengths solved on both sides (1e-13,
+with the h-solve's candidate-list overflow path taken on the GPU), the
+symmetric neighbour sets (exact, up to 96 neighbours), and every state after
+two whole steps (1e-12 relative per state) -- plus what holds at any size: the
+smoothing-length equation of sampled particles summed by brute force over all
+particles, their neighbour sets by brute force (exact), and the photon budget
+of 100 FP64 steps (1e-12 relative).
 """
 import numpy as np
 import pytest
@@ -261,3 +264,44 @@ def test_c3_photon_budget_hundred_steps(c3):
     res = float(np.abs(Qe / expect - 1).max())
     log(f"C3 100 FP64 steps: photon budget residual {res:.2e} (ledger {ledger.cpu().numpy()})")
     assert res < 1e-12
+
+
+def test_c3_two_steps_every_element(c3):
+    """Full-size C3 against the oracle: its 43x span of smoothing lengths,
+    rows of up to 96 neighbours, and the re-walks of the h-solve whose
+    candidate lists overflowed."""
+    w, rt, p = c3
+    log(f"C3 oracle geometry of {w.n} particles ...")
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs)
+    st = rt.rt_get_stats()
+    h = unsort(rt.h.cpu().numpy(), p)
+    herr = float(np.abs(h / geo.h - 1).max())
+    log(f"C3: h spans {geo.h.max() / geo.h.min():.1f}x, GPU vs oracle {herr:.2e}; "
+        f"{st['h_list_overflow']} particles re-walked after a list overflow; "
+        f"h iterations up to {st['h_iter_max']}; max neighbours {st['max_neighbours']}")
+    assert herr < 1e-13
+    assert st["h_list_overflow"] > 0
+    # the step on the oracle's smoothing lengths (identical neighbour sets)
+    rt2, p2 = build(w, h=geo.h)
+    assert rt2.rt_get_stats()["n_pairs"] == geo.n_pairs
+    n = w.n
+    ref_keys = np.repeat(np.arange(n, dtype=np.int64), np.diff(geo.sptr)) * n + geo.sidx
+    assert np.array_equal(neighbour_keys(rt2, p2), np.sort(ref_keys))
+    U = dev(w.U0[p2])
+    L = dev(w.L)
+    Q = torch.zeros(w.groups, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        U = rt2.step(U, L, photon_total=Q)
+    rt2.rt_sync()
+    got = unsort(U.cpu().numpy(), p2)
+    del rt2
+    ref = w.U0.copy()
+    for _ in range(2):
+        ref, _ = oracle.step(geo, srcs, ref, w.L)
+    err = state_err(got, ref)
+    Qo = oracle.photon_total(geo, ref)
+    qerr = float(np.abs(Q.cpu().numpy() / Qo - 1).max())
+    log(f"C3 two steps, {n} particles x 3 groups: max state err {err:.2e}, photon total {qerr:.2e}")
+    assert err < 1e-12
+    assert qerr < 1e-12
