@@ -127,7 +127,7 @@ void rt_destroy(rt_ctx *ctx) {
                     ctx->inj_gas, ctx->inj_src, ctx->inj_coef, ctx->inj_xi, ctx->src_ptr,
                     ctx->src_gas, ctx->src_coef, ctx->status, ctx->partials, ctx->scan_tmp,
                     ctx->adj_buf, ctx->hll_table, ctx->hll_table32, ctx->vol, ctx->ivan,
-                    ctx->bin8};
+                    ctx->bin8, ctx->task, ctx->n_task};
     for (void *b : bufs) rt_free(ctx, b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;

@@ -77,6 +77,8 @@ struct rt_ctx {
     int32_t *n_gath = nullptr;   // [n]
     int64_t *wave_base = nullptr;// [nwaves + 1]
     int32_t *nbr = nullptr;      // [slots]
+    int32_t *task = nullptr;     // [slots] task lists of the FP64 tile transport (same slots)
+    int32_t *n_task = nullptr;   // [n]
 
     // sources
     int32_t S = 0;

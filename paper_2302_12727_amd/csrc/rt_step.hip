@@ -512,6 +512,230 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     }
 }
 
+// Transport with the pairs inside a tile evaluated once (FP64, GLF, Hopkins
+// surfaces, one global step, all G <= 3 groups in one wave).
+//
+// A wave owns one tile: the 64 consecutive Morton particles of one column
+// block of the neighbour table.  It treats the tile in 4 passes of 16
+// particles with 4 lanes each (so a pass keeps the cache footprint of the
+// two-sided kernel).  A particle's task list (k_tasks, built with the
+// geometry) holds its neighbours outside the tile and its share of the pairs
+// inside it: an in-tile pair (k, l) is evaluated by one of its particles only
+// (chosen to balance the lists' lengths), flagged by the sign bit.  That lane
+// adds Phi_kl to its own sum and -Phi_kl, by an LDS
+// atomic add, to the other particle's row of the wave's accumulator; the
+// pair's face states are the same from either side, so its face-guard counts
+// are taken twice.  Each pass ends by adding its particles' own sums to their
+// rows; after the last pass lane L updates particle L of the tile.  The
+// in-tile pair flux is antisymmetric bit for bit.  49.5% of the neighbour
+// entries of the 128^3 lattice lie inside their tile, so a step evaluates
+// 75% of the pair fluxes of the two-sided kernel.
+constexpr int32_t kTaskMirror = int32_t(0x80000000u);
+
+template <int G>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
+                   const int32_t *__restrict__ task, const int64_t *__restrict__ wave_base,
+                   const int32_t *__restrict__ n_task, const double *__restrict__ UD,
+                   const double *__restrict__ dtp, double c, double box,
+                   double *__restrict__ Uout, double *__restrict__ partials,
+                   unsigned long long *__restrict__ counts, double *__restrict__ Uung,
+                   int32_t *__restrict__ status) {
+    constexpr int NQ = 4 * G, MS = NQ + 1;     // accumulator row, padded against bank conflicts
+    __shared__ double stage[kBlock / 64][64 * kStage];
+    __shared__ double mir[kBlock / 64][64 * MS];
+    __shared__ double smem[(kBlock / 64) * 2 * G];
+    __shared__ unsigned long long scnt[4];
+    const int64_t blk = xcd_block(nb);
+    if (blk >= nb) return;                      // whole block: no barrier is skipped
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int sub = lane & 3;
+    const int64_t w = blk * (kBlock / 64) + wv; // the wave's tile
+    const int64_t t0 = w * 64;                  // its first particle
+    const bool wave_live = t0 < n;              // wave-uniform
+    const double ibox = 1.0 / box, hc = 0.5 * c, c3 = 3.0 * c;
+    if (threadIdx.x < 4) scnt[threadIdx.x] = 0;
+    double *sb = stage[wv];
+    double *mw = mir[wv];
+    for (int e = lane; e < 64 * MS; e += 64) mw[e] = 0.0;
+    wave_lds_sync();
+    int cE = 0, cF = 0;
+    if (wave_live) {
+        const int64_t wb = wave_base[w];
+        for (int pass = 0; pass < 4; ++pass) {
+            const int pl = 16 * pass + (lane >> 2);   // the lane's particle in the tile
+            const int64_t i = t0 + pl;
+            const bool active = i < n;
+            const int64_t ic = active ? i : n - 1;
+            const int32_t nn = active ? n_task[i] : 0;
+            int32_t kmax = nn;                      // the longest list of the pass
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
+            if (kmax == 0) continue;
+            const double *rk = geo + (int64_t)kRec * ic;
+            double Ui[NQ], Di[3 * NQ];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const double *r = UD + (ic * G + g) * 16;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    Ui[4 * g + m] = r[m];
+                    Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
+                    Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
+                    Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
+                }
+            }
+            double acc[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+            const int64_t base = wb + pl;
+            // the task of the next iteration is loaded one iteration ahead
+            int32_t tn = sub < nn ? task[base + 64 * (int64_t)sub] : (int32_t)ic;
+            for (int32_t kk = 0; kk < kmax; kk += 4) {
+                const int32_t k = kk + sub;
+                const bool valid = k < nn;
+                const int32_t t = tn;
+                tn = k + 4 < nn ? task[base + 64 * (int64_t)(k + 4)] : (int32_t)ic;
+                const bool mirror = t < 0;
+                const int32_t j = t & 0x7fffffff;
+                int32_t rw[8];
+                const double *gp[8], *udp[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) rw[m] = __shfl(j, 8 * m + (lane >> 3), 64);
+                row_ptrs(geo, rw, 1, 0, lane, gp);
+                row_ptrs(UD, rw, G, 0, lane, udp);
+                {
+                    double2 v[8];
+                    load_at(gp, 0, v);
+                    store_lines(v, sb, lane);
+                }
+                double rl[12];
+#pragma unroll
+                for (int q = 0; q < 12; ++q) rl[q] = sb[lane * kStage + q];
+                PairGeo pg;
+                pair_geometry64(rk, rl, box, ibox, pg);
+                const bool use = valid && pg.An > 0.0;
+                const int cnt2 = mirror ? 2 : 1;
+                const int mr = mirror ? (j - (int32_t)t0) * MS : 0;   // the partner's row
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    {
+                        double2 v[8];
+                        load_at(udp, g, v);
+                        store_lines(v, sb, lane);
+                    }
+                    const double *Rl = sb + lane * kStage;
+                    double qL[4], qR[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int q = 4 * g + m;
+                        const double dk = Di[3 * q] * pg.sx + Di[3 * q + 1] * pg.sy + Di[3 * q + 2] * pg.sz;
+                        const double dl = Rl[4 + 3 * m] * pg.sx + Rl[5 + 3 * m] * pg.sy + Rl[6 + 3 * m] * pg.sz;
+                        const double mm = minmod_med(dk, dl);
+                        qL[m] = Ui[q] + pg.fk * mm;
+                        qR[m] = Rl[m] - pg.fl * mm;
+                    }
+                    double FAL, aL, bL, FAR, aR, bR;
+                    const int f1 = face_m164(qL, pg.Ax, pg.Ay, pg.Az, c, c3, FAL, aL, bL);
+                    const int f2 = face_m164(qR, pg.Ax, pg.Ay, pg.Az, c, c3, FAR, aR, bR);
+                    const double w3 = -hc * pg.An;
+                    if (use) {
+                        cE += cnt2 * ((f1 & 1) + (f2 & 1));
+                        cF += cnt2 * ((f1 >> 1) + (f2 >> 1));
+                        const double al = __builtin_fma(0.5, aL, 0.5 * aR);
+                        const double bl = 0.5 * bL, br = 0.5 * bR;
+                        double phi[4];
+                        phi[0] = __builtin_fma(w3, qR[0] - qL[0], __builtin_fma(0.5, FAL, 0.5 * FAR));
+                        const double Av[3] = {pg.Ax, pg.Ay, pg.Az};
+#pragma unroll
+                        for (int m = 1; m < 4; ++m)
+                            phi[m] = __builtin_fma(w3, qR[m] - qL[m],
+                                                   __builtin_fma(al, Av[m - 1],
+                                                                 __builtin_fma(bl, qL[m], br * qR[m])));
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) acc[4 * g + m] += phi[m];
+                        if (mirror) {
+#pragma unroll
+                            for (int m = 0; m < 4; ++m) atomicAdd(mw + mr + 4 * g + m, -phi[m]);
+                        }
+                    }
+                }
+            }
+            // the 4 lanes' partial sums, combined by a fixed butterfly, go to
+            // the particle's row after this pass's deposits
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                for (int o = 1; o < 4; o <<= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+            wave_lds_sync();
+            if (sub == 0 && active) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) mw[pl * MS + q] += acc[q];
+            }
+            wave_lds_sync();
+        }
+    }
+    // update, post-update guard, ledger, photon budget: lane L, particle L
+    const int64_t i = t0 + lane;
+    const bool owner = wave_live && i < n;
+    double red[2 * G];
+    int gE = 0, gF = 0;
+    double chk = 0.0;   // NaN iff an updated state is NaN or infinite
+    if (owner) {
+        const double V = geo[(int64_t)kRec * i + R_V];
+        const double dtV = dtp[0] / V;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const double *u = UD + (i * G + g) * 16;
+            double q0 = u[0] - dtV * mw[lane * MS + 4 * g + 0];
+            double q1 = u[1] - dtV * mw[lane * MS + 4 * g + 1];
+            double q2 = u[2] - dtV * mw[lane * MS + 4 * g + 2];
+            double q3 = u[3] - dtV * mw[lane * MS + 4 * g + 3];
+            const double Epre = q0;
+            chk = __builtin_fma(q0, 0.0, chk);
+            chk = __builtin_fma(q1, 0.0, chk);
+            chk = __builtin_fma(q2, 0.0, chk);
+            chk = __builtin_fma(q3, 0.0, chk);
+            if (Uung) {
+                double *uu = Uung + i * NQ + 4 * g;
+                uu[0] = q0;
+                uu[1] = q1;
+                uu[2] = q2;
+                uu[3] = q3;
+            }
+            const int f = guard64(q0, q1, q2, q3, c);
+            gE += f & 1;
+            gF += f >> 1;
+            double *o = Uout + i * NQ + 4 * g;
+            o[0] = q0;
+            o[1] = q1;
+            o[2] = q2;
+            o[3] = q3;
+            red[g] = V * q0;
+            red[G + g] = (f & 1) ? -Epre * V : 0.0;
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < 2 * G; ++p) red[p] = 0.0;
+    }
+    if (chk != chk) atomicOr(status, ST_NONFINITE);
+    if (partials)
+        block_reduce_store<2 * G>(red, partials + blk * 2 * G, smem, [&](int p) { return p; });
+    if (counts) {
+        int64_t v0 = wave_sum_i64(cE), v1 = wave_sum_i64(cF), v2 = wave_sum_i64(gE),
+                v3 = wave_sum_i64(gF);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&scnt[0], (unsigned long long)v0);
+            atomicAdd(&scnt[1], (unsigned long long)v1);
+            atomicAdd(&scnt[2], (unsigned long long)v2);
+            atomicAdd(&scnt[3], (unsigned long long)v3);
+        }
+        __syncthreads();
+        if (threadIdx.x < 4 && scnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], scnt[threadIdx.x]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Photon budget Q_g = sum_k V_k E_kg: block partials, then one block combines
 // them with compensated (two-sum) arithmetic in a fixed order.
@@ -663,6 +887,21 @@ constexpr int kQ = RT_TRANSPORT_Q;
 // rows of block partials the FP64 transport writes (one per block)
 inline int64_t transport_rows(int64_t n) { return (n + kBlock / kQ - 1) / (kBlock / kQ); }
 
+// The FP64 global step with GLF and the Hopkins surfaces (up to 3 groups, all
+// in one wave) evaluates in-tile pairs once (k_transport64_tile); 0 selects
+// the two-sided kernel for it too.
+#ifndef RT_TRANSPORT_TILE
+#define RT_TRANSPORT_TILE 1
+#endif
+inline bool use_tile64(const rt_ctx *ctx) {
+    return RT_TRANSPORT_TILE != 0 && ctx->p.precision == RT_FP64 && ctx->solver == RT_GLF &&
+           ctx->surfaces == RT_HOPKINS && ctx->p.groups <= 3 && ctx->task != nullptr;
+}
+// rows of block partials the FP64 transport writes (one per block)
+inline int64_t transport64_rows(const rt_ctx *ctx) {
+    return use_tile64(ctx) ? (ctx->p.n + kBlock - 1) / kBlock : transport_rows(ctx->p.n);
+}
+
 template <int G>
 void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double *Uout,
                         double *partials, int64_t *counts, double *Uung) {
@@ -672,6 +911,15 @@ void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double 
     const int64_t n = ctx->p.n, nb = transport_rows(n);
     const double2 *tab = (const double2 *)ctx->hll_table;
     const bool iva = ctx->surfaces == RT_IVANOVA;
+    if constexpr (G <= 3) {
+        if (use_tile64(ctx)) {
+            const int64_t nt = transport64_rows(ctx);
+            k_transport64_tile<G><<<(unsigned)xcd_grid(nt), kBlock, 0, ctx->stream>>>(
+                n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt, ctx->p.c_red,
+                ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, ctx->status);
+            return;
+        }
+    }
 #define RT_TRANSPORT_LAUNCH(W, HLL_, IVA_)                                                    \
     k_transport64<G, W, false, HLL_, IVA_, kQ, own_lds(HLL_, IVA_, W),                        \
                   pipe_on(HLL_, IVA_, W)>                                                     \
@@ -800,7 +1048,7 @@ rt_status rt_gradient_impl(rt_ctx *ctx, const void *U, void *UD) {
 rt_status rt_transport_impl(rt_ctx *ctx, const void *UD, const double *dt, void *U_out,
                             double *Q, int64_t *counts, double *ledger, void *Uung) {
     // rows of block partials: the FP64 kernel's blocks, or one per kBlock particles
-    const int64_t nb = ctx->p.precision == RT_FP64 ? transport_rows(ctx->p.n)
+    const int64_t nb = ctx->p.precision == RT_FP64 ? transport64_rows(ctx)
                                                    : rt_transport32_rows(ctx->p.n);
     double *part = (Q || ledger) ? ctx->partials : nullptr;
     rt_timer_begin(ctx, "transport");

@@ -170,6 +170,9 @@ def test_plummer_mid():
     err = state_err(got_U, ref_U)
     log(f"plummer 2 steps: max state err {err:.3e}")
     assert err < TOL
+    # the same steps again give the same bits (the in-tile exchanges meet in
+    # LDS accumulators; their order is fixed by the wave's program order)
+    assert np.array_equal(run_gpu(rt, p, w, 2)[0], got_U)
 
 
 @pytest.mark.parametrize("n_side,groups", [(7, 2), (9, 1), (11, 4)])
