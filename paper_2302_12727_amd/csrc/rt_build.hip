@@ -599,10 +599,11 @@ __global__ void k_src_gas(int32_t S, Tree T, const double *__restrict__ xs, int6
 }
 
 // Task lists of the tile transport (k_transport64_tile): particle i's
-// neighbours outside its tile (the 64 particles of its column block of the
-// neighbour table), then, flagged by the sign bit, the tile partners it
-// evaluates for both.  Which of the two evaluates an in-tile pair is chosen
-// to balance the lists, whose longest in each group of 16 particles sets the
+// neighbours outside its tile (kTile consecutive particles within its
+// 64-particle column block of the neighbour table) and, flagged by the sign
+// bit, the tile partners it evaluates for both.  Which of the two evaluates
+// an in-tile pair is chosen to balance the lists, whose longest in each
+// group of 16 particles (one wave of the transport) sets the
 // iterations of a pass: one wave per tile starts from each particle's count
 // of neighbours outside the tile and gives the tile's pairs, in a fixed order
 // (by the lower index, then by its list order), one by one to the particle
@@ -625,7 +626,7 @@ __global__ __launch_bounds__(64) void k_tasks(int64_t n, const int64_t *__restri
     const int32_t nn = active ? n_nbr[i] : 0;
     int32_t out = 0;
     for (int32_t k = 0; k < nn; ++k)
-        out += (nbr[base + 64 * (int64_t)k] >> 6) != (int32_t)blockIdx.x;
+        out += nbr[base + 64 * (int64_t)k] / kTile != (int32_t)(i / kTile);
     cnt[lane] = out;
     own[lane] = 0;
     __syncthreads();
@@ -636,7 +637,8 @@ __global__ __launch_bounds__(64) void k_tasks(int64_t n, const int64_t *__restri
             for (int32_t k = 0; k < nn; ++k) {
                 const int32_t j = nbr[base + 64 * (int64_t)k];
                 const int jl = j - (int32_t)t0;
-                if (jl <= src || jl >= 64) continue;     // outside the tile, or already given
+                // outside the tile, or already given
+                if (jl <= src || jl >= 64 || jl / kTile != src / kTile) continue;
                 const int32_t cj = cnt[jl];
                 if (cj < ci) {
                     cnt[jl] = cj + 1;
@@ -657,7 +659,7 @@ __global__ __launch_bounds__(64) void k_tasks(int64_t n, const int64_t *__restri
     for (int32_t k = 0; k < nn; ++k) {
         int32_t j = nbr[base + 64 * (int64_t)k];
         const int jl = j - (int32_t)t0;
-        if (jl >= 0 && jl < 64) {
+        if (jl >= 0 && jl < 64 && jl / kTile == lane / kTile) {
             if (!((mine >> jl) & 1)) continue;
             j |= int32_t(0x80000000u);
         }

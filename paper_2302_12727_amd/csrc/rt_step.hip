@@ -515,22 +515,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 // Transport with the pairs inside a tile evaluated once (FP64, GLF, Hopkins
 // surfaces, one global step, all G <= 3 groups in one wave).
 //
-// A wave owns one tile: the 64 consecutive Morton particles of one column
-// block of the neighbour table.  It treats the tile in 4 passes of 16
-// particles with 4 lanes each (so a pass keeps the cache footprint of the
-// two-sided kernel).  A particle's task list (k_tasks, built with the
-// geometry) holds its neighbours outside the tile and its share of the pairs
-// inside it: an in-tile pair (k, l) is evaluated by one of its particles only
-// (chosen to balance the lists' lengths), flagged by the sign bit.  That lane
-// adds Phi_kl to its own sum and -Phi_kl, by an LDS
-// atomic add, to the other particle's row of the wave's accumulator; the
-// pair's face states are the same from either side, so its face-guard counts
-// are taken twice.  Each pass ends by adding its particles' own sums to their
-// rows; after the last pass lane L updates particle L of the tile.  The
-// in-tile pair flux is antisymmetric bit for bit.  49.5% of the neighbour
-// entries of the 128^3 lattice lie inside their tile, so a step evaluates
-// 75% of the pair fluxes of the two-sided kernel.
-constexpr int32_t kTaskMirror = int32_t(0x80000000u);
+// A block owns one tile: the 64 consecutive Morton particles of one column
+// block of the neighbour table, 16 per wave with 4 lanes each (the layout, and
+// so the cache footprint, of the two-sided kernel).  A particle's task list
+// (k_tasks, built with the geometry) holds its neighbours outside the tile and
+// its share of the pairs inside it: an in-tile pair (k, l) is evaluated by one
+// of its particles only (chosen to balance the lists' lengths), flagged by
+// the sign bit.  That lane adds Phi_kl to its own sum and -Phi_kl, by an LDS
+// atomic add, to the other particle's row of its own wave's copy of the
+// tile's accumulator; the pair's face states are the same from either side,
+// so its face-guard counts are taken twice.  After a block barrier each
+// particle's sum is its own partial sums plus the 4 waves' rows, added in a
+// fixed order, so runs are bitwise reproducible, and the in-tile pair flux
+// is antisymmetric bit for bit.  49.5% of the neighbour entries of the 128^3
+// lattice lie inside their tile, so a step evaluates 75% of the pair fluxes
+// of the two-sided kernel.  (With a wave owning a whole tile in 4 passes the
+// XCD's working set spanned 4 times the particles and its L2 hit rate fell
+// from 92% to 38%.)
 
 template <int G>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void
@@ -543,27 +544,30 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                    int32_t *__restrict__ status) {
     constexpr int NQ = 4 * G, MS = NQ + 1;     // accumulator row, padded against bank conflicts
     __shared__ double stage[kBlock / 64][64 * kStage];
-    __shared__ double mir[kBlock / 64][64 * MS];
+    static_assert(kTile == 64 && kBlock == 256, "a block of 4 waves x 16 particles per tile");
+    __shared__ double mir[kBlock / 64][kTile * MS];
     __shared__ double smem[(kBlock / 64) * 2 * G];
     __shared__ unsigned long long scnt[4];
     const int64_t blk = xcd_block(nb);
     if (blk >= nb) return;                      // whole block: no barrier is skipped
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int sub = lane & 3;
-    const int64_t w = blk * (kBlock / 64) + wv; // the wave's tile
-    const int64_t t0 = w * 64;                  // its first particle
-    const bool wave_live = t0 < n;              // wave-uniform
+    const int64_t t0 = blk * kTile;             // the tile's first particle
+    const bool wave_live = t0 + 16 * wv < n;    // wave-uniform
     const double ibox = 1.0 / box, hc = 0.5 * c, c3 = 3.0 * c;
     if (threadIdx.x < 4) scnt[threadIdx.x] = 0;
     double *sb = stage[wv];
-    double *mw = mir[wv];
-    for (int e = lane; e < 64 * MS; e += 64) mw[e] = 0.0;
+    double *mw = mir[wv];                       // this wave's copy of the accumulator
+    for (int e = lane; e < kTile * MS; e += 64) mw[e] = 0.0;
     wave_lds_sync();
     int cE = 0, cF = 0;
+    const int pl = 16 * wv + (lane >> 2);       // the lane's particle in the tile
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     if (wave_live) {
-        const int64_t wb = wave_base[w];
-        for (int pass = 0; pass < 4; ++pass) {
-            const int pl = 16 * pass + (lane >> 2);   // the lane's particle in the tile
+        const int64_t wb = wave_base[blk];
+        {
             const int64_t i = t0 + pl;
             const bool active = i < n;
             const int64_t ic = active ? i : n - 1;
@@ -571,7 +575,6 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
             int32_t kmax = nn;                      // the longest list of the pass
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
-            if (kmax == 0) continue;
             const double *rk = geo + (int64_t)kRec * ic;
             double Ui[NQ], Di[3 * NQ];
 #pragma unroll
@@ -585,10 +588,7 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                     Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
                 }
             }
-            double acc[NQ];
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-            const int64_t base = wb + pl;
+            const int64_t base = wb + pl;   // the particle's column in the table
             // the task of the next iteration is loaded one iteration ahead
             int32_t tn = sub < nn ? task[base + 64 * (int64_t)sub] : (int32_t)ic;
             for (int32_t kk = 0; kk < kmax; kk += 4) {
@@ -661,23 +661,20 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                     }
                 }
             }
-            // the 4 lanes' partial sums, combined by a fixed butterfly, go to
-            // the particle's row after this pass's deposits
+            // the 4 lanes' partial sums, combined by a fixed butterfly
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
 #pragma unroll
                 for (int o = 1; o < 4; o <<= 1) acc[q] += __shfl_xor(acc[q], o, 64);
-            wave_lds_sync();
-            if (sub == 0 && active) {
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) mw[pl * MS + q] += acc[q];
-            }
-            wave_lds_sync();
         }
     }
-    // update, post-update guard, ledger, photon budget: lane L, particle L
-    const int64_t i = t0 + lane;
-    const bool owner = wave_live && i < n;
+    // every wave's deposits are in its copy of the accumulator
+    __syncthreads();
+    // update, post-update guard, ledger, photon budget: the first lane of each
+    // particle; its sum is its own partial sums plus the 4 waves' rows, in
+    // that fixed order
+    const int64_t i = t0 + pl;
+    const bool owner = wave_live && sub == 0 && i < n;
     double red[2 * G];
     int gE = 0, gF = 0;
     double chk = 0.0;   // NaN iff an updated state is NaN or infinite
@@ -685,12 +682,16 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
         const double V = geo[(int64_t)kRec * i + R_V];
         const double dtV = dtp[0] / V;
 #pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int v = 0; v < kBlock / 64; ++v) acc[q] += mir[v][pl * MS + q];
+#pragma unroll
         for (int g = 0; g < G; ++g) {
             const double *u = UD + (i * G + g) * 16;
-            double q0 = u[0] - dtV * mw[lane * MS + 4 * g + 0];
-            double q1 = u[1] - dtV * mw[lane * MS + 4 * g + 1];
-            double q2 = u[2] - dtV * mw[lane * MS + 4 * g + 2];
-            double q3 = u[3] - dtV * mw[lane * MS + 4 * g + 3];
+            double q0 = u[0] - dtV * acc[4 * g + 0];
+            double q1 = u[1] - dtV * acc[4 * g + 1];
+            double q2 = u[2] - dtV * acc[4 * g + 2];
+            double q3 = u[3] - dtV * acc[4 * g + 3];
             const double Epre = q0;
             chk = __builtin_fma(q0, 0.0, chk);
             chk = __builtin_fma(q1, 0.0, chk);
@@ -899,7 +900,7 @@ inline bool use_tile64(const rt_ctx *ctx) {
 }
 // rows of block partials the FP64 transport writes (one per block)
 inline int64_t transport64_rows(const rt_ctx *ctx) {
-    return use_tile64(ctx) ? (ctx->p.n + kBlock - 1) / kBlock : transport_rows(ctx->p.n);
+    return use_tile64(ctx) ? (ctx->p.n + kTile - 1) / kTile : transport_rows(ctx->p.n);
 }
 
 template <int G>
