@@ -129,7 +129,8 @@ rt_status rt_inject(rt_ctx *ctx, void *U, const double *L, const double *dt);
 /* Least-squares gradients (eq:gradient) of every component of U:
  *   dU_i = sum_{j: r_ij < H_i} (U_j - U_i) psi_tilde_j(x_i).
  * U [n][G][4] in; UD [n][G][16] out (state and gradients, see above).
- * U and UD must not overlap. */
+ * U and UD must not overlap and must be 16-byte aligned (RT_EINVAL
+ * otherwise): the neighbours' states are moved in 16-byte pieces. */
 rt_status rt_gradient(rt_ctx *ctx, const void *U, void *UD);
 
 /* One transport step (eq:transport-update-explicit with one global dt):
@@ -293,8 +294,8 @@ rt_status rt_time_bins(rt_ctx *ctx, int32_t max_bin, int32_t *bins, int64_t *cyc
  * sums of both particles; the particles that end a step apply
  * U - (flux sum) / V, guard the result as rt_transport does, and clear their
  * sums.
- *   U    [n][G][4] in/out: the states (double in FP64 contexts, float in
- *        FP32C ones).
+ *   U    [n][G][4] in/out, 16-byte aligned: the states (double in FP64
+ *        contexts, float in FP32C ones).
  *   L    [S][G] luminosities (NULL without sources).
  *   UD   [n][G][16] in/out, 16-byte aligned, the state's type: the stored
  *        gradient records.  Before tick 0 fill it with rt_gradient of the

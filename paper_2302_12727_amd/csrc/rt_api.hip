@@ -190,7 +190,8 @@ rt_status rt_gradient(rt_ctx *ctx, const void *U, void *UD) {
     size_t es = ctx->p.precision == RT_FP64 ? 8 : 4;
     size_t nu = es * 4 * ctx->p.groups * ctx->p.n;
     if (overlap(U, nu, UD, 4 * nu)) return rt_fail(ctx, RT_EINVAL, "U and UD overlap");
-    if (!aligned16(UD)) return rt_fail(ctx, RT_EINVAL, "UD must be 16-byte aligned");
+    if (!aligned16(U) || !aligned16(UD))
+        return rt_fail(ctx, RT_EINVAL, "U and UD must be 16-byte aligned");
     return rt_gradient_impl(ctx, U, UD);
 }
 
@@ -304,7 +305,8 @@ rt_status rt_tick(rt_ctx *ctx, void *U, const double *L, int64_t tick, void *UD,
     const size_t nu = es * 4 * ctx->p.groups * ctx->p.n, na = sizeof(double) * 4 * ctx->p.groups * ctx->p.n;
     if (overlap(UD, 4 * nu, U, nu) || overlap(UD, 4 * nu, acc, na) || overlap(U, nu, acc, na))
         return rt_fail(ctx, RT_EINVAL, "U, UD and acc must not overlap");
-    if (!aligned16(UD)) return rt_fail(ctx, RT_EINVAL, "UD must be 16-byte aligned");
+    if (!aligned16(U) || !aligned16(UD))
+        return rt_fail(ctx, RT_EINVAL, "U and UD must be 16-byte aligned");
     return rt_tick_impl(ctx, U, L, tick, UD, acc, photon_total, counts, ledger);
 }
 

@@ -63,6 +63,9 @@ __global__ void k_inject(int32_t ngas, int G, const int32_t *__restrict__ gptr,
     }
 }
 
+// two doubles as one 16-byte access (a native vector: copies stay in registers)
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
 // ---------------------------------------------------------------------------
 // Gradient (eq:gradient):  grad q_i = sum_j (q_j - q_i) psi~_j(x_i)
 //   = S_i^{-1} sum_j (q_j - q_i) w(r_ij / H_i) s_ij   (the kernel normalisation
@@ -72,59 +75,183 @@ __global__ void k_inject(int32_t ngas, int G, const int32_t *__restrict__ gptr,
 //
 // Q lanes share a particle, each summing every Q-th gather neighbour; the
 // partial sums are combined by a fixed butterfly (the same bits on every lane
-// of the particle) and the first lane writes the record.
-// Up to 3 groups the FP64 gradient is held to 3 waves per SIMD (168 VGPRs, 9
-// spilled; 190 and 2 waves otherwise): 1.31 against 1.35 ms on the 3-group
-// 128^3 lattice.
+// of the particle), and the Q lanes write the particle's record together.
+//
+// Neighbour rows are staged through LDS.  Gathered lane by lane, each of the
+// 8 loads of a neighbour's state and position touches 64 different cache
+// lines (1.31 ms on the 3-group 128^3 lattice, the L1 doing about one tag
+// lookup a cycle).  Here the wave moves the 64 rows of an iteration with
+// consecutive lanes taking consecutive pieces: 2G loads of 16 bytes for the
+// neighbours' states (64 / 2G rows a load) and 3 of 8 bytes for their
+// positions (x, y, z from the packed position array, 21 rows a load; the
+// heads of the 128-byte geometry records would take a cache line per
+// neighbour and raised the L1 misses by 60%).  The lane that stores a piece
+// subtracts the same piece of the row's own particle (the wave's own rows sit
+// in LDS in the same layout), so a lane reads U_j - U_i and x_j - x_i from its
+// row and holds neither its own state nor its position, which keeps the
+// kernel at 3 waves per SIMD without spills.  Rows lie 2G + 3 pieces of 16
+// bytes apart in LDS, an odd number, so the 16-byte stores and reads are free
+// of bank conflicts (with 8-byte halves the stores conflicted 2-way).  Past
+// the end of its list a lane's row is its own particle's, whose differences
+// are zero: the sums need no branch.  The table entry of an iteration is
+// loaded two iterations ahead and its rows one.  1.20 ms on the lattice: the
+// texture data path stays busy 95% of the time, half of it waiting for L1
+// misses (a wave's 16 particles reach about 400 distinct neighbours, more
+// than the L1 holds).  Two iterations of rows in flight at 2 waves per SIMD
+// ran 1.25 ms, blocks of 8 and 12 waves 1.41 and 1.31 ms.
 #ifndef RT_GRADIENT_WAVES
 #define RT_GRADIENT_WAVES 3
 #endif
+#ifndef RT_GRADIENT_BLOCK
+#define RT_GRADIENT_BLOCK 4
+#endif
+constexpr int gradient_waves(int G) { return G <= 3 ? RT_GRADIENT_WAVES : G == 4 ? 2 : 1; }
+static_assert(RT_GRADIENT_BLOCK >= 1 && RT_GRADIENT_BLOCK <= 16, "1 to 16 waves per block");
+// threads per block of the FP64 gradient: at most the waves of one CU and
+// the LDS of one CU (80 staged rows of 2G + 3 pieces per wave at 4 lanes
+// per particle)
+constexpr int grad_block(int G) {
+    const int lds = 80 * (2 * G + 3) * 16, by_lds = 163840 / lds;
+    int w = RT_GRADIENT_BLOCK;
+    if (w > 4 * gradient_waves(G)) w = 4 * gradient_waves(G);
+    if (w > by_lds) w = by_lds;
+    return 64 * w;
+}
+
 template <int G, bool BIN = false, int Q = 1>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
-    G <= 3 ? RT_GRADIENT_WAVES : 1))) void k_gradient64(
+__global__ __launch_bounds__(grad_block(G)) __attribute__((amdgpu_waves_per_eu(
+    gradient_waves(G), gradient_waves(G)))) void k_gradient64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const double *__restrict__ xs,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_gath, const double *__restrict__ U, double *__restrict__ UD,
     int32_t *__restrict__ status, double box, int64_t tick = 0) {
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
+    constexpr int NQ = 4 * G;
+    constexpr int PU = 2 * G;           // 16-byte pieces of a state
+    constexpr int S = PU + 3;           // LDS row stride in pieces: state, x y z, pad (odd)
+    constexpr int NP = 64 / Q;          // particles of a wave
+    constexpr int W = grad_block(G) / 64;
+    static_assert(Q != 4 || 80 * (2 * G + 3) * 16 * W <= 163840, "LDS of one CU");
+    __shared__ dvec2 stage[W][64 * S];
+    __shared__ dvec2 own[W][NP * S];
     const int64_t blk = xcd_block(nb);
     if (blk >= nb) return;                      // whole block
-    const int sub = (threadIdx.x & 63) % Q;
-    const int64_t i = blk * (kBlock / Q) + threadIdx.x / Q;
-    // a particle's Q lanes are adjacent in one wave and leave together
-    if (i >= n) return;
-    if (BIN && ((tick + 1) & ((int64_t(1) << (int32_t)geo[(int64_t)kRec * i + 12]) - 1)) != 0)
-        return;
-    constexpr int NQ = 4 * G;
-    const double ibox = 1.0 / box;
-    const double *rec = geo + (int64_t)kRec * i;
-    const double px = xs[3 * i], py = xs[3 * i + 1], pz = xs[3 * i + 2];
-    const double iH = rec[R_IH], iV = 1.0 / rec[R_V];
-    double Ui[NQ];
+    const int lane = threadIdx.x & 63;
+    const int sub = lane % Q;
+    // the wave's first particle; the wave stays whole (its loads are shared)
+    const int64_t i0 = blk * (grad_block(G) / Q) + (threadIdx.x >> 6) * NP;
+    if (i0 >= n) return;                        // whole wave
+    const int64_t i = i0 + lane / Q;
+    const int64_t ic = i < n ? i : n - 1;
+    const double *rec = geo + (int64_t)kRec * ic;
+    const bool active =
+        i < n && (!BIN || ((tick + 1) & ((int64_t(1) << (int32_t)rec[12]) - 1)) == 0);
+    const int32_t ng = active ? n_gath[ic] : 0;
+    int32_t kmax = ng;                          // the wave's longest list
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) Ui[q] = U[i * NQ + q];
+    for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
+    const double ibox = 1.0 / box;
+    const double iH = rec[R_IH];
     double acc[NQ][3];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
-    const int64_t base = wave_base[i >> 6] + (i & 63);
-    const int32_t ng = n_gath[i];
-    // the next neighbour index is loaded one iteration ahead
-    int64_t jn = sub < ng ? nbr[base + 64 * (int64_t)sub] : 0;
-    for (int32_t k = sub; k < ng; k += Q) {
-        const int64_t j = jn;
-        if (k + Q < ng) jn = nbr[base + 64 * (int64_t)(k + Q)];
-        const double sx = min_image(xs[3 * j] - px, box, ibox);
-        const double sy = min_image(xs[3 * j + 1] - py, box, ibox);
-        const double sz = min_image(xs[3 * j + 2] - pz, box, ibox);
-        const double w = kern_w(sqrt64(sx * sx + sy * sy + sz * sz) * iH);
-        const double wx = w * sx, wy = w * sy, wz = w * sz;
-        const double *Uj = U + j * NQ;
+    dvec2 *sb = stage[threadIdx.x >> 6], *ob = own[threadIdx.x >> 6];
+    double *sd = reinterpret_cast<double *>(sb), *od = reinterpret_cast<double *>(ob);
+    const dvec2 *U2 = reinterpret_cast<const dvec2 *>(U);
+    // the wave's own rows (the last particle repeated past n)
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const double d = Uj[q] - Ui[q];
-            acc[q][0] += d * wx;
-            acc[q][1] += d * wy;
-            acc[q][2] += d * wz;
+    for (int c = 0; c < (NP * PU + 63) / 64; ++c) {
+        const int e = 64 * c + lane;
+        if (NP * PU % 64 == 0 || e < NP * PU) {
+            const uint32_t jo = (uint32_t)min(i0 + e / PU, n - 1);
+            ob[(e / PU) * S + e % PU] = U2[jo * (uint32_t)PU + (uint32_t)(e % PU)];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < (NP * 3 + 63) / 64; ++c) {
+        const int e = 64 * c + lane;
+        if (NP * 3 % 64 == 0 || e < NP * 3) {
+            const uint32_t jo = (uint32_t)min(i0 + e / 3, n - 1);
+            od[(e / 3) * 2 * S + 2 * PU + e % 3] = xs[jo * 3u + (uint32_t)(e % 3)];
+        }
+    }
+    if (kmax > 0) {
+        // Slot k of the particle's column, or slot 0 past the end of its list
+        // (present: some column of this table block holds an entry); an index
+        // past the end is replaced by the particle's own.
+        const int32_t *col = nbr + wave_base[ic >> 6] + (ic & 63);
+        auto entry = [&](int32_t k) __attribute__((always_inline)) {
+            return col[64 * (k < ng ? k : 0)];
+        };
+        auto index = [&](int32_t k, int32_t e) __attribute__((always_inline)) {
+            return k < ng ? e : (int32_t)ic;
+        };
+        // the rows of lane j's: state piece c of every lane is e = 64 c + lane,
+        // row e / PU; position double c is e = 64 c + lane, row e / 3
+        struct Rows { dvec2 u[PU]; double x[3]; };
+        auto load = [&](Rows &v, int32_t j) __attribute__((always_inline)) {
+#pragma unroll
+            for (int c = 0; c < PU; ++c) {
+                const int e = 64 * c + lane;
+                const uint32_t jr = (uint32_t)__shfl(j, e / PU, 64);
+                v.u[c] = U2[jr * (uint32_t)PU + (uint32_t)(e % PU)];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int e = 64 * c + lane;
+                const uint32_t jr = (uint32_t)__shfl(j, e / 3, 64);
+                v.x[c] = xs[jr * 3u + (uint32_t)(e % 3)];
+            }
+        };
+        // store the pieces less the own particle's, for the lanes to read
+        auto put = [&](const Rows &v) __attribute__((always_inline)) {
+            wave_lds_sync();
+#pragma unroll
+            for (int c = 0; c < PU; ++c) {
+                const int e = 64 * c + lane, r = e / PU, p = e % PU;
+                sb[r * S + p] = v.u[c] - ob[(r / Q) * S + p];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int e = 64 * c + lane, r = e / 3, p = 2 * PU + e % 3;
+                sd[r * 2 * S + p] = v.x[c] - od[(r / Q) * 2 * S + p];
+            }
+            wave_lds_sync();
+        };
+        auto gather = [&]() __attribute__((always_inline)) {
+            const dvec2 *row = sb + lane * S;
+            const dvec2 s01 = row[PU], s23 = row[PU + 1];
+            const double sx = min_image(s01.x, box, ibox);
+            const double sy = min_image(s01.y, box, ibox);
+            const double sz = min_image(s23.x, box, ibox);
+            const double w = kern_w(sqrt64(sx * sx + sy * sy + sz * sz) * iH);
+            const double wx = w * sx, wy = w * sy, wz = w * sz;
+#pragma unroll
+            for (int t = 0; t < PU; ++t) {
+                const dvec2 d = row[t];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int q = 2 * t + h;
+                    acc[q][0] += d[h] * wx;
+                    acc[q][1] += d[h] * wy;
+                    acc[q][2] += d[h] * wz;
+                }
+            }
+        };
+        // Each table entry is loaded before the rows of the iteration ahead of
+        // it, so waiting for the entry never waits for rows still in flight;
+        // no step is skipped near the end (rows past every list are the own
+        // rows), so that every path through the loop body is alike.
+        Rows v;
+        const int32_t e0 = entry(sub);
+        int32_t e1 = entry(Q + sub);
+        load(v, index(sub, e0));
+        for (int32_t kk = 0; kk < kmax; kk += Q) {
+            put(v);
+            const int32_t e2 = entry(kk + 2 * Q + sub);
+            load(v, index(kk + Q + sub, e1));
+            e1 = e2;
+            gather();
         }
     }
     if (Q > 1) {
@@ -134,32 +261,49 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             for (int a = 0; a < 3; ++a)
 #pragma unroll
                 for (int o = 1; o < Q; o <<= 1) acc[q][a] += __shfl_xor(acc[q][a], o, 64);
-        if (sub != 0) return;
     }
+    if (!active) return;
+    // the own state, as loaded, from the wave's own row
+    wave_lds_sync();
+    double Ui[NQ];
+#pragma unroll
+    for (int t = 0; t < PU; ++t) {
+        const dvec2 x = ob[(lane / Q) * S + t];
+        Ui[2 * t] = x.x;
+        Ui[2 * t + 1] = x.y;
+    }
+    const double iV = 1.0 / rec[R_V];
     const double b00 = rec[R_B] * iV, b01 = rec[R_B + 1] * iV, b02 = rec[R_B + 2] * iV;
     const double b11 = rec[R_B + 3] * iV, b12 = rec[R_B + 4] * iV, b22 = rec[R_B + 5] * iV;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double d0 = b00 * acc[q][0] + b01 * acc[q][1] + b02 * acc[q][2];
+        const double d1 = b01 * acc[q][0] + b11 * acc[q][1] + b12 * acc[q][2];
+        const double d2 = b02 * acc[q][0] + b12 * acc[q][1] + b22 * acc[q][2];
+        acc[q][0] = d0;
+        acc[q][1] = d1;
+        acc[q][2] = d2;
+    }
     // group-major record: per group the state then its gradients (one line);
-    // chk stays 0 unless a value written is NaN or infinite (0 x v is 0 for
-    // finite v and NaN otherwise)
+    // double d of the record, d = 16 g + s
+    auto value = [&](int d) {
+        const int g = d / 16, s = d % 16;
+        return s < 4 ? Ui[4 * g + s] : acc[4 * g + (s - 4) / 3][(s - 4) % 3];
+    };
+    // the Q lanes write consecutive 16-byte pieces of the record; chk stays 0
+    // unless a value written is NaN or infinite (0 x v is 0 for finite v and
+    // NaN otherwise)
+    double *o = UD + ic * (16 * G);
     double chk = 0.0;
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        double *o = UD + (i * G + g) * 16;
+    for (int t = 0; t < 8 * G / Q; ++t) {
+        double2 val = make_double2(value(2 * Q * t), value(2 * Q * t + 1));
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int q = 4 * g + m;
-            const double d0 = b00 * acc[q][0] + b01 * acc[q][1] + b02 * acc[q][2];
-            const double d1 = b01 * acc[q][0] + b11 * acc[q][1] + b12 * acc[q][2];
-            const double d2 = b02 * acc[q][0] + b12 * acc[q][1] + b22 * acc[q][2];
-            o[m] = Ui[q];
-            o[4 + 3 * m + 0] = d0;
-            o[4 + 3 * m + 1] = d1;
-            o[4 + 3 * m + 2] = d2;
-            chk = __builtin_fma(Ui[q], 0.0, chk);
-            chk = __builtin_fma(d0, 0.0, chk);
-            chk = __builtin_fma(d1, 0.0, chk);
-            chk = __builtin_fma(d2, 0.0, chk);
-        }
+        for (int s = 1; s < Q; ++s)
+            if (sub == s) val = make_double2(value(2 * (Q * t + s)), value(2 * (Q * t + s) + 1));
+        chk = __builtin_fma(val.x, 0.0, chk);
+        chk = __builtin_fma(val.y, 0.0, chk);
+        *reinterpret_cast<double2 *>(o + 2 * (Q * t + sub)) = val;
     }
     if (chk != chk) atomicOr(status, ST_NONFINITE);
 }
@@ -947,8 +1091,9 @@ constexpr int kGQ = RT_GRADIENT_Q;
 
 template <int G>
 void launch_gradient64(rt_ctx *ctx, const double *U, double *UD) {
-    const int64_t n = ctx->p.n, nb = (n + kBlock / kGQ - 1) / (kBlock / kGQ);
-    k_gradient64<G, false, kGQ><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
+    constexpr int B = grad_block(G);
+    const int64_t n = ctx->p.n, nb = (n + B / kGQ - 1) / (B / kGQ);
+    k_gradient64<G, false, kGQ><<<(unsigned)xcd_grid(nb), B, 0, ctx->stream>>>(
         n, nb, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->status,
         ctx->p.box);
 }
@@ -957,8 +1102,9 @@ template <int G>
 void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, double *Uout,
                    double *partials, int64_t *counts, int64_t tick, double *accm) {
     const int64_t n = ctx->p.n;
-    const int64_t ng = (n + kBlock / kGQ - 1) / (kBlock / kGQ);
-    k_gradient64<G, true, kGQ><<<(unsigned)xcd_grid(ng), kBlock, 0, ctx->stream>>>(
+    constexpr int B = grad_block(G);
+    const int64_t ng = (n + B / kGQ - 1) / (B / kGQ);
+    k_gradient64<G, true, kGQ><<<(unsigned)xcd_grid(ng), B, 0, ctx->stream>>>(
         n, ng, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->status,
         ctx->p.box, tick);
     constexpr int GW = transport_slice(G), HW = hll_slice(G);

@@ -128,3 +128,24 @@ def test_negative_energies_are_clipped_like_the_oracle():
     assert counts[0].item() > 0            # face states clipped
     oc = info["counts"]
     assert counts[0].item() == oc[0] and counts[2].item() == oc[2]
+
+
+def test_misaligned_state_is_refused():
+    """The gradient moves the neighbours' states in 16-byte pieces: a state
+    array 8 bytes off a 16-byte boundary is refused before any launch."""
+    w = workloads.config(0)
+    log(f"case misaligned U n={w.n}")
+    rt = RT(w.n, w.groups)
+    perm, *_ = rt.rt_build_cells(dev(w.x))
+    p = perm.cpu().numpy()
+    buf = torch.empty(w.n * w.groups * 4 + 1, dtype=torch.float64, device="cuda")
+    U = buf[1:].view(w.n, w.groups, 4)
+    U.copy_(dev(w.U0[p]))
+    assert U.data_ptr() % 16 == 8
+    with pytest.raises(RTError) as e:
+        rt.rt_gradient(U)
+    assert e.value.code == RT_EINVAL
+    # the same values at an aligned address go through
+    UD = rt.rt_gradient(U.clone())
+    rt.rt_sync()
+    assert np.array_equal(rt.states_of(UD).cpu().numpy(), w.U0[p])
