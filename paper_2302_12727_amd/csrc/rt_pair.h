@@ -360,6 +360,34 @@ __device__ __forceinline__ void load_at(const double *const (&p)[8], int g, doub
 #pragma unroll
     for (int m = 0; m < 8; ++m) v[m] = *reinterpret_cast<const double2 *>(p[m] + 16 * g);
 }
+// This lane's 16-byte pieces of line g of rows r[m] of a table of rows
+// `stride` lines long, addressed either by 8 pointers (OFF32 false) or by 8
+// byte offsets from the table's base (OFF32 true: the table is smaller than
+// 4 GiB).  The offsets take half the registers of the pointers, and the base
+// stays in scalar registers.
+template <bool OFF32> struct RowLines;
+template <> struct RowLines<false> {
+    const double *p[8];
+    __device__ __forceinline__ RowLines(const double *__restrict__ src, const int32_t (&r)[8],
+                                        int stride, int lane) {
+        row_ptrs(src, r, stride, 0, lane, p);
+    }
+    __device__ __forceinline__ void load(int g, double2 (&v)[8]) const { load_at(p, g, v); }
+};
+template <> struct RowLines<true> {
+    const char *b;
+    uint32_t o[8];
+    __device__ __forceinline__ RowLines(const double *__restrict__ src, const int32_t (&r)[8],
+                                        int stride, int lane)
+        : b(reinterpret_cast<const char *>(src)) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) o[m] = (uint32_t)r[m] * (uint32_t)(128 * stride) + 16u * (lane & 7);
+    }
+    __device__ __forceinline__ void load(int g, double2 (&v)[8]) const {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = *reinterpret_cast<const double2 *>(b + o[m] + 128u * g);
+    }
+};
 __device__ __forceinline__ void stage_lines(const double *__restrict__ src, const int64_t (&row)[8],
                                             double *sb, int lane) {
     double2 v[8];

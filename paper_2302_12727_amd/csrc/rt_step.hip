@@ -89,9 +89,11 @@ typedef double dvec2 __attribute__((ext_vector_type(2)));
 // subtracts the same piece of the row's own particle (the wave's own rows sit
 // in LDS in the same layout), so a lane reads U_j - U_i and x_j - x_i from its
 // row and holds neither its own state nor its position, which keeps the
-// kernel at 3 waves per SIMD without spills.  Rows lie 2G + 3 pieces of 16
-// bytes apart in LDS, an odd number, so the 16-byte stores and reads are free
-// of bank conflicts (with 8-byte halves the stores conflicted 2-way).  Past
+// kernel at 3 waves per SIMD without spills.  State rows lie 2G + 1 pieces of
+// 16 bytes apart in LDS, an odd number, and positions are packed 3 doubles a
+// row in an array of their own, so that the stores and reads of both are
+// free of bank conflicts (8-byte halves of the state pieces, or positions
+// inside the state rows, conflicted 2-way).  Past
 // the end of its list a lane's row is its own particle's, whose differences
 // are zero: the sums need no branch.  The table entry of an iteration is
 // loaded two iterations ahead and its rows one.  1.20 ms on the lattice: the
@@ -108,10 +110,11 @@ typedef double dvec2 __attribute__((ext_vector_type(2)));
 constexpr int gradient_waves(int G) { return G <= 3 ? RT_GRADIENT_WAVES : G == 4 ? 2 : 1; }
 static_assert(RT_GRADIENT_BLOCK >= 1 && RT_GRADIENT_BLOCK <= 16, "1 to 16 waves per block");
 // threads per block of the FP64 gradient: at most the waves of one CU and
-// the LDS of one CU (80 staged rows of 2G + 3 pieces per wave at 4 lanes
-// per particle)
+// the LDS of one CU (80 staged rows of 2G + 1 pieces and 3 doubles per wave at
+// 4 lanes per particle)
+constexpr int grad_lds_wave(int G) { return 80 * ((2 * G + 1) * 16 + 24); }
 constexpr int grad_block(int G) {
-    const int lds = 80 * (2 * G + 3) * 16, by_lds = 163840 / lds;
+    const int by_lds = 163840 / grad_lds_wave(G);
     int w = RT_GRADIENT_BLOCK;
     if (w > 4 * gradient_waves(G)) w = 4 * gradient_waves(G);
     if (w > by_lds) w = by_lds;
@@ -128,12 +131,14 @@ __global__ __launch_bounds__(grad_block(G)) __attribute__((amdgpu_waves_per_eu(
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     constexpr int NQ = 4 * G;
     constexpr int PU = 2 * G;           // 16-byte pieces of a state
-    constexpr int S = PU + 3;           // LDS row stride in pieces: state, x y z, pad (odd)
+    constexpr int S = PU + 1;           // LDS row stride in pieces (odd)
     constexpr int NP = 64 / Q;          // particles of a wave
     constexpr int W = grad_block(G) / 64;
-    static_assert(Q != 4 || 80 * (2 * G + 3) * 16 * W <= 163840, "LDS of one CU");
+    static_assert(Q != 4 || grad_lds_wave(G) * W <= 163840, "LDS of one CU");
     __shared__ dvec2 stage[W][64 * S];
     __shared__ dvec2 own[W][NP * S];
+    __shared__ double spos[W][64 * 3];
+    __shared__ double opos[W][NP * 3];
     const int64_t blk = xcd_block(nb);
     if (blk >= nb) return;                      // whole block
     const int lane = threadIdx.x & 63;
@@ -156,7 +161,7 @@ __global__ __launch_bounds__(grad_block(G)) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
     dvec2 *sb = stage[threadIdx.x >> 6], *ob = own[threadIdx.x >> 6];
-    double *sd = reinterpret_cast<double *>(sb), *od = reinterpret_cast<double *>(ob);
+    double *sd = spos[threadIdx.x >> 6], *od = opos[threadIdx.x >> 6];
     const dvec2 *U2 = reinterpret_cast<const dvec2 *>(U);
     // the wave's own rows (the last particle repeated past n)
 #pragma unroll
@@ -172,7 +177,7 @@ __global__ __launch_bounds__(grad_block(G)) __attribute__((amdgpu_waves_per_eu(
         const int e = 64 * c + lane;
         if (NP * 3 % 64 == 0 || e < NP * 3) {
             const uint32_t jo = (uint32_t)min(i0 + e / 3, n - 1);
-            od[(e / 3) * 2 * S + 2 * PU + e % 3] = xs[jo * 3u + (uint32_t)(e % 3)];
+            od[e] = xs[jo * 3u + (uint32_t)(e % 3)];
         }
     }
     if (kmax > 0) {
@@ -213,17 +218,16 @@ __global__ __launch_bounds__(grad_block(G)) __attribute__((amdgpu_waves_per_eu(
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const int e = 64 * c + lane, r = e / 3, p = 2 * PU + e % 3;
-                sd[r * 2 * S + p] = v.x[c] - od[(r / Q) * 2 * S + p];
+                const int e = 64 * c + lane;
+                sd[e] = v.x[c] - od[(e / (3 * Q)) * 3 + e % 3];
             }
             wave_lds_sync();
         };
         auto gather = [&]() __attribute__((always_inline)) {
             const dvec2 *row = sb + lane * S;
-            const dvec2 s01 = row[PU], s23 = row[PU + 1];
-            const double sx = min_image(s01.x, box, ibox);
-            const double sy = min_image(s01.y, box, ibox);
-            const double sz = min_image(s23.x, box, ibox);
+            const double sx = min_image(sd[3 * lane], box, ibox);
+            const double sy = min_image(sd[3 * lane + 1], box, ibox);
+            const double sz = min_image(sd[3 * lane + 2], box, ibox);
             const double w = kern_w(sqrt64(sx * sx + sy * sy + sz * sz) * iH);
             const double wx = w * sx, wy = w * sy, wz = w * sz;
 #pragma unroll
@@ -677,7 +681,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 // XCD's working set spanned 4 times the particles and its L2 hit rate fell
 // from 92% to 38%.)
 
-template <int G>
+template <int G, bool OFF32>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                    const int32_t *__restrict__ task, const int64_t *__restrict__ wave_base,
@@ -743,14 +747,12 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                 const bool mirror = t < 0;
                 const int32_t j = t & 0x7fffffff;
                 int32_t rw[8];
-                const double *gp[8], *udp[8];
 #pragma unroll
                 for (int m = 0; m < 8; ++m) rw[m] = __shfl(j, 8 * m + (lane >> 3), 64);
-                row_ptrs(geo, rw, 1, 0, lane, gp);
-                row_ptrs(UD, rw, G, 0, lane, udp);
+                const RowLines<OFF32> gl(geo, rw, 1, lane), ul(UD, rw, G, lane);
                 {
                     double2 v[8];
-                    load_at(gp, 0, v);
+                    gl.load(0, v);
                     store_lines(v, sb, lane);
                 }
                 double rl[12];
@@ -765,7 +767,7 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                 for (int g = 0; g < G; ++g) {
                     {
                         double2 v[8];
-                        load_at(udp, g, v);
+                        ul.load(g, v);
                         store_lines(v, sb, lane);
                     }
                     const double *Rl = sb + lane * kStage;
@@ -1059,9 +1061,15 @@ void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double 
     if constexpr (G <= 3) {
         if (use_tile64(ctx)) {
             const int64_t nt = transport64_rows(ctx);
-            k_transport64_tile<G><<<(unsigned)xcd_grid(nt), kBlock, 0, ctx->stream>>>(
-                n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt, ctx->p.c_red,
-                ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, ctx->status);
+            // rows addressed by 32-bit offsets while the gradient records fit 4 GiB
+            if ((uint64_t)n * 128u * G < (uint64_t(1) << 32))
+                k_transport64_tile<G, true><<<(unsigned)xcd_grid(nt), kBlock, 0, ctx->stream>>>(
+                    n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt, ctx->p.c_red,
+                    ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, ctx->status);
+            else
+                k_transport64_tile<G, false><<<(unsigned)xcd_grid(nt), kBlock, 0, ctx->stream>>>(
+                    n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt, ctx->p.c_red,
+                    ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, ctx->status);
             return;
         }
     }
