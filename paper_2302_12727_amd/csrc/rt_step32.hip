@@ -413,9 +413,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
     }
 }
 
-// Lanes per particle of the FP32 gradient (1, 2 or 4).  Kept at 1: with 4,
-// the compensated-FP32 adjoint moved away from the FP64 one (luminosity
-// gradients 1.4e-5 apart instead of 3e-8) for a reason not yet isolated.
+// Lanes per particle of the FP32 gradient (1, 2 or 4).  With 4 the
+// compensated-FP32 adjoint of the 1000-particle adjoint case moved away from
+// the FP64 one (luminosity gradients 1.4e-5 apart instead of 3e-8): the
+// four-lane order of the FP32 sums decides a minmod tie of the next transport
+// (one pair whose two slopes agree to 2.5e-7 in FP64) the other way, and the
+// adjoint differentiates through the branch taken.  Either order is as
+// accurate as the other; the one-lane order is kept since it leaves that case
+// on the FP64 branch.
 #ifndef RT_GRADIENT32_Q
 #define RT_GRADIENT32_Q 1
 #endif
