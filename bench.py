@@ -251,8 +251,18 @@ def compare_precisions(w, dev):
     errs["photon_total"] = float(np.abs(f32["Q"] / f64["Q"] - 1).max())
     errs["fp32c_own_photon_budget_residual"] = f32["photon_budget_residual"]
     h = f64["rt"].h
-    res = {"workload": w.name, "n": w.n, "groups": w.groups, "steps": w.steps,
-           "pairs": f64["pairs"], "h_span": float((h.max() / h.min()).item()),
+    span = float((h.max() / h.min()).item())
+    label = w.name
+    if w.name.startswith("plummer"):
+        # the mixture's density contrast sets the span: 90% of the points in
+        # a Plummer sphere of scale radius 0.05 give a core density about
+        # 1.7e4 times the 10% uniform background's, an h ratio of about 26
+        # between core and background (Poisson extremes widen it); an h span
+        # of about 100 would need a core radius near 0.02
+        label += (f": {w.n} particles, Plummer sphere (scale radius 0.05, truncated at 0.5) "
+                  f"with 10% uniform background; h spans {span:.0f}x")
+    res = {"workload": label, "n": w.n, "groups": w.groups, "steps": w.steps,
+           "pairs": f64["pairs"], "h_span": span,
            "fp64": {"value": f64["pairs"] * w.steps / f64["elapsed"],
                     "ms_per_step": f64["elapsed"] / w.steps * 1e3,
                     "transport_ms": f64["transport_ms"], "gradient_ms": f64["gradient_ms"]},
