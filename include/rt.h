@@ -373,6 +373,11 @@ typedef struct {
     int64_t h_list_overflow;   /* particles of the last build whose smoothing-
                                length candidate list overflowed (their later
                                evaluations walked the tree again)               */
+    int64_t union_blocks;      /* FP64, up to 4 groups: blocks of 64 particles
+                               whose gradient reads its neighbours from their
+                               union staged in LDS                              */
+    int64_t union_staged_blocks; /* those whose union did not fit (the gradient
+                               stages their rows per pair instead)              */
 } rt_stats;
 rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out /* [host] */);
 

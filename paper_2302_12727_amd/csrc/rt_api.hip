@@ -127,7 +127,8 @@ void rt_destroy(rt_ctx *ctx) {
                     ctx->inj_gas, ctx->inj_src, ctx->inj_coef, ctx->inj_xi, ctx->src_ptr,
                     ctx->src_gas, ctx->src_coef, ctx->status, ctx->partials, ctx->scan_tmp,
                     ctx->adj_buf, ctx->hll_table, ctx->hll_table32, ctx->vol, ctx->ivan,
-                    ctx->bin8, ctx->task, ctx->n_task};
+                    ctx->bin8, ctx->task, ctx->n_task, ctx->uoff, ctx->urow, ctx->gloc,
+                    ctx->uown, ctx->ublk};
     for (void *b : bufs) rt_free(ctx, b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -363,6 +364,8 @@ rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out) {
     out->device_bytes = ctx->device_bytes;
     out->device_bytes_peak = ctx->device_peak;
     out->h_list_overflow = ctx->h_list_overflow;
+    out->union_blocks = ctx->uoff ? ctx->nwaves - ctx->n_ublk : 0;
+    out->union_staged_blocks = ctx->uoff ? ctx->n_ublk : 0;
     return RT_OK;
 }
 

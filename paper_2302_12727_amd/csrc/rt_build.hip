@@ -669,6 +669,104 @@ __global__ __launch_bounds__(64) void k_tasks(int64_t n, const int64_t *__restri
     n_task[i] = c;
 }
 
+// Neighbour unions of the FP64 gradient (k_gradient64u): for every block of
+// 64 particles (a column block of the neighbour table) the sorted distinct
+// indices of its particles and of their gather neighbours, which the
+// gradient stages in LDS once instead of fetching a neighbour's row for every
+// pair (each row is used 6-8 times by a block).  Each gather slot gets the
+// 16-bit position of its neighbour in the union (gloc), each particle its own
+// (uown).  The distinct indices are collected in an LDS hash table (open
+// addressing with bounded probing) and sorted (bitonic, kUnionSort keys).
+// Count pass (FILL false): rows[b] = the union's size, or 0 if it does not
+// fit `cap` (the block is left to the staged gradient); the fill pass writes
+// the rows at uoff[b], gloc and uown.  One block of 256 threads (4 per
+// particle) per 64-particle block.
+constexpr int kUnionHash = 4096;
+
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_union(int64_t n, int cap,
+                                               const int64_t *__restrict__ wave_base,
+                                               const int32_t *__restrict__ n_gath,
+                                               const int32_t *__restrict__ nbr,
+                                               int64_t *__restrict__ rows,
+                                               const int64_t *__restrict__ uoff,
+                                               int32_t *__restrict__ urow,
+                                               uint16_t *__restrict__ gloc,
+                                               uint16_t *__restrict__ uown) {
+    __shared__ int32_t keys[kUnionHash];
+    __shared__ int32_t srt[kUnionSort];
+    __shared__ int32_t cnt, fail;
+    const int64_t b = blockIdx.x, t0 = b * 64;
+    for (int e = threadIdx.x; e < kUnionHash; e += 256) keys[e] = -1;
+    if (threadIdx.x == 0) {
+        cnt = 0;
+        fail = 0;
+    }
+    __syncthreads();
+    const int p = threadIdx.x >> 2, sub = threadIdx.x & 3;
+    const int64_t i = t0 + p;
+    const bool active = i < n;
+    const int64_t base = wave_base[b] + p;
+    const int32_t ng = active ? n_gath[i] : 0;
+    auto insert = [&](int32_t j) {
+        uint32_t h = ((uint32_t)j * 2654435761u) >> 20;     // 12 bits
+        for (int probe = 0; probe < kUnionHash; ++probe) {
+            const int32_t old = atomicCAS(&keys[h], -1, j);
+            if (old == -1 || old == j) return;
+            h = (h + 1) & (kUnionHash - 1);
+        }
+        atomicOr(&fail, 1);                                 // table full
+    };
+    if (active && sub == 0) insert((int32_t)i);
+    for (int32_t k = sub; k < ng; k += 4) insert(nbr[base + 64 * (int64_t)k]);
+    __syncthreads();
+    // compact in any order (sorted next)
+    for (int e = threadIdx.x; e < kUnionHash; e += 256) {
+        const int32_t key = keys[e];
+        if (key >= 0) {
+            const int32_t pos = atomicAdd(&cnt, 1);
+            if (pos < kUnionSort) srt[pos] = key;
+        }
+    }
+    __syncthreads();
+    const int32_t m = cnt;
+    const bool fits = fail == 0 && m <= cap;                // block-uniform
+    if (!FILL) {
+        if (threadIdx.x == 0) rows[b] = fits ? m : 0;
+        return;
+    }
+    if (!fits) return;
+    for (int e = m + threadIdx.x; e < kUnionSort; e += 256) srt[e] = INT32_MAX;
+    __syncthreads();
+    for (int k = 2; k <= kUnionSort; k <<= 1)
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int e = threadIdx.x; e < kUnionSort; e += 256) {
+                const int l = e ^ jj;
+                if (l > e) {
+                    const int32_t a = srt[e], c = srt[l];
+                    if ((a > c) == ((e & k) == 0)) {
+                        srt[e] = c;
+                        srt[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    const int64_t u0 = uoff[b];
+    for (int e = threadIdx.x; e < m; e += 256) urow[u0 + e] = srt[e];
+    auto find = [&](int32_t j) {                            // j is in the union
+        int lo = 0, hi = m - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (srt[mid] < j) lo = mid + 1;
+            else hi = mid;
+        }
+        return (uint16_t)lo;
+    };
+    if (active && sub == 0) uown[i] = find((int32_t)i);
+    for (int32_t k = sub; k < ng; k += 4) gloc[base + 64 * (int64_t)k] = find(nbr[base + 64 * (int64_t)k]);
+}
+
 inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -696,6 +794,10 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     rt_free(ctx, ctx->node_hmax); rt_free(ctx, ctx->n_nbr); rt_free(ctx, ctx->n_gath); rt_free(ctx, ctx->wave_base);
     rt_free(ctx, ctx->nbr); rt_free(ctx, ctx->vol); rt_free(ctx, ctx->ivan);
     rt_free(ctx, ctx->task); rt_free(ctx, ctx->n_task);
+    rt_free(ctx, ctx->uoff); rt_free(ctx, ctx->urow); rt_free(ctx, ctx->gloc);
+    rt_free(ctx, ctx->uown); rt_free(ctx, ctx->ublk);
+    ctx->uoff = nullptr; ctx->urow = nullptr; ctx->gloc = nullptr; ctx->uown = nullptr;
+    ctx->ublk = nullptr; ctx->n_ublk = 0;
     ctx->vol = nullptr;
     ctx->ivan = nullptr;
     ctx->task = nullptr;
@@ -719,6 +821,7 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     int64_t *width = nullptr;
     void *sort_tmp = nullptr;
     size_t sort_bytes = 0;
+    int64_t *width_u = nullptr;   // union sizes of the gradient's blocks
 
 #define ALLOC(p, bytes)                                              \
     do {                                                             \
@@ -848,6 +951,60 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
             ALLOC(ctx->n_task, sizeof(int32_t) * n);
             k_tasks<<<(unsigned)ctx->nwaves, 64, 0, st>>>(n, ctx->wave_base, ctx->n_nbr, ctx->nbr,
                                                           ctx->task, ctx->n_task);
+            // neighbour unions of the gradient: sizes at the 2-wave capacity,
+            // then 3 waves per SIMD if nearly every block fits that capacity
+            int cap = union_cap(ctx->p.groups);
+            if (cap > 0) {
+                const int64_t nw = ctx->nwaves;
+                std::vector<int64_t> rows(nw + 1);
+                ALLOC(width_u, sizeof(int64_t) * (nw + 1));
+                k_union<false><<<(unsigned)nw, 256, 0, st>>>(n, cap, ctx->wave_base, ctx->n_gath,
+                                                             ctx->nbr, width_u, nullptr, nullptr,
+                                                             nullptr, nullptr);
+                RT_HIP(hipMemcpyAsync(rows.data(), width_u, sizeof(int64_t) * nw,
+                                      hipMemcpyDeviceToHost, st));
+                RT_HIP(hipStreamSynchronize(st));
+                const int cap3 = union_cap3(ctx->p.groups);
+                ctx->union_waves = 2;
+                if (cap3 > 0) {
+                    int64_t fit = 0;
+                    for (int64_t b = 0; b < nw; ++b) fit += rows[b] > 0 && rows[b] <= cap3;
+                    if (fit >= nw - nw / 20) {
+                        ctx->union_waves = 3;
+                        cap = cap3;
+                        for (int64_t b = 0; b < nw; ++b)
+                            if (rows[b] > cap3) rows[b] = 0;
+                    }
+                }
+                // offsets (exclusive sums), and the blocks left to the staged gradient
+                std::vector<int32_t> over;
+                int64_t acc = 0;
+                for (int64_t b = 0; b < nw; ++b) {
+                    const int64_t r = rows[b];
+                    rows[b] = acc;
+                    acc += r;
+                    if (r == 0) over.push_back((int32_t)b);
+                }
+                rows[nw] = acc;
+                ALLOC(ctx->uoff, sizeof(int64_t) * (nw + 1));
+                RT_HIP(hipMemcpyAsync(ctx->uoff, rows.data(), sizeof(int64_t) * (nw + 1),
+                                      hipMemcpyHostToDevice, st));
+                ALLOC(ctx->urow, sizeof(int32_t) * std::max<int64_t>(acc, 1));
+                ALLOC(ctx->gloc, sizeof(uint16_t) * std::max<int64_t>(ctx->slots, 1));
+                ALLOC(ctx->uown, sizeof(uint16_t) * n);
+                k_union<true><<<(unsigned)nw, 256, 0, st>>>(n, cap, ctx->wave_base, ctx->n_gath,
+                                                            ctx->nbr, nullptr, ctx->uoff, ctx->urow,
+                                                            ctx->gloc, ctx->uown);
+                ctx->n_ublk = (int64_t)over.size();
+                if (!over.empty()) {
+                    ALLOC(ctx->ublk, sizeof(int32_t) * over.size());
+                    RT_HIP(hipMemcpyAsync(ctx->ublk, over.data(), sizeof(int32_t) * over.size(),
+                                          hipMemcpyHostToDevice, st));
+                }
+                RT_HIP(hipStreamSynchronize(st));
+                rt_free(ctx, width_u);
+                width_u = nullptr;
+            }
         }
         // geometry records, volumes, time step
         RT_HIP(hipMemsetAsync(ctx->status, 0, sizeof(int32_t), st));
@@ -899,7 +1056,7 @@ fail:
     (void)hipMemsetAsync(ctx->status, 0, sizeof(int32_t), st);
     (void)hipStreamSynchronize(st);
     rt_free(ctx, keys_in); rt_free(ctx, idx_in); rt_free(ctx, Htmp); rt_free(ctx, width); rt_free(ctx, dxpart);
-    rt_free(ctx, sort_tmp); rt_free(ctx, nlist);
+    rt_free(ctx, sort_tmp); rt_free(ctx, nlist); rt_free(ctx, width_u);
     return rs;
 #undef ALLOC
 }

@@ -23,6 +23,14 @@ constexpr int kRec = 16;      // doubles per particle geometry record (one 128-b
 // evaluated once.  (Tiles of 16 and 32 particles, one wave per tile, ran
 // 3.84 and 3.78 ms against 3.64 for 64 on the 3-group 128^3 lattice.)
 constexpr int kTile = 64;
+// Rows of a block's neighbour union that the FP64 gradient stages in LDS (a
+// block of 64 particles, two blocks per CU: 4G + 3 doubles a row in at most
+// 80 KB); 0: no union path at this group count.  At most kUnionSort.
+constexpr int kUnionSort = 1024;
+constexpr int union_cap(int G) { return G == 1 ? 1024 : G == 2 ? 880 : G == 3 ? 640 : G == 4 ? 512 : 0; }
+// At 3 groups a smaller union (420 rows) lets three blocks share a CU, 3
+// waves per SIMD; the build takes it when nearly every block's union fits.
+constexpr int union_cap3(int G) { return G == 3 ? 420 : 0; }
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kSigma3 = 16.0 / kPi;   // cubic spline normalisation in 3D
 
@@ -84,6 +92,15 @@ struct rt_ctx {
     int32_t *nbr = nullptr;      // [slots]
     int32_t *task = nullptr;     // [slots] task lists of the FP64 tile transport (same slots)
     int32_t *n_task = nullptr;   // [n]
+    // neighbour unions of the FP64 gradient (k_union): per block of 64
+    // particles its sorted distinct gather neighbours and own particles
+    int64_t *uoff = nullptr;     // [nwaves + 1] offsets into urow (no rows: staged gradient)
+    int32_t *urow = nullptr;     // [uoff[nwaves]]
+    uint16_t *gloc = nullptr;    // [slots] a gather slot's position in its block's union
+    uint16_t *uown = nullptr;    // [n] a particle's position in its block's union
+    int32_t *ublk = nullptr;     // [n_ublk] blocks left to the staged gradient
+    int64_t n_ublk = 0;
+    int union_waves = 2;         // waves per SIMD of the union gradient (capacity by it)
 
     // sources
     int32_t S = 0;

@@ -66,6 +66,48 @@ __global__ void k_inject(int32_t ngas, int G, const int32_t *__restrict__ gptr,
 // two doubles as one 16-byte access (a native vector: copies stay in registers)
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
+// Gradient record of particle i from its Q lanes' sums (every lane holds the
+// combined sums acc = sum_j (q_j - q_i) w_ij s_ij and the own state Ui): the
+// gradients are B_i/V_i acc; the Q lanes write consecutive 16-byte pieces of
+// the record.  chk stays 0 unless a value written is NaN or infinite (0 x v is
+// 0 for finite v and NaN otherwise).
+template <int G, int Q>
+__device__ __forceinline__ void gradient_record(double (&acc)[4 * G][3], const double (&Ui)[4 * G],
+                                                const double *__restrict__ rec, double *o, int sub,
+                                                int32_t *__restrict__ status) {
+    constexpr int NQ = 4 * G;
+    const double iV = 1.0 / rec[R_V];
+    const double b00 = rec[R_B] * iV, b01 = rec[R_B + 1] * iV, b02 = rec[R_B + 2] * iV;
+    const double b11 = rec[R_B + 3] * iV, b12 = rec[R_B + 4] * iV, b22 = rec[R_B + 5] * iV;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double d0 = b00 * acc[q][0] + b01 * acc[q][1] + b02 * acc[q][2];
+        const double d1 = b01 * acc[q][0] + b11 * acc[q][1] + b12 * acc[q][2];
+        const double d2 = b02 * acc[q][0] + b12 * acc[q][1] + b22 * acc[q][2];
+        acc[q][0] = d0;
+        acc[q][1] = d1;
+        acc[q][2] = d2;
+    }
+    // group-major record: per group the state then its gradients (one line);
+    // double d of the record, d = 16 g + s
+    auto value = [&](int d) {
+        const int g = d / 16, s = d % 16;
+        return s < 4 ? Ui[4 * g + s] : acc[4 * g + (s - 4) / 3][(s - 4) % 3];
+    };
+    double chk = 0.0;
+#pragma unroll
+    for (int t = 0; t < 8 * G / Q; ++t) {
+        double2 val = make_double2(value(2 * Q * t), value(2 * Q * t + 1));
+#pragma unroll
+        for (int s = 1; s < Q; ++s)
+            if (sub == s) val = make_double2(value(2 * (Q * t + s)), value(2 * (Q * t + s) + 1));
+        chk = __builtin_fma(val.x, 0.0, chk);
+        chk = __builtin_fma(val.y, 0.0, chk);
+        *reinterpret_cast<double2 *>(o + 2 * (Q * t + sub)) = val;
+    }
+    if (chk != chk) atomicOr(status, ST_NONFINITE);
+}
+
 // ---------------------------------------------------------------------------
 // Gradient (eq:gradient):  grad q_i = sum_j (q_j - q_i) psi~_j(x_i)
 //   = S_i^{-1} sum_j (q_j - q_i) w(r_ij / H_i) s_ij   (the kernel normalisation
@@ -127,7 +169,8 @@ __global__ __launch_bounds__(grad_block(G)) __attribute__((amdgpu_waves_per_eu(
     int64_t n, int64_t nb, const double *__restrict__ geo, const double *__restrict__ xs,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_gath, const double *__restrict__ U, double *__restrict__ UD,
-    int32_t *__restrict__ status, double box, int64_t tick = 0) {
+    int32_t *__restrict__ status, double box, int64_t tick = 0,
+    const int32_t *__restrict__ blist = nullptr) {
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     constexpr int NQ = 4 * G;
     constexpr int PU = 2 * G;           // 16-byte pieces of a state
@@ -139,8 +182,9 @@ __global__ __launch_bounds__(grad_block(G)) __attribute__((amdgpu_waves_per_eu(
     __shared__ dvec2 own[W][NP * S];
     __shared__ double spos[W][64 * 3];
     __shared__ double opos[W][NP * 3];
-    const int64_t blk = xcd_block(nb);
-    if (blk >= nb) return;                      // whole block
+    const int64_t bx = xcd_block(nb);
+    if (bx >= nb) return;                       // whole block
+    const int64_t blk = blist ? (int64_t)blist[bx] : bx;   // only the listed blocks
     const int lane = threadIdx.x & 63;
     const int sub = lane % Q;
     // the wave's first particle; the wave stays whole (its loads are shared)
@@ -276,40 +320,140 @@ __global__ __launch_bounds__(grad_block(G)) __attribute__((amdgpu_waves_per_eu(
         Ui[2 * t] = x.x;
         Ui[2 * t + 1] = x.y;
     }
-    const double iV = 1.0 / rec[R_V];
-    const double b00 = rec[R_B] * iV, b01 = rec[R_B + 1] * iV, b02 = rec[R_B + 2] * iV;
-    const double b11 = rec[R_B + 3] * iV, b12 = rec[R_B + 4] * iV, b22 = rec[R_B + 5] * iV;
+    gradient_record<G, Q>(acc, Ui, rec, UD + ic * (16 * G), sub, status);
+}
+
+// Gradient from the block's neighbour union (FP64, up to 4 groups, the global
+// step).  The 64 particles of a block (a column block of the neighbour table)
+// gather from about 360 (lattice) to 580 (Plummer set) distinct particles,
+// each 6-8 times.  The build lists them (k_union); this kernel stages their
+// states and positions in LDS once, with coalesced loads, and every pair then
+// reads its neighbour's row from LDS by its 16-bit position in the union
+// (gloc): no global load in the pair loop but the table's 2-byte entry.
+// Blocks whose union did not fit the LDS are left to k_gradient64 (a second
+// launch over their list).  Sums in the same order as k_gradient64 (lane sub
+// takes the slots sub, sub + Q, ...; rows past a list are the own row, whose
+// differences are zero), so the two give the same bits.
+template <int G, int Q, int W>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(W, W))) void
+k_gradient64u(int64_t n, int64_t nb, const double *__restrict__ geo, const double *__restrict__ xs,
+              const int32_t *__restrict__ urow, const int64_t *__restrict__ uoff,
+              const uint16_t *__restrict__ gloc, const uint16_t *__restrict__ uown,
+              const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_gath,
+              const double *__restrict__ U, double *__restrict__ UD, int32_t *__restrict__ status,
+              double box) {
+    static_assert(Q == 4 && kBlock == 256, "one block of 64 particles per table column block");
+    constexpr int NQ = 4 * G, PU = 2 * G, UC = W == 3 ? union_cap3(G) : union_cap(G);
+    static_assert(UC > 0 && UC <= kUnionSort, "union capacity");
+    __shared__ dvec2 ust[UC * PU];
+    __shared__ double upos[UC * 3];
+    __shared__ int32_t uidx[UC];
+    const int64_t blk = xcd_block(nb);
+    if (blk >= nb) return;                      // whole block
+    const int64_t u0 = uoff[blk];
+    const int32_t rows = (int32_t)(uoff[blk + 1] - u0);
+    if (rows == 0) return;                      // left to the staged gradient (whole block)
+    // stage the union: its indices first, then every thread's pieces of the
+    // states (16 bytes) and positions (doubles) in flight at once (a chain of
+    // dependent loads per piece left the blocks waiting: 1.38 ms)
+    for (int e = threadIdx.x; e < rows; e += kBlock) uidx[e] = urow[u0 + e];
+    __syncthreads();
+    const dvec2 *U2 = reinterpret_cast<const dvec2 *>(U);
+    const int ts = rows * PU, tp = rows * 3;
+    {
+        constexpr int MS = (UC * PU + kBlock - 1) / kBlock, MP = (UC * 3 + kBlock - 1) / kBlock;
+        dvec2 v[MS];
+        double x[MP];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const double d0 = b00 * acc[q][0] + b01 * acc[q][1] + b02 * acc[q][2];
-        const double d1 = b01 * acc[q][0] + b11 * acc[q][1] + b12 * acc[q][2];
-        const double d2 = b02 * acc[q][0] + b12 * acc[q][1] + b22 * acc[q][2];
-        acc[q][0] = d0;
-        acc[q][1] = d1;
-        acc[q][2] = d2;
+        for (int r = 0; r < MS; ++r) {
+            const int e = threadIdx.x + r * kBlock;
+            if (e < ts) v[r] = U2[(uint32_t)uidx[e / PU] * (uint32_t)PU + (uint32_t)(e % PU)];
+        }
+#pragma unroll
+        for (int r = 0; r < MP; ++r) {
+            const int e = threadIdx.x + r * kBlock;
+            if (e < tp) x[r] = xs[(uint32_t)uidx[e / 3] * 3u + (uint32_t)(e % 3)];
+        }
+#pragma unroll
+        for (int r = 0; r < MS; ++r)
+            if (threadIdx.x + r * kBlock < ts) ust[threadIdx.x + r * kBlock] = v[r];
+#pragma unroll
+        for (int r = 0; r < MP; ++r)
+            if (threadIdx.x + r * kBlock < tp) upos[threadIdx.x + r * kBlock] = x[r];
     }
-    // group-major record: per group the state then its gradients (one line);
-    // double d of the record, d = 16 g + s
-    auto value = [&](int d) {
-        const int g = d / 16, s = d % 16;
-        return s < 4 ? Ui[4 * g + s] : acc[4 * g + (s - 4) / 3][(s - 4) % 3];
-    };
-    // the Q lanes write consecutive 16-byte pieces of the record; chk stays 0
-    // unless a value written is NaN or infinite (0 x v is 0 for finite v and
-    // NaN otherwise)
-    double *o = UD + ic * (16 * G);
-    double chk = 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, sub = lane % Q;
+    const int p = threadIdx.x / Q;              // the particle in the block
+    const int64_t i = blk * (kBlock / Q) + p;
+    const bool active = i < n;
+    const int64_t ic = active ? i : n - 1;
+    const int32_t ng = active ? n_gath[ic] : 0;
+    const int il = active ? (int)uown[ic] : 0;  // a row of the union (not used past n)
+    int32_t kmax = ng;                          // the wave's longest list
 #pragma unroll
-    for (int t = 0; t < 8 * G / Q; ++t) {
-        double2 val = make_double2(value(2 * Q * t), value(2 * Q * t + 1));
+    for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
+    const double *rec = geo + (int64_t)kRec * ic;
+    const double ibox = 1.0 / box, iH = rec[R_IH];
+    double Ui[NQ];
 #pragma unroll
-        for (int s = 1; s < Q; ++s)
-            if (sub == s) val = make_double2(value(2 * (Q * t + s)), value(2 * (Q * t + s) + 1));
-        chk = __builtin_fma(val.x, 0.0, chk);
-        chk = __builtin_fma(val.y, 0.0, chk);
-        *reinterpret_cast<double2 *>(o + 2 * (Q * t + sub)) = val;
+    for (int t = 0; t < PU; ++t) {
+        const dvec2 x = ust[il * PU + t];
+        Ui[2 * t] = x.x;
+        Ui[2 * t + 1] = x.y;
     }
-    if (chk != chk) atomicOr(status, ST_NONFINITE);
+    const double px = upos[3 * il], py = upos[3 * il + 1], pz = upos[3 * il + 2];
+    double acc[NQ][3];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
+    if (kmax > 0) {
+        // slot k of the particle's column, or slot 0 past the end of its list
+        // (present: some column of this table block holds an entry)
+        const uint16_t *col = gloc + wave_base[blk] + p;
+        auto entry = [&](int32_t k) __attribute__((always_inline)) {
+            return (int)col[64 * (k < ng ? k : 0)];
+        };
+        auto pair = [&](int jl) __attribute__((always_inline)) {
+            const dvec2 *row = ust + jl * PU;
+            const double sx = min_image(upos[3 * jl] - px, box, ibox);
+            const double sy = min_image(upos[3 * jl + 1] - py, box, ibox);
+            const double sz = min_image(upos[3 * jl + 2] - pz, box, ibox);
+            const double w = kern_w(sqrt64(sx * sx + sy * sy + sz * sz) * iH);
+            const double wx = w * sx, wy = w * sy, wz = w * sz;
+#pragma unroll
+            for (int t = 0; t < PU; ++t) {
+                const dvec2 uj = row[t];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int q = 2 * t + h;
+                    const double d = uj[h] - Ui[q];
+                    acc[q][0] += d * wx;
+                    acc[q][1] += d * wy;
+                    acc[q][2] += d * wz;
+                }
+            }
+        };
+        // The table streams from HBM: each entry is loaded two iterations
+        // ahead, into the register its own use has just freed (a rotating
+        // set of registers made every iteration wait for the newest load).
+        // Both halves always run: past a list the row is the own one.
+        int ea = entry(sub), eb = entry(Q + sub);
+        for (int32_t kk = 0; kk < kmax; kk += 2 * Q) {
+            const int ja = kk + sub < ng ? ea : il;
+            ea = entry(kk + 2 * Q + sub);
+            pair(ja);
+            const int jb = kk + Q + sub < ng ? eb : il;
+            eb = entry(kk + 3 * Q + sub);
+            pair(jb);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int o = 1; o < Q; o <<= 1) acc[q][a] += __shfl_xor(acc[q][a], o, 64);
+    if (!active) return;
+    gradient_record<G, Q>(acc, Ui, rec, UD + ic * (16 * G), sub, status);
 }
 
 // Transport (eq:transport-update-explicit with the GLF flux eq:riemann-GLF).
@@ -1100,6 +1244,28 @@ constexpr int kGQ = RT_GRADIENT_Q;
 template <int G>
 void launch_gradient64(rt_ctx *ctx, const double *U, double *UD) {
     constexpr int B = grad_block(G);
+    if constexpr (union_cap(G) > 0 && kGQ == 4 && B == 256) {
+        if (ctx->uoff) {
+            // blocks whose union fits: from LDS; the others: staged, by list
+            const int64_t nw = ctx->nwaves;
+#define RT_UNION_LAUNCH(W_)                                                                    \
+    k_gradient64u<G, kGQ, W_><<<(unsigned)xcd_grid(nw), kBlock, 0, ctx->stream>>>(            \
+        ctx->p.n, nw, ctx->geo, ctx->xs, ctx->urow, ctx->uoff, ctx->gloc, ctx->uown,          \
+        ctx->wave_base, ctx->n_gath, U, UD, ctx->status, ctx->p.box)
+            if constexpr (union_cap3(G) > 0) {
+                if (ctx->union_waves == 3) RT_UNION_LAUNCH(3);
+                else RT_UNION_LAUNCH(2);
+            } else {
+                RT_UNION_LAUNCH(2);
+            }
+#undef RT_UNION_LAUNCH
+            if (ctx->n_ublk > 0)
+                k_gradient64<G, false, kGQ><<<(unsigned)xcd_grid(ctx->n_ublk), B, 0, ctx->stream>>>(
+                    ctx->p.n, ctx->n_ublk, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath,
+                    U, UD, ctx->status, ctx->p.box, 0, ctx->ublk);
+            return;
+        }
+    }
     const int64_t n = ctx->p.n, nb = (n + B / kGQ - 1) / (B / kGQ);
     k_gradient64<G, false, kGQ><<<(unsigned)xcd_grid(nb), B, 0, ctx->stream>>>(
         n, nb, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->status,

@@ -212,3 +212,29 @@ def test_support_beyond_half_box_is_refused():
     rt = RT(27, 1)
     with pytest.raises(RTError, match="RT_EINVAL"):
         rt.rt_build_cells(dev(x))
+
+
+def test_gradient_union_and_staged_blocks():
+    """The FP64 gradient reads a block's neighbours from their union staged in
+    LDS where it fits (512 rows at 4 groups) and stages rows per pair in the
+    other blocks: a 4-group Plummer set takes both paths.  Every record
+    against the oracle."""
+    w = workloads.config(4, scale=(1 << 14) / (1 << 24))   # Plummer + background, 4 groups
+    log(f"case plummer n={w.n} G={w.groups}: gradient union and staged blocks")
+    geo = oracle.build_geometry(w.x)
+    rt = RT(w.n, w.groups)
+    perm, *_ = rt.rt_build_cells(dev(w.x), dev(geo.h))
+    p = perm.cpu().numpy()
+    st = rt.rt_get_stats()
+    log(f"blocks from the union: {st['union_blocks']}, staged: {st['union_staged_blocks']}")
+    assert st["union_blocks"] > 0 and st["union_staged_blocks"] > 0
+    assert st["union_blocks"] + st["union_staged_blocks"] == (w.n + 63) // 64
+    UD = rt.rt_gradient(dev(w.U0[p]))
+    rt.rt_sync()
+    got = unsort(rt.gradients_of(UD).cpu().numpy(), p)
+    ref = oracle.gradient(geo, w.U0)
+    scale = np.abs(ref).max(axis=(-1, -2), keepdims=True)
+    err = (np.abs(got - ref) / scale).max()
+    log(f"gradient max rel err {err:.3e}")
+    assert err < 1e-12
+    assert np.array_equal(unsort(rt.states_of(UD).cpu().numpy(), p), w.U0)
