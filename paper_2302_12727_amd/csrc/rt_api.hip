@@ -128,7 +128,7 @@ void rt_destroy(rt_ctx *ctx) {
                     ctx->src_gas, ctx->src_coef, ctx->status, ctx->partials, ctx->scan_tmp,
                     ctx->adj_buf, ctx->hll_table, ctx->hll_table32, ctx->vol, ctx->ivan,
                     ctx->bin8, ctx->task, ctx->n_task, ctx->uoff, ctx->urow, ctx->gloc,
-                    ctx->uown, ctx->ublk};
+                    ctx->uown, ctx->ublk, ctx->goff};
     for (void *b : bufs) rt_free(ctx, b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;

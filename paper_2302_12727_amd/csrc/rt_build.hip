@@ -679,8 +679,8 @@ __global__ __launch_bounds__(64) void k_tasks(int64_t n, const int64_t *__restri
 // addressing with bounded probing) and sorted (bitonic, kUnionSort keys).
 // Count pass (FILL false): rows[b] = the union's size, or 0 if it does not
 // fit `cap` (the block is left to the staged gradient); the fill pass writes
-// the rows at uoff[b], gloc and uown.  One block of 256 threads (4 per
-// particle) per 64-particle block.
+// the rows at uoff[b], gloc (packed, see rt_ctx) and uown.  One block of 256
+// threads (4 per particle) per 64-particle block.
 constexpr int kUnionHash = 4096;
 
 template <bool FILL>
@@ -691,6 +691,7 @@ __global__ __launch_bounds__(256) void k_union(int64_t n, int cap,
                                                int64_t *__restrict__ rows,
                                                const int64_t *__restrict__ uoff,
                                                int32_t *__restrict__ urow,
+                                               const int64_t *__restrict__ goff,
                                                uint16_t *__restrict__ gloc,
                                                uint16_t *__restrict__ uown) {
     __shared__ int32_t keys[kUnionHash];
@@ -764,7 +765,9 @@ __global__ __launch_bounds__(256) void k_union(int64_t n, int cap,
         return (uint16_t)lo;
     };
     if (active && sub == 0) uown[i] = find((int32_t)i);
-    for (int32_t k = sub; k < ng; k += 4) gloc[base + 64 * (int64_t)k] = find(nbr[base + 64 * (int64_t)k]);
+    uint16_t *g = gloc + goff[b] + 4 * (int64_t)threadIdx.x;   // lane 4p + sub
+    for (int32_t k = sub; k < ng; k += 4)
+        g[(int64_t)(k >> 4) * 1024 + ((k >> 2) & 3)] = find(nbr[base + 64 * (int64_t)k]);
 }
 
 inline unsigned nblk(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
@@ -795,8 +798,9 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     rt_free(ctx, ctx->nbr); rt_free(ctx, ctx->vol); rt_free(ctx, ctx->ivan);
     rt_free(ctx, ctx->task); rt_free(ctx, ctx->n_task);
     rt_free(ctx, ctx->uoff); rt_free(ctx, ctx->urow); rt_free(ctx, ctx->gloc);
-    rt_free(ctx, ctx->uown); rt_free(ctx, ctx->ublk);
+    rt_free(ctx, ctx->uown); rt_free(ctx, ctx->ublk); rt_free(ctx, ctx->goff);
     ctx->uoff = nullptr; ctx->urow = nullptr; ctx->gloc = nullptr; ctx->uown = nullptr;
+    ctx->goff = nullptr;
     ctx->ublk = nullptr; ctx->n_ublk = 0;
     ctx->vol = nullptr;
     ctx->ivan = nullptr;
@@ -960,7 +964,7 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
                 ALLOC(width_u, sizeof(int64_t) * (nw + 1));
                 k_union<false><<<(unsigned)nw, 256, 0, st>>>(n, cap, ctx->wave_base, ctx->n_gath,
                                                              ctx->nbr, width_u, nullptr, nullptr,
-                                                             nullptr, nullptr);
+                                                             nullptr, nullptr, nullptr);
                 RT_HIP(hipMemcpyAsync(rows.data(), width_u, sizeof(int64_t) * nw,
                                       hipMemcpyDeviceToHost, st));
                 RT_HIP(hipStreamSynchronize(st));
@@ -990,11 +994,22 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
                 RT_HIP(hipMemcpyAsync(ctx->uoff, rows.data(), sizeof(int64_t) * (nw + 1),
                                       hipMemcpyHostToDevice, st));
                 ALLOC(ctx->urow, sizeof(int32_t) * std::max<int64_t>(acc, 1));
-                ALLOC(ctx->gloc, sizeof(uint16_t) * std::max<int64_t>(ctx->slots, 1));
+                // packed table entries: 1024 per group of 16 table rows of a block
+                std::vector<int64_t> wb(nw + 1), go(nw + 1);
+                RT_HIP(hipMemcpyAsync(wb.data(), ctx->wave_base, sizeof(int64_t) * (nw + 1),
+                                      hipMemcpyDeviceToHost, st));
+                RT_HIP(hipStreamSynchronize(st));
+                go[0] = 0;
+                for (int64_t b = 0; b < nw; ++b)
+                    go[b + 1] = go[b] + 1024 * (((wb[b + 1] - wb[b]) / 64 + 15) / 16);
+                ALLOC(ctx->goff, sizeof(int64_t) * (nw + 1));
+                RT_HIP(hipMemcpyAsync(ctx->goff, go.data(), sizeof(int64_t) * (nw + 1),
+                                      hipMemcpyHostToDevice, st));
+                ALLOC(ctx->gloc, sizeof(uint16_t) * std::max<int64_t>(go[nw], 4));
                 ALLOC(ctx->uown, sizeof(uint16_t) * n);
                 k_union<true><<<(unsigned)nw, 256, 0, st>>>(n, cap, ctx->wave_base, ctx->n_gath,
                                                             ctx->nbr, nullptr, ctx->uoff, ctx->urow,
-                                                            ctx->gloc, ctx->uown);
+                                                            ctx->goff, ctx->gloc, ctx->uown);
                 ctx->n_ublk = (int64_t)over.size();
                 if (!over.empty()) {
                     ALLOC(ctx->ublk, sizeof(int32_t) * over.size());

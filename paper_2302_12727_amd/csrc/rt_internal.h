@@ -96,7 +96,11 @@ struct rt_ctx {
     // particles its sorted distinct gather neighbours and own particles
     int64_t *uoff = nullptr;     // [nwaves + 1] offsets into urow (no rows: staged gradient)
     int32_t *urow = nullptr;     // [uoff[nwaves]]
-    uint16_t *gloc = nullptr;    // [slots] a gather slot's position in its block's union
+    // a gather slot's position in its block's union, packed so that a lane's
+    // entries of four consecutive iterations share 8 bytes: entry (p, k) of
+    // block b at goff[b] + (k / 16) 1024 + (4 p + k % 4) 4 + (k / 4) % 4
+    uint16_t *gloc = nullptr;
+    int64_t *goff = nullptr;     // [nwaves + 1], 1024 ceil(rows / 16) entries per block
     uint16_t *uown = nullptr;    // [n] a particle's position in its block's union
     int32_t *ublk = nullptr;     // [n_ublk] blocks left to the staged gradient
     int64_t n_ublk = 0;
