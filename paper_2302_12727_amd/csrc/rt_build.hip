@@ -955,9 +955,13 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
             ALLOC(ctx->n_task, sizeof(int32_t) * n);
             k_tasks<<<(unsigned)ctx->nwaves, 64, 0, st>>>(n, ctx->wave_base, ctx->n_nbr, ctx->nbr,
                                                           ctx->task, ctx->n_task);
-            // neighbour unions of the gradient: sizes at the 2-wave capacity,
-            // then 3 waves per SIMD if nearly every block fits that capacity
-            int cap = union_cap(ctx->p.groups);
+        }
+        {
+            // neighbour unions of the gradient: FP64 sizes at the 2-wave
+            // capacity, then 3 waves per SIMD if nearly every block fits that
+            // capacity; FP32C at its 3-wave capacity
+            const bool f64 = ctx->p.precision == RT_FP64;
+            int cap = f64 ? union_cap(ctx->p.groups) : union_cap32(ctx->p.groups);
             if (cap > 0) {
                 const int64_t nw = ctx->nwaves;
                 std::vector<int64_t> rows(nw + 1);
@@ -968,8 +972,8 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
                 RT_HIP(hipMemcpyAsync(rows.data(), width_u, sizeof(int64_t) * nw,
                                       hipMemcpyDeviceToHost, st));
                 RT_HIP(hipStreamSynchronize(st));
-                const int cap3 = union_cap3(ctx->p.groups);
-                ctx->union_waves = 2;
+                const int cap3 = f64 ? union_cap3(ctx->p.groups) : 0;
+                ctx->union_waves = f64 ? 2 : 3;
                 if (cap3 > 0) {
                     int64_t fit = 0;
                     for (int64_t b = 0; b < nw; ++b) fit += rows[b] > 0 && rows[b] <= cap3;

@@ -31,6 +31,9 @@ constexpr int union_cap(int G) { return G == 1 ? 1024 : G == 2 ? 880 : G == 3 ? 
 // At 3 groups a smaller union (420 rows) lets three blocks share a CU, 3
 // waves per SIMD; the build takes it when nearly every block's union fits.
 constexpr int union_cap3(int G) { return G == 3 ? 420 : 0; }
+// The compensated-FP32 gradient's union: FP32 states (16G bytes a row), FP64
+// positions, three blocks per CU (at most 53 KB each).
+constexpr int union_cap32(int G) { return G == 1 ? 1024 : G == 2 ? 880 : G == 3 ? 672 : G == 4 ? 576 : 0; }
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kSigma3 = 16.0 / kPi;   // cubic spline normalisation in 3D
 

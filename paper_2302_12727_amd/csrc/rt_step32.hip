@@ -20,12 +20,18 @@ __global__ __launch_bounds__(kBlock) void k_gradient32(
     int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ xs,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_gath, const float *__restrict__ U, float *__restrict__ UD,
-    int32_t *__restrict__ status, double box, int64_t tick = 0) {
+    int32_t *__restrict__ status, double box, int64_t tick = 0,
+    const int32_t *__restrict__ blist = nullptr, int64_t n_list = 0) {
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
-    const int64_t blk = xcd_block(nb);
-    if (blk >= nb) return;
+    const int64_t bx = xcd_block(nb);
+    if (bx >= nb) return;
     const int sub = (threadIdx.x & 63) % Q;
-    const int64_t i = blk * (kBlock / Q) + threadIdx.x / Q;
+    int64_t i = bx * (kBlock / Q) + threadIdx.x / Q;
+    if (blist) {                                // only the listed 64-particle blocks, 4 / Q a block
+        const int64_t e = bx * (4 / Q) + (threadIdx.x / Q) / 64;
+        if (e >= n_list) return;
+        i = (int64_t)blist[e] * 64 + (threadIdx.x / Q) % 64;
+    }
     if (i >= n) return;                         // a particle's Q lanes leave together
     if (BIN && ((tick + 1) & ((int64_t(1) << (int32_t)geo32[(int64_t)F_REC * i + F_BIN]) - 1)) != 0)
         return;
@@ -92,6 +98,179 @@ __global__ __launch_bounds__(kBlock) void k_gradient32(
             chk = __builtin_fmaf(d1, 0.0f, chk);
             chk = __builtin_fmaf(d2, 0.0f, chk);
         }
+    }
+    if (chk != chk) atomicOr(status, ST_NONFINITE);
+}
+
+// four floats as one 16-byte access (a native vector: copies stay in registers)
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+// quad broadcast: every lane of a quad takes lane L's value (DPP quad_perm)
+template <int L>
+__device__ __forceinline__ float quad_bcast(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), L * 0x55, 0xf, 0xf, false));
+}
+template <int L>
+__device__ __forceinline__ int quad_bcast(int v) {
+    return __builtin_amdgcn_mov_dpp(v, L * 0x55, 0xf, 0xf, false);
+}
+
+// Gradient from the block's neighbour union in FP32 (compensated mode, up to
+// 4 groups; see k_gradient64u): the union's FP32 states (16G bytes a row) and
+// FP64 positions are staged in LDS once per block of 64 particles, and every
+// pair reads its neighbour's row from LDS by its 16-bit position in the union.
+// Three blocks per CU, 3 waves per SIMD.
+//
+// A particle's four lanes form a quad.  Each lane forms the pair geometry
+// w(r/H_i) s of every fourth neighbour, the quad shares the four by DPP
+// broadcasts, and lane m then accumulates component m (E, F_x, F_y, F_z) of
+// every group over all neighbours in list order: every sum is formed in the
+// same order and with the same operations as one lane per particle
+// (k_gradient32 with Q = 1), so the two give identical bits (see
+// RT_GRADIENT32_Q for why that order is kept).  Padding past a list is the
+// own row, which adds an exact zero.  Blocks whose union did not fit are
+// left to k_gradient32 with one lane per particle.
+template <int G>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void
+k_gradient32u(int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ xs,
+              const int32_t *__restrict__ urow, const int64_t *__restrict__ uoff,
+              const uint16_t *__restrict__ gloc, const int64_t *__restrict__ goff,
+              const uint16_t *__restrict__ uown, const int32_t *__restrict__ n_gath,
+              const float *__restrict__ U, float *__restrict__ UD, int32_t *__restrict__ status,
+              double box) {
+    constexpr int Q = 4, UC = union_cap32(G);
+    static_assert(kBlock == 256 && UC > 0 && UC <= kUnionSort, "64 particles per block");
+    __shared__ fvec4 ust[UC * G];              // G pieces of 16 bytes a row
+    __shared__ double upos[UC * 3];
+    __shared__ int32_t uidx[UC];
+    const int64_t blk = xcd_block(nb);
+    if (blk >= nb) return;                      // whole block
+    const int64_t u0 = uoff[blk];
+    const int32_t rows = (int32_t)(uoff[blk + 1] - u0);
+    if (rows == 0) return;                      // left to k_gradient32 (whole block)
+    for (int e = threadIdx.x; e < rows; e += kBlock) uidx[e] = urow[u0 + e];
+    __syncthreads();
+    const fvec4 *U4 = reinterpret_cast<const fvec4 *>(U);
+    const int ts = rows * G, tp = rows * 3;
+    {   // positions, then states (one set of loads in flight at a time)
+        constexpr int MP = (UC * 3 + kBlock - 1) / kBlock;
+        double x[MP];
+#pragma unroll
+        for (int r = 0; r < MP; ++r) {
+            const int e = threadIdx.x + r * kBlock;
+            if (e < tp) x[r] = xs[(uint32_t)uidx[e / 3] * 3u + (uint32_t)(e % 3)];
+        }
+#pragma unroll
+        for (int r = 0; r < MP; ++r)
+            if (threadIdx.x + r * kBlock < tp) upos[threadIdx.x + r * kBlock] = x[r];
+    }
+    {
+        constexpr int MS = (UC * G + kBlock - 1) / kBlock;
+        fvec4 v[MS];
+#pragma unroll
+        for (int r = 0; r < MS; ++r) {
+            const int e = threadIdx.x + r * kBlock;
+            if (e < ts) v[r] = U4[(uint32_t)uidx[e / G] * (uint32_t)G + (uint32_t)(e % G)];
+        }
+#pragma unroll
+        for (int r = 0; r < MS; ++r)
+            if (threadIdx.x + r * kBlock < ts) ust[threadIdx.x + r * kBlock] = v[r];
+    }
+    __syncthreads();
+    const int sub = threadIdx.x % Q;            // the component this lane sums
+    const int p = threadIdx.x / Q;              // the particle in the block
+    const int64_t i = blk * (kBlock / Q) + p;
+    const bool active = i < n;
+    const int64_t ic = active ? i : n - 1;
+    const int32_t ng = active ? n_gath[ic] : 0;
+    const int il = active ? (int)uown[ic] : 0;  // a row of the union (not used past n)
+    int32_t kmax = ng;                          // the wave's longest list
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
+    const float *rec = geo32 + (int64_t)F_REC * ic;
+    const double ibox = 1.0 / box;
+    const float iH = rec[F_IH];
+    const float *ustf = reinterpret_cast<const float *>(ust) + sub;
+    float Ui[G];                                // component sub of every group
+#pragma unroll
+    for (int t = 0; t < G; ++t) Ui[t] = ustf[(il * G + t) * 4];
+    const double px = upos[3 * il], py = upos[3 * il + 1], pz = upos[3 * il + 2];
+    float acc[G][3];
+#pragma unroll
+    for (int t = 0; t < G; ++t) acc[t][0] = acc[t][1] = acc[t][2] = 0.0f;
+    if (kmax > 0) {
+        // the four neighbours 4 it + 0..3: this lane's geometry for 4 it + sub,
+        // then every lane adds all four to its component
+        auto four_pairs = [&](int jl) __attribute__((always_inline)) {
+            const float sx = (float)min_image(upos[3 * jl] - px, box, ibox);
+            const float sy = (float)min_image(upos[3 * jl + 1] - py, box, ibox);
+            const float sz = (float)min_image(upos[3 * jl + 2] - pz, box, ibox);
+            const float w = kern_wf(sqrt32(sx * sx + sy * sy + sz * sz) * iH);
+            const float wx = w * sx, wy = w * sy, wz = w * sz;
+            auto one = [&](int jq, float qx, float qy, float qz) __attribute__((always_inline)) {
+#pragma unroll
+                for (int t = 0; t < G; ++t) {
+                    const float d = ustf[(jq * G + t) * 4] - Ui[t];
+                    acc[t][0] += d * qx;
+                    acc[t][1] += d * qy;
+                    acc[t][2] += d * qz;
+                }
+            };
+            one(quad_bcast<0>(jl), quad_bcast<0>(wx), quad_bcast<0>(wy), quad_bcast<0>(wz));
+            one(quad_bcast<1>(jl), quad_bcast<1>(wx), quad_bcast<1>(wy), quad_bcast<1>(wz));
+            one(quad_bcast<2>(jl), quad_bcast<2>(wx), quad_bcast<2>(wy), quad_bcast<2>(wz));
+            one(quad_bcast<3>(jl), quad_bcast<3>(wx), quad_bcast<3>(wy), quad_bcast<3>(wz));
+        };
+        // packed table entries, as in k_gradient64u
+        const int64_t g0 = goff[blk];
+        const int ngb = (int)((goff[blk + 1] - g0) >> 10);      // the block's groups
+        const uint64_t *gw = reinterpret_cast<const uint64_t *>(gloc + g0) + threadIdx.x;
+        auto word = [&](int gq) __attribute__((always_inline)) {
+            return gw[(int64_t)(gq < ngb ? gq : ngb - 1) * 256];
+        };
+        const int T = (kmax + Q - 1) / Q, ngq = (T + 3) / 4;    // this wave's iterations, groups
+        auto four = [&](uint64_t wd, int gq) __attribute__((always_inline)) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (4 * gq + u < T) {                            // wave-uniform
+                    const int k = Q * (4 * gq + u) + sub;
+                    four_pairs(k < ng ? (int)((wd >> (16 * u)) & 0xffff) : il);
+                }
+            }
+        };
+        uint64_t ea = word(0), eb = word(1);
+        for (int gq = 0; gq < ngq; gq += 2) {
+            const uint64_t wa = ea;
+            ea = word(gq + 2);
+            four(wa, gq);
+            if (gq + 1 >= ngq) break;
+            const uint64_t wb = eb;
+            eb = word(gq + 3);
+            four(wb, gq + 1);
+        }
+    }
+    if (!active) return;
+    // the record, as k_gradient32 forms it: lane m writes state m and the
+    // gradient of component m of every group
+    const float iV = 1.0f / rec[F_V];
+    const float b00 = rec[F_B] * iV, b01 = rec[F_B + 1] * iV, b02 = rec[F_B + 2] * iV;
+    const float b11 = rec[F_B + 3] * iV, b12 = rec[F_B + 4] * iV, b22 = rec[F_B + 5] * iV;
+    float chk = 0.0f;
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+        const float d0 = b00 * acc[t][0] + b01 * acc[t][1] + b02 * acc[t][2];
+        const float d1 = b01 * acc[t][0] + b11 * acc[t][1] + b12 * acc[t][2];
+        const float d2 = b02 * acc[t][0] + b12 * acc[t][1] + b22 * acc[t][2];
+        float *o = UD + (ic * G + t) * 16;
+        o[sub] = Ui[t];
+        o[4 + 3 * sub + 0] = d0;
+        o[4 + 3 * sub + 1] = d1;
+        o[4 + 3 * sub + 2] = d2;
+        chk = __builtin_fmaf(Ui[t], 0.0f, chk);
+        chk = __builtin_fmaf(d0, 0.0f, chk);
+        chk = __builtin_fmaf(d1, 0.0f, chk);
+        chk = __builtin_fmaf(d2, 0.0f, chk);
     }
     if (chk != chk) atomicOr(status, ST_NONFINITE);
 }
@@ -428,6 +607,23 @@ constexpr int kGQ32 = RT_GRADIENT32_Q;
 
 template <int G>
 void launch_gradient32(rt_ctx *ctx, const float *U, float *UD) {
+    if constexpr (union_cap32(G) > 0 && kGQ32 == 1) {   // the union sums in one lane's order
+        if (ctx->uoff) {
+            // blocks whose union fits: from LDS; the others: one lane per
+            // particle (the same order), by list
+            const int64_t nw = ctx->nwaves;
+            k_gradient32u<G><<<(unsigned)xcd_grid(nw), kBlock, 0, ctx->stream>>>(
+                ctx->p.n, nw, ctx->geo32, ctx->xs, ctx->urow, ctx->uoff, ctx->gloc, ctx->goff,
+                ctx->uown, ctx->n_gath, U, UD, ctx->status, ctx->p.box);
+            if (ctx->n_ublk > 0) {
+                const int64_t nl = (ctx->n_ublk + 3) / 4;
+                k_gradient32<G, 1><<<(unsigned)xcd_grid(nl), kBlock, 0, ctx->stream>>>(
+                    ctx->p.n, nl, ctx->geo32, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U,
+                    UD, ctx->status, ctx->p.box, 0, ctx->ublk, ctx->n_ublk);
+            }
+            return;
+        }
+    }
     const int64_t n = ctx->p.n, nb = (n + kBlock / kGQ32 - 1) / (kBlock / kGQ32);
     k_gradient32<G, kGQ32><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
         n, nb, ctx->geo32, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->status,

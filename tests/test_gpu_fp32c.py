@@ -76,6 +76,60 @@ def test_fp32c_gradient_close():
     assert err < 1e-5
 
 
+def test_fp32c_gradient_union_and_staged_blocks():
+    """The FP32C gradient reads a block's neighbours from their union staged in
+    LDS where it fits (576 rows at 4 groups) and stages rows per pair in the
+    other blocks: a 4-group Plummer set takes both paths."""
+    w = workloads.config(4, scale=(1 << 14) / (1 << 24))   # Plummer + background, 4 groups
+    log(f"case plummer n={w.n} G={w.groups}: fp32c gradient union and staged blocks")
+    geo = oracle.build_geometry(w.x)
+    rt = RT(w.n, w.groups, precision="fp32c")
+    perm, *_ = rt.rt_build_cells(dev(w.x), dev(geo.h))
+    p = perm.cpu().numpy()
+    st = rt.rt_get_stats()
+    log(f"fp32c blocks from the union: {st['union_blocks']}, staged: {st['union_staged_blocks']}")
+    assert st["union_blocks"] > 0 and st["union_staged_blocks"] > 0
+    assert st["union_blocks"] + st["union_staged_blocks"] == (w.n + 63) // 64
+    UD = rt.rt_gradient(dev(w.U0[p]).float())
+    rt.rt_sync()
+    got = unsort(rt.gradients_of(UD).double().cpu().numpy(), p)
+    ref = oracle.gradient(geo, w.U0)
+    scale = np.abs(ref).max(axis=(-1, -2), keepdims=True)
+    err = (np.abs(got - ref) / scale).max()
+    log(f"fp32c union gradient max rel err {err:.3e}")
+    assert err < 1e-5
+    assert np.array_equal(unsort(rt.states_of(UD).cpu().numpy(), p), w.U0.astype(np.float32))
+
+
+def test_fp32c_gradient_paths_identical_bits():
+    """The union kernel sums every component in the same order as one lane per
+    particle (the staged kernel), so a block gives identical bits on either
+    path.  Groups do not mix in the gradient, so group g of a 4-group run
+    equals a 1-group run on group g's states; a 1-group union holds 1024 rows
+    against 576 at 4 groups, so blocks between the two take the union path in
+    one run and the staged path in the other."""
+    w = workloads.config(4, scale=(1 << 14) / (1 << 24))   # Plummer + background, 4 groups
+    geo = oracle.build_geometry(w.x)
+    rt4 = RT(w.n, 4, precision="fp32c")
+    perm4, *_ = rt4.rt_build_cells(dev(w.x), dev(geo.h))
+    s4 = rt4.rt_get_stats()
+    U = dev(w.U0[perm4.cpu().numpy()]).float()
+    G4 = rt4.gradients_of(rt4.rt_gradient(U)).cpu().numpy()
+    switched = 0
+    for g in range(4):
+        rt1 = RT(w.n, 1, precision="fp32c")
+        perm1, *_ = rt1.rt_build_cells(dev(w.x), dev(geo.h))
+        assert torch.equal(perm1, perm4)
+        s1 = rt1.rt_get_stats()
+        switched = s1["union_blocks"] - s4["union_blocks"]
+        G1 = rt1.gradients_of(rt1.rt_gradient(U[:, g:g + 1].contiguous())).cpu().numpy()
+        assert np.array_equal(G1[:, 0].view(np.uint32), G4[:, g].view(np.uint32)), g
+        del rt1
+    log(f"fp32c gradient paths: 4 groups {s4['union_blocks']} union / {s4['union_staged_blocks']} "
+        f"staged; {switched} blocks on the union path only at 1 group; identical bits")
+    assert switched > 0
+
+
 def test_fp32c_lattice16_ten_steps():
     w = workloads.config(0)
     geo = oracle.build_geometry(w.x)
