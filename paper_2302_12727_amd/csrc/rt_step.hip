@@ -851,6 +851,8 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
     __shared__ double stage[kBlock / 64][64 * kStage];
     static_assert(kTile == 64 && kBlock == 256, "a block of 4 waves x 16 particles per tile");
     __shared__ double mir[kBlock / 64][kTile * MS];
+    constexpr int DS = 3 * NQ + 1;              // own-gradient row, padded
+    __shared__ double dsh[kBlock / 64][16 * DS];
     __shared__ double smem[(kBlock / 64) * 2 * G];
     __shared__ unsigned long long scnt[4];
     const int64_t blk = xcd_block(nb);
@@ -881,37 +883,50 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
             const double *rk = geo + (int64_t)kRec * ic;
-            double Ui[NQ], Di[3 * NQ];
+            double Ui[NQ];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const double *r = UD + (ic * G + g) * 16;
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    Ui[4 * g + m] = r[m];
-                    Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
-                    Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
-                    Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
-                }
+                for (int m = 0; m < 4; ++m) Ui[4 * g + m] = r[m];
             }
+            // the own gradients live in LDS (4 lanes read one address); lane
+            // sub copies component sub's
+            double *Dsh = dsh[wv] + (lane >> 2) * DS;
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    Dsh[3 * (4 * g + sub) + a] = UD[(ic * G + g) * 16 + 4 + 3 * sub + a];
+            wave_lds_sync();
             const int64_t base = wb + pl;   // the particle's column in the table
-            // the task of the next iteration is loaded one iteration ahead
-            int32_t tn = sub < nn ? task[base + 64 * (int64_t)sub] : (int32_t)ic;
+            // Lines in flight: v holds the loads of the next stage (the
+            // geometry lines, then each group's record lines) while the
+            // current stage is evaluated from the stage buffer.  The task of
+            // the next iteration is loaded one iteration ahead.
+            int32_t tc = sub < nn ? task[base + 64 * (int64_t)sub] : (int32_t)ic;
+            int32_t rw[8];
+            double2 v[8];
+            {
+                const int32_t j = tc & 0x7fffffff;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) rw[m] = __shfl(j, 8 * m + (lane >> 3), 64);
+                const RowLines<OFF32> gl(geo, rw, 1, lane);
+                gl.load(0, v);
+            }
             for (int32_t kk = 0; kk < kmax; kk += 4) {
                 const int32_t k = kk + sub;
                 const bool valid = k < nn;
-                const int32_t t = tn;
-                tn = k + 4 < nn ? task[base + 64 * (int64_t)(k + 4)] : (int32_t)ic;
+                const int32_t t = tc;
+                // (slot 0 of the tile's table exists once kmax > 0: no branch
+                // around the load, whose wait would then be a full one)
+                const int32_t tl = task[base + 64 * (int64_t)(k + 4 < nn ? k + 4 : 0)];
+                const int32_t tn = k + 4 < nn ? tl : (int32_t)ic;
                 const bool mirror = t < 0;
                 const int32_t j = t & 0x7fffffff;
-                int32_t rw[8];
-#pragma unroll
-                for (int m = 0; m < 8; ++m) rw[m] = __shfl(j, 8 * m + (lane >> 3), 64);
-                const RowLines<OFF32> gl(geo, rw, 1, lane), ul(UD, rw, G, lane);
-                {
-                    double2 v[8];
-                    gl.load(0, v);
-                    store_lines(v, sb, lane);
-                }
+                const RowLines<OFF32> ul(UD, rw, G, lane);
+                store_lines(v, sb, lane);       // the geometry lines
+                ul.load(0, v);
                 double rl[12];
 #pragma unroll
                 for (int q = 0; q < 12; ++q) rl[q] = sb[lane * kStage + q];
@@ -922,17 +937,25 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                 const int mr = mirror ? (j - (int32_t)t0) * MS : 0;   // the partner's row
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    {
-                        double2 v[8];
-                        ul.load(g, v);
-                        store_lines(v, sb, lane);
+                    // the stages in program order: each one's loads stay in
+                    // flight across the evaluation of the previous one
+                    __builtin_amdgcn_sched_barrier(0);
+                    store_lines(v, sb, lane);   // group g's record lines
+                    if (g + 1 < G) {
+                        ul.load(g + 1, v);
+                    } else {                    // the next iteration's geometry lines
+                        const int32_t jn = tn & 0x7fffffff;
+#pragma unroll
+                        for (int m = 0; m < 8; ++m) rw[m] = __shfl(jn, 8 * m + (lane >> 3), 64);
+                        const RowLines<OFF32> gn(geo, rw, 1, lane);
+                        gn.load(0, v);
                     }
                     const double *Rl = sb + lane * kStage;
                     double qL[4], qR[4];
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
                         const int q = 4 * g + m;
-                        const double dk = Di[3 * q] * pg.sx + Di[3 * q + 1] * pg.sy + Di[3 * q + 2] * pg.sz;
+                        const double dk = Dsh[3 * q] * pg.sx + Dsh[3 * q + 1] * pg.sy + Dsh[3 * q + 2] * pg.sz;
                         const double dl = Rl[4 + 3 * m] * pg.sx + Rl[5 + 3 * m] * pg.sy + Rl[6 + 3 * m] * pg.sz;
                         const double mm = minmod_med(dk, dl);
                         qL[m] = Ui[q] + pg.fk * mm;
@@ -963,6 +986,8 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                         }
                     }
                 }
+                tc = tn;
+                __builtin_amdgcn_sched_barrier(0);
             }
             // the 4 lanes' partial sums, combined by a fixed butterfly
 #pragma unroll
