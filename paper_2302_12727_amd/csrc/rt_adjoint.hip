@@ -276,13 +276,10 @@ void k_adj_pair64(
     if (Q > 1) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-#pragma unroll
-            for (int o = 1; o < Q; o <<= 1) {
-                aU[q] += __shfl_xor(aU[q], o, 64);
-                aD[3 * q] += __shfl_xor(aD[3 * q], o, 64);
-                aD[3 * q + 1] += __shfl_xor(aD[3 * q + 1], o, 64);
-                aD[3 * q + 2] += __shfl_xor(aD[3 * q + 2], o, 64);
-            }
+            quad_sum<Q>(aU[q]);
+            quad_sum<Q>(aD[3 * q]);
+            quad_sum<Q>(aD[3 * q + 1]);
+            quad_sum<Q>(aD[3 * q + 2]);
         }
     }
     if (!owner) return;
@@ -404,13 +401,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad64(
     }
     if (Q > 1) {
 #pragma unroll
-        for (int o = 1; o < Q; o <<= 1) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) acc[q] += __shfl_xor(acc[q], o, 64);
-            sgx += __shfl_xor(sgx, o, 64);
-            sgy += __shfl_xor(sgy, o, 64);
-            sgz += __shfl_xor(sgz, o, 64);
-        }
+        for (int q = 0; q < NQ; ++q) quad_sum<Q>(acc[q]);
+        quad_sum<Q>(sgx);
+        quad_sum<Q>(sgy);
+        quad_sum<Q>(sgz);
     }
     if (!owner) return;
 #pragma unroll

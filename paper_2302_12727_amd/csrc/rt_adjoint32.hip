@@ -329,13 +329,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad32(
     for (int q = 0; q < NQ; ++q) av[q] = acc[q].value();
     if (Q > 1) {
 #pragma unroll
-        for (int o = 1; o < Q; o <<= 1) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) av[q] += __shfl_xor(av[q], o, 64);
-            sgx += __shfl_xor(sgx, o, 64);
-            sgy += __shfl_xor(sgy, o, 64);
-            sgz += __shfl_xor(sgz, o, 64);
-        }
+        for (int q = 0; q < NQ; ++q) quad_sum<Q>(av[q]);
+        quad_sum<Q>(sgx);
+        quad_sum<Q>(sgy);
+        quad_sum<Q>(sgz);
     }
     if (!owner) return;
 #pragma unroll

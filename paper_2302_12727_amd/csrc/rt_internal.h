@@ -161,6 +161,34 @@ namespace gearrt {
 
 // Dimensionless cubic B-spline w(q), q = r/H, written branch-free:
 // (1-q)^3 - 4 (1/2-q)^3 for q <= 1/2, (1-q)^3 for 1/2 < q < 1, 0 beyond.
+// Exchange within a quad of lanes by DPP (a VALU move, no LDS round trip):
+// quad_xor<O> returns the value of the lane whose index differs in bit O
+// (1 or 2); quad_sum<Q> adds the Q lanes' values (Q = 1, 2 or 4) in the
+// order xor 1, then xor 2, leaving the same bits on every lane.  Every lane of
+// the quad must be active.
+template <int O>
+__device__ __forceinline__ int quad_xor_i(int v) {
+    static_assert(O == 1 || O == 2, "a quad's bit 0 or 1");
+    return __builtin_amdgcn_mov_dpp(v, O == 1 ? 0xB1 : 0x4E, 0xf, 0xf, false);
+}
+template <int O>
+__device__ __forceinline__ float quad_xor(float v) {
+    return __builtin_bit_cast(float, quad_xor_i<O>(__builtin_bit_cast(int, v)));
+}
+template <int O>
+__device__ __forceinline__ double quad_xor(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)quad_xor_i<O>((int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)quad_xor_i<O>((int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <int Q, class T>
+__device__ __forceinline__ void quad_sum(T &v) {
+    static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
+    if constexpr (Q >= 2) v += quad_xor<1>(v);
+    if constexpr (Q >= 4) v += quad_xor<2>(v);
+}
+
 __device__ __forceinline__ double kern_w(double q) {
     double a = fmax(1.0 - q, 0.0);
     double b = fmax(0.5 - q, 0.0);

@@ -307,8 +307,7 @@ __global__ __launch_bounds__(grad_block(G)) __attribute__((amdgpu_waves_per_eu(
         for (int q = 0; q < NQ; ++q)
 #pragma unroll
             for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int o = 1; o < Q; o <<= 1) acc[q][a] += __shfl_xor(acc[q][a], o, 64);
+                quad_sum<Q>(acc[q][a]);
     }
     if (!active) return;
     // the own state, as loaded, from the wave's own row
@@ -463,8 +462,7 @@ k_gradient64u(int64_t n, int64_t nb, const double *__restrict__ geo, const doubl
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int o = 1; o < Q; o <<= 1) acc[q][a] += __shfl_xor(acc[q][a], o, 64);
+            quad_sum<Q>(acc[q][a]);
     if (!active) return;
     gradient_record<G, Q>(acc, Ui, rec, UD + ic * (16 * G), sub, status);
 }
@@ -725,12 +723,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
         }
     }
     // sum of the Q partial sums of each particle (a fixed butterfly: the same
-    // bits on every lane of the particle)
+    // bits on every lane of the particle; by LDS permutes in the time-bin
+    // instantiations, where the DPP form left more registers spilled)
     if (Q > 1) {
 #pragma unroll
-        for (int q = 0; q < 4 * GW; ++q)
+        for (int q = 0; q < 4 * GW; ++q) {
+            if constexpr (BIN) {
 #pragma unroll
-            for (int o = 1; o < Q; o <<= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+                for (int o = 1; o < Q; o <<= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+            } else {
+                quad_sum<Q>(acc[q]);
+            }
+        }
     }
     // update, post-update guard, ledger, photon budget
     double red[2 * GW];
@@ -992,8 +996,7 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
             // the 4 lanes' partial sums, combined by a fixed butterfly
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
-#pragma unroll
-                for (int o = 1; o < 4; o <<= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+                quad_sum<4>(acc[q]);
         }
     }
     // every wave's deposits are in its copy of the accumulator

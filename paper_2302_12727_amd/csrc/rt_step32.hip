@@ -72,8 +72,7 @@ __global__ __launch_bounds__(kBlock) void k_gradient32(
         for (int q = 0; q < NQ; ++q)
 #pragma unroll
             for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int o = 1; o < Q; o <<= 1) acc[q][a] += __shfl_xor(acc[q][a], o, 64);
+                quad_sum<Q>(acc[q][a]);
         if (sub != 0) return;
     }
     const float b00 = rec[F_B] * iV, b01 = rec[F_B + 1] * iV, b02 = rec[F_B + 2] * iV;
@@ -477,8 +476,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
     if (Q > 1) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-#pragma unroll
-            for (int o = 1; o < Q; o <<= 1) av[q] += __shfl_xor(av[q], o, 64);
+            quad_sum<Q>(av[q]);
     }
     double red[2 * G];
     int gE = 0, gF = 0;
