@@ -171,7 +171,10 @@ void k_adj_pair64(
             const int32_t k = kk + sub;
             const bool valid = k < nn;
             const int32_t j = jn;
-            jn = k + Q < nn ? nbr[base + 64 * (int64_t)(k + Q)] : (int32_t)ic;
+            // (slot 0 of the wave's table exists once kmax > 0: no branch
+            // around the load, whose wait would then be a full one)
+            const int32_t jl = nbr[base + 64 * (int64_t)(k + Q < nn ? k + Q : 0)];
+            jn = k + Q < nn ? jl : (int32_t)ic;
             int64_t row[8];
 #pragma unroll
             for (int m = 0; m < 8; ++m) row[m] = __shfl(j, 8 * m + (lane >> 3), 64);
@@ -192,14 +195,18 @@ void k_adj_pair64(
             const double dtVl = dt / rl[R_V];
 #pragma unroll
             for (int g = 0; g < GW; ++g) {
+                // the record lines and the cotangent rows in one round trip
                 int64_t rowg[8];
 #pragma unroll
                 for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g0 + g;
-                stage_lines(UD, rowg, sb, lane);
+                double2 v[8], vl[2];
+                load_lines(UD, rowg, lane, v);
+                load_rows4(lam2 + 4 * (g0 + g), 4 * G, j, lane, vl);
+                store_lines(v, sb, lane);
                 double Rl[16];
 #pragma unroll
                 for (int q = 0; q < 16; ++q) Rl[q] = sb[lane * kStage + q];
-                stage_rows4(lam2 + 4 * (g0 + g), 4 * G, j, sb, lane);
+                store_rows4(vl, sb, lane);
                 double Ll[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) Ll[m] = sb[lane * kStage + m];
