@@ -378,6 +378,10 @@ typedef struct {
                                union staged in LDS                              */
     int64_t union_staged_blocks; /* those whose union did not fit (the gradient
                                stages their rows per pair instead)              */
+    int64_t adj_union_blocks;  /* FP64, up to 4 groups: blocks of 64 particles
+                               whose adjoint transposed gradient reads the
+                               union of their symmetric lists from LDS          */
+    int64_t adj_union_staged_blocks; /* those whose union did not fit           */
 } rt_stats;
 rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out /* [host] */);
 

@@ -312,16 +312,19 @@ void k_adj_pair64(
 // loads of one neighbour slot (position and 1/H, and the G records of rho)
 // are issued before the first is staged, so their latencies overlap.
 // Q lanes share a particle as in the pair pass.
+// blist: only the listed blocks (of kBlock / Q particles).
 template <int G, int Q = 1>
 __global__ __launch_bounds__(kBlock) void k_adj_grad64(
     int64_t n, int64_t nb, const double *__restrict__ geo, const int32_t *__restrict__ nbr,
     const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_nbr,
-    const double *__restrict__ R, double *__restrict__ lam, double box) {
+    const double *__restrict__ R, double *__restrict__ lam, double box,
+    const int32_t *__restrict__ blist = nullptr) {
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     constexpr int NQ = 4 * G, PW = 64 / Q, PB = kBlock / Q;
     __shared__ double stage[kBlock / 64][64 * kStage];
-    const int64_t blk = xcd_block(nb);
-    if (blk >= nb) return;
+    const int64_t bx = xcd_block(nb);
+    if (bx >= nb) return;
+    const int64_t blk = blist ? (int64_t)blist[bx] : bx;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int sub = lane % Q;
     const int64_t i0 = blk * PB + wv * PW;      // first particle of the wave
@@ -425,6 +428,153 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad64(
     }
 }
 
+// Pass C from the block's neighbour union (FP64, the symmetric lists): the
+// union's positions and 1/H are staged in LDS once per block of 64 particles,
+// then for each group in turn its rows of rho (the gradient cotangents of the
+// records R), and every pair reads its neighbour's row from LDS by its 16-bit
+// position in the union.  A lane sums the same slots in the same order with
+// the same operations as k_adj_grad64 with four lanes (rows past a list are
+// the own row with zero weights), so the two give identical bits; blocks whose
+// union did not fit are left to it, by list.
+typedef double dvec2a __attribute__((ext_vector_type(2)));
+template <int G, int W>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(W, W))) void
+k_adj_grad64u(int64_t n, int64_t nb, const double *__restrict__ geo,
+              const int32_t *__restrict__ urow, const int64_t *__restrict__ uoff,
+              const uint16_t *__restrict__ gloc, const int64_t *__restrict__ goff,
+              const uint16_t *__restrict__ uown, const int32_t *__restrict__ n_nbr,
+              const double *__restrict__ R, double *__restrict__ lam, double box) {
+    constexpr int Q = 4, UC = adj_union_cap(W);
+    static_assert(kBlock == 256 && UC <= 1024, "64 particles per block");
+    __shared__ dvec2a upos[UC * 2];             // x, y | z, 1/H: the record's first line piece
+    __shared__ dvec2a urho[UC * 6];             // one group's 12 gradient cotangents
+    __shared__ int32_t uidx[UC];
+    const int64_t blk = xcd_block(nb);
+    if (blk >= nb) return;                      // whole block
+    const int64_t u0 = uoff[blk];
+    const int32_t rows = (int32_t)(uoff[blk + 1] - u0);
+    if (rows == 0) return;                      // left to k_adj_grad64 (whole block)
+    for (int e = threadIdx.x; e < rows; e += kBlock) uidx[e] = urow[u0 + e];
+    __syncthreads();
+    {   // positions and 1/H, all loads in flight
+        constexpr int MP = (UC * 2 + kBlock - 1) / kBlock;
+        const dvec2a *G2 = reinterpret_cast<const dvec2a *>(geo);
+        dvec2a v[MP];
+#pragma unroll
+        for (int r = 0; r < MP; ++r) {
+            const int e = threadIdx.x + r * kBlock;
+            if (e < 2 * rows) v[r] = G2[(uint32_t)uidx[e >> 1] * (uint32_t)(kRec / 2) + (uint32_t)(e & 1)];
+        }
+#pragma unroll
+        for (int r = 0; r < MP; ++r)
+            if (threadIdx.x + r * kBlock < 2 * rows) upos[threadIdx.x + r * kBlock] = v[r];
+    }
+    const int lane = threadIdx.x & 63, sub = lane % Q;
+    const int p = threadIdx.x / Q;              // the particle in the block
+    const int64_t i = blk * (kBlock / Q) + p;
+    const bool active = i < n;
+    const bool owner = active && sub == 0;
+    const int64_t ic = active ? i : n - 1;
+    const int32_t nn = active ? n_nbr[ic] : 0;
+    const int il = active ? (int)uown[ic] : 0;  // a row of the union (not used past n)
+    int32_t kmax = nn;                          // the wave's longest list
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
+    const double *rp = geo + (int64_t)kRec * ic;
+    const double px = rp[0], py = rp[1], pz = rp[2], iHp = rp[R_IH];
+    const double ibox = 1.0 / box;
+    const int64_t g0 = goff[blk];
+    const int ngb = (int)((goff[blk + 1] - g0) >> 10);          // the block's entry groups
+    const uint64_t *gw = reinterpret_cast<const uint64_t *>(gloc + g0) + threadIdx.x;
+    const int T = (kmax + Q - 1) / Q, ngq = (T + 3) / 4;        // this wave's iterations, groups
+    double sgx = 0.0, sgy = 0.0, sgz = 0.0;
+    const dvec2a *R2 = reinterpret_cast<const dvec2a *>(R);
+#pragma unroll 1
+    for (int g = 0; g < G; ++g) {
+        __syncthreads();                        // the previous group's rows are read
+        {   // group g's rows of rho, all loads in flight
+            constexpr int MS = (UC * 6 + kBlock - 1) / kBlock;
+            dvec2a v[MS];
+#pragma unroll
+            for (int r = 0; r < MS; ++r) {
+                const int e = threadIdx.x + r * kBlock;
+                if (e < 6 * rows)
+                    v[r] = R2[((uint32_t)uidx[e / 6] * (uint32_t)G + (uint32_t)g) * 8u + 2u +
+                              (uint32_t)(e % 6)];
+            }
+#pragma unroll
+            for (int r = 0; r < MS; ++r)
+                if (threadIdx.x + r * kBlock < 6 * rows) urho[threadIdx.x + r * kBlock] = v[r];
+        }
+        __syncthreads();
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (kmax > 0) {
+            auto pair = [&](int jl, bool valid) __attribute__((always_inline)) {
+                const dvec2a a = upos[2 * jl], b = upos[2 * jl + 1];
+                const double sx = min_image(a.x - px, box, ibox);
+                const double sy = min_image(a.y - py, box, ibox);
+                const double sz = min_image(b.x - pz, box, ibox);
+                const double iHl = b.y;
+                const double r = sqrt64(sx * sx + sy * sy + sz * sz);
+                if (g == 0) {
+                    const double wpi = valid ? kern_w(r * iHp) : 0.0;
+                    sgx += wpi * sx;
+                    sgy += wpi * sy;
+                    sgz += wpi * sz;
+                }
+                const double wip = valid ? kern_w(r * iHl) : 0.0;
+                const dvec2a *Rl = urho + 6 * jl;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    // doubles 3m .. 3m+2 of the row: pieces (3m)/2 ..
+                    const double d0 = Rl[(3 * m) >> 1][(3 * m) & 1];
+                    const double d1 = Rl[(3 * m + 1) >> 1][(3 * m + 1) & 1];
+                    const double d2 = Rl[(3 * m + 2) >> 1][(3 * m + 2) & 1];
+                    acc[m] -= wip * (d0 * sx + d1 * sy + d2 * sz);
+                }
+            };
+            auto word = [&](int gq) __attribute__((always_inline)) {
+                return gw[(int64_t)(gq < ngb ? gq : ngb - 1) * 256];
+            };
+            auto four = [&](uint64_t wd, int gq) __attribute__((always_inline)) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (4 * gq + u < T) {                        // wave-uniform
+                        const int k = Q * (4 * gq + u) + sub;
+                        const bool valid = k < nn;
+                        pair(valid ? (int)((wd >> (16 * u)) & 0xffff) : il, valid);
+                    }
+                }
+            };
+            uint64_t ea = word(0), eb = word(1);
+            for (int gq = 0; gq < ngq; gq += 2) {
+                const uint64_t wa = ea;
+                ea = word(gq + 2);
+                four(wa, gq);
+                if (gq + 1 >= ngq) break;
+                const uint64_t wb = eb;
+                eb = word(gq + 3);
+                four(wb, gq + 1);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) quad_sum<Q>(acc[m]);
+        if (g == 0) {
+            quad_sum<Q>(sgx);
+            quad_sum<Q>(sgy);
+            quad_sum<Q>(sgz);
+        }
+        if (owner) {
+            const double *Rp = R + (i * G + g) * 16;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                lam[(i * G + g) * 4 + m] =
+                    Rp[m] - (sgx * Rp[4 + 3 * m] + sgy * Rp[5 + 3 * m] + sgz * Rp[6 + 3 * m]) +
+                    acc[m];
+        }
+    }
+}
+
 // Pass D: dLoss/dL_s += dt sum_{g in s} coef_sg lam_E,g, one block per source.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_adj_inject(int32_t S, int G,
@@ -492,6 +642,25 @@ void launch_adjoint64(rt_ctx *ctx, const double *UD, const double *Uung, const d
         else RT_ADJ_PAIR_LAUNCH(false, false);
     }
 #undef RT_ADJ_PAIR_LAUNCH
+    if constexpr (G <= 4 && kAGQ == 4) {
+        if (ctx->aoff) {
+            // blocks whose union fits: from LDS; the others: by list
+            const int64_t nw = ctx->nwaves;
+            if (ctx->adj_union_waves == 3)
+                k_adj_grad64u<G, 3><<<(unsigned)xcd_grid(nw), kBlock, 0, st>>>(
+                    n, nw, ctx->geo, ctx->arow, ctx->aoff, ctx->agloc, ctx->goff, ctx->aown,
+                    ctx->n_nbr, R, lam, ctx->p.box);
+            else
+                k_adj_grad64u<G, 2><<<(unsigned)xcd_grid(nw), kBlock, 0, st>>>(
+                    n, nw, ctx->geo, ctx->arow, ctx->aoff, ctx->agloc, ctx->goff, ctx->aown,
+                    ctx->n_nbr, R, lam, ctx->p.box);
+            if (ctx->n_ablk > 0)
+                k_adj_grad64<G, 4><<<(unsigned)xcd_grid(ctx->n_ablk), kBlock, 0, st>>>(
+                    n, ctx->n_ablk, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, R, lam,
+                    ctx->p.box, ctx->ablk);
+            return;
+        }
+    }
     const int64_t ng = (n + kBlock / kAGQ - 1) / (kBlock / kAGQ);
     k_adj_grad64<G, kAGQ><<<(unsigned)xcd_grid(ng), kBlock, 0, st>>>(
         n, ng, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, R, lam, ctx->p.box);

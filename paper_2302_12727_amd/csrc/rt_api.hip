@@ -128,7 +128,8 @@ void rt_destroy(rt_ctx *ctx) {
                     ctx->src_gas, ctx->src_coef, ctx->status, ctx->partials, ctx->scan_tmp,
                     ctx->adj_buf, ctx->hll_table, ctx->hll_table32, ctx->vol, ctx->ivan,
                     ctx->bin8, ctx->task, ctx->n_task, ctx->uoff, ctx->urow, ctx->gloc,
-                    ctx->uown, ctx->ublk, ctx->goff};
+                    ctx->uown, ctx->ublk, ctx->goff, ctx->aoff, ctx->arow, ctx->agloc,
+                    ctx->aown, ctx->ablk};
     for (void *b : bufs) rt_free(ctx, b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -366,6 +367,8 @@ rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out) {
     out->h_list_overflow = ctx->h_list_overflow;
     out->union_blocks = ctx->uoff ? ctx->nwaves - ctx->n_ublk : 0;
     out->union_staged_blocks = ctx->uoff ? ctx->n_ublk : 0;
+    out->adj_union_blocks = ctx->aoff ? ctx->nwaves - ctx->n_ablk : 0;
+    out->adj_union_staged_blocks = ctx->aoff ? ctx->n_ablk : 0;
     return RT_OK;
 }
 

@@ -669,13 +669,14 @@ __global__ __launch_bounds__(64) void k_tasks(int64_t n, const int64_t *__restri
     n_task[i] = c;
 }
 
-// Neighbour unions of the FP64 gradient (k_gradient64u): for every block of
-// 64 particles (a column block of the neighbour table) the sorted distinct
-// indices of its particles and of their gather neighbours, which the
-// gradient stages in LDS once instead of fetching a neighbour's row for every
-// pair (each row is used 6-8 times by a block).  Each gather slot gets the
-// 16-bit position of its neighbour in the union (gloc), each particle its own
-// (uown).  The distinct indices are collected in an LDS hash table (open
+// Neighbour unions of the gradient (k_gradient64u, k_gradient32u; over the
+// gather lists) and of the adjoint's transposed gradient (k_adj_grad64u; over
+// the symmetric lists): for every block of 64 particles (a column block of the
+// neighbour table) the sorted distinct indices of its particles and of the
+// first len[i] neighbours of each, which the kernel stages in LDS once instead
+// of fetching a neighbour's row for every pair (each row is used 6-8 times by
+// a block).  Each of those slots gets the 16-bit position of its neighbour in
+// the union (gloc), each particle its own (uown).  The distinct indices are collected in an LDS hash table (open
 // addressing with bounded probing) and sorted (bitonic, kUnionSort keys).
 // Count pass (FILL false): rows[b] = the union's size, or 0 if it does not
 // fit `cap` (the block is left to the staged gradient); the fill pass writes
@@ -686,7 +687,7 @@ constexpr int kUnionHash = 4096;
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_union(int64_t n, int cap,
                                                const int64_t *__restrict__ wave_base,
-                                               const int32_t *__restrict__ n_gath,
+                                               const int32_t *__restrict__ len,
                                                const int32_t *__restrict__ nbr,
                                                int64_t *__restrict__ rows,
                                                const int64_t *__restrict__ uoff,
@@ -708,7 +709,7 @@ __global__ __launch_bounds__(256) void k_union(int64_t n, int cap,
     const int64_t i = t0 + p;
     const bool active = i < n;
     const int64_t base = wave_base[b] + p;
-    const int32_t ng = active ? n_gath[i] : 0;
+    const int32_t ng = active ? len[i] : 0;
     auto insert = [&](int32_t j) {
         uint32_t h = ((uint32_t)j * 2654435761u) >> 20;     // 12 bits
         for (int probe = 0; probe < kUnionHash; ++probe) {
@@ -786,6 +787,67 @@ static void build_tree(rt_ctx *ctx, const double *H) {
                                                                ctx->node_hi, ctx->node_hmax);
 }
 
+// One set of neighbour unions (k_union) over the first len[i] entries of each
+// particle's table column: sizes at capacity cap (w0 waves per SIMD), or at
+// cap3 (3 waves) when cap3 > 0 and at least 95% of the blocks fit it.  Blocks
+// over the capacity get no rows and are listed in *left.  The packed entries
+// (nloc of them) go to the offsets ctx->goff, already on the device.
+static rt_status build_union(rt_ctx *ctx, const int32_t *len, int cap, int w0, int cap3,
+                             int64_t nloc, int64_t **off, int32_t **row, uint16_t **loc,
+                             uint16_t **own, int32_t **left, int64_t *n_left, int *waves) {
+    const int64_t n = ctx->p.n, nw = ctx->nwaves;
+    hipStream_t st = ctx->stream;
+    std::vector<int64_t> rows(nw + 1);
+    int64_t *width = nullptr;
+    rt_status rs = rt_alloc(ctx, (void **)&width, sizeof(int64_t) * (nw + 1));
+    if (rs != RT_OK) return rs;
+    k_union<false><<<(unsigned)nw, 256, 0, st>>>(n, cap, ctx->wave_base, len, ctx->nbr, width,
+                                                 nullptr, nullptr, nullptr, nullptr, nullptr);
+    hipError_t e = hipMemcpyAsync(rows.data(), width, sizeof(int64_t) * nw,
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    rt_free(ctx, width);
+    if (e != hipSuccess) return rt_fail(ctx, RT_EHIP, hipGetErrorString(e));
+    *waves = w0;
+    if (cap3 > 0) {
+        int64_t fit = 0;
+        for (int64_t b = 0; b < nw; ++b) fit += rows[b] > 0 && rows[b] <= cap3;
+        if (fit >= nw - nw / 20) {
+            *waves = 3;
+            cap = cap3;
+            for (int64_t b = 0; b < nw; ++b)
+                if (rows[b] > cap3) rows[b] = 0;
+        }
+    }
+    // offsets (exclusive sums), and the blocks left out
+    std::vector<int32_t> over;
+    int64_t acc = 0;
+    for (int64_t b = 0; b < nw; ++b) {
+        const int64_t r = rows[b];
+        rows[b] = acc;
+        acc += r;
+        if (r == 0) over.push_back((int32_t)b);
+    }
+    rows[nw] = acc;
+    if ((rs = rt_alloc(ctx, (void **)off, sizeof(int64_t) * (nw + 1))) != RT_OK) return rs;
+    RT_HIP(hipMemcpyAsync(*off, rows.data(), sizeof(int64_t) * (nw + 1), hipMemcpyHostToDevice, st));
+    if ((rs = rt_alloc(ctx, (void **)row, sizeof(int32_t) * std::max<int64_t>(acc, 1))) != RT_OK)
+        return rs;
+    if ((rs = rt_alloc(ctx, (void **)loc, sizeof(uint16_t) * std::max<int64_t>(nloc, 4))) != RT_OK)
+        return rs;
+    if ((rs = rt_alloc(ctx, (void **)own, sizeof(uint16_t) * n)) != RT_OK) return rs;
+    k_union<true><<<(unsigned)nw, 256, 0, st>>>(n, cap, ctx->wave_base, len, ctx->nbr, nullptr,
+                                                *off, *row, ctx->goff, *loc, *own);
+    *n_left = (int64_t)over.size();
+    if (!over.empty()) {
+        if ((rs = rt_alloc(ctx, (void **)left, sizeof(int32_t) * over.size())) != RT_OK) return rs;
+        RT_HIP(hipMemcpyAsync(*left, over.data(), sizeof(int32_t) * over.size(),
+                              hipMemcpyHostToDevice, st));
+    }
+    RT_HIP(hipStreamSynchronize(st));
+    return RT_OK;
+}
+
 rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_t *perm,
                         double *h, double *V, double *dt) {
     const int64_t n = ctx->p.n;
@@ -799,9 +861,13 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     rt_free(ctx, ctx->task); rt_free(ctx, ctx->n_task);
     rt_free(ctx, ctx->uoff); rt_free(ctx, ctx->urow); rt_free(ctx, ctx->gloc);
     rt_free(ctx, ctx->uown); rt_free(ctx, ctx->ublk); rt_free(ctx, ctx->goff);
+    rt_free(ctx, ctx->aoff); rt_free(ctx, ctx->arow); rt_free(ctx, ctx->agloc);
+    rt_free(ctx, ctx->aown); rt_free(ctx, ctx->ablk);
     ctx->uoff = nullptr; ctx->urow = nullptr; ctx->gloc = nullptr; ctx->uown = nullptr;
     ctx->goff = nullptr;
     ctx->ublk = nullptr; ctx->n_ublk = 0;
+    ctx->aoff = nullptr; ctx->arow = nullptr; ctx->agloc = nullptr; ctx->aown = nullptr;
+    ctx->ablk = nullptr; ctx->n_ablk = 0;
     ctx->vol = nullptr;
     ctx->ivan = nullptr;
     ctx->task = nullptr;
@@ -825,7 +891,6 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     int64_t *width = nullptr;
     void *sort_tmp = nullptr;
     size_t sort_bytes = 0;
-    int64_t *width_u = nullptr;   // union sizes of the gradient's blocks
 
 #define ALLOC(p, bytes)                                              \
     do {                                                             \
@@ -957,47 +1022,16 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
                                                           ctx->task, ctx->n_task);
         }
         {
-            // neighbour unions of the gradient: FP64 sizes at the 2-wave
-            // capacity, then 3 waves per SIMD if nearly every block fits that
-            // capacity; FP32C at its 3-wave capacity
+            // neighbour unions of the gradient (gather lists): FP64 at the
+            // 2-wave capacity, then 3 waves per SIMD if nearly every block
+            // fits that capacity; FP32C at its 3-wave capacity.  FP64 also
+            // builds those of the adjoint's transposed gradient (the
+            // symmetric lists), which stages one group at a time.
             const bool f64 = ctx->p.precision == RT_FP64;
-            int cap = f64 ? union_cap(ctx->p.groups) : union_cap32(ctx->p.groups);
+            const int G = ctx->p.groups;
+            const int cap = f64 ? union_cap(G) : union_cap32(G);
             if (cap > 0) {
                 const int64_t nw = ctx->nwaves;
-                std::vector<int64_t> rows(nw + 1);
-                ALLOC(width_u, sizeof(int64_t) * (nw + 1));
-                k_union<false><<<(unsigned)nw, 256, 0, st>>>(n, cap, ctx->wave_base, ctx->n_gath,
-                                                             ctx->nbr, width_u, nullptr, nullptr,
-                                                             nullptr, nullptr, nullptr);
-                RT_HIP(hipMemcpyAsync(rows.data(), width_u, sizeof(int64_t) * nw,
-                                      hipMemcpyDeviceToHost, st));
-                RT_HIP(hipStreamSynchronize(st));
-                const int cap3 = f64 ? union_cap3(ctx->p.groups) : 0;
-                ctx->union_waves = f64 ? 2 : 3;
-                if (cap3 > 0) {
-                    int64_t fit = 0;
-                    for (int64_t b = 0; b < nw; ++b) fit += rows[b] > 0 && rows[b] <= cap3;
-                    if (fit >= nw - nw / 20) {
-                        ctx->union_waves = 3;
-                        cap = cap3;
-                        for (int64_t b = 0; b < nw; ++b)
-                            if (rows[b] > cap3) rows[b] = 0;
-                    }
-                }
-                // offsets (exclusive sums), and the blocks left to the staged gradient
-                std::vector<int32_t> over;
-                int64_t acc = 0;
-                for (int64_t b = 0; b < nw; ++b) {
-                    const int64_t r = rows[b];
-                    rows[b] = acc;
-                    acc += r;
-                    if (r == 0) over.push_back((int32_t)b);
-                }
-                rows[nw] = acc;
-                ALLOC(ctx->uoff, sizeof(int64_t) * (nw + 1));
-                RT_HIP(hipMemcpyAsync(ctx->uoff, rows.data(), sizeof(int64_t) * (nw + 1),
-                                      hipMemcpyHostToDevice, st));
-                ALLOC(ctx->urow, sizeof(int32_t) * std::max<int64_t>(acc, 1));
                 // packed table entries: 1024 per group of 16 table rows of a block
                 std::vector<int64_t> wb(nw + 1), go(nw + 1);
                 RT_HIP(hipMemcpyAsync(wb.data(), ctx->wave_base, sizeof(int64_t) * (nw + 1),
@@ -1009,20 +1043,16 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
                 ALLOC(ctx->goff, sizeof(int64_t) * (nw + 1));
                 RT_HIP(hipMemcpyAsync(ctx->goff, go.data(), sizeof(int64_t) * (nw + 1),
                                       hipMemcpyHostToDevice, st));
-                ALLOC(ctx->gloc, sizeof(uint16_t) * std::max<int64_t>(go[nw], 4));
-                ALLOC(ctx->uown, sizeof(uint16_t) * n);
-                k_union<true><<<(unsigned)nw, 256, 0, st>>>(n, cap, ctx->wave_base, ctx->n_gath,
-                                                            ctx->nbr, nullptr, ctx->uoff, ctx->urow,
-                                                            ctx->goff, ctx->gloc, ctx->uown);
-                ctx->n_ublk = (int64_t)over.size();
-                if (!over.empty()) {
-                    ALLOC(ctx->ublk, sizeof(int32_t) * over.size());
-                    RT_HIP(hipMemcpyAsync(ctx->ublk, over.data(), sizeof(int32_t) * over.size(),
-                                          hipMemcpyHostToDevice, st));
+                rs = build_union(ctx, ctx->n_gath, cap, f64 ? 2 : 3, f64 ? union_cap3(G) : 0,
+                                 go[nw], &ctx->uoff, &ctx->urow, &ctx->gloc, &ctx->uown,
+                                 &ctx->ublk, &ctx->n_ublk, &ctx->union_waves);
+                if (rs != RT_OK) goto fail;
+                if (f64) {
+                    rs = build_union(ctx, ctx->n_nbr, adj_union_cap(2), 2, adj_union_cap(3), go[nw],
+                                     &ctx->aoff, &ctx->arow, &ctx->agloc, &ctx->aown, &ctx->ablk,
+                                     &ctx->n_ablk, &ctx->adj_union_waves);
+                    if (rs != RT_OK) goto fail;
                 }
-                RT_HIP(hipStreamSynchronize(st));
-                rt_free(ctx, width_u);
-                width_u = nullptr;
             }
         }
         // geometry records, volumes, time step
@@ -1075,7 +1105,7 @@ fail:
     (void)hipMemsetAsync(ctx->status, 0, sizeof(int32_t), st);
     (void)hipStreamSynchronize(st);
     rt_free(ctx, keys_in); rt_free(ctx, idx_in); rt_free(ctx, Htmp); rt_free(ctx, width); rt_free(ctx, dxpart);
-    rt_free(ctx, sort_tmp); rt_free(ctx, nlist); rt_free(ctx, width_u);
+    rt_free(ctx, sort_tmp); rt_free(ctx, nlist);
     return rs;
 #undef ALLOC
 }

@@ -34,6 +34,10 @@ constexpr int union_cap3(int G) { return G == 3 ? 420 : 0; }
 // The compensated-FP32 gradient's union: FP32 states (16G bytes a row), FP64
 // positions, three blocks per CU (at most 53 KB each).
 constexpr int union_cap32(int G) { return G == 1 ? 1024 : G == 2 ? 880 : G == 3 ? 672 : G == 4 ? 576 : 0; }
+// Rows of a block's union in the adjoint's transposed gradient, which stages
+// one group at a time: position, 1/H and the 12 gradient cotangents (128
+// bytes) plus the row index, 132 bytes a row.  2 or 3 blocks of 4 waves per CU.
+constexpr int adj_union_cap(int waves) { return waves == 3 ? 400 : 600; }
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kSigma3 = 16.0 / kPi;   // cubic spline normalisation in 3D
 
@@ -108,6 +112,15 @@ struct rt_ctx {
     int32_t *ublk = nullptr;     // [n_ublk] blocks left to the staged gradient
     int64_t n_ublk = 0;
     int union_waves = 2;         // waves per SIMD of the union gradient (capacity by it)
+    // the same over the symmetric lists, for the FP64 adjoint's transposed
+    // gradient (entries packed as gloc, at the same goff)
+    int64_t *aoff = nullptr;
+    int32_t *arow = nullptr;
+    uint16_t *agloc = nullptr;
+    uint16_t *aown = nullptr;
+    int32_t *ablk = nullptr;
+    int64_t n_ablk = 0;
+    int adj_union_waves = 2;
 
     // sources
     int32_t S = 0;

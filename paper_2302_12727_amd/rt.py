@@ -57,7 +57,8 @@ class rt_stats(ctypes.Structure):
                 ("max_neighbours", ctypes.c_int32), ("h_iter_max", ctypes.c_int32),
                 ("n_inject", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("device_bytes_peak", ctypes.c_int64), ("h_list_overflow", ctypes.c_int64),
-                ("union_blocks", ctypes.c_int64), ("union_staged_blocks", ctypes.c_int64)]
+                ("union_blocks", ctypes.c_int64), ("union_staged_blocks", ctypes.c_int64),
+                ("adj_union_blocks", ctypes.c_int64), ("adj_union_staged_blocks", ctypes.c_int64)]
 
 
 _lib = None

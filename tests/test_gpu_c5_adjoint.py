@@ -111,7 +111,12 @@ def test_c5_short_rollout_fp64_adjoint_against_torch_reference(c5small):
     gU_ref, gL_ref = torch.autograd.grad(loss, (U0, L))
     lg, gU, gL = gpu_gradients(rt, p, w, steps, ckpt, Et)
     e1, e2 = rel(gU, gU_ref.numpy()), rel(gL, gL_ref.numpy())
+    st = rt.rt_get_stats()
     log(f"C5 set, {steps}-step rollout: loss {lg:.6e} (reference {float(loss):.6e}); "
-        f"dU0 rel err {e1:.2e}, dL rel err {e2:.2e}")
+        f"dU0 rel err {e1:.2e}, dL rel err {e2:.2e}; transposed gradient: "
+        f"{st['adj_union_blocks']} blocks from the union, {st['adj_union_staged_blocks']} staged")
+    # the clustered set takes both paths of the transposed gradient
+    assert st["adj_union_blocks"] > 0 and st["adj_union_staged_blocks"] > 0
+    assert st["adj_union_blocks"] + st["adj_union_staged_blocks"] == (w.n + 63) // 64
     assert lg == pytest.approx(float(loss), rel=1e-12)
     assert e1 < 1e-9 and e2 < 1e-9
