@@ -307,6 +307,217 @@ void k_adj_pair64(
     }
 }
 
+// Pass B with the pairs inside a tile evaluated once: the adjoint of the tile
+// transport (GLF, Hopkins surfaces).  A block owns one 64-particle tile and
+// GW of the groups; its particles walk the forward's task lists (k_tasks), in
+// which an in-tile pair (k, l) appears once, flagged, in one particle's list.
+// That lane pulls the pair back for both particles: its own cotangents as in
+// k_adj_pair64, and the partner's, added by LDS atomics to the partner's row
+// of its wave's copy of the tile's accumulator.  The forward evaluates the
+// pair's face states once and uses the flux with opposite signs at its two
+// particles, so from l's side the face states swap, s and A change sign, and
+// the pull-back gives l
+//   the cotangent of its state: t_R (k's right-face cotangent),
+//   that of its gradient: (f_k t_L - f_l t_R) s where l's slope was the
+//     limiter's choice (|d_l| <= |d_k|, same signs),
+// which is the exact adjoint of the forward's single evaluation.  After a
+// block barrier each particle's sums are its own plus the 4 waves' rows in a
+// fixed order, as in the forward.
+template <int G, int GW>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void
+k_adj_pair64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
+                  const int32_t *__restrict__ task, const int64_t *__restrict__ wave_base,
+                  const int32_t *__restrict__ n_task, const double *__restrict__ UD,
+                  const double *__restrict__ lam2, const double *__restrict__ dtp, double c,
+                  double box, double *__restrict__ R) {
+    static_assert(G % GW == 0, "group slices must tile the groups");
+    constexpr int NS = G / GW, NQ = 4 * GW, MS = 16 * GW + 1;   // accumulator row, padded
+    static_assert(kTile == 64 && kBlock == 256, "a block of 4 waves x 16 particles per tile");
+    __shared__ double stage[kBlock / 64][64 * kStage];
+    __shared__ double mir[kBlock / 64][kTile * MS];
+    const int64_t bg = xcd_block(nb * NS);
+    if (bg >= nb * NS) return;                  // whole block: no barrier is skipped
+    const int64_t blk = bg / NS;
+    const int g0 = (int)(bg - blk * NS) * GW;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int sub = lane & 3;
+    const int64_t t0 = blk * kTile;             // the tile's first particle
+    const int pl = 16 * wv + (lane >> 2);       // the lane's particle in the tile
+    const int64_t i = t0 + pl;
+    const bool active = i < n;
+    const bool owner = active && sub == 0;
+    const int64_t ic = active ? i : n - 1;
+    const bool wave_live = t0 + 16 * wv < n;    // wave-uniform
+    const double ibox = 1.0 / box;
+    const double dt = dtp[0];
+    double *sb = stage[wv];
+    double *mw = mir[wv];                       // this wave's copy of the accumulator
+    for (int e = lane; e < kTile * MS; e += 64) mw[e] = 0.0;
+    wave_lds_sync();
+
+    const double *rk = geo + (int64_t)kRec * ic;
+    const double dtVk = dt / rk[R_V];
+    double Ui[NQ], Di[NQ * 3], Li[NQ];
+#pragma unroll
+    for (int g = 0; g < GW; ++g) {
+        const double *r = UD + (ic * G + g0 + g) * 16;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            Ui[4 * g + m] = r[m];
+            Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
+            Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
+            Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
+            Li[4 * g + m] = lam2[(ic * G + g0 + g) * 4 + m];
+        }
+    }
+    double aU[NQ], aD[NQ * 3];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) aU[q] = aD[3 * q] = aD[3 * q + 1] = aD[3 * q + 2] = 0.0;
+
+    if (wave_live) {
+        const int64_t base = wave_base[blk] + pl;   // the particle's column in the table
+        const int32_t nn = active ? n_task[i] : 0;
+        int32_t kmax = nn;                          // the longest list of the wave
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
+        // the next iteration's task is loaded one iteration ahead
+        int32_t tn = sub < nn ? task[base + 64 * (int64_t)sub] : (int32_t)ic;
+        for (int32_t kk = 0; kk < kmax; kk += 4) {
+            const int32_t k = kk + sub;
+            const bool valid = k < nn;
+            const int32_t t = tn;
+            // (slot 0 of the tile's table exists once kmax > 0: no branch
+            // around the load, whose wait would then be a full one)
+            const int32_t tl = task[base + 64 * (int64_t)(k + 4 < nn ? k + 4 : 0)];
+            tn = k + 4 < nn ? tl : (int32_t)ic;
+            const bool mirror = t < 0;
+            const int32_t j = t & 0x7fffffff;
+            const int mr = mirror ? (j - (int32_t)t0) * MS : 0;   // the partner's row
+            int64_t row[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) row[m] = __shfl(j, 8 * m + (lane >> 3), 64);
+            stage_lines(geo, row, sb, lane);
+            double rl[12];
+#pragma unroll
+            for (int q = 0; q < 12; ++q) rl[q] = sb[lane * kStage + q];
+            PairGeo pg;
+            pair_geometry64(rk, rl, box, ibox, pg);
+            const bool use = valid && pg.An > 0.0;
+            const double dtVl = dt / rl[R_V];
+#pragma unroll
+            for (int g = 0; g < GW; ++g) {
+                // the record lines and the cotangent rows in one round trip
+                int64_t rowg[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g0 + g;
+                double2 v[8], vl[2];
+                load_lines(UD, rowg, lane, v);
+                load_rows4(lam2 + 4 * (g0 + g), 4 * G, j, lane, vl);
+                store_lines(v, sb, lane);
+                double Rl[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) Rl[q] = sb[lane * kStage + q];
+                store_rows4(vl, sb, lane);
+                double Ll[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) Ll[m] = sb[lane * kStage + m];
+                // forward recompute of this pair and group
+                double qLp[4], qRp[4], qL[4], qR[4];
+                bool slope_k[4], slope_l[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int q = 4 * g + m;
+                    const double dk = Di[3 * q] * pg.sx + Di[3 * q + 1] * pg.sy + Di[3 * q + 2] * pg.sz;
+                    const double dl = Rl[4 + 3 * m] * pg.sx + Rl[5 + 3 * m] * pg.sy + Rl[6 + 3 * m] * pg.sz;
+                    const double mm = minmod(dk, dl);
+                    slope_k[m] = (dk * dl > 0.0) && (fabs(dk) <= fabs(dl));
+                    slope_l[m] = (dk * dl > 0.0) && (fabs(dl) <= fabs(dk));
+                    qLp[m] = qL[m] = Ui[q] + pg.fk * mm;
+                    qRp[m] = qR[m] = Rl[m] - pg.fl * mm;
+                }
+                guard64(qL[0], qL[1], qL[2], qL[3], c);
+                guard64(qR[0], qR[1], qR[2], qR[3], c);
+                // cotangent of P_kl and its pull-back to the face states
+                double nu[4], tL[4], tR[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) nu[m] = 0.5 * (dtVl * Ll[m] - dtVk * Li[4 * g + m]);
+                m1_flux64_vjp(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, nu, tL, nullptr);
+                m1_flux64_vjp(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, nu, tR, nullptr);
+                const double dis = c * pg.An;   // 2 * (c/2) |A| times nu = mu/2
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    tL[m] += dis * nu[m];
+                    tR[m] -= dis * nu[m];
+                }
+                guard64_vjp(qLp, tL, c);
+                guard64_vjp(qRp, tR, c);
+                if (use) {
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int q = 4 * g + m;
+                        aU[q] += tL[m];
+                        const double lm = slope_k[m] ? pg.fk * tL[m] - pg.fl * tR[m] : 0.0;
+                        aD[3 * q] += lm * pg.sx;
+                        aD[3 * q + 1] += lm * pg.sy;
+                        aD[3 * q + 2] += lm * pg.sz;
+                    }
+                    if (mirror) {
+                        double *o = mw + mr + 16 * g;
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            const double ll = slope_l[m] ? pg.fk * tL[m] - pg.fl * tR[m] : 0.0;
+                            atomicAdd(o + m, tR[m]);
+                            atomicAdd(o + 4 + 3 * m, ll * pg.sx);
+                            atomicAdd(o + 5 + 3 * m, ll * pg.sy);
+                            atomicAdd(o + 6 + 3 * m, ll * pg.sz);
+                        }
+                    }
+                }
+            }
+        }
+        // the 4 lanes' partial sums, combined by a fixed butterfly
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            quad_sum<4>(aU[q]);
+            quad_sum<4>(aD[3 * q]);
+            quad_sum<4>(aD[3 * q + 1]);
+            quad_sum<4>(aD[3 * q + 2]);
+        }
+    }
+    // every wave's deposits are in its copy of the accumulator
+    __syncthreads();
+    if (!owner || !wave_live) return;
+#pragma unroll
+    for (int g = 0; g < GW; ++g)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int q = 4 * g + m;
+#pragma unroll
+            for (int v = 0; v < kBlock / 64; ++v) {
+                const double *o = mir[v] + pl * MS + 16 * g;
+                aU[q] += o[m];
+                aD[3 * q] += o[4 + 3 * m];
+                aD[3 * q + 1] += o[5 + 3 * m];
+                aD[3 * q + 2] += o[6 + 3 * m];
+            }
+        }
+    const double iV = 1.0 / rk[R_V];
+    const double b00 = rk[R_B] * iV, b01 = rk[R_B + 1] * iV, b02 = rk[R_B + 2] * iV;
+    const double b11 = rk[R_B + 3] * iV, b12 = rk[R_B + 4] * iV, b22 = rk[R_B + 5] * iV;
+#pragma unroll
+    for (int g = 0; g < GW; ++g) {
+        double *o = R + (i * G + g0 + g) * 16;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int q = 4 * g + m;
+            o[m] = Li[q] + aU[q];
+            o[4 + 3 * m + 0] = b00 * aD[3 * q] + b01 * aD[3 * q + 1] + b02 * aD[3 * q + 2];
+            o[4 + 3 * m + 1] = b01 * aD[3 * q] + b11 * aD[3 * q + 1] + b12 * aD[3 * q + 2];
+            o[4 + 3 * m + 2] = b02 * aD[3 * q] + b12 * aD[3 * q + 1] + b22 * aD[3 * q + 2];
+        }
+    }
+}
+
 // Pass C: transpose of the least-squares gradient, gathered over the
 // symmetric neighbour lists (i is a gather neighbour of p iff r < H_i).  All
 // loads of one neighbour slot (position and 1/H, and the G records of rho)
@@ -630,6 +841,13 @@ void launch_adjoint64(rt_ctx *ctx, const double *UD, const double *Uung, const d
     const int64_t np = (n + kBlock / kAQ - 1) / (kBlock / kAQ);
     const double2 *tab = (const double2 *)ctx->hll_table;
     const bool iva = ctx->surfaces == RT_IVANOVA;
+    if (ctx->solver == RT_GLF && !iva && ctx->task) {
+        // the adjoint of the tile transport (in-tile pairs once)
+        const int64_t nt = (n + kTile - 1) / kTile;
+        k_adj_pair64_tile<G, GW><<<(unsigned)xcd_grid(nt * (G / GW)), kBlock, 0, st>>>(
+            n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, lam2, dt, ctx->p.c_red,
+            ctx->p.box, R);
+    } else {
 #define RT_ADJ_PAIR_LAUNCH(HLL_, IVA_)                                                          \
     k_adj_pair64<G, GW, kAQ, HLL_, IVA_, (HLL_ && kAdjHllOwn)><<<(unsigned)xcd_grid(np * (G / GW)), kBlock, 0, st>>>( \
         n, np, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, lam2, dt, ctx->p.c_red,      \
@@ -642,6 +860,7 @@ void launch_adjoint64(rt_ctx *ctx, const double *UD, const double *Uung, const d
         else RT_ADJ_PAIR_LAUNCH(false, false);
     }
 #undef RT_ADJ_PAIR_LAUNCH
+    }
     if constexpr (G <= 4 && kAGQ == 4) {
         if (ctx->aoff) {
             // blocks whose union fits: from LDS; the others: by list
