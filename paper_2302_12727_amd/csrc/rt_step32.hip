@@ -9,6 +9,11 @@
 
 using namespace gearrt;
 
+// Waves per SIMD of the GLF FP32C transport up to 3 groups.
+#ifndef RT_TRANSPORT32_WAVES
+#define RT_TRANSPORT32_WAVES 3
+#endif
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -292,7 +297,8 @@ k_gradient32u(int64_t n, int64_t nb, const float *__restrict__ geo32, const doub
 // each due pair's exchange weighted by dt 2^min(b_k, b_l) in the compensated
 // sums; pending sums accm in FP64).
 template <int G, bool HLL = false, int Q = 1, bool IVA = false, bool BIN = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ? 3 : 1))) void k_transport32(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
+    G <= 3 ? (HLL ? 3 : RT_TRANSPORT32_WAVES) : 1))) void k_transport32(
     int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ geo,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_nbr, const float *__restrict__ UD,
@@ -302,6 +308,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
     const float2 *__restrict__ hll = nullptr, const double *__restrict__ ivan = nullptr,
     int64_t tick = 0, double *__restrict__ accm = nullptr) {
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
+    // PIPE: the next stage's rows in flight during each evaluation (GLF; the
+    // HLL instantiation has no registers left for them)
+    constexpr bool PIPE = !HLL;
     constexpr int NQ = 4 * G, PW = 64 / Q, PB = kBlock / Q;
     __shared__ float stage[kBlock / 64][64 * kStage32];
     __shared__ double smem[(kBlock / 64) * 2 * G];
@@ -369,17 +378,38 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
             for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
         }
         if (BIN && __ballot(nn > 0) == 0) kmax = 0;   // no due pair in this wave
-        // the next iteration's neighbour index is loaded one iteration ahead
-        int32_t jn = sub < nn ? nbr[base + 64 * (int64_t)sub] : (int32_t)ic;
+        // Rows in flight: v holds the loads of the next stage (the geometry
+        // rows, then each group's record rows) while the current stage is
+        // evaluated from the stage buffer.  The next iteration's neighbour
+        // index is loaded one iteration ahead.
+        int32_t jc = sub < nn ? nbr[base + 64 * (int64_t)sub] : (int32_t)ic;
+        int64_t row[4];
+        float4 v[4];
+        if constexpr (PIPE) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) row[m] = __shfl(jc, 16 * m + (lane >> 2), 64);
+            load_rows32(geo32, row, lane, v);
+        }
         for (int32_t kk = 0; kk < kmax; kk += Q) {
             const int32_t k = kk + sub;
             const bool valid = k < nn;
-            const int32_t j = jn;
-            jn = k + Q < nn ? nbr[base + 64 * (int64_t)(k + Q)] : (int32_t)ic;
-            int64_t row[4];
+            const int32_t j = jc;
+            // (slot 0 of the wave's table exists once kmax > 0: no branch
+            // around the load, whose wait would then be a full one)
+            const int32_t jl = nbr[base + 64 * (int64_t)(k + Q < nn ? k + Q : 0)];
+            const int32_t jn = k + Q < nn ? jl : (int32_t)ic;
+            if constexpr (!PIPE) {
 #pragma unroll
-            for (int m = 0; m < 4; ++m) row[m] = __shfl(j, 16 * m + (lane >> 2), 64);
-            stage_rows32(geo32, row, sb, lane);
+                for (int m = 0; m < 4; ++m) row[m] = __shfl(j, 16 * m + (lane >> 2), 64);
+                load_rows32(geo32, row, lane, v);
+            }
+            store_rows32(v, sb, lane);          // the geometry rows
+            if constexpr (PIPE) {
+                int64_t rowg[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) rowg[m] = row[m] * G;
+                load_rows32(UD, rowg, lane, v);
+            }
             const float *rl = sb + lane * kStage32;
             // separation in FP64 from FP64 positions, rounded once
             double xl[3];
@@ -431,10 +461,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
             const float iAn = (HLL && An > 0.0f) ? rcp32(An) : 0.0f;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                int64_t rowg[4];
+                // the stages in program order: each one's loads stay in
+                // flight across the evaluation of the previous one
+                if constexpr (PIPE) {
+                    __builtin_amdgcn_sched_barrier(0);
+                } else {
+                    int64_t rowg[4];
 #pragma unroll
-                for (int m = 0; m < 4; ++m) rowg[m] = row[m] * G + g;
-                stage_rows32(UD, rowg, sb, lane);
+                    for (int m = 0; m < 4; ++m) rowg[m] = row[m] * G + g;
+                    load_rows32(UD, rowg, lane, v);
+                }
+                store_rows32(v, sb, lane);      // group g's record rows
+                if constexpr (PIPE) {
+                    if (g + 1 < G) {
+                        int64_t rowg[4];
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) rowg[m] = row[m] * G + g + 1;
+                        load_rows32(UD, rowg, lane, v);
+                    } else {                    // the next iteration's geometry rows
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) row[m] = __shfl(jn, 16 * m + (lane >> 2), 64);
+                        load_rows32(geo32, row, lane, v);
+                    }
+                }
                 const float *Rl = sb + lane * kStage32;
                 float qL[4], qR[4];
 #pragma unroll
@@ -468,6 +517,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(G <= 3 ?
                         acc[4 * g + m].add(wkl * (w1 * FL[m] + w2 * FR[m] + w3 * (qR[m] - qL[m])));
                 }
             }
+            jc = jn;
+            if constexpr (PIPE) __builtin_amdgcn_sched_barrier(0);
         }
     }
     double av[NQ];
