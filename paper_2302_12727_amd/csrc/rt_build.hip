@@ -1014,8 +1014,8 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
         k_neighbours<true><<<nblk(n), kBlock, 0, st>>>(n, T, ctx->xs, Htmp, ctx->p.box,
                                                        ctx->n_nbr, ctx->n_gath, ctx->wave_base,
                                                        ctx->nbr, nlist, ncap);
-        if (ctx->p.precision == RT_FP64) {
-            // task lists of the FP64 tile transport
+        {
+            // task lists of the tile transports
             ALLOC(ctx->task, sizeof(int32_t) * std::max<int64_t>(ctx->slots, 1));
             ALLOC(ctx->n_task, sizeof(int32_t) * n);
             k_tasks<<<(unsigned)ctx->nwaves, 64, 0, st>>>(n, ctx->wave_base, ctx->n_nbr, ctx->nbr,

@@ -13,6 +13,11 @@ using namespace gearrt;
 #ifndef RT_TRANSPORT32_WAVES
 #define RT_TRANSPORT32_WAVES 3
 #endif
+// 1: the GLF FP32C transport with Hopkins surfaces evaluates in-tile pairs
+// once (k_transport32_tile); 0: always two-sided.
+#ifndef RT_TRANSPORT32_TILE
+#define RT_TRANSPORT32_TILE 1
+#endif
 
 namespace {
 
@@ -641,6 +646,287 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     }
 }
 
+// FP32C transport with the pairs inside a tile evaluated once (GLF, Hopkins
+// surfaces, one global step, up to 3 groups): the tile scheme of the FP64
+// transport (k_transport64_tile, the same task lists) with the FP32 pair
+// arithmetic of k_transport32.  The lane that evaluates an in-tile pair adds
+// Phi_kl to its own compensated sums and -Phi_kl, in FP64 by an LDS atomic
+// add, to the partner's row of its wave's copy of the tile accumulator; after
+// a block barrier each particle's FP64 sum is its own (compensated, combined
+// by the butterfly) plus the 4 waves' rows in a fixed order.  Each stage's
+// rows are in flight across the previous stage's evaluation, as in the
+// two-sided kernel.
+template <int G>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RT_TRANSPORT32_WAVES))) void
+k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
+                   const double *__restrict__ geo, const int32_t *__restrict__ task,
+                   const int64_t *__restrict__ wave_base, const int32_t *__restrict__ n_task,
+                   const float *__restrict__ UD, const double *__restrict__ dtp, double c,
+                   double box, float *__restrict__ Uout, double *__restrict__ partials,
+                   unsigned long long *__restrict__ counts, float *__restrict__ Uung,
+                   int32_t *__restrict__ status) {
+    constexpr int NQ = 4 * G, MS = NQ + 1;      // accumulator row, padded against bank conflicts
+    static_assert(kTile == 64 && kBlock == 256, "a block of 4 waves x 16 particles per tile");
+    __shared__ float stage[kBlock / 64][64 * kStage32];
+    __shared__ double mir[kBlock / 64][kTile * MS];
+    __shared__ double smem[(kBlock / 64) * 2 * G];
+    __shared__ unsigned long long scnt[4];
+    const int64_t blk = xcd_block(nb);
+    if (blk >= nb) return;                      // whole block: no barrier is skipped
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int sub = lane & 3;
+    const int64_t t0 = blk * kTile;             // the tile's first particle
+    const int pl = 16 * wv + (lane >> 2);       // the lane's particle in the tile
+    const int64_t i = t0 + pl;
+    const bool active = i < n;
+    const bool owner = active && sub == 0;
+    const int64_t ic = active ? i : n - 1;
+    const bool wave_live = t0 + 16 * wv < n;    // wave-uniform
+    const double ibox = 1.0 / box;
+    const float cf = (float)c, c2 = (float)(c * c), ic2 = (float)(1.0 / (c * c)), hc = 0.5f * cf;
+    if (threadIdx.x < 4) scnt[threadIdx.x] = 0;
+    float *sb = stage[wv];
+    double *mw = mir[wv];                       // this wave's copy of the accumulator
+    for (int e = lane; e < kTile * MS; e += 64) mw[e] = 0.0;
+    wave_lds_sync32();
+
+    const float *rk = geo32 + (int64_t)F_REC * ic;
+    const double *xk = reinterpret_cast<const double *>(rk);
+    const double pkx = xk[0], pky = xk[1], pkz = xk[2];
+    const float iHk = rk[F_IH], hk = rk[F_H];
+    float Bk[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) Bk[a] = rk[F_B + a];
+    float Ui[NQ], Di[NQ * 3];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const float *r = UD + (ic * G + g) * 16;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            Ui[4 * g + m] = r[m];
+            Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
+            Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
+            Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
+        }
+    }
+    Kahan acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q].s = acc[q].c = 0.0f;
+    int cE = 0, cF = 0;
+    if (wave_live) {
+        const int64_t base = wave_base[blk] + pl;   // the particle's column in the table
+        const int32_t nn = active ? n_task[i] : 0;
+        int32_t kmax = nn;                          // the longest list of the wave
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
+        // rows in flight as in k_transport32; the task of the next iteration
+        // is loaded one iteration ahead
+        int32_t tc = sub < nn ? task[base + 64 * (int64_t)sub] : (int32_t)ic;
+        int64_t row[4];
+        float4 v[4];
+        {
+            const int32_t j = tc & 0x7fffffff;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) row[m] = __shfl(j, 16 * m + (lane >> 2), 64);
+            load_rows32(geo32, row, lane, v);
+        }
+        for (int32_t kk = 0; kk < kmax; kk += 4) {
+            const int32_t k = kk + sub;
+            const bool valid = k < nn;
+            const int32_t t = tc;
+            // (slot 0 of the tile's table exists once kmax > 0: no branch
+            // around the load, whose wait would then be a full one)
+            const int32_t tl = task[base + 64 * (int64_t)(k + 4 < nn ? k + 4 : 0)];
+            const int32_t tn = k + 4 < nn ? tl : (int32_t)ic;
+            const bool mirror = t < 0;
+            const int32_t j = t & 0x7fffffff;
+            const int mr = mirror ? (j - (int32_t)t0) * MS : 0;   // the partner's row
+            store_rows32(v, sb, lane);          // the geometry rows
+            {
+                int64_t rowg[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) rowg[m] = row[m] * G;
+                load_rows32(UD, rowg, lane, v);
+            }
+            const float *rl = sb + lane * kStage32;
+            // separation in FP64 from FP64 positions, rounded once
+            double xl[3];
+            {
+                union { float f[2]; double d; } u;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    u.f[0] = rl[2 * a];
+                    u.f[1] = rl[2 * a + 1];
+                    xl[a] = u.d;
+                }
+            }
+            const float sx = (float)min_image(xl[0] - pkx, box, ibox);
+            const float sy = (float)min_image(xl[1] - pky, box, ibox);
+            const float sz = (float)min_image(xl[2] - pkz, box, ibox);
+            const float r = sqrt32(sx * sx + sy * sy + sz * sz);
+            const float wk = kern_wf(r * iHk);
+            const float wl = kern_wf(r * rl[F_IH]);
+            const float m00 = wk * Bk[0] + wl * rl[F_B + 0];
+            const float m01 = wk * Bk[1] + wl * rl[F_B + 1];
+            const float m02 = wk * Bk[2] + wl * rl[F_B + 2];
+            const float m11 = wk * Bk[3] + wl * rl[F_B + 3];
+            const float m12 = wk * Bk[4] + wl * rl[F_B + 4];
+            const float m22 = wk * Bk[5] + wl * rl[F_B + 5];
+            const float Ax = m00 * sx + m01 * sy + m02 * sz;
+            const float Ay = m01 * sx + m11 * sy + m12 * sz;
+            const float Az = m02 * sx + m12 * sy + m22 * sz;
+            const float An = sqrt32(Ax * Ax + Ay * Ay + Az * Az);
+            const float hl = rl[F_H];
+            const float ih = rcp32(hk + hl);
+            const float fk = hk * ih, fl = hl * ih;
+            const bool use = valid && An > 0.0f;
+            const int cnt2 = mirror ? 2 : 1;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                // the stages in program order: each one's loads stay in
+                // flight across the evaluation of the previous one
+                __builtin_amdgcn_sched_barrier(0);
+                store_rows32(v, sb, lane);      // group g's record rows
+                if (g + 1 < G) {
+                    int64_t rowg[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) rowg[m] = row[m] * G + g + 1;
+                    load_rows32(UD, rowg, lane, v);
+                } else {                        // the next iteration's geometry rows
+                    const int32_t jn = tn & 0x7fffffff;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) row[m] = __shfl(jn, 16 * m + (lane >> 2), 64);
+                    load_rows32(geo32, row, lane, v);
+                }
+                const float *Rl = sb + lane * kStage32;
+                float qL[4], qR[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int q = 4 * g + m;
+                    const float dk = Di[3 * q] * sx + Di[3 * q + 1] * sy + Di[3 * q + 2] * sz;
+                    const float dl = Rl[4 + 3 * m] * sx + Rl[5 + 3 * m] * sy + Rl[6 + 3 * m] * sz;
+                    const float mm = minmod32(dk, dl);
+                    qL[m] = Ui[q] + fk * mm;
+                    qR[m] = Rl[m] - fl * mm;
+                }
+                const int f1 = guard32(qL[0], qL[1], qL[2], qL[3], cf);
+                const int f2 = guard32(qR[0], qR[1], qR[2], qR[3], cf);
+                const float w3 = -hc * An;      // GLF
+                float FL[4], FR[4];
+                m1_flux32(qL[0], qL[1], qL[2], qL[3], Ax, Ay, Az, c2, ic2, FL);
+                m1_flux32(qR[0], qR[1], qR[2], qR[3], Ax, Ay, Az, c2, ic2, FR);
+                if (use) {
+                    cE += cnt2 * ((f1 & 1) + (f2 & 1));
+                    cF += cnt2 * ((f1 >> 1) + (f2 >> 1));
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const float phi = 0.5f * FL[m] + 0.5f * FR[m] + w3 * (qR[m] - qL[m]);
+                        acc[4 * g + m].add(phi);
+                        if (mirror) atomicAdd(mw + mr + 4 * g + m, -(double)phi);
+                    }
+                }
+            }
+            tc = tn;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    double av[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        av[q] = acc[q].value();
+        quad_sum<4>(av[q]);
+    }
+    // every wave's deposits are in its copy of the accumulator
+    __syncthreads();
+    double red[2 * G];
+    int gE = 0, gF = 0;
+    float chk = 0.0f;   // NaN iff an updated state is NaN or infinite
+    if (owner) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int v = 0; v < kBlock / 64; ++v) av[q] += mir[v][pl * MS + q];
+        const double V = geo[(int64_t)kRec * i + R_V];
+        const double dtV = dtp[0] / V;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            double q0 = (double)Ui[4 * g + 0] - dtV * av[4 * g + 0];
+            double q1 = (double)Ui[4 * g + 1] - dtV * av[4 * g + 1];
+            double q2 = (double)Ui[4 * g + 2] - dtV * av[4 * g + 2];
+            double q3 = (double)Ui[4 * g + 3] - dtV * av[4 * g + 3];
+            const double Epre = q0;
+            if (Uung) {
+                float *u = Uung + i * NQ + 4 * g;
+                u[0] = (float)q0;
+                u[1] = (float)q1;
+                u[2] = (float)q2;
+                u[3] = (float)q3;
+            }
+            int f = 0;
+            if (q0 < 0.0) {
+                q0 = q1 = q2 = q3 = 0.0;
+                f = 1;
+            } else if (q0 == 0.0) {
+                q1 = q2 = q3 = 0.0;
+            } else {
+                const double F2 = q1 * q1 + q2 * q2 + q3 * q3, lim = c * q0;
+                if (F2 > lim * lim) {
+                    const double sc = lim * rsq64(F2);
+                    q1 *= sc;
+                    q2 *= sc;
+                    q3 *= sc;
+                    f = 2;
+                }
+            }
+            gE += f & 1;
+            gF += f >> 1;
+            float *o = Uout + i * NQ + 4 * g;
+            const float o0 = (float)q0, o1 = (float)q1, o2 = (float)q2, o3 = (float)q3;
+            o[0] = o0;
+            o[1] = o1;
+            o[2] = o2;
+            o[3] = o3;
+            chk = __builtin_fmaf((float)Epre, 0.0f, chk);
+            chk = __builtin_fmaf(o1, 0.0f, chk);
+            chk = __builtin_fmaf(o2, 0.0f, chk);
+            chk = __builtin_fmaf(o3, 0.0f, chk);
+            red[g] = V * (double)o0;
+            red[G + g] = (f & 1) ? -Epre * V : 0.0;
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < 2 * G; ++p) red[p] = 0.0;
+    }
+    if (chk != chk) atomicOr(status, ST_NONFINITE);
+    if (partials) {
+        const int ln = threadIdx.x & 63;
+#pragma unroll
+        for (int p = 0; p < 2 * G; ++p) {
+            double x = wave_sum(red[p]);
+            if (ln == 0) smem[wv * 2 * G + p] = x;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * G) {
+            double s = 0.0;
+            for (int u = 0; u < kBlock / 64; ++u) s += smem[u * 2 * G + threadIdx.x];
+            partials[blk * 2 * G + threadIdx.x] = s;
+        }
+    }
+    if (counts) {
+        int64_t v0 = wave_sum_i64(cE), v1 = wave_sum_i64(cF), v2 = wave_sum_i64(gE),
+                v3 = wave_sum_i64(gF);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&scnt[0], (unsigned long long)v0);
+            atomicAdd(&scnt[1], (unsigned long long)v1);
+            atomicAdd(&scnt[2], (unsigned long long)v2);
+            atomicAdd(&scnt[3], (unsigned long long)v3);
+        }
+        __syncthreads();
+        if (threadIdx.x < 4 && scnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], scnt[threadIdx.x]);
+    }
+}
+
 // Lanes per particle of the FP32 gradient (1, 2 or 4).  With 4 the
 // compensated-FP32 adjoint of the 1000-particle adjoint case moved away from
 // the FP64 one (luminosity gradients 1.4e-5 apart instead of 3e-8): the
@@ -692,6 +978,18 @@ void launch_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *U
     const int64_t n = ctx->p.n, nb = rt_transport32_rows(n);
     const float2 *tab = (const float2 *)ctx->hll_table32;
     const bool iva = ctx->surfaces == RT_IVANOVA;
+    if constexpr (G <= 3) {
+        if (RT_TRANSPORT32_TILE != 0 && ctx->solver == RT_GLF && !iva && ctx->task) {
+            // pair-once tiles: one block of 64 particles per tile, as many
+            // blocks (and rows of partials) as the two-sided kernel
+            static_assert(kBlock / kQ32 == kTile, "a tile per two-sided block");
+            k_transport32_tile<G><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
+                n, nb, ctx->geo32, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt,
+                ctx->p.c_red, ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung,
+                ctx->status);
+            return;
+        }
+    }
 #define RT_TRANSPORT32_LAUNCH(HLL_, IVA_)                                                     \
     k_transport32<G, HLL_, kQ32, IVA_><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(   \
         n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt,            \
