@@ -669,6 +669,8 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
     static_assert(kTile == 64 && kBlock == 256, "a block of 4 waves x 16 particles per tile");
     __shared__ float stage[kBlock / 64][64 * kStage32];
     __shared__ double mir[kBlock / 64][kTile * MS];
+    constexpr int DS = 3 * NQ + 1;              // own-gradient row, padded
+    __shared__ float dsh[kBlock / 64][16 * DS];
     __shared__ double smem[(kBlock / 64) * 2 * G];
     __shared__ unsigned long long scnt[4];
     const int64_t blk = xcd_block(nb);
@@ -697,18 +699,23 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
     float Bk[6];
 #pragma unroll
     for (int a = 0; a < 6; ++a) Bk[a] = rk[F_B + a];
-    float Ui[NQ], Di[NQ * 3];
+    float Ui[NQ];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const float *r = UD + (ic * G + g) * 16;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            Ui[4 * g + m] = r[m];
-            Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
-            Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
-            Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
-        }
+        for (int m = 0; m < 4; ++m) Ui[4 * g + m] = r[m];
     }
+    // the own gradients live in LDS (the 4 lanes of a particle read one
+    // address; in registers they left 36 bytes a lane spilled); lane sub
+    // copies component sub's
+    float *Dsh = dsh[wv] + (lane >> 2) * DS;
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            Dsh[3 * (4 * g + sub) + a] = UD[(ic * G + g) * 16 + 4 + 3 * sub + a];
+    wave_lds_sync32();
     Kahan acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q].s = acc[q].c = 0.0f;
@@ -803,7 +810,7 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const int q = 4 * g + m;
-                    const float dk = Di[3 * q] * sx + Di[3 * q + 1] * sy + Di[3 * q + 2] * sz;
+                    const float dk = Dsh[3 * q] * sx + Dsh[3 * q + 1] * sy + Dsh[3 * q + 2] * sz;
                     const float dl = Rl[4 + 3 * m] * sx + Rl[5 + 3 * m] * sy + Rl[6 + 3 * m] * sz;
                     const float mm = minmod32(dk, dl);
                     qL[m] = Ui[q] + fk * mm;
