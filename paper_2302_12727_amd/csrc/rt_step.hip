@@ -108,6 +108,64 @@ __device__ __forceinline__ void gradient_record(double (&acc)[4 * G][3], const d
     if (chk != chk) atomicOr(status, ST_NONFINITE);
 }
 
+// Reduce-scatter of a particle's four lanes' partial sums (4 lanes a
+// particle, DPP): afterwards lane sub holds in s[g] the full sums of
+// component sub of every group g, formed with the same additions in the same
+// order as quad_sum, so with the same bits, while no lane holds all 12 G sums
+// (the record then needs a quarter of the registers).  After the first step
+// slot k of a lane with bit 0 = b0 holds q = 2k + b0, after the second slot g
+// of lane sub holds q = 4g + sub.
+template <int G>
+__device__ __forceinline__ void quad_scatter(const double (&acc)[4 * G][3], int sub,
+                                             double (&s)[G][3]) {
+    const bool b0 = (sub & 1) != 0, b1 = (sub & 2) != 0;
+    double t[2 * G][3];
+#pragma unroll
+    for (int k = 0; k < 2 * G; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double mine = b0 ? acc[2 * k + 1][a] : acc[2 * k][a];
+            const double other = b0 ? acc[2 * k][a] : acc[2 * k + 1][a];
+            t[k][a] = mine + quad_xor<1>(other);
+        }
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double mine = b1 ? t[2 * g + 1][a] : t[2 * g][a];
+            const double other = b1 ? t[2 * g][a] : t[2 * g + 1][a];
+            s[g][a] = mine + quad_xor<2>(other);
+        }
+}
+
+// The record from the scattered sums (gradient_record's arithmetic): lane sub
+// writes component sub of every group, its state u[g] and its gradient.
+template <int G>
+__device__ __forceinline__ void gradient_record_part(const double (&s)[G][3], const double (&u)[G],
+                                                     const double *__restrict__ rec, double *o,
+                                                     int sub, int32_t *__restrict__ status) {
+    const double iV = 1.0 / rec[R_V];
+    const double b00 = rec[R_B] * iV, b01 = rec[R_B + 1] * iV, b02 = rec[R_B + 2] * iV;
+    const double b11 = rec[R_B + 3] * iV, b12 = rec[R_B + 4] * iV, b22 = rec[R_B + 5] * iV;
+    double chk = 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const double d0 = b00 * s[g][0] + b01 * s[g][1] + b02 * s[g][2];
+        const double d1 = b01 * s[g][0] + b11 * s[g][1] + b12 * s[g][2];
+        const double d2 = b02 * s[g][0] + b12 * s[g][1] + b22 * s[g][2];
+        double *og = o + 16 * g;
+        og[sub] = u[g];
+        og[4 + 3 * sub] = d0;
+        og[5 + 3 * sub] = d1;
+        og[6 + 3 * sub] = d2;
+        chk = __builtin_fma(u[g], 0.0, chk);
+        chk = __builtin_fma(d0, 0.0, chk);
+        chk = __builtin_fma(d1, 0.0, chk);
+        chk = __builtin_fma(d2, 0.0, chk);
+    }
+    if (chk != chk) atomicOr(status, ST_NONFINITE);
+}
+
 // ---------------------------------------------------------------------------
 // Gradient (eq:gradient):  grad q_i = sum_j (q_j - q_i) psi~_j(x_i)
 //   = S_i^{-1} sum_j (q_j - q_i) w(r_ij / H_i) s_ij   (the kernel normalisation
@@ -302,6 +360,21 @@ __global__ __launch_bounds__(grad_block(G)) __attribute__((amdgpu_waves_per_eu(
             gather();
         }
     }
+    if constexpr (Q == 4) {
+        double sg[G][3];
+        quad_scatter<G>(acc, sub, sg);
+        if (!active) return;
+        // the own state, as loaded, from the wave's own row: component sub
+        wave_lds_sync();
+        double u[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const dvec2 x = ob[(lane / Q) * S + 2 * g + (sub >> 1)];
+            u[g] = (sub & 1) ? x.y : x.x;
+        }
+        gradient_record_part<G>(sg, u, rec, UD + ic * (16 * G), sub, status);
+        return;
+    }
     if (Q > 1) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
@@ -458,13 +531,17 @@ k_gradient64u(int64_t n, int64_t nb, const double *__restrict__ geo, const doubl
             four(wb, gq + 1);
         }
     }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            quad_sum<Q>(acc[q][a]);
+    double sg[G][3];
+    quad_scatter<G>(acc, sub, sg);
     if (!active) return;
-    gradient_record<G, Q>(acc, Ui, rec, UD + ic * (16 * G), sub, status);
+    // the own state component sub of every group, from the union's row
+    double u[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const dvec2 x = ust[il * PU + 2 * g + (sub >> 1)];
+        u[g] = (sub & 1) ? x.y : x.x;
+    }
+    gradient_record_part<G>(sg, u, rec, UD + ic * (16 * G), sub, status);
 }
 
 // Transport (eq:transport-update-explicit with the GLF flux eq:riemann-GLF).
