@@ -323,7 +323,7 @@ void k_adj_pair64(
 // which is the exact adjoint of the forward's single evaluation.  After a
 // block barrier each particle's sums are its own plus the 4 waves' rows in a
 // fixed order, as in the forward.
-template <int G, int GW>
+template <int G, int GW, bool OFF32>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void
 k_adj_pair64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                   const int32_t *__restrict__ task, const int64_t *__restrict__ wave_base,
@@ -393,25 +393,29 @@ k_adj_pair64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
             const bool mirror = t < 0;
             const int32_t j = t & 0x7fffffff;
             const int mr = mirror ? (j - (int32_t)t0) * MS : 0;   // the partner's row
-            int64_t row[8];
+            // rows by 32-bit byte offsets from the tables' bases while the
+            // records fit 4 GiB (OFF32), as in the tile transport
+            int32_t rw[8];
 #pragma unroll
-            for (int m = 0; m < 8; ++m) row[m] = __shfl(j, 8 * m + (lane >> 3), 64);
-            stage_lines(geo, row, sb, lane);
+            for (int m = 0; m < 8; ++m) rw[m] = __shfl(j, 8 * m + (lane >> 3), 64);
+            const RowLines<OFF32> gl(geo, rw, 1, lane), ul(UD, rw, G, lane);
+            {
+                double2 v[8];
+                gl.load(0, v);
+                store_lines(v, sb, lane);
+            }
             double rl[12];
 #pragma unroll
             for (int q = 0; q < 12; ++q) rl[q] = sb[lane * kStage + q];
             PairGeo pg;
             pair_geometry64(rk, rl, box, ibox, pg);
             const bool use = valid && pg.An > 0.0;
-            const double dtVl = dt / rl[R_V];
+            const double dtVl = dt * rcp64(rl[R_V]);   // (about 1 ulp; no IEEE division per pair)
 #pragma unroll
             for (int g = 0; g < GW; ++g) {
                 // the record lines and the cotangent rows in one round trip
-                int64_t rowg[8];
-#pragma unroll
-                for (int m = 0; m < 8; ++m) rowg[m] = row[m] * G + g0 + g;
                 double2 v[8], vl[2];
-                load_lines(UD, rowg, lane, v);
+                ul.load(g0 + g, v);
                 load_rows4(lam2 + 4 * (g0 + g), 4 * G, j, lane, vl);
                 store_lines(v, sb, lane);
                 double Rl[16];
@@ -844,9 +848,14 @@ void launch_adjoint64(rt_ctx *ctx, const double *UD, const double *Uung, const d
     if (ctx->solver == RT_GLF && !iva && ctx->task) {
         // the adjoint of the tile transport (in-tile pairs once)
         const int64_t nt = (n + kTile - 1) / kTile;
-        k_adj_pair64_tile<G, GW><<<(unsigned)xcd_grid(nt * (G / GW)), kBlock, 0, st>>>(
-            n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, lam2, dt, ctx->p.c_red,
-            ctx->p.box, R);
+        if ((uint64_t)n * 128u * G < (uint64_t(1) << 32))
+            k_adj_pair64_tile<G, GW, true><<<(unsigned)xcd_grid(nt * (G / GW)), kBlock, 0, st>>>(
+                n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, lam2, dt,
+                ctx->p.c_red, ctx->p.box, R);
+        else
+            k_adj_pair64_tile<G, GW, false><<<(unsigned)xcd_grid(nt * (G / GW)), kBlock, 0, st>>>(
+                n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, lam2, dt,
+                ctx->p.c_red, ctx->p.box, R);
     } else {
 #define RT_ADJ_PAIR_LAUNCH(HLL_, IVA_)                                                          \
     k_adj_pair64<G, GW, kAQ, HLL_, IVA_, (HLL_ && kAdjHllOwn)><<<(unsigned)xcd_grid(np * (G / GW)), kBlock, 0, st>>>( \
