@@ -561,7 +561,7 @@ def main():
                      "hbm_frac": (traffic / tr_avg / PEAK_HBM) if traffic else None,
                      # 'alu' is the binding roofline at the algorithmic counts
                      # (flop/byte above the ridge); what the counters show
-                     # holding the kernel back is latency and LDS traffic
+                     # holding the kernel back is the neighbour lines' load path
                      "limiter": "the load path of the neighbour lines (rocprofv3 counters: "
                                 "texture-data path 86% busy, 31% of wave cycles waiting): "
                                 "the SIMDs are about half VALU-busy",
