@@ -238,3 +238,32 @@ def test_gradient_union_and_staged_blocks():
     log(f"gradient max rel err {err:.3e}")
     assert err < 1e-12
     assert np.array_equal(unsort(rt.states_of(UD).cpu().numpy(), p), w.U0)
+
+
+
+def test_gradient_paths_identical_bits():
+    """The FP64 union and staged gradients sum the same slots in the same
+    order and join the four lanes by the same reduce-scatter, so a block gives
+    identical bits on either path.  Groups do not mix in the gradient, so
+    group g of a 4-group run equals a 1-group run on group g's states; a
+    1-group union holds 1024 rows against 512 at 4 groups, so blocks between
+    the two take the union path in one run and the staged path in the other."""
+    w = workloads.config(4, scale=(1 << 14) / (1 << 24))   # Plummer + background, 4 groups
+    geo = oracle.build_geometry(w.x)
+    rt4 = RT(w.n, 4)
+    perm4, *_ = rt4.rt_build_cells(dev(w.x), dev(geo.h))
+    s4 = rt4.rt_get_stats()
+    U = dev(w.U0[perm4.cpu().numpy()])
+    G4 = rt4.gradients_of(rt4.rt_gradient(U)).cpu().numpy()
+    switched = 0
+    for g in range(4):
+        rt1 = RT(w.n, 1)
+        perm1, *_ = rt1.rt_build_cells(dev(w.x), dev(geo.h))
+        assert torch.equal(perm1, perm4)
+        switched = rt1.rt_get_stats()["union_blocks"] - s4["union_blocks"]
+        G1 = rt1.gradients_of(rt1.rt_gradient(U[:, g:g + 1].contiguous())).cpu().numpy()
+        assert np.array_equal(G1[:, 0].view(np.uint64), G4[:, g].view(np.uint64)), g
+        del rt1
+    log(f"fp64 gradient paths: 4 groups {s4['union_blocks']} union / {s4['union_staged_blocks']} "
+        f"staged; {switched} blocks on the union path only at 1 group; identical bits")
+    assert switched > 0
