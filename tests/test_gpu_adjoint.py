@@ -63,6 +63,38 @@ def test_single_step_vjp(case):
     assert e1 < 1e-9 and e2 < 1e-9
 
 
+@pytest.mark.parametrize("n_side,groups", [(9, 1), (11, 3)])
+def test_single_step_vjp_ragged(n_side, groups):
+    """The adjoint's tile pair pass and its neighbour-union transposed gradient
+    at 1 and 3 groups on lattices whose last tile is partial (729 and 1331
+    particles), against the torch reference."""
+    w = workloads.lattice_workload(n_side, groups, 2, 1, seed=700 + n_side, name="adj-ragged")
+    log(f"case adjoint ragged lattice{n_side} G={groups} n={w.n}")
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs)
+    ts = TorchStep(geo, srcs)
+    rt = RT(w.n, w.groups)
+    perm, *_ = rt.rt_build_cells(dev(w.x), dev(geo.h))
+    rt.rt_set_sources(dev(w.xs))
+    p = perm.cpu().numpy()
+    g = workloads.rng(710 + n_side)
+    lam_next = g.normal(size=w.U0.shape)
+    U = torch.from_numpy(w.U0.copy()).requires_grad_(True)
+    L = torch.from_numpy(w.L.copy()).requires_grad_(True)
+    out = ts.step(U, L, geo.dt)
+    gU, gL = torch.autograd.grad(out, (U, L), grad_outputs=torch.from_numpy(lam_next))
+    dLdL = torch.zeros(w.L.shape, dtype=torch.float64, device="cuda")
+    lam = rt.rt_adjoint(dev(w.U0[p]), dev(w.L), dev(lam_next[p]), dL_dL=dLdL)
+    st = rt.rt_get_stats()
+    got = unsort(lam.cpu().numpy(), p)
+    e1, e2 = rel(got, gU.numpy()), rel(dLdL.cpu().numpy(), gL.numpy())
+    log(f"ragged VJP lattice{n_side} G={groups}: dU rel err {e1:.2e}, dL rel err {e2:.2e}; "
+        f"transposed gradient: {st['adj_union_blocks']} union blocks, "
+        f"{st['adj_union_staged_blocks']} staged")
+    assert st["adj_union_blocks"] + st["adj_union_staged_blocks"] == (w.n + 63) // 64
+    assert e1 < 1e-9 and e2 < 1e-9
+
+
 def test_vjp_with_stored_records_equals_recompute(case):
     w, geo, ts, rt, p, _, _ = case
     g = workloads.rng(10)

@@ -169,3 +169,19 @@ def test_fp32c_mid_lattice_sources():
     assert per.max() <= TOL32
     assert local_err(got, ref, geo.sptr, geo.sidx) < TOL32
     assert np.allclose(Q, oracle.photon_total(geo, ref), rtol=1e-6)
+
+
+@pytest.mark.parametrize("n_side,groups", [(9, 1), (11, 2), (7, 3)])
+def test_fp32c_ragged_sizes(n_side, groups):
+    """The compensated-FP32 tile transport and union gradient at 1-3 groups on
+    lattices whose last tile is partial (729, 1331 and 343 particles), with
+    sources, against the oracle."""
+    w = workloads.lattice_workload(n_side, groups, 2, 3, seed=920 + n_side, name="ragged32")
+    log(f"case fp32c ragged lattice{n_side} G={groups} n={w.n}")
+    geo = oracle.build_geometry(w.x)
+    srcs = oracle.build_sources(geo, w.xs)
+    ref, _ = oracle.run(geo, srcs, w.U0, w.L, 3)
+    got, Q, _, _ = run32(w, 3)
+    per = report(f"fp32c ragged lattice{n_side} G={groups} 3 steps", got, ref)
+    assert per.max() <= TOL32
+    assert np.allclose(Q, oracle.photon_total(geo, ref), rtol=1e-6)

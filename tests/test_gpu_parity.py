@@ -175,7 +175,7 @@ def test_plummer_mid():
     assert np.array_equal(run_gpu(rt, p, w, 2)[0], got_U)
 
 
-@pytest.mark.parametrize("n_side,groups", [(7, 2), (9, 1), (11, 4)])
+@pytest.mark.parametrize("n_side,groups", [(7, 2), (9, 1), (11, 4), (13, 3)])
 def test_ragged_sizes(n_side, groups):
     w = workloads.lattice_workload(n_side, groups, 2, 3, seed=900 + n_side, name="ragged")
     log(f"case ragged lattice{n_side} G={groups} n={w.n}")
