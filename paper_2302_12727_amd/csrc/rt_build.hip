@@ -598,6 +598,72 @@ __global__ void k_src_gas(int32_t S, Tree T, const double *__restrict__ xs, int6
     }
 }
 
+// Second pass of the task lists: lower the tile's longest list, which sets
+// how long the tile's block runs, by augmenting paths.  A particle k with the
+// longest list (L entries) passes one of the pairs it evaluates, (k, l), to l;
+// if l's list is not at least 2 shorter than L, l passes one of its own on,
+// and so on along a breadth-first path (lowest indices first) that ends at a
+// particle with at most L - 2 entries: k's list shrinks by one, the end's
+// grows by one, the others keep their length.  Repeated while some particle
+// with the longest list has such a path; each move lowers the sum of the
+// squared lengths, so the loop ends.  On the lattices this reaches the lower
+// bound, the larger of the longest list of neighbours outside the tile and
+// the mean, in all but a few tiles.  One wave (lane = particle of the tile); cnt[k]:
+// particle k's list length, bit l of own[k]: k evaluates the pair (k, l).
+__device__ void level_tasks(bool active, int lane, int32_t *cnt, uint64_t *own) {
+    __shared__ int32_t prev[64];
+    for (int guard = 0; guard < 64 * 64; ++guard) {
+        const int32_t c = active ? cnt[lane] : -1;
+        int32_t top = c;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) top = max(top, __shfl_xor(top, o, 64));
+        uint64_t tops = __ballot(active && c == top);
+        bool moved = false;
+        while (tops && !moved) {
+            const int v = __ffsll((unsigned long long)tops) - 1;
+            tops &= tops - 1;
+            uint64_t visited = uint64_t(1) << v, frontier = visited;
+            int found = -1;
+            while (frontier && found < 0) {
+                // each lane not yet reached finds the lowest particle of the
+                // frontier that can pass it a pair
+                int pu = -1;
+                if (!((visited >> lane) & 1)) {
+                    for (uint64_t f = frontier; f; f &= f - 1) {
+                        const int u = __ffsll((unsigned long long)f) - 1;
+                        if ((own[u] >> lane) & 1) {
+                            pu = u;
+                            break;
+                        }
+                    }
+                }
+                if (pu >= 0) prev[lane] = pu;
+                const uint64_t disc = __ballot(pu >= 0);
+                const uint64_t good = __ballot(pu >= 0 && c <= top - 2);
+                if (good) found = __ffsll((unsigned long long)good) - 1;
+                visited |= disc;
+                frontier = disc;
+            }
+            if (found >= 0) {
+                __syncthreads();
+                if (lane == 0) {
+                    for (int w = found; w != v;) {
+                        const int u = prev[w];
+                        own[u] &= ~(uint64_t(1) << w);
+                        own[w] |= uint64_t(1) << u;
+                        w = u;
+                    }
+                    --cnt[v];
+                    ++cnt[found];
+                }
+                __syncthreads();
+                moved = true;
+            }
+        }
+        if (!moved) break;
+    }
+}
+
 // Task lists of the tile transport (k_transport64_tile): particle i's
 // neighbours outside its tile (kTile consecutive particles within its
 // 64-particle column block of the neighbour table) and, flagged by the sign
@@ -607,11 +673,13 @@ __global__ void k_src_gas(int32_t S, Tree T, const double *__restrict__ xs, int6
 // iterations of a pass: one wave per tile starts from each particle's count
 // of neighbours outside the tile and gives the tile's pairs, in a fixed order
 // (by the lower index, then by its list order), one by one to the particle
-// with the shorter list so far (the lower index on ties).  On the 64^3
-// lattice this takes the wave iterations of the transport to 0.75 of the
-// two-sided kernel's (0.82 with a fixed rule by index parity).  Same slots as
-// the neighbour table, in table order; n_task[i] entries.  Launched with one
-// wave (64 threads) per tile.
+// with the shorter list so far (the lower index on ties); level_tasks then
+// lowers the tile's longest list.  On the 32^3 lattice the greedy pass takes
+// the mean wave iterations of the transport to 0.75 of the two-sided
+// kernel's (0.82 with a fixed rule by index parity) and the longest list of a
+// tile, which sets its block's time, to 0.81; the leveling takes them to 0.70
+// and 0.69.  Same slots as the neighbour table, in table order; n_task[i]
+// entries.  Launched with one wave (64 threads) per tile.
 __global__ __launch_bounds__(64) void k_tasks(int64_t n, const int64_t *__restrict__ wave_base,
                                               const int32_t *__restrict__ n_nbr,
                                               const int32_t *__restrict__ nbr,
@@ -653,6 +721,7 @@ __global__ __launch_bounds__(64) void k_tasks(int64_t n, const int64_t *__restri
         }
         __syncthreads();
     }
+    level_tasks(active, lane, cnt, own);
     if (!active) return;
     const uint64_t mine = own[lane];
     int32_t c = 0;
