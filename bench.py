@@ -562,9 +562,14 @@ def main():
                      # 'alu' is the binding roofline at the algorithmic counts
                      # (flop/byte above the ridge); what the counters show
                      # holding the kernel back is the neighbour lines' load path
-                     "limiter": "the load path of the neighbour lines (rocprofv3 counters: "
-                                "texture-data path 86% busy, 31% of wave cycles waiting): "
-                                "the SIMDs are about half VALU-busy",
+                     "limiter": ("the load path of the neighbour lines (rocprofv3 counters: "
+                                 "texture-data path 85% busy, 29% of wave cycles waiting): "
+                                 "the SIMDs are about half VALU-busy"
+                                 if args.precision == "fp64" else
+                                 "the load path of the neighbour lines and VALU issue "
+                                 "(rocprofv3 counters: texture-data path 86% busy, VALU "
+                                 "issue 83% of the kernel at the FP64 rate, packed FP32 "
+                                 "being off)"),
                      "target_frac": 0.5, "target_met": bool(achieved / peak >= 0.5)},
         "kernel_ms": {"transport": fw["transport_ms"], "gradient": fw["gradient_ms"],
                       "inject": fw["inject_ms"]},

@@ -676,9 +676,9 @@ __device__ void level_tasks(bool active, int lane, int32_t *cnt, uint64_t *own) 
 // with the shorter list so far (the lower index on ties); level_tasks then
 // lowers the tile's longest list.  On the 32^3 lattice the greedy pass takes
 // the mean wave iterations of the transport to 0.75 of the two-sided
-// kernel's (0.82 with a fixed rule by index parity) and the longest list of a
-// tile, which sets its block's time, to 0.81; the leveling takes them to 0.70
-// and 0.69.  Same slots as the neighbour table, in table order; n_task[i]
+// kernel's (a fixed rule by index parity took them to 0.82 on the 64^3
+// lattice) and the longest list of a tile, which sets its block's time, to
+// 0.81; the leveling takes them to 0.70 and 0.69.  Same slots as the neighbour table, in table order; n_task[i]
 // entries.  Launched with one wave (64 threads) per tile.
 __global__ __launch_bounds__(64) void k_tasks(int64_t n, const int64_t *__restrict__ wave_base,
                                               const int32_t *__restrict__ n_nbr,

@@ -25,10 +25,11 @@ COPY_BYTES = 1 << 30
 
 
 def transport_sources(precision: str):
-    """Source files that define the transport kernel of one precision."""
+    """Source files that define the transport kernel of one precision and what
+    it reads (the neighbour table and the tile task lists of rt_build.hip)."""
     d = os.path.join(HERE, "csrc")
     names = ["rt_step.hip", "rt_pair.h"] if precision == "fp64" else ["rt_step32.hip", "rt_pair32.h"]
-    return [os.path.join(d, f) for f in names + ["rt_internal.h"]]
+    return [os.path.join(d, f) for f in names + ["rt_internal.h", "rt_build.hip"]]
 
 
 def source_sha(*paths: str) -> str:
