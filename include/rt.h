@@ -382,6 +382,11 @@ typedef struct {
                                whose adjoint transposed gradient reads the
                                union of their symmetric lists from LDS          */
     int64_t adj_union_staged_blocks; /* those whose union did not fit           */
+    int64_t task_longest;      /* tile transports: the longest task list of each
+                               64-particle tile, summed over the tiles          */
+    int64_t task_bound;        /* its lower bound in each tile (the longest list
+                               of neighbours outside the tile, or the mean list
+                               length rounded up), summed over the tiles        */
 } rt_stats;
 rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out /* [host] */);
 

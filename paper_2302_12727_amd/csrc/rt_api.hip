@@ -127,7 +127,7 @@ void rt_destroy(rt_ctx *ctx) {
                     ctx->inj_gas, ctx->inj_src, ctx->inj_coef, ctx->inj_xi, ctx->src_ptr,
                     ctx->src_gas, ctx->src_coef, ctx->status, ctx->partials, ctx->scan_tmp,
                     ctx->adj_buf, ctx->hll_table, ctx->hll_table32, ctx->vol, ctx->ivan,
-                    ctx->bin8, ctx->task, ctx->n_task, ctx->uoff, ctx->urow, ctx->gloc,
+                    ctx->bin8, ctx->task, ctx->n_task, ctx->tstat, ctx->uoff, ctx->urow, ctx->gloc,
                     ctx->uown, ctx->ublk, ctx->goff, ctx->aoff, ctx->arow, ctx->agloc,
                     ctx->aown, ctx->ablk};
     for (void *b : bufs) rt_free(ctx, b);
@@ -369,6 +369,13 @@ rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out) {
     out->union_staged_blocks = ctx->uoff ? ctx->n_ublk : 0;
     out->adj_union_blocks = ctx->aoff ? ctx->nwaves - ctx->n_ablk : 0;
     out->adj_union_staged_blocks = ctx->aoff ? ctx->n_ablk : 0;
+    if (ctx->tstat) {
+        int64_t t[2];
+        RT_HIP(hipStreamSynchronize(ctx->stream));
+        RT_HIP(hipMemcpy(t, ctx->tstat, sizeof t, hipMemcpyDeviceToHost));
+        out->task_longest = t[0];
+        out->task_bound = t[1];
+    }
     return RT_OK;
 }
 

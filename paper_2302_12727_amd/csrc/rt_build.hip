@@ -684,7 +684,8 @@ __global__ __launch_bounds__(64) void k_tasks(int64_t n, const int64_t *__restri
                                               const int32_t *__restrict__ n_nbr,
                                               const int32_t *__restrict__ nbr,
                                               int32_t *__restrict__ task,
-                                              int32_t *__restrict__ n_task) {
+                                              int32_t *__restrict__ n_task,
+                                              int64_t *__restrict__ tstat) {
     __shared__ int32_t cnt[64];
     __shared__ uint64_t own[64];     // bit l of own[k]: particle k evaluates pair (k, l)
     const int lane = threadIdx.x;
@@ -722,6 +723,23 @@ __global__ __launch_bounds__(64) void k_tasks(int64_t n, const int64_t *__restri
         __syncthreads();
     }
     level_tasks(active, lane, cnt, own);
+    {
+        // the tile's longest list and its lower bound: the longest list of
+        // neighbours outside the tile, or the mean length rounded up
+        int32_t lm = active ? cnt[lane] : 0, om = out, sm = lm, na = active ? 1 : 0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lm = max(lm, __shfl_xor(lm, o, 64));
+            om = max(om, __shfl_xor(om, o, 64));
+            sm += __shfl_xor(sm, o, 64);
+            na += __shfl_xor(na, o, 64);
+        }
+        if (lane == 0 && na > 0) {
+            atomicAdd((unsigned long long *)&tstat[0], (unsigned long long)lm);
+            atomicAdd((unsigned long long *)&tstat[1],
+                      (unsigned long long)max(om, (sm + na - 1) / na));
+        }
+    }
     if (!active) return;
     const uint64_t mine = own[lane];
     int32_t c = 0;
@@ -927,7 +945,7 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     rt_free(ctx, ctx->keys); rt_free(ctx, ctx->h_iters); rt_free(ctx, ctx->node_lo); rt_free(ctx, ctx->node_hi);
     rt_free(ctx, ctx->node_hmax); rt_free(ctx, ctx->n_nbr); rt_free(ctx, ctx->n_gath); rt_free(ctx, ctx->wave_base);
     rt_free(ctx, ctx->nbr); rt_free(ctx, ctx->vol); rt_free(ctx, ctx->ivan);
-    rt_free(ctx, ctx->task); rt_free(ctx, ctx->n_task);
+    rt_free(ctx, ctx->task); rt_free(ctx, ctx->n_task); rt_free(ctx, ctx->tstat);
     rt_free(ctx, ctx->uoff); rt_free(ctx, ctx->urow); rt_free(ctx, ctx->gloc);
     rt_free(ctx, ctx->uown); rt_free(ctx, ctx->ublk); rt_free(ctx, ctx->goff);
     rt_free(ctx, ctx->aoff); rt_free(ctx, ctx->arow); rt_free(ctx, ctx->agloc);
@@ -941,6 +959,7 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     ctx->ivan = nullptr;
     ctx->task = nullptr;
     ctx->n_task = nullptr;
+    ctx->tstat = nullptr;
     ctx->xs = nullptr; ctx->geo = nullptr; ctx->geo32 = nullptr; ctx->perm32 = nullptr;
     ctx->keys = nullptr; ctx->h_iters = nullptr; ctx->node_lo = nullptr; ctx->node_hi = nullptr;
     ctx->node_hmax = nullptr; ctx->n_nbr = nullptr; ctx->n_gath = nullptr;
@@ -1087,8 +1106,10 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
             // task lists of the tile transports
             ALLOC(ctx->task, sizeof(int32_t) * std::max<int64_t>(ctx->slots, 1));
             ALLOC(ctx->n_task, sizeof(int32_t) * n);
+            ALLOC(ctx->tstat, 2 * sizeof(int64_t));
+            RT_HIP(hipMemsetAsync(ctx->tstat, 0, 2 * sizeof(int64_t), st));
             k_tasks<<<(unsigned)ctx->nwaves, 64, 0, st>>>(n, ctx->wave_base, ctx->n_nbr, ctx->nbr,
-                                                          ctx->task, ctx->n_task);
+                                                          ctx->task, ctx->n_task, ctx->tstat);
         }
         {
             // neighbour unions of the gradient (gather lists): FP64 at the

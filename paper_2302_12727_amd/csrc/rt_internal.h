@@ -99,6 +99,7 @@ struct rt_ctx {
     int32_t *nbr = nullptr;      // [slots]
     int32_t *task = nullptr;     // [slots] task lists of the FP64 tile transport (same slots)
     int32_t *n_task = nullptr;   // [n]
+    int64_t *tstat = nullptr;    // [2] over the tiles: the longest task list, its lower bound
     // neighbour unions of the FP64 gradient (k_union): per block of 64
     // particles its sorted distinct gather neighbours and own particles
     int64_t *uoff = nullptr;     // [nwaves + 1] offsets into urow (no rows: staged gradient)

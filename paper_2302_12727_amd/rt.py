@@ -58,7 +58,8 @@ class rt_stats(ctypes.Structure):
                 ("n_inject", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("device_bytes_peak", ctypes.c_int64), ("h_list_overflow", ctypes.c_int64),
                 ("union_blocks", ctypes.c_int64), ("union_staged_blocks", ctypes.c_int64),
-                ("adj_union_blocks", ctypes.c_int64), ("adj_union_staged_blocks", ctypes.c_int64)]
+                ("adj_union_blocks", ctypes.c_int64), ("adj_union_staged_blocks", ctypes.c_int64),
+                ("task_longest", ctypes.c_int64), ("task_bound", ctypes.c_int64)]
 
 
 _lib = None
