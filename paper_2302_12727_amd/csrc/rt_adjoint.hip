@@ -42,6 +42,11 @@ constexpr int kAdjHllWaves = RT_ADJ_HLL_WAVES;
 #ifndef RT_ADJ_HLL_OWN
 #define RT_ADJ_HLL_OWN 1
 #endif
+// The HLL pair pass of up to 3 groups takes the tiles of the forward (the
+// adjoint of the tile transport); 0 keeps it two-sided.
+#ifndef RT_ADJ_TILE_HLL
+#define RT_ADJ_TILE_HLL 1
+#endif
 constexpr bool kAdjHllOwn = RT_ADJ_HLL_OWN != 0;
 
 template <int G>
@@ -322,19 +327,26 @@ void k_adj_pair64(
 //     limiter's choice (|d_l| <= |d_k|, same signs),
 // which is the exact adjoint of the forward's single evaluation.  After a
 // block barrier each particle's sums are its own plus the 4 waves' rows in a
-// fixed order, as in the forward.
-template <int G, int GW, bool OFF32>
+// fixed order, as in the forward.  HLL: the HLL solver's pull-back of
+// k_adj_pair64 (its flux is antisymmetric like GLF's, so the partner's share
+// is the same t_R and slope term); it keeps the particle's own state,
+// gradients and cotangent in LDS (OWNL), which the HLL pull-back's registers
+// need.
+template <int G, int GW, bool OFF32, bool HLL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void
 k_adj_pair64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                   const int32_t *__restrict__ task, const int64_t *__restrict__ wave_base,
                   const int32_t *__restrict__ n_task, const double *__restrict__ UD,
                   const double *__restrict__ lam2, const double *__restrict__ dtp, double c,
-                  double box, double *__restrict__ R) {
+                  double box, double *__restrict__ R, const double2 *__restrict__ hll) {
     static_assert(G % GW == 0, "group slices must tile the groups");
     constexpr int NS = G / GW, NQ = 4 * GW, MS = 16 * GW + 1;   // accumulator row, padded
     static_assert(kTile == 64 && kBlock == 256, "a block of 4 waves x 16 particles per tile");
     __shared__ double stage[kBlock / 64][64 * kStage];
     __shared__ double mir[kBlock / 64][kTile * MS];
+    constexpr bool OWNL = HLL;
+    constexpr int OS = 5 * NQ + 1;              // own row: U (NQ), D (3 NQ), lambda (NQ), pad
+    __shared__ double own[OWNL ? kTile * OS : 1];
     const int64_t bg = xcd_block(nb * NS);
     if (bg >= nb * NS) return;                  // whole block: no barrier is skipped
     const int64_t blk = bg / NS;
@@ -357,19 +369,40 @@ k_adj_pair64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
 
     const double *rk = geo + (int64_t)kRec * ic;
     const double dtVk = dt / rk[R_V];
-    double Ui[NQ], Di[NQ * 3], Li[NQ];
+    double Ui[OWNL ? 1 : NQ], Di[OWNL ? 1 : NQ * 3], Li[OWNL ? 1 : NQ];
+    double *orow = own + (OWNL ? pl * OS : 0);  // (OWNL) the particle's row
+    if constexpr (OWNL) {
+        // lane sub copies component sub of each group
 #pragma unroll
-    for (int g = 0; g < GW; ++g) {
-        const double *r = UD + (ic * G + g0 + g) * 16;
+        for (int g = 0; g < GW; ++g) {
+            const double *r = UD + (ic * G + g0 + g) * 16;
+            const int q = 4 * g + sub;
+            orow[q] = r[sub];
+            orow[NQ + 3 * q + 0] = r[4 + 3 * sub];
+            orow[NQ + 3 * q + 1] = r[5 + 3 * sub];
+            orow[NQ + 3 * q + 2] = r[6 + 3 * sub];
+            orow[4 * NQ + q] = lam2[(ic * G + g0 + g) * 4 + sub];
+        }
+        wave_lds_sync();
+    } else {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            Ui[4 * g + m] = r[m];
-            Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
-            Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
-            Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
-            Li[4 * g + m] = lam2[(ic * G + g0 + g) * 4 + m];
+        for (int g = 0; g < GW; ++g) {
+            const double *r = UD + (ic * G + g0 + g) * 16;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                Ui[4 * g + m] = r[m];
+                Di[3 * (4 * g + m) + 0] = r[4 + 3 * m];
+                Di[3 * (4 * g + m) + 1] = r[5 + 3 * m];
+                Di[3 * (4 * g + m) + 2] = r[6 + 3 * m];
+                Li[4 * g + m] = lam2[(ic * G + g0 + g) * 4 + m];
+            }
         }
     }
+    auto ui = [&](int q) -> double { if constexpr (OWNL) return orow[q]; else return Ui[q]; };
+    auto di = [&](int q, int a) -> double {
+        if constexpr (OWNL) return orow[NQ + 3 * q + a]; else return Di[3 * q + a];
+    };
+    auto li = [&](int q) -> double { if constexpr (OWNL) return orow[4 * NQ + q]; else return Li[q]; };
     double aU[NQ], aD[NQ * 3];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) aU[q] = aD[3 * q] = aD[3 * q + 1] = aD[3 * q + 2] = 0.0;
@@ -431,12 +464,12 @@ k_adj_pair64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const int q = 4 * g + m;
-                    const double dk = Di[3 * q] * pg.sx + Di[3 * q + 1] * pg.sy + Di[3 * q + 2] * pg.sz;
+                    const double dk = di(q, 0) * pg.sx + di(q, 1) * pg.sy + di(q, 2) * pg.sz;
                     const double dl = Rl[4 + 3 * m] * pg.sx + Rl[5 + 3 * m] * pg.sy + Rl[6 + 3 * m] * pg.sz;
                     const double mm = minmod(dk, dl);
                     slope_k[m] = (dk * dl > 0.0) && (fabs(dk) <= fabs(dl));
                     slope_l[m] = (dk * dl > 0.0) && (fabs(dl) <= fabs(dk));
-                    qLp[m] = qL[m] = Ui[q] + pg.fk * mm;
+                    qLp[m] = qL[m] = ui(q) + pg.fk * mm;
                     qRp[m] = qR[m] = Rl[m] - pg.fl * mm;
                 }
                 guard64(qL[0], qL[1], qL[2], qL[3], c);
@@ -444,14 +477,41 @@ k_adj_pair64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                 // cotangent of P_kl and its pull-back to the face states
                 double nu[4], tL[4], tR[4];
 #pragma unroll
-                for (int m = 0; m < 4; ++m) nu[m] = 0.5 * (dtVl * Ll[m] - dtVk * Li[4 * g + m]);
-                m1_flux64_vjp(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, nu, tL, nullptr);
-                m1_flux64_vjp(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, nu, tR, nullptr);
-                const double dis = c * pg.An;   // 2 * (c/2) |A| times nu = mu/2
+                for (int m = 0; m < 4; ++m) nu[m] = 0.5 * (dtVl * Ll[m] - dtVk * li(4 * g + m));
+                double S1 = 0.0, S2 = 0.0;   // HLL: m . F_L, m . F_R
+                m1_flux64_vjp(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, c, nu, tL,
+                              HLL ? &S1 : nullptr);
+                m1_flux64_vjp(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, c, nu, tR,
+                              HLL ? &S2 : nullptr);
+                if constexpr (HLL) {
+                    const double iAn = pg.An > 0.0 ? rcp64(pg.An) : 0.0;
+                    double loL, hiL, loR, hiR, w1, w2, w3;
+                    hll_speeds64(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, iAn, c, hll, loL,
+                                 hiL);
+                    hll_speeds64(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, iAn, c, hll, loR,
+                                 hiR);
+                    hll_weights(loL, hiL, loR, hiR, pg.An, w1, w2, w3);
+                    double S3 = 0.0;                       // m . (U_R - U_L)
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    tL[m] += dis * nu[m];
-                    tR[m] -= dis * nu[m];
+                    for (int m = 0; m < 4; ++m) {
+                        S3 += nu[m] * (qR[m] - qL[m]);
+                        tL[m] = 2.0 * (w1 * tL[m] - w3 * nu[m]);
+                        tR[m] = 2.0 * (w2 * tR[m] + w3 * nu[m]);
+                    }
+                    double gloL, ghiL, gloR, ghiR;
+                    hll_weights_vjp(loL, hiL, loR, hiR, pg.An, 2.0 * S1, 2.0 * S2, 2.0 * S3,
+                                    gloL, ghiL, gloR, ghiR);
+                    hll_speeds64_vjp(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, iAn, c, hll,
+                                     gloL, ghiL, tL);
+                    hll_speeds64_vjp(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, iAn, c, hll,
+                                     gloR, ghiR, tR);
+                } else {
+                    const double dis = c * pg.An;   // 2 * (c/2) |A| times nu = mu/2
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        tL[m] += dis * nu[m];
+                        tR[m] -= dis * nu[m];
+                    }
                 }
                 guard64_vjp(qLp, tL, c);
                 guard64_vjp(qRp, tR, c);
@@ -514,7 +574,7 @@ k_adj_pair64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int q = 4 * g + m;
-            o[m] = Li[q] + aU[q];
+            o[m] = li(q) + aU[q];
             o[4 + 3 * m + 0] = b00 * aD[3 * q] + b01 * aD[3 * q + 1] + b02 * aD[3 * q + 2];
             o[4 + 3 * m + 1] = b01 * aD[3 * q] + b11 * aD[3 * q + 1] + b12 * aD[3 * q + 2];
             o[4 + 3 * m + 2] = b02 * aD[3 * q] + b12 * aD[3 * q + 1] + b22 * aD[3 * q + 2];
@@ -845,17 +905,25 @@ void launch_adjoint64(rt_ctx *ctx, const double *UD, const double *Uung, const d
     const int64_t np = (n + kBlock / kAQ - 1) / (kBlock / kAQ);
     const double2 *tab = (const double2 *)ctx->hll_table;
     const bool iva = ctx->surfaces == RT_IVANOVA;
-    if (ctx->solver == RT_GLF && !iva && ctx->task) {
+    const bool hll_tile = RT_ADJ_TILE_HLL != 0 && ctx->solver == RT_HLL && G <= 3;
+    if ((ctx->solver == RT_GLF || hll_tile) && !iva && ctx->task) {
         // the adjoint of the tile transport (in-tile pairs once)
         const int64_t nt = (n + kTile - 1) / kTile;
-        if ((uint64_t)n * 128u * G < (uint64_t(1) << 32))
-            k_adj_pair64_tile<G, GW, true><<<(unsigned)xcd_grid(nt * (G / GW)), kBlock, 0, st>>>(
-                n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, lam2, dt,
-                ctx->p.c_red, ctx->p.box, R);
-        else
-            k_adj_pair64_tile<G, GW, false><<<(unsigned)xcd_grid(nt * (G / GW)), kBlock, 0, st>>>(
-                n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, lam2, dt,
-                ctx->p.c_red, ctx->p.box, R);
+        const bool off32 = (uint64_t)n * 128u * G < (uint64_t(1) << 32);
+#define RT_ADJ_TILE_LAUNCH(OFF32_, HLL_)                                                        \
+    k_adj_pair64_tile<G, GW, OFF32_, HLL_><<<(unsigned)xcd_grid(nt * (G / GW)), kBlock, 0, st>>>( \
+        n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, lam2, dt, ctx->p.c_red,     \
+        ctx->p.box, R, tab)
+        if (hll_tile) {
+            if constexpr (G <= 3) {
+                if (off32) RT_ADJ_TILE_LAUNCH(true, true);
+                else RT_ADJ_TILE_LAUNCH(false, true);
+            }
+        } else {
+            if (off32) RT_ADJ_TILE_LAUNCH(true, false);
+            else RT_ADJ_TILE_LAUNCH(false, false);
+        }
+#undef RT_ADJ_TILE_LAUNCH
     } else {
 #define RT_ADJ_PAIR_LAUNCH(HLL_, IVA_)                                                          \
     k_adj_pair64<G, GW, kAQ, HLL_, IVA_, (HLL_ && kAdjHllOwn)><<<(unsigned)xcd_grid(np * (G / GW)), kBlock, 0, st>>>( \

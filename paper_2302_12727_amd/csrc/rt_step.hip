@@ -919,7 +919,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 // XCD's working set spanned 4 times the particles and its L2 hit rate fell
 // from 92% to 38%.)
 
-template <int G, bool OFF32>
+template <int G, bool OFF32, bool HLL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                    const int32_t *__restrict__ task, const int64_t *__restrict__ wave_base,
@@ -927,7 +927,7 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                    const double *__restrict__ dtp, double c, double box,
                    double *__restrict__ Uout, double *__restrict__ partials,
                    unsigned long long *__restrict__ counts, double *__restrict__ Uung,
-                   int32_t *__restrict__ status) {
+                   int32_t *__restrict__ status, const double2 *__restrict__ hll) {
     constexpr int NQ = 4 * G, MS = NQ + 1;     // accumulator row, padded against bank conflicts
     __shared__ double stage[kBlock / 64][64 * kStage];
     static_assert(kTile == 64 && kBlock == 256, "a block of 4 waves x 16 particles per tile");
@@ -1014,6 +1014,7 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                 PairGeo pg;
                 pair_geometry64(rk, rl, box, ibox, pg);
                 const bool use = valid && pg.An > 0.0;
+                const double iAn = (HLL && pg.An > 0.0) ? rcp64(pg.An) : 0.0;
                 const int cnt2 = mirror ? 2 : 1;
                 const int mr = mirror ? (j - (int32_t)t0) * MS : 0;   // the partner's row
 #pragma unroll
@@ -1045,14 +1046,22 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                     double FAL, aL, bL, FAR, aR, bR;
                     const int f1 = face_m164(qL, pg.Ax, pg.Ay, pg.Az, c, c3, FAL, aL, bL);
                     const int f2 = face_m164(qR, pg.Ax, pg.Ay, pg.Az, c, c3, FAR, aR, bR);
-                    const double w3 = -hc * pg.An;
+                    double w1 = 0.5, w2 = 0.5, w3 = -hc * pg.An;   // GLF
+                    if constexpr (HLL) {
+                        double loL, hiL, loR, hiR;
+                        hll_speeds64(qL[0], qL[1], qL[2], qL[3], pg.Ax, pg.Ay, pg.Az, iAn, c, hll,
+                                     loL, hiL);
+                        hll_speeds64(qR[0], qR[1], qR[2], qR[3], pg.Ax, pg.Ay, pg.Az, iAn, c, hll,
+                                     loR, hiR);
+                        hll_weights(loL, hiL, loR, hiR, pg.An, w1, w2, w3);
+                    }
                     if (use) {
                         cE += cnt2 * ((f1 & 1) + (f2 & 1));
                         cF += cnt2 * ((f1 >> 1) + (f2 >> 1));
-                        const double al = __builtin_fma(0.5, aL, 0.5 * aR);
-                        const double bl = 0.5 * bL, br = 0.5 * bR;
+                        const double al = __builtin_fma(w1, aL, w2 * aR);
+                        const double bl = w1 * bL, br = w2 * bR;
                         double phi[4];
-                        phi[0] = __builtin_fma(w3, qR[0] - qL[0], __builtin_fma(0.5, FAL, 0.5 * FAR));
+                        phi[0] = __builtin_fma(w3, qR[0] - qL[0], __builtin_fma(w1, FAL, w2 * FAR));
                         const double Av[3] = {pg.Ax, pg.Ay, pg.Az};
 #pragma unroll
                         for (int m = 1; m < 4; ++m)
@@ -1302,8 +1311,14 @@ inline int64_t transport_rows(int64_t n) { return (n + kBlock / kQ - 1) / (kBloc
 #ifndef RT_TRANSPORT_TILE
 #define RT_TRANSPORT_TILE 1
 #endif
+// The HLL solver takes the tiles too (its flux is as antisymmetric as GLF's);
+// 0 keeps it two-sided.
+#ifndef RT_TRANSPORT_TILE_HLL
+#define RT_TRANSPORT_TILE_HLL 1
+#endif
 inline bool use_tile64(const rt_ctx *ctx) {
-    return RT_TRANSPORT_TILE != 0 && ctx->p.precision == RT_FP64 && ctx->solver == RT_GLF &&
+    return RT_TRANSPORT_TILE != 0 && ctx->p.precision == RT_FP64 &&
+           (ctx->solver == RT_GLF || (RT_TRANSPORT_TILE_HLL != 0 && ctx->solver == RT_HLL)) &&
            ctx->surfaces == RT_HOPKINS && ctx->p.groups <= 3 && ctx->task != nullptr;
 }
 // rows of block partials the FP64 transport writes (one per block)
@@ -1324,14 +1339,23 @@ void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double 
         if (use_tile64(ctx)) {
             const int64_t nt = transport64_rows(ctx);
             // rows addressed by 32-bit offsets while the gradient records fit 4 GiB
-            if ((uint64_t)n * 128u * G < (uint64_t(1) << 32))
-                k_transport64_tile<G, true><<<(unsigned)xcd_grid(nt), kBlock, 0, ctx->stream>>>(
-                    n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt, ctx->p.c_red,
-                    ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, ctx->status);
-            else
-                k_transport64_tile<G, false><<<(unsigned)xcd_grid(nt), kBlock, 0, ctx->stream>>>(
-                    n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt, ctx->p.c_red,
-                    ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, ctx->status);
+#define RT_TILE_LAUNCH(OFF32_, HLL_)                                                           \
+    k_transport64_tile<G, OFF32_, HLL_><<<(unsigned)xcd_grid(nt), kBlock, 0, ctx->stream>>>(     \
+        n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt, ctx->p.c_red,           \
+        ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, ctx->status, tab)
+            const bool off32 = (uint64_t)n * 128u * G < (uint64_t(1) << 32);
+            if (ctx->solver == RT_HLL) {
+                if (off32)
+                    RT_TILE_LAUNCH(true, true);
+                else
+                    RT_TILE_LAUNCH(false, true);
+            } else {
+                if (off32)
+                    RT_TILE_LAUNCH(true, false);
+                else
+                    RT_TILE_LAUNCH(false, false);
+            }
+#undef RT_TILE_LAUNCH
             return;
         }
     }
