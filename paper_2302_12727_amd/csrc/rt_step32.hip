@@ -18,6 +18,10 @@ using namespace gearrt;
 #ifndef RT_TRANSPORT32_TILE
 #define RT_TRANSPORT32_TILE 1
 #endif
+// The HLL solver takes the FP32C tiles too; 0 keeps it two-sided.
+#ifndef RT_TRANSPORT32_TILE_HLL
+#define RT_TRANSPORT32_TILE_HLL 1
+#endif
 
 namespace {
 
@@ -656,7 +660,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 // by the butterfly) plus the 4 waves' rows in a fixed order.  Each stage's
 // rows are in flight across the previous stage's evaluation, as in the
 // two-sided kernel.
-template <int G>
+template <int G, bool HLL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RT_TRANSPORT32_WAVES))) void
 k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
                    const double *__restrict__ geo, const int32_t *__restrict__ task,
@@ -664,7 +668,7 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
                    const float *__restrict__ UD, const double *__restrict__ dtp, double c,
                    double box, float *__restrict__ Uout, double *__restrict__ partials,
                    unsigned long long *__restrict__ counts, float *__restrict__ Uung,
-                   int32_t *__restrict__ status) {
+                   int32_t *__restrict__ status, const float2 *__restrict__ hll) {
     constexpr int NQ = 4 * G, MS = NQ + 1;      // accumulator row, padded against bank conflicts
     static_assert(kTile == 64 && kBlock == 256, "a block of 4 waves x 16 particles per tile");
     __shared__ float stage[kBlock / 64][64 * kStage32];
@@ -787,6 +791,7 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
             const float ih = rcp32(hk + hl);
             const float fk = hk * ih, fl = hl * ih;
             const bool use = valid && An > 0.0f;
+            const float iAn = (HLL && An > 0.0f) ? rcp32(An) : 0.0f;
             const int cnt2 = mirror ? 2 : 1;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
@@ -818,7 +823,15 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
                 }
                 const int f1 = guard32(qL[0], qL[1], qL[2], qL[3], cf);
                 const int f2 = guard32(qR[0], qR[1], qR[2], qR[3], cf);
-                const float w3 = -hc * An;      // GLF
+                float w1 = 0.5f, w2 = 0.5f, w3 = -hc * An;   // GLF
+                if constexpr (HLL) {
+                    float loL, hiL, loR, hiR;
+                    hll_speeds32(qL[0], qL[1], qL[2], qL[3], Ax, Ay, Az, iAn, cf, ic2, hll, loL,
+                                 hiL);
+                    hll_speeds32(qR[0], qR[1], qR[2], qR[3], Ax, Ay, Az, iAn, cf, ic2, hll, loR,
+                                 hiR);
+                    hll_weights32(loL, hiL, loR, hiR, An, w1, w2, w3);
+                }
                 float FL[4], FR[4];
                 m1_flux32(qL[0], qL[1], qL[2], qL[3], Ax, Ay, Az, c2, ic2, FL);
                 m1_flux32(qR[0], qR[1], qR[2], qR[3], Ax, Ay, Az, c2, ic2, FR);
@@ -827,7 +840,7 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
                     cF += cnt2 * ((f1 >> 1) + (f2 >> 1));
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
-                        const float phi = 0.5f * FL[m] + 0.5f * FR[m] + w3 * (qR[m] - qL[m]);
+                        const float phi = w1 * FL[m] + w2 * FR[m] + w3 * (qR[m] - qL[m]);
                         acc[4 * g + m].add(phi);
                         if (mirror) atomicAdd(mw + mr + 4 * g + m, -(double)phi);
                     }
@@ -986,14 +999,22 @@ void launch_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *U
     const float2 *tab = (const float2 *)ctx->hll_table32;
     const bool iva = ctx->surfaces == RT_IVANOVA;
     if constexpr (G <= 3) {
-        if (RT_TRANSPORT32_TILE != 0 && ctx->solver == RT_GLF && !iva && ctx->task) {
+        const bool hll = ctx->solver == RT_HLL;
+        if (RT_TRANSPORT32_TILE != 0 && (ctx->solver == RT_GLF || (RT_TRANSPORT32_TILE_HLL != 0 && hll)) &&
+            !iva && ctx->task) {
             // pair-once tiles: one block of 64 particles per tile, as many
             // blocks (and rows of partials) as the two-sided kernel
             static_assert(kBlock / kQ32 == kTile, "a tile per two-sided block");
-            k_transport32_tile<G><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(
-                n, nb, ctx->geo32, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt,
-                ctx->p.c_red, ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung,
-                ctx->status);
+#define RT_TILE32_LAUNCH(HLL_)                                                                  \
+    k_transport32_tile<G, HLL_><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(            \
+        n, nb, ctx->geo32, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt,            \
+        ctx->p.c_red, ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung,           \
+        ctx->status, tab)
+            if (hll)
+                RT_TILE32_LAUNCH(true);
+            else
+                RT_TILE32_LAUNCH(false);
+#undef RT_TILE32_LAUNCH
             return;
         }
     }
