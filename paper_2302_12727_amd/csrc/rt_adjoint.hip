@@ -47,6 +47,12 @@ constexpr int kAdjHllWaves = RT_ADJ_HLL_WAVES;
 #ifndef RT_ADJ_TILE_HLL
 #define RT_ADJ_TILE_HLL 1
 #endif
+// Waves per SIMD of the HLL tile pair pass: at 2 it spills 28 bytes outside
+// its inner loop; at 1 (no spill) the 20-step backward of the 3-group 128^3
+// lattice took 406 ms against 305.
+#ifndef RT_ADJ_TILE_HLL_WAVES
+#define RT_ADJ_TILE_HLL_WAVES 2
+#endif
 constexpr bool kAdjHllOwn = RT_ADJ_HLL_OWN != 0;
 
 template <int G>
@@ -333,7 +339,7 @@ void k_adj_pair64(
 // gradients and cotangent in LDS (OWNL), which the HLL pull-back's registers
 // need.
 template <int G, int GW, bool OFF32, bool HLL>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(HLL ? RT_ADJ_TILE_HLL_WAVES : 2))) void
 k_adj_pair64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                   const int32_t *__restrict__ task, const int64_t *__restrict__ wave_base,
                   const int32_t *__restrict__ n_task, const double *__restrict__ UD,
