@@ -6,9 +6,10 @@
 // Time bins: dt_i = dt 2^b_i (dt the smallest CFL step, as rt_build_cells
 // computes it), b_i the largest n <= max_bin with dt 2^n <= C_cfl dx_i / c,
 // then lowered until interacting particles are at most 2 bins apart.  The
-// bins live in slot 12 of the geometry records and the smallest bin of each
-// particle's neighbourhood in slot 13 (both 0 after rt_build_cells: the global
-// step).  A tick t advances the time by dt; particle i ends a step at the end
+// bins live in slot 12 of the geometry records, and with the smallest bin of
+// each particle's neighbourhood in bin8 (n bytes each; all 0 after
+// rt_build_cells: the global step).  Slots 13-15 of the records hold the
+// Ivanova kernel-gradient sums.  A tick t advances the time by dt; particle i ends a step at the end
 // of tick t when (t + 1) is a multiple of 2^b_i.
 #include "rt_internal.h"
 
@@ -50,9 +51,9 @@ __global__ void k_bins_limit(int64_t n, const int32_t *__restrict__ nbr,
     if (m != bin[i]) atomicOr(changed, 1);
 }
 
-// bins into the geometry records (slot 12) with the smallest bin of the
-// neighbourhood (slot 13), and into the FP32 records (slot F_BIN) of FP32C
-// contexts
+// bins into the geometry records (slot 12), into bin8 with the smallest bin of
+// each neighbourhood (bin8[n + i]), and into the FP32 records (slot F_BIN) of
+// FP32C contexts
 __global__ void k_bins_store(int64_t n, const int32_t *__restrict__ nbr,
                              const int64_t *__restrict__ wave_base,
                              const int32_t *__restrict__ n_nbr, const int32_t *__restrict__ bin,
@@ -65,9 +66,9 @@ __global__ void k_bins_store(int64_t n, const int32_t *__restrict__ nbr,
     const int32_t nn = n_nbr[i];
     for (int32_t k = 0; k < nn; ++k) m = min(m, bin[nbr[base + 64 * (int64_t)k]]);
     geo[(int64_t)kRec * i + 12] = (double)bin[i];
-    geo[(int64_t)kRec * i + 13] = (double)m;
     if (geo32) geo32[(int64_t)F_REC * i + F_BIN] = (float)bin[i];
     bin8[i] = (uint8_t)bin[i];
+    bin8[n + i] = (uint8_t)m;
 }
 
 __global__ void k_bins_max(int64_t n, const int32_t *__restrict__ bin, int32_t *__restrict__ top) {
@@ -141,7 +142,7 @@ rt_status rt_time_bins_impl(rt_ctx *ctx, int32_t max_bin, int32_t *bins_out, int
         b2 = tmp;
         ++sweeps;
     }
-    if (!ctx->bin8 && (rs = rt_alloc(ctx, (void **)&ctx->bin8, (size_t)n)) != RT_OK) {
+    if (!ctx->bin8 && (rs = rt_alloc(ctx, (void **)&ctx->bin8, 2 * (size_t)n)) != RT_OK) {
         rt_free(ctx, work);
         return rs;
     }

@@ -1187,7 +1187,7 @@ rt_status rt_build_impl(rt_ctx *ctx, const double *x, const double *h_in, int64_
     ctx->built = 1;
     if (ctx->surfaces == RT_IVANOVA && (rs = rt_ivanova_impl(ctx)) != RT_OK) return rs;
     ctx->bin_top = -1;   // the records were rewritten with all time bins 0
-    if (ctx->bin8) RT_HIP(hipMemsetAsync(ctx->bin8, 0, (size_t)n, st));
+    if (ctx->bin8) RT_HIP(hipMemsetAsync(ctx->bin8, 0, 2 * (size_t)n, st));
     return RT_OK;
 fail:
     // the conditions of the build are reported by its return code, not by a

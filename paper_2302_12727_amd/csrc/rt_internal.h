@@ -153,7 +153,8 @@ struct rt_ctx {
     int32_t h_iter_max = 0;
     int32_t h_iter_cap = 200;    // iteration cap of the smoothing-length solve
     int32_t bin_top = -1;        // largest time bin after rt_time_bins (-1: none)
-    uint8_t *bin8 = nullptr;     // [n] time bins as set by rt_time_bins (0 after a build)
+    uint8_t *bin8 = nullptr;     // [2n] time bins as set by rt_time_bins, then the smallest
+                                 // bin of each particle's neighbourhood (0 after a build)
     int32_t solver = RT_GLF;     // Riemann solver of the transport
     double *hll_table = nullptr; // [RT_HLL_NF][RT_HLL_NMU][2] wave speeds / c
     float *hll_table32 = nullptr;// the same in FP32 (FP32C contexts)

@@ -9,9 +9,10 @@ namespace {
 
 // g_i = sum_k grad W_k(x_i) over the gather neighbours of i (r_ik < H_i),
 // grad W_k(x_i) = (sigma / H_i^4) w'(r_ik / H_i) (x_i - x_k) / r_ik, written
-// to ivan[i][0..2] (ivan[i][3] = 0).
+// to ivan[i][0..2] (ivan[i][3] = 0) and to slots 13-15 of the geometry record,
+// where the FP64 transports find a neighbour's with the rest of its record.
 __global__ __launch_bounds__(kBlock) void k_ivanova_sums(
-    int64_t n, const double *__restrict__ geo, const double *__restrict__ xs,
+    int64_t n, double *__restrict__ geo, const double *__restrict__ xs,
     const int32_t *__restrict__ nbr, const int64_t *__restrict__ wave_base,
     const int32_t *__restrict__ n_gath, double box, double *__restrict__ ivan) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -41,6 +42,10 @@ __global__ __launch_bounds__(kBlock) void k_ivanova_sums(
     o[1] = gy;
     o[2] = gz;
     o[3] = 0.0;
+    double *r = geo + (int64_t)kRec * i;
+    r[13] = gx;
+    r[14] = gy;
+    r[15] = gz;
 }
 
 }  // namespace

@@ -566,7 +566,7 @@ k_gradient64u(int64_t n, int64_t nb, const double *__restrict__ geo, const doubl
 //
 // BIN: one tick of the individual-time-step scheme (time bins in slot 12 of
 // the geometry records, the smallest bin of each particle's neighbourhood in
-// slot 13): only pairs whose smaller bin ends a step in this tick contribute,
+// binm): only pairs whose smaller bin ends a step in this tick contribute,
 // each with dt 2^min(b_k, b_l); the sums go to the pending flux sums accm, and
 // the particles that end a step apply and clear theirs (Part III
 // eq:transport-update-explicit with min{dt_k, dt_l}).
@@ -582,7 +582,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     double *__restrict__ Uout, double *__restrict__ partials,
     unsigned long long *__restrict__ counts, double *__restrict__ Uung,
     int32_t *__restrict__ status, int64_t tick = 0, double *__restrict__ accm = nullptr,
-    const double2 *__restrict__ hll = nullptr, const double *__restrict__ ivan = nullptr) {
+    const double2 *__restrict__ hll = nullptr, const uint8_t *__restrict__ binm = nullptr) {
     static_assert(G % GW == 0, "group slices must tile the groups");
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     constexpr int NS = G / GW, NQ = 4 * G;
@@ -645,18 +645,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
     for (int q = 0; q < 4 * GW; ++q) acc[q] = 0.0;
     int cE = 0, cF = 0;
-    double gk[3] = {0.0, 0.0, 0.0};   // IVA: own kernel-gradient sum
+    double gk[3] = {0.0, 0.0, 0.0};   // IVA: own kernel-gradient sum (record slots 13-15)
     if (IVA) {
-        gk[0] = ivan[4 * ic];
-        gk[1] = ivan[4 * ic + 1];
-        gk[2] = ivan[4 * ic + 2];
+        gk[0] = rk[13];
+        gk[1] = rk[14];
+        gk[2] = rk[15];
     }
     // time bins: this particle ends a step in this tick (ends), or some pair of
-    // its neighbourhood does (touched)
+    // its neighbourhood does (touched); binm: the smallest bin of each
+    // neighbourhood (none before rt_time_bins: every bin is 0)
     const int64_t t1 = tick + 1;
     const int32_t bk = BIN ? (int32_t)rk[12] : 0;
     const bool ends = !BIN || (t1 & ((int64_t(1) << bk) - 1)) == 0;
-    const bool touched = !BIN || (t1 & ((int64_t(1) << (int32_t)rk[13]) - 1)) == 0;
+    const int32_t bm = (BIN && binm) ? (int32_t)binm[ic] : 0;
+    const bool touched = !BIN || (t1 & ((int64_t(1) << bm) - 1)) == 0;
 
     if (wave_live) {
         const int64_t base = wave_base[w] + (i & 63);
@@ -713,14 +715,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             double rl[12];
 #pragma unroll
             for (int q = 0; q < 12; ++q) rl[q] = sb[lane * kStage + q];
-            // the neighbour's time bin (slot 12 of its record), read before the
-            // Ivanova staging reuses the buffer
+            // the neighbour's time bin (slot 12 of its record)
             const int32_t bl = BIN ? (int32_t)sb[lane * kStage + 12] : 0;
             PairGeo pg;
             if (IVA) {
-                stage_rows4(ivan, 4, j, sb, lane);
-                const double gl[3] = {sb[lane * kStage], sb[lane * kStage + 1],
-                                      sb[lane * kStage + 2]};
+                // its kernel-gradient sum: slots 13-15 of the same record
+                const double gl[3] = {sb[lane * kStage + 13], sb[lane * kStage + 14],
+                                      sb[lane * kStage + 15]};
                 pair_geometry_ivanova64(rk, rl, gk, gl, box, ibox, pg);
             } else {
                 pair_geometry64(rk, rl, box, ibox, pg);
@@ -1365,7 +1366,7 @@ void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double 
         <<<(unsigned)xcd_grid(nb * (G / W)), kBlock, 0, ctx->stream>>>(                       \
         n, nb, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,          \
         ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, ctx->status, 0,       \
-        nullptr, tab, ctx->ivan)
+        nullptr, tab, nullptr)
     if (ctx->solver == RT_HLL) {
         if (iva) RT_TRANSPORT_LAUNCH(HW, true, true);
         else RT_TRANSPORT_LAUNCH(HW, true, false);
@@ -1433,7 +1434,7 @@ void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, d
         <<<(unsigned)xcd_grid(nt * (G / W)), kBlock, 0, ctx->stream>>>(                        \
             n, nt, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,       \
             ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, ctx->status,    \
-            tick, accm, tab, ctx->ivan)
+            tick, accm, tab, ctx->bin8 ? ctx->bin8 + n : nullptr)
     if (ctx->solver == RT_HLL) {
         if (iva) RT_TICK_LAUNCH(HW, true, true);
         else RT_TICK_LAUNCH(HW, true, false);

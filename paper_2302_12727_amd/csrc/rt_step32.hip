@@ -302,7 +302,8 @@ k_gradient32u(int64_t n, int64_t nb, const float *__restrict__ geo32, const doub
 // separation from the FP64 positions as for the Hopkins surfaces.
 //
 // BIN: one tick of the individual-time-step scheme, as in the FP64 transport
-// (bins from the FP64 records' slots 12 and 13 and the FP32 records' F_BIN;
+// (bins from the FP64 records' slot 12, the neighbourhoods' smallest from
+// binm, and the FP32 records' F_BIN;
 // each due pair's exchange weighted by dt 2^min(b_k, b_l) in the compensated
 // sums; pending sums accm in FP64).
 template <int G, bool HLL = false, int Q = 1, bool IVA = false, bool BIN = false>
@@ -315,7 +316,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     double *__restrict__ partials, unsigned long long *__restrict__ counts,
     float *__restrict__ Uung, int32_t *__restrict__ status,
     const float2 *__restrict__ hll = nullptr, const double *__restrict__ ivan = nullptr,
-    int64_t tick = 0, double *__restrict__ accm = nullptr) {
+    int64_t tick = 0, double *__restrict__ accm = nullptr,
+    const uint8_t *__restrict__ binm = nullptr) {
     static_assert(Q == 1 || Q == 2 || Q == 4, "lanes per particle: 1, 2 or 4");
     // PIPE: the next stage's rows in flight during each evaluation (GLF; the
     // HLL instantiation has no registers left for them)
@@ -374,8 +376,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     const int64_t t1 = tick + 1;
     const int32_t bk = BIN ? (int32_t)geo[(int64_t)kRec * ic + 12] : 0;
     const bool ends = !BIN || (t1 & ((int64_t(1) << bk) - 1)) == 0;
-    const bool touched =
-        !BIN || (t1 & ((int64_t(1) << (int32_t)geo[(int64_t)kRec * ic + 13]) - 1)) == 0;
+    const int32_t bm = (BIN && binm) ? (int32_t)binm[ic] : 0;
+    const bool touched = !BIN || (t1 & ((int64_t(1) << bm) - 1)) == 0;
 
     if (wave_live) {
         const int64_t base = wave_base[w] + (i & 63);
@@ -1048,7 +1050,7 @@ void launch_tick32(rt_ctx *ctx, float *U, float *UD, const double *dt, double *p
     k_transport32<G, HLL_, kQ32, IVA_, true><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>( \
         n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt,             \
         ctx->p.c_red, ctx->p.box, U, partials, (unsigned long long *)counts, nullptr,          \
-        ctx->status, tab, ctx->ivan, tick, accm)
+        ctx->status, tab, ctx->ivan, tick, accm, ctx->bin8 ? ctx->bin8 + n : nullptr)
     if (ctx->solver == RT_HLL) {
         if (iva) RT_TICK32_LAUNCH(true, true);
         else RT_TICK32_LAUNCH(true, false);
