@@ -920,7 +920,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 // XCD's working set spanned 4 times the particles and its L2 hit rate fell
 // from 92% to 38%.)
 
-template <int G, bool OFF32, bool HLL>
+template <int G, bool OFF32, bool HLL, bool IVA>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                    const int32_t *__restrict__ task, const int64_t *__restrict__ wave_base,
@@ -965,6 +965,8 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
             const double *rk = geo + (int64_t)kRec * ic;
+            // IVA: the kernel-gradient sums, slots 13-15 of the records
+            const double gk[3] = {IVA ? rk[13] : 0.0, IVA ? rk[14] : 0.0, IVA ? rk[15] : 0.0};
             double Ui[NQ];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
@@ -1013,7 +1015,13 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
 #pragma unroll
                 for (int q = 0; q < 12; ++q) rl[q] = sb[lane * kStage + q];
                 PairGeo pg;
-                pair_geometry64(rk, rl, box, ibox, pg);
+                if constexpr (IVA) {
+                    const double gl[3] = {sb[lane * kStage + 13], sb[lane * kStage + 14],
+                                          sb[lane * kStage + 15]};
+                    pair_geometry_ivanova64(rk, rl, gk, gl, box, ibox, pg);
+                } else {
+                    pair_geometry64(rk, rl, box, ibox, pg);
+                }
                 const bool use = valid && pg.An > 0.0;
                 const double iAn = (HLL && pg.An > 0.0) ? rcp64(pg.An) : 0.0;
                 const int cnt2 = mirror ? 2 : 1;
@@ -1317,10 +1325,18 @@ inline int64_t transport_rows(int64_t n) { return (n + kBlock / kQ - 1) / (kBloc
 #ifndef RT_TRANSPORT_TILE_HLL
 #define RT_TRANSPORT_TILE_HLL 1
 #endif
+// The Ivanova surfaces too (antisymmetric as well, A_lk = -A_kl; the
+// kernel-gradient sums come with the geometry records); 0 keeps them
+// two-sided.
+#ifndef RT_TRANSPORT_TILE_IVA
+#define RT_TRANSPORT_TILE_IVA 1
+#endif
 inline bool use_tile64(const rt_ctx *ctx) {
     return RT_TRANSPORT_TILE != 0 && ctx->p.precision == RT_FP64 &&
            (ctx->solver == RT_GLF || (RT_TRANSPORT_TILE_HLL != 0 && ctx->solver == RT_HLL)) &&
-           ctx->surfaces == RT_HOPKINS && ctx->p.groups <= 3 && ctx->task != nullptr;
+           (ctx->surfaces == RT_HOPKINS ||
+            (RT_TRANSPORT_TILE_IVA != 0 && ctx->surfaces == RT_IVANOVA)) &&
+           ctx->p.groups <= 3 && ctx->task != nullptr;
 }
 // rows of block partials the FP64 transport writes (one per block)
 inline int64_t transport64_rows(const rt_ctx *ctx) {
@@ -1340,22 +1356,24 @@ void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double 
         if (use_tile64(ctx)) {
             const int64_t nt = transport64_rows(ctx);
             // rows addressed by 32-bit offsets while the gradient records fit 4 GiB
-#define RT_TILE_LAUNCH(OFF32_, HLL_)                                                           \
-    k_transport64_tile<G, OFF32_, HLL_><<<(unsigned)xcd_grid(nt), kBlock, 0, ctx->stream>>>(     \
+#define RT_TILE_LAUNCH(OFF32_, HLL_, IVA_)                                                     \
+    k_transport64_tile<G, OFF32_, HLL_, IVA_><<<(unsigned)xcd_grid(nt), kBlock, 0, ctx->stream>>>( \
         n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt, ctx->p.c_red,           \
         ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, ctx->status, tab)
+#define RT_TILE_LAUNCH_S(HLL_, IVA_)                                                           \
+    do {                                                                                       \
+        if (off32) RT_TILE_LAUNCH(true, HLL_, IVA_);                                           \
+        else RT_TILE_LAUNCH(false, HLL_, IVA_);                                                \
+    } while (0)
             const bool off32 = (uint64_t)n * 128u * G < (uint64_t(1) << 32);
             if (ctx->solver == RT_HLL) {
-                if (off32)
-                    RT_TILE_LAUNCH(true, true);
-                else
-                    RT_TILE_LAUNCH(false, true);
+                if (iva) RT_TILE_LAUNCH_S(true, true);
+                else RT_TILE_LAUNCH_S(true, false);
             } else {
-                if (off32)
-                    RT_TILE_LAUNCH(true, false);
-                else
-                    RT_TILE_LAUNCH(false, false);
+                if (iva) RT_TILE_LAUNCH_S(false, true);
+                else RT_TILE_LAUNCH_S(false, false);
             }
+#undef RT_TILE_LAUNCH_S
 #undef RT_TILE_LAUNCH
             return;
         }
