@@ -319,7 +319,9 @@ void k_adj_pair64(
 }
 
 // Pass B with the pairs inside a tile evaluated once: the adjoint of the tile
-// transport (GLF, Hopkins surfaces).  A block owns one 64-particle tile and
+// transport (GLF or HLL, Hopkins surfaces; with the Ivanova surfaces the
+// two-sided pass serves the tile forward, whose flux it differentiates up to
+// rounding).  A block owns one 64-particle tile and
 // GW of the groups; its particles walk the forward's task lists (k_tasks), in
 // which an in-tile pair (k, l) appears once, flagged, in one particle's list.
 // That lane pulls the pair back for both particles: its own cotangents as in

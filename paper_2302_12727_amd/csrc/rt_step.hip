@@ -899,8 +899,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     }
 }
 
-// Transport with the pairs inside a tile evaluated once (FP64, GLF, Hopkins
-// surfaces, one global step, all G <= 3 groups in one wave).
+// Transport with the pairs inside a tile evaluated once (FP64, GLF or HLL,
+// Hopkins or Ivanova surfaces, one global step, all G <= 3 groups in one
+// wave).  Both solvers' pair fluxes and both surfaces are antisymmetric, so
+// one evaluation serves both particles of a pair.
 //
 // A block owns one tile: the 64 consecutive Morton particles of one column
 // block of the neighbour table, 16 per wave with 4 lanes each (the layout, and

@@ -13,7 +13,7 @@ using namespace gearrt;
 #ifndef RT_TRANSPORT32_WAVES
 #define RT_TRANSPORT32_WAVES 3
 #endif
-// 1: the GLF FP32C transport with Hopkins surfaces evaluates in-tile pairs
+// 1: the FP32C transport with Hopkins surfaces evaluates in-tile pairs
 // once (k_transport32_tile); 0: always two-sided.
 #ifndef RT_TRANSPORT32_TILE
 #define RT_TRANSPORT32_TILE 1
@@ -652,8 +652,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     }
 }
 
-// FP32C transport with the pairs inside a tile evaluated once (GLF, Hopkins
-// surfaces, one global step, up to 3 groups): the tile scheme of the FP64
+// FP32C transport with the pairs inside a tile evaluated once (GLF or HLL,
+// Hopkins surfaces, one global step, up to 3 groups): the tile scheme of the FP64
 // transport (k_transport64_tile, the same task lists) with the FP32 pair
 // arithmetic of k_transport32.  The lane that evaluates an in-tile pair adds
 // Phi_kl to its own compensated sums and -Phi_kl, in FP64 by an LDS atomic
