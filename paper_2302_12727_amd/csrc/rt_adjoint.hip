@@ -47,6 +47,10 @@ constexpr int kAdjHllWaves = RT_ADJ_HLL_WAVES;
 #ifndef RT_ADJ_TILE_HLL
 #define RT_ADJ_TILE_HLL 1
 #endif
+// ... and with the Ivanova surfaces; 0 keeps those two-sided.
+#ifndef RT_ADJ_TILE_IVA
+#define RT_ADJ_TILE_IVA 1
+#endif
 // Waves per SIMD of the HLL tile pair pass: at 2 it spills 28 bytes outside
 // its inner loop; at 1 (no spill) the 20-step backward of the 3-group 128^3
 // lattice took 406 ms against 305.
@@ -319,9 +323,7 @@ void k_adj_pair64(
 }
 
 // Pass B with the pairs inside a tile evaluated once: the adjoint of the tile
-// transport (GLF or HLL, Hopkins surfaces; with the Ivanova surfaces the
-// two-sided pass serves the tile forward, whose flux it differentiates up to
-// rounding).  A block owns one 64-particle tile and
+// transport (GLF or HLL, Hopkins or Ivanova surfaces).  A block owns one 64-particle tile and
 // GW of the groups; its particles walk the forward's task lists (k_tasks), in
 // which an in-tile pair (k, l) appears once, flagged, in one particle's list.
 // That lane pulls the pair back for both particles: its own cotangents as in
@@ -339,8 +341,10 @@ void k_adj_pair64(
 // k_adj_pair64 (its flux is antisymmetric like GLF's, so the partner's share
 // is the same t_R and slope term); it keeps the particle's own state,
 // gradients and cotangent in LDS (OWNL), which the HLL pull-back's registers
-// need.
-template <int G, int GW, bool OFF32, bool HLL>
+// need.  IVA: the Ivanova surfaces (static, so only the recomputed pair
+// geometry changes), with the kernel-gradient sums from slots 13-15 of the
+// geometry records, and the own values in LDS as for HLL.
+template <int G, int GW, bool OFF32, bool HLL, bool IVA>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(HLL ? RT_ADJ_TILE_HLL_WAVES : 2))) void
 k_adj_pair64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                   const int32_t *__restrict__ task, const int64_t *__restrict__ wave_base,
@@ -352,7 +356,7 @@ k_adj_pair64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
     static_assert(kTile == 64 && kBlock == 256, "a block of 4 waves x 16 particles per tile");
     __shared__ double stage[kBlock / 64][64 * kStage];
     __shared__ double mir[kBlock / 64][kTile * MS];
-    constexpr bool OWNL = HLL;
+    constexpr bool OWNL = HLL || IVA;
     constexpr int OS = 5 * NQ + 1;              // own row: U (NQ), D (3 NQ), lambda (NQ), pad
     __shared__ double own[OWNL ? kTile * OS : 1];
     const int64_t bg = xcd_block(nb * NS);
@@ -377,6 +381,7 @@ k_adj_pair64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
 
     const double *rk = geo + (int64_t)kRec * ic;
     const double dtVk = dt / rk[R_V];
+    const double gk[3] = {IVA ? rk[13] : 0.0, IVA ? rk[14] : 0.0, IVA ? rk[15] : 0.0};
     double Ui[OWNL ? 1 : NQ], Di[OWNL ? 1 : NQ * 3], Li[OWNL ? 1 : NQ];
     double *orow = own + (OWNL ? pl * OS : 0);  // (OWNL) the particle's row
     if constexpr (OWNL) {
@@ -449,7 +454,13 @@ k_adj_pair64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
 #pragma unroll
             for (int q = 0; q < 12; ++q) rl[q] = sb[lane * kStage + q];
             PairGeo pg;
-            pair_geometry64(rk, rl, box, ibox, pg);
+            if constexpr (IVA) {
+                const double gl[3] = {sb[lane * kStage + 13], sb[lane * kStage + 14],
+                                      sb[lane * kStage + 15]};
+                pair_geometry_ivanova64(rk, rl, gk, gl, box, ibox, pg);
+            } else {
+                pair_geometry64(rk, rl, box, ibox, pg);
+            }
             const bool use = valid && pg.An > 0.0;
             const double dtVl = dt * rcp64(rl[R_V]);   // (about 1 ulp; no IEEE division per pair)
 #pragma unroll
@@ -914,23 +925,31 @@ void launch_adjoint64(rt_ctx *ctx, const double *UD, const double *Uung, const d
     const double2 *tab = (const double2 *)ctx->hll_table;
     const bool iva = ctx->surfaces == RT_IVANOVA;
     const bool hll_tile = RT_ADJ_TILE_HLL != 0 && ctx->solver == RT_HLL && G <= 3;
-    if ((ctx->solver == RT_GLF || hll_tile) && !iva && ctx->task) {
+    const bool iva_tile = RT_ADJ_TILE_IVA != 0 && iva && G <= 3;
+    if ((ctx->solver == RT_GLF || hll_tile) && (!iva || iva_tile) && ctx->task) {
         // the adjoint of the tile transport (in-tile pairs once)
         const int64_t nt = (n + kTile - 1) / kTile;
         const bool off32 = (uint64_t)n * 128u * G < (uint64_t(1) << 32);
-#define RT_ADJ_TILE_LAUNCH(OFF32_, HLL_)                                                        \
-    k_adj_pair64_tile<G, GW, OFF32_, HLL_><<<(unsigned)xcd_grid(nt * (G / GW)), kBlock, 0, st>>>( \
-        n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, lam2, dt, ctx->p.c_red,     \
-        ctx->p.box, R, tab)
-        if (hll_tile) {
+#define RT_ADJ_TILE_LAUNCH(OFF32_, HLL_, IVA_)                                                  \
+    k_adj_pair64_tile<G, GW, OFF32_, HLL_, IVA_>                                                \
+        <<<(unsigned)xcd_grid(nt * (G / GW)), kBlock, 0, st>>>(                                 \
+            n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, lam2, dt,              \
+            ctx->p.c_red, ctx->p.box, R, tab)
+#define RT_ADJ_TILE_LAUNCH_S(HLL_, IVA_)                                                        \
+    do {                                                                                        \
+        if (off32) RT_ADJ_TILE_LAUNCH(true, HLL_, IVA_);                                        \
+        else RT_ADJ_TILE_LAUNCH(false, HLL_, IVA_);                                             \
+    } while (0)
+        if (hll_tile || iva_tile) {
             if constexpr (G <= 3) {
-                if (off32) RT_ADJ_TILE_LAUNCH(true, true);
-                else RT_ADJ_TILE_LAUNCH(false, true);
+                if (hll_tile && iva_tile) RT_ADJ_TILE_LAUNCH_S(true, true);
+                else if (hll_tile) RT_ADJ_TILE_LAUNCH_S(true, false);
+                else RT_ADJ_TILE_LAUNCH_S(false, true);
             }
         } else {
-            if (off32) RT_ADJ_TILE_LAUNCH(true, false);
-            else RT_ADJ_TILE_LAUNCH(false, false);
+            RT_ADJ_TILE_LAUNCH_S(false, false);
         }
+#undef RT_ADJ_TILE_LAUNCH_S
 #undef RT_ADJ_TILE_LAUNCH
     } else {
 #define RT_ADJ_PAIR_LAUNCH(HLL_, IVA_)                                                          \
