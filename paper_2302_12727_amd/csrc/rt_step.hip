@@ -922,7 +922,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 // XCD's working set spanned 4 times the particles and its L2 hit rate fell
 // from 92% to 38%.)
 
-template <int G, bool OFF32, bool HLL, bool IVA>
+//
+// BIN: one tick of the individual-time-step scheme on the tiles.  A pair is
+// due when its smaller bin ends a step in this tick, a symmetric condition,
+// and its flux weighted by dt 2^min(b_k, b_l) is antisymmetric as before; a
+// particle none of whose pairs is due (binm) walks no list.  The particles
+// that do not end a step add their sums to the pending sums accm, the others
+// apply theirs, as in the two-sided binned kernel.
+template <int G, bool OFF32, bool HLL, bool IVA, bool BIN>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                    const int32_t *__restrict__ task, const int64_t *__restrict__ wave_base,
@@ -930,7 +937,9 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                    const double *__restrict__ dtp, double c, double box,
                    double *__restrict__ Uout, double *__restrict__ partials,
                    unsigned long long *__restrict__ counts, double *__restrict__ Uung,
-                   int32_t *__restrict__ status, const double2 *__restrict__ hll) {
+                   int32_t *__restrict__ status, const double2 *__restrict__ hll,
+                   int64_t tick = 0, double *__restrict__ accm = nullptr,
+                   const uint8_t *__restrict__ binm = nullptr) {
     constexpr int NQ = 4 * G, MS = NQ + 1;     // accumulator row, padded against bank conflicts
     __shared__ double stage[kBlock / 64][64 * kStage];
     static_assert(kTile == 64 && kBlock == 256, "a block of 4 waves x 16 particles per tile");
@@ -956,13 +965,25 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    // BIN: this particle ends a step in this tick (ends), or some pair of its
+    // neighbourhood is due (touched)
+    const int64_t t1 = tick + 1;
+    int32_t bk = 0;
+    bool ends = true, touched = true;
+    if constexpr (BIN) {
+        const int64_t icb = t0 + pl < n ? t0 + pl : n - 1;
+        bk = (int32_t)geo[(int64_t)kRec * icb + 12];
+        const int32_t bm = binm ? (int32_t)binm[icb] : 0;
+        ends = (t1 & ((int64_t(1) << bk) - 1)) == 0;
+        touched = (t1 & ((int64_t(1) << bm) - 1)) == 0;
+    }
     if (wave_live) {
         const int64_t wb = wave_base[blk];
         {
             const int64_t i = t0 + pl;
             const bool active = i < n;
             const int64_t ic = active ? i : n - 1;
-            const int32_t nn = active ? n_task[i] : 0;
+            const int32_t nn = (active && touched) ? n_task[i] : 0;
             int32_t kmax = nn;                      // the longest list of the pass
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
@@ -1024,7 +1045,14 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                 } else {
                     pair_geometry64(rk, rl, box, ibox, pg);
                 }
-                const bool use = valid && pg.An > 0.0;
+                bool use = valid && pg.An > 0.0;
+                double wkl = 1.0;                   // BIN: time integration of the exchange
+                if constexpr (BIN) {
+                    const int32_t bl = (int32_t)sb[lane * kStage + 12];
+                    const int32_t bmin = bk < bl ? bk : bl;
+                    use = use && (t1 & ((int64_t(1) << bmin) - 1)) == 0;
+                    wkl = ldexp(dtp[0], bmin);
+                }
                 const double iAn = (HLL && pg.An > 0.0) ? rcp64(pg.An) : 0.0;
                 const int cnt2 = mirror ? 2 : 1;
                 const int mr = mirror ? (j - (int32_t)t0) * MS : 0;   // the partner's row
@@ -1079,6 +1107,10 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
                             phi[m] = __builtin_fma(w3, qR[m] - qL[m],
                                                    __builtin_fma(al, Av[m - 1],
                                                                  __builtin_fma(bl, qL[m], br * qR[m])));
+                        if constexpr (BIN) {
+#pragma unroll
+                            for (int m = 0; m < 4; ++m) phi[m] *= wkl;
+                        }
 #pragma unroll
                         for (int m = 0; m < 4; ++m) acc[4 * g + m] += phi[m];
                         if (mirror) {
@@ -1106,13 +1138,42 @@ k_transport64_tile(int64_t n, int64_t nb, const double *__restrict__ geo,
     double red[2 * G];
     int gE = 0, gF = 0;
     double chk = 0.0;   // NaN iff an updated state is NaN or infinite
-    if (owner) {
+    if (BIN && owner && !ends) {
+        // no update in this tick: keep the pending sums, count the current state
         const double V = geo[(int64_t)kRec * i + R_V];
-        const double dtV = dtp[0] / V;
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
 #pragma unroll
             for (int v = 0; v < kBlock / 64; ++v) acc[q] += mir[v][pl * MS + q];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (touched) {
+                double *a = accm + (i * G + g) * 4;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) a[m] += acc[4 * g + m];
+            }
+            red[g] = V * UD[(i * G + g) * 16];
+            red[G + g] = 0.0;
+        }
+    } else if (owner) {
+        const double V = geo[(int64_t)kRec * i + R_V];
+        // the update: U - dt/V sum (global step), or U - (pending + this tick)/V
+        const double dtV = BIN ? 1.0 / V : dtp[0] / V;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int v = 0; v < kBlock / 64; ++v) acc[q] += mir[v][pl * MS + q];
+        if constexpr (BIN) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                double *a = accm + (i * G + g) * 4;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    acc[4 * g + m] += a[m];
+                    a[m] = 0.0;
+                }
+            }
+        }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const double *u = UD + (i * G + g) * 16;
@@ -1333,6 +1394,11 @@ inline int64_t transport_rows(int64_t n) { return (n + kBlock / kQ - 1) / (kBloc
 #ifndef RT_TRANSPORT_TILE_IVA
 #define RT_TRANSPORT_TILE_IVA 1
 #endif
+// The ticks of the individual time steps on the tiles too (a due pair's
+// weighted flux is antisymmetric); 0 keeps them two-sided.
+#ifndef RT_TICK_TILE
+#define RT_TICK_TILE 1
+#endif
 inline bool use_tile64(const rt_ctx *ctx) {
     return RT_TRANSPORT_TILE != 0 && ctx->p.precision == RT_FP64 &&
            (ctx->solver == RT_GLF || (RT_TRANSPORT_TILE_HLL != 0 && ctx->solver == RT_HLL)) &&
@@ -1359,7 +1425,7 @@ void launch_transport64(rt_ctx *ctx, const double *UD, const double *dt, double 
             const int64_t nt = transport64_rows(ctx);
             // rows addressed by 32-bit offsets while the gradient records fit 4 GiB
 #define RT_TILE_LAUNCH(OFF32_, HLL_, IVA_)                                                     \
-    k_transport64_tile<G, OFF32_, HLL_, IVA_><<<(unsigned)xcd_grid(nt), kBlock, 0, ctx->stream>>>( \
+    k_transport64_tile<G, OFF32_, HLL_, IVA_, false><<<(unsigned)xcd_grid(nt), kBlock, 0, ctx->stream>>>( \
         n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt, ctx->p.c_red,           \
         ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung, ctx->status, tab)
 #define RT_TILE_LAUNCH_S(HLL_, IVA_)                                                           \
@@ -1448,13 +1514,43 @@ void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, d
     const int64_t nt = transport_rows(n);
     const double2 *tab = (const double2 *)ctx->hll_table;
     const bool iva = ctx->surfaces == RT_IVANOVA;
+    const uint8_t *binm = ctx->bin8 ? ctx->bin8 + n : nullptr;
+    if constexpr (G <= 3) {
+        if (RT_TICK_TILE != 0 && use_tile64(ctx)) {
+            // the tiles in their time-bin mode (one row of partials per tile,
+            // as many as the two-sided kernel's blocks)
+            static_assert(kBlock / kQ == kTile, "a tile per two-sided block");
+            const bool off32 = (uint64_t)n * 128u * G < (uint64_t(1) << 32);
+#define RT_TICK_TILE_LAUNCH(OFF32_, HLL_, IVA_)                                                 \
+    k_transport64_tile<G, OFF32_, HLL_, IVA_, true>                                             \
+        <<<(unsigned)xcd_grid(nt), kBlock, 0, ctx->stream>>>(                                   \
+            n, nt, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt, ctx->p.c_red,      \
+            ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, ctx->status,     \
+            tab, tick, accm, binm)
+#define RT_TICK_TILE_S(HLL_, IVA_)                                                              \
+    do {                                                                                        \
+        if (off32) RT_TICK_TILE_LAUNCH(true, HLL_, IVA_);                                       \
+        else RT_TICK_TILE_LAUNCH(false, HLL_, IVA_);                                            \
+    } while (0)
+            if (ctx->solver == RT_HLL) {
+                if (iva) RT_TICK_TILE_S(true, true);
+                else RT_TICK_TILE_S(true, false);
+            } else {
+                if (iva) RT_TICK_TILE_S(false, true);
+                else RT_TICK_TILE_S(false, false);
+            }
+#undef RT_TICK_TILE_S
+#undef RT_TICK_TILE_LAUNCH
+            return;
+        }
+    }
 #define RT_TICK_LAUNCH(W, HLL_, IVA_)                                                          \
     k_transport64<G, W, true, HLL_, IVA_, kQ, own_lds(HLL_, IVA_, W),                         \
                   pipe_on(HLL_, IVA_, W)>                                                     \
         <<<(unsigned)xcd_grid(nt * (G / W)), kBlock, 0, ctx->stream>>>(                        \
             n, nt, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt, ctx->p.c_red,       \
             ctx->p.box, Uout, partials, (unsigned long long *)counts, nullptr, ctx->status,    \
-            tick, accm, tab, ctx->bin8 ? ctx->bin8 + n : nullptr)
+            tick, accm, tab, binm)
     if (ctx->solver == RT_HLL) {
         if (iva) RT_TICK_LAUNCH(HW, true, true);
         else RT_TICK_LAUNCH(HW, true, false);
