@@ -22,6 +22,10 @@ using namespace gearrt;
 #ifndef RT_TRANSPORT32_TILE_HLL
 #define RT_TRANSPORT32_TILE_HLL 1
 #endif
+// The time-bin ticks too; 0 keeps them two-sided.
+#ifndef RT_TICK32_TILE
+#define RT_TICK32_TILE 1
+#endif
 
 namespace {
 
@@ -662,7 +666,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 // by the butterfly) plus the 4 waves' rows in a fixed order.  Each stage's
 // rows are in flight across the previous stage's evaluation, as in the
 // two-sided kernel.
-template <int G, bool HLL>
+// BIN: one tick of the individual-time-step scheme on the tiles, as in the
+// FP64 tile kernel (due pairs weighted by dt 2^min(b_k, b_l) in the
+// compensated sums, pending sums accm in FP64).
+template <int G, bool HLL, bool BIN>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RT_TRANSPORT32_WAVES))) void
 k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
                    const double *__restrict__ geo, const int32_t *__restrict__ task,
@@ -670,7 +677,9 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
                    const float *__restrict__ UD, const double *__restrict__ dtp, double c,
                    double box, float *__restrict__ Uout, double *__restrict__ partials,
                    unsigned long long *__restrict__ counts, float *__restrict__ Uung,
-                   int32_t *__restrict__ status, const float2 *__restrict__ hll) {
+                   int32_t *__restrict__ status, const float2 *__restrict__ hll,
+                   int64_t tick = 0, double *__restrict__ accm = nullptr,
+                   const uint8_t *__restrict__ binm = nullptr) {
     constexpr int NQ = 4 * G, MS = NQ + 1;      // accumulator row, padded against bank conflicts
     static_assert(kTile == 64 && kBlock == 256, "a block of 4 waves x 16 particles per tile");
     __shared__ float stage[kBlock / 64][64 * kStage32];
@@ -726,9 +735,20 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q].s = acc[q].c = 0.0f;
     int cE = 0, cF = 0;
+    // BIN: this particle ends a step in this tick (ends), or some pair of its
+    // neighbourhood is due (touched)
+    const int64_t t1 = tick + 1;
+    int32_t bk = 0;
+    bool ends = true, touched = true;
+    if constexpr (BIN) {
+        bk = (int32_t)geo[(int64_t)kRec * ic + 12];
+        const int32_t bm = binm ? (int32_t)binm[ic] : 0;
+        ends = (t1 & ((int64_t(1) << bk) - 1)) == 0;
+        touched = (t1 & ((int64_t(1) << bm) - 1)) == 0;
+    }
     if (wave_live) {
         const int64_t base = wave_base[blk] + pl;   // the particle's column in the table
-        const int32_t nn = active ? n_task[i] : 0;
+        const int32_t nn = (active && touched) ? n_task[i] : 0;
         int32_t kmax = nn;                          // the longest list of the wave
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o, 64));
@@ -792,7 +812,14 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
             const float hl = rl[F_H];
             const float ih = rcp32(hk + hl);
             const float fk = hk * ih, fl = hl * ih;
-            const bool use = valid && An > 0.0f;
+            bool use = valid && An > 0.0f;
+            float wkl = 1.0f;                       // BIN: time integration of the exchange
+            if constexpr (BIN) {
+                const int32_t bl = (int32_t)rl[F_BIN];
+                const int32_t bmin = bk < bl ? bk : bl;
+                use = use && (t1 & ((int64_t(1) << bmin) - 1)) == 0;
+                wkl = (float)ldexp(dtp[0], bmin);
+            }
             const float iAn = (HLL && An > 0.0f) ? rcp32(An) : 0.0f;
             const int cnt2 = mirror ? 2 : 1;
 #pragma unroll
@@ -842,7 +869,8 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
                     cF += cnt2 * ((f1 >> 1) + (f2 >> 1));
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
-                        const float phi = w1 * FL[m] + w2 * FR[m] + w3 * (qR[m] - qL[m]);
+                        const float phi = BIN ? wkl * (w1 * FL[m] + w2 * FR[m] + w3 * (qR[m] - qL[m]))
+                                              : w1 * FL[m] + w2 * FR[m] + w3 * (qR[m] - qL[m]);
                         acc[4 * g + m].add(phi);
                         if (mirror) atomicAdd(mw + mr + 4 * g + m, -(double)phi);
                     }
@@ -863,13 +891,42 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
     double red[2 * G];
     int gE = 0, gF = 0;
     float chk = 0.0f;   // NaN iff an updated state is NaN or infinite
-    if (owner) {
+    if (BIN && owner && !ends) {
+        // no update in this tick: keep the pending sums, count the current state
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
 #pragma unroll
             for (int v = 0; v < kBlock / 64; ++v) av[q] += mir[v][pl * MS + q];
         const double V = geo[(int64_t)kRec * i + R_V];
-        const double dtV = dtp[0] / V;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (touched) {
+                double *a = accm + (i * G + g) * 4;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) a[m] += av[4 * g + m];
+            }
+            red[g] = V * (double)Ui[4 * g];
+            red[G + g] = 0.0;
+        }
+    } else if (owner) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int v = 0; v < kBlock / 64; ++v) av[q] += mir[v][pl * MS + q];
+        const double V = geo[(int64_t)kRec * i + R_V];
+        // the update: U - dt/V sum (global step), or U - (pending + this tick)/V
+        const double dtV = BIN ? 1.0 / V : dtp[0] / V;
+        if constexpr (BIN) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                double *a = accm + (i * G + g) * 4;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    av[4 * g + m] += a[m];
+                    a[m] = 0.0;
+                }
+            }
+        }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             double q0 = (double)Ui[4 * g + 0] - dtV * av[4 * g + 0];
@@ -1008,7 +1065,7 @@ void launch_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *U
             // blocks (and rows of partials) as the two-sided kernel
             static_assert(kBlock / kQ32 == kTile, "a tile per two-sided block");
 #define RT_TILE32_LAUNCH(HLL_)                                                                  \
-    k_transport32_tile<G, HLL_><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(            \
+    k_transport32_tile<G, HLL_, false><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(     \
         n, nb, ctx->geo32, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt,            \
         ctx->p.c_red, ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung,           \
         ctx->status, tab)
@@ -1046,11 +1103,31 @@ void launch_tick32(rt_ctx *ctx, float *U, float *UD, const double *dt, double *p
     const int64_t nb = rt_transport32_rows(n);
     const float2 *tab = (const float2 *)ctx->hll_table32;
     const bool iva = ctx->surfaces == RT_IVANOVA;
+    const uint8_t *binm = ctx->bin8 ? ctx->bin8 + n : nullptr;
+    if constexpr (G <= 3) {
+        const bool hll = ctx->solver == RT_HLL;
+        if (RT_TICK32_TILE != 0 && RT_TRANSPORT32_TILE != 0 &&
+            (ctx->solver == RT_GLF || (RT_TRANSPORT32_TILE_HLL != 0 && hll)) && !iva && ctx->task) {
+            // the tiles in their time-bin mode (one row of partials per tile)
+            static_assert(kBlock / kQ32 == kTile, "a tile per two-sided block");
+#define RT_TICK32_TILE_LAUNCH(HLL_)                                                             \
+    k_transport32_tile<G, HLL_, true><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(      \
+        n, nb, ctx->geo32, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt,            \
+        ctx->p.c_red, ctx->p.box, U, partials, (unsigned long long *)counts, nullptr,           \
+        ctx->status, tab, tick, accm, binm)
+            if (hll)
+                RT_TICK32_TILE_LAUNCH(true);
+            else
+                RT_TICK32_TILE_LAUNCH(false);
+#undef RT_TICK32_TILE_LAUNCH
+            return;
+        }
+    }
 #define RT_TICK32_LAUNCH(HLL_, IVA_)                                                           \
     k_transport32<G, HLL_, kQ32, IVA_, true><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>( \
         n, nb, ctx->geo32, ctx->geo, ctx->nbr, ctx->wave_base, ctx->n_nbr, UD, dt,             \
         ctx->p.c_red, ctx->p.box, U, partials, (unsigned long long *)counts, nullptr,          \
-        ctx->status, tab, ctx->ivan, tick, accm, ctx->bin8 ? ctx->bin8 + n : nullptr)
+        ctx->status, tab, ctx->ivan, tick, accm, binm)
     if (ctx->solver == RT_HLL) {
         if (iva) RT_TICK32_LAUNCH(true, true);
         else RT_TICK32_LAUNCH(true, false);
