@@ -26,6 +26,10 @@ using namespace gearrt;
 #ifndef RT_TICK32_TILE
 #define RT_TICK32_TILE 1
 #endif
+// The Ivanova surfaces too; 0 keeps them two-sided.
+#ifndef RT_TRANSPORT32_TILE_IVA
+#define RT_TRANSPORT32_TILE_IVA 1
+#endif
 
 namespace {
 
@@ -668,8 +672,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 // two-sided kernel.
 // BIN: one tick of the individual-time-step scheme on the tiles, as in the
 // FP64 tile kernel (due pairs weighted by dt 2^min(b_k, b_l) in the
-// compensated sums, pending sums accm in FP64).
-template <int G, bool HLL, bool BIN>
+// compensated sums, pending sums accm in FP64).  IVA: the Ivanova surfaces
+// as in k_transport32, each neighbour's kernel-gradient sum read from ivan.
+template <int G, bool HLL, bool BIN, bool IVA>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RT_TRANSPORT32_WAVES))) void
 k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
                    const double *__restrict__ geo, const int32_t *__restrict__ task,
@@ -679,7 +684,8 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
                    unsigned long long *__restrict__ counts, float *__restrict__ Uung,
                    int32_t *__restrict__ status, const float2 *__restrict__ hll,
                    int64_t tick = 0, double *__restrict__ accm = nullptr,
-                   const uint8_t *__restrict__ binm = nullptr) {
+                   const uint8_t *__restrict__ binm = nullptr,
+                   const double *__restrict__ ivan = nullptr) {
     constexpr int NQ = 4 * G, MS = NQ + 1;      // accumulator row, padded against bank conflicts
     static_assert(kTile == 64 && kBlock == 256, "a block of 4 waves x 16 particles per tile");
     __shared__ float stage[kBlock / 64][64 * kStage32];
@@ -711,6 +717,12 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
     const double *xk = reinterpret_cast<const double *>(rk);
     const double pkx = xk[0], pky = xk[1], pkz = xk[2];
     const float iHk = rk[F_IH], hk = rk[F_H];
+    float gk[3] = {0.0f, 0.0f, 0.0f};   // IVA: own kernel-gradient sum
+    if constexpr (IVA) {
+        gk[0] = (float)ivan[4 * ic];
+        gk[1] = (float)ivan[4 * ic + 1];
+        gk[2] = (float)ivan[4 * ic + 2];
+    }
     float Bk[6];
 #pragma unroll
     for (int a = 0; a < 6; ++a) Bk[a] = rk[F_B + a];
@@ -797,17 +809,25 @@ k_transport32_tile(int64_t n, int64_t nb, const float *__restrict__ geo32,
             const float sy = (float)min_image(xl[1] - pky, box, ibox);
             const float sz = (float)min_image(xl[2] - pkz, box, ibox);
             const float r = sqrt32(sx * sx + sy * sy + sz * sz);
-            const float wk = kern_wf(r * iHk);
-            const float wl = kern_wf(r * rl[F_IH]);
-            const float m00 = wk * Bk[0] + wl * rl[F_B + 0];
-            const float m01 = wk * Bk[1] + wl * rl[F_B + 1];
-            const float m02 = wk * Bk[2] + wl * rl[F_B + 2];
-            const float m11 = wk * Bk[3] + wl * rl[F_B + 3];
-            const float m12 = wk * Bk[4] + wl * rl[F_B + 4];
-            const float m22 = wk * Bk[5] + wl * rl[F_B + 5];
-            const float Ax = m00 * sx + m01 * sy + m02 * sz;
-            const float Ay = m01 * sx + m11 * sy + m12 * sz;
-            const float Az = m02 * sx + m12 * sy + m22 * sz;
+            float Ax, Ay, Az;
+            if constexpr (IVA) {
+                const double *gd = ivan + 4 * (int64_t)j;
+                const float gl[3] = {(float)gd[0], (float)gd[1], (float)gd[2]};
+                ivanova_surface32(sx, sy, sz, r, iHk, rk[F_V], gk, rl[F_IH], rl[F_V], gl, Ax, Ay,
+                                  Az);
+            } else {
+                const float wk = kern_wf(r * iHk);
+                const float wl = kern_wf(r * rl[F_IH]);
+                const float m00 = wk * Bk[0] + wl * rl[F_B + 0];
+                const float m01 = wk * Bk[1] + wl * rl[F_B + 1];
+                const float m02 = wk * Bk[2] + wl * rl[F_B + 2];
+                const float m11 = wk * Bk[3] + wl * rl[F_B + 3];
+                const float m12 = wk * Bk[4] + wl * rl[F_B + 4];
+                const float m22 = wk * Bk[5] + wl * rl[F_B + 5];
+                Ax = m00 * sx + m01 * sy + m02 * sz;
+                Ay = m01 * sx + m11 * sy + m12 * sz;
+                Az = m02 * sx + m12 * sy + m22 * sz;
+            }
             const float An = sqrt32(Ax * Ax + Ay * Ay + Az * Az);
             const float hl = rl[F_H];
             const float ih = rcp32(hk + hl);
@@ -1060,19 +1080,22 @@ void launch_transport32(rt_ctx *ctx, const float *UD, const double *dt, float *U
     if constexpr (G <= 3) {
         const bool hll = ctx->solver == RT_HLL;
         if (RT_TRANSPORT32_TILE != 0 && (ctx->solver == RT_GLF || (RT_TRANSPORT32_TILE_HLL != 0 && hll)) &&
-            !iva && ctx->task) {
+            (!iva || RT_TRANSPORT32_TILE_IVA != 0) && ctx->task) {
             // pair-once tiles: one block of 64 particles per tile, as many
             // blocks (and rows of partials) as the two-sided kernel
             static_assert(kBlock / kQ32 == kTile, "a tile per two-sided block");
-#define RT_TILE32_LAUNCH(HLL_)                                                                  \
-    k_transport32_tile<G, HLL_, false><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(     \
+#define RT_TILE32_LAUNCH(HLL_, IVA_)                                                            \
+    k_transport32_tile<G, HLL_, false, IVA_><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>( \
         n, nb, ctx->geo32, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt,            \
         ctx->p.c_red, ctx->p.box, Uout, partials, (unsigned long long *)counts, Uung,           \
-        ctx->status, tab)
-            if (hll)
-                RT_TILE32_LAUNCH(true);
-            else
-                RT_TILE32_LAUNCH(false);
+        ctx->status, tab, 0, nullptr, nullptr, ctx->ivan)
+            if (hll) {
+                if (iva) RT_TILE32_LAUNCH(true, true);
+                else RT_TILE32_LAUNCH(true, false);
+            } else {
+                if (iva) RT_TILE32_LAUNCH(false, true);
+                else RT_TILE32_LAUNCH(false, false);
+            }
 #undef RT_TILE32_LAUNCH
             return;
         }
@@ -1107,18 +1130,22 @@ void launch_tick32(rt_ctx *ctx, float *U, float *UD, const double *dt, double *p
     if constexpr (G <= 3) {
         const bool hll = ctx->solver == RT_HLL;
         if (RT_TICK32_TILE != 0 && RT_TRANSPORT32_TILE != 0 &&
-            (ctx->solver == RT_GLF || (RT_TRANSPORT32_TILE_HLL != 0 && hll)) && !iva && ctx->task) {
+            (ctx->solver == RT_GLF || (RT_TRANSPORT32_TILE_HLL != 0 && hll)) &&
+            (!iva || RT_TRANSPORT32_TILE_IVA != 0) && ctx->task) {
             // the tiles in their time-bin mode (one row of partials per tile)
             static_assert(kBlock / kQ32 == kTile, "a tile per two-sided block");
-#define RT_TICK32_TILE_LAUNCH(HLL_)                                                             \
-    k_transport32_tile<G, HLL_, true><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>(      \
+#define RT_TICK32_TILE_LAUNCH(HLL_, IVA_)                                                       \
+    k_transport32_tile<G, HLL_, true, IVA_><<<(unsigned)xcd_grid(nb), kBlock, 0, ctx->stream>>>( \
         n, nb, ctx->geo32, ctx->geo, ctx->task, ctx->wave_base, ctx->n_task, UD, dt,            \
         ctx->p.c_red, ctx->p.box, U, partials, (unsigned long long *)counts, nullptr,           \
-        ctx->status, tab, tick, accm, binm)
-            if (hll)
-                RT_TICK32_TILE_LAUNCH(true);
-            else
-                RT_TICK32_TILE_LAUNCH(false);
+        ctx->status, tab, tick, accm, binm, ctx->ivan)
+            if (hll) {
+                if (iva) RT_TICK32_TILE_LAUNCH(true, true);
+                else RT_TICK32_TILE_LAUNCH(true, false);
+            } else {
+                if (iva) RT_TICK32_TILE_LAUNCH(false, true);
+                else RT_TICK32_TILE_LAUNCH(false, false);
+            }
 #undef RT_TICK32_TILE_LAUNCH
             return;
         }
