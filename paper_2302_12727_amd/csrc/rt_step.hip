@@ -407,14 +407,17 @@ __global__ __launch_bounds__(grad_block(G)) __attribute__((amdgpu_waves_per_eu(
 // launch over their list).  Sums in the same order as k_gradient64 (lane sub
 // takes the slots sub, sub + Q, ...; rows past a list are the own row, whose
 // differences are zero), so the two give the same bits.
-template <int G, int Q, int W>
+// BIN: only the particles that end a step in tick `tick` recompute their
+// record, as in k_gradient64; a block none of whose particles does so stages
+// nothing.
+template <int G, int Q, int W, bool BIN = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(W, W))) void
 k_gradient64u(int64_t n, int64_t nb, const double *__restrict__ geo, const double *__restrict__ xs,
               const int32_t *__restrict__ urow, const int64_t *__restrict__ uoff,
               const uint16_t *__restrict__ gloc, const int64_t *__restrict__ goff,
               const uint16_t *__restrict__ uown, const int32_t *__restrict__ n_gath,
               const double *__restrict__ U, double *__restrict__ UD, int32_t *__restrict__ status,
-              double box) {
+              double box, int64_t tick = 0) {
     static_assert(Q == 4 && kBlock == 256, "one block of 64 particles per table column block");
     constexpr int NQ = 4 * G, PU = 2 * G, UC = W == 3 ? union_cap3(G) : union_cap(G);
     static_assert(UC > 0 && UC <= kUnionSort, "union capacity");
@@ -426,6 +429,12 @@ k_gradient64u(int64_t n, int64_t nb, const double *__restrict__ geo, const doubl
     const int64_t u0 = uoff[blk];
     const int32_t rows = (int32_t)(uoff[blk + 1] - u0);
     if (rows == 0) return;                      // left to the staged gradient (whole block)
+    if constexpr (BIN) {
+        const int64_t ib = blk * (kBlock / Q) + threadIdx.x / Q;
+        const bool e = ib < n &&
+                       ((tick + 1) & ((int64_t(1) << (int32_t)geo[(int64_t)kRec * ib + 12]) - 1)) == 0;
+        if (!__syncthreads_or(e)) return;       // whole block: no particle ends a step
+    }
     // stage the union: its indices first, then every thread's pieces of the
     // states (16 bytes) and positions (doubles) in flight at once (a chain of
     // dependent loads per piece left the blocks waiting: 1.38 ms)
@@ -458,7 +467,8 @@ k_gradient64u(int64_t n, int64_t nb, const double *__restrict__ geo, const doubl
     const int lane = threadIdx.x & 63, sub = lane % Q;
     const int p = threadIdx.x / Q;              // the particle in the block
     const int64_t i = blk * (kBlock / Q) + p;
-    const bool active = i < n;
+    const bool active =
+        i < n && (!BIN || ((tick + 1) & ((int64_t(1) << (int32_t)geo[(int64_t)kRec * i + 12]) - 1)) == 0);
     const int64_t ic = active ? i : n - 1;
     const int32_t ng = active ? n_gath[ic] : 0;
     const int il = active ? (int)uown[ic] : 0;  // a row of the union (not used past n)
@@ -1399,6 +1409,10 @@ inline int64_t transport_rows(int64_t n) { return (n + kBlock / kQ - 1) / (kBloc
 #ifndef RT_TICK_TILE
 #define RT_TICK_TILE 1
 #endif
+// ... and their gradients from the neighbour unions; 0: staged.
+#ifndef RT_TICK_UNION
+#define RT_TICK_UNION 1
+#endif
 inline bool use_tile64(const rt_ctx *ctx) {
     return RT_TRANSPORT_TILE != 0 && ctx->p.precision == RT_FP64 &&
            (ctx->solver == RT_GLF || (RT_TRANSPORT_TILE_HLL != 0 && ctx->solver == RT_HLL)) &&
@@ -1507,9 +1521,34 @@ void launch_tick64(rt_ctx *ctx, const double *U, double *UD, const double *dt, d
     const int64_t n = ctx->p.n;
     constexpr int B = grad_block(G);
     const int64_t ng = (n + B / kGQ - 1) / (B / kGQ);
-    k_gradient64<G, true, kGQ><<<(unsigned)xcd_grid(ng), B, 0, ctx->stream>>>(
-        n, ng, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->status,
-        ctx->p.box, tick);
+    bool grad_done = false;
+    if constexpr (union_cap(G) > 0 && kGQ == 4 && B == 256) {
+        if (RT_TICK_UNION != 0 && ctx->uoff) {
+            // the neighbour unions, in their time-bin mode; the blocks whose
+            // union does not fit: staged, by list
+            const int64_t nw = ctx->nwaves;
+#define RT_TICK_UNION_LAUNCH(W_)                                                               \
+    k_gradient64u<G, kGQ, W_, true><<<(unsigned)xcd_grid(nw), kBlock, 0, ctx->stream>>>(      \
+        n, nw, ctx->geo, ctx->xs, ctx->urow, ctx->uoff, ctx->gloc, ctx->goff, ctx->uown,       \
+        ctx->n_gath, U, UD, ctx->status, ctx->p.box, tick)
+            if constexpr (union_cap3(G) > 0) {
+                if (ctx->union_waves == 3) RT_TICK_UNION_LAUNCH(3);
+                else RT_TICK_UNION_LAUNCH(2);
+            } else {
+                RT_TICK_UNION_LAUNCH(2);
+            }
+#undef RT_TICK_UNION_LAUNCH
+            if (ctx->n_ublk > 0)
+                k_gradient64<G, true, kGQ><<<(unsigned)xcd_grid(ctx->n_ublk), B, 0, ctx->stream>>>(
+                    n, ctx->n_ublk, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath,
+                    U, UD, ctx->status, ctx->p.box, tick, ctx->ublk);
+            grad_done = true;
+        }
+    }
+    if (!grad_done)
+        k_gradient64<G, true, kGQ><<<(unsigned)xcd_grid(ng), B, 0, ctx->stream>>>(
+            n, ng, ctx->geo, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->status,
+            ctx->p.box, tick);
     constexpr int GW = transport_slice(G), HW = hll_slice(G);
     const int64_t nt = transport_rows(n);
     const double2 *tab = (const double2 *)ctx->hll_table;
