@@ -26,6 +26,10 @@ using namespace gearrt;
 #ifndef RT_TICK32_TILE
 #define RT_TICK32_TILE 1
 #endif
+// ... with their gradients from the neighbour unions; 0: staged.
+#ifndef RT_TICK_UNION32
+#define RT_TICK_UNION32 1
+#endif
 // The Ivanova surfaces too; 0 keeps them two-sided.
 #ifndef RT_TRANSPORT32_TILE_IVA
 #define RT_TRANSPORT32_TILE_IVA 1
@@ -151,15 +155,17 @@ __device__ __forceinline__ int quad_bcast(int v) {
 // (k_gradient32 with Q = 1), so the two give identical bits (see
 // RT_GRADIENT32_Q for why that order is kept).  Padding past a list is the
 // own row, which adds an exact zero.  Blocks whose union did not fit are
-// left to k_gradient32 with one lane per particle.
-template <int G>
+// left to k_gradient32 with one lane per particle.  BIN: only the particles
+// that end a step in tick `tick` recompute their record; a block none of
+// whose particles does so stages nothing.
+template <int G, bool BIN = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 k_gradient32u(int64_t n, int64_t nb, const float *__restrict__ geo32, const double *__restrict__ xs,
               const int32_t *__restrict__ urow, const int64_t *__restrict__ uoff,
               const uint16_t *__restrict__ gloc, const int64_t *__restrict__ goff,
               const uint16_t *__restrict__ uown, const int32_t *__restrict__ n_gath,
               const float *__restrict__ U, float *__restrict__ UD, int32_t *__restrict__ status,
-              double box) {
+              double box, int64_t tick = 0) {
     constexpr int Q = 4, UC = union_cap32(G);
     static_assert(kBlock == 256 && UC > 0 && UC <= kUnionSort, "64 particles per block");
     __shared__ fvec4 ust[UC * G];              // G pieces of 16 bytes a row
@@ -170,6 +176,11 @@ k_gradient32u(int64_t n, int64_t nb, const float *__restrict__ geo32, const doub
     const int64_t u0 = uoff[blk];
     const int32_t rows = (int32_t)(uoff[blk + 1] - u0);
     if (rows == 0) return;                      // left to k_gradient32 (whole block)
+    if constexpr (BIN) {
+        const int64_t ib = blk * (kBlock / Q) + threadIdx.x / Q;
+        const bool e = ib < n && ((tick + 1) & ((int64_t(1) << (int32_t)geo32[(int64_t)F_REC * ib + F_BIN]) - 1)) == 0;
+        if (!__syncthreads_or(e)) return;       // whole block: no particle ends a step
+    }
     for (int e = threadIdx.x; e < rows; e += kBlock) uidx[e] = urow[u0 + e];
     __syncthreads();
     const fvec4 *U4 = reinterpret_cast<const fvec4 *>(U);
@@ -202,7 +213,8 @@ k_gradient32u(int64_t n, int64_t nb, const float *__restrict__ geo32, const doub
     const int sub = threadIdx.x % Q;            // the component this lane sums
     const int p = threadIdx.x / Q;              // the particle in the block
     const int64_t i = blk * (kBlock / Q) + p;
-    const bool active = i < n;
+    const bool active =
+        i < n && (!BIN || ((tick + 1) & ((int64_t(1) << (int32_t)geo32[(int64_t)F_REC * i + F_BIN]) - 1)) == 0);
     const int64_t ic = active ? i : n - 1;
     const int32_t ng = active ? n_gath[ic] : 0;
     const int il = active ? (int)uown[ic] : 0;  // a row of the union (not used past n)
@@ -1120,9 +1132,28 @@ void launch_tick32(rt_ctx *ctx, float *U, float *UD, const double *dt, double *p
                    int64_t *counts, int64_t tick, double *accm) {
     const int64_t n = ctx->p.n;
     const int64_t ng = (n + kBlock / kGQ32 - 1) / (kBlock / kGQ32);
-    k_gradient32<G, kGQ32, true><<<(unsigned)xcd_grid(ng), kBlock, 0, ctx->stream>>>(
-        n, ng, ctx->geo32, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->status,
-        ctx->p.box, tick);
+    bool grad_done = false;
+    if constexpr (union_cap32(G) > 0 && kGQ32 == 1) {
+        if (RT_TICK_UNION32 != 0 && ctx->uoff) {
+            // the neighbour unions in their time-bin mode; the blocks whose
+            // union does not fit: one lane per particle, by list
+            const int64_t nw = ctx->nwaves;
+            k_gradient32u<G, true><<<(unsigned)xcd_grid(nw), kBlock, 0, ctx->stream>>>(
+                n, nw, ctx->geo32, ctx->xs, ctx->urow, ctx->uoff, ctx->gloc, ctx->goff,
+                ctx->uown, ctx->n_gath, U, UD, ctx->status, ctx->p.box, tick);
+            if (ctx->n_ublk > 0) {
+                const int64_t nl = (ctx->n_ublk + 3) / 4;
+                k_gradient32<G, 1, true><<<(unsigned)xcd_grid(nl), kBlock, 0, ctx->stream>>>(
+                    n, nl, ctx->geo32, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD,
+                    ctx->status, ctx->p.box, tick, ctx->ublk, ctx->n_ublk);
+            }
+            grad_done = true;
+        }
+    }
+    if (!grad_done)
+        k_gradient32<G, kGQ32, true><<<(unsigned)xcd_grid(ng), kBlock, 0, ctx->stream>>>(
+            n, ng, ctx->geo32, ctx->xs, ctx->nbr, ctx->wave_base, ctx->n_gath, U, UD, ctx->status,
+            ctx->p.box, tick);
     const int64_t nb = rt_transport32_rows(n);
     const float2 *tab = (const float2 *)ctx->hll_table32;
     const bool iva = ctx->surfaces == RT_IVANOVA;
